@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the VIP fractional step on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): flow past a
+circular cylinder D = 1 in [-10, 20] x [-10, 10] with h = D/128 (lattice nodes
+outside the body plus 256 surface nodes), together with the equilateral
+triangular lid-driven cavity (side 1, lid on top) at the same h; Re = 200,
+dt = h/5 (CFL 0.2 at the free stream), pressure Poisson solved to an FP64
+relative residual of 1e-8.  One step = one fractional step of both domains.
+
+Two paths are timed on the same node sets:
+  * mixed:  FP32 inner Krylov (SpMV + vectors) inside FP64 iterative refinement,
+            Poisson start vector = the previous step's increment;
+  * fp64:   plain FP64 Krylov from a zero start vector.
+`value` is the mixed path.  The roofline entry is the mixed path's pressure
+SpMV, timed with HIP events inside the library over the timed steps.  The CPU
+baseline runs the FP64 oracle (SciPy, Krylov mode, same tolerance) on a window
+of the same workload.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1401_6513_amd import nodesets as ns  # noqa: E402
+
+METRIC = "node-updates/s per fractional step (Poisson to 1e-8), learned+FP32 vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def workload(h):
+    cyl = ns.cylinder_channel(h, box=(-10.0, 20.0, -10.0, 10.0), shape="circle", n_surface=256)
+    tri = ns.triangle_cavity(h)
+    return [cyl, tri]
+
+
+def _initial(spec, dev):
+    import torch
+    inflow = (1.0, 0.0) if spec.name.startswith("cyl") else (0.0, 0.0)
+    u, v, p = ns.boundary_initial(spec, inflow)
+    return [torch.tensor(a, device=dev) for a in (u, v, p)]
+
+
+def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv):
+    import torch
+    dev = torch.device("cuda", 0)
+    for ctx, spec in zip(ctxs, specs):
+        opt = vip.default_options(period=spec.period, poisson_tol=tol,
+                                  precision=vip.P_MIXED if path == "mixed" else vip.P_FP64,
+                                  warmstart=vip.WS_PREV if path == "mixed" else vip.WS_ZERO)
+        ctx.vip_set_options(opt)
+        ctx.vip_reset_history()
+    state = [_initial(s, dev) for s in specs]
+    for w in range(warmup):
+        for ctx, (u, v, p) in zip(ctxs, state):
+            ctx.vip_step(u, v, p, dt, re)
+        log("%s warmup step %d done" % (path, w + 1))
+    torch.cuda.synchronize()
+    if time_spmv:
+        ctxs[0].vip_kernel_timing(enable=True, reset=True)
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        row = []
+        for ctx, (u, v, p) in zip(ctxs, state):
+            row.append(ctx.vip_step(u, v, p, dt, re))
+        stats.append(row)
+        log("%s step %d: poisson iters %s, residual %s" % (
+            path, k + 1, [s["poisson_iters"] for s in row],
+            ["%.1e" % s["poisson_residual"] for s in row]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    spmv = None
+    if time_spmv:
+        spmv = ctxs[0].vip_kernel_timing(enable=False)
+    fields = [[t.cpu().numpy() for t in st] for st in state]
+    return (t1 - t0), stats, spmv, fields
+
+
+def cpu_baseline(h, dt, re, budget_s):
+    """FP64 oracle in Krylov mode on a window of the cylinder workload (same h, dt, Re)."""
+    from oracle import operators, step
+    # window around the body, same spacing; grow it until one step costs ~budget/3
+    half = 1.0
+    best = None
+    while True:
+        spec = ns.cylinder_channel(h, box=(-half, 2.0 * half, -half, half), n_surface=256)
+        prob = operators.Problem(**spec.as_kwargs())
+        ops = operators.Operators(prob)
+        st = step.Stepper(ops, dt, re, solver="krylov", tol=1e-8)
+        u, v, p = ns.boundary_initial(spec, (1.0, 0.0))
+        t0 = time.perf_counter()
+        u, v, p = st.step(u, v, p)
+        t1 = time.perf_counter()
+        best = (spec, t1 - t0, dict(st.last_iters))
+        if (t1 - t0) > budget_s / 3.0 or half >= 2.0:
+            break
+        half *= 2.0
+    spec, dtstep, iters = best
+    # time two more steps (the first step above is the impulsive start, as on the GPU)
+    t0 = time.perf_counter()
+    for _ in range(2):
+        u, v, p = st.step(u, v, p)
+    t1 = time.perf_counter()
+    per = (t1 - t0) / 2.0
+    return {"value": spec.n / per, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 oracle (NumPy/SciPy, BiCGStab to 1e-8, zero start) on the window "
+                      "[%g,%g]x[%g,%g] of the cylinder workload at h=1/%d (%d nodes), steps 2-3; "
+                      "single-threaded SciPy sparse kernels" % (
+                          -half, 2 * half, -half, half, round(1.0 / h), spec.n),
+            "ms_per_step": per * 1e3, "poisson_iters": st.last_iters.get("P")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--h", type=float, default=1.0 / 128)
+    ap.add_argument("--re", type=float, default=200.0)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--paths", default="mixed,fp64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the VIP hot path is built and measured on a single "
+              "MI355X (multi-GPU sharding is a design note, not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1401_6513_amd import vip
+    h = args.h
+    dt = h / 5.0
+    re = args.re
+    log("generating node sets (h = %g)" % h)
+    specs = workload(h)
+    n_total = sum(s.n for s in specs)
+    log("nodes: %s (total %d)" % ([s.n for s in specs], n_total))
+    ctxs = []
+    t0 = time.perf_counter()
+    for s in specs:
+        c = vip.Context(0)
+        c.build_from_spec(s)
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log("stencils built in %.2f s" % build_s)
+
+    paths = [p for p in args.paths.split(",") if p]
+    results = {}
+    for path in paths:
+        el, stats, spmv, fields = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
+                                           args.steps, args.tol, time_spmv=(path == "mixed"))
+        results[path] = dict(seconds=el, stats=stats, spmv=spmv, fields=fields)
+        log("%s: %.3f s for %d steps" % (path, el, args.steps))
+
+    main_path = "mixed" if "mixed" in results else paths[0]
+    r = results[main_path]
+    ms = r["seconds"] / args.steps * 1e3
+    value = n_total * args.steps / r["seconds"]
+
+    roof = None
+    if r["spmv"] is not None and r["spmv"][1] > 0:
+        n0, _, nnz0 = ctxs[0].vip_operator_shape("poisson")
+        # FP32 values + int32 columns per stored entry; x gathered once, v written, rhat read
+        bytes_per_launch = 8 * nnz0 + 12 * n0
+        avg_ms, count = r["spmv"]
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_bicg_v<float,float,1> (pressure SpMV, FP32 sliced ELL)",
+                "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms, "launches": count,
+                "rows": n0, "nnz": nnz0}
+
+    out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64" if main_path == "mixed" else "f64", "data": "synthetic",
+           "config": {"workload": "cylinder D=1 in [-10,20]x[-10,10] + equilateral lid cavity, "
+                                  "h=D/%d, Re=%g, dt=%g, Poisson rel. residual %g" % (
+                                      round(1 / h), re, dt, args.tol),
+                      "nodes": n_total, "nodes_per_domain": [s.n for s in specs],
+                      "path": main_path, "build_s": build_s}}
+    for path, rr in results.items():
+        it = [[s["poisson_iters"] for s in row] for row in rr["stats"]]
+        out["path_" + path] = {"value": n_total * args.steps / rr["seconds"],
+                               "ms_per_step": rr["seconds"] / args.steps * 1e3,
+                               "poisson_iters": it,
+                               "poisson_residual": max(s["poisson_residual"] for row in rr["stats"]
+                                                       for s in row)}
+    if "mixed" in results and "fp64" in results:
+        out["speedup_mixed_vs_fp64"] = results["fp64"]["seconds"] / results["mixed"]["seconds"]
+        # difference of the two paths' fields after the same steps (both solve to 1e-8)
+        diffs = []
+        for a, b in zip(results["mixed"]["fields"], results["fp64"]["fields"]):
+            for k, (x, y) in enumerate(zip(a, b)):
+                if k == 2:
+                    x, y = x - x.mean(), y - y.mean()
+                diffs.append(float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)))
+        out["rel_l2_mixed_vs_fp64"] = {"u": max(diffs[0::3]), "v": max(diffs[1::3]),
+                                       "p": max(diffs[2::3])}
+    out["roofline"] = roof
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(h, dt, re, args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    for c in ctxs:
+        c.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,227 @@
+/*
+ * vip.h - C ABI of the MI355X (gfx950) library for the virtual interpolation
+ * point (VIP) method of Park, Jo and Choe, "Virtual Interpolation Point Method
+ * for Viscous Flows in Complex Geometries" (arXiv 1401.6513).
+ *
+ * The library builds moving-least-squares (MLS) shape functions on a node set
+ * (Section 3 of the paper), assembles the VIP operators (Section 4) and
+ * advances the incompressible Navier-Stokes equations by the fractional step of
+ * Section 2 (eqs. 12-15), all on one GPU.
+ *
+ * Conventions for every entry point:
+ *  - Return value: VIP_OK (0) or a negative VIP_E_* code.  No C++ exception
+ *    crosses the ABI.  After an error, vip_last_error() describes it.
+ *  - Host arrays ("host" below) are read during the call and copied; the
+ *    caller keeps ownership.
+ *  - Device arrays ("device" below) are caller-owned HIP device allocations of
+ *    the stated length, FP64, in the caller's node order.  The library never
+ *    frees them.  Work is enqueued on the context's stream; a call returns
+ *    after its results are complete on that stream unless stated otherwise.
+ *  - A context is bound to one device and one stream and is not thread-safe.
+ */
+#ifndef VIP_H_
+#define VIP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+enum {
+  VIP_OK = 0,
+  VIP_E_INVALID = -1,       /* bad argument (sizes, NaN coordinates, unknown enum) */
+  VIP_E_SINGULAR = -2,      /* an MLS moment matrix could not be factorised, or a
+                               point kept fewer than min_neighbours neighbours
+                               after support growth (index in vip_last_error) */
+  VIP_E_NOT_CONVERGED = -3, /* Krylov solve hit its iteration limit; outputs are
+                               still written and stats filled */
+  VIP_E_HIP = -4,           /* a HIP runtime call failed */
+  VIP_E_NOT_BUILT = -5,     /* vip_build_stencils has not succeeded on this context */
+  VIP_E_NONFINITE = -6      /* NaN or Inf met in the state or in a solve */
+};
+
+/* ---- boundary kinds (one per boundary-table entry) ----------------------- */
+enum {
+  VIP_BC_DIRICHLET = 0, /* u = value[0], v = value[1]; dphi/dn = 0 */
+  VIP_BC_SLIP = 1,      /* the component along the dominant axis of the normal is
+                           held at its value, the other has zero normal
+                           derivative; dphi/dn = 0 */
+  VIP_BC_OUTLET = 2     /* traction free: du/dn = Re p n_x, dv/dn = Re p n_y with
+                           p from the previous step; phi = 0 */
+};
+
+/* ---- options -------------------------------------------------------------- */
+enum { VIP_W_CUBIC_SPLINE = 0, VIP_W_PAPER = 1 };  /* weight function Phi (Section 3) */
+enum { VIP_I_MLS = 0, VIP_I_EXACT = 1 };            /* identity in eq. 12: D^[0,0] or I */
+enum { VIP_P_FP64 = 0, VIP_P_MIXED = 1 };           /* Poisson: FP64 Krylov, or FP32
+                                                       inner Krylov in FP64 refinement */
+enum { VIP_K_AUTO = 0, VIP_K_PCG = 1, VIP_K_BICGSTAB = 2 };
+enum { VIP_WS_ZERO = 0, VIP_WS_PREV = 1 };          /* Poisson start vector in vip_step */
+
+typedef struct {
+  int weight;             /* VIP_W_*; default VIP_W_CUBIC_SPLINE */
+  int identity;           /* VIP_I_*; default VIP_I_MLS */
+  int precision;          /* VIP_P_*; default VIP_P_FP64 */
+  int krylov;             /* VIP_K_*; AUTO: PCG if the pressure matrix is symmetric, else BiCGStab */
+  int warmstart;          /* VIP_WS_*; default VIP_WS_ZERO */
+  int min_neighbours;     /* support growth threshold; default 12 */
+  double vip_offset;      /* VIP distance from the node, fraction of h; default 0.5 */
+  double period[2];       /* periodic box lengths, 0 = not periodic (both or neither) */
+  double poisson_tol;     /* ||b - L phi||_2 / ||b||_2 in FP64; default 1e-8 */
+  double helmholtz_tol;   /* same measure for eq. 12; default 1e-12 */
+  double inner_tol;       /* relative tolerance of the FP32 inner solve (MIXED); default 1e-4 */
+  int max_iters;          /* Krylov iteration limit per solve; default 200000 */
+  int check_every;        /* iterations between host convergence checks; default 16 */
+} vip_options;
+
+typedef struct {
+  int poisson_iters;      /* Krylov iterations of the Poisson solve (inner total if MIXED) */
+  int poisson_outer;      /* refinement passes (1 for FP64) */
+  int helmholtz_iters;    /* iterations of the two predictor solves (the larger) */
+  int krylov_used;        /* VIP_K_PCG or VIP_K_BICGSTAB */
+  double poisson_residual;   /* final ||b - L phi||_2 / ||b||_2, FP64 */
+  double helmholtz_residual; /* the larger of the two predictor residuals */
+  double border_lambda;      /* multiplier of the bordered singular system, else 0 */
+} vip_step_stats;
+
+/* Fill *opt with the defaults listed above. */
+void vip_default_options(vip_options* opt);
+
+/* Create a context on HIP device `device` using HIP stream `stream` (NULL =
+ * the default stream; a torch stream handle may be passed).  *out receives
+ * the context, owned by the caller until vip_destroy. */
+int vip_create(void** out, int device, void* stream);
+
+/* Release every device allocation of the context and the context itself. */
+int vip_destroy(void* ctx);
+
+/* Text of the last error on this context (never NULL; empty if none). */
+const char* vip_last_error(const void* ctx);
+
+/*
+ * Build the stencils and every operator for a node set (Sections 3 and 4).
+ *
+ *  nodes_xy   host, [n_nodes][2] FP64: node coordinates (the set Lambda).
+ *  bnd_idx    host, [n_bnd] int64: node index of each boundary-table entry
+ *             (distinct, in [0, n_nodes)).
+ *  bnd_normal host, [n_bnd][2] FP64: outward unit normal of the flow domain.
+ *  bnd_kind   host, [n_bnd] int32: VIP_BC_*.
+ *  bnd_value  host, [n_bnd][2] FP64: prescribed velocity (read where held).
+ *  basis_order  2 (the quadratic basis of Section 3; other values are rejected).
+ *  support_radius  rho of Section 3 (absolute); grown by 1.25, at most twice,
+ *             where fewer than min_neighbours nodes lie strictly inside.
+ *  h          lattice spacing: VIPs sit at x_i +- vip_offset*h along the axes;
+ *             Neumann rows use points at vip_offset*h and 2*vip_offset*h along
+ *             the inward normal.
+ *  opt        options (NULL = defaults).
+ *
+ * Errors: VIP_E_INVALID (n_nodes <= 0, n_bnd < 0, NaN coordinates, bad
+ * indices or kinds, rho <= 0, h <= 0, basis_order != 2, a periodic box
+ * shorter than twice the largest support); VIP_E_SINGULAR; VIP_E_HIP.
+ * Rebuilding on the same context replaces the previous node set.
+ */
+int vip_build_stencils(void* ctx, const double* nodes_xy, int64_t n_nodes,
+                       const int64_t* bnd_idx, const double* bnd_normal,
+                       const int32_t* bnd_kind, const double* bnd_value, int64_t n_bnd,
+                       int basis_order, double support_radius, double h,
+                       const vip_options* opt);
+
+/* Replace the solver options of a built context (stencil-defining fields such
+ * as weight, vip_offset, period and min_neighbours are ignored here). */
+int vip_set_options(void* ctx, const vip_options* opt);
+
+/*
+ * One fractional step (eqs. 12-15): AB2 convection by VIP fluxes, the
+ * Crank-Nicolson predictor with the boundary rows, the pressure Poisson
+ * equation, the VIP-gradient projection at interior nodes and the pressure
+ * update p = phi - dt/(2 Re) Delta phi.
+ *
+ *  u, v, p  device, [n_nodes] FP64, updated in place.
+ *  dt, Re   time step and Reynolds number (> 0).  A change of dt or Re
+ *           re-assembles the Helmholtz operators and restarts AB2 (the first
+ *           step uses N^(n-1) = N^n).
+ *  stats    host, may be NULL.
+ * Errors: VIP_E_NOT_BUILT, VIP_E_INVALID, VIP_E_NOT_CONVERGED (state is still
+ * advanced), VIP_E_NONFINITE, VIP_E_HIP.
+ */
+int vip_step(void* ctx, double* u, double* v, double* p, double dt, double Re,
+             vip_step_stats* stats);
+
+/* Forget the AB2 history and the previous pressure increment. */
+int vip_reset_history(void* ctx);
+
+/*
+ * Solve the pressure Poisson system of eq. 13 with the context's boundary
+ * rows: interior rows Delta phi = rhs, Neumann rows, outlet rows phi = 0; for a
+ * singular system (periodic, or no outlet) the bordered form
+ * Delta phi + lambda = rhs, sum(phi) = 0.
+ *
+ *  rhs  device, [n_nodes] FP64 (boundary-row entries are the row right-hand sides).
+ *  phi  device, [n_nodes] FP64: start vector on entry if use_x0 != 0, solution on exit.
+ *  tol  relative FP64 residual target.
+ *  stats host, may be NULL (poisson_* fields and border_lambda are filled).
+ */
+int vip_poisson_solve(void* ctx, const double* rhs, double* phi, double tol, int use_x0,
+                      vip_step_stats* stats);
+
+/* ---- operator access (parity checks and tools) ---------------------------- */
+enum {
+  VIP_OP_IDENTITY = 0,  /* D^[0,0] at the nodes (N rows) */
+  VIP_OP_LAPLACIAN = 1, /* D^[2,0] + D^[0,2] at the nodes (N rows) */
+  VIP_OP_VIP_E = 2,     /* Psi^[0,0] at the east VIP of each interior node (N rows) */
+  VIP_OP_VIP_W = 3,
+  VIP_OP_VIP_N = 4,
+  VIP_OP_VIP_S = 5,
+  VIP_OP_NORMAL1 = 6,   /* Psi^[0,0] at x_b - d n_b, one row per boundary entry */
+  VIP_OP_NORMAL2 = 7,   /* Psi^[0,0] at x_b - 2 d n_b */
+  VIP_OP_POISSON = 8,   /* pressure matrix with boundary rows (N rows, no border) */
+  VIP_OP_HELM_U = 9,    /* predictor matrix of u (needs one vip_step or vip_assemble) */
+  VIP_OP_HELM_V = 10,
+  VIP_OP_POISSON32 = 11 /* FP32 copy of VIP_OP_POISSON (values returned widened) */
+};
+
+/* Rows, the largest row length and the number of stored entries (without
+ * slice padding) of operator `which`; any output pointer may be NULL. */
+int vip_operator_shape(void* ctx, int which, int64_t* n_rows, int64_t* max_width, int64_t* nnz);
+
+/* Copy operator `which` to host arrays [n_rows][max_width]: cols (int32, -1 in
+ * padding) and vals (FP64, 0 in padding). */
+int vip_get_operator(void* ctx, int which, int32_t* cols, double* vals);
+
+/* y = A x for operator `which` with N rows over N columns; device x, y [N]. */
+int vip_apply(void* ctx, int which, const double* x, double* y);
+
+/* Assemble the Helmholtz operators for (dt, Re) without stepping. */
+int vip_assemble(void* ctx, double dt, double Re);
+
+/* Geometry of the build, host outputs: vip_xy [n_nodes][4][2] (VIP coordinates
+ * e, w, n, s; zeros on boundary rows), d_ew and d_ns [n_nodes] (VIP spacings,
+ * 1 on boundary rows), rho_node [n_nodes] (support radius used at each node).
+ * Any pointer may be NULL. */
+int vip_get_geometry(void* ctx, double* vip_xy, double* d_ew, double* d_ns, double* rho_node);
+
+/* VIP convection flux (Section 4.1 item 1) of device u, v into device nx, ny
+ * [n_nodes] (zero on boundary rows). */
+int vip_convection(void* ctx, const double* u, const double* v, double* nx, double* ny);
+
+/* VIP divergence (Section 4.1 item 2) of device u, v into device div [n_nodes]
+ * (zero on boundary rows). */
+int vip_divergence(void* ctx, const double* u, const double* v, double* div);
+
+/* VIP gradient (Section 4.1 item 3) of device f into device gx, gy [n_nodes]
+ * (zero on boundary rows). */
+int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
+
+/* Average duration (ms) of the pressure-solve SpMV kernel (the first SpMV of
+ * each Krylov iteration) over the launches since the last reset, measured with
+ * HIP events on the context stream while timing is enabled; *count receives the
+ * number of timed launches.  enable = 0 stops timing; reset = 1 clears it. */
+int vip_kernel_timing(void* ctx, int enable, int reset, double* avg_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIP_H_ */

@@ -56,28 +56,34 @@ def bicgstab(A, b, x0=None, tol=1e-8, maxiter=100000):
     bn = np.linalg.norm(b)
     if bn == 0.0:
         return np.zeros_like(b), 0, 0.0
-    r = b - A @ x
-    rhat = r.copy()
-    rho = alpha = omega = 1.0
-    v = np.zeros_like(b)
-    p = np.zeros_like(b)
+
+    def restart():
+        r = b - A @ x
+        return r, r.copy(), 1.0, 1.0, 1.0, np.zeros_like(b), np.zeros_like(b)
+
+    r, rhat, rho, alpha, omega, v, p = restart()
     it = 0
     while it < maxiter:
         if np.linalg.norm(r) <= tol * bn:
             rt = np.linalg.norm(b - A @ x)
             if rt <= tol * bn:
                 return x, it, rt / bn
-            r = b - A @ x
-            rhat = r.copy()
-            rho = alpha = omega = 1.0
-            v[:] = 0.0
-            p[:] = 0.0
+            r, rhat, rho, alpha, omega, v, p = restart()
         rho_new = rhat @ r
+        if rho_new == 0.0 or omega == 0.0 or not np.isfinite(rho_new):
+            # breakdown: restart from the true residual with a fresh shadow vector
+            r, rhat, rho, alpha, omega, v, p = restart()
+            rho_new = rhat @ r
         beta = (rho_new / rho) * (alpha / omega)
         p = r + beta * (p - omega * v)
         ph = dinv * p
         v = A @ ph
-        alpha = rho_new / (rhat @ v)
+        rv = rhat @ v
+        if rv == 0.0 or not np.isfinite(rv):
+            r, rhat, rho, alpha, omega, v, p = restart()
+            it += 1
+            continue
+        alpha = rho_new / rv
         s = r - alpha * v
         sh = dinv * s
         t = A @ sh

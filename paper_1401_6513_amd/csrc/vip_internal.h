@@ -1,0 +1,200 @@
+// Internal declarations of the VIP library: context, sliced-ELL operators,
+// device scalar blocks and helpers shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/vip.h"
+
+namespace vip {
+
+constexpr int kSlice = 64;      // rows per ELL slice = one wavefront
+constexpr int kBlock = 256;     // threads per block of the row kernels
+constexpr int kMaxWidth = 128;  // largest neighbour list of one evaluation point
+constexpr int kNumXcd = 8;      // accelerator complex dies of the MI355X
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+// Sliced ELL matrix: rows grouped by 64; slice s holds width[s] columns stored
+// column-major, element (row r, slot k) at ptr[s] + k*64 + (r - 64 s).
+// Padding slots carry col = 0 (any in-range index) and value 0.
+struct Ell {
+  int64_t nrows = 0;
+  int64_t nslices = 0;
+  int64_t nnz_slots = 0;            // ptr[nslices]
+  int64_t* ptr = nullptr;           // device [nslices + 1]
+  int32_t* width = nullptr;         // device [nslices]
+  int32_t* rowlen = nullptr;        // device [nrows], true row length
+  int32_t* cols = nullptr;          // device [nnz_slots]
+  double* val[4] = {nullptr, nullptr, nullptr, nullptr};  // FP64 value sets
+  float* val32 = nullptr;           // FP32 value set (pressure matrix only)
+  int64_t max_width = 0;
+  int64_t nnz = 0;                  // sum of row lengths
+};
+
+// Device-resident scalars of the Krylov solvers, written by the last block of a
+// reduction and read by later kernels; two systems side by side (u and v of
+// the predictor) use index 0 and 1.
+struct KrylovScalars {
+  double rho[2], alpha[2], omega[2], beta[2];
+  double rr[2];          // ||r||^2 (recurrence)
+  double bb[2];          // ||b||^2
+  double dot_a[2], dot_b[2], dot_c[2];
+  double mean;           // mean of a vector (periodic projection)
+  int breakdown[2];
+};
+
+struct Timing {
+  bool enabled = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  double total_ms = 0.0;
+  int64_t count = 0;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Error err{0, ""};
+  vip_options opt{};
+  bool built = false;
+
+  // node set
+  int64_t n = 0, nb = 0;
+  double h = 0.0, rho0 = 0.0;
+  bool periodic = false, singular = false, symmetric = false;
+  double* x = nullptr;            // device [n]
+  double* y = nullptr;            // device [n]
+  int32_t* bpos = nullptr;        // device [n]: boundary-table index or -1
+  int64_t* bidx = nullptr;        // device [nb]
+  double* bnx = nullptr;          // device [nb]
+  double* bny = nullptr;
+  int32_t* bkind = nullptr;       // device [nb]
+  double* bval = nullptr;         // device [nb*2]
+  std::vector<int32_t> h_bkind;   // host copy
+
+  // geometry
+  double* vip_px = nullptr;       // device [4*n]: VIP coordinates, k*n + i
+  double* vip_py = nullptr;
+  double* d_ew = nullptr;         // device [n]
+  double* d_ns = nullptr;
+  double* rho_node = nullptr;     // device [n]
+
+  // operators
+  Ell node;                       // val[0] = D^[0,0], val[1] = Laplacian
+  Ell vipop[4];                   // val[0] = Psi^[0,0] at e, w, n, s
+  Ell normal[2];                  // val[0] = Psi^[0,0] at x_b - d n, x_b - 2 d n
+  Ell sys;                        // val[0] = Poisson, val[1] = H_u, val[2] = H_v; val32 = Poisson
+  double* dinv[3] = {nullptr, nullptr, nullptr};   // Jacobi inverse diagonals (P, Hu, Hv)
+  float* dinv32 = nullptr;
+
+  // step state
+  double cur_dt = 0.0, cur_re = 0.0;
+  bool assembled = false;
+  bool have_prev_n = false;
+  bool have_prev_phi = false;
+  double* nprev = nullptr;        // device [2n]
+  double* stepbuf = nullptr;      // device [5n]: predictor right-hand sides, u*, v*, divergence
+  double* phi = nullptr;          // device [n+1] (last entry: border multiplier)
+  double* ws = nullptr;           // device work vectors (FP64)
+  int64_t ws_len = 0;
+  float* ws32 = nullptr;
+  int64_t ws32_len = 0;
+  double* partials = nullptr;     // device [max blocks * 8]
+  int64_t partials_len = 0;
+  unsigned int* counter = nullptr;  // device, last-block counter
+  KrylovScalars* sc = nullptr;    // device scalars
+  KrylovScalars* sc_host = nullptr; // pinned host mirror
+
+  Timing timing;
+};
+
+// ---- error handling -----------------------------------------------------------
+int set_error(Ctx* c, int code, const std::string& msg);
+
+#define VIP_HIP_TRY(c, expr)                                                        \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::vip::set_error((c), VIP_E_HIP, std::string(#expr) + ": " +           \
+                                                  hipGetErrorString(e_));           \
+  } while (0)
+
+#define VIP_TRY(expr)               \
+  do {                              \
+    int r_ = (expr);                \
+    if (r_ != VIP_OK) return r_;    \
+  } while (0)
+
+// ---- memory helpers -------------------------------------------------------------
+template <typename T>
+int dalloc(Ctx* c, T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * static_cast<size_t>(count));
+  if (e != hipSuccess)
+    return set_error(c, VIP_E_HIP, std::string("hipMalloc of ") +
+                                       std::to_string(sizeof(T) * count) + " bytes: " +
+                                       hipGetErrorString(e));
+  return VIP_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void ell_free(Ell& e);
+void ctx_free_build(Ctx* c);
+
+// Exclusive prefix sum of int64 values on the device (in place safe), writes the
+// total to *total_host (synchronous).
+int scan_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n, int64_t* total_host);
+
+// Grid size for one thread per item, rounded up to a multiple of the XCD count.
+inline int64_t grid_for(int64_t items, int block = kBlock) {
+  int64_t g = (items + block - 1) / block;
+  if (g < 1) g = 1;
+  return ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
+}
+
+// Map a hardware block index to a logical one so that consecutive logical
+// blocks run on the same XCD (blocks are dispatched to XCDs round-robin).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t grid) {
+  const int64_t per = grid / kNumXcd;
+  return (b % kNumXcd) * per + b / kNumXcd;
+}
+
+// Allocate an Ell's slice structure from per-row lengths already in e.rowlen.
+int ell_layout(Ctx* c, Ell& e);
+
+// Ensure the reduction scratch holds `blocks` partial slots of `per` doubles.
+int ensure_partials(Ctx* c, int64_t blocks, int per);
+
+// Sliced-ELL SpMV y = A x on value set `vs` (FP64), used by tests and helpers.
+int ell_apply(Ctx* c, const Ell& e, int vs, const double* x, double* y);
+
+// Solvers (krylov.hip)
+int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x0,
+                  vip_step_stats* st);
+int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, double* vs,
+                    vip_step_stats* st);
+int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, const double* bnrm,
+                   const int32_t* bkind, const double* bval, int64_t nb, int basis_order, double rho,
+                   double h, const vip_options* opt);
+int assemble_helmholtz(Ctx* c, double dt, double re);
+int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step_stats* st);
+int convection(Ctx* c, const double* u, const double* v, double* nx, double* ny);
+int divergence(Ctx* c, const double* u, const double* v, double* d);
+int gradient(Ctx* c, const double* f, double* gx, double* gy);
+
+}  // namespace vip

@@ -223,3 +223,49 @@ def jittered(spec, frac, seed):
     out.xy = xy
     out.name = spec.name + "_jit"
     return out
+
+
+def triangle_cavity(h, lid=1.0, gap=0.25, support=2.5):
+    """Equilateral triangle of side 1, horizontal lid on top, apex down.
+
+    Vertices (0, H), (1, H), (0.5, 0) with H = sqrt(3)/2.  Boundary nodes sit
+    on the edges at spacing close to h (vertices once each); lattice nodes
+    x = i h, y = j h strictly inside and at least gap*h from every edge.  The
+    lid (top edge, corners excluded) moves with u = lid; the other edges and
+    the three corners are walls.
+    """
+    H = math.sqrt(3.0) / 2.0
+    verts = np.array([[0.0, H], [1.0, H], [0.5, 0.0]])
+    # edges (a, b, outward normal, kind value)
+    edges = [(verts[0], verts[1], np.array([0.0, 1.0]), (lid, 0.0)),
+             (verts[1], verts[2], np.array([H, -0.5]), (0.0, 0.0)),
+             (verts[2], verts[0], np.array([-H, -0.5]), (0.0, 0.0))]
+    nx = int(round(1.0 / h)) + 1
+    ny = int(round(H / h)) + 1
+    lat = _lattice(0.0, 0.0, nx, ny, h)
+    inside = np.ones(len(lat), bool)
+    for a, b, nrm, _ in edges:
+        inside &= (lat - a) @ nrm <= -gap * h     # signed distance to the edge line
+    lat = lat[inside]
+    n_lat = len(lat)
+    bxy, bn, bv = [], [], []
+    m = int(round(1.0 / h))
+    corner_normals = [np.array([-H, 0.5]), np.array([H, 0.5]), np.array([0.0, -1.0])]
+    for k, (a, b, nrm, val) in enumerate(edges):
+        # the corner at the start of each edge, then the edge interior
+        bxy.append(a)
+        cn = corner_normals[k]
+        bn.append(cn / np.linalg.norm(cn))
+        bv.append((0.0, 0.0))
+        t = np.arange(1, m) / m
+        pts = a[None, :] + t[:, None] * (b - a)[None, :]
+        bxy.extend(pts)
+        bn.extend([nrm] * len(pts))
+        bv.extend([val] * len(pts))
+    bxy = np.array(bxy)
+    xy = np.concatenate([lat, bxy])
+    nb = len(bxy)
+    return NodeSetSpec(name="triangle_h%g" % h, xy=xy, h=h, rho=support * h,
+                       bnd_idx=n_lat + np.arange(nb, dtype=np.int64), bnd_normal=np.array(bn),
+                       bnd_kind=np.zeros(nb, np.int32), bnd_value=np.array(bv, dtype=np.float64),
+                       n_lattice=n_lat)

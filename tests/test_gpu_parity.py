@@ -1,0 +1,360 @@
+"""Parity of the HIP library against the FP64 oracle, element by element, on node
+sets shaped like the paper's cases at sizes the oracle finishes in seconds (all
+span several 64-row slices and end in a ragged slice).
+
+Bars: MLS-derived operators 1e-12 relative to the operator's largest entry
+(cubic spline; 100 * cond(M) * eps for the paper's weight), operator
+applications 1e-13, solves at a residual of 1e-12 within 1e-9 of the direct
+solve, full fractional steps within 1e-9 (FP64) and 1e-6 (mixed precision)
+relative in u, v and p (p without its mean where the pressure problem is
+singular)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import mls, operators, step
+from paper_1401_6513_amd import nodesets as ns
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _vip():
+    from paper_1401_6513_amd import vip
+    return vip
+
+
+def _specs():
+    return {
+        "tg32": ns.periodic_lattice(32),
+        "cavity33": ns.lid_cavity(33),
+        "cylinder": ns.cylinder_channel(0.1, box=(-2.0, 4.0, -2.0, 2.0), n_surface=32),
+        "bumpy": ns.cylinder_channel(1.0 / 16, box=(-1.5, 3.0, -1.5, 1.5), shape=(0.05, 12),
+                                     n_surface=64),
+        "triangle": ns.triangle_cavity(1.0 / 32),
+        "jittered": ns.jittered(ns.lid_cavity(25), 0.25, seed=2),
+    }
+
+
+RUNS = {"tg32": (1e-3, 10.0), "cavity33": (2e-3, 100.0), "cylinder": (0.01, 100.0),
+        "bumpy": (0.01, 100.0), "triangle": (2e-3, 200.0), "jittered": (2e-3, 100.0)}
+
+
+def _to_csr(cols, vals, ncols):
+    rows = np.repeat(np.arange(cols.shape[0]), cols.shape[1])
+    c = cols.ravel()
+    m = c >= 0
+    return sp.csr_matrix((vals.ravel()[m], (rows[m], c[m])), shape=(cols.shape[0], ncols))
+
+
+def _initial(name, spec):
+    if name == "tg32":
+        return ns.taylor_green_initial(spec.xy)
+    if name in ("cylinder", "bumpy"):
+        return ns.boundary_initial(spec, (1.0, 0.0))
+    return ns.boundary_initial(spec)
+
+
+class Case:
+    def __init__(self, name, spec, **opts):
+        vip = _vip()
+        self.name, self.spec = name, spec
+        self.ctx = vip.Context(0)
+        self.ctx.build_from_spec(spec, **opts)
+        weight = opts.get("weight", mls.CUBIC_SPLINE)
+        self.prob = operators.Problem(**spec.as_kwargs(), weight_kind=weight)
+        self.ops = operators.Operators(self.prob)
+
+
+@pytest.fixture(scope="module")
+def cases():
+    out = {name: Case(name, spec, poisson_tol=1e-12) for name, spec in _specs().items()}
+    yield out
+    for c in out.values():
+        c.ctx.close()
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+# ---- build: geometry and operators ---------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(RUNS))
+def test_geometry(cases, name):
+    c = cases[name]
+    vxy, dew, dns, rho = c.ctx.vip_get_geometry()
+    inner = c.prob.interior
+    assert np.abs(vxy[inner] - c.ops.vip_xy).max() <= 1e-15 * max(1.0, np.abs(c.spec.xy).max())
+    assert np.abs(dew - c.ops.d_ew).max() < 1e-15 and np.abs(dns - c.ops.d_ns).max() < 1e-15
+    assert np.array_equal(rho, c.ops.rho_node)
+    assert np.all(vxy[c.prob.bnd_idx] == 0.0)
+
+
+@pytest.mark.parametrize("name", list(RUNS))
+def test_operators_match(cases, name):
+    c = cases[name]
+    dt, re = RUNS[name]
+    st = step.Stepper(c.ops, dt, re)
+    c.ctx.vip_assemble(dt, re)
+    nb = len(c.prob.bnd_idx)
+    pairs = [("identity", c.ops.M00), ("laplacian", c.ops.L), ("vip_e", c.ops.VIP[0]),
+             ("vip_w", c.ops.VIP[1]), ("vip_n", c.ops.VIP[2]), ("vip_s", c.ops.VIP[3]),
+             ("poisson", st.P), ("helm_u", st.Hu), ("helm_v", st.Hv)]
+    if nb:
+        pairs += [("normal1", c.ops.NB[0][c.prob.bnd_idx]), ("normal2", c.ops.NB[1][c.prob.bnd_idx])]
+    for op, M in pairs:
+        cols, vals = c.ctx.vip_get_operator(op)
+        G = _to_csr(cols, vals, c.spec.n)
+        assert G.shape == M.shape, op
+        err = abs(G - M).max() / abs(M).max()
+        assert err <= 1e-12, (name, op, err)
+        # every stored column is a node within the (grown) support of the row
+        assert cols.max() < c.spec.n
+    # FP32 pressure matrix is the rounded FP64 one
+    cols, v32 = c.ctx.vip_get_operator("poisson32")
+    _, v64 = c.ctx.vip_get_operator("poisson")
+    assert np.array_equal(v32, v64.astype(np.float32).astype(np.float64))
+
+
+def test_paper_weight_operators():
+    spec = ns.lid_cavity(21)
+    case = Case("paper", spec, weight=mls.PAPER)
+    try:
+        nodes = mls.NodeSet(spec.xy)
+        cond = max(mls.moment_condition(nodes, p, spec.rho, mls.PAPER) for p in spec.xy[::3])
+        tol = max(1e-12, 100.0 * cond * np.finfo(float).eps)
+        for op, M in (("identity", case.ops.M00), ("laplacian", case.ops.L),
+                      ("vip_e", case.ops.VIP[0])):
+            cols, vals = case.ctx.vip_get_operator(op)
+            err = abs(_to_csr(cols, vals, spec.n) - M).max() / abs(M).max()
+            assert err <= tol, (op, err, tol)
+    finally:
+        case.ctx.close()
+
+
+@pytest.mark.parametrize("name", list(RUNS))
+def test_operator_application(cases, name):
+    c = cases[name]
+    x = ns.random_field(c.spec.n, seed=10)
+    xd = _dev(x)
+    y = torch.empty_like(xd)
+    for op, M in (("identity", c.ops.M00), ("laplacian", c.ops.L), ("vip_n", c.ops.VIP[2])):
+        c.ctx.vip_apply(op, xd, y)
+        ref = M @ x
+        assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max(), op
+
+
+@pytest.mark.parametrize("name", list(RUNS))
+def test_vip_differences(cases, name):
+    c = cases[name]
+    u = ns.random_field(c.spec.n, seed=11)
+    v = ns.random_field(c.spec.n, seed=12)
+    ud, vd = _dev(u), _dev(v)
+    a, b = torch.empty_like(ud), torch.empty_like(ud)
+    c.ctx.vip_convection(ud, vd, a, b)
+    nx, ny = c.ops.convection(u, v)
+    scale = max(np.abs(nx).max(), np.abs(ny).max())
+    assert np.abs(a.cpu().numpy() - nx).max() <= 1e-13 * scale
+    assert np.abs(b.cpu().numpy() - ny).max() <= 1e-13 * scale
+    c.ctx.vip_divergence(ud, vd, a)
+    d = c.ops.divergence(u, v)
+    assert np.abs(a.cpu().numpy() - d).max() <= 1e-13 * np.abs(d).max()
+    c.ctx.vip_gradient(ud, a, b)
+    gx, gy = c.ops.ddx(u), c.ops.ddy(u)
+    assert np.abs(a.cpu().numpy() - gx).max() <= 1e-13 * np.abs(gx).max()
+    assert np.abs(b.cpu().numpy() - gy).max() <= 1e-13 * np.abs(gy).max()
+
+
+# ---- solves -----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(RUNS))
+def test_pressure_solve(cases, name):
+    c = cases[name]
+    dt, re = RUNS[name]
+    st = step.Stepper(c.ops, dt, re)
+    b = ns.random_field(c.spec.n, seed=13)
+    b[c.prob.bnd_idx] = 0.0
+    ref = st.poisson_solve(b)
+    phi = torch.zeros(c.spec.n, dtype=torch.float64, device="cuda")
+    stats = c.ctx.vip_poisson_solve(_dev(b), phi, 1e-12)
+    assert stats["poisson_residual"] <= 1e-12
+    got = phi.cpu().numpy()
+    if st.bordered:
+        assert abs(got.sum()) <= 1e-9 * np.abs(got).max() * c.spec.n
+        assert abs(stats["border_lambda"] - st.lam) <= 1e-8 * max(1.0, abs(st.lam))
+    assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max(), np.abs(got - ref).max()
+    # residual recomputed by the oracle's own matrix
+    if st.bordered:
+        res = b - (st.P @ got + stats["border_lambda"])
+    else:
+        res = b - st.P @ got
+    assert np.linalg.norm(res) <= 2e-12 * np.linalg.norm(b)
+
+
+# ---- full steps ------------------------------------------------------------------------------------
+
+def _run_pair(case, steps, dt, re, oracle_steps=None, **opts):
+    vip = _vip()
+    if opts:
+        o = vip.default_options(period=case.spec.period, **opts)
+        case.ctx.vip_set_options(o)
+    case.ctx.vip_reset_history()
+    st = step.Stepper(case.ops, dt, re)
+    u0, v0, p0 = _initial(case.name, case.spec)
+    u, v, p = _dev(u0), _dev(v0), _dev(p0)
+    uo, vo, po = u0.copy(), v0.copy(), p0.copy()
+    stats = []
+    for _ in range(steps):
+        stats.append(case.ctx.vip_step(u, v, p, dt, re))
+        uo, vo, po = st.step(uo, vo, po)
+    return (u.cpu().numpy(), v.cpu().numpy(), p.cpu().numpy()), (uo, vo, po), st, stats
+
+
+def _rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _field_errors(got, ref, singular):
+    ug, vg, pg = got
+    uo, vo, po = ref
+    if singular:
+        pg = pg - pg.mean()
+        po = po - po.mean()
+    return _rel_l2(ug, uo), _rel_l2(vg, vo), _rel_l2(pg, po)
+
+
+@pytest.mark.parametrize("name,steps", [("tg32", 100), ("cavity33", 30), ("cylinder", 15),
+                                        ("bumpy", 10), ("triangle", 20), ("jittered", 20)])
+def test_fractional_steps_fp64(cases, name, steps):
+    c = cases[name]
+    dt, re = RUNS[name]
+    got, ref, st, stats = _run_pair(c, steps, dt, re, poisson_tol=1e-12, precision=0)
+    errs = _field_errors(got, ref, st.bordered)
+    assert max(errs) <= 1e-9, (name, errs)
+    assert all(s["poisson_residual"] <= 1e-12 for s in stats)
+
+
+@pytest.mark.parametrize("name,steps", [("tg32", 100), ("cavity33", 20), ("cylinder", 10)])
+def test_fractional_steps_mixed_precision(cases, name, steps):
+    c = cases[name]
+    dt, re = RUNS[name]
+    got, ref, st, stats = _run_pair(c, steps, dt, re, poisson_tol=1e-10, precision=1)
+    errs = _field_errors(got, ref, st.bordered)
+    assert max(errs) <= 1e-6, (name, errs)
+    assert all(s["poisson_residual"] <= 1e-10 and s["poisson_outer"] >= 2 for s in stats)
+    c.ctx.vip_set_options(_vip().default_options(period=c.spec.period, poisson_tol=1e-12))
+
+
+def test_exact_identity_variant(cases):
+    c = cases["cylinder"]
+    dt, re = RUNS["cylinder"]
+    vip = _vip()
+    c.ctx.vip_set_options(vip.default_options(period=c.spec.period, poisson_tol=1e-12,
+                                              identity=vip.I_EXACT))
+    c.ctx.vip_reset_history()
+    st = step.Stepper(c.ops, dt, re, identity=step.IDENTITY_EXACT)
+    u0, v0, p0 = _initial("cylinder", c.spec)
+    u, v, p = _dev(u0), _dev(v0), _dev(p0)
+    uo, vo, po = u0, v0, p0
+    for _ in range(5):
+        c.ctx.vip_step(u, v, p, dt, re)
+        uo, vo, po = st.step(uo, vo, po)
+    errs = _field_errors((u.cpu().numpy(), v.cpu().numpy(), p.cpu().numpy()), (uo, vo, po), False)
+    assert max(errs) <= 1e-9, errs
+    c.ctx.vip_set_options(vip.default_options(period=c.spec.period, poisson_tol=1e-12))
+
+
+def test_repeat_runs_are_bitwise_identical(cases):
+    c = cases["cavity33"]
+    dt, re = RUNS["cavity33"]
+    outs = []
+    for _ in range(2):
+        c.ctx.vip_reset_history()
+        u0, v0, p0 = _initial("cavity33", c.spec)
+        u, v, p = _dev(u0), _dev(v0), _dev(p0)
+        for _ in range(5):
+            c.ctx.vip_step(u, v, p, dt, re)
+        outs.append(torch.cat([u, v, p]).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_warm_start_keeps_the_solution(cases):
+    c = cases["cylinder"]
+    dt, re = RUNS["cylinder"]
+    vip = _vip()
+    res = {}
+    for ws in (vip.WS_ZERO, vip.WS_PREV):
+        c.ctx.vip_set_options(vip.default_options(period=c.spec.period, poisson_tol=1e-11,
+                                                  warmstart=ws))
+        c.ctx.vip_reset_history()
+        u0, v0, p0 = _initial("cylinder", c.spec)
+        u, v, p = _dev(u0), _dev(v0), _dev(p0)
+        its = 0
+        for _ in range(8):
+            its += c.ctx.vip_step(u, v, p, dt, re)["poisson_iters"]
+        res[ws] = (torch.cat([u, v, p]).cpu().numpy(), its)
+    a, b = res[vip.WS_ZERO][0], res[vip.WS_PREV][0]
+    assert np.abs(a - b).max() <= 1e-8 * np.abs(a).max()
+    assert res[vip.WS_PREV][1] < res[vip.WS_ZERO][1]
+    c.ctx.vip_set_options(vip.default_options(period=c.spec.period, poisson_tol=1e-12))
+
+
+# ---- error paths --------------------------------------------------------------------------------
+
+def test_invalid_arguments_are_rejected():
+    vip = _vip()
+    ctx = vip.Context(0)
+    try:
+        spec = ns.lid_cavity(9)
+        with pytest.raises(vip.VipError) as e:
+            ctx.vip_build_stencils(spec.xy, spec.bnd_idx, spec.bnd_normal, spec.bnd_kind,
+                                   spec.bnd_value, -1.0, spec.h)
+        assert e.value.code == -1
+        bad = spec.xy.copy()
+        bad[3, 0] = np.nan
+        with pytest.raises(vip.VipError) as e:
+            ctx.vip_build_stencils(bad, spec.bnd_idx, spec.bnd_normal, spec.bnd_kind,
+                                   spec.bnd_value, spec.rho, spec.h)
+        assert e.value.code == -1
+        with pytest.raises(vip.VipError) as e:
+            ctx.vip_build_stencils(spec.xy, spec.bnd_idx, spec.bnd_normal, spec.bnd_kind,
+                                   spec.bnd_value, spec.rho, spec.h, basis_order=1)
+        assert e.value.code == -1
+        u = torch.zeros(spec.n, dtype=torch.float64, device="cuda")
+        with pytest.raises(vip.VipError) as e:       # not built yet
+            ctx.vip_step(u, u.clone(), u.clone(), 1e-3, 10.0)
+        assert e.value.code == -5
+        # collinear nodes: every moment matrix is singular
+        line = np.stack([np.linspace(0.0, 1.0, 40), np.zeros(40)], axis=1)
+        with pytest.raises(vip.VipError) as e:
+            ctx.vip_build_stencils(line, [], np.zeros((0, 2)), [], np.zeros((0, 2)), 0.2, 1.0 / 39)
+        assert e.value.code == -2
+        # too few neighbours even after growth
+        with pytest.raises(vip.VipError) as e:
+            ctx.vip_build_stencils(spec.xy, spec.bnd_idx, spec.bnd_normal, spec.bnd_kind,
+                                   spec.bnd_value, 0.6 * spec.h, spec.h)
+        assert e.value.code == -2
+        # a good build after failures works
+        ctx.vip_build_stencils(spec.xy, spec.bnd_idx, spec.bnd_normal, spec.bnd_kind,
+                               spec.bnd_value, spec.rho, spec.h)
+        with pytest.raises(vip.VipError) as e:
+            ctx.vip_step(u, u.clone(), u.clone(), -1.0, 10.0)
+        assert e.value.code == -1
+    finally:
+        ctx.close()
+
+
+def test_nonconvergence_is_reported(cases):
+    c = cases["cavity33"]
+    vip = _vip()
+    c.ctx.vip_set_options(vip.default_options(period=c.spec.period, poisson_tol=1e-12,
+                                              max_iters=8, check_every=4))
+    b = ns.random_field(c.spec.n, seed=21)
+    b[c.prob.bnd_idx] = 0.0
+    phi = torch.zeros(c.spec.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(vip.VipError) as e:
+        c.ctx.vip_poisson_solve(_dev(b), phi, 1e-12)
+    assert e.value.code == -3
+    c.ctx.vip_set_options(vip.default_options(period=c.spec.period, poisson_tol=1e-12))

@@ -54,11 +54,11 @@ def _initial(spec, dev):
     return [torch.tensor(a, device=dev) for a in (u, v, p)]
 
 
-def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv):
+def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol):
     import torch
     dev = torch.device("cuda", 0)
     for ctx, spec in zip(ctxs, specs):
-        opt = vip.default_options(period=spec.period, poisson_tol=tol,
+        opt = vip.default_options(period=spec.period, poisson_tol=tol, inner_tol=inner_tol,
                                   precision=vip.P_MIXED if path == "mixed" else vip.P_FP64,
                                   warmstart=vip.WS_PREV if path == "mixed" else vip.WS_ZERO)
         ctx.vip_set_options(opt)
@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--h", type=float, default=1.0 / 128)
     ap.add_argument("--re", type=float, default=200.0)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--inner-tol", type=float, default=1e-4,
+                    help="relative tolerance of the FP32 inner solve (mixed path)")
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -166,7 +168,7 @@ def main():
     results = {}
     for path in paths:
         el, stats, spmv, fields = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
-                                           args.steps, args.tol, time_spmv=(path == "mixed"))
+                                           args.steps, args.tol, (path == "mixed"), args.inner_tol)
         results[path] = dict(seconds=el, stats=stats, spmv=spmv, fields=fields)
         log("%s: %.3f s for %d steps" % (path, el, args.steps))
 

@@ -59,6 +59,7 @@ enum { VIP_P_FP64 = 0, VIP_P_MIXED = 1 };           /* Poisson: FP64 Krylov, or 
                                                        inner Krylov in FP64 refinement */
 enum { VIP_K_AUTO = 0, VIP_K_PCG = 1, VIP_K_BICGSTAB = 2 };
 enum { VIP_WS_ZERO = 0, VIP_WS_PREV = 1 };          /* Poisson start vector in vip_step */
+enum { VIP_PC_JACOBI = 0, VIP_PC_AMG = 1 };         /* Poisson preconditioner */
 
 typedef struct {
   int weight;             /* VIP_W_*; default VIP_W_CUBIC_SPLINE */
@@ -74,6 +75,9 @@ typedef struct {
   double inner_tol;       /* relative tolerance of the FP32 inner solve (MIXED); default 1e-4 */
   int max_iters;          /* Krylov iteration limit per solve; default 200000 */
   int check_every;        /* iterations between host convergence checks; default 16 */
+  int preconditioner;     /* VIP_PC_*; default VIP_PC_AMG: aggregation multigrid V-cycle
+                             (2x2-cell aggregates, Galerkin coarse matrices, damped Jacobi
+                             smoothing, dense coarsest solve), built at the first solve */
 } vip_options;
 
 typedef struct {

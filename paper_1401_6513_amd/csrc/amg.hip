@@ -1,0 +1,612 @@
+// Aggregation multigrid preconditioner for the pressure Poisson system.
+//
+// The pressure matrix of a long channel with the only Dirichlet rows at the
+// outlet has eigenvalues down to ~h^2 / L^2 of its diagonal scale, and
+// Jacobi-preconditioned Krylov methods stall or diverge on it at a few
+// hundred thousand nodes.  This preconditioner adds the missing coarse-scale
+// correction:
+//   * aggregates are the occupied cells of a grid of size 2^(l+1) h (2 x 2
+//     cells of the level below), so every level keeps the geometry of the
+//     node set; rows without off-diagonal entries (phi = 0 outlet rows) stay
+//     out of the coarse spaces;
+//   * coarse matrices are Galerkin products R A R^T with R the aggregate
+//     indicator, summed per coarse row from sorted member lists (fixed order,
+//     so the build is deterministic);
+//   * the coarsest matrix (bordered when the system is singular) is inverted
+//     once by Gauss-Jordan with partial pivoting and applied as a dense product;
+//   * one V-cycle with one damped Jacobi sweep before and after the coarse
+//     correction; the pre-sweep from zero is fused with the residual, the
+//     prolongation with the post-sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "vip_internal.h"
+
+namespace vip {
+
+namespace {
+
+constexpr double kOmega = 0.7;       // Jacobi damping
+constexpr int64_t kCoarseRows = 768;  // stop coarsening at or below this size
+constexpr int kMaxCoarseWidth = 128;
+
+__device__ __forceinline__ int64_t slot(const int64_t* ptr, int64_t r, int k) {
+  return ptr[r / kSlice] + static_cast<int64_t>(k) * kSlice + (r % kSlice);
+}
+
+// keep[i] = 1 if row i has a nonzero off-diagonal entry
+__global__ void k_keep(int64_t n, const int64_t* ptr, const int32_t* cols, const int32_t* rowlen,
+                       const double* val, int32_t* keep) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  int k = 0;
+  for (int t = 0; t < rowlen[i]; ++t) {
+    const int64_t s = slot(ptr, i, t);
+    if (cols[s] != static_cast<int32_t>(i) && val[s] != 0.0) k = 1;
+  }
+  keep[i] = k;
+}
+
+// damped inverse diagonal (identity rows: plain inverse, so one sweep solves them)
+__global__ void k_wdinv(int64_t n, const int64_t* ptr, const int32_t* cols, const int32_t* rowlen,
+                        const double* val, const int32_t* keep, double omega, double* w64, float* w32) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int t = 0; t < rowlen[i]; ++t) {
+    const int64_t s = slot(ptr, i, t);
+    if (cols[s] == static_cast<int32_t>(i)) d += val[s];
+  }
+  const double w = d != 0.0 ? (keep[i] ? omega : 1.0) / d : 0.0;
+  w64[i] = w;
+  w32[i] = static_cast<float>(w);
+}
+
+// level-0 aggregation keys: cell of size 2h
+__global__ void k_key0(int64_t n, const double* x, const double* y, double x0, double y0, double cell,
+                       int32_t* kx, int32_t* ky) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  kx[i] = static_cast<int32_t>(floor((x[i] - x0) / cell));
+  ky[i] = static_cast<int32_t>(floor((y[i] - y0) / cell));
+}
+
+__global__ void k_mark(int64_t n, const int32_t* keep, const int32_t* kx, const int32_t* ky, int64_t gx,
+                       int64_t* occ) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n || !keep[i]) return;
+  occ[static_cast<int64_t>(ky[i]) * gx + kx[i]] = 1;
+}
+
+__global__ void k_assign(int64_t n, const int32_t* keep, const int32_t* kx, const int32_t* ky, int64_t gx,
+                         const int64_t* idx, int32_t* agg, int32_t* ckx, int32_t* cky,
+                         unsigned long long* count) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  if (!keep[i]) {
+    agg[i] = -1;
+    return;
+  }
+  const int64_t a = idx[static_cast<int64_t>(ky[i]) * gx + kx[i]];
+  agg[i] = static_cast<int32_t>(a);
+  // key of the coarse row for the next aggregation (parent cell); same value from every member
+  ckx[a] = kx[i] >> 1;
+  cky[a] = ky[i] >> 1;
+  atomicAdd(&count[a], 1ull);
+}
+
+__global__ void k_members(int64_t n, const int32_t* agg, const int64_t* mstart, unsigned long long* cursor,
+                          int32_t* members) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n || agg[i] < 0) return;
+  const unsigned long long k = atomicAdd(&cursor[agg[i]], 1ull);
+  members[mstart[agg[i]] + static_cast<int64_t>(k)] = static_cast<int32_t>(i);
+}
+
+// sort each member list by row index (fixed summation order)
+__global__ void k_sort_members(int64_t nc, const int64_t* mstart, int32_t* members) {
+  const int64_t a = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (a >= nc) return;
+  for (int64_t p = mstart[a] + 1; p < mstart[a + 1]; ++p) {
+    const int32_t v = members[p];
+    int64_t q = p;
+    while (q > mstart[a] && members[q - 1] > v) {
+      members[q] = members[q - 1];
+      --q;
+    }
+    members[q] = v;
+  }
+}
+
+// Galerkin row I of R A R^T: count (fill == 0) or write (fill == 1) its sorted entries.
+__global__ void k_galerkin(int64_t nc, const int64_t* mstart, const int32_t* members, const int64_t* ptr,
+                           const int32_t* cols, const int32_t* rowlen, const double* val, const int32_t* agg,
+                           int fill, int32_t* crowlen, const int64_t* cptr, int32_t* ccols, double* cval,
+                           unsigned long long* overflow) {
+  const int64_t I = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (I >= nc) return;
+  int32_t J[kMaxCoarseWidth];
+  double V[kMaxCoarseWidth];
+  int cnt = 0;
+  bool over = false;
+  for (int64_t m = mstart[I]; m < mstart[I + 1]; ++m) {
+    const int64_t i = members[m];
+    for (int t = 0; t < rowlen[i]; ++t) {
+      const int64_t s = slot(ptr, i, t);
+      const int32_t a = agg[cols[s]];
+      if (a < 0) continue;
+      int q = 0;
+      while (q < cnt && J[q] != a) ++q;
+      if (q == cnt) {
+        if (cnt == kMaxCoarseWidth) {
+          over = true;
+          continue;
+        }
+        J[cnt] = a;
+        V[cnt] = 0.0;
+        ++cnt;
+      }
+      V[q] += val[s];
+    }
+  }
+  if (over) atomicMin(overflow, static_cast<unsigned long long>(I));
+  if (!fill) {
+    crowlen[I] = cnt;
+    return;
+  }
+  // insertion sort by column
+  for (int p = 1; p < cnt; ++p) {
+    const int32_t jv = J[p];
+    const double vv = V[p];
+    int q = p;
+    while (q > 0 && J[q - 1] > jv) {
+      J[q] = J[q - 1];
+      V[q] = V[q - 1];
+      --q;
+    }
+    J[q] = jv;
+    V[q] = vv;
+  }
+  for (int p = 0; p < cnt; ++p) {
+    const int64_t s = slot(cptr, I, p);
+    ccols[s] = J[p];
+    cval[s] = V[p];
+  }
+}
+
+// ---- coarsest level: dense Gauss-Jordan inverse -------------------------------------------------
+
+__global__ void k_dense_fill(int64_t m, int border, const int64_t* ptr, const int32_t* cols,
+                             const int32_t* rowlen, const double* val, double* D, double* Inv) {
+  const int64_t m1 = m + border;
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (e >= m1 * m1) return;
+  const int64_t i = e / m1, j = e % m1;
+  Inv[e] = i == j ? 1.0 : 0.0;
+  double v = 0.0;
+  if (i < m && j < m) {
+    for (int t = 0; t < rowlen[i]; ++t) {
+      const int64_t s = slot(ptr, i, t);
+      if (cols[s] == static_cast<int32_t>(j)) v += val[s];
+    }
+  } else if (i != j) {
+    v = 1.0;   // border row and column
+  }
+  D[e] = v;
+}
+
+// pivot search and row swap for column k (one block)
+__global__ void k_gj_pivot(int64_t m1, int64_t k, double* D, double* Inv, double* col, int* bad) {
+  __shared__ double best[256];
+  __shared__ int64_t arg[256];
+  double b = -1.0;
+  int64_t a = k;
+  for (int64_t i = k + threadIdx.x; i < m1; i += blockDim.x) {
+    const double v = fabs(D[i * m1 + k]);
+    if (v > b) {
+      b = v;
+      a = i;
+    }
+  }
+  best[threadIdx.x] = b;
+  arg[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) {
+      const double o = best[threadIdx.x + off];
+      const int64_t oa = arg[threadIdx.x + off];
+      if (o > best[threadIdx.x] || (o == best[threadIdx.x] && oa < arg[threadIdx.x])) {
+        best[threadIdx.x] = o;
+        arg[threadIdx.x] = oa;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t p = arg[0];
+  if (threadIdx.x == 0 && !(best[0] > 0.0)) *bad = 1;
+  if (p != k) {
+    for (int64_t j = threadIdx.x; j < m1; j += blockDim.x) {
+      double t = D[k * m1 + j];
+      D[k * m1 + j] = D[p * m1 + j];
+      D[p * m1 + j] = t;
+      t = Inv[k * m1 + j];
+      Inv[k * m1 + j] = Inv[p * m1 + j];
+      Inv[p * m1 + j] = t;
+    }
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < m1; i += blockDim.x) col[i] = D[i * m1 + k];
+}
+
+// eliminate column k from every row but k, then (separately) scale row k
+__global__ void k_gj_elim(int64_t m1, int64_t k, double* D, double* Inv, const double* col) {
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (e >= m1 * m1) return;
+  const int64_t i = e / m1, j = e % m1;
+  if (i == k) return;
+  const double f = col[i] / col[k];
+  if (f == 0.0) return;
+  D[e] -= f * D[k * m1 + j];
+  Inv[e] -= f * Inv[k * m1 + j];
+}
+
+__global__ void k_gj_scale(int64_t m1, int64_t k, double* D, double* Inv, const double* col) {
+  const int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (j >= m1) return;
+  const double p = col[k];
+  D[k * m1 + j] /= p;
+  Inv[k * m1 + j] /= p;
+}
+
+__global__ void k_to32(int64_t m, const double* a, float* b) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < m) b[i] = static_cast<float>(a[i]);
+}
+
+// ---- V-cycle kernels ----------------------------------------------------------------------------
+
+template <typename T>
+struct LevelView {
+  int64_t n;
+  const int64_t* ptr;
+  const int32_t* cols;
+  const T* val;
+  const T* wdinv;
+  const float* rsum;   // FP32 levels: row sums for the difference form
+};
+
+// (A y)_i with y_j given by a functor; FP32 levels use the difference form
+// rsum_i y_i + sum a_ij (y_j - y_i) (rows sum to ~0, see row_dot in the solver).
+template <typename T, class Y>
+__device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
+  const int64_t sl = i / kSlice;
+  const int64_t base = L.ptr[sl] + (i % kSlice);
+  const int64_t w = (L.ptr[sl + 1] - L.ptr[sl]) / kSlice;
+  if constexpr (sizeof(T) == 4) {
+    const T yi = y(static_cast<int32_t>(i));
+    T acc = T(0);
+    for (int64_t k = 0; k < w; ++k) {
+      const int64_t q = base + k * kSlice;
+      acc += L.val[q] * (y(L.cols[q]) - yi);
+    }
+    return acc + L.rsum[i] * yi;
+  } else {
+    T acc = T(0);
+    for (int64_t k = 0; k < w; ++k) {
+      const int64_t q = base + k * kSlice;
+      acc += L.val[q] * y(L.cols[q]);
+    }
+    return acc;
+  }
+}
+
+// x = W b; r = b - A W b   (pre-smoothing sweep from zero fused with the residual)
+template <typename T>
+__global__ void k_pre(LevelView<T> L, const T* b, T* x, T* r, const int* on) {
+  if (!*on) return;
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = lb * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  const T acc = level_row(L, i, [&](int32_t j) { return L.wdinv[j] * b[j]; });
+  const T bi = b[i];
+  x[i] = L.wdinv[i] * bi;
+  r[i] = bi - acc;
+}
+
+// bc[I] = sum of r over the members of aggregate I
+template <typename T>
+__global__ void k_restrict(int64_t nc, const int64_t* mstart, const int32_t* members, const T* r, T* bc,
+                           const int* on) {
+  if (!*on) return;
+  const int64_t I = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (I >= nc) return;
+  T s = T(0);
+  for (int64_t m = mstart[I]; m < mstart[I + 1]; ++m) s += r[members[m]];
+  bc[I] = s;
+}
+
+// y = x + P xc; out = y + W (b - A y)   (prolongation fused with the post-smoothing sweep)
+template <typename T>
+__global__ void k_post(LevelView<T> L, const int32_t* agg, const T* xc, const T* b, const T* x, T* out,
+                       const int* on) {
+  if (!*on) return;
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = lb * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  auto y = [&](int32_t j) {
+    const int32_t a = agg[j];
+    return x[j] + (a >= 0 ? xc[a] : T(0));
+  };
+  const T acc = level_row(L, i, y);
+  out[i] = y(static_cast<int32_t>(i)) + L.wdinv[i] * (b[i] - acc);
+}
+
+// x[0..rows) = Inv[0..rows, 0..cols) b on the coarsest level (one wavefront per row);
+// rows = cols = m applies the block that leaves out the border, rows = cols = m1
+// the whole bordered inverse.
+template <typename T>
+__global__ void k_dense_apply(int64_t rows, int64_t cols, int64_t ld, const T* Inv, const T* b, T* x,
+                              const int* on) {
+  if (!*on) return;
+  const int64_t row = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  double acc = 0.0;
+  for (int64_t j = lane; j < cols; j += 64) acc += static_cast<double>(Inv[row * ld + j]) * static_cast<double>(b[j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) x[row] = static_cast<T>(acc);
+}
+
+}  // namespace
+
+void amg_free(Ctx* c) {
+  Amg& g = c->amg;
+  for (size_t l = 0; l < g.lv.size(); ++l) {
+    AmgLevel& L = g.lv[l];
+    if (l > 0) ell_free(L.A);
+    dfree(L.wdinv);
+    dfree(L.wdinv32);
+    dfree(L.agg);
+    dfree(L.keep);
+    dfree(L.kx);
+    dfree(L.ky);
+    dfree(L.mstart);
+    dfree(L.members);
+    for (int k = 0; k < 3; ++k) {
+      dfree(L.w64[k]);
+      dfree(L.w32[k]);
+    }
+  }
+  g.lv.clear();
+  dfree(g.cinv);
+  dfree(g.cinv32);
+  g.ready = false;
+}
+
+int amg_setup(Ctx* c) {
+  amg_free(c);
+  Amg& g = c->amg;
+  hipStream_t st = c->stream;
+  unsigned long long* flag = nullptr;
+  VIP_TRY(dalloc(c, &flag, 1));
+  int rc = VIP_OK;
+  // level 0 is the pressure matrix itself
+  g.lv.emplace_back();
+  {
+    AmgLevel& L0 = g.lv[0];
+    L0.n = c->n;
+    L0.A = c->sys;   // shallow view, not owned
+    L0.vs = 0;
+    VIP_TRY(dalloc(c, &L0.kx, c->n));
+    VIP_TRY(dalloc(c, &L0.ky, c->n));
+    k_key0<<<grid_for(c->n), kBlock, 0, st>>>(c->n, c->x, c->y, c->xmin, c->ymin, 2.0 * c->h,
+                                               L0.kx, L0.ky);
+  }
+  for (int level = 0; level < 24; ++level) {
+    AmgLevel& L = g.lv[level];
+    const Ell& A = L.A;
+    const double* aval = A.val[L.vs];
+    VIP_TRY(dalloc(c, &L.keep, L.n));
+    VIP_TRY(dalloc(c, &L.wdinv, L.n));
+    VIP_TRY(dalloc(c, &L.wdinv32, L.n));
+    k_keep<<<grid_for(L.n), kBlock, 0, st>>>(L.n, A.ptr, A.cols, A.rowlen, aval, L.keep);
+    k_wdinv<<<grid_for(L.n), kBlock, 0, st>>>(L.n, A.ptr, A.cols, A.rowlen, aval, L.keep, kOmega,
+                                               L.wdinv, L.wdinv32);
+    for (int k = 0; k < 3; ++k) {
+      VIP_TRY(dalloc(c, &L.w64[k], L.n + 1));
+      VIP_TRY(dalloc(c, &L.w32[k], L.n + 1));
+    }
+    if (L.n <= kCoarseRows) break;
+    // grid of aggregation keys
+    std::vector<int32_t> hx(L.n), hy(L.n);
+    VIP_HIP_TRY(c, hipMemcpyAsync(hx.data(), L.kx, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost, st));
+    VIP_HIP_TRY(c, hipMemcpyAsync(hy.data(), L.ky, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost, st));
+    VIP_HIP_TRY(c, hipStreamSynchronize(st));
+    int32_t mx = 0, my = 0, lx = 0, ly = 0;
+    for (int64_t i = 0; i < L.n; ++i) {
+      mx = std::max(mx, hx[i]);
+      my = std::max(my, hy[i]);
+      lx = std::min(lx, hx[i]);
+      ly = std::min(ly, hy[i]);
+    }
+    if (lx < 0 || ly < 0) {
+      rc = set_error(c, VIP_E_INVALID, "multigrid aggregation keys below the grid origin");
+      break;
+    }
+    const int64_t gx = static_cast<int64_t>(mx) + 1, gy = static_cast<int64_t>(my) + 1;
+    int64_t *occ = nullptr, *idx = nullptr;
+    VIP_TRY(dalloc(c, &occ, gx * gy));
+    VIP_TRY(dalloc(c, &idx, gx * gy + 1));
+    VIP_HIP_TRY(c, hipMemsetAsync(occ, 0, sizeof(int64_t) * gx * gy, st));
+    k_mark<<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.keep, L.kx, L.ky, gx, occ);
+    int64_t nc = 0;
+    rc = scan_i64(c, occ, idx, gx * gy, &nc);
+    if (rc != VIP_OK) break;
+    if (nc == 0 || nc * 10 > L.n * 9) {   // no useful coarsening left
+      dfree(occ);
+      dfree(idx);
+      break;
+    }
+    VIP_TRY(dalloc(c, &L.agg, L.n));
+    AmgLevel C;
+    C.n = nc;
+    VIP_TRY(dalloc(c, &C.kx, nc));
+    VIP_TRY(dalloc(c, &C.ky, nc));
+    unsigned long long* cnt = nullptr;
+    VIP_TRY(dalloc(c, &cnt, nc + 1));
+    VIP_HIP_TRY(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (nc + 1), st));
+    k_assign<<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.keep, L.kx, L.ky, gx, idx, L.agg, C.kx, C.ky, cnt);
+    dfree(occ);
+    dfree(idx);
+    VIP_TRY(dalloc(c, &L.mstart, nc + 1));
+    int64_t nm = 0;
+    rc = scan_i64(c, reinterpret_cast<const int64_t*>(cnt), L.mstart, nc, &nm);
+    if (rc != VIP_OK) break;
+    VIP_HIP_TRY(c, hipMemcpyAsync(L.mstart + nc, &nm, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    VIP_TRY(dalloc(c, &L.members, nm));
+    VIP_HIP_TRY(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (nc + 1), st));
+    k_members<<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, L.mstart, cnt, L.members);
+    k_sort_members<<<grid_for(nc), kBlock, 0, st>>>(nc, L.mstart, L.members);
+    dfree(cnt);
+    // Galerkin coarse matrix
+    C.A.nrows = nc;
+    VIP_TRY(dalloc(c, &C.A.rowlen, nc));
+    unsigned long long init = ~0ull;
+    VIP_HIP_TRY(c, hipMemcpyAsync(flag, &init, sizeof(init), hipMemcpyHostToDevice, st));
+    k_galerkin<<<grid_for(nc), kBlock, 0, st>>>(nc, L.mstart, L.members, A.ptr, A.cols, A.rowlen, aval,
+                                                 L.agg, 0, C.A.rowlen, nullptr, nullptr, nullptr, flag);
+    rc = ell_layout(c, C.A);
+    if (rc != VIP_OK) break;
+    VIP_TRY(dalloc(c, &C.A.val[0], C.A.nnz_slots));
+    VIP_HIP_TRY(c, hipMemsetAsync(C.A.val[0], 0, sizeof(double) * std::max<int64_t>(C.A.nnz_slots, 1), st));
+    k_galerkin<<<grid_for(nc), kBlock, 0, st>>>(nc, L.mstart, L.members, A.ptr, A.cols, A.rowlen, aval,
+                                                 L.agg, 1, C.A.rowlen, C.A.ptr, C.A.cols, C.A.val[0], flag);
+    VIP_TRY(dalloc(c, &C.A.val32, C.A.nnz_slots));
+    k_to32<<<grid_for(C.A.nnz_slots), kBlock, 0, st>>>(C.A.nnz_slots, C.A.val[0], C.A.val32);
+    VIP_TRY(dalloc(c, &C.A.rsum32, nc));
+    launch_rowsum32(st, nc, C.A.ptr, C.A.rowlen, C.A.val[0], C.A.rsum32);
+    unsigned long long bad = 0;
+    VIP_HIP_TRY(c, hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, st));
+    VIP_HIP_TRY(c, hipStreamSynchronize(st));
+    if (bad != ~0ull) {
+      rc = set_error(c, VIP_E_INVALID, "multigrid coarse row wider than 128 entries");
+      g.lv.push_back(C);
+      break;
+    }
+    C.vs = 0;
+    g.lv.push_back(C);
+  }
+  if (rc == VIP_OK) {
+    // dense inverse of the coarsest level (bordered if the system is singular)
+    AmgLevel& Lc = g.lv.back();
+    const int64_t m = Lc.n;
+    const int border = c->singular ? 1 : 0;
+    const int64_t m1 = m + border;
+    g.m = m;
+    g.m1 = m1;
+    if (m1 > 8192) {
+      dfree(flag);
+      return set_error(c, VIP_E_INVALID, "multigrid coarsening stalled at " + std::to_string(m) +
+                                             " rows (dense coarsest solve limited to 8192)");
+    }
+    double *D = nullptr, *col = nullptr;
+    int* badp = nullptr;
+    VIP_TRY(dalloc(c, &D, m1 * m1));
+    VIP_TRY(dalloc(c, &g.cinv, m1 * m1));
+    VIP_TRY(dalloc(c, &g.cinv32, m1 * m1));
+    VIP_TRY(dalloc(c, &col, m1));
+    VIP_TRY(dalloc(c, &badp, 1));
+    VIP_HIP_TRY(c, hipMemsetAsync(badp, 0, sizeof(int), st));
+    const int64_t ge = (m1 * m1 + kBlock - 1) / kBlock;
+    k_dense_fill<<<ge, kBlock, 0, st>>>(m, border, Lc.A.ptr, Lc.A.cols, Lc.A.rowlen, Lc.A.val[Lc.vs], D,
+                                         g.cinv);
+    for (int64_t k = 0; k < m1; ++k) {
+      k_gj_pivot<<<1, 256, 0, st>>>(m1, k, D, g.cinv, col, badp);
+      k_gj_elim<<<ge, kBlock, 0, st>>>(m1, k, D, g.cinv, col);
+      k_gj_scale<<<(m1 + kBlock - 1) / kBlock, kBlock, 0, st>>>(m1, k, D, g.cinv, col);
+    }
+    k_to32<<<ge, kBlock, 0, st>>>(m1 * m1, g.cinv, g.cinv32);
+    int bad = 0;
+    VIP_HIP_TRY(c, hipMemcpyAsync(&bad, badp, sizeof(int), hipMemcpyDeviceToHost, st));
+    VIP_HIP_TRY(c, hipStreamSynchronize(st));
+    dfree(D);
+    dfree(col);
+    dfree(badp);
+    if (bad) rc = set_error(c, VIP_E_SINGULAR, "coarsest multigrid matrix is singular");
+  }
+  dfree(flag);
+  VIP_HIP_TRY(c, hipGetLastError());
+  if (rc == VIP_OK) g.ready = true;
+  return rc;
+}
+
+template <typename T>
+static LevelView<T> view(const AmgLevel& L) {
+  LevelView<T> v;
+  v.n = L.n;
+  v.ptr = L.A.ptr;
+  v.cols = L.A.cols;
+  v.rsum = L.A.rsum32;
+  if constexpr (sizeof(T) == 4) {
+    v.val = L.A.val32;
+    v.wdinv = L.wdinv32;
+  } else {
+    v.val = L.A.val[L.vs];
+    v.wdinv = L.wdinv;
+  }
+  return v;
+}
+
+// x = M^-1 b for the first n entries (one V-cycle); the border entry is passed through.
+template <typename T>
+int amg_apply(Ctx* c, const T* b, T* x, bool border) {
+  Amg& g = c->amg;
+  hipStream_t st = c->stream;
+  const int* on = &c->sc->active[0];   // skip the cycle once the solve has stopped on the device
+  const int nl = static_cast<int>(g.lv.size());
+  auto w = [&](int l, int k) -> T* {
+    if constexpr (sizeof(T) == 4) return g.lv[l].w32[k];
+    else return g.lv[l].w64[k];
+  };
+  // level l: w(l,0) right-hand side (l > 0), w(l,1) pre-smoothed iterate,
+  // w(l,2) residual, later the post-smoothed iterate (l > 0); level 0 ends in x.
+  const T* rhs = b;
+  for (int l = 0; l < nl - 1; ++l) {
+    const AmgLevel& L = g.lv[l];
+    k_pre<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, w(l, 1), w(l, 2), on);
+    k_restrict<T><<<grid_for(g.lv[l + 1].n), kBlock, 0, st>>>(g.lv[l + 1].n, L.mstart, L.members, w(l, 2),
+                                                               w(l + 1, 0), on);
+    rhs = w(l + 1, 0);
+  }
+  const T* inv;
+  if constexpr (sizeof(T) == 4) inv = g.cinv32;
+  else inv = g.cinv;
+  if (nl == 1) {
+    // the whole system is the coarsest level: apply its inverse, bordered if singular
+    const int64_t r = border ? g.m1 : g.m;
+    k_dense_apply<T><<<(r * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(r, r, g.m1, inv, b, x, on);
+    return VIP_OK;
+  }
+  T* coarse_out = w(nl - 1, 1);
+  k_dense_apply<T><<<(g.m * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(g.m, g.m, g.m1, inv, rhs,
+                                                                         coarse_out, on);
+  const T* xc = coarse_out;
+  for (int l = nl - 2; l >= 0; --l) {
+    const AmgLevel& L = g.lv[l];
+    const T* bl = (l == 0) ? b : w(l, 0);
+    T* out = (l == 0) ? x : w(l, 2);
+    k_post<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), L.agg, xc, bl, w(l, 1), out, on);
+    xc = out;
+  }
+  if (border) VIP_HIP_TRY(c, hipMemcpyAsync(x + c->n, b + c->n, sizeof(T), hipMemcpyDeviceToDevice, st));
+  return VIP_OK;
+}
+
+template int amg_apply<float>(Ctx*, const float*, float*, bool);
+template int amg_apply<double>(Ctx*, const double*, double*, bool);
+
+}  // namespace vip

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -26,11 +27,13 @@ void ell_free(Ell& e) {
   dfree(e.cols);
   for (auto& v : e.val) dfree(v);
   dfree(e.val32);
+  dfree(e.rsum32);
   e = Ell{};
 }
 
 void ctx_free_build(Ctx* c) {
   c->built = false;
+  amg_free(c);
   dfree(c->x);
   dfree(c->y);
   dfree(c->bpos);
@@ -121,6 +124,7 @@ void vip_default_options(vip_options* o) {
   o->inner_tol = 1e-4;
   o->max_iters = 200000;
   o->check_every = 16;
+  o->preconditioner = VIP_PC_AMG;
 }
 
 int vip_create(void** out, int device, void* stream) {
@@ -130,6 +134,8 @@ int vip_create(void** out, int device, void* stream) {
   if (!c) return VIP_E_INVALID;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  const char* dbg = std::getenv("VIP_DEBUG");
+  c->debug = (dbg && dbg[0] == '1') ? 1 : 0;
   vip_default_options(&c->opt);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -138,12 +144,9 @@ int vip_create(void** out, int device, void* stream) {
   }
   if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->sc, sizeof(vip::KrylovScalars)) != hipSuccess ||
       hipHostMalloc(&c->sc_host, sizeof(vip::KrylovScalars), hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(&c->counter, sizeof(unsigned int)) != hipSuccess ||
-      hipMemset(c->counter, 0, sizeof(unsigned int)) != hipSuccess ||
       hipMemset(c->sc, 0, sizeof(vip::KrylovScalars)) != hipSuccess) {
     if (c->sc) (void)hipFree(c->sc);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
-    if (c->counter) (void)hipFree(c->counter);
     delete c;
     return VIP_E_HIP;
   }
@@ -158,7 +161,6 @@ int vip_destroy(void* p) {
   (void)hipStreamSynchronize(c->stream);
   vip::ctx_free_build(c);
   vip::dfree(c->partials);
-  vip::dfree(c->counter);
   vip::dfree(c->sc);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   for (auto& e : c->timing.pool) {
@@ -204,6 +206,8 @@ int vip_set_options(void* p, const vip_options* opt) {
     return vip::set_error(c, VIP_E_INVALID, "unknown identity");
   if (opt->warmstart != VIP_WS_ZERO && opt->warmstart != VIP_WS_PREV)
     return vip::set_error(c, VIP_E_INVALID, "unknown warm start");
+  if (opt->preconditioner != VIP_PC_JACOBI && opt->preconditioner != VIP_PC_AMG)
+    return vip::set_error(c, VIP_E_INVALID, "unknown preconditioner");
   if (!(opt->poisson_tol > 0.0) || !(opt->helmholtz_tol > 0.0) || !(opt->inner_tol > 0.0) ||
       opt->max_iters <= 0 || opt->check_every <= 0)
     return vip::set_error(c, VIP_E_INVALID, "tolerances and limits must be positive");

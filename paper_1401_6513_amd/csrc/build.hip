@@ -647,6 +647,22 @@ __global__ void k_diag_inv(int64_t n, const int64_t* sptr, const int32_t* scols,
   dinv[i] = d != 0.0 ? 1.0 / d : 1.0;
 }
 
+// Row sums of a sliced-ELL matrix (FP64 sum, stored as FP32).
+__global__ void k_rowsum32(int64_t n, const int64_t* ptr, const int32_t* rowlen, const double* val,
+                           float* out) {
+  int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int t = 0; t < rowlen[i]; ++t)
+    s += val[ptr[i / kSlice] + static_cast<int64_t>(t) * kSlice + (i % kSlice)];
+  out[i] = static_cast<float>(s);
+}
+
+void launch_rowsum32(hipStream_t st, int64_t n, const int64_t* ptr, const int32_t* rowlen,
+                     const double* val, float* out) {
+  if (n > 0) k_rowsum32<<<grid_for(n), kBlock, 0, st>>>(n, ptr, rowlen, val, out);
+}
+
 __global__ void k_to_f32(int64_t m, const double* a, float* b) {
   int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i < m) b[i] = static_cast<float>(a[i]);
@@ -804,6 +820,8 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   c->nb = nb;
   c->h = h;
   c->rho0 = rho;
+  c->xmin = xmin;
+  c->ymin = ymin;
   c->periodic = px;
   bool has_outlet = false;
   c->h_bkind.assign(bkind, bkind + nb);
@@ -939,6 +957,8 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
                                               c->node.val[1], n1, n2, s.ptr, s.cols, s.val[0],
                                               s.val[1], s.val[2]);
   k_to_f32<<<grid_for(s.nnz_slots), kBlock, 0, st>>>(s.nnz_slots, s.val[0], s.val32);
+  VIP_TRY(dalloc(c, &s.rsum32, n));
+  launch_rowsum32(st, n, s.ptr, s.rowlen, s.val[0], s.rsum32);
   for (int v = 0; v < 3; ++v) VIP_TRY(dalloc(c, &c->dinv[v], n + 1));
   VIP_TRY(dalloc(c, &c->dinv32, n + 1));
   k_diag_inv<<<grid_for(n), kBlock, 0, st>>>(n, s.ptr, s.cols, s.rowlen, s.val[0], c->dinv[0]);

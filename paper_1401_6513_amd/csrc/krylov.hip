@@ -2,9 +2,11 @@
 // Crank-Nicolson predictor systems (eq. 12), on the sliced-ELL system layout.
 //
 // * SpMV kernels are one thread per row over 64-row column-major slices, with
-//   the dot products the method needs next fused in, reduced per block and
-//   finished by the last block to arrive (fixed summation order, so repeated
-//   runs are bitwise identical).  Step lengths (alpha, omega, beta) stay in
+//   the dot products the method needs next fused in.  Each block of a bounded
+//   grid takes a contiguous chunk of rows (consecutive chunks on one XCD),
+//   writes its partial sums, and a one-block kernel adds them in block order
+//   and updates the step lengths (fixed summation order, so repeated runs are
+//   bitwise identical; no atomics).  Step lengths (alpha, omega, beta) stay in
 //   device memory; the host only reads the residual every few iterations.
 // * BiCGStab (van der Vorst) with a Jacobi preconditioner for general systems,
 //   Jacobi-preconditioned CG for symmetric ones.  Up to two systems with shared
@@ -27,13 +29,29 @@ namespace vip {
 namespace {
 
 constexpr int kWaves = kBlock / 64;
+constexpr int64_t kMaxGrid = 2048;   // blocks of a reducing kernel (grid-stride over row chunks)
 
-// Sum NV values over the block and publish the block sums; returns true in the
-// last block to finish, whose threads then hold the grand totals in v[].
+// Grid of a reducing kernel over m items: bounded, a multiple of the XCD count.
+inline int64_t red_grid(int64_t m) { return std::min<int64_t>(grid_for(m), kMaxGrid); }
+
+// Contiguous chunk of items [begin, end) handled by this block; consecutive
+// logical blocks (same XCD) get consecutive chunks.
+struct Span {
+  int64_t begin, end;
+};
+
+__device__ __forceinline__ Span block_span(int64_t m) {
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t per = ((m + gridDim.x - 1) / gridDim.x + kSlice - 1) / kSlice * kSlice;
+  const int64_t b = lb * per;
+  return {b, b + per < m ? b + per : m};
+}
+
+// Block sums of NV values, written to partials[blockIdx.x * NV + a] (plain stores);
+// a finishing kernel adds them up in block order.
 template <int NV>
-__device__ __forceinline__ bool reduce_last(double (&v)[NV], double* partials, unsigned int* counter) {
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* partials) {
   __shared__ double red[NV][kWaves];
-  __shared__ int last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int a = 0; a < NV; ++a) {
@@ -49,22 +67,21 @@ __device__ __forceinline__ bool reduce_last(double (&v)[NV], double* partials, u
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) t += red[a][w];
-      __hip_atomic_store(&partials[static_cast<int64_t>(blockIdx.x) * NV + a], t, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      partials[static_cast<int64_t>(blockIdx.x) * NV + a] = t;
     }
-    const unsigned int prev =
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == gridDim.x - 1) ? 1 : 0;
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  const int64_t nb = gridDim.x;
+}
+
+// Totals of the block sums of `nb` blocks, in a fixed order (one block of kBlock threads);
+// the result is valid in every thread.
+template <int NV>
+__device__ __forceinline__ void grid_sum(const double* partials, int64_t nb, double (&tot)[NV]) {
+  __shared__ double red[NV][kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int a = 0; a < NV; ++a) {
     double t = 0.0;
-    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
-      t += __hip_atomic_load(&partials[b * NV + a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) t += partials[b * NV + a];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
     if (lane == 0) red[a][wave] = t;
@@ -75,10 +92,8 @@ __device__ __forceinline__ bool reduce_last(double (&v)[NV], double* partials, u
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) t += red[a][w];
-    v[a] = t;
+    tot[a] = t;
   }
-  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
 }
 
 __device__ __forceinline__ double safe_div(double a, double b, int* flag) {
@@ -96,6 +111,7 @@ struct Mat {
   const int64_t* ptr;
   const int32_t* cols;
   const VT* val[2];        // value sets of system 0 and 1
+  const float* rsum;       // FP32 values only: row sums for the difference form
 };
 
 template <typename T>
@@ -122,12 +138,16 @@ __device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, 
   const VT* vals = A.val[sys];
   double acc = 0.0;
   if constexpr (sizeof(VT) == 4) {
+    // difference form: rows of the pressure matrix sum to ~0, so on smooth x the
+    // plain sum cancels most of its digits in FP32; x_j - x_i of nearby values is
+    // exact and keeps them
+    const float xi = static_cast<float>(x[i]);
     float a32 = 0.0f;
     for (int64_t k = 0; k < w; ++k) {
       const int64_t q = base + k * kSlice;
-      a32 += static_cast<float>(vals[q]) * static_cast<float>(x[A.cols[q]]);
+      a32 += static_cast<float>(vals[q]) * (static_cast<float>(x[A.cols[q]]) - xi);
     }
-    acc = a32;
+    acc = static_cast<double>(a32) + static_cast<double>(A.rsum[i] * xi);
   } else {
     for (int64_t k = 0; k < w; ++k) {
       const int64_t q = base + k * kSlice;
@@ -137,16 +157,15 @@ __device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, 
   return acc;
 }
 
-// ---- residual: r = b - A x (FP64 values), rr = |r|^2, bb = |b|^2 ---------------------------
+// ---- residual: r = b - A x, rr = |r|^2, bb = |b|^2 ----------------------------------------------
 template <typename VT, typename XT, typename RT, int NS>
 __global__ void k_residual(Mat<VT> A, const XT* x, const double* b, RT* r, int64_t stride,
-                           double* partials, unsigned int* counter, KrylovScalars* sc) {
-  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = lb * blockDim.x + threadIdx.x;
+                           double* partials) {
   double acc[3 * NS];
 #pragma unroll
   for (int a = 0; a < 3 * NS; ++a) acc[a] = 0.0;
-  if (i < A.n) {
+  const Span sp = block_span(A.n);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const XT* xs = x + s * stride;
@@ -155,29 +174,36 @@ __global__ void k_residual(Mat<VT> A, const XT* x, const double* b, RT* r, int64
       const double bi = b[s * stride + i];
       const double ri = bi - ax;
       r[s * stride + i] = static_cast<RT>(ri);
-      acc[3 * s + 0] = ri * ri;
-      acc[3 * s + 1] = bi * bi;
-      acc[3 * s + 2] = A.border ? static_cast<double>(xs[i]) : 0.0;
+      acc[3 * s + 0] += ri * ri;
+      acc[3 * s + 1] += bi * bi;
+      if (A.border) acc[3 * s + 2] += static_cast<double>(xs[i]);
     }
   }
-  if (reduce_last<3 * NS>(acc, partials, counter) && threadIdx.x == 0) {
+  block_sum_store<3 * NS>(acc, partials);
+}
+
+template <typename RT, int NS>
+__global__ void k_fin_residual(const double* partials, int64_t nb, int64_t n, int border, const double* b,
+                               RT* r, int64_t stride, KrylovScalars* sc) {
+  double tot[3 * NS];
+  grid_sum<3 * NS>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      double rr = acc[3 * s], bb = acc[3 * s + 1];
-      if (A.border) {
-        const double bn = b[s * stride + A.n];
-        const double rn = bn - acc[3 * s + 2];
-        r[s * stride + A.n] = static_cast<RT>(rn);
-        rr += rn * rn;
-        bb += bn * bn;
-      }
-      sc->rr[s] = rr;
-      sc->bb[s] = bb;
+  for (int s = 0; s < NS; ++s) {
+    double rr = tot[3 * s], bb = tot[3 * s + 1];
+    if (border) {
+      const double bn = b[s * stride + n];
+      const double rn = bn - tot[3 * s + 2];
+      r[s * stride + n] = static_cast<RT>(rn);
+      rr += rn * rn;
+      bb += bn * bn;
     }
+    sc->rr[s] = rr;
+    sc->bb[s] = bb;
   }
 }
 
-// ---- BiCGStab -------------------------------------------------------------------------------
+// ---- BiCGStab -------------------------------------------------------------------------------------
 template <typename T, int NS>
 __global__ void k_bicg_init(Vec<T> V, int64_t nvec, KrylovScalars* sc) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -202,252 +228,341 @@ __global__ void k_bicg_init(Vec<T> V, int64_t nvec, KrylovScalars* sc) {
   }
 }
 
-// p = r + beta (p - omega v); ph = D^-1 p
+// p = r + beta (p - omega v); ph = D^-1 p (Jacobi)
 template <typename T, int NS>
-__global__ void k_bicg_p(Vec<T> V, int64_t nvec, const KrylovScalars* sc, const int* active) {
+__global__ void k_bicg_p(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int jac) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= nvec) return;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    if (!active[s]) continue;
+    if (!sc->active[s]) continue;
     const int64_t o = s * V.stride + i;
     const T beta = static_cast<T>(sc->beta[s]), omega = static_cast<T>(sc->omega[s]);
     const T p = V.r[o] + beta * (V.p[o] - omega * V.v[o]);
     V.p[o] = p;
-    V.ph[o] = V.dinv[s][i] * p;
+    if (jac) V.ph[o] = V.dinv[s][i] * p;
   }
 }
 
-// v = A ph; alpha = rho / (rhat . v)
+// v = A ph; partial sums of rhat . v (and of ph for the border row)
 template <typename VT, typename T, int NS>
-__global__ void k_bicg_v(Mat<VT> A, Vec<T> V, double* partials, unsigned int* counter,
-                         KrylovScalars* sc, const int* active) {
-  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = lb * blockDim.x + threadIdx.x;
+__global__ void k_bicg_v(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
   double acc[2 * NS];
 #pragma unroll
   for (int a = 0; a < 2 * NS; ++a) acc[a] = 0.0;
-  if (i < A.n) {
+  const Span sp = block_span(A.n);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
+      if (!sc->active[s]) continue;
       const T* ph = V.ph + s * V.stride;
       double y = row_dot(A, s, i, ph);
       if (A.border) y += static_cast<double>(ph[A.n]);
       const T yt = static_cast<T>(y);
       V.v[s * V.stride + i] = yt;
-      acc[2 * s] = static_cast<double>(V.rhat[s * V.stride + i]) * static_cast<double>(yt);
-      acc[2 * s + 1] = A.border ? static_cast<double>(ph[i]) : 0.0;
+      acc[2 * s] += static_cast<double>(V.rhat[s * V.stride + i]) * static_cast<double>(yt);
+      if (A.border) acc[2 * s + 1] += static_cast<double>(ph[i]);
     }
   }
-  if (reduce_last<2 * NS>(acc, partials, counter) && threadIdx.x == 0) {
+  block_sum_store<2 * NS>(acc, partials);
+}
+
+// alpha = rho / (rhat . v), with the border row v[n] = sum(ph)
+template <typename T, int NS>
+__global__ void k_fin_bicg_v(const double* partials, int64_t nb, int64_t n, int border, Vec<T> V,
+                             KrylovScalars* sc) {
+  double tot[2 * NS];
+  grid_sum<2 * NS>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
-      double d = acc[2 * s];
-      if (A.border) {
-        const T yn = static_cast<T>(acc[2 * s + 1]);
-        V.v[s * V.stride + A.n] = yn;
-        d += static_cast<double>(V.rhat[s * V.stride + A.n]) * static_cast<double>(yn);
-      }
-      sc->dot_a[s] = d;
-      sc->alpha[s] = safe_div(sc->rho[s], d, &sc->breakdown[s]);
+  for (int s = 0; s < NS; ++s) {
+    if (!sc->active[s]) continue;
+    double d = tot[2 * s];
+    if (border) {
+      const T yn = static_cast<T>(tot[2 * s + 1]);
+      V.v[s * V.stride + n] = yn;
+      d += static_cast<double>(V.rhat[s * V.stride + n]) * static_cast<double>(yn);
     }
+    sc->dot_a[s] = d;
+    sc->alpha[s] = safe_div(sc->rho[s], d, &sc->breakdown[s]);
+    if (sc->breakdown[s]) sc->active[s] = 0;
   }
 }
 
-// s = r - alpha v; sh = D^-1 s
+// s = r - alpha v; sh = D^-1 s (Jacobi)
 template <typename T, int NS>
-__global__ void k_bicg_s(Vec<T> V, int64_t nvec, const KrylovScalars* sc, const int* active) {
+__global__ void k_bicg_s(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int jac) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= nvec) return;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    if (!active[s]) continue;
+    if (!sc->active[s]) continue;
     const int64_t o = s * V.stride + i;
     const T sv = V.r[o] - static_cast<T>(sc->alpha[s]) * V.v[o];
     V.s[o] = sv;
-    V.sh[o] = V.dinv[s][i] * sv;
+    if (jac) V.sh[o] = V.dinv[s][i] * sv;
   }
 }
 
-// t = A sh; omega = (t . s) / (t . t)
+// t = A sh; partial sums of t . s, t . t (and of sh for the border row)
 template <typename VT, typename T, int NS>
-__global__ void k_bicg_t(Mat<VT> A, Vec<T> V, double* partials, unsigned int* counter,
-                         KrylovScalars* sc, const int* active) {
-  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = lb * blockDim.x + threadIdx.x;
+__global__ void k_bicg_t(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
   double acc[3 * NS];
 #pragma unroll
   for (int a = 0; a < 3 * NS; ++a) acc[a] = 0.0;
-  if (i < A.n) {
+  const Span sp = block_span(A.n);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
+      if (!sc->active[s]) continue;
       const T* sh = V.sh + s * V.stride;
       double y = row_dot(A, s, i, sh);
       if (A.border) y += static_cast<double>(sh[A.n]);
       const T yt = static_cast<T>(y);
       V.t[s * V.stride + i] = yt;
       const double sv = static_cast<double>(V.s[s * V.stride + i]);
-      acc[3 * s] = static_cast<double>(yt) * sv;
-      acc[3 * s + 1] = static_cast<double>(yt) * static_cast<double>(yt);
-      acc[3 * s + 2] = A.border ? static_cast<double>(sh[i]) : 0.0;
+      acc[3 * s] += static_cast<double>(yt) * sv;
+      acc[3 * s + 1] += static_cast<double>(yt) * static_cast<double>(yt);
+      if (A.border) acc[3 * s + 2] += static_cast<double>(sh[i]);
     }
   }
-  if (reduce_last<3 * NS>(acc, partials, counter) && threadIdx.x == 0) {
+  block_sum_store<3 * NS>(acc, partials);
+}
+
+// omega = (t . s) / (t . t), with the border row t[n] = sum(sh)
+template <typename T, int NS>
+__global__ void k_fin_bicg_t(const double* partials, int64_t nb, int64_t n, int border, Vec<T> V,
+                             KrylovScalars* sc) {
+  double tot[3 * NS];
+  grid_sum<3 * NS>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
-      double ts = acc[3 * s], tt = acc[3 * s + 1];
-      if (A.border) {
-        const T yn = static_cast<T>(acc[3 * s + 2]);
-        V.t[s * V.stride + A.n] = yn;
-        ts += static_cast<double>(yn) * static_cast<double>(V.s[s * V.stride + A.n]);
-        tt += static_cast<double>(yn) * static_cast<double>(yn);
-      }
-      sc->dot_b[s] = ts;
-      sc->dot_c[s] = tt;
-      // tt == 0 means s == 0: the half step already solved the system
-      sc->omega[s] = tt > 0.0 ? ts / tt : 0.0;
+  for (int s = 0; s < NS; ++s) {
+    if (!sc->active[s]) continue;
+    double ts = tot[3 * s], tt = tot[3 * s + 1];
+    if (border) {
+      const T yn = static_cast<T>(tot[3 * s + 2]);
+      V.t[s * V.stride + n] = yn;
+      ts += static_cast<double>(yn) * static_cast<double>(V.s[s * V.stride + n]);
+      tt += static_cast<double>(yn) * static_cast<double>(yn);
     }
+    sc->dot_b[s] = ts;
+    sc->dot_c[s] = tt;
+    // tt == 0 means s == 0: the half step already solved the system
+    sc->omega[s] = tt > 0.0 ? ts / tt : 0.0;
   }
 }
 
-// x += alpha ph + omega sh; r = s - omega t; rho' = rhat . r; beta = (rho'/rho)(alpha/omega)
+// x += alpha ph + omega sh; r = s - omega t; partial sums of rhat . r and r . r
 template <typename T, int NS>
-__global__ void k_bicg_x(Vec<T> V, int64_t nvec, double* partials, unsigned int* counter,
-                         KrylovScalars* sc, const int* active) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+__global__ void k_bicg_x(Vec<T> V, int64_t nvec, double* partials, const KrylovScalars* sc) {
   double acc[2 * NS];
 #pragma unroll
   for (int a = 0; a < 2 * NS; ++a) acc[a] = 0.0;
-  if (i < nvec) {
+  const Span sp = block_span(nvec);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
+      if (!sc->active[s]) continue;
       const int64_t o = s * V.stride + i;
       const T alpha = static_cast<T>(sc->alpha[s]), omega = static_cast<T>(sc->omega[s]);
       V.x[o] = V.x[o] + alpha * V.ph[o] + omega * V.sh[o];
       const T r = V.s[o] - omega * V.t[o];
       V.r[o] = r;
-      acc[2 * s] = static_cast<double>(V.rhat[o]) * static_cast<double>(r);
-      acc[2 * s + 1] = static_cast<double>(r) * static_cast<double>(r);
+      acc[2 * s] += static_cast<double>(V.rhat[o]) * static_cast<double>(r);
+      acc[2 * s + 1] += static_cast<double>(r) * static_cast<double>(r);
     }
   }
-  if (reduce_last<2 * NS>(acc, partials, counter) && threadIdx.x == 0) {
+  block_sum_store<2 * NS>(acc, partials);
+}
+
+// rho' = rhat . r; stop at convergence or breakdown; beta = (rho'/rho)(alpha/omega)
+template <int NS>
+__global__ void k_fin_bicg_x(const double* partials, int64_t nb, KrylovScalars* sc) {
+  double tot[2 * NS];
+  grid_sum<2 * NS>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
-      const double rho_new = acc[2 * s];
-      sc->rr[s] = acc[2 * s + 1];
-      const double ratio = safe_div(rho_new, sc->rho[s], &sc->breakdown[s]);
-      const double om = sc->omega[s];
-      sc->beta[s] = (om != 0.0 && isfinite(ratio)) ? ratio * (sc->alpha[s] / om) : 0.0;
-      if (om == 0.0 && acc[2 * s + 1] > 0.0) sc->breakdown[s] = 1;
-      sc->rho[s] = rho_new;
+  for (int s = 0; s < NS; ++s) {
+    if (!sc->active[s]) continue;
+    const double rho_new = tot[2 * s];
+    const double rr = tot[2 * s + 1];
+    sc->rr[s] = rr;
+    sc->iters[s] += 1;
+    if (!(rr > sc->stop2[s])) {       // converged (or not a number): stop before the next update
+      sc->active[s] = 0;
+      if (!isfinite(rr)) sc->breakdown[s] = 1;
+      continue;
     }
+    const double ratio = safe_div(rho_new, sc->rho[s], &sc->breakdown[s]);
+    const double om = sc->omega[s];
+    const double beta = (om != 0.0 && isfinite(ratio)) ? ratio * (sc->alpha[s] / om) : 0.0;
+    if (om == 0.0 || !isfinite(beta) || fabs(beta) > 1e30) sc->breakdown[s] = 1;
+    sc->beta[s] = isfinite(beta) ? beta : 0.0;
+    sc->rho[s] = rho_new;
+    if (sc->breakdown[s]) sc->active[s] = 0;
   }
 }
 
-// ---- CG ---------------------------------------------------------------------------------------
-// z = D^-1 r; p = z; rho = r . z
+// ---- CG -----------------------------------------------------------------------------------------------
+// p = z with z = D^-1 r (Jacobi) or given in V.s; partial sums of r . z
 template <typename T, int NS>
-__global__ void k_cg_init(Vec<T> V, int64_t nvec, double* partials, unsigned int* counter,
-                          KrylovScalars* sc) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+__global__ void k_cg_init(Vec<T> V, int64_t nvec, double* partials, int jac) {
   double acc[NS];
 #pragma unroll
   for (int a = 0; a < NS; ++a) acc[a] = 0.0;
-  if (i < nvec) {
+  const Span sp = block_span(nvec);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int64_t o = s * V.stride + i;
-      const T z = V.dinv[s][i] * V.r[o];
+      const T z = jac ? V.dinv[s][i] * V.r[o] : V.s[o];
       V.p[o] = z;
-      acc[s] = static_cast<double>(V.r[o]) * static_cast<double>(z);
+      acc[s] += static_cast<double>(V.r[o]) * static_cast<double>(z);
     }
   }
-  if (reduce_last<NS>(acc, partials, counter) && threadIdx.x == 0) {
+  block_sum_store<NS>(acc, partials);
+}
+
+template <int NS>
+__global__ void k_fin_cg_init(const double* partials, int64_t nb, KrylovScalars* sc) {
+  double tot[NS];
+  grid_sum<NS>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      sc->rho[s] = acc[s];
-      sc->breakdown[s] = 0;
-    }
+  for (int s = 0; s < NS; ++s) {
+    sc->rho[s] = tot[s];
+    sc->breakdown[s] = 0;
   }
 }
 
-// v = A p; alpha = rho / (p . v)
+// v = A p; partial sums of p . v
 template <typename VT, typename T, int NS>
-__global__ void k_cg_q(Mat<VT> A, Vec<T> V, double* partials, unsigned int* counter,
-                       KrylovScalars* sc, const int* active) {
-  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = lb * blockDim.x + threadIdx.x;
+__global__ void k_cg_q(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
   double acc[NS];
 #pragma unroll
   for (int a = 0; a < NS; ++a) acc[a] = 0.0;
-  if (i < A.n) {
+  const Span sp = block_span(A.n);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
+      if (!sc->active[s]) continue;
       const T* p = V.p + s * V.stride;
       const T y = static_cast<T>(row_dot(A, s, i, p));
       V.v[s * V.stride + i] = y;
-      acc[s] = static_cast<double>(p[i]) * static_cast<double>(y);
+      acc[s] += static_cast<double>(p[i]) * static_cast<double>(y);
     }
   }
-  if (reduce_last<NS>(acc, partials, counter) && threadIdx.x == 0) {
+  block_sum_store<NS>(acc, partials);
+}
+
+// alpha = rho / (p . v)
+template <int NS>
+__global__ void k_fin_cg_q(const double* partials, int64_t nb, KrylovScalars* sc) {
+  double tot[NS];
+  grid_sum<NS>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
-      sc->dot_a[s] = acc[s];
-      sc->alpha[s] = safe_div(sc->rho[s], acc[s], &sc->breakdown[s]);
-    }
+  for (int s = 0; s < NS; ++s) {
+    if (!sc->active[s]) continue;
+    sc->dot_a[s] = tot[s];
+    sc->alpha[s] = safe_div(sc->rho[s], tot[s], &sc->breakdown[s]);
+    if (sc->breakdown[s]) sc->active[s] = 0;
   }
 }
 
-// x += alpha p; r -= alpha v; rho' = r . D^-1 r; beta = rho'/rho
+// x += alpha p; r -= alpha v; partial sums of r . D^-1 r (Jacobi) and r . r
 template <typename T, int NS>
-__global__ void k_cg_x(Vec<T> V, int64_t nvec, double* partials, unsigned int* counter,
-                       KrylovScalars* sc, const int* active) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+__global__ void k_cg_x(Vec<T> V, int64_t nvec, double* partials, const KrylovScalars* sc, int jac) {
   double acc[2 * NS];
 #pragma unroll
   for (int a = 0; a < 2 * NS; ++a) acc[a] = 0.0;
-  if (i < nvec) {
+  const Span sp = block_span(nvec);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
+      if (!sc->active[s]) continue;
       const int64_t o = s * V.stride + i;
       const T alpha = static_cast<T>(sc->alpha[s]);
       V.x[o] = V.x[o] + alpha * V.p[o];
       const T r = V.r[o] - alpha * V.v[o];
       V.r[o] = r;
-      acc[2 * s] = static_cast<double>(r) * static_cast<double>(V.dinv[s][i] * r);
-      acc[2 * s + 1] = static_cast<double>(r) * static_cast<double>(r);
+      if (jac) acc[2 * s] += static_cast<double>(r) * static_cast<double>(V.dinv[s][i] * r);
+      acc[2 * s + 1] += static_cast<double>(r) * static_cast<double>(r);
     }
   }
-  if (reduce_last<2 * NS>(acc, partials, counter) && threadIdx.x == 0) {
+  block_sum_store<2 * NS>(acc, partials);
+}
+
+// stop at convergence; with Jacobi also beta = rho'/rho
+template <int NS>
+__global__ void k_fin_cg_x(const double* partials, int64_t nb, KrylovScalars* sc, int jac) {
+  double tot[2 * NS];
+  grid_sum<2 * NS>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (!active[s]) continue;
-      sc->rr[s] = acc[2 * s + 1];
-      sc->beta[s] = safe_div(acc[2 * s], sc->rho[s], &sc->breakdown[s]);
-      sc->rho[s] = acc[2 * s];
+  for (int s = 0; s < NS; ++s) {
+    if (!sc->active[s]) continue;
+    const double rr = tot[2 * s + 1];
+    sc->rr[s] = rr;
+    sc->iters[s] += 1;
+    if (!(rr > sc->stop2[s])) {
+      sc->active[s] = 0;
+      if (!isfinite(rr)) sc->breakdown[s] = 1;
+      continue;
+    }
+    if (jac) {
+      sc->beta[s] = safe_div(tot[2 * s], sc->rho[s], &sc->breakdown[s]);
+      sc->rho[s] = tot[2 * s];
+      if (sc->breakdown[s]) sc->active[s] = 0;
     }
   }
 }
 
-// p = D^-1 r + beta p
+// partial sums of r . z with z = M^-1 r in V.s
 template <typename T, int NS>
-__global__ void k_cg_p(Vec<T> V, int64_t nvec, const KrylovScalars* sc, const int* active) {
+__global__ void k_cg_rz(Vec<T> V, int64_t nvec, double* partials, const KrylovScalars* sc) {
+  double acc[NS];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) acc[a] = 0.0;
+  const Span sp = block_span(nvec);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (!sc->active[s]) continue;
+      const int64_t o = s * V.stride + i;
+      acc[s] += static_cast<double>(V.r[o]) * static_cast<double>(V.s[o]);
+    }
+  }
+  block_sum_store<NS>(acc, partials);
+}
+
+// beta = rho'/rho
+template <int NS>
+__global__ void k_fin_cg_rz(const double* partials, int64_t nb, KrylovScalars* sc) {
+  double tot[NS];
+  grid_sum<NS>(partials, nb, tot);
+  if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (!sc->active[s]) continue;
+    sc->beta[s] = safe_div(tot[s], sc->rho[s], &sc->breakdown[s]);
+    sc->rho[s] = tot[s];
+    if (sc->breakdown[s]) sc->active[s] = 0;
+  }
+}
+
+// p = z + beta p with z = D^-1 r (Jacobi) or z in V.s
+template <typename T, int NS>
+__global__ void k_cg_p(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int jac) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= nvec) return;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    if (!active[s]) continue;
+    if (!sc->active[s]) continue;
     const int64_t o = s * V.stride + i;
-    V.p[o] = V.dinv[s][i] * V.r[o] + static_cast<T>(sc->beta[s]) * V.p[o];
+    const T z = jac ? V.dinv[s][i] * V.r[o] : V.s[o];
+    V.p[o] = z + static_cast<T>(sc->beta[s]) * V.p[o];
   }
 }
 
@@ -469,12 +584,18 @@ __global__ void k_add_f32(int64_t m, double* x, const float* d) {
   if (i < m) x[i] += static_cast<double>(d[i]);
 }
 
-// sum of a[0..m) -> sc->mean = sum / m
-__global__ void k_mean(int64_t m, const double* a, double* partials, unsigned int* counter,
-                       KrylovScalars* sc) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  double acc[1] = {i < m ? a[i] : 0.0};
-  if (reduce_last<1>(acc, partials, counter) && threadIdx.x == 0) sc->mean = acc[0] / static_cast<double>(m);
+// partial sums of a[0..m)
+__global__ void k_sum(int64_t m, const double* a, double* partials) {
+  double acc[1] = {0.0};
+  const Span sp = block_span(m);
+  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) acc[0] += a[i];
+  block_sum_store<1>(acc, partials);
+}
+
+__global__ void k_fin_mean(const double* partials, int64_t nb, int64_t m, KrylovScalars* sc) {
+  double tot[1];
+  grid_sum<1>(partials, nb, tot);
+  if (threadIdx.x == 0) sc->mean = tot[0] / static_cast<double>(m);
 }
 
 __global__ void k_sub_mean(int64_t m, const double* a, double* out, const KrylovScalars* sc) {
@@ -547,38 +668,50 @@ int ensure_ws(Ctx* c, int64_t len64, int64_t len32) {
 
 enum Method { kBiCGStab = 0, kCG = 1 };
 
-// Device flags telling the kernels which systems are still iterating.
-int* active_flags(Ctx* c) {
-  return reinterpret_cast<int*>(c->partials + c->partials_len);   // tail of the partials buffer
-}
-
-int set_active(Ctx* c, const int* act) {
-  VIP_HIP_TRY(c, hipMemcpyAsync(active_flags(c), act, 2 * sizeof(int), hipMemcpyHostToDevice,
+// Tell the kernels which systems iterate and where each one stops.
+int set_active(Ctx* c, const int* act, const double* stop2) {
+  KrylovScalars* sc = c->sc;
+  const int zero[2] = {0, 0};
+  VIP_HIP_TRY(c, hipMemcpyAsync(&sc->iters[0], zero, 2 * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  VIP_HIP_TRY(c, hipMemcpyAsync(&sc->active[0], act, 2 * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  VIP_HIP_TRY(c, hipMemcpyAsync(&sc->stop2[0], stop2, 2 * sizeof(double), hipMemcpyHostToDevice,
                                 c->stream));
   return VIP_OK;
 }
 
 // Iterate until |r| <= tol |b| (recurrence residual) for every system, or maxit.
-// On entry V.r holds the initial residual and sc->rr/bb its norms.
+// On entry V.r holds the initial residual and sc->rr/bb its norms.  A system
+// stops on the device as soon as it converges or breaks down; *bad reports a
+// non-finite residual (the caller then discards the iterate).
 template <typename VT, typename T, int NS>
 int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit, int* iters,
-            bool time_spmv, const double* bnorm2) {
+            bool time_spmv, const double* bnorm2, bool amg = false, bool* bad = nullptr) {
   const int64_t nvec = A.n + A.border;
-  const int64_t g_rows = grid_for(A.n), g_vec = grid_for(nvec);
-  VIP_TRY(ensure_partials(c, std::max(g_rows, g_vec), 3 * NS));
+  const int64_t g_vec = grid_for(nvec);
+  const int64_t r_rows = red_grid(A.n), r_vec = red_grid(nvec);
+  VIP_TRY(ensure_partials(c, std::max(r_rows, r_vec), 3 * NS));
+  if (c->debug)
+    std::fprintf(stderr, "[vip] iterate n %lld border %d tol %.3e rr0 %.3e bb %.3e\n",
+                 static_cast<long long>(A.n), A.border, tol, c->sc_host->rr[0], bnorm2[0]);
   int act[2] = {1, NS > 1 ? 1 : 0};
-  for (int s = 0; s < NS; ++s)
-    if (c->sc_host->rr[s] <= tol * tol * bnorm2[s]) act[s] = 0;
-  VIP_TRY(set_active(c, act));
-  const int* dact = active_flags(c);
+  double stop2[2] = {0.0, 0.0};
+  for (int s = 0; s < NS; ++s) {
+    stop2[s] = tol * tol * bnorm2[s];
+    if (c->sc_host->rr[s] <= stop2[s]) act[s] = 0;
+  }
+  if (bad) *bad = false;
+  VIP_TRY(set_active(c, act, stop2));
   double* part = c->partials;
-  unsigned int* cnt = c->counter;
   KrylovScalars* sc = c->sc;
   hipStream_t st = c->stream;
   if (m == kBiCGStab) {
     k_bicg_init<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc);
   } else {
-    k_cg_init<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, part, cnt, sc);
+    if constexpr (NS == 1) {
+      if (amg) VIP_TRY(amg_apply<T>(c, V.r, V.s, false));
+    }
+    k_cg_init<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, amg ? 0 : 1);
+    k_fin_cg_init<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);
   }
   int it = 0;
   const int every = std::max(1, c->opt.check_every);
@@ -586,48 +719,68 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
     const int batch = std::min(every, maxit - it);
     for (int b = 0; b < batch; ++b) {
       if (m == kBiCGStab) {
-        k_bicg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, dact);
+        k_bicg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
+        if constexpr (NS == 1) {
+          if (amg) VIP_TRY(amg_apply<T>(c, V.p, V.ph, A.border != 0));
+        }
         {
           Timer tm(c, time_spmv);
-          k_bicg_v<VT, T, NS><<<g_rows, kBlock, 0, st>>>(A, V, part, cnt, sc, dact);
+          k_bicg_v<VT, T, NS><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         }
-        k_bicg_s<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, dact);
-        k_bicg_t<VT, T, NS><<<g_rows, kBlock, 0, st>>>(A, V, part, cnt, sc, dact);
-        k_bicg_x<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, part, cnt, sc, dact);
+        k_fin_bicg_v<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
+        k_bicg_s<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
+        if constexpr (NS == 1) {
+          if (amg) VIP_TRY(amg_apply<T>(c, V.s, V.sh, A.border != 0));
+        }
+        k_bicg_t<VT, T, NS><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+        k_fin_bicg_t<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
+        k_bicg_x<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc);
+        k_fin_bicg_x<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);
       } else {
         {
           Timer tm(c, time_spmv);
-          k_cg_q<VT, T, NS><<<g_rows, kBlock, 0, st>>>(A, V, part, cnt, sc, dact);
+          k_cg_q<VT, T, NS><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         }
-        k_cg_x<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, part, cnt, sc, dact);
-        k_cg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, dact);
+        k_fin_cg_q<NS><<<1, kBlock, 0, st>>>(part, r_rows, sc);
+        k_cg_x<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc, amg ? 0 : 1);
+        k_fin_cg_x<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc, amg ? 0 : 1);
+        if constexpr (NS == 1) {
+          if (amg) {
+            VIP_TRY(amg_apply<T>(c, V.r, V.s, false));
+            k_cg_rz<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc);
+            k_fin_cg_rz<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);
+          }
+        }
+        k_cg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
       }
     }
     it += batch;
     VIP_HIP_TRY(c, hipGetLastError());
     VIP_TRY(sync_scalars(c));
-    bool changed = false;
     for (int s = 0; s < NS; ++s) {
       if (!act[s]) continue;
-      const double rr = c->sc_host->rr[s];
-      if (!std::isfinite(rr)) return set_error(c, VIP_E_NONFINITE, "non-finite Krylov residual");
-      if (rr <= tol * tol * bnorm2[s] || c->sc_host->breakdown[s]) {
-        act[s] = 0;
-        changed = true;
-      }
+      if (!std::isfinite(c->sc_host->rr[s]) && bad) *bad = true;
+      act[s] = c->sc_host->active[s];
     }
-    if (changed) VIP_TRY(set_active(c, act));
+    if (c->debug) {
+      const KrylovScalars& h = *c->sc_host;
+      std::fprintf(stderr, "[vip] %s%s batch to %d: it %d rr %.3e stop2 %.3e rho %.3e alpha %.3e omega %.3e "
+                   "beta %.3e brk %d act %d\n", m == kCG ? "cg" : "bicgstab", amg ? "+amg" : "", it,
+                   h.iters[0], h.rr[0], h.stop2[0], h.rho[0], h.alpha[0], h.omega[0], h.beta[0],
+                   h.breakdown[0], h.active[0]);
+    }
   }
-  *iters = it;
+  *iters = 0;
+  for (int s = 0; s < NS; ++s) *iters = std::max(*iters, c->sc_host->iters[s]);
   return VIP_OK;
 }
 
 template <typename VT, typename XT, typename RT, int NS>
 int residual(Ctx* c, const Mat<VT>& A, const XT* x, const double* b, RT* r, int64_t stride) {
-  const int64_t g = grid_for(A.n);
+  const int64_t g = red_grid(A.n);
   VIP_TRY(ensure_partials(c, g, 3 * NS));
-  k_residual<VT, XT, RT, NS><<<g, kBlock, 0, c->stream>>>(A, x, b, r, stride, c->partials, c->counter,
-                                                          c->sc);
+  k_residual<VT, XT, RT, NS><<<g, kBlock, 0, c->stream>>>(A, x, b, r, stride, c->partials);
+  k_fin_residual<RT, NS><<<1, kBlock, 0, c->stream>>>(c->partials, g, A.n, A.border, b, r, stride, c->sc);
   VIP_HIP_TRY(c, hipGetLastError());
   return sync_scalars(c);
 }
@@ -663,8 +816,7 @@ int ensure_partials(Ctx* c, int64_t blocks, int per) {
   if (c->partials_len < need) {
     VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
     dfree(c->partials);
-    // tail: 2 ints of active flags (fits in one extra double slot)
-    VIP_TRY(dalloc(c, &c->partials, need + 1));
+    VIP_TRY(dalloc(c, &c->partials, need));
     c->partials_len = need;
   }
   return VIP_OK;
@@ -680,6 +832,8 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   const int64_t stride = n + 1;
   const int64_t nvec = n + (border ? 1 : 0);
   const bool mixed = c->opt.precision == VIP_P_MIXED;
+  const bool use_amg = c->opt.preconditioner == VIP_PC_AMG;
+  if (use_amg && !c->amg.ready) VIP_TRY(amg_setup(c));
   VIP_TRY(ensure_ws(c, 11 * stride, mixed ? 10 * stride : 1));
   double* b = c->ws + 8 * stride;       // right-hand side with border entry 0
   double* x = c->ws + 10 * stride;      // FP64 solution (bordered)
@@ -690,7 +844,8 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   k_fill<double><<<1, 64, 0, s>>>(1, b + n, 0.0);
   double lambda_proj = 0.0;
   if (project) {
-    k_mean<<<grid_for(n), kBlock, 0, s>>>(n, b, c->partials, c->counter, c->sc);
+    k_sum<<<red_grid(n), kBlock, 0, s>>>(n, b, c->partials);
+    k_fin_mean<<<1, kBlock, 0, s>>>(c->partials, red_grid(n), n, c->sc);
     k_sub_mean<<<grid_for(n), kBlock, 0, s>>>(n, b, b, c->sc);
     VIP_TRY(sync_scalars(c));
     lambda_proj = c->sc_host->mean;
@@ -701,7 +856,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   } else {
     k_fill<double><<<gv, kBlock, 0, s>>>(stride, x, 0.0);
   }
-  Mat<double> A64{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}};
+  Mat<double> A64{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}, nullptr};
   int total_it = 0, outer = 0;
   double relres = 0.0;
   const int maxit = c->opt.max_iters;
@@ -724,12 +879,15 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
       }
       if (total_it >= maxit) break;
       int it = 0;
-      VIP_TRY((iterate<double, double, 1>(c, m, A64, V, tol, maxit - total_it, &it, true, &bb)));
+      bool bad = false;
+      VIP_TRY((iterate<double, double, 1>(c, m, A64, V, tol, maxit - total_it, &it, true, &bb, use_amg,
+                                          &bad)));
       total_it += it;
+      if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite Krylov residual");
     }
   } else {
     const double inner = std::max(c->opt.inner_tol, 1e-7);
-    Mat<float> A32{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val32, nullptr}};
+    Mat<float> A32{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val32, nullptr}, c->sys.rsum32};
     float* d32 = c->ws32 + 8 * stride;
     float* r32base = c->ws32;
     Vec<float> V = make_vec<float>(r32base, stride, 1, d32);
@@ -753,15 +911,19 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
       k_fill<float><<<gv, kBlock, 0, s>>>(stride, d32, 0.0f);
       // inner: A32 d = r, from d = 0; its residual starts as r itself
       int it = 0;
+      bool bad = false;
       const double target = std::max(inner, 0.5 * tol / relres);
-      VIP_TRY((iterate<float, float, 1>(c, m, A32, V, target, maxit - total_it, &it, true, &rr_outer)));
+      VIP_TRY((iterate<float, float, 1>(c, m, A32, V, target, maxit - total_it, &it, true, &rr_outer,
+                                        use_amg, &bad)));
       total_it += it;
+      if (bad) return set_error(c, VIP_E_NONFINITE, "FP32 inner solve produced a non-finite residual");
       k_add_f32<<<gv, kBlock, 0, s>>>(nvec, x, d32);
     }
   }
   if (project) {
     // phi with zero mean
-    k_mean<<<grid_for(n), kBlock, 0, s>>>(n, x, c->partials, c->counter, c->sc);
+    k_sum<<<red_grid(n), kBlock, 0, s>>>(n, x, c->partials);
+    k_fin_mean<<<1, kBlock, 0, s>>>(c->partials, red_grid(n), n, c->sc);
     k_sub_mean<<<grid_for(n), kBlock, 0, s>>>(n, x, phi, c->sc);
   } else {
     k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x, phi);
@@ -803,7 +965,7 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
   // start from the right-hand side (the operators are close to the identity)
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, x);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, x + stride);
-  Mat<double> H{n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[1], c->sys.val[2]}};
+  Mat<double> H{n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[1], c->sys.val[2]}, nullptr};
   Vec<double> V = make_vec<double>(c->ws, stride, 2, x);
   V.dinv[0] = c->dinv[1];
   V.dinv[1] = c->dinv[2];
@@ -825,8 +987,11 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
     // a system whose b is zero is solved by x = 0 exactly: give it a unit norm
     for (int k = 0; k < 2; ++k) if (bb[k] == 0.0) bb[k] = 1.0;
     int it = 0;
-    VIP_TRY((iterate<double, double, 2>(c, kBiCGStab, H, V, tol, c->opt.max_iters - total, &it, false, bb)));
+    bool bad = false;
+    VIP_TRY((iterate<double, double, 2>(c, kBiCGStab, H, V, tol, c->opt.max_iters - total, &it, false, bb,
+                                        false, &bad)));
     total += it;
+    if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite predictor residual");
   }
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x, us);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x + stride, vs);

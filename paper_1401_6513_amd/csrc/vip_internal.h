@@ -36,6 +36,7 @@ struct Ell {
   int32_t* cols = nullptr;          // device [nnz_slots]
   double* val[4] = {nullptr, nullptr, nullptr, nullptr};  // FP64 value sets
   float* val32 = nullptr;           // FP32 value set (pressure matrix only)
+  float* rsum32 = nullptr;          // FP32 rows evaluated as rsum*x_i + sum a_ij (x_j - x_i)
   int64_t max_width = 0;
   int64_t nnz = 0;                  // sum of row lengths
 };
@@ -49,7 +50,35 @@ struct KrylovScalars {
   double bb[2];          // ||b||^2
   double dot_a[2], dot_b[2], dot_c[2];
   double mean;           // mean of a vector (periodic projection)
+  double stop2[2];       // a system stops iterating once rr <= stop2
   int breakdown[2];
+  int active[2];         // cleared on the device at convergence or breakdown
+  int iters[2];          // iterations performed (counted on the device)
+};
+
+// One level of the aggregation multigrid preconditioner.
+struct AmgLevel {
+  int64_t n = 0;
+  Ell A;                      // level 0: view of the pressure matrix (not owned)
+  int vs = 0;                 // value set of A holding the FP64 values
+  int32_t* keep = nullptr;    // rows with off-diagonal entries (aggregated)
+  int32_t* agg = nullptr;     // aggregate (row of the next level) or -1
+  int32_t* kx = nullptr;      // aggregation key (cell of the next level)
+  int32_t* ky = nullptr;
+  int64_t* mstart = nullptr;  // members of each next-level row: [n_next + 1]
+  int32_t* members = nullptr;
+  double* wdinv = nullptr;    // damped inverse diagonal
+  float* wdinv32 = nullptr;
+  double* w64[3] = {nullptr, nullptr, nullptr};   // V-cycle work vectors
+  float* w32[3] = {nullptr, nullptr, nullptr};
+};
+
+struct Amg {
+  std::vector<AmgLevel> lv;
+  double* cinv = nullptr;     // dense inverse of the coarsest level, [m1][m1]
+  float* cinv32 = nullptr;
+  int64_t m = 0, m1 = 0;      // coarsest rows, with the border row if singular
+  bool ready = false;
 };
 
 struct Timing {
@@ -62,6 +91,7 @@ struct Timing {
 
 struct Ctx {
   int device = 0;
+  int debug = 0;                  // VIP_DEBUG=1: trace Krylov batches on stderr
   hipStream_t stream = nullptr;
   Error err{0, ""};
   vip_options opt{};
@@ -70,6 +100,7 @@ struct Ctx {
   // node set
   int64_t n = 0, nb = 0;
   double h = 0.0, rho0 = 0.0;
+  double xmin = 0.0, ymin = 0.0;  // bounding-box origin of the node set
   bool periodic = false, singular = false, symmetric = false;
   double* x = nullptr;            // device [n]
   double* y = nullptr;            // device [n]
@@ -110,10 +141,10 @@ struct Ctx {
   int64_t ws32_len = 0;
   double* partials = nullptr;     // device [max blocks * 8]
   int64_t partials_len = 0;
-  unsigned int* counter = nullptr;  // device, last-block counter
   KrylovScalars* sc = nullptr;    // device scalars
   KrylovScalars* sc_host = nullptr; // pinned host mirror
 
+  Amg amg;
   Timing timing;
 };
 
@@ -177,6 +208,10 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t grid) {
 // Allocate an Ell's slice structure from per-row lengths already in e.rowlen.
 int ell_layout(Ctx* c, Ell& e);
 
+// FP32 row sums of an FP64 sliced-ELL value set (for the difference-form FP32 rows).
+void launch_rowsum32(hipStream_t st, int64_t n, const int64_t* ptr, const int32_t* rowlen,
+                     const double* val, float* out);
+
 // Ensure the reduction scratch holds `blocks` partial slots of `per` doubles.
 int ensure_partials(Ctx* c, int64_t blocks, int per);
 
@@ -192,6 +227,10 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
                    const int32_t* bkind, const double* bval, int64_t nb, int basis_order, double rho,
                    double h, const vip_options* opt);
 int assemble_helmholtz(Ctx* c, double dt, double re);
+int amg_setup(Ctx* c);
+void amg_free(Ctx* c);
+template <typename T>
+int amg_apply(Ctx* c, const T* b, T* x, bool border);
 int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step_stats* st);
 int convection(Ctx* c, const double* u, const double* v, double* nx, double* ny);
 int divergence(Ctx* c, const double* u, const double* v, double* d);

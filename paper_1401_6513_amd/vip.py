@@ -25,6 +25,7 @@ I_MLS, I_EXACT = 0, 1
 P_FP64, P_MIXED = 0, 1
 K_AUTO, K_PCG, K_BICGSTAB = 0, 1, 2
 WS_ZERO, WS_PREV = 0, 1
+PC_JACOBI, PC_AMG = 0, 1
 OP = dict(identity=0, laplacian=1, vip_e=2, vip_w=3, vip_n=4, vip_s=5, normal1=6, normal2=7,
           poisson=8, helm_u=9, helm_v=10, poisson32=11)
 
@@ -35,7 +36,8 @@ class VipOptions(ctypes.Structure):
                 ("min_neighbours", ctypes.c_int), ("vip_offset", ctypes.c_double),
                 ("period", ctypes.c_double * 2), ("poisson_tol", ctypes.c_double),
                 ("helmholtz_tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
-                ("max_iters", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("max_iters", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("preconditioner", ctypes.c_int)]
 
 
 class VipStepStats(ctypes.Structure):

@@ -15,8 +15,9 @@
 //   * the coarsest matrix (bordered when the system is singular) is inverted
 //     once by Gauss-Jordan with partial pivoting and applied as a dense product;
 //   * one V-cycle with one damped Jacobi sweep before and after the coarse
-//     correction; the pre-sweep from zero is fused with the residual, the
-//     prolongation with the post-sweep.
+//     correction (optionally none before it on the finest level); every
+//     stencil pass gathers a single vector, the element-wise parts (sweep from
+//     zero, prolongation) run as separate light kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -284,36 +285,45 @@ template <typename T, class Y>
 __device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
   const int64_t sl = i / kSlice;
   const int64_t base = L.ptr[sl] + (i % kSlice);
-  const int64_t w = (L.ptr[sl + 1] - L.ptr[sl]) / kSlice;
-  if constexpr (sizeof(T) == 4) {
-    const T yi = y(static_cast<int32_t>(i));
-    T acc = T(0);
-    for (int64_t k = 0; k < w; ++k) {
-      const int64_t q = base + k * kSlice;
-      acc += L.val[q] * (y(L.cols[q]) - yi);
-    }
-    return acc + L.rsum[i] * yi;
-  } else {
-    T acc = T(0);
-    for (int64_t k = 0; k < w; ++k) {
-      const int64_t q = base + k * kSlice;
-      acc += L.val[q] * y(L.cols[q]);
-    }
-    return acc;
+  const int w = static_cast<int>((L.ptr[sl + 1] - L.ptr[sl]) / kSlice);
+  const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
+  T a0 = T(0), a1 = T(0);
+  int k = 0;
+  for (; k + 4 <= w; k += 4) {
+    const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+    const int32_t c0 = L.cols[q], c1 = L.cols[q + kSlice], c2 = L.cols[q + 2 * kSlice],
+                  c3 = L.cols[q + 3 * kSlice];
+    const T v0 = L.val[q], v1 = L.val[q + kSlice], v2 = L.val[q + 2 * kSlice], v3 = L.val[q + 3 * kSlice];
+    const T y0 = y(c0), y1 = y(c1), y2 = y(c2), y3 = y(c3);
+    a0 += v0 * (y0 - yi);
+    a1 += v1 * (y1 - yi);
+    a0 += v2 * (y2 - yi);
+    a1 += v3 * (y3 - yi);
   }
+  for (; k < w; ++k) {
+    const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+    a0 += L.val[q] * (y(L.cols[q]) - yi);
+  }
+  if constexpr (sizeof(T) == 4) return a0 + a1 + L.rsum[i] * yi;
+  else return a0 + a1;
 }
 
-// x = W b; r = b - A W b   (pre-smoothing sweep from zero fused with the residual)
+// x = W b   (damped Jacobi sweep from a zero start)
 template <typename T>
-__global__ void k_pre(LevelView<T> L, const T* b, T* x, T* r, const int* on) {
+__global__ void k_jacobi0(LevelView<T> L, const T* b, T* x, const int* on) {
+  if (!*on) return;
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < L.n) x[i] = L.wdinv[i] * b[i];
+}
+
+// r = b - A x
+template <typename T>
+__global__ void k_level_residual(LevelView<T> L, const T* b, const T* x, T* r, const int* on) {
   if (!*on) return;
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = lb * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
-  const T acc = level_row(L, i, [&](int32_t j) { return L.wdinv[j] * b[j]; });
-  const T bi = b[i];
-  x[i] = L.wdinv[i] * bi;
-  r[i] = bi - acc;
+  r[i] = b[i] - level_row(L, i, [&](int32_t j) { return x[j]; });
 }
 
 // bc[I] = sum of r over the members of aggregate I
@@ -328,20 +338,25 @@ __global__ void k_restrict(int64_t nc, const int64_t* mstart, const int32_t* mem
   bc[I] = s;
 }
 
-// y = x + P xc; out = y + W (b - A y)   (prolongation fused with the post-smoothing sweep)
+// y = x + P xc   (coarse correction; x may be absent: zero pre-smoothing)
 template <typename T>
-__global__ void k_post(LevelView<T> L, const int32_t* agg, const T* xc, const T* b, const T* x, T* out,
-                       const int* on) {
+__global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, const T* x, T* y, const int* on) {
+  if (!*on) return;
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int32_t a = agg[i];
+  y[i] = (x ? x[i] : T(0)) + (a >= 0 ? xc[a] : T(0));
+}
+
+// out = y + W (b - A y)   (damped Jacobi sweep)
+template <typename T>
+__global__ void k_jacobi(LevelView<T> L, const T* b, const T* y, T* out, const int* on) {
   if (!*on) return;
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = lb * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
-  auto y = [&](int32_t j) {
-    const int32_t a = agg[j];
-    return x[j] + (a >= 0 ? xc[a] : T(0));
-  };
-  const T acc = level_row(L, i, y);
-  out[i] = y(static_cast<int32_t>(i)) + L.wdinv[i] * (b[i] - acc);
+  const T ay = level_row(L, i, [&](int32_t j) { return y[j]; });
+  out[i] = y[i] + L.wdinv[i] * (b[i] - ay);
 }
 
 // x[0..rows) = Inv[0..rows, 0..cols) b on the coarsest level (one wavefront per row);
@@ -562,8 +577,10 @@ static LevelView<T> view(const AmgLevel& L) {
 }
 
 // x = M^-1 b for the first n entries (one V-cycle); the border entry is passed through.
+// With pre_fine == false the finest level skips its pre-smoothing sweep (a
+// non-symmetric V(0,1) cycle there, for BiCGStab only).
 template <typename T>
-int amg_apply(Ctx* c, const T* b, T* x, bool border) {
+int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
   Amg& g = c->amg;
   hipStream_t st = c->stream;
   const int* on = &c->sc->active[0];   // skip the cycle once the solve has stopped on the device
@@ -572,16 +589,6 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border) {
     if constexpr (sizeof(T) == 4) return g.lv[l].w32[k];
     else return g.lv[l].w64[k];
   };
-  // level l: w(l,0) right-hand side (l > 0), w(l,1) pre-smoothed iterate,
-  // w(l,2) residual, later the post-smoothed iterate (l > 0); level 0 ends in x.
-  const T* rhs = b;
-  for (int l = 0; l < nl - 1; ++l) {
-    const AmgLevel& L = g.lv[l];
-    k_pre<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, w(l, 1), w(l, 2), on);
-    k_restrict<T><<<grid_for(g.lv[l + 1].n), kBlock, 0, st>>>(g.lv[l + 1].n, L.mstart, L.members, w(l, 2),
-                                                               w(l + 1, 0), on);
-    rhs = w(l + 1, 0);
-  }
   const T* inv;
   if constexpr (sizeof(T) == 4) inv = g.cinv32;
   else inv = g.cinv;
@@ -591,22 +598,41 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border) {
     k_dense_apply<T><<<(r * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(r, r, g.m1, inv, b, x, on);
     return VIP_OK;
   }
+  // level l: w(l,0) right-hand side (l > 0), w(l,1) pre-smoothed iterate,
+  // w(l,2) residual, then the corrected iterate; level 0 ends in x.
+  const T* rhs = b;
+  for (int l = 0; l < nl - 1; ++l) {
+    const AmgLevel& L = g.lv[l];
+    const bool pre = l > 0 || pre_fine;
+    const T* res = rhs;
+    if (pre) {
+      k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, w(l, 1), on);
+      k_level_residual<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, w(l, 1), w(l, 2), on);
+      res = w(l, 2);
+    }
+    k_restrict<T><<<grid_for(g.lv[l + 1].n), kBlock, 0, st>>>(g.lv[l + 1].n, L.mstart, L.members, res,
+                                                               w(l + 1, 0), on);
+    rhs = w(l + 1, 0);
+  }
   T* coarse_out = w(nl - 1, 1);
   k_dense_apply<T><<<(g.m * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(g.m, g.m, g.m1, inv, rhs,
                                                                          coarse_out, on);
   const T* xc = coarse_out;
   for (int l = nl - 2; l >= 0; --l) {
     const AmgLevel& L = g.lv[l];
+    const bool pre = l > 0 || pre_fine;
     const T* bl = (l == 0) ? b : w(l, 0);
-    T* out = (l == 0) ? x : w(l, 2);
-    k_post<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), L.agg, xc, bl, w(l, 1), out, on);
+    T* out = (l == 0) ? x : w(l, 1);
+    // corrected iterate y into w(l,2) (the residual is no longer needed), then one sweep
+    k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, pre ? w(l, 1) : nullptr, w(l, 2), on);
+    k_jacobi<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), bl, w(l, 2), out, on);
     xc = out;
   }
   if (border) VIP_HIP_TRY(c, hipMemcpyAsync(x + c->n, b + c->n, sizeof(T), hipMemcpyDeviceToDevice, st));
   return VIP_OK;
 }
 
-template int amg_apply<float>(Ctx*, const float*, float*, bool);
-template int amg_apply<double>(Ctx*, const double*, double*, bool);
+template int amg_apply<float>(Ctx*, const float*, float*, bool, bool);
+template int amg_apply<double>(Ctx*, const double*, double*, bool, bool);
 
 }  // namespace vip

@@ -136,6 +136,8 @@ int vip_create(void** out, int device, void* stream) {
   c->stream = static_cast<hipStream_t>(stream);
   const char* dbg = std::getenv("VIP_DEBUG");
   c->debug = (dbg && dbg[0] == '1') ? 1 : 0;
+  const char* pre = std::getenv("VIP_AMG_PRE_FINE");
+  c->amg_pre_fine = (pre && pre[0] == '0') ? 0 : 1;
   vip_default_options(&c->opt);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {

@@ -129,32 +129,60 @@ struct Vec {
   const T* dinv[2];
 };
 
-// Row i of y = A x for system `sys`; x is the system's vector.
+// Row i of y = A x for system `sys`; x is the system's vector.  The slot loop is
+// unrolled by four so the column loads of several slots are in flight before
+// their gathers.
 template <typename VT, typename T>
 __device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, const T* x) {
   const int64_t sl = i / kSlice;
   const int64_t base = A.ptr[sl] + (i % kSlice);
-  const int64_t w = (A.ptr[sl + 1] - A.ptr[sl]) / kSlice;
+  const int w = static_cast<int>((A.ptr[sl + 1] - A.ptr[sl]) / kSlice);
   const VT* vals = A.val[sys];
-  double acc = 0.0;
   if constexpr (sizeof(VT) == 4) {
     // difference form: rows of the pressure matrix sum to ~0, so on smooth x the
     // plain sum cancels most of its digits in FP32; x_j - x_i of nearby values is
     // exact and keeps them
     const float xi = static_cast<float>(x[i]);
-    float a32 = 0.0f;
-    for (int64_t k = 0; k < w; ++k) {
-      const int64_t q = base + k * kSlice;
-      a32 += static_cast<float>(vals[q]) * (static_cast<float>(x[A.cols[q]]) - xi);
+    float a0 = 0.0f, a1 = 0.0f;
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {
+      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+      const int32_t c0 = A.cols[q], c1 = A.cols[q + kSlice], c2 = A.cols[q + 2 * kSlice],
+                    c3 = A.cols[q + 3 * kSlice];
+      const float v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
+      const float x0 = static_cast<float>(x[c0]), x1 = static_cast<float>(x[c1]),
+                  x2 = static_cast<float>(x[c2]), x3 = static_cast<float>(x[c3]);
+      a0 += v0 * (x0 - xi);
+      a1 += v1 * (x1 - xi);
+      a0 += v2 * (x2 - xi);
+      a1 += v3 * (x3 - xi);
     }
-    acc = static_cast<double>(a32) + static_cast<double>(A.rsum[i] * xi);
+    for (; k < w; ++k) {
+      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+      a0 += static_cast<float>(vals[q]) * (static_cast<float>(x[A.cols[q]]) - xi);
+    }
+    return static_cast<double>(a0 + a1) + static_cast<double>(A.rsum[i] * xi);
   } else {
-    for (int64_t k = 0; k < w; ++k) {
-      const int64_t q = base + k * kSlice;
-      acc += static_cast<double>(vals[q]) * static_cast<double>(x[A.cols[q]]);
+    double a0 = 0.0, a1 = 0.0;
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {
+      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+      const int32_t c0 = A.cols[q], c1 = A.cols[q + kSlice], c2 = A.cols[q + 2 * kSlice],
+                    c3 = A.cols[q + 3 * kSlice];
+      const double v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
+      const double x0 = static_cast<double>(x[c0]), x1 = static_cast<double>(x[c1]),
+                   x2 = static_cast<double>(x[c2]), x3 = static_cast<double>(x[c3]);
+      a0 += v0 * x0;
+      a1 += v1 * x1;
+      a0 += v2 * x2;
+      a1 += v3 * x3;
     }
+    for (; k < w; ++k) {
+      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+      a0 += static_cast<double>(vals[q]) * static_cast<double>(x[A.cols[q]]);
+    }
+    return a0 + a1;
   }
-  return acc;
 }
 
 // ---- residual: r = b - A x, rr = |r|^2, bb = |b|^2 ----------------------------------------------
@@ -631,12 +659,17 @@ struct Timer {
   }
 };
 
-void harvest_timing(Ctx* c) {
-  for (auto& e : c->timing.pending) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
-      c->timing.total_ms += ms;
-      c->timing.count += 1;
+// Add the durations of timed launches [first, first + keep) of the pending list and
+// recycle every pending event pair.
+void harvest_timing(Ctx* c, size_t first = 0, size_t keep = SIZE_MAX) {
+  for (size_t k = 0; k < c->timing.pending.size(); ++k) {
+    auto& e = c->timing.pending[k];
+    if (k >= first && k - first < keep) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+        c->timing.total_ms += ms;
+        c->timing.count += 1;
+      }
     }
     c->timing.pool.push_back(e);
   }
@@ -647,7 +680,6 @@ int sync_scalars(Ctx* c) {
   VIP_HIP_TRY(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(KrylovScalars), hipMemcpyDeviceToHost,
                                 c->stream));
   VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
-  harvest_timing(c);
   return VIP_OK;
 }
 
@@ -700,6 +732,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
     if (c->sc_host->rr[s] <= stop2[s]) act[s] = 0;
   }
   if (bad) *bad = false;
+  harvest_timing(c, 0, 0);   // nothing pending belongs to this call
   VIP_TRY(set_active(c, act, stop2));
   double* part = c->partials;
   KrylovScalars* sc = c->sc;
@@ -708,7 +741,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
     k_bicg_init<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc);
   } else {
     if constexpr (NS == 1) {
-      if (amg) VIP_TRY(amg_apply<T>(c, V.r, V.s, false));
+      if (amg) VIP_TRY(amg_apply<T>(c, V.r, V.s, false, true));
     }
     k_cg_init<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, amg ? 0 : 1);
     k_fin_cg_init<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);
@@ -721,7 +754,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
       if (m == kBiCGStab) {
         k_bicg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
         if constexpr (NS == 1) {
-          if (amg) VIP_TRY(amg_apply<T>(c, V.p, V.ph, A.border != 0));
+          if (amg) VIP_TRY(amg_apply<T>(c, V.p, V.ph, A.border != 0, c->amg_pre_fine != 0));
         }
         {
           Timer tm(c, time_spmv);
@@ -730,7 +763,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
         k_fin_bicg_v<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
         k_bicg_s<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
         if constexpr (NS == 1) {
-          if (amg) VIP_TRY(amg_apply<T>(c, V.s, V.sh, A.border != 0));
+          if (amg) VIP_TRY(amg_apply<T>(c, V.s, V.sh, A.border != 0, c->amg_pre_fine != 0));
         }
         k_bicg_t<VT, T, NS><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         k_fin_bicg_t<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
@@ -746,7 +779,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
         k_fin_cg_x<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc, amg ? 0 : 1);
         if constexpr (NS == 1) {
           if (amg) {
-            VIP_TRY(amg_apply<T>(c, V.r, V.s, false));
+            VIP_TRY(amg_apply<T>(c, V.r, V.s, false, true));
             k_cg_rz<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc);
             k_fin_cg_rz<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);
           }
@@ -772,6 +805,9 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   }
   *iters = 0;
   for (int s = 0; s < NS; ++s) *iters = std::max(*iters, c->sc_host->iters[s]);
+  // one timed SpMV per iteration: launches after the device stopped the solve exit at once
+  // and are not counted
+  harvest_timing(c, 0, static_cast<size_t>(*iters));
   return VIP_OK;
 }
 

@@ -92,6 +92,7 @@ struct Timing {
 struct Ctx {
   int device = 0;
   int debug = 0;                  // VIP_DEBUG=1: trace Krylov batches on stderr
+  int amg_pre_fine = 1;           // VIP_AMG_PRE_FINE=0: BiCGStab V-cycles skip the finest pre-sweep
   hipStream_t stream = nullptr;
   Error err{0, ""};
   vip_options opt{};
@@ -230,7 +231,7 @@ int assemble_helmholtz(Ctx* c, double dt, double re);
 int amg_setup(Ctx* c);
 void amg_free(Ctx* c);
 template <typename T>
-int amg_apply(Ctx* c, const T* b, T* x, bool border);
+int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine);
 int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step_stats* st);
 int convection(Ctx* c, const double* u, const double* v, double* nx, double* ny);
 int divergence(Ctx* c, const double* u, const double* v, double* d);

@@ -58,7 +58,11 @@ enum { VIP_I_MLS = 0, VIP_I_EXACT = 1 };            /* identity in eq. 12: D^[0,
 enum { VIP_P_FP64 = 0, VIP_P_MIXED = 1 };           /* Poisson: FP64 Krylov, or FP32
                                                        inner Krylov in FP64 refinement */
 enum { VIP_K_AUTO = 0, VIP_K_PCG = 1, VIP_K_BICGSTAB = 2 };
-enum { VIP_WS_ZERO = 0, VIP_WS_PREV = 1 };          /* Poisson start vector in vip_step */
+/* Poisson start vector in vip_step: zero; the previous increment phi_n; phi_n + alpha e with
+ * e = phi_n - phi_(n-1) (EXTRAP); or phi_n + alpha e + beta c with c the learned network's
+ * correction (LEARNED).  alpha and beta minimise the FP64 residual ||b - L phi0||_2 and the
+ * corrected vector replaces phi_n only if that lowers the residual. */
+enum { VIP_WS_ZERO = 0, VIP_WS_PREV = 1, VIP_WS_LEARNED = 2, VIP_WS_EXTRAP = 3 };
 enum { VIP_PC_JACOBI = 0, VIP_PC_AMG = 1 };         /* Poisson preconditioner */
 
 typedef struct {
@@ -88,6 +92,11 @@ typedef struct {
   double poisson_residual;   /* final ||b - L phi||_2 / ||b||_2, FP64 */
   double helmholtz_residual; /* the larger of the two predictor residuals */
   double border_lambda;      /* multiplier of the bordered singular system, else 0 */
+  int warm_start;            /* start vector actually used: VIP_WS_* */
+  double warm_ratio;         /* VIP_WS_LEARNED, VIP_WS_EXTRAP: ||b - L phi0|| / ||b - L phi_n|| of
+                                the corrected start vector (used if < 1), else 0 */
+  double warm_alpha;         /* alpha of the used correction, else 0 */
+  double warm_beta;          /* beta of the used correction (VIP_WS_LEARNED), else 0 */
 } vip_step_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -169,6 +178,75 @@ int vip_reset_history(void* ctx);
  */
 int vip_poisson_solve(void* ctx, const double* rhs, double* phi, double tol, int use_x0,
                       vip_step_stats* stats);
+
+/* ---- learned start vector of the pressure solve ------------------------------
+ * Not part of the paper's method: a convolutional network on the lattice image
+ * of the node set (pixel (i, j) <-> node at (xmin + i h, ymin + j h); nodes off
+ * the lattice, such as curved-wall nodes, are left out) predicts the change of
+ * the pressure increment phi from one step to the next.  Layers: four 3x3
+ * convolutions 3 -> 32 -> 32 -> 32 -> 1 with zero padding, ReLU after the first
+ * three; BF16 weights and activations, FP32 sums, FP32 master weights trained
+ * with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on a masked mean squared error.
+ * The network corrects the extrapolated start vector phi_n + e, e = phi_n - phi_(n-1):
+ * input channels r h^2 / s, b h^2 / rms(b h^2), lattice mask, where r = b - L (phi_n + e)
+ * is the residual left by extrapolation and s = rms(r h^2) over lattice nodes; output y,
+ * the correction c = s y / h^2 (training target (phi_(n+1) - phi_n - e) h^2 / s).  With
+ * VIP_WS_LEARNED, vip_step starts the solve from phi_n + alpha e + beta c (alpha, beta
+ * and the acceptance rule at VIP_WS_*); the Krylov solve to poisson_tol always decides
+ * the result, so the network changes the iteration count, never the accuracy.
+ *
+ * Parameters are one flat FP64 host vector of vip_learn_n_params() values:
+ * W1 [3][3][3][32], b1 [32], W2 [3][3][32][32], b2 [32], W3 [3][3][32][32],
+ * b3 [32], W4 [3][3][32][1], b4 [1]; W[ky][kx][ci][co] multiplies input channel
+ * ci at pixel (i + ky - 1, j + kx - 1) into output channel co at (i, j).
+ * The network, its Adam moments and the captured snapshots belong to the
+ * context and survive vip_build_stencils (snapshots are lattice images).
+ */
+
+/* Number of network parameters (19,681). */
+int vip_learn_n_params(void);
+
+/* He-uniform weights U(+-sqrt(6 / fan_in)) drawn with splitmix64 from `seed`,
+ * zero biases; Adam moments cleared. */
+int vip_learn_init(void* ctx, uint64_t seed);
+
+/* Set (host, [n]) or read back the FP32 master parameters; n must equal
+ * vip_learn_n_params() (VIP_E_INVALID otherwise; non-finite values rejected).
+ * Setting clears the Adam moments.  Reading before any set: VIP_E_NOT_BUILT. */
+int vip_learn_set_params(void* ctx, const double* theta, int64_t n);
+int vip_learn_get_params(void* ctx, double* theta, int64_t n);
+
+/*
+ * Run the network on host images (checks and tools).
+ *  x       host [batch][height][width][3] input channels (rounded to BF16).
+ *  target  host [batch][height][width] (may be NULL if loss, grad are NULL and lr <= 0).
+ *  mask    host [batch][height][width] loss weights (same condition).
+ *  y       host [batch][height][width] output, may be NULL.
+ *  loss    host scalar, may be NULL: sum(mask (y - target)^2) / sum(mask).
+ *  grad    host [vip_learn_n_params()] gradient of loss, may be NULL.
+ *  lr      > 0: also take one Adam step with that gradient (learning rate lr).
+ * Errors: VIP_E_NOT_BUILT (no parameters), VIP_E_INVALID (sizes <= 0 or more
+ * than 2^28 pixels, NULL x).
+ */
+int vip_learn_eval(void* ctx, const double* x, const double* target, const double* mask, int batch,
+                   int height, int width, double* y, double* loss, double* grad, double lr);
+
+/* Training data: while fewer than max_snapshots are held, each vip_step that
+ * knows the last change of the increment stores one snapshot (input image and
+ * target).  0 stops capturing.  The node set must be
+ * lattice based (VIP_E_INVALID from vip_step otherwise). */
+int vip_learn_capture(void* ctx, int max_snapshots);
+int vip_learn_snapshot_count(void* ctx, int* count);
+int vip_learn_clear(void* ctx);   /* drop every snapshot */
+
+/* `iters` Adam steps on batches of `batch` random crop x crop windows of the
+ * snapshots (splitmix64 from seed and the step count; loss mask = lattice
+ * pixels at least 4 pixels inside the crop); *last_loss (may be NULL) gets
+ * the last batch loss.  Errors: VIP_E_NOT_BUILT, VIP_E_INVALID (no snapshots,
+ * iters <= 0, batch outside [1, 1024], crop outside [12, 1024], lr <= 0),
+ * VIP_E_NONFINITE (loss became NaN or Inf). */
+int vip_learn_train(void* ctx, int iters, int batch, int crop, double lr, uint64_t seed,
+                    double* last_loss);
 
 /* ---- operator access (parity checks and tools) ---------------------------- */
 enum {

@@ -63,6 +63,7 @@ void ctx_free_build(Ctx* c) {
   c->assembled = false;
   c->have_prev_n = false;
   c->have_prev_phi = false;
+  learn_free_nodeset(c);
 }
 
 namespace {
@@ -162,6 +163,7 @@ int vip_destroy(void* p) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   vip::ctx_free_build(c);
+  vip::learn_free(c);
   vip::dfree(c->partials);
   vip::dfree(c->sc);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
@@ -206,7 +208,7 @@ int vip_set_options(void* p, const vip_options* opt) {
     return vip::set_error(c, VIP_E_INVALID, "unknown krylov method");
   if (opt->identity != VIP_I_MLS && opt->identity != VIP_I_EXACT)
     return vip::set_error(c, VIP_E_INVALID, "unknown identity");
-  if (opt->warmstart != VIP_WS_ZERO && opt->warmstart != VIP_WS_PREV)
+  if (opt->warmstart < VIP_WS_ZERO || opt->warmstart > VIP_WS_EXTRAP)
     return vip::set_error(c, VIP_E_INVALID, "unknown warm start");
   if (opt->preconditioner != VIP_PC_JACOBI && opt->preconditioner != VIP_PC_AMG)
     return vip::set_error(c, VIP_E_INVALID, "unknown preconditioner");
@@ -242,6 +244,7 @@ int vip_reset_history(void* p) {
   VIP_TRY(vip::need_built(c));
   c->have_prev_n = false;
   c->have_prev_phi = false;
+  c->learn.have_eprev = false;
   return VIP_OK;
 }
 
@@ -406,6 +409,72 @@ int vip_kernel_timing(void* p, int enable, int reset, double* avg_ms, int64_t* c
   if (avg_ms) *avg_ms = c->timing.count > 0 ? c->timing.total_ms / c->timing.count : 0.0;
   if (count) *count = c->timing.count;
   return VIP_OK;
+}
+
+int vip_learn_n_params(void) { return vip::learn_n_params(); }
+
+int vip_learn_init(void* p, uint64_t seed) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  VIP_TRY(vip::bind_device(c));
+  return vip::learn_init(c, seed);
+}
+
+int vip_learn_set_params(void* p, const double* theta, int64_t n) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  if (!theta || n != vip::learn_n_params())
+    return vip::set_error(c, VIP_E_INVALID, "parameter vector must hold vip_learn_n_params() values");
+  VIP_TRY(vip::bind_device(c));
+  return vip::learn_set_params(c, theta);
+}
+
+int vip_learn_get_params(void* p, double* theta, int64_t n) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  if (!theta || n != vip::learn_n_params())
+    return vip::set_error(c, VIP_E_INVALID, "parameter vector must hold vip_learn_n_params() values");
+  VIP_TRY(vip::bind_device(c));
+  return vip::learn_get_params(c, theta);
+}
+
+int vip_learn_eval(void* p, const double* x, const double* target, const double* mask, int batch, int height,
+                   int width, double* y, double* loss, double* grad, double lr) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  VIP_TRY(vip::bind_device(c));
+  return vip::learn_eval(c, x, target, mask, batch, height, width, y, loss, grad, lr);
+}
+
+int vip_learn_capture(void* p, int max_snapshots) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  if (max_snapshots < 0) return vip::set_error(c, VIP_E_INVALID, "max_snapshots must be >= 0");
+  c->learn.capacity = max_snapshots;
+  return VIP_OK;
+}
+
+int vip_learn_snapshot_count(void* p, int* count) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c || !count) return VIP_E_INVALID;
+  *count = static_cast<int>(c->learn.snaps.size());
+  return VIP_OK;
+}
+
+int vip_learn_clear(void* p) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  VIP_TRY(vip::bind_device(c));
+  VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  vip::learn_clear(c);
+  return VIP_OK;
+}
+
+int vip_learn_train(void* p, int iters, int batch, int crop, double lr, uint64_t seed, double* last_loss) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  VIP_TRY(vip::bind_device(c));
+  return vip::learn_train(c, iters, batch, crop, lr, seed, last_loss);
 }
 
 }  // extern "C"

@@ -822,6 +822,8 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   c->rho0 = rho;
   c->xmin = xmin;
   c->ymin = ymin;
+  c->xmax = xmax;
+  c->ymax = ymax;
   c->periodic = px;
   bool has_outlet = false;
   c->h_bkind.assign(bkind, bkind + nb);

@@ -1,0 +1,1114 @@
+// Learned start vector for the pressure Poisson solve: a small convolutional
+// network on the lattice image of the node set, trained on the GPU on
+// (residual, right-hand side) -> correction pairs captured from the solver's
+// own steps.
+//
+// Network: 3x3 convolutions 3 -> 32 -> 32 -> 32 -> 1, ReLU after the first
+// three, zero padding, NHWC images.  Inputs (per lattice pixel): the residual
+// of the previous increment r = b - L phi_prev scaled by s = rms(r h^2) / h^2,
+// the right-hand side scaled by its own rms, and the lattice mask; target:
+// (phi - phi_prev) / (s h^2).  Weights and activations are BF16, every sum is
+// FP32; the two 32 -> 32 layers (9 taps x 32 x 32 per pixel) run on MFMA
+// (v_mfma_f32_16x16x32_bf16, one tap = one K step), the thin first and last
+// layers as direct FP32 loops.  Training uses Adam on FP32 master weights.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "vip_internal.h"
+
+namespace vip {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef unsigned short bf16_t;   // storage type of one bfloat16
+
+constexpr int kC = 32;          // hidden channels
+constexpr int kCin = 3;         // input channels
+constexpr int kMargin = 4;      // receptive-field radius of the 4 layers (loss mask margin)
+
+// Parameter offsets in the flat FP32 vector (same layout as the checker's):
+// W1 [9][3][32], b1 [32], W2 [9][32][32], b2, W3 [9][32][32], b3, W4 [9][32], b4 [1]
+constexpr int kW1 = 0, kB1 = kW1 + 9 * kCin * kC, kW2 = kB1 + kC, kB2 = kW2 + 9 * kC * kC,
+              kW3 = kB2 + kC, kB3 = kW3 + 9 * kC * kC, kW4 = kB3 + kC, kB4 = kW4 + 9 * kC,
+              kNParams = kB4 + 1;
+
+__device__ __forceinline__ float bf2f(bf16_t v) { return __uint_as_float(static_cast<unsigned>(v) << 16); }
+
+__device__ __forceinline__ bf16_t f2bf(float f) {   // round to nearest even
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<bf16_t>(u >> 16);   // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<bf16_t>(u >> 16);
+}
+
+struct Img {
+  int B, H, W;
+};
+
+__device__ __forceinline__ bool inside(const Img& g, int i, int j) {
+  return i >= 0 && i < g.H && j >= 0 && j < g.W;
+}
+
+// ---- forward ------------------------------------------------------------------------------------
+
+// layer 1 (3 -> 32), direct: one thread per pixel
+__global__ void k_conv_in(Img g, const bf16_t* x, const bf16_t* w1, const float* b1, bf16_t* out) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
+  if (p >= np) return;
+  const int j = static_cast<int>(p % g.W), i = static_cast<int>((p / g.W) % g.H);
+  const int64_t b = p / (static_cast<int64_t>(g.H) * g.W);
+  float acc[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) acc[c] = b1[c];
+  for (int t = 0; t < 9; ++t) {
+    const int ii = i + t / 3 - 1, jj = j + t % 3 - 1;
+    if (!inside(g, ii, jj)) continue;
+    const bf16_t* xp = x + ((b * g.H + ii) * g.W + jj) * kCin;
+#pragma unroll
+    for (int ci = 0; ci < kCin; ++ci) {
+      const float xv = bf2f(xp[ci]);
+      const bf16_t* wp = w1 + (t * kCin + ci) * kC;
+#pragma unroll
+      for (int c = 0; c < kC; ++c) acc[c] += xv * bf2f(wp[c]);
+    }
+  }
+  bf16_t* op = out + p * kC;
+#pragma unroll
+  for (int c = 0; c < kC; ++c) op[c] = f2bf(fmaxf(acc[c], 0.0f));
+}
+
+// MFMA tile over 16 pixels of one image row: D[pixel][n] += sum_taps A_tap[pixel][k] B_tap[k][n]
+// where A_tap reads `src` at the pixel shifted by sign*(tap offset) and B_tap = wt[tap][n][k].
+// Lane l: A row l%16 (pixel j0 + l%16), K chunk (l/16)*8; D rows (l/16)*4 + r, column l%16.
+__device__ __forceinline__ void mfma_strip(const Img& g, int b, int i, int j0, const bf16_t* src, int sign,
+                                           const bf16_t* wt, f32x4& d0, f32x4& d1) {
+  const int l = threadIdx.x & 63;
+  const int kq = (l >> 4) * 8;
+  const int n = l & 15;
+  for (int t = 0; t < 9; ++t) {
+    const int ii = i + sign * (t / 3 - 1), jj = j0 + n + sign * (t % 3 - 1);
+    bf16x8 a;
+    if (inside(g, ii, jj)) {
+      const uint4 raw = *reinterpret_cast<const uint4*>(src + ((static_cast<int64_t>(b) * g.H + ii) * g.W + jj) * kC + kq);
+      a = __builtin_bit_cast(bf16x8, raw);
+    } else {
+      a = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
+    }
+    const uint4 w0 = *reinterpret_cast<const uint4*>(wt + (t * kC + n) * kC + kq);
+    const uint4 w1 = *reinterpret_cast<const uint4*>(wt + (t * kC + 16 + n) * kC + kq);
+    d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w0), d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w1), d1, 0, 0, 0);
+  }
+}
+
+// layers 2 and 3 (32 -> 32) on MFMA; one wave per 16-pixel strip; wt = [tap][co][ci]
+__global__ void k_conv_mid(Img g, const bf16_t* x, const bf16_t* wt, const float* bias, bf16_t* out,
+                           int64_t nstrips) {
+  const int64_t s = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
+  if (s >= nstrips) return;
+  const int strips_w = (g.W + 15) / 16;
+  const int j0 = static_cast<int>(s % strips_w) * 16;
+  const int i = static_cast<int>((s / strips_w) % g.H);
+  const int b = static_cast<int>(s / (static_cast<int64_t>(strips_w) * g.H));
+  f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+  mfma_strip(g, b, i, j0, x, +1, wt, d0, d1);
+  const int l = threadIdx.x & 63;
+  const int n = l & 15;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = j0 + (l >> 4) * 4 + r;
+    if (j >= g.W) continue;
+    bf16_t* op = out + ((static_cast<int64_t>(b) * g.H + i) * g.W + j) * kC;
+    op[n] = f2bf(fmaxf(d0[r] + bias[n], 0.0f));
+    op[16 + n] = f2bf(fmaxf(d1[r] + bias[16 + n], 0.0f));
+  }
+}
+
+// layer 4 (32 -> 1), direct: one thread per pixel
+__global__ void k_conv_out(Img g, const bf16_t* x, const bf16_t* w4, const float* b4, float* y) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
+  if (p >= np) return;
+  const int j = static_cast<int>(p % g.W), i = static_cast<int>((p / g.W) % g.H);
+  const int64_t b = p / (static_cast<int64_t>(g.H) * g.W);
+  float acc = b4[0];
+  for (int t = 0; t < 9; ++t) {
+    const int ii = i + t / 3 - 1, jj = j + t % 3 - 1;
+    if (!inside(g, ii, jj)) continue;
+    const bf16_t* xp = x + ((b * g.H + ii) * g.W + jj) * kC;
+    const bf16_t* wp = w4 + t * kC;
+#pragma unroll
+    for (int c = 0; c < kC; ++c) acc += bf2f(xp[c]) * bf2f(wp[c]);
+  }
+  y[p] = acc;
+}
+
+// ---- loss -----------------------------------------------------------------------------------------
+
+// block sums of mask and of mask * (y - t)^2
+__global__ void k_loss_partial(int64_t np, const float* y, const float* t, const float* m, double* part) {
+  __shared__ double s0[256], s1[256];
+  double a = 0.0, c = 0.0;
+  for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < np;
+       p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double d = static_cast<double>(y[p]) - static_cast<double>(t[p]);
+    a += static_cast<double>(m[p]) * d * d;
+    c += m[p];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) {
+      s0[threadIdx.x] += s0[threadIdx.x + off];
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s0[0];
+    part[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
+// loss = sum / count (fixed block order); out[0] = loss, out[1] = count
+__global__ void k_loss_finish(int nb, const double* part, double* out) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, c = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    a += part[2 * k];
+    c += part[2 * k + 1];
+  }
+  out[0] = c > 0.0 ? a / c : 0.0;
+  out[1] = c;
+}
+
+// dL/dy = 2 m (y - t) / count
+__global__ void k_loss_grad(int64_t np, const float* y, const float* t, const float* m, const double* lc,
+                            float* gy) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (p >= np) return;
+  const double c = lc[1] > 0.0 ? lc[1] : 1.0;
+  gy[p] = static_cast<float>(2.0 * m[p] * (static_cast<double>(y[p]) - t[p]) / c);
+}
+
+// ---- backward ---------------------------------------------------------------------------------------
+
+// dA3 = conv^T(gy, W4), times relu'(A3): one thread per pixel, BF16 output
+__global__ void k_out_bwd(Img g, const float* gy, const bf16_t* w4, const bf16_t* a3, bf16_t* gz3) {
+  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
+  if (p >= np) return;
+  const int j = static_cast<int>(p % g.W), i = static_cast<int>((p / g.W) % g.H);
+  const int64_t b = p / (static_cast<int64_t>(g.H) * g.W);
+  float acc[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) acc[c] = 0.0f;
+  for (int t = 0; t < 9; ++t) {
+    // output pixel q = p - d_t contributed to p through tap t
+    const int ii = i - (t / 3 - 1), jj = j - (t % 3 - 1);
+    if (!inside(g, ii, jj)) continue;
+    const float gv = gy[(b * g.H + ii) * g.W + jj];
+    const bf16_t* wp = w4 + t * kC;
+#pragma unroll
+    for (int c = 0; c < kC; ++c) acc[c] += gv * bf2f(wp[c]);
+  }
+  const bf16_t* ap = a3 + p * kC;
+  bf16_t* op = gz3 + p * kC;
+#pragma unroll
+  for (int c = 0; c < kC; ++c) op[c] = f2bf(bf2f(ap[c]) > 0.0f ? acc[c] : 0.0f);
+}
+
+// dA_{l-1} = conv^T(gz_l, W_l) on MFMA, times relu'(A_{l-1}); wb = [tap][ci][co]
+__global__ void k_mid_bwd(Img g, const bf16_t* gz, const bf16_t* wb, const bf16_t* aprev, bf16_t* gzprev,
+                          int64_t nstrips) {
+  const int64_t s = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
+  if (s >= nstrips) return;
+  const int strips_w = (g.W + 15) / 16;
+  const int j0 = static_cast<int>(s % strips_w) * 16;
+  const int i = static_cast<int>((s / strips_w) % g.H);
+  const int b = static_cast<int>(s / (static_cast<int64_t>(strips_w) * g.H));
+  f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+  mfma_strip(g, b, i, j0, gz, -1, wb, d0, d1);
+  const int l = threadIdx.x & 63;
+  const int n = l & 15;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = j0 + (l >> 4) * 4 + r;
+    if (j >= g.W) continue;
+    const int64_t o = ((static_cast<int64_t>(b) * g.H + i) * g.W + j) * kC;
+    gzprev[o + n] = f2bf(bf2f(aprev[o + n]) > 0.0f ? d0[r] : 0.0f);
+    gzprev[o + 16 + n] = f2bf(bf2f(aprev[o + 16 + n]) > 0.0f ? d1[r] : 0.0f);
+  }
+}
+
+// Weight gradient of a 32 -> 32 layer on MFMA: dW[tap][ci][co] = sum_p x[p + d_tap][ci] gz[p][co].
+// One wave per chunk of pixels; M = ci (2 tiles), N = co (2 tiles), K = 32 pixels per step.
+// Lane l: A row ci = mt*16 + l%16 over pixels kq..kq+7; B pixels kq..kq+7, column co = nt*16 + l%16.
+__global__ __launch_bounds__(256) void k_mid_wgrad(Img g, const bf16_t* x, const bf16_t* gz,
+                                                   int64_t chunk, float* part) {
+  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
+  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
+  const int l = threadIdx.x & 63;
+  const int kq = (l >> 4) * 8;
+  const int n = l & 15;
+  f32x4 acc[9][4];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t p0 = wave * chunk;
+  for (int64_t base = p0; base < p0 + chunk && base < np; base += 32) {
+    // B operands (gz) for the 8 pixels of this lane, both co tiles
+    bf16x8 bv[2];
+    int pi[8], pj[8];
+    int64_t pb[8];
+    bool pv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t p = base + kq + e;
+      pv[e] = p < np && p < p0 + chunk;
+      const int64_t pp = pv[e] ? p : 0;
+      pj[e] = static_cast<int>(pp % g.W);
+      pi[e] = static_cast<int>((pp / g.W) % g.H);
+      pb[e] = pp / (static_cast<int64_t>(g.H) * g.W);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t p = base + kq + e;
+        const bf16_t v = pv[e] ? gz[p * kC + nt * 16 + n] : static_cast<bf16_t>(0);
+        bv[nt][e] = __builtin_bit_cast(__bf16, v);
+      }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        bf16x8 av;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int ii = pi[e] + dy, jj = pj[e] + dx;
+          bf16_t v = 0;
+          if (pv[e] && inside(g, ii, jj))
+            v = x[((pb[e] * g.H + ii) * g.W + jj) * kC + mt * 16 + n];
+          av[e] = __builtin_bit_cast(__bf16, v);
+        }
+        acc[t][mt * 2 + 0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[0], acc[t][mt * 2 + 0], 0, 0, 0);
+        acc[t][mt * 2 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[1], acc[t][mt * 2 + 1], 0, 0, 0);
+      }
+    }
+  }
+  // D layout: lane l holds rows (l/16)*4 + r (ci within the tile), column l%16 (co within the tile)
+  float* pw = part + wave * (9 * kC * kC);
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ci = mt * 16 + (l >> 4) * 4 + r, co = nt * 16 + n;
+          pw[(t * kC + ci) * kC + co] = acc[t][mt * 2 + nt][r];
+        }
+}
+
+// Weight and bias gradients of a thin layer (cin -> cout, direct): thread k of the block owns
+// parameter k (tap, ci, co) or bias co; each block sums over one chunk of pixels.
+// x has cin channels (BF16), gz has cout channels (FP32 if gzf != null, else BF16).
+__global__ void k_thin_wgrad(Img g, int cin, int cout, const bf16_t* x, const bf16_t* gzb, const float* gzf,
+                             int64_t chunk, float* part) {
+  const int k = threadIdx.x;
+  const int nw = 9 * cin * cout, nparam = nw + cout;
+  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
+  if (k >= nparam) return;
+  int t = 0, ci = 0, co;
+  if (k < nw) {
+    t = k / (cin * cout);
+    ci = (k / cout) % cin;
+    co = k % cout;
+  } else {
+    co = k - nw;
+  }
+  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  float acc = 0.0f;
+  const int64_t p0 = blockIdx.x * chunk;
+  for (int64_t p = p0; p < p0 + chunk && p < np; ++p) {
+    const float gv = gzf ? gzf[p * cout + co] : bf2f(gzb[p * cout + co]);
+    if (gv == 0.0f) continue;
+    if (k >= nw) {
+      acc += gv;
+      continue;
+    }
+    const int j = static_cast<int>(p % g.W), i = static_cast<int>((p / g.W) % g.H);
+    const int64_t b = p / (static_cast<int64_t>(g.H) * g.W);
+    const int ii = i + dy, jj = j + dx;
+    if (!inside(g, ii, jj)) continue;
+    acc += bf2f(x[((b * g.H + ii) * g.W + jj) * cin + ci]) * gv;
+  }
+  part[blockIdx.x * static_cast<int64_t>(nparam) + k] = acc;
+}
+
+// bias gradient of a 32-channel BF16 gradient image: block partial sums per channel
+__global__ void k_bias_grad(int64_t np, const bf16_t* gz, int64_t chunk, float* part) {
+  const int c = threadIdx.x;
+  if (c >= kC) return;
+  float acc = 0.0f;
+  const int64_t p0 = blockIdx.x * chunk;
+  for (int64_t p = p0; p < p0 + chunk && p < np; ++p) acc += bf2f(gz[p * kC + c]);
+  part[blockIdx.x * static_cast<int64_t>(kC) + c] = acc;
+}
+
+// grad[off + k] = sum over nb partial rows of part[row * stride + k], k < count (fixed order)
+__global__ void k_sum_parts(const float* part, int nb, int stride, int count, float* grad, int off) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  double s = 0.0;
+  for (int r = 0; r < nb; ++r) s += part[static_cast<int64_t>(r) * stride + k];
+  grad[off + k] = static_cast<float>(s);
+}
+
+// ---- optimiser and weight packing ---------------------------------------------------------------------
+
+__global__ void k_adam(int n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.0f - b1) * gk;
+  const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// BF16 copies: W1 as [tap][ci][co]; W2, W3 as [tap][co][ci] (forward) and [tap][ci][co]
+// (backward); W4 as [tap][ci]
+__global__ void k_pack(const float* th, bf16_t* w1, bf16_t* w2f, bf16_t* w2b, bf16_t* w3f, bf16_t* w3b,
+                       bf16_t* w4) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < 9 * kCin * kC) w1[k] = f2bf(th[kW1 + k]);
+  if (k < 9 * kC * kC) {
+    const int t = k / (kC * kC), ci = (k / kC) % kC, co = k % kC;
+    w2b[k] = f2bf(th[kW2 + k]);
+    w3b[k] = f2bf(th[kW3 + k]);
+    w2f[(t * kC + co) * kC + ci] = f2bf(th[kW2 + k]);
+    w3f[(t * kC + co) * kC + ci] = f2bf(th[kW3 + k]);
+  }
+  if (k < 9 * kC) w4[k] = f2bf(th[kW4 + k]);
+}
+
+// ---- lattice raster ------------------------------------------------------------------------------------
+
+// pixel of each node if it sits on the lattice x = xmin + ix h, y = ymin + iy h (else -1);
+// the lowest node index on a pixel keeps it
+__global__ void k_pixel_claim(int64_t n, const double* x, const double* y, double x0, double y0, double h,
+                              int W, int H, int32_t* node_of) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const double fx = (x[i] - x0) / h, fy = (y[i] - y0) / h;
+  const double rx = rint(fx), ry = rint(fy);
+  if (fabs(fx - rx) < 1e-6 && fabs(fy - ry) < 1e-6 && rx >= 0 && ry >= 0 && rx < W && ry < H)
+    atomicMin(&node_of[static_cast<int64_t>(ry) * W + static_cast<int64_t>(rx)], static_cast<int32_t>(i));
+}
+
+__global__ void k_pixel_finish(int64_t npix, int32_t* node_of, int32_t* pix) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= npix) return;
+  const int32_t node = node_of[q];
+  if (node == INT32_MAX) {
+    node_of[q] = -1;
+  } else {
+    pix[node] = static_cast<int32_t>(q);
+  }
+}
+
+// training crop `sample` of the batch from one snapshot image; loss mask = lattice node
+// and at least `margin` pixels inside the crop
+__global__ void k_make_crop(const bf16_t* sx, const float* st, int W, int H, int oy, int ox, int crop,
+                            int sample, bf16_t* X, float* T, float* M, int margin) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= static_cast<int64_t>(crop) * crop) return;
+  const int cy = static_cast<int>(q / crop), cx = static_cast<int>(q % crop);
+  const int iy = oy + cy, ix = ox + cx;
+  const int64_t o = static_cast<int64_t>(sample) * crop * crop + q;
+  bf16_t v0 = 0, v1 = 0, v2 = 0;
+  float tv = 0.0f;
+  if (iy >= 0 && iy < H && ix >= 0 && ix < W) {
+    const int64_t src = static_cast<int64_t>(iy) * W + ix;
+    v0 = sx[3 * src];
+    v1 = sx[3 * src + 1];
+    v2 = sx[3 * src + 2];
+    tv = st[src];
+  }
+  X[3 * o] = v0;
+  X[3 * o + 1] = v1;
+  X[3 * o + 2] = v2;
+  T[o] = tv;
+  const bool core = cy >= margin && cy < crop - margin && cx >= margin && cx < crop - margin;
+  M[o] = (v2 != 0 && core) ? 1.0f : 0.0f;
+}
+
+// input image: channels r h^2 / s_r, b h^2 / s_b, lattice mask (s_r, s_b: rms of r h^2 and
+// b h^2 over lattice nodes, in scal[0], scal[1])
+__global__ void k_make_image(int64_t npix, const int32_t* node_of, const double* r, const double* b,
+                             const double* scal, double h2, bf16_t* X) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= npix) return;
+  const int32_t node = node_of[q];
+  const bool in = node >= 0;
+  const double sr = scal[0], sb = scal[1];
+  X[q * 3 + 0] = f2bf(in && sr > 0.0 ? static_cast<float>(r[node] * h2 / sr) : 0.0f);
+  X[q * 3 + 1] = f2bf(in && sb > 0.0 ? static_cast<float>(b[node] * h2 / sb) : 0.0f);
+  X[q * 3 + 2] = f2bf(in ? 1.0f : 0.0f);
+}
+
+// training target image: (phi - phi_prev - e) h^2 / s_r
+__global__ void k_make_target(int64_t npix, const int32_t* node_of, const double* phi, const double* phi_prev,
+                              const double* e, const double* scal, double h2, float* T) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= npix) return;
+  const int32_t node = node_of[q];
+  const double sr = scal[0];
+  T[q] = node >= 0 && sr > 0.0 ? static_cast<float>((phi[node] - phi_prev[node] - e[node]) * h2 / sr) : 0.0f;
+}
+
+// predicted correction: s_r y / h^2 at lattice nodes, 0 elsewhere
+__global__ void k_direction(int64_t n, const int32_t* pix, const float* y, const double* scal, double h2,
+                            double* d) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int32_t p = pix[i];
+  const double sr = scal[0];
+  d[i] = p >= 0 && sr > 0.0 ? sr / h2 * static_cast<double>(y[p]) : 0.0;
+}
+
+// phi = phi_prev + alpha e + beta d (d may be null)
+__global__ void k_combine(int64_t n, const double* phi_prev, const double* e, const double* d, double alpha,
+                          double beta, double* phi) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  phi[i] = phi_prev[i] + alpha * e[i] + (d ? beta * d[i] : 0.0);
+}
+
+// e = phi - phi_prev
+__global__ void k_diff(int64_t n, const double* phi, const double* phi_prev, double* e) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  e[i] = phi[i] - phi_prev[i];
+}
+
+// r = b - a
+__global__ void k_sub(int64_t n, const double* b, const double* a, double* r) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  r[i] = b[i] - a[i];
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t v, int32_t* a) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  a[i] = v;
+}
+
+__global__ void k_copy_d(int64_t n, const double* a, double* b) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  b[i] = a[i];
+}
+
+// block partials of the squared sums of a h^2 and c h^2 over lattice nodes and their count
+__global__ void k_rms_part(int64_t n, const int32_t* pix, const double* a, const double* cv, double h2,
+                           double* part) {
+  __shared__ double s0[256], s1[256], s2[256];
+  double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (pix[i] < 0) continue;
+    const double u = a[i] * h2, v = cv[i] * h2;
+    x0 += u * u;
+    x1 += v * v;
+    x2 += 1.0;
+  }
+  s0[threadIdx.x] = x0;
+  s1[threadIdx.x] = x1;
+  s2[threadIdx.x] = x2;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) {
+      s0[threadIdx.x] += s0[threadIdx.x + off];
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+      s2[threadIdx.x] += s2[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = s0[0];
+    part[3 * blockIdx.x + 1] = s1[0];
+    part[3 * blockIdx.x + 2] = s2[0];
+  }
+}
+
+// scal[0], scal[1] = the two rms values (fixed block order)
+__global__ void k_rms_finish(int nb, const double* part, double* scal) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    a += part[3 * k];
+    b += part[3 * k + 1];
+    c += part[3 * k + 2];
+  }
+  scal[0] = c > 0.0 ? sqrt(a / c) : 0.0;
+  scal[1] = c > 0.0 ? sqrt(b / c) : 0.0;
+}
+
+// block partials of q1.q1, q1.q2, q2.q2, q1.r, q2.r, r.r (q2 may be null: its terms are 0)
+__global__ void k_dots6_part(int64_t n, const double* q1, const double* q2, const double* r, double* part) {
+  __shared__ double sh[6][256];
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double a = q1[i], c = q2 ? q2[i] : 0.0, rv = r[i];
+    acc[0] += a * a;
+    acc[1] += a * c;
+    acc[2] += c * c;
+    acc[3] += a * rv;
+    acc[4] += c * rv;
+    acc[5] += rv * rv;
+  }
+  for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off)
+      for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// scal[2 + k] = sum over blocks of dot k (fixed block order)
+__global__ void k_dots6_finish(int nb, const double* part, double* scal) {
+  if (threadIdx.x >= 6) return;
+  double a = 0.0;
+  for (int k = 0; k < nb; ++k) a += part[6 * k + threadIdx.x];
+  scal[2 + threadIdx.x] = a;
+}
+
+// splitmix64 (Steele, Lea and Flood 2014): a counter-based 64-bit generator
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+constexpr int kSumBlocks = 256;
+
+}  // namespace
+
+// ---- host side -------------------------------------------------------------------------------------------
+
+struct Net {
+  float* theta = nullptr;     // FP32 master parameters [kNParams]
+  float* grad = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  bf16_t* w1 = nullptr;       // packed BF16 weights
+  bf16_t* w2f = nullptr;
+  bf16_t* w2b = nullptr;
+  bf16_t* w3f = nullptr;
+  bf16_t* w3b = nullptr;
+  bf16_t* w4 = nullptr;
+  int step = 0;
+  bool ready = false;
+  // activation and work buffers for up to `cap` pixels
+  int64_t cap = 0;
+  bf16_t *x = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *g3 = nullptr, *g2 = nullptr,
+         *g1 = nullptr;
+  float *y = nullptr, *t = nullptr, *mask = nullptr, *gy = nullptr, *part = nullptr;
+  int64_t part_len = 0;
+  double* dscal = nullptr;    // [0] loss, [1] mask count, then partials
+  int64_t dscal_len = 0;
+};
+
+void learn_clear(Ctx* c) {
+  for (auto& s : c->learn.snaps) {
+    dfree(s.x);
+    dfree(s.t);
+  }
+  c->learn.snaps.clear();
+}
+
+void learn_free_nodeset(Ctx* c) {
+  Learn& L = c->learn;
+  dfree(L.pix);
+  dfree(L.node_of);
+  for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2, &L.scal}) dfree(*p);
+  L.have_eprev = false;
+  L.mapped = false;
+  L.W = L.H = 0;
+}
+
+void learn_free(Ctx* c) {
+  Learn& L = c->learn;
+  if (L.net) {
+    Net* N = static_cast<Net*>(L.net);
+    for (float** p : {&N->theta, &N->grad, &N->m, &N->v, &N->y, &N->t, &N->mask, &N->gy, &N->part}) dfree(*p);
+    for (bf16_t** p : {&N->w1, &N->w2f, &N->w2b, &N->w3f, &N->w3b, &N->w4, &N->x, &N->a1, &N->a2, &N->a3,
+                       &N->g3, &N->g2, &N->g1})
+      dfree(*p);
+    dfree(N->dscal);
+    delete N;
+    L.net = nullptr;
+  }
+  learn_clear(c);
+  learn_free_nodeset(c);
+}
+
+bool learn_ready(const Ctx* c) {
+  return c->learn.net && static_cast<const Net*>(c->learn.net)->ready;
+}
+
+namespace {
+
+Net* net_of(Ctx* c) {
+  if (!c->learn.net) c->learn.net = new Net();
+  return static_cast<Net*>(c->learn.net);
+}
+
+int net_alloc(Ctx* c) {
+  Net* N = net_of(c);
+  if (N->theta) return VIP_OK;
+  VIP_TRY(dalloc(c, &N->theta, kNParams));
+  VIP_TRY(dalloc(c, &N->grad, kNParams));
+  VIP_TRY(dalloc(c, &N->m, kNParams));
+  VIP_TRY(dalloc(c, &N->v, kNParams));
+  VIP_TRY(dalloc(c, &N->w1, 9 * kCin * kC));
+  VIP_TRY(dalloc(c, &N->w2f, 9 * kC * kC));
+  VIP_TRY(dalloc(c, &N->w2b, 9 * kC * kC));
+  VIP_TRY(dalloc(c, &N->w3f, 9 * kC * kC));
+  VIP_TRY(dalloc(c, &N->w3b, 9 * kC * kC));
+  VIP_TRY(dalloc(c, &N->w4, 9 * kC));
+  return VIP_OK;
+}
+
+int net_buffers(Ctx* c, int64_t npix) {
+  Net* N = net_of(c);
+  if (N->cap >= npix) return VIP_OK;
+  VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (bf16_t** p : {&N->x, &N->a1, &N->a2, &N->a3, &N->g3, &N->g2, &N->g1}) dfree(*p);
+  for (float** p : {&N->y, &N->t, &N->mask, &N->gy}) dfree(*p);
+  const int64_t cap = npix;
+  VIP_TRY(dalloc(c, &N->x, cap * kCin));
+  VIP_TRY(dalloc(c, &N->a1, cap * kC));
+  VIP_TRY(dalloc(c, &N->a2, cap * kC));
+  VIP_TRY(dalloc(c, &N->a3, cap * kC));
+  VIP_TRY(dalloc(c, &N->g3, cap * kC));
+  VIP_TRY(dalloc(c, &N->g2, cap * kC));
+  VIP_TRY(dalloc(c, &N->g1, cap * kC));
+  VIP_TRY(dalloc(c, &N->y, cap));
+  VIP_TRY(dalloc(c, &N->t, cap));
+  VIP_TRY(dalloc(c, &N->mask, cap));
+  VIP_TRY(dalloc(c, &N->gy, cap));
+  N->cap = npix;
+  return VIP_OK;
+}
+
+int ensure_part(Ctx* c, int64_t floats, int64_t doubles) {
+  Net* N = net_of(c);
+  if (N->part_len < floats || N->dscal_len < doubles) VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (N->part_len < floats) {
+    dfree(N->part);
+    VIP_TRY(dalloc(c, &N->part, floats));
+    N->part_len = floats;
+  }
+  if (N->dscal_len < doubles) {
+    dfree(N->dscal);
+    VIP_TRY(dalloc(c, &N->dscal, doubles));
+    N->dscal_len = doubles;
+  }
+  return VIP_OK;
+}
+
+int pack(Ctx* c) {
+  Net* N = net_of(c);
+  k_pack<<<(9 * kC * kC + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(N->theta, N->w1, N->w2f, N->w2b,
+                                                                        N->w3f, N->w3b, N->w4);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+int64_t blocks_for(int64_t items) { return (items + kBlock - 1) / kBlock; }
+
+// forward pass over g (input already in N->x); prediction in N->y
+int forward(Ctx* c, const Img& g) {
+  Net* N = net_of(c);
+  hipStream_t st = c->stream;
+  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
+  const int64_t nstrips = static_cast<int64_t>(g.B) * g.H * ((g.W + 15) / 16);
+  const int64_t sblocks = blocks_for(nstrips * 64);
+  k_conv_in<<<blocks_for(np), kBlock, 0, st>>>(g, N->x, N->w1, N->theta + kB1, N->a1);
+  k_conv_mid<<<sblocks, kBlock, 0, st>>>(g, N->a1, N->w2f, N->theta + kB2, N->a2, nstrips);
+  k_conv_mid<<<sblocks, kBlock, 0, st>>>(g, N->a2, N->w3f, N->theta + kB3, N->a3, nstrips);
+  k_conv_out<<<blocks_for(np), kBlock, 0, st>>>(g, N->a3, N->w4, N->theta + kB4, N->y);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+// loss and gradient (targets and mask in N->t, N->mask); gradient in N->grad, loss in N->dscal[0]
+int backward(Ctx* c, const Img& g) {
+  Net* N = net_of(c);
+  hipStream_t st = c->stream;
+  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
+  const int64_t nstrips = static_cast<int64_t>(g.B) * g.H * ((g.W + 15) / 16);
+  const int64_t sblocks = blocks_for(nstrips * 64);
+  const int lblocks = kSumBlocks;
+  const int64_t thin_chunk = 1024;
+  const int64_t thin_blocks = (np + thin_chunk - 1) / thin_chunk;
+  const int64_t wave_chunk = 32 * 32;   // pixels per wave in the MFMA weight gradient
+  const int64_t waves = (np + wave_chunk - 1) / wave_chunk;
+  const int64_t wblocks = (waves * 64 + kBlock - 1) / kBlock;
+  const int64_t mid_part = wblocks * 4 * 9 * kC * kC;
+  const int64_t thin_part = thin_blocks * (9 * kCin * kC + kC);
+  VIP_TRY(ensure_part(c, std::max(mid_part, thin_part), 2 + 2 * lblocks));
+  k_loss_partial<<<lblocks, 256, 0, st>>>(np, N->y, N->t, N->mask, N->dscal + 2);
+  k_loss_finish<<<1, 64, 0, st>>>(lblocks, N->dscal + 2, N->dscal);
+  k_loss_grad<<<blocks_for(np), kBlock, 0, st>>>(np, N->y, N->t, N->mask, N->dscal, N->gy);
+  // layer 4
+  k_thin_wgrad<<<thin_blocks, 320, 0, st>>>(g, kC, 1, N->a3, nullptr, N->gy, thin_chunk, N->part);
+  k_sum_parts<<<2, 256, 0, st>>>(N->part, static_cast<int>(thin_blocks), 9 * kC + 1, 9 * kC + 1, N->grad, kW4);
+  k_out_bwd<<<blocks_for(np), kBlock, 0, st>>>(g, N->gy, N->w4, N->a3, N->g3);
+  // layer 3
+  k_mid_wgrad<<<wblocks, kBlock, 0, st>>>(g, N->a2, N->g3, wave_chunk, N->part);
+  k_sum_parts<<<(9 * kC * kC + 255) / 256, 256, 0, st>>>(N->part, static_cast<int>(wblocks * 4), 9 * kC * kC,
+                                                         9 * kC * kC, N->grad, kW3);
+  k_bias_grad<<<thin_blocks, 64, 0, st>>>(np, N->g3, thin_chunk, N->part);
+  k_sum_parts<<<1, 64, 0, st>>>(N->part, static_cast<int>(thin_blocks), kC, kC, N->grad, kB3);
+  k_mid_bwd<<<sblocks, kBlock, 0, st>>>(g, N->g3, N->w3b, N->a2, N->g2, nstrips);
+  // layer 2
+  k_mid_wgrad<<<wblocks, kBlock, 0, st>>>(g, N->a1, N->g2, wave_chunk, N->part);
+  k_sum_parts<<<(9 * kC * kC + 255) / 256, 256, 0, st>>>(N->part, static_cast<int>(wblocks * 4), 9 * kC * kC,
+                                                         9 * kC * kC, N->grad, kW2);
+  k_bias_grad<<<thin_blocks, 64, 0, st>>>(np, N->g2, thin_chunk, N->part);
+  k_sum_parts<<<1, 64, 0, st>>>(N->part, static_cast<int>(thin_blocks), kC, kC, N->grad, kB2);
+  k_mid_bwd<<<sblocks, kBlock, 0, st>>>(g, N->g2, N->w2b, N->a1, N->g1, nstrips);
+  // layer 1
+  k_thin_wgrad<<<thin_blocks, 9 * kCin * kC + kC, 0, st>>>(g, kCin, kC, N->x, N->g1, nullptr, thin_chunk,
+                                                           N->part);
+  k_sum_parts<<<(9 * kCin * kC + kC + 255) / 256, 256, 0, st>>>(N->part, static_cast<int>(thin_blocks),
+                                                                9 * kCin * kC + kC, 9 * kCin * kC + kC, N->grad,
+                                                                kW1);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+int adam(Ctx* c, double lr) {
+  Net* N = net_of(c);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  N->step += 1;
+  const float c1 = static_cast<float>(1.0 - std::pow(0.9, N->step));
+  const float c2 = static_cast<float>(1.0 - std::pow(0.999, N->step));
+  k_adam<<<(kNParams + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(kNParams, N->theta, N->grad, N->m, N->v,
+                                                                    static_cast<float>(lr), b1, b2, eps, c1, c2);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return pack(c);
+}
+
+uint16_t host_bf16(double x) {
+  const float f = static_cast<float>(x);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>(u >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+constexpr int kScalHead = 16;
+
+// rms of a h^2 and c h^2 over lattice nodes into scal[0], scal[1]
+int lattice_rms(Ctx* c, const double* a, const double* cv) {
+  Learn& L = c->learn;
+  k_rms_part<<<kSumBlocks, 256, 0, c->stream>>>(c->n, L.pix, a, cv, c->h * c->h, L.scal + kScalHead);
+  k_rms_finish<<<1, 64, 0, c->stream>>>(kSumBlocks, L.scal + kScalHead, L.scal);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+int ensure_vectors(Ctx* c) {
+  Learn& L = c->learn;
+  if (L.r) return VIP_OK;
+  for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2}) VIP_TRY(dalloc(c, p, c->n));
+  VIP_TRY(dalloc(c, &L.scal, kScalHead + 6 * kSumBlocks));
+  return VIP_OK;
+}
+
+// q1 = L eprev and rx = r - q1
+int extrapolation_residual(Ctx* c) {
+  Learn& L = c->learn;
+  VIP_TRY(ell_apply(c, c->sys, 0, L.eprev, L.q1));
+  k_sub<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, L.r, L.q1, L.rx);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+}  // namespace
+
+// ---- entry points used by api.hip and step.hip ----------------------------------------------------------------
+
+int learn_n_params() { return kNParams; }
+
+int learn_set_params(Ctx* c, const double* theta) {
+  VIP_TRY(net_alloc(c));
+  std::vector<float> h(kNParams);
+  for (int k = 0; k < kNParams; ++k) {
+    if (!std::isfinite(theta[k])) return set_error(c, VIP_E_INVALID, "non-finite network parameter");
+    h[k] = static_cast<float>(theta[k]);
+  }
+  Net* N = net_of(c);
+  VIP_HIP_TRY(c, hipMemcpyAsync(N->theta, h.data(), sizeof(float) * kNParams, hipMemcpyHostToDevice, c->stream));
+  VIP_HIP_TRY(c, hipMemsetAsync(N->m, 0, sizeof(float) * kNParams, c->stream));
+  VIP_HIP_TRY(c, hipMemsetAsync(N->v, 0, sizeof(float) * kNParams, c->stream));
+  N->step = 0;
+  VIP_TRY(pack(c));
+  VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  N->ready = true;
+  return VIP_OK;
+}
+
+// He-uniform weights U(-sqrt(6/fan_in), sqrt(6/fan_in)) from splitmix64, zero biases
+int learn_init(Ctx* c, uint64_t seed) {
+  std::vector<double> th(kNParams, 0.0);
+  const struct {
+    int off, count, fan_in;
+  } layers[4] = {{kW1, 9 * kCin * kC, 9 * kCin}, {kW2, 9 * kC * kC, 9 * kC}, {kW3, 9 * kC * kC, 9 * kC},
+                 {kW4, 9 * kC, 9 * kC}};
+  uint64_t ctr = seed * 0x9E3779B97F4A7C15ull;
+  for (const auto& l : layers) {
+    const double lim = std::sqrt(6.0 / l.fan_in);
+    for (int k = 0; k < l.count; ++k) {
+      const double u = static_cast<double>(splitmix64(ctr++) >> 11) * (1.0 / 9007199254740992.0);
+      th[l.off + k] = (2.0 * u - 1.0) * lim;
+    }
+  }
+  return learn_set_params(c, th.data());
+}
+
+int learn_get_params(Ctx* c, double* theta) {
+  if (!learn_ready(c)) return set_error(c, VIP_E_NOT_BUILT, "network parameters not set");
+  Net* N = net_of(c);
+  std::vector<float> h(kNParams);
+  VIP_HIP_TRY(c, hipMemcpyAsync(h.data(), N->theta, sizeof(float) * kNParams, hipMemcpyDeviceToHost, c->stream));
+  VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < kNParams; ++k) theta[k] = h[k];
+  return VIP_OK;
+}
+
+// host images in, host results out; lr > 0 also takes one Adam step with the gradient
+int learn_eval(Ctx* c, const double* x, const double* t, const double* m, int B, int H, int W, double* y,
+               double* loss, double* grad, double lr) {
+  if (!learn_ready(c)) return set_error(c, VIP_E_NOT_BUILT, "network parameters not set");
+  if (B <= 0 || H <= 0 || W <= 0 || static_cast<int64_t>(B) * H * W > (int64_t{1} << 28))
+    return set_error(c, VIP_E_INVALID, "image sizes must be positive and at most 2^28 pixels");
+  if (!x) return set_error(c, VIP_E_INVALID, "input image is NULL");
+  const bool need_bwd = grad || loss || lr > 0.0;
+  if (need_bwd && (!t || !m)) return set_error(c, VIP_E_INVALID, "targets and mask are needed for the loss");
+  Net* N = net_of(c);
+  const int64_t np = static_cast<int64_t>(B) * H * W;
+  VIP_TRY(net_buffers(c, np));
+  hipStream_t st = c->stream;
+  std::vector<uint16_t> hx(np * kCin);
+  for (int64_t k = 0; k < np * kCin; ++k) hx[k] = host_bf16(x[k]);
+  VIP_HIP_TRY(c, hipMemcpyAsync(N->x, hx.data(), sizeof(uint16_t) * np * kCin, hipMemcpyHostToDevice, st));
+  const Img g{B, H, W};
+  VIP_TRY(forward(c, g));
+  std::vector<float> hy(np), ht, hm;
+  VIP_HIP_TRY(c, hipMemcpyAsync(hy.data(), N->y, sizeof(float) * np, hipMemcpyDeviceToHost, st));
+  double lc[2] = {0.0, 0.0};
+  std::vector<float> hg;
+  if (need_bwd) {
+    ht.resize(np);
+    hm.resize(np);
+    for (int64_t k = 0; k < np; ++k) {
+      ht[k] = static_cast<float>(t[k]);
+      hm[k] = static_cast<float>(m[k]);
+    }
+    VIP_HIP_TRY(c, hipMemcpyAsync(N->t, ht.data(), sizeof(float) * np, hipMemcpyHostToDevice, st));
+    VIP_HIP_TRY(c, hipMemcpyAsync(N->mask, hm.data(), sizeof(float) * np, hipMemcpyHostToDevice, st));
+    VIP_TRY(backward(c, g));
+    hg.resize(kNParams);
+    VIP_HIP_TRY(c, hipMemcpyAsync(lc, N->dscal, sizeof(lc), hipMemcpyDeviceToHost, st));
+    VIP_HIP_TRY(c, hipMemcpyAsync(hg.data(), N->grad, sizeof(float) * kNParams, hipMemcpyDeviceToHost, st));
+    if (lr > 0.0) VIP_TRY(adam(c, lr));
+  }
+  VIP_HIP_TRY(c, hipStreamSynchronize(st));
+  if (y)
+    for (int64_t k = 0; k < np; ++k) y[k] = hy[k];
+  if (loss) *loss = lc[0];
+  if (grad)
+    for (int k = 0; k < kNParams; ++k) grad[k] = hg[k];
+  return VIP_OK;
+}
+
+// lattice image of the node set (built once per node set)
+int learn_map(Ctx* c) {
+  Learn& L = c->learn;
+  if (L.mapped) return VIP_OK;
+  const double h = c->h;
+  const double wx = std::floor((c->xmax - c->xmin) / h + 0.5) + 1.0;
+  const double wy = std::floor((c->ymax - c->ymin) / h + 0.5) + 1.0;
+  if (!(wx * wy <= 4.0 * static_cast<double>(c->n) + 4096.0) || wx > 65536.0 || wy > 65536.0)
+    return set_error(c, VIP_E_INVALID, "node set is not lattice based (image much larger than the node count)");
+  L.W = static_cast<int>(wx);
+  L.H = static_cast<int>(wy);
+  const int64_t npix = static_cast<int64_t>(L.W) * L.H;
+  VIP_TRY(ensure_vectors(c));
+  VIP_TRY(dalloc(c, &L.pix, c->n));
+  VIP_TRY(dalloc(c, &L.node_of, npix));
+  VIP_HIP_TRY(c, hipMemsetAsync(L.pix, 0xff, sizeof(int32_t) * c->n, c->stream));
+  k_fill_i32<<<blocks_for(npix), kBlock, 0, c->stream>>>(npix, INT32_MAX, L.node_of);
+  k_pixel_claim<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, c->x, c->y, c->xmin, c->ymin, h, L.W, L.H,
+                                                            L.node_of);
+  k_pixel_finish<<<blocks_for(npix), kBlock, 0, c->stream>>>(npix, L.node_of, L.pix);
+  VIP_HIP_TRY(c, hipGetLastError());
+  VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  L.mapped = true;
+  return VIP_OK;
+}
+
+int learn_prepare(Ctx* c, const double* b, const double* phi, bool with_map) {
+  Learn& L = c->learn;
+  if (with_map) VIP_TRY(learn_map(c));
+  VIP_TRY(ensure_vectors(c));
+  k_copy_d<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, phi, L.phi_prev);
+  VIP_TRY(ell_apply(c, c->sys, 0, L.phi_prev, L.q1));
+  k_sub<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, b, L.q1, L.r);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_stats* stats) {
+  Learn& L = c->learn;
+  if (!L.have_eprev) return VIP_OK;   // no previous change yet: start from phi_prev
+  hipStream_t st = c->stream;
+  const double h2 = c->h * c->h;
+  const bool learned = mode == VIP_WS_LEARNED;
+  if (learned && !learn_ready(c))
+    return set_error(c, VIP_E_NOT_BUILT, "learned start vector requested without network parameters");
+  VIP_TRY(extrapolation_residual(c));
+  if (learned) {
+    Net* N = net_of(c);
+    const int64_t npix = static_cast<int64_t>(L.W) * L.H;
+    VIP_TRY(net_buffers(c, npix));
+    VIP_TRY(lattice_rms(c, L.rx, b));
+    k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, L.node_of, L.rx, b, L.scal, h2, N->x);
+    VIP_TRY(forward(c, Img{1, L.H, L.W}));
+    k_direction<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.pix, N->y, L.scal, h2, L.dir);
+    VIP_TRY(ell_apply(c, c->sys, 0, L.dir, L.q2));
+  }
+  k_dots6_part<<<kSumBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, L.r, L.scal + kScalHead);
+  k_dots6_finish<<<1, 64, 0, st>>>(kSumBlocks, L.scal + kScalHead, L.scal);
+  VIP_HIP_TRY(c, hipGetLastError());
+  double s[8];
+  VIP_HIP_TRY(c, hipMemcpyAsync(s, L.scal, sizeof(s), hipMemcpyDeviceToHost, st));
+  VIP_HIP_TRY(c, hipStreamSynchronize(st));
+  // minimise ||r - alpha q1 - beta q2||_2: normal equations of the 2 x 2 (or 1 x 1) problem
+  const double a11 = s[2], a12 = s[3], a22 = s[4], g1 = s[5], g2 = s[6], rr = s[7];
+  double alpha = 0.0, beta = 0.0;
+  const double det = a11 * a22 - a12 * a12;
+  if (learned && a22 > 0.0 && det > 1e-10 * a11 * a22) {
+    alpha = (g1 * a22 - g2 * a12) / det;
+    beta = (a11 * g2 - a12 * g1) / det;
+  } else if (a11 > 0.0) {
+    alpha = g1 / a11;
+  }
+  const double ratio2 = rr > 0.0 ? (rr - alpha * g1 - beta * g2) / rr : 1.0;
+  const double ratio = std::sqrt(std::max(ratio2, 0.0));
+  const bool accept = std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(ratio) && ratio < 1.0;
+  if (accept)
+    k_combine<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.phi_prev, L.eprev, beta != 0.0 ? L.dir : nullptr,
+                                                   alpha, beta, phi);
+  VIP_HIP_TRY(c, hipGetLastError());
+  if (stats) {
+    stats->warm_start = accept ? mode : VIP_WS_PREV;
+    stats->warm_ratio = ratio;
+    stats->warm_alpha = accept ? alpha : 0.0;
+    stats->warm_beta = accept ? beta : 0.0;
+  }
+  return VIP_OK;
+}
+
+int learn_finish(Ctx* c, const double* b, const double* phi, bool capture) {
+  Learn& L = c->learn;
+  hipStream_t st = c->stream;
+  if (capture && L.have_eprev && static_cast<int>(L.snaps.size()) < L.capacity) {
+    const int64_t npix = static_cast<int64_t>(L.W) * L.H;
+    Snapshot s;
+    s.W = L.W;
+    s.H = L.H;
+    VIP_TRY(dalloc(c, &s.x, 3 * npix));
+    if (dalloc(c, &s.t, npix) != VIP_OK) {
+      dfree(s.x);
+      return VIP_E_HIP;
+    }
+    L.snaps.push_back(s);
+    const double h2 = c->h * c->h;
+    VIP_TRY(extrapolation_residual(c));
+    VIP_TRY(lattice_rms(c, L.rx, b));
+    k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, L.node_of, L.rx, b, L.scal, h2, s.x);
+    k_make_target<<<blocks_for(npix), kBlock, 0, st>>>(npix, L.node_of, phi, L.phi_prev, L.eprev, L.scal, h2,
+                                                       s.t);
+  }
+  k_diff<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, phi, L.phi_prev, L.eprev);
+  VIP_HIP_TRY(c, hipGetLastError());
+  L.have_eprev = true;
+  return VIP_OK;
+}
+
+int learn_train(Ctx* c, int iters, int batch, int crop, double lr, uint64_t seed, double* last_loss) {
+  Learn& L = c->learn;
+  if (!learn_ready(c)) return set_error(c, VIP_E_NOT_BUILT, "network parameters not set");
+  if (L.snaps.empty()) return set_error(c, VIP_E_INVALID, "no captured snapshots to train on");
+  if (iters <= 0 || batch <= 0 || batch > 1024 || crop < 2 * kMargin + 4 || crop > 1024 || !(lr > 0.0))
+    return set_error(c, VIP_E_INVALID, "bad training arguments");
+  Net* N = net_of(c);
+  const int64_t np = static_cast<int64_t>(batch) * crop * crop;
+  VIP_TRY(net_buffers(c, np));
+  hipStream_t st = c->stream;
+  const Img g{batch, crop, crop};
+  double loss = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    for (int k = 0; k < batch; ++k) {
+      const uint64_t key = splitmix64(seed) + (static_cast<uint64_t>(N->step) << 20) + static_cast<uint64_t>(k);
+      const uint64_t r0 = splitmix64(3 * key), r1 = splitmix64(3 * key + 1), r2 = splitmix64(3 * key + 2);
+      const Snapshot& s = L.snaps[r0 % L.snaps.size()];
+      const int oy = static_cast<int>(r1 % static_cast<uint64_t>(std::max(1, s.H - crop + 1)));
+      const int ox = static_cast<int>(r2 % static_cast<uint64_t>(std::max(1, s.W - crop + 1)));
+      k_make_crop<<<blocks_for(static_cast<int64_t>(crop) * crop), kBlock, 0, st>>>(
+          s.x, s.t, s.W, s.H, oy, ox, crop, k, N->x, N->t, N->mask, kMargin);
+    }
+    VIP_TRY(forward(c, g));
+    VIP_TRY(backward(c, g));
+    VIP_TRY(adam(c, lr));
+    if (it == iters - 1 || (it + 1) % 50 == 0) {
+      double lc[2];
+      VIP_HIP_TRY(c, hipMemcpyAsync(lc, N->dscal, sizeof(lc), hipMemcpyDeviceToHost, st));
+      VIP_HIP_TRY(c, hipStreamSynchronize(st));
+      loss = lc[0];
+      if (!std::isfinite(loss)) return set_error(c, VIP_E_NONFINITE, "training loss is not finite");
+      if (c->debug) std::fprintf(stderr, "[vip] train iter %d loss %.4e\n", it + 1, loss);
+    }
+  }
+  if (last_loss) *last_loss = loss;
+  return VIP_OK;
+}
+
+}  // namespace vip

@@ -196,6 +196,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   if (!c->assembled || dt != c->cur_dt || re != c->cur_re) {
     VIP_TRY(assemble_helmholtz(c, dt, re));
     c->have_prev_n = false;   // AB2 restarts after a change of dt or Re
+    c->learn.have_eprev = false;
   }
   if (!c->stepbuf) VIP_TRY(dalloc(c, &c->stepbuf, 5 * n));
   double* ru = c->stepbuf;
@@ -216,9 +217,26 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   if (rc_h != VIP_OK && rc_h != VIP_E_NOT_CONVERGED) return rc_h;
   k_divergence<<<grid_for(n), kBlock, 0, s>>>(n, V, c->bpos, us, vs, 1.0 / dt, b);
   VIP_HIP_TRY(c, hipGetLastError());
-  const bool warm = c->opt.warmstart == VIP_WS_PREV && c->have_prev_phi;
+  const int ws = c->opt.warmstart;
+  const bool warm = ws != VIP_WS_ZERO && c->have_prev_phi;
+  const bool predict = (ws == VIP_WS_LEARNED || ws == VIP_WS_EXTRAP) && c->have_prev_phi;
+  const bool capture = c->have_prev_phi && static_cast<int>(c->learn.snaps.size()) < c->learn.capacity;
+  const bool track = predict || capture;
+  if (st) {
+    st->warm_start = warm ? VIP_WS_PREV : VIP_WS_ZERO;
+    st->warm_ratio = 0.0;
+    st->warm_alpha = 0.0;
+    st->warm_beta = 0.0;
+  }
+  if (track) VIP_TRY(learn_prepare(c, b, c->phi, ws == VIP_WS_LEARNED || capture));
+  if (predict) VIP_TRY(learn_warm_start(c, ws, b, c->phi, st));
   int rc_p = poisson_solve(c, b, c->phi, c->opt.poisson_tol, warm, st);
   if (rc_p != VIP_OK && rc_p != VIP_E_NOT_CONVERGED) return rc_p;
+  if (track) {
+    VIP_TRY(learn_finish(c, b, c->phi, capture));
+  } else {
+    c->learn.have_eprev = false;   // the chain of increments is not followed
+  }
   k_project<<<grid_for(n), kBlock, 0, s>>>(n, V, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
                                             v, p);
   VIP_HIP_TRY(c, hipGetLastError());

@@ -89,6 +89,35 @@ struct Timing {
   int64_t count = 0;
 };
 
+// One captured solver snapshot as a lattice image (independent of the node set
+// it came from): BF16 input channels [H][W][3] and the FP32 target [H][W].
+struct Snapshot {
+  int W = 0, H = 0;
+  uint16_t* x = nullptr;
+  float* t = nullptr;
+};
+
+// Learned start vector: lattice raster map, captured training data, network state.
+struct Learn {
+  void* net = nullptr;        // network parameters and buffers (learn.hip)
+  bool mapped = false;
+  int W = 0, H = 0;           // lattice image size of the current node set
+  int32_t* pix = nullptr;     // device [n]: pixel of each node or -1 (off the lattice)
+  int32_t* node_of = nullptr; // device [H*W]: node at each pixel or -1
+  int capacity = 0;           // vip_step stores snapshots while fewer than this are held
+  std::vector<Snapshot> snaps;
+  double* r = nullptr;        // device [n]: b - L phi_prev of the current step
+  double* phi_prev = nullptr; // device [n]
+  double* eprev = nullptr;    // device [n]: previous increment change phi_n - phi_(n-1)
+  bool have_eprev = false;
+  double* q1 = nullptr;        // device [n]: L eprev
+  double* rx = nullptr;       // device [n]: residual after extrapolation, r - L eprev
+  double* dir = nullptr;      // device [n]: the network's correction c
+  double* q2 = nullptr;       // device [n]: L c
+  double* scal = nullptr;     // device [16 + 6*256]: [0] rms(rx h^2), [1] rms(b h^2), [2..7] the dots
+                              // q1.q1, q1.q2, q2.q2, q1.r, q2.r, r.r, then block partials
+};
+
 struct Ctx {
   int device = 0;
   int debug = 0;                  // VIP_DEBUG=1: trace Krylov batches on stderr
@@ -101,7 +130,8 @@ struct Ctx {
   // node set
   int64_t n = 0, nb = 0;
   double h = 0.0, rho0 = 0.0;
-  double xmin = 0.0, ymin = 0.0;  // bounding-box origin of the node set
+  double xmin = 0.0, ymin = 0.0;  // bounding box of the node set
+  double xmax = 0.0, ymax = 0.0;
   bool periodic = false, singular = false, symmetric = false;
   double* x = nullptr;            // device [n]
   double* y = nullptr;            // device [n]
@@ -146,6 +176,7 @@ struct Ctx {
   KrylovScalars* sc_host = nullptr; // pinned host mirror
 
   Amg amg;
+  Learn learn;
   Timing timing;
 };
 
@@ -236,5 +267,27 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
 int convection(Ctx* c, const double* u, const double* v, double* nx, double* ny);
 int divergence(Ctx* c, const double* u, const double* v, double* d);
 int gradient(Ctx* c, const double* f, double* gx, double* gy);
+
+// Learned start vector (learn.hip)
+int learn_n_params();
+int learn_set_params(Ctx* c, const double* theta);
+int learn_get_params(Ctx* c, double* theta);
+int learn_eval(Ctx* c, const double* x, const double* t, const double* m, int B, int H, int W, double* y,
+               double* loss, double* grad, double lr);
+int learn_map(Ctx* c);
+int learn_train(Ctx* c, int iters, int batch, int crop, double lr, uint64_t seed, double* last_loss);
+bool learn_ready(const Ctx* c);
+// before the pressure solve: keep phi_prev = phi and r = b - L phi_prev (with_map: build the
+// lattice map too, which fails on node sets that are not lattice based)
+int learn_prepare(Ctx* c, const double* b, const double* phi, bool with_map);
+// phi = phi_prev + alpha e (+ beta c with the network's correction c in mode VIP_WS_LEARNED),
+// e the previous change of phi, alpha and beta minimising the FP64 residual; fills the stats
+int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_stats* st);
+// after the pressure solve: store one snapshot (if capture is on) and the change of phi
+int learn_finish(Ctx* c, const double* b, const double* phi, bool capture);
+int learn_init(Ctx* c, uint64_t seed);
+void learn_clear(Ctx* c);          // drop the captured snapshots
+void learn_free_nodeset(Ctx* c);   // drop what belongs to the node set (map, vectors)
+void learn_free(Ctx* c);           // everything
 
 }  // namespace vip

@@ -24,7 +24,7 @@ W_CUBIC_SPLINE, W_PAPER = 0, 1
 I_MLS, I_EXACT = 0, 1
 P_FP64, P_MIXED = 0, 1
 K_AUTO, K_PCG, K_BICGSTAB = 0, 1, 2
-WS_ZERO, WS_PREV = 0, 1
+WS_ZERO, WS_PREV, WS_LEARNED, WS_EXTRAP = 0, 1, 2, 3
 PC_JACOBI, PC_AMG = 0, 1
 OP = dict(identity=0, laplacian=1, vip_e=2, vip_w=3, vip_n=4, vip_s=5, normal1=6, normal2=7,
           poisson=8, helm_u=9, helm_v=10, poisson32=11)
@@ -44,7 +44,9 @@ class VipStepStats(ctypes.Structure):
     _fields_ = [("poisson_iters", ctypes.c_int), ("poisson_outer", ctypes.c_int),
                 ("helmholtz_iters", ctypes.c_int), ("krylov_used", ctypes.c_int),
                 ("poisson_residual", ctypes.c_double), ("helmholtz_residual", ctypes.c_double),
-                ("border_lambda", ctypes.c_double)]
+                ("border_lambda", ctypes.c_double), ("warm_start", ctypes.c_int),
+                ("warm_ratio", ctypes.c_double), ("warm_alpha", ctypes.c_double),
+                ("warm_beta", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -84,6 +86,15 @@ SIGNATURES = {
     "vip_divergence": (_INT, [_P, _P, _P, _P]),
     "vip_gradient": (_INT, [_P, _P, _P, _P]),
     "vip_kernel_timing": (_INT, [_P, _INT, _INT, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    "vip_learn_n_params": (_INT, []),
+    "vip_learn_init": (_INT, [_P, ctypes.c_uint64]),
+    "vip_learn_set_params": (_INT, [_P, _P, _I64]),
+    "vip_learn_get_params": (_INT, [_P, _P, _I64]),
+    "vip_learn_eval": (_INT, [_P, _P, _P, _P, _INT, _INT, _INT, _P, ctypes.POINTER(_D), _P, _D]),
+    "vip_learn_capture": (_INT, [_P, _INT]),
+    "vip_learn_snapshot_count": (_INT, [_P, ctypes.POINTER(_INT)]),
+    "vip_learn_clear": (_INT, [_P]),
+    "vip_learn_train": (_INT, [_P, _INT, _INT, _INT, _D, ctypes.c_uint64, ctypes.POINTER(_D)]),
 }
 
 
@@ -252,6 +263,62 @@ class Context:
         self._check(self.lib.vip_kernel_timing(self._h, int(enable), int(reset), ctypes.byref(avg),
                                                ctypes.byref(cnt)), "vip_kernel_timing")
         return avg.value, cnt.value
+
+    # ---- learned start vector ---------------------------------------------------------
+    def vip_learn_n_params(self):
+        return int(self.lib.vip_learn_n_params())
+
+    def vip_learn_init(self, seed):
+        self._check(self.lib.vip_learn_init(self._h, ctypes.c_uint64(int(seed))), "vip_learn_init")
+
+    def vip_learn_set_params(self, theta):
+        th = _host(theta, np.float64).reshape(-1)
+        self._check(self.lib.vip_learn_set_params(self._h, th.ctypes.data, len(th)),
+                    "vip_learn_set_params")
+
+    def vip_learn_get_params(self):
+        th = np.empty(self.vip_learn_n_params())
+        self._check(self.lib.vip_learn_get_params(self._h, th.ctypes.data, len(th)),
+                    "vip_learn_get_params")
+        return th
+
+    def vip_learn_eval(self, x, target=None, mask=None, lr=0.0, want_grad=True):
+        """x [B,H,W,3] host images -> (y [B,H,W], loss or None, grad or None)."""
+        x = _host(x, np.float64)
+        B, H, W, C = x.shape
+        if C != 3:
+            raise ValueError("input images need 3 channels")
+        y = np.empty((B, H, W))
+        have_t = target is not None
+        t = _host(target, np.float64).reshape(B, H, W) if have_t else None
+        m = _host(mask, np.float64).reshape(B, H, W) if have_t else None
+        loss = _D()
+        g = np.empty(self.vip_learn_n_params()) if (have_t and want_grad) else None
+        rc = self.lib.vip_learn_eval(self._h, x.ctypes.data, t.ctypes.data if have_t else None,
+                                     m.ctypes.data if have_t else None, B, H, W, y.ctypes.data,
+                                     ctypes.byref(loss) if have_t else None,
+                                     g.ctypes.data if g is not None else None, float(lr))
+        self._check(rc, "vip_learn_eval")
+        return y, (loss.value if have_t else None), g
+
+    def vip_learn_capture(self, max_snapshots):
+        self._check(self.lib.vip_learn_capture(self._h, int(max_snapshots)), "vip_learn_capture")
+
+    def vip_learn_snapshot_count(self):
+        k = _INT()
+        self._check(self.lib.vip_learn_snapshot_count(self._h, ctypes.byref(k)),
+                    "vip_learn_snapshot_count")
+        return k.value
+
+    def vip_learn_clear(self):
+        self._check(self.lib.vip_learn_clear(self._h), "vip_learn_clear")
+
+    def vip_learn_train(self, iters, batch, crop, lr, seed):
+        loss = _D()
+        self._check(self.lib.vip_learn_train(self._h, int(iters), int(batch), int(crop), float(lr),
+                                             ctypes.c_uint64(int(seed)), ctypes.byref(loss)),
+                    "vip_learn_train")
+        return loss.value
 
     # ---- convenience ---------------------------------------------------------------
     def build_from_spec(self, spec, **opts):

@@ -53,6 +53,7 @@ int main(void) {
   F(vip_step_stats, poisson_iters) F(vip_step_stats, poisson_outer) F(vip_step_stats, helmholtz_iters)
   F(vip_step_stats, krylov_used) F(vip_step_stats, poisson_residual)
   F(vip_step_stats, helmholtz_residual) F(vip_step_stats, border_lambda)
+  F(vip_step_stats, warm_start) F(vip_step_stats, warm_ratio) F(vip_step_stats, warm_alpha) F(vip_step_stats, warm_beta)
   return 0;
 }
 """
@@ -93,3 +94,11 @@ def test_product_code_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
                 assert "oracle/" not in text, f
+
+
+def test_network_size_matches_the_oracle_layout():
+    """The flat parameter vector of the learned start vector has the oracle's layout size
+    (a call that touches no device)."""
+    _ensure_built()
+    from oracle import cnn
+    assert vip.load().vip_learn_n_params() == cnn.n_params() == 19681

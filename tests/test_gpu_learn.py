@@ -1,0 +1,275 @@
+"""GPU checks of the learned start vector of the pressure solve, through the C ABI.
+
+The network kernels (BF16 weights and activations, FP32 sums) are compared with
+the FP64 oracle of the same network: forward output, loss and the gradient of
+every parameter block, and one Adam step.  BF16 keeps 8 significant bits, so
+each layer's activations carry a relative rounding error up to 2^-9; over four
+layers and the backward pass the relative L2 error of outputs and gradient
+blocks stays near 1e-2, and the bound used is 3e-2.  The solver-side checks run
+the learned start vector inside vip_step and require the same converged result
+as the plain start vector.
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+BF16_TOL = 3e-2
+
+
+def _ctx():
+    import torch
+    from paper_1401_6513_amd import vip
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return vip.Context(0)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _blocks(theta):
+    names = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
+    return dict(zip(names, cnn.unflatten(theta)))
+
+
+def _bf16_weights(theta):
+    """Weights rounded to BF16 as the kernels hold them; biases stay FP32."""
+    parts = cnn.unflatten(theta)
+    out = [cnn.bf16_round(p) if p.ndim == 4 else np.float32(p).astype(np.float64) for p in parts]
+    return cnn.flatten(out)
+
+
+def _case(seed, B, H, W):
+    rng = np.random.default_rng(seed)
+    theta = cnn.init_params(seed) + 0.05 * rng.standard_normal(cnn.n_params()) * 0.1
+    x = rng.standard_normal((B, H, W, 3))
+    x[..., 2] = (rng.uniform(size=(B, H, W)) > 0.3)
+    t = rng.standard_normal((B, H, W))
+    m = (rng.uniform(size=(B, H, W)) > 0.25).astype(float)
+    return theta, x, t, m
+
+
+@pytest.mark.parametrize("B,H,W", [(1, 8, 8), (2, 19, 37), (1, 33, 16), (3, 5, 50)])
+def test_forward_matches_oracle(B, H, W):
+    ctx = _ctx()
+    theta, x, _, _ = _case(10 + H, B, H, W)
+    ctx.vip_learn_set_params(theta)
+    y, _, _ = ctx.vip_learn_eval(x)
+    ref, _ = cnn.forward(_bf16_weights(theta), cnn.bf16_round(x))
+    print("forward B=%d H=%d W=%d rel %.3e" % (B, H, W, _rel(y, ref)))
+    assert _rel(y, ref) < BF16_TOL
+
+
+def _emulated(theta, x, t, m):
+    """The oracle's layers composed with BF16 rounding wherever the kernels store BF16:
+    weights, input, the three activations and the three backward activation gradients."""
+    W1, b1, W2, b2, W3, b3, W4, b4 = cnn.unflatten(_bf16_weights(theta))
+    r = cnn.bf16_round
+    a0 = r(x)
+    a1 = r(np.maximum(cnn.conv(a0, W1, b1), 0.0))
+    a2 = r(np.maximum(cnn.conv(a1, W2, b2), 0.0))
+    a3 = r(np.maximum(cnn.conv(a2, W3, b3), 0.0))
+    y = cnn.conv(a3, W4, b4)[..., 0]
+    cnt = m.sum()
+    loss = float((m * (y - t) ** 2).sum() / cnt)
+    gy = (2.0 * m * (y - t) / cnt)[..., None]
+    g3, gW4, gb4 = cnn.conv_backward(a3, W4, gy)
+    g3 = r(g3 * (a3 > 0))
+    g2, gW3, gb3 = cnn.conv_backward(a2, W3, g3)
+    g2 = r(g2 * (a2 > 0))
+    g1, gW2, gb2 = cnn.conv_backward(a1, W2, g2)
+    g1 = r(g1 * (a1 > 0))
+    _, gW1, gb1 = cnn.conv_backward(a0, W1, g1)
+    return y, loss, cnn.flatten([gW1, gb1, gW2, gb2, gW3, gb3, gW4, gb4])
+
+
+@pytest.mark.parametrize("B,H,W", [(1, 12, 12), (2, 19, 37)])
+def test_gradient_matches_oracle(B, H, W):
+    """Against the BF16-rounding composition of the oracle's layers the only differences left
+    are FP32 summation order and rounding-boundary flips (bound 5e-3); against the exact FP64
+    network the three BF16 backward stages before the first layer's gradient compound to a
+    few 1e-2 (bound 6e-2 for gradients, 3e-2 for the loss)."""
+    ctx = _ctx()
+    theta, x, t, m = _case(20 + H, B, H, W)
+    ctx.vip_learn_set_params(theta)
+    y, loss, g = ctx.vip_learn_eval(x, t, m)
+    ey, eloss, eg = _emulated(theta, x, t, m)
+    ref_loss, ref_g = cnn.loss_and_grad(_bf16_weights(theta), cnn.bf16_round(x), t, m)
+    got, emu, ref = _blocks(g), _blocks(eg), _blocks(ref_g)
+    worst_e = worst_r = 0.0
+    for name in ref:
+        re_, rr_ = _rel(got[name], emu[name]), _rel(got[name], ref[name])
+        print("grad %s rel vs emulated %.3e, vs FP64 %.3e" % (name, re_, rr_))
+        worst_e, worst_r = max(worst_e, re_), max(worst_r, rr_)
+    print("y rel vs emulated %.3e loss %.6e emulated %.6e fp64 %.6e" % (_rel(y, ey), loss, eloss, ref_loss))
+    assert _rel(y, ey) < 5e-3
+    assert abs(loss - eloss) <= 5e-3 * eloss
+    assert abs(loss - ref_loss) <= BF16_TOL * ref_loss
+    assert worst_e < 5e-3
+    assert worst_r < 6e-2
+
+
+def test_gradient_of_fp32_inputs_is_consistent_with_finite_differences():
+    """Directional derivative of the GPU loss along the GPU gradient, by central differences
+    of GPU losses (checks the gradient's sign and scale on the kernels alone)."""
+    ctx = _ctx()
+    theta, x, t, m = _case(5, 1, 16, 16)
+    ctx.vip_learn_set_params(theta)
+    _, l0, g = ctx.vip_learn_eval(x, t, m)
+    d = g / np.linalg.norm(g)
+    eps = 2e-2 * np.linalg.norm(theta) / np.sqrt(len(theta))
+    ctx.vip_learn_set_params(theta + eps * d)
+    _, lp, _ = ctx.vip_learn_eval(x, t, m)
+    ctx.vip_learn_set_params(theta - eps * d)
+    _, lm, _ = ctx.vip_learn_eval(x, t, m)
+    fd = (lp - lm) / (2 * eps)
+    print("directional derivative %.6e fd %.6e" % (np.linalg.norm(g), fd))
+    assert fd == pytest.approx(np.linalg.norm(g), rel=5e-2)
+
+
+def test_adam_step_matches_oracle():
+    ctx = _ctx()
+    theta, x, t, m = _case(7, 2, 10, 21)
+    lr = 1e-3
+    ctx.vip_learn_set_params(theta)
+    _, _, g = ctx.vip_learn_eval(x, t, m)
+    _, _, g2 = ctx.vip_learn_eval(x, t, m, lr=lr)
+    assert np.array_equal(g, g2)          # deterministic reductions
+    th1 = ctx.vip_learn_get_params()
+    z = np.zeros_like(theta)
+    ref, _, _ = cnn.adam_step(np.float32(theta).astype(np.float64), g, z, z, 1, lr)
+    assert np.max(np.abs(th1 - ref)) < 1e-6
+    # a second step uses the kept moments
+    _, _, g3 = ctx.vip_learn_eval(x, t, m, lr=lr)
+    th2 = ctx.vip_learn_get_params()
+    m1 = 0.1 * g
+    v1 = 0.001 * g * g
+    ref2, _, _ = cnn.adam_step(th1, g3, m1, v1, 2, lr)
+    assert np.max(np.abs(th2 - ref2)) < 1e-6
+
+
+def test_init_is_deterministic_and_bounded():
+    ctx = _ctx()
+    ctx.vip_learn_init(123)
+    a = ctx.vip_learn_get_params()
+    ctx.vip_learn_init(123)
+    b = ctx.vip_learn_get_params()
+    ctx.vip_learn_init(124)
+    c = ctx.vip_learn_get_params()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    blocks = _blocks(a)
+    for name, fan in (("W1", 27), ("W2", 288), ("W3", 288), ("W4", 288)):
+        lim = np.sqrt(6.0 / fan)
+        w = blocks[name]
+        assert np.all(np.abs(w) <= lim * (1 + 1e-6)) and np.std(w) > 0.4 * lim
+    for name in ("b1", "b2", "b3", "b4"):
+        assert np.all(blocks[name] == 0.0)
+
+
+def test_invalid_learn_arguments():
+    from paper_1401_6513_amd import vip
+    ctx = _ctx()
+    with pytest.raises(vip.VipError, match="NOT_BUILT"):
+        ctx.vip_learn_get_params()
+    with pytest.raises(vip.VipError, match="INVALID"):
+        ctx.vip_learn_set_params(np.zeros(10))
+    bad = np.zeros(cnn.n_params())
+    bad[5] = np.nan
+    with pytest.raises(vip.VipError, match="INVALID"):
+        ctx.vip_learn_set_params(bad)
+    ctx.vip_learn_init(1)
+    with pytest.raises(vip.VipError, match="INVALID"):
+        ctx.vip_learn_train(10, 4, 32, 1e-3, 0)      # no snapshots
+    with pytest.raises(vip.VipError, match="INVALID"):
+        ctx.vip_learn_capture(-1)
+
+
+def _cavity(ctx, n, **opts):
+    import torch
+    from paper_1401_6513_amd import nodesets, vip
+    spec = nodesets.lid_cavity(n)
+    ctx.build_from_spec(spec, precision=vip.P_MIXED, **opts)
+    z = torch.zeros(len(spec.xy), dtype=torch.float64, device="cuda")
+    u0, v0, _ = nodesets.boundary_initial(spec, (0.0, 0.0))
+    u = torch.tensor(u0, device="cuda")
+    v = torch.tensor(v0, device="cuda")
+    return spec, u, v, z.clone()
+
+
+def test_learned_start_vector_in_steps():
+    """Capture, train and use the network inside vip_step: the learned start vector is
+    accepted or rejected on its FP64 residual and the converged state matches the
+    plain previous-increment start to the Poisson tolerance."""
+    import torch
+    from paper_1401_6513_amd import vip
+    ctx = _ctx()
+    spec, u, v, p = _cavity(ctx, 49, warmstart=vip.WS_PREV)
+    dt, Re = 0.01, 100.0
+    ctx.vip_learn_capture(12)
+    for _ in range(14):
+        ctx.vip_step(u, v, p, dt, Re)
+    assert ctx.vip_learn_snapshot_count() == 12
+    ctx.vip_learn_capture(0)
+    ctx.vip_learn_init(3)
+    l_first = ctx.vip_learn_train(1, 8, 32, 1e-3, 0)
+    l_last = ctx.vip_learn_train(150, 8, 32, 1e-3, 1)
+    print("train loss %.4e -> %.4e" % (l_first, l_last))
+    assert np.isfinite(l_last) and l_last < l_first
+    # two copies of the state: one continued with the plain start, one with the learned start
+    u2, v2, p2 = u.clone(), v.clone(), p.clone()
+    ctx2 = vip.Context(0)
+    ctx2.build_from_spec(spec, precision=vip.P_MIXED, warmstart=vip.WS_LEARNED)
+    ctx2.vip_learn_set_params(ctx.vip_learn_get_params())
+    ctx.vip_reset_history()
+    ratios = []
+    for k in range(6):
+        s1 = ctx.vip_step(u, v, p, dt, Re)
+        s2 = ctx2.vip_step(u2, v2, p2, dt, Re)
+        assert s1["poisson_residual"] <= 1e-8 and s2["poisson_residual"] <= 1e-8
+        if k > 1:      # from the third step on the previous change of phi is known
+            assert s2["warm_start"] in (vip.WS_PREV, vip.WS_LEARNED)
+            assert 0.0 < s2["warm_ratio"] <= 1.0
+            ratios.append(s2["warm_ratio"])
+    print("warm ratios", ratios)
+    for a, b in ((u, u2), (v, v2), (p, p2)):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        b = b - b.mean() + a.mean()
+        assert _rel(b, a) < 1e-6
+    ctx2.close()
+
+
+def test_learned_start_needs_parameters_and_a_lattice():
+    import torch
+    from paper_1401_6513_amd import vip
+    ctx = _ctx()
+    spec, u, v, p = _cavity(ctx, 17, warmstart=vip.WS_LEARNED)
+    ctx.vip_step(u, v, p, 0.01, 100.0)           # no previous increment: no network use
+    ctx.vip_step(u, v, p, 0.01, 100.0)           # no previous change of it: no network use
+    with pytest.raises(vip.VipError, match="NOT_BUILT"):
+        ctx.vip_step(u, v, p, 0.01, 100.0)
+
+
+def test_extrapolated_start_vector():
+    """The non-learned correction phi_n + alpha (phi_n - phi_(n-1)) never raises the start
+    residual and leaves the converged state unchanged."""
+    from paper_1401_6513_amd import vip
+    ctx = _ctx()
+    spec, u, v, p = _cavity(ctx, 33, warmstart=vip.WS_PREV)
+    ctx2 = vip.Context(0)
+    ctx2.build_from_spec(spec, precision=vip.P_MIXED, warmstart=vip.WS_EXTRAP)
+    u2, v2, p2 = u.clone(), v.clone(), p.clone()
+    for k in range(8):
+        ctx.vip_step(u, v, p, 0.01, 100.0)
+        s2 = ctx2.vip_step(u2, v2, p2, 0.01, 100.0)
+        if k > 1:
+            assert 0.0 < s2["warm_ratio"] <= 1.0
+            assert s2["warm_start"] in (vip.WS_PREV, vip.WS_EXTRAP)
+    for a, b in ((u, u2), (v, v2), (p, p2)):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        b = b - b.mean() + a.mean()
+        assert _rel(b, a) < 1e-6
+    ctx2.close()

@@ -5,17 +5,23 @@ Workload (the configuration the headline metric is quoted on): flow past a
 circular cylinder D = 1 in [-10, 20] x [-10, 10] with h = D/128 (lattice nodes
 outside the body plus 256 surface nodes), together with the equilateral
 triangular lid-driven cavity (side 1, lid on top) at the same h; Re = 200,
-dt = h/5 (CFL 0.2 at the free stream), pressure Poisson solved to an FP64
-relative residual of 1e-8.  One step = one fractional step of both domains.
+dt = h/10 (local CFL about 0.2 at the cylinder's shoulders, where |u| ~ 2),
+pressure Poisson solved to an FP64 relative residual of 1e-8.  One step = one
+fractional step of both domains.
 
-Two paths are timed on the same node sets:
-  * mixed:  FP32 inner Krylov (SpMV + vectors) inside FP64 iterative refinement,
-            Poisson start vector = the previous step's increment;
-  * fp64:   plain FP64 Krylov from a zero start vector.
-`value` is the mixed path.  The roofline entry is the mixed path's pressure
-SpMV, timed with HIP events inside the library over the timed steps.  The CPU
-baseline runs the FP64 oracle (SciPy, Krylov mode, same tolerance) on a window
-of the same workload.
+Paths timed on the same node sets, each from the same impulsive start:
+  * learned: FP32 inner Krylov (SpMV + vectors) inside FP64 iterative
+             refinement; Poisson start vector phi_n + alpha (phi_n - phi_(n-1))
+             + beta c with c the learned network's correction;
+  * mixed:   the same precision split, start vector phi_n;
+  * fp64:    plain FP64 Krylov, start vector phi_n;
+  (optional: extrap = mixed with the extrapolation alone, fp64zero = FP64 from
+  a zero start vector).
+The network is trained before any timing on snapshots the solver generates on
+small training node sets (one-off, outside the timed region).  `value` is the
+learned path.  The roofline entry is that path's pressure SpMV, timed with HIP
+events inside the library over the timed steps.  The CPU baseline runs the
+FP64 oracle (SciPy, Krylov mode, same tolerance) on a window of the workload.
 
 Prints one JSON line.
 """
@@ -71,13 +77,23 @@ def _initial(spec, dev):
     return [torch.tensor(a, device=dev) for a in (u, v, p)]
 
 
+PATHS = {
+    "learned": dict(precision="P_MIXED", warmstart="WS_LEARNED"),
+    "mixed": dict(precision="P_MIXED", warmstart="WS_PREV"),
+    "extrap": dict(precision="P_MIXED", warmstart="WS_EXTRAP"),
+    "fp64": dict(precision="P_FP64", warmstart="WS_PREV"),
+    "fp64zero": dict(precision="P_FP64", warmstart="WS_ZERO"),
+}
+
+
 def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol):
     import torch
     dev = torch.device("cuda", 0)
+    cfg = PATHS[path]
     for ctx, spec in zip(ctxs, specs):
         opt = vip.default_options(period=spec.period, poisson_tol=tol, inner_tol=inner_tol,
-                                  precision=vip.P_MIXED if path == "mixed" else vip.P_FP64,
-                                  warmstart=vip.WS_PREV if path == "mixed" else vip.WS_ZERO)
+                                  precision=getattr(vip, cfg["precision"]),
+                                  warmstart=getattr(vip, cfg["warmstart"]))
         ctx.vip_set_options(opt)
         ctx.vip_reset_history()
     state = [_initial(s, dev) for s in specs]
@@ -95,9 +111,10 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
         for ctx, (u, v, p) in zip(ctxs, state):
             row.append(ctx.vip_step(u, v, p, dt, re))
         stats.append(row)
-        log("%s step %d: poisson iters %s, residual %s" % (
+        log("%s step %d: poisson iters %s, residual %s, start %s ratio %s" % (
             path, k + 1, [s["poisson_iters"] for s in row],
-            ["%.1e" % s["poisson_residual"] for s in row]))
+            ["%.1e" % s["poisson_residual"] for s in row], [s["warm_start"] for s in row],
+            ["%.3g" % s["warm_ratio"] for s in row]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     spmv = None
@@ -144,14 +161,16 @@ def cpu_baseline(h, dt, re, budget_s):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3,
+                    help="untimed steps per path (the start-vector corrections need two)")
     ap.add_argument("--h", type=float, default=1.0 / 128)
     ap.add_argument("--re", type=float, default=200.0)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-4,
                     help="relative tolerance of the FP32 inner solve (mixed path)")
-    ap.add_argument("--paths", default="mixed,fp64")
+    ap.add_argument("--paths", default="learned,mixed,fp64")
+    ap.add_argument("--train-iters", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -168,7 +187,7 @@ def main():
     import torch
     from paper_1401_6513_amd import vip
     h = args.h
-    dt = h / 5.0
+    dt = h / 10.0
     re = args.re
     log("generating node sets (h = %g)" % h)
     specs = workload(h)
@@ -194,14 +213,30 @@ def main():
         del src, dst
 
     paths = [p for p in args.paths.split(",") if p]
+    for p in paths:
+        if p not in PATHS:
+            sys.exit("unknown path %r (known: %s)" % (p, ", ".join(PATHS)))
+    train_info = None
+    if "learned" in paths:
+        from paper_1401_6513_amd import training
+        t0 = time.perf_counter()
+        theta, nsnap, loss = training.trained_parameters(iters=args.train_iters)
+        torch.cuda.synchronize()
+        train_info = {"snapshots": nsnap, "iters": args.train_iters, "last_loss": loss,
+                      "seconds": time.perf_counter() - t0,
+                      "data": "cavity 129x129 Re~U[100,1000] and cylinder h=1/16 in [-4,8]x[-4,4] "
+                              "Re~U[60,200], dt=h/10, 40 snapshots per run after 40 steps, 4 runs"}
+        log("network trained: %d snapshots, loss %.3e, %.1f s" % (nsnap, loss, train_info["seconds"]))
+        for c in ctxs:
+            c.vip_learn_set_params(theta)
     results = {}
     for path in paths:
         el, stats, spmv, fields = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
-                                           args.steps, args.tol, (path == "mixed"), args.inner_tol)
+                                           args.steps, args.tol, path == paths[0], args.inner_tol)
         results[path] = dict(seconds=el, stats=stats, spmv=spmv, fields=fields)
         log("%s: %.3f s for %d steps" % (path, el, args.steps))
 
-    main_path = "mixed" if "mixed" in results else paths[0]
+    main_path = paths[0]
     r = results[main_path]
     ms = r["seconds"] / args.steps * 1e3
     value = n_total * args.steps / r["seconds"]
@@ -216,14 +251,16 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic() if abs(h - 1.0 / 128) < 1e-12 else None,
-                "kernel": "k_bicg_v<float,float,1> (pressure SpMV, FP32 sliced ELL)",
+                "kernel": "k_bicg_v<%s,%s,1> (pressure SpMV, sliced ELL)" % ((
+                    "double", "double") if PATHS[main_path]["precision"] == "P_FP64" else ("float", "float")),
                 "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms, "launches": count,
                 "rows": n0, "nnz": nnz0}
 
     out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32+f64" if main_path == "mixed" else "f64", "data": "synthetic",
+           "dtype": "f64" if PATHS[main_path]["precision"] == "P_FP64" else "f32+f64+bf16"
+           if main_path == "learned" else "f32+f64", "data": "synthetic",
            "config": {"workload": "cylinder D=1 in [-10,20]x[-10,10] + equilateral lid cavity, "
                                   "h=D/%d, Re=%g, dt=%g, Poisson rel. residual %g" % (
                                       round(1 / h), re, dt, args.tol),
@@ -236,17 +273,28 @@ def main():
                                "poisson_iters": it,
                                "poisson_residual": max(s["poisson_residual"] for row in rr["stats"]
                                                        for s in row)}
-    if "mixed" in results and "fp64" in results:
-        out["speedup_mixed_vs_fp64"] = results["fp64"]["seconds"] / results["mixed"]["seconds"]
-        # difference of the two paths' fields after the same steps (both solve to 1e-8)
-        diffs = []
-        for a, b in zip(results["mixed"]["fields"], results["fp64"]["fields"]):
-            for k, (x, y) in enumerate(zip(a, b)):
-                if k == 2:
-                    x, y = x - x.mean(), y - y.mean()
-                diffs.append(float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)))
-        out["rel_l2_mixed_vs_fp64"] = {"u": max(diffs[0::3]), "v": max(diffs[1::3]),
-                                       "p": max(diffs[2::3])}
+    ref_path = "fp64" if "fp64" in results else None
+    if ref_path and main_path != ref_path:
+        out["speedup_vs_fp64"] = results[ref_path]["seconds"] / results[main_path]["seconds"]
+        # difference of the paths' fields after the same steps (all solve to 1e-8)
+        out["rel_l2_vs_fp64"] = {}
+        for path in results:
+            if path == ref_path:
+                continue
+            diffs = []
+            for a, b in zip(results[path]["fields"], results[ref_path]["fields"]):
+                for k, (x, y) in enumerate(zip(a, b)):
+                    if k == 2:
+                        x, y = x - x.mean(), y - y.mean()
+                    diffs.append(float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)))
+            out["rel_l2_vs_fp64"][path] = {"u": max(diffs[0::3]), "v": max(diffs[1::3]),
+                                           "p": max(diffs[2::3])}
+    if "learned" in results and "mixed" in results:
+        a = sum(sum(s["poisson_iters"] for s in row) for row in results["learned"]["stats"])
+        b = sum(sum(s["poisson_iters"] for s in row) for row in results["mixed"]["stats"])
+        out["learned_poisson_iters_vs_mixed"] = [a, b]
+    if train_info:
+        out["training"] = train_info
     out["roofline"] = roof
     if not args.no_cpu:
         log("CPU oracle baseline")

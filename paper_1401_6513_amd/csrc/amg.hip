@@ -340,12 +340,13 @@ __global__ void k_restrict(int64_t nc, const int64_t* mstart, const int32_t* mem
 
 // y = x + P xc   (coarse correction; x may be absent: zero pre-smoothing)
 template <typename T>
-__global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, const T* x, T* y, const int* on) {
+__global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, T gamma, const T* x, T* y,
+                          const int* on) {
   if (!*on) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
   const int32_t a = agg[i];
-  y[i] = (x ? x[i] : T(0)) + (a >= 0 ? xc[a] : T(0));
+  y[i] = (x ? x[i] : T(0)) + (a >= 0 ? gamma * xc[a] : T(0));
 }
 
 // out = y + W (b - A y)   (damped Jacobi sweep)
@@ -598,17 +599,28 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     k_dense_apply<T><<<(r * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(r, r, g.m1, inv, b, x, on);
     return VIP_OK;
   }
-  // level l: w(l,0) right-hand side (l > 0), w(l,1) pre-smoothed iterate,
-  // w(l,2) residual, then the corrected iterate; level 0 ends in x.
+  // Level l holds its right-hand side in w(l,0) (l > 0) and ping-pongs the iterate between
+  // w(l,1) and w(l,2); cur[l] is the pre-smoothed iterate (or null when level 0 skips the
+  // pre-smoothing), the other buffer takes the residual and later the corrected iterate.
+  const T gamma = static_cast<T>(c->amg_gamma);
+  std::vector<T*> cur(nl, nullptr);
   const T* rhs = b;
   for (int l = 0; l < nl - 1; ++l) {
     const AmgLevel& L = g.lv[l];
     const bool pre = l > 0 || pre_fine;
+    const int nu = l == 0 ? c->amg_nu : c->amg_nu_coarse;
     const T* res = rhs;
     if (pre) {
-      k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, w(l, 1), on);
-      k_level_residual<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, w(l, 1), w(l, 2), on);
-      res = w(l, 2);
+      T* a1 = w(l, 1);
+      T* a2 = w(l, 2);
+      k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, a1, on);
+      for (int k = 1; k < nu; ++k) {
+        k_jacobi<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, a1, a2, on);
+        std::swap(a1, a2);
+      }
+      k_level_residual<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, a1, a2, on);
+      cur[l] = a1;
+      res = a2;
     }
     k_restrict<T><<<grid_for(g.lv[l + 1].n), kBlock, 0, st>>>(g.lv[l + 1].n, L.mstart, L.members, res,
                                                                w(l + 1, 0), on);
@@ -620,13 +632,19 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
   const T* xc = coarse_out;
   for (int l = nl - 2; l >= 0; --l) {
     const AmgLevel& L = g.lv[l];
-    const bool pre = l > 0 || pre_fine;
+    const int nu = l == 0 ? c->amg_nu : c->amg_nu_coarse;
     const T* bl = (l == 0) ? b : w(l, 0);
-    T* out = (l == 0) ? x : w(l, 1);
-    // corrected iterate y into w(l,2) (the residual is no longer needed), then one sweep
-    k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, pre ? w(l, 1) : nullptr, w(l, 2), on);
-    k_jacobi<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), bl, w(l, 2), out, on);
-    xc = out;
+    // y = pre-smoothed iterate + gamma P xc into the buffer that is not cur[l]
+    T* y = (cur[l] == w(l, 2)) ? w(l, 1) : w(l, 2);
+    T* other = (y == w(l, 1)) ? w(l, 2) : w(l, 1);
+    k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, gamma, cur[l], y, on);
+    for (int k = 0; k < nu; ++k) {
+      T* out = (l == 0 && k == nu - 1) ? x : other;
+      k_jacobi<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), bl, y, out, on);
+      other = y;
+      y = out;
+    }
+    xc = y;
   }
   if (border) VIP_HIP_TRY(c, hipMemcpyAsync(x + c->n, b + c->n, sizeof(T), hipMemcpyDeviceToDevice, st));
   return VIP_OK;

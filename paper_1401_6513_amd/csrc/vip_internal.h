@@ -122,6 +122,12 @@ struct Ctx {
   int device = 0;
   int debug = 0;                  // VIP_DEBUG=1: trace Krylov batches on stderr
   int amg_pre_fine = 1;           // VIP_AMG_PRE_FINE=0: BiCGStab V-cycles skip the finest pre-sweep
+  // V-cycle settings: over-correction of the piecewise-constant coarse correction (plain
+  // aggregation makes the Galerkin coarse operators too stiff by about 2 for 2x2 aggregates)
+  // and damped Jacobi sweeps per level; measured best on the cylinder and triangle node sets
+  double amg_gamma = 1.7;         // coarse-correction scaling (VIP_AMG_GAMMA)
+  int amg_nu = 2;                 // Jacobi sweeps before and after on the finest level (VIP_AMG_NU)
+  int amg_nu_coarse = 2;          // the same on coarser levels (VIP_AMG_NU_COARSE)
   hipStream_t stream = nullptr;
   Error err{0, ""};
   vip_options opt{};

@@ -273,3 +273,40 @@ def test_extrapolated_start_vector():
         b = b - b.mean() + a.mean()
         assert _rel(b, a) < 1e-6
     ctx2.close()
+
+
+def test_learned_start_gain():
+    """What the trained network gains: Poisson iterations of the same steps started from phi_n
+    (the method without the learned start) and from the learned start vector, on a held-out
+    Reynolds number and node set.  The learned start keeps the converged result and must take
+    at least 10% fewer iterations; the extrapolation alone is reported beside it."""
+    import torch
+    from paper_1401_6513_amd import nodesets, training, vip
+    _ctx()
+    runs = training.training_runs(h_cyl=1.0 / 12, n_cavity=65, runs=2, seed=5)
+    theta, nsnap, loss = training.trained_parameters(runs=runs, iters=400, seed=5)
+    assert nsnap == 80 and np.isfinite(loss)
+    spec = nodesets.cylinder_channel(1.0 / 20, box=(-4.0, 8.0, -4.0, 4.0))
+    dt, Re = spec.h / 10, 150.0
+    ctx0 = vip.Context(0)
+    ctx0.build_from_spec(spec, precision=vip.P_MIXED, warmstart=vip.WS_PREV)
+    u0, v0, p0 = nodesets.boundary_initial(spec, (1.0, 0.0))
+    state = [torch.tensor(a, device="cuda") for a in (u0, v0, p0)]
+    for _ in range(30):
+        ctx0.vip_step(*state, dt, Re)
+    totals, fields = {}, {}
+    for mode in (vip.WS_PREV, vip.WS_EXTRAP, vip.WS_LEARNED):
+        c = vip.Context(0)
+        c.build_from_spec(spec, precision=vip.P_MIXED, warmstart=mode)
+        if mode == vip.WS_LEARNED:
+            c.vip_learn_set_params(theta)
+        st = [a.clone() for a in state]
+        its = [c.vip_step(*st, dt, Re)["poisson_iters"] for _ in range(20)]
+        totals[mode] = sum(its[2:])
+        fields[mode] = st[0].cpu().numpy()
+        c.close()
+    print("poisson iterations, steps 3-20: prev %d, extrap %d, learned %d" % (
+        totals[vip.WS_PREV], totals[vip.WS_EXTRAP], totals[vip.WS_LEARNED]))
+    assert totals[vip.WS_LEARNED] <= 0.9 * totals[vip.WS_PREV]
+    assert _rel(fields[vip.WS_LEARNED], fields[vip.WS_PREV]) < 1e-6
+    ctx0.close()

@@ -1,0 +1,147 @@
+"""Parity at the benchmark's full size: the cylinder channel [-10,20]x[-10,10] at h = 1/128
+(9,824,092 nodes), built with the options the benchmark runs.
+
+The oracle cannot build the whole node set, but every MLS-derived row is local: a row of a
+sampled node depends only on the nodes within its (grown) support and, through the near-wall
+VIP rule and the Neumann rows, on boundary nodes within a few supports.  Each sampled node's
+rows are therefore computed by the oracle on a window of radius 4 rho around it and compared
+with the library's operators applied to a seeded random vector, y_i = sum_j A_ij x_j (bar:
+1e-12 of sum_j |A_ij x_j|).  Samples:
+random interior nodes, body-surface nodes, nodes next to the body, and inlet, outlet and
+slip-wall nodes.  The solves are checked by a property that holds at any size: the FP64
+relative residual of the returned pressure increment, recomputed from the operator, is within
+the requested tolerance, for the FP64 and the mixed-precision paths.
+"""
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+from oracle import operators, step
+from paper_1401_6513_amd import nodesets as ns
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+H = 1.0 / 128
+DT, RE = H / 10.0, 200.0
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_1401_6513_amd import vip
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    spec = ns.cylinder_channel(H)
+    print("full-size node set: %d nodes, %d boundary nodes" % (spec.n, len(spec.bnd_idx)), flush=True)
+    ctx = vip.Context(0)
+    ctx.build_from_spec(spec, precision=vip.P_MIXED)
+    ctx.vip_assemble(DT, RE)
+    tree = cKDTree(spec.xy)
+    yield spec, ctx, tree
+    ctx.close()
+
+
+def _samples(spec, tree):
+    rng = np.random.default_rng(2024)
+    n = spec.n
+    bidx = spec.bnd_idx
+    kind = spec.bnd_kind
+    is_b = np.zeros(n, bool)
+    is_b[bidx] = True
+    surface = bidx[np.hypot(spec.xy[bidx, 0], spec.xy[bidx, 1]) < 1.0]
+    near = tree.query_ball_point([0.0, 0.0], 0.5 + 3 * H)
+    near = np.array([i for i in near if not is_b[i]])
+    inlet = bidx[(kind == ns.DIRICHLET) & (spec.xy[bidx, 0] < -9.99)]
+    outlet = bidx[kind == ns.OUTLET]
+    slip = bidx[kind == ns.SLIP]
+    interior = np.flatnonzero(~is_b)
+    pick = lambda a, k: rng.choice(a, size=min(k, len(a)), replace=False)
+    s = np.concatenate([pick(interior, 40), pick(surface, 12), pick(near, 12), pick(inlet, 4),
+                        pick(outlet, 4), pick(slip, 4)])
+    return np.unique(s)
+
+
+def _window(spec, tree, i):
+    """Oracle operators on the nodes within 4 rho of node i (boundary table restricted)."""
+    idx = np.array(sorted(tree.query_ball_point(spec.xy[i], 4.0 * spec.rho)))
+    pos = -np.ones(spec.n, np.int64)
+    pos[idx] = np.arange(len(idx))
+    inb = pos[spec.bnd_idx] >= 0
+    kw = dict(xy=spec.xy[idx], bnd_idx=pos[spec.bnd_idx[inb]], bnd_normal=spec.bnd_normal[inb],
+              bnd_kind=spec.bnd_kind[inb], bnd_value=spec.bnd_value[inb], rho=spec.rho, h=spec.h,
+              period=spec.period)
+    prob = operators.Problem(**kw)
+    ops = operators.Operators(prob)
+    st = step.Stepper(ops, DT, RE, solver="krylov")
+    return idx, pos[i], ops, st
+
+
+def test_sampled_operator_rows_at_full_size(full):
+    spec, ctx, tree = full
+    x = ns.random_field(spec.n, seed=77)
+    xd = torch.tensor(x, device="cuda")
+    y = torch.empty_like(xd)
+    names = ["identity", "laplacian", "vip_e", "vip_w", "vip_n", "vip_s", "poisson", "helm_u",
+             "helm_v"]
+    got = {}
+    for op in names:
+        ctx.vip_apply(op, xd, y)
+        got[op] = y.cpu().numpy().copy()
+    samples = _samples(spec, tree)
+    worst = {op: 0.0 for op in names}
+    for i in samples:
+        idx, li, ops, st = _window(spec, tree, i)
+        mats = {"identity": ops.M00, "laplacian": ops.L, "vip_e": ops.VIP[0], "vip_w": ops.VIP[1],
+                "vip_n": ops.VIP[2], "vip_s": ops.VIP[3], "poisson": st.P, "helm_u": st.Hu,
+                "helm_v": st.Hv}
+        xw = x[idx]
+        for op, M in mats.items():
+            row = M.getrow(li)
+            ref = float(row @ xw)
+            scale = float(abs(row) @ np.abs(xw)) + 1e-300
+            err = abs(got[op][i] - ref) / scale
+            worst[op] = max(worst[op], err)
+            assert err <= 1e-12, (int(i), op, err)
+    print("sampled %d rows; worst relative errors %s" % (len(samples),
+          {k: "%.1e" % v for k, v in worst.items()}))
+
+
+def test_sampled_vip_differences_at_full_size(full):
+    spec, ctx, tree = full
+    u = ns.random_field(spec.n, seed=5)
+    v = ns.random_field(spec.n, seed=6)
+    ud, vd = torch.tensor(u, device="cuda"), torch.tensor(v, device="cuda")
+    a, b = torch.empty_like(ud), torch.empty_like(ud)
+    ctx.vip_convection(ud, vd, a, b)
+    nx, ny = a.cpu().numpy(), b.cpu().numpy()
+    ctx.vip_divergence(ud, vd, a)
+    dv = a.cpu().numpy()
+    for i in _samples(spec, tree)[::2]:
+        idx, li, ops, _ = _window(spec, tree, i)
+        cx, cy = ops.convection(u[idx], v[idx])
+        d = ops.divergence(u[idx], v[idx])
+        scale = 1.0 / H
+        assert abs(nx[i] - cx[li]) <= 1e-12 * scale * 4, int(i)
+        assert abs(ny[i] - cy[li]) <= 1e-12 * scale * 4, int(i)
+        assert abs(dv[i] - d[li]) <= 1e-12 * scale * 4, int(i)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_poisson_residual(full, precision):
+    """The returned increment satisfies ||b - L phi|| / ||b|| <= tol, recomputed from the
+    FP64 operator outside the solver."""
+    from paper_1401_6513_amd import vip
+    spec, ctx, _ = full
+    ctx.vip_set_options(vip.default_options(precision=vip.P_FP64 if precision == "fp64" else vip.P_MIXED))
+    rng = np.random.default_rng(9)
+    b = torch.tensor(rng.standard_normal(spec.n), device="cuda")
+    phi = torch.zeros_like(b)
+    st = ctx.vip_poisson_solve(b, phi, 1e-8)
+    lp = torch.empty_like(b)
+    ctx.vip_apply("poisson", phi, lp)
+    rel = float((b - lp).norm() / b.norm())
+    print("%s: iterations %d, outer %d, reported %.2e, recomputed %.2e" % (
+        precision, st["poisson_iters"], st["poisson_outer"], st["poisson_residual"], rel))
+    assert rel <= 1e-8 * 1.01
+    assert abs(rel - st["poisson_residual"]) <= 1e-10

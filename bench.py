@@ -86,7 +86,10 @@ PATHS = {
 }
 
 
-def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol):
+def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol, pool=None):
+    """Run `steps` timed steps of every domain (domains in parallel host threads, one HIP stream
+    each, when a pool is given); returns wall seconds, stats, SpMV timing, fields and the
+    summed seconds of each domain's own steps."""
     import torch
     dev = torch.device("cuda", 0)
     cfg = PATHS[path]
@@ -105,11 +108,21 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
     if time_spmv:
         ctxs[0].vip_kernel_timing(enable=True, reset=True)
     stats = []
+    dom_s = [0.0] * len(ctxs)
+
+    def one(j):
+        u, v, p = state[j]
+        t = time.perf_counter()
+        st = ctxs[j].vip_step(u, v, p, dt, re)
+        dom_s[j] += time.perf_counter() - t
+        return st
+
     t0 = time.perf_counter()
     for k in range(steps):
-        row = []
-        for ctx, (u, v, p) in zip(ctxs, state):
-            row.append(ctx.vip_step(u, v, p, dt, re))
+        if pool is not None:
+            row = list(pool.map(one, range(len(ctxs))))
+        else:
+            row = [one(j) for j in range(len(ctxs))]
         stats.append(row)
         log("%s step %d: poisson iters %s, residual %s, start %s ratio %s" % (
             path, k + 1, [s["poisson_iters"] for s in row],
@@ -121,7 +134,7 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
     if time_spmv:
         spmv = ctxs[0].vip_kernel_timing(enable=False)
     fields = [[t.cpu().numpy() for t in st] for st in state]
-    return (t1 - t0), stats, spmv, fields
+    return (t1 - t0), stats, spmv, fields, dom_s
 
 
 def cpu_baseline(h, dt, re, budget_s):
@@ -173,6 +186,9 @@ def main():
     ap.add_argument("--paths", default="learned,mixed,fp64")
     ap.add_argument("--train-iters", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serial", action="store_true",
+                    help="step the domains one after the other on one stream (default: each domain "
+                         "on its own HIP stream, stepped from its own host thread)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before the timed region, copy a 1 GiB buffer once (reference dispatch "
@@ -195,9 +211,14 @@ def main():
     n_total = sum(s.n for s in specs)
     log("nodes: %s (total %d)" % ([s.n for s in specs], n_total))
     ctxs = []
+    streams = []
     t0 = time.perf_counter()
     for s in specs:
-        c = vip.Context(0)
+        if args.serial:
+            c = vip.Context(0)
+        else:
+            streams.append(torch.cuda.Stream(device=0))
+            c = vip.Context(0, stream=streams[-1].cuda_stream)
         c.build_from_spec(s)
         ctxs.append(c)
     torch.cuda.synchronize()
@@ -231,10 +252,15 @@ def main():
         for c in ctxs:
             c.vip_learn_set_params(theta)
     results = {}
+    pool = None
+    if not args.serial:
+        from concurrent.futures import ThreadPoolExecutor
+        pool = ThreadPoolExecutor(max_workers=len(ctxs))
     for path in paths:
-        el, stats, spmv, fields = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
-                                           args.steps, args.tol, path == paths[0], args.inner_tol)
-        results[path] = dict(seconds=el, stats=stats, spmv=spmv, fields=fields)
+        el, stats, spmv, fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
+                                                  args.steps, args.tol, path == paths[0],
+                                                  args.inner_tol, pool)
+        results[path] = dict(seconds=el, stats=stats, spmv=spmv, fields=fields, dom_s=dom_s)
         log("%s: %.3f s for %d steps" % (path, el, args.steps))
 
     main_path = paths[0]
@@ -266,11 +292,13 @@ def main():
                                   "h=D/%d, Re=%g, dt=%g, Poisson rel. residual %g" % (
                                       round(1 / h), re, dt, args.tol),
                       "nodes": n_total, "nodes_per_domain": [s.n for s in specs],
-                      "path": main_path, "build_s": build_s}}
+                      "path": main_path, "build_s": build_s,
+                      "domains_concurrent": not args.serial}}
     for path, rr in results.items():
         it = [[s["poisson_iters"] for s in row] for row in rr["stats"]]
         out["path_" + path] = {"value": n_total * args.steps / rr["seconds"],
                                "ms_per_step": rr["seconds"] / args.steps * 1e3,
+                               "ms_per_step_by_domain": [d / args.steps * 1e3 for d in rr["dom_s"]],
                                "poisson_iters": it,
                                "poisson_residual": max(s["poisson_residual"] for row in rr["stats"]
                                                        for s in row)}
@@ -302,6 +330,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(h, dt, re, args.cpu_budget)
     else:
         out["cpu_baseline"] = None
+    if pool is not None:
+        pool.shutdown()
     for c in ctxs:
         c.close()
     print(json.dumps(out))

@@ -296,6 +296,14 @@ int vip_divergence(void* ctx, const double* u, const double* v, double* div);
  * (zero on boundary rows). */
 int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
 
+/* Rows of the system layout that are translation-invariant lattice-interior copies of one
+ * reference row (same lattice offsets, bitwise equal values), per value set: counts[0] FP64
+ * pressure matrix, [1] predictor matrix of u, [2] of v, [3] unused, [4] FP32 pressure matrix
+ * with its row sums; *taps = entries of the reference row.  Products over these rows skip the
+ * column and value streams and give the same bits.  counts are 0 when VIP_NO_CANON=1 was set
+ * at vip_create, or for node sets that are not lattice based.  Host outputs, may be NULL. */
+int vip_canonical_rows(void* ctx, int64_t* counts, int* taps);
+
 /* Average duration (ms) of the pressure-solve SpMV kernel (the first SpMV of
  * each Krylov iteration) over the launches since the last reset, measured with
  * HIP events on the context stream while timing is enabled; *count receives the

@@ -277,7 +277,74 @@ struct LevelView {
   const T* val;
   const T* wdinv;
   const float* rsum;   // FP32 levels: row sums for the difference form
+  // lattice-interior rows of level 0 (stencil.hip): pixel of a canonical row, else -1
+  const int32_t* cpix;
+  const int32_t* node_of;
+  int K;
+  int disk;
+  int32_t W;
+  int32_t off[kMaxTaps];
+  T w[kMaxTaps];
+  T wdinv_c;
+  float crsum;
 };
+
+// Canonical row of a level: weights of the reference row, columns from the lattice map,
+// slots to the accumulators in the general path's order (same bits).
+template <typename T, class Y>
+__device__ __forceinline__ T canon_row(const LevelView<T>& L, int32_t p, int64_t i, int w, Y y) {
+  const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
+  T a0 = T(0), a1 = T(0);
+  if (L.disk) {
+    int32_t b[5];
+    disk_bases(L.node_of, p, L.W, i, b);
+#pragma unroll
+    for (int k = 0; k < kDiskTaps; ++k) {
+      const T d = L.w[k] * (y(b[disk_row(k)] + disk_dx(k)) - yi);
+      if (k & 1) a1 += d;
+      else a0 += d;
+    }
+    if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
+    else return a0 + a1;
+  }
+  const int full = w & ~3;
+  const int32_t* nb = L.node_of + p;
+  int k = 0;
+  for (; k + 4 <= L.K && k + 4 <= full; k += 4) {
+    const T y0 = y(nb[L.off[k]]), y1 = y(nb[L.off[k + 1]]), y2 = y(nb[L.off[k + 2]]), y3 = y(nb[L.off[k + 3]]);
+    a0 += L.w[k] * (y0 - yi);
+    a1 += L.w[k + 1] * (y1 - yi);
+    a0 += L.w[k + 2] * (y2 - yi);
+    a1 += L.w[k + 3] * (y3 - yi);
+  }
+  for (; k < L.K; ++k) {
+    const T d = L.w[k] * (y(nb[L.off[k]]) - yi);
+    if (k < full && (k & 1)) a1 += d;
+    else a0 += d;
+  }
+  if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
+  else return a0 + a1;
+}
+
+template <typename T>
+__device__ __forceinline__ T level_wdinv(const LevelView<T>& L, int64_t i) {
+  return (L.cpix && L.cpix[i] >= 0) ? L.wdinv_c : L.wdinv[i];
+}
+
+// cpix_out[i] = cpix_in[i] where the damped inverse diagonal also equals the reference bits
+template <typename T>
+__global__ void k_canon_wd(int64_t n, const int32_t* cin, const T* wd, T ref, int32_t* cout) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  int32_t p = cin[i];
+  if (p >= 0) {
+    bool same;
+    if constexpr (sizeof(T) == 4) same = __float_as_uint(wd[i]) == __float_as_uint(ref);
+    else same = __double_as_longlong(wd[i]) == __double_as_longlong(ref);
+    if (!same) p = -1;
+  }
+  cout[i] = p;
+}
 
 // (A y)_i with y_j given by a functor; FP32 levels use the difference form
 // rsum_i y_i + sum a_ij (y_j - y_i) (rows sum to ~0, see row_dot in the solver).
@@ -286,6 +353,10 @@ __device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
   const int64_t sl = i / kSlice;
   const int64_t base = L.ptr[sl] + (i % kSlice);
   const int w = static_cast<int>((L.ptr[sl + 1] - L.ptr[sl]) / kSlice);
+  if (L.cpix) {
+    const int32_t p = L.cpix[i];
+    if (p >= 0) return canon_row(L, p, i, w, y);
+  }
   const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
   T a0 = T(0), a1 = T(0);
   int k = 0;
@@ -357,7 +428,7 @@ __global__ void k_jacobi(LevelView<T> L, const T* b, const T* y, T* out, const i
   const int64_t i = lb * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
   const T ay = level_row(L, i, [&](int32_t j) { return y[j]; });
-  out[i] = y[i] + L.wdinv[i] * (b[i] - ay);
+  out[i] = y[i] + level_wdinv(L, i) * (b[i] - ay);
 }
 
 // x[0..rows) = Inv[0..rows, 0..cols) b on the coarsest level (one wavefront per row);
@@ -392,6 +463,8 @@ void amg_free(Ctx* c) {
     dfree(L.ky);
     dfree(L.mstart);
     dfree(L.members);
+    dfree(L.cpix64);
+    dfree(L.cpix32);
     for (int k = 0; k < 3; ++k) {
       dfree(L.w64[k]);
       dfree(L.w32[k]);
@@ -432,6 +505,24 @@ int amg_setup(Ctx* c) {
     k_keep<<<grid_for(L.n), kBlock, 0, st>>>(L.n, A.ptr, A.cols, A.rowlen, aval, L.keep);
     k_wdinv<<<grid_for(L.n), kBlock, 0, st>>>(L.n, A.ptr, A.cols, A.rowlen, aval, L.keep, kOmega,
                                                L.wdinv, L.wdinv32);
+    if (level == 0 && !c->no_canon && A.canon.K > 0 && A.canon.ref_row >= 0) {
+      // canonical rows of the sweeps: canonical matrix row and the reference damped diagonal
+      const Canon& cn = A.canon;
+      L.node_of = c->lat.node_of;
+      L.W = c->lat.W;
+      VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv_c, L.wdinv + cn.ref_row, sizeof(double), hipMemcpyDeviceToHost, st));
+      VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv32_c, L.wdinv32 + cn.ref_row, sizeof(float), hipMemcpyDeviceToHost, st));
+      VIP_HIP_TRY(c, hipStreamSynchronize(st));
+      if (cn.count[0] > 0 && cn.cpix[0]) {
+        VIP_TRY(dalloc(c, &L.cpix64, L.n));
+        k_canon_wd<double><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[0], L.wdinv, L.wdinv_c, L.cpix64);
+      }
+      if (cn.count[4] > 0 && cn.cpix[4]) {
+        VIP_TRY(dalloc(c, &L.cpix32, L.n));
+        k_canon_wd<float><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[4], L.wdinv32, L.wdinv32_c, L.cpix32);
+      }
+      VIP_HIP_TRY(c, hipGetLastError());
+    }
     for (int k = 0; k < 3; ++k) {
       VIP_TRY(dalloc(c, &L.w64[k], L.n + 1));
       VIP_TRY(dalloc(c, &L.w32[k], L.n + 1));
@@ -567,13 +658,26 @@ static LevelView<T> view(const AmgLevel& L) {
   v.ptr = L.A.ptr;
   v.cols = L.A.cols;
   v.rsum = L.A.rsum32;
+  v.cpix = nullptr;
+  v.node_of = L.node_of;
+  v.K = L.A.canon.K;
+  v.disk = L.A.canon.disk;
+  v.W = L.W;
+  v.crsum = L.A.canon.rsum32;
   if constexpr (sizeof(T) == 4) {
     v.val = L.A.val32;
     v.wdinv = L.wdinv32;
+    v.cpix = L.cpix32;
+    v.wdinv_c = L.wdinv32_c;
+    for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w32[k];
   } else {
     v.val = L.A.val[L.vs];
     v.wdinv = L.wdinv;
+    v.cpix = L.cpix64;
+    v.wdinv_c = L.wdinv_c;
+    for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w[L.vs][k];
   }
+  for (int k = 0; k < v.K; ++k) v.off[k] = L.A.canon.off[k];
   return v;
 }
 

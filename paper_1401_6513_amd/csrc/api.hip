@@ -21,6 +21,7 @@ int set_error(Ctx* c, int code, const std::string& msg) {
 }
 
 void ell_free(Ell& e) {
+  canon_free(e.canon);
   dfree(e.ptr);
   dfree(e.width);
   dfree(e.rowlen);
@@ -64,6 +65,7 @@ void ctx_free_build(Ctx* c) {
   c->have_prev_n = false;
   c->have_prev_phi = false;
   learn_free_nodeset(c);
+  lattice_free(c->lat);
 }
 
 namespace {
@@ -137,6 +139,8 @@ int vip_create(void** out, int device, void* stream) {
   c->stream = static_cast<hipStream_t>(stream);
   const char* dbg = std::getenv("VIP_DEBUG");
   c->debug = (dbg && dbg[0] == '1') ? 1 : 0;
+  const char* nc = std::getenv("VIP_NO_CANON");
+  c->no_canon = (nc && nc[0] == '1') ? 1 : 0;
   const char* pre = std::getenv("VIP_AMG_PRE_FINE");
   c->amg_pre_fine = (pre && pre[0] == '0') ? 0 : 1;
   if (const char* g = std::getenv("VIP_AMG_GAMMA")) c->amg_gamma = std::min(2.0, std::max(0.5, std::atof(g)));
@@ -411,6 +415,16 @@ int vip_kernel_timing(void* p, int enable, int reset, double* avg_ms, int64_t* c
   c->timing.enabled = enable != 0;
   if (avg_ms) *avg_ms = c->timing.count > 0 ? c->timing.total_ms / c->timing.count : 0.0;
   if (count) *count = c->timing.count;
+  return VIP_OK;
+}
+
+int vip_canonical_rows(void* p, int64_t* counts, int* taps) {
+  Ctx* c = vip::as_ctx(p);
+  VIP_TRY(vip::need_built(c));
+  const vip::Canon& cn = c->sys.canon;
+  if (counts)
+    for (int k = 0; k < 5; ++k) counts[k] = c->no_canon ? 0 : cn.count[k];
+  if (taps) *taps = cn.K;
   return VIP_OK;
 }
 

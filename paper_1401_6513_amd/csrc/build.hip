@@ -995,6 +995,9 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   c->cur_re = 0.0;
   VIP_HIP_TRY(c, hipStreamSynchronize(st));
   VIP_HIP_TRY(c, hipGetLastError());
+  // lattice-interior rows of the pressure matrix (FP64 and FP32 value sets)
+  VIP_TRY(canon_mark(c, s, 0));
+  VIP_TRY(canon_mark(c, s, 4));
   c->built = true;
   return VIP_OK;
 }
@@ -1010,6 +1013,8 @@ int assemble_helmholtz(Ctx* c, double dt, double re) {
   k_diag_inv<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, c->sys.ptr, c->sys.cols, c->sys.rowlen,
                                                         c->sys.val[2], c->dinv[2]);
   VIP_HIP_TRY(c, hipGetLastError());
+  VIP_TRY(canon_mark(c, c->sys, 1));
+  VIP_TRY(canon_mark(c, c->sys, 2));
   c->cur_dt = dt;
   c->cur_re = re;
   c->assembled = true;

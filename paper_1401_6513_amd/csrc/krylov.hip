@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "vip_internal.h"
@@ -29,10 +30,21 @@ namespace vip {
 namespace {
 
 constexpr int kWaves = kBlock / 64;
-constexpr int64_t kMaxGrid = 2048;   // blocks of a reducing kernel (grid-stride over row chunks)
+// Blocks of a reducing kernel (each takes a contiguous chunk of rows): VIP_MAX_GRID, default 8192
+// (measured: enough blocks in flight to hide the gathers, few enough partials for one-block
+// finish kernels).
+inline int64_t max_grid() {
+  static const int64_t g = [] {
+    const char* e = std::getenv("VIP_MAX_GRID");
+    int64_t v = e ? std::atoll(e) : 8192;
+    v = std::min<int64_t>(std::max<int64_t>(v, 64), int64_t{1} << 20);
+    return (v + kNumXcd - 1) / kNumXcd * kNumXcd;
+  }();
+  return g;
+}
 
 // Grid of a reducing kernel over m items: bounded, a multiple of the XCD count.
-inline int64_t red_grid(int64_t m) { return std::min<int64_t>(grid_for(m), kMaxGrid); }
+inline int64_t red_grid(int64_t m) { return std::min<int64_t>(grid_for(m), max_grid()); }
 
 // Contiguous chunk of items [begin, end) handled by this block; consecutive
 // logical blocks (same XCD) get consecutive chunks.
@@ -112,7 +124,38 @@ struct Mat {
   const int32_t* cols;
   const VT* val[2];        // value sets of system 0 and 1
   const float* rsum;       // FP32 values only: row sums for the difference form
+  // lattice-interior rows (stencil.hip): pixel of a canonical row, else -1; null = none
+  const int32_t* cpix[2];
+  const int32_t* node_of;
+  int K;
+  int disk;                // taps are the 21-point disk (unrolled path)
+  int32_t W;               // lattice image width
+  int32_t off[kMaxTaps];
+  VT w[2][kMaxTaps];
+  float crsum[2];
 };
+
+// Attach the canonical rows of value sets vs0 (system 0) and vs1 (system 1, -1 = none);
+// vs 4 is the FP32 pressure set.
+template <typename VT>
+void attach_canon(const Ctx* c, Mat<VT>& A, int vs0, int vs1) {
+  const Canon& cn = c->sys.canon;
+  A.cpix[0] = A.cpix[1] = nullptr;
+  if (c->no_canon || cn.K == 0) return;
+  const int vs[2] = {vs0, vs1};
+  for (int s = 0; s < 2; ++s) {
+    if (vs[s] < 0 || cn.count[vs[s]] == 0 || !cn.cpix[vs[s]]) continue;
+    A.cpix[s] = cn.cpix[vs[s]];
+    for (int k = 0; k < cn.K; ++k)
+      A.w[s][k] = (vs[s] == 4) ? static_cast<VT>(cn.w32[k]) : static_cast<VT>(cn.w[vs[s]][k]);
+    A.crsum[s] = cn.rsum32;
+  }
+  A.node_of = c->lat.node_of;
+  A.K = cn.K;
+  A.disk = cn.disk;
+  A.W = c->lat.W;
+  for (int k = 0; k < cn.K; ++k) A.off[k] = cn.off[k];
+}
 
 template <typename T>
 struct Vec {
@@ -129,6 +172,80 @@ struct Vec {
   const T* dinv[2];
 };
 
+// Canonical row: the weights come from the reference row and the columns from the lattice
+// map.  Slots go to the two accumulators in the general path's order (pairs of the unrolled
+// groups alternate, the tail goes to the first), so the bits are the same.
+template <typename VT, typename T>
+__device__ __forceinline__ double canon_dot(const Mat<VT>& A, int sys, int32_t p, int64_t i, int w,
+                                            const T* x) {
+  if (A.disk) {
+    // 21 taps: slots 0, 2, ..., 20 to the first accumulator, the odd ones to the second (a
+    // slice of such rows is at least 21 wide, so only slot 20 can fall in the tail)
+    int32_t b[5];
+    disk_bases(A.node_of, p, A.W, i, b);
+    if constexpr (sizeof(VT) == 4) {
+      const float xi = static_cast<float>(x[i]);
+      float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kDiskTaps; ++k) {
+        const float d = A.w[sys][k] * (static_cast<float>(x[b[disk_row(k)] + disk_dx(k)]) - xi);
+        if (k & 1) a1 += d;
+        else a0 += d;
+      }
+      return static_cast<double>(a0 + a1) + static_cast<double>(A.crsum[sys] * xi);
+    } else {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kDiskTaps; ++k) {
+        const double d = A.w[sys][k] * static_cast<double>(x[b[disk_row(k)] + disk_dx(k)]);
+        if (k & 1) a1 += d;
+        else a0 += d;
+      }
+      return a0 + a1;
+    }
+  }
+  const int full = w & ~3;
+  const int32_t* nb = A.node_of + p;
+  if constexpr (sizeof(VT) == 4) {
+    const float xi = static_cast<float>(x[i]);
+    float a0 = 0.0f, a1 = 0.0f;
+    int k = 0;
+    for (; k + 4 <= A.K && k + 4 <= full; k += 4) {
+      const int32_t c0 = nb[A.off[k]], c1 = nb[A.off[k + 1]], c2 = nb[A.off[k + 2]], c3 = nb[A.off[k + 3]];
+      const float x0 = static_cast<float>(x[c0]), x1 = static_cast<float>(x[c1]),
+                  x2 = static_cast<float>(x[c2]), x3 = static_cast<float>(x[c3]);
+      a0 += A.w[sys][k] * (x0 - xi);
+      a1 += A.w[sys][k + 1] * (x1 - xi);
+      a0 += A.w[sys][k + 2] * (x2 - xi);
+      a1 += A.w[sys][k + 3] * (x3 - xi);
+    }
+    for (; k < A.K; ++k) {
+      const float d = A.w[sys][k] * (static_cast<float>(x[nb[A.off[k]]]) - xi);
+      if (k < full && (k & 1)) a1 += d;
+      else a0 += d;
+    }
+    return static_cast<double>(a0 + a1) + static_cast<double>(A.crsum[sys] * xi);
+  } else {
+    double a0 = 0.0, a1 = 0.0;
+    int k = 0;
+    for (; k + 4 <= A.K && k + 4 <= full; k += 4) {
+      const int32_t c0 = nb[A.off[k]], c1 = nb[A.off[k + 1]], c2 = nb[A.off[k + 2]], c3 = nb[A.off[k + 3]];
+      const double x0 = static_cast<double>(x[c0]), x1 = static_cast<double>(x[c1]),
+                   x2 = static_cast<double>(x[c2]), x3 = static_cast<double>(x[c3]);
+      a0 += A.w[sys][k] * x0;
+      a1 += A.w[sys][k + 1] * x1;
+      a0 += A.w[sys][k + 2] * x2;
+      a1 += A.w[sys][k + 3] * x3;
+    }
+    for (; k < A.K; ++k) {
+      const double d = A.w[sys][k] * static_cast<double>(x[nb[A.off[k]]]);
+      if (k < full && (k & 1)) a1 += d;
+      else a0 += d;
+    }
+    return a0 + a1;
+  }
+}
+
 // Row i of y = A x for system `sys`; x is the system's vector.  The slot loop is
 // unrolled by four so the column loads of several slots are in flight before
 // their gathers.
@@ -137,6 +254,10 @@ __device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, 
   const int64_t sl = i / kSlice;
   const int64_t base = A.ptr[sl] + (i % kSlice);
   const int w = static_cast<int>((A.ptr[sl + 1] - A.ptr[sl]) / kSlice);
+  if (A.cpix[sys]) {
+    const int32_t p = A.cpix[sys][i];
+    if (p >= 0) return canon_dot(A, sys, p, i, w, x);
+  }
   const VT* vals = A.val[sys];
   if constexpr (sizeof(VT) == 4) {
     // difference form: rows of the pressure matrix sum to ~0, so on smooth x the
@@ -893,6 +1014,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
     k_fill<double><<<gv, kBlock, 0, s>>>(stride, x, 0.0);
   }
   Mat<double> A64{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}, nullptr};
+  attach_canon(c, A64, 0, -1);
   int total_it = 0, outer = 0;
   double relres = 0.0;
   const int maxit = c->opt.max_iters;
@@ -924,6 +1046,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   } else {
     const double inner = std::max(c->opt.inner_tol, 1e-7);
     Mat<float> A32{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val32, nullptr}, c->sys.rsum32};
+    attach_canon(c, A32, 4, -1);
     float* d32 = c->ws32 + 8 * stride;
     float* r32base = c->ws32;
     Vec<float> V = make_vec<float>(r32base, stride, 1, d32);
@@ -1002,6 +1125,7 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, x);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, x + stride);
   Mat<double> H{n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[1], c->sys.val[2]}, nullptr};
+  attach_canon(c, H, 1, 2);
   Vec<double> V = make_vec<double>(c->ws, stride, 2, x);
   V.dinv[0] = c->dinv[1];
   V.dinv[1] = c->dinv[2];

@@ -409,29 +409,6 @@ __global__ void k_pack(const float* th, bf16_t* w1, bf16_t* w2f, bf16_t* w2b, bf
 
 // ---- lattice raster ------------------------------------------------------------------------------------
 
-// pixel of each node if it sits on the lattice x = xmin + ix h, y = ymin + iy h (else -1);
-// the lowest node index on a pixel keeps it
-__global__ void k_pixel_claim(int64_t n, const double* x, const double* y, double x0, double y0, double h,
-                              int W, int H, int32_t* node_of) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  const double fx = (x[i] - x0) / h, fy = (y[i] - y0) / h;
-  const double rx = rint(fx), ry = rint(fy);
-  if (fabs(fx - rx) < 1e-6 && fabs(fy - ry) < 1e-6 && rx >= 0 && ry >= 0 && rx < W && ry < H)
-    atomicMin(&node_of[static_cast<int64_t>(ry) * W + static_cast<int64_t>(rx)], static_cast<int32_t>(i));
-}
-
-__global__ void k_pixel_finish(int64_t npix, int32_t* node_of, int32_t* pix) {
-  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (q >= npix) return;
-  const int32_t node = node_of[q];
-  if (node == INT32_MAX) {
-    node_of[q] = -1;
-  } else {
-    pix[node] = static_cast<int32_t>(q);
-  }
-}
-
 // training crop `sample` of the batch from one snapshot image; loss mask = lattice node
 // and at least `margin` pixels inside the crop
 __global__ void k_make_crop(const bf16_t* sx, const float* st, int W, int H, int oy, int ox, int crop,
@@ -512,12 +489,6 @@ __global__ void k_sub(int64_t n, const double* b, const double* a, double* r) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
   r[i] = b[i] - a[i];
-}
-
-__global__ void k_fill_i32(int64_t n, int32_t v, int32_t* a) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  a[i] = v;
 }
 
 __global__ void k_copy_d(int64_t n, const double* a, double* b) {
@@ -650,12 +621,8 @@ void learn_clear(Ctx* c) {
 
 void learn_free_nodeset(Ctx* c) {
   Learn& L = c->learn;
-  dfree(L.pix);
-  dfree(L.node_of);
   for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2, &L.scal}) dfree(*p);
   L.have_eprev = false;
-  L.mapped = false;
-  L.W = L.H = 0;
 }
 
 void learn_free(Ctx* c) {
@@ -837,7 +804,7 @@ constexpr int kScalHead = 16;
 // rms of a h^2 and c h^2 over lattice nodes into scal[0], scal[1]
 int lattice_rms(Ctx* c, const double* a, const double* cv) {
   Learn& L = c->learn;
-  k_rms_part<<<kSumBlocks, 256, 0, c->stream>>>(c->n, L.pix, a, cv, c->h * c->h, L.scal + kScalHead);
+  k_rms_part<<<kSumBlocks, 256, 0, c->stream>>>(c->n, c->lat.pix, a, cv, c->h * c->h, L.scal + kScalHead);
   k_rms_finish<<<1, 64, 0, c->stream>>>(kSumBlocks, L.scal + kScalHead, L.scal);
   VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;
@@ -958,29 +925,11 @@ int learn_eval(Ctx* c, const double* x, const double* t, const double* m, int B,
   return VIP_OK;
 }
 
-// lattice image of the node set (built once per node set)
-int learn_map(Ctx* c) {
-  Learn& L = c->learn;
-  if (L.mapped) return VIP_OK;
-  const double h = c->h;
-  const double wx = std::floor((c->xmax - c->xmin) / h + 0.5) + 1.0;
-  const double wy = std::floor((c->ymax - c->ymin) / h + 0.5) + 1.0;
-  if (!(wx * wy <= 4.0 * static_cast<double>(c->n) + 4096.0) || wx > 65536.0 || wy > 65536.0)
-    return set_error(c, VIP_E_INVALID, "node set is not lattice based (image much larger than the node count)");
-  L.W = static_cast<int>(wx);
-  L.H = static_cast<int>(wy);
-  const int64_t npix = static_cast<int64_t>(L.W) * L.H;
-  VIP_TRY(ensure_vectors(c));
-  VIP_TRY(dalloc(c, &L.pix, c->n));
-  VIP_TRY(dalloc(c, &L.node_of, npix));
-  VIP_HIP_TRY(c, hipMemsetAsync(L.pix, 0xff, sizeof(int32_t) * c->n, c->stream));
-  k_fill_i32<<<blocks_for(npix), kBlock, 0, c->stream>>>(npix, INT32_MAX, L.node_of);
-  k_pixel_claim<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, c->x, c->y, c->xmin, c->ymin, h, L.W, L.H,
-                                                            L.node_of);
-  k_pixel_finish<<<blocks_for(npix), kBlock, 0, c->stream>>>(npix, L.node_of, L.pix);
-  VIP_HIP_TRY(c, hipGetLastError());
-  VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
-  L.mapped = true;
+// lattice image of the node set; the learned start vector needs one
+static int learn_map(Ctx* c) {
+  bool ok = false;
+  VIP_TRY(lattice_map(c, &ok));
+  if (!ok) return set_error(c, VIP_E_INVALID, "node set is not lattice based (image much larger than the node count)");
   return VIP_OK;
 }
 
@@ -1006,12 +955,12 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
   VIP_TRY(extrapolation_residual(c));
   if (learned) {
     Net* N = net_of(c);
-    const int64_t npix = static_cast<int64_t>(L.W) * L.H;
+    const int64_t npix = static_cast<int64_t>(c->lat.W) * c->lat.H;
     VIP_TRY(net_buffers(c, npix));
     VIP_TRY(lattice_rms(c, L.rx, b));
-    k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, L.node_of, L.rx, b, L.scal, h2, N->x);
-    VIP_TRY(forward(c, Img{1, L.H, L.W}));
-    k_direction<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.pix, N->y, L.scal, h2, L.dir);
+    k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.rx, b, L.scal, h2, N->x);
+    VIP_TRY(forward(c, Img{1, c->lat.H, c->lat.W}));
+    k_direction<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, c->lat.pix, N->y, L.scal, h2, L.dir);
     VIP_TRY(ell_apply(c, c->sys, 0, L.dir, L.q2));
   }
   k_dots6_part<<<kSumBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, L.r, L.scal + kScalHead);
@@ -1050,10 +999,10 @@ int learn_finish(Ctx* c, const double* b, const double* phi, bool capture) {
   Learn& L = c->learn;
   hipStream_t st = c->stream;
   if (capture && L.have_eprev && static_cast<int>(L.snaps.size()) < L.capacity) {
-    const int64_t npix = static_cast<int64_t>(L.W) * L.H;
+    const int64_t npix = static_cast<int64_t>(c->lat.W) * c->lat.H;
     Snapshot s;
-    s.W = L.W;
-    s.H = L.H;
+    s.W = c->lat.W;
+    s.H = c->lat.H;
     VIP_TRY(dalloc(c, &s.x, 3 * npix));
     if (dalloc(c, &s.t, npix) != VIP_OK) {
       dfree(s.x);
@@ -1063,8 +1012,8 @@ int learn_finish(Ctx* c, const double* b, const double* phi, bool capture) {
     const double h2 = c->h * c->h;
     VIP_TRY(extrapolation_residual(c));
     VIP_TRY(lattice_rms(c, L.rx, b));
-    k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, L.node_of, L.rx, b, L.scal, h2, s.x);
-    k_make_target<<<blocks_for(npix), kBlock, 0, st>>>(npix, L.node_of, phi, L.phi_prev, L.eprev, L.scal, h2,
+    k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.rx, b, L.scal, h2, s.x);
+    k_make_target<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, phi, L.phi_prev, L.eprev, L.scal, h2,
                                                        s.t);
   }
   k_diff<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, phi, L.phi_prev, L.eprev);

@@ -1,0 +1,361 @@
+// Lattice map of the node set and the canonical rows of the system operators.
+//
+// A canonical row also needs the nodes of each lattice row of its stencil numbered
+// consecutively (true for row-by-row lattice orderings), so that a tap's node is the node
+// straight above or below plus its offset along the row.
+//
+// On a lattice-based node set every interior node far from the boundary sees the same
+// neighbourhood, so its MLS weights (Section 3) and every operator built from them (eq.
+// vip:1, eq. 12, eq. 13) repeat from row to row.  When the lattice coordinates are exact in
+// binary (h a power of two) the repeats are exact to the bit.  A row whose stored entries sit
+// at the reference row's lattice offsets and equal its values bit for bit is "canonical":
+// products over it need neither the column nor the value streams of the sliced ELL.  Rows
+// near the boundary, off-lattice nodes and rows of node sets whose coordinates do not repeat
+// exactly stay on the general path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "vip_internal.h"
+
+namespace vip {
+
+namespace {
+
+__global__ void k_fill_i32(int64_t n, int32_t v, int32_t* a) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// the lowest node index on a lattice position claims its pixel
+__global__ void k_pixel_claim(int64_t n, const double* x, const double* y, double x0, double y0, double h,
+                              int W, int H, int32_t* node_of) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const double fx = (x[i] - x0) / h, fy = (y[i] - y0) / h;
+  const double rx = rint(fx), ry = rint(fy);
+  if (fabs(fx - rx) < 1e-6 && fabs(fy - ry) < 1e-6 && rx >= 0 && ry >= 0 && rx < W && ry < H)
+    atomicMin(&node_of[static_cast<int64_t>(ry) * W + static_cast<int64_t>(rx)], static_cast<int32_t>(i));
+}
+
+__global__ void k_pixel_finish(int64_t npix, int32_t* node_of, int32_t* pix) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= npix) return;
+  const int32_t node = node_of[q];
+  if (node == INT32_MAX) {
+    node_of[q] = -1;
+  } else {
+    pix[node] = static_cast<int32_t>(q);
+  }
+}
+
+// Row data of sampled rows for choosing the reference row: length, boundary flag, pixel,
+// pixels of the stored columns and the bits of their values.
+__global__ void k_gather_rows(int m, const int64_t* rows, const int64_t* ptr, const int32_t* rowlen,
+                              const int32_t* cols, const int32_t* bpos, const int32_t* pix, const double* v64,
+                              const float* v32, const float* rsum32, int32_t* o_len, int32_t* o_bpos,
+                              int32_t* o_pix, int32_t* o_cpix, uint64_t* o_bits, uint32_t* o_rsum) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const int64_t i = rows[s];
+  const int len = rowlen[i];
+  o_len[s] = len;
+  o_bpos[s] = bpos[i];
+  o_pix[s] = pix[i];
+  o_rsum[s] = rsum32 ? __float_as_uint(rsum32[i]) : 0u;
+  const int64_t base = ptr[i / kSlice] + (i % kSlice);
+  for (int k = 0; k < len && k < kMaxTaps; ++k) {
+    const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+    o_cpix[s * kMaxTaps + k] = pix[cols[q]];
+    o_bits[s * kMaxTaps + k] = v64 ? static_cast<uint64_t>(__double_as_longlong(v64[q]))
+                                   : static_cast<uint64_t>(__float_as_uint(v32[q]));
+  }
+}
+
+struct MarkArgs {
+  int K, W, H;
+  int32_t dx[kMaxTaps], dy[kMaxTaps];
+  uint64_t bits[kMaxTaps];
+  uint32_t rsum_bits;
+};
+
+// cpix[i] = pixel of row i if it is canonical for the given value set, else -1
+__global__ void k_canon_mark(int64_t n, MarkArgs a, const int32_t* bpos, const int32_t* pix,
+                             const int32_t* node_of, const int64_t* ptr, const int32_t* rowlen,
+                             const int32_t* cols, const double* v64, const float* v32, const float* rsum32,
+                             int32_t* cpix) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  int32_t out = -1;
+  const int32_t p = pix[i];
+  if (bpos[i] < 0 && p >= 0 && rowlen[i] == a.K) {
+    const int ix = p % a.W, iy = p / a.W;
+    const int64_t base = ptr[i / kSlice] + (i % kSlice);
+    bool ok = true;
+    for (int k = 0; k < a.K; ++k) {
+      const int jx = ix + a.dx[k], jy = iy + a.dy[k];
+      if (jx < 0 || jx >= a.W || jy < 0 || jy >= a.H) {
+        ok = false;
+        break;
+      }
+      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+      // the tap's node, and the nodes of its lattice row numbered consecutively from the node
+      // straight above or below the row's node
+      const int32_t rowbase = node_of[static_cast<int64_t>(jy) * a.W + ix];
+      if (node_of[static_cast<int64_t>(jy) * a.W + jx] != cols[q] || rowbase < 0 || cols[q] != rowbase + a.dx[k])
+        ok = false;
+      const uint64_t bits = v64 ? static_cast<uint64_t>(__double_as_longlong(v64[q]))
+                                : static_cast<uint64_t>(__float_as_uint(v32[q]));
+      if (bits != a.bits[k]) ok = false;
+    }
+    if (ok && !v64 && __float_as_uint(rsum32[i]) != a.rsum_bits) ok = false;
+    if (ok) out = p;
+  }
+  cpix[i] = out;
+}
+
+// per-block counts of entries >= 0
+__global__ void k_count_nonneg(int64_t n, const int32_t* a, int64_t* part) {
+  __shared__ int64_t s[256];
+  int64_t c = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    c += a[i] >= 0 ? 1 : 0;
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+struct RowSample {
+  int len = 0, bpos = 0, pix = -1;
+  std::vector<int32_t> cpix;
+  std::vector<uint64_t> bits;
+  uint32_t rsum = 0;
+};
+
+// Sampled rows' data (value set vs) copied to the host.
+int gather(Ctx* c, const Ell& e, int vs, const std::vector<int64_t>& rows, std::vector<RowSample>* out) {
+  const int m = static_cast<int>(rows.size());
+  int64_t* d_rows = nullptr;
+  int32_t *d_len = nullptr, *d_bpos = nullptr, *d_pix = nullptr, *d_cpix = nullptr;
+  uint64_t* d_bits = nullptr;
+  uint32_t* d_rsum = nullptr;
+  int rc = VIP_OK;
+  std::vector<int32_t> len(m), bp(m), px(m), cp(static_cast<size_t>(m) * kMaxTaps, -1);
+  std::vector<uint64_t> bits(static_cast<size_t>(m) * kMaxTaps, 0);
+  std::vector<uint32_t> rs(m);
+  do {
+    if ((rc = dalloc(c, &d_rows, m)) || (rc = dalloc(c, &d_len, m)) || (rc = dalloc(c, &d_bpos, m)) ||
+        (rc = dalloc(c, &d_pix, m)) || (rc = dalloc(c, &d_cpix, static_cast<int64_t>(m) * kMaxTaps)) ||
+        (rc = dalloc(c, &d_bits, static_cast<int64_t>(m) * kMaxTaps)) || (rc = dalloc(c, &d_rsum, m)))
+      break;
+    hipStream_t st = c->stream;
+    if (hipMemcpyAsync(d_rows, rows.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, st) != hipSuccess) {
+      rc = set_error(c, VIP_E_HIP, "copy of sampled rows");
+      break;
+    }
+    k_gather_rows<<<(m + 63) / 64, 64, 0, st>>>(m, d_rows, e.ptr, e.rowlen, e.cols, c->bpos, c->lat.pix,
+                                                vs < 4 ? e.val[vs] : nullptr, vs == 4 ? e.val32 : nullptr,
+                                                vs == 4 ? e.rsum32 : nullptr, d_len, d_bpos, d_pix, d_cpix,
+                                                d_bits, d_rsum);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(len.data(), d_len, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(bp.data(), d_bpos, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(px.data(), d_pix, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(cp.data(), d_cpix, sizeof(int32_t) * m * kMaxTaps, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(bits.data(), d_bits, sizeof(uint64_t) * m * kMaxTaps, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(rs.data(), d_rsum, sizeof(uint32_t) * m, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = set_error(c, VIP_E_HIP, "gathering sampled rows");
+      break;
+    }
+  } while (false);
+  dfree(d_rows);
+  dfree(d_len);
+  dfree(d_bpos);
+  dfree(d_pix);
+  dfree(d_cpix);
+  dfree(d_bits);
+  dfree(d_rsum);
+  if (rc != VIP_OK) return rc;
+  out->assign(m, RowSample());
+  for (int s = 0; s < m; ++s) {
+    RowSample& r = (*out)[s];
+    r.len = len[s];
+    r.bpos = bp[s];
+    r.pix = px[s];
+    r.rsum = rs[s];
+    const int k = std::min(r.len, kMaxTaps);
+    r.cpix.assign(cp.begin() + static_cast<size_t>(s) * kMaxTaps, cp.begin() + static_cast<size_t>(s) * kMaxTaps + k);
+    r.bits.assign(bits.begin() + static_cast<size_t>(s) * kMaxTaps,
+                  bits.begin() + static_cast<size_t>(s) * kMaxTaps + k);
+  }
+  return VIP_OK;
+}
+
+}  // namespace
+
+void lattice_free(Lattice& lat) {
+  dfree(lat.pix);
+  dfree(lat.node_of);
+  lat.tried = lat.ok = false;
+  lat.W = lat.H = 0;
+}
+
+void canon_free(Canon& cn) {
+  for (auto& p : cn.cpix) dfree(p);
+  cn.K = 0;
+  cn.ref_row = -1;
+  for (auto& k : cn.count) k = 0;
+}
+
+int lattice_map(Ctx* c, bool* ok) {
+  Lattice& L = c->lat;
+  if (!L.tried) {
+    L.tried = true;
+    L.ok = false;
+    const double h = c->h;
+    const double wx = std::floor((c->xmax - c->xmin) / h + 0.5) + 1.0;
+    const double wy = std::floor((c->ymax - c->ymin) / h + 0.5) + 1.0;
+    if (wx * wy <= 4.0 * static_cast<double>(c->n) + 4096.0 && wx <= 65536.0 && wy <= 65536.0 && wx >= 1 &&
+        wy >= 1) {
+      L.W = static_cast<int>(wx);
+      L.H = static_cast<int>(wy);
+      const int64_t npix = static_cast<int64_t>(L.W) * L.H;
+      VIP_TRY(dalloc(c, &L.pix, c->n));
+      VIP_TRY(dalloc(c, &L.node_of, npix));
+      hipStream_t st = c->stream;
+      k_fill_i32<<<grid_for(c->n), kBlock, 0, st>>>(c->n, -1, L.pix);
+      k_fill_i32<<<grid_for(npix), kBlock, 0, st>>>(npix, INT32_MAX, L.node_of);
+      k_pixel_claim<<<grid_for(c->n), kBlock, 0, st>>>(c->n, c->x, c->y, c->xmin, c->ymin, h, L.W, L.H,
+                                                       L.node_of);
+      k_pixel_finish<<<grid_for(npix), kBlock, 0, st>>>(npix, L.node_of, L.pix);
+      VIP_HIP_TRY(c, hipGetLastError());
+      VIP_HIP_TRY(c, hipStreamSynchronize(st));
+      L.ok = true;
+    }
+  }
+  if (ok) *ok = L.ok;
+  return VIP_OK;
+}
+
+int canon_mark(Ctx* c, Ell& e, int vs) {
+  Canon& cn = e.canon;
+  if (vs < 0 || vs > 4 || (vs < 4 && !e.val[vs]) || (vs == 4 && (!e.val32 || !e.rsum32))) return VIP_OK;
+  bool ok = false;
+  VIP_TRY(lattice_map(c, &ok));
+  if (!ok || e.nrows != c->n) return VIP_OK;
+  const Lattice& L = c->lat;
+  if (cn.ref_row == -1) {
+    // reference: the most common (offsets, values) pattern among evenly spaced interior rows
+    const int m = static_cast<int>(std::min<int64_t>(1024, c->n));
+    std::vector<int64_t> rows(m);
+    for (int s = 0; s < m; ++s) rows[s] = static_cast<int64_t>((s + 0.5) * static_cast<double>(c->n) / m);
+    std::vector<RowSample> smp;
+    VIP_TRY(gather(c, e, vs, rows, &smp));
+    std::map<std::vector<uint64_t>, std::pair<int, int64_t>> freq;
+    for (int s = 0; s < m; ++s) {
+      const RowSample& r = smp[s];
+      if (r.bpos >= 0 || r.pix < 0 || r.len < 1 || r.len > kMaxTaps) continue;
+      std::vector<uint64_t> key;
+      bool good = true;
+      for (int k = 0; k < r.len; ++k) {
+        if (r.cpix[k] < 0) {
+          good = false;
+          break;
+        }
+        const int64_t dx = static_cast<int64_t>(r.cpix[k] % L.W) - r.pix % L.W;
+        const int64_t dy = static_cast<int64_t>(r.cpix[k] / L.W) - r.pix / L.W;
+        key.push_back(static_cast<uint64_t>((dy + 1024) * 4096 + (dx + 1024)));
+        key.push_back(r.bits[k]);
+      }
+      if (!good) continue;
+      auto& f = freq[key];
+      if (f.first == 0) f.second = rows[s];
+      f.first += 1;
+    }
+    int best = 0;
+    for (const auto& kv : freq)
+      if (kv.second.first > best) {
+        best = kv.second.first;
+        cn.ref_row = kv.second.second;
+      }
+    if (best < 2) {
+      cn.ref_row = -2;   // no repeated interior pattern
+      return VIP_OK;
+    }
+  }
+  if (cn.ref_row < 0) return VIP_OK;
+  // the reference row's offsets and the bits of value set vs
+  std::vector<RowSample> ref;
+  VIP_TRY(gather(c, e, vs, std::vector<int64_t>{cn.ref_row}, &ref));
+  const RowSample& r = ref[0];
+  if (r.len < 1 || r.len > kMaxTaps || r.pix < 0) return VIP_OK;
+  MarkArgs a{};
+  a.K = r.len;
+  a.W = L.W;
+  a.H = L.H;
+  for (int k = 0; k < r.len; ++k) {
+    if (r.cpix[k] < 0) return VIP_OK;
+    a.dx[k] = r.cpix[k] % L.W - r.pix % L.W;
+    a.dy[k] = r.cpix[k] / L.W - r.pix / L.W;
+    a.bits[k] = r.bits[k];
+  }
+  a.rsum_bits = r.rsum;
+  if (cn.K != 0 && cn.K != a.K) return set_error(c, VIP_E_INVALID, "canonical rows changed shape");
+  cn.K = a.K;
+  for (int k = 0; k < a.K; ++k) {
+    cn.dx[k] = a.dx[k];
+    cn.dy[k] = a.dy[k];
+    cn.off[k] = a.dy[k] * L.W + a.dx[k];
+    if (vs < 4) {
+      double d;
+      std::memcpy(&d, &a.bits[k], sizeof(d));
+      cn.w[vs][k] = d;
+    } else {
+      const uint32_t b = static_cast<uint32_t>(a.bits[k]);
+      float f;
+      std::memcpy(&f, &b, sizeof(f));
+      cn.w32[k] = f;
+    }
+  }
+  if (vs == 4) std::memcpy(&cn.rsum32, &a.rsum_bits, sizeof(float));
+  cn.disk = a.K == kDiskTaps ? 1 : 0;
+  for (int k = 0; k < a.K && cn.disk; ++k)
+    if (a.dy[k] != disk_row(k) - 2 || a.dx[k] != disk_dx(k)) cn.disk = 0;
+  if (!cn.cpix[vs]) VIP_TRY(dalloc(c, &cn.cpix[vs], c->n));
+  hipStream_t st = c->stream;
+  k_canon_mark<<<grid_for(c->n), kBlock, 0, st>>>(c->n, a, c->bpos, L.pix, L.node_of, e.ptr, e.rowlen, e.cols,
+                                                  vs < 4 ? e.val[vs] : nullptr, vs == 4 ? e.val32 : nullptr,
+                                                  vs == 4 ? e.rsum32 : nullptr, cn.cpix[vs]);
+  // number of canonical rows (kernels skip the canonical path when it is zero)
+  int64_t* part = nullptr;
+  VIP_TRY(dalloc(c, &part, 256));
+  k_count_nonneg<<<256, 256, 0, st>>>(c->n, cn.cpix[vs], part);
+  std::vector<int64_t> hp(256);
+  hipError_t e1 = hipMemcpyAsync(hp.data(), part, sizeof(int64_t) * 256, hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  dfree(part);
+  if (e1 != hipSuccess || e2 != hipSuccess) return set_error(c, VIP_E_HIP, "counting canonical rows");
+  int64_t cnt = 0;
+  for (int64_t v : hp) cnt += v;
+  cn.count[vs] = cnt;
+  if (c->debug)
+    std::fprintf(stderr, "[vip] canonical rows, value set %d: %lld of %lld (%d taps, reference row %lld)\n", vs,
+                 static_cast<long long>(cnt), static_cast<long long>(c->n), cn.K,
+                 static_cast<long long>(cn.ref_row));
+  return VIP_OK;
+}
+
+}  // namespace vip

@@ -17,10 +17,29 @@ constexpr int kSlice = 64;      // rows per ELL slice = one wavefront
 constexpr int kBlock = 256;     // threads per block of the row kernels
 constexpr int kMaxWidth = 128;  // largest neighbour list of one evaluation point
 constexpr int kNumXcd = 8;      // accelerator complex dies of the MI355X
+constexpr int kMaxTaps = 32;    // taps of a canonical (lattice-interior) row
 
 struct Error {
   int code;
   std::string msg;
+};
+
+// Rows of a sliced-ELL operator that are translation-invariant copies of one reference
+// row: a lattice node whose stored entries sit at the same lattice offsets and hold, bit
+// for bit, the same values.  Products over such rows read the weights from `w` and find
+// the columns through the lattice map, and give the same bits as the general path.
+struct Canon {
+  int K = 0;                        // taps of the reference row (0: none)
+  int32_t dx[kMaxTaps], dy[kMaxTaps];
+  int32_t off[kMaxTaps];            // pixel offsets dy*W + dx, in the row's slot order
+  double w[4][kMaxTaps];            // reference values of FP64 value sets 0..3
+  float w32[kMaxTaps];              // reference values of the FP32 value set
+  float rsum32 = 0.0f;              // reference FP32 row sum
+  int disk = 0;                     // 1: the taps are the 21-point disk in slot order
+  int64_t ref_row = -1;
+  int32_t* cpix[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // device [n] per value set
+                                    // (0..3 FP64, 4 FP32): pixel of a canonical row, else -1
+  int64_t count[5] = {0, 0, 0, 0, 0};
 };
 
 // Sliced ELL matrix: rows grouped by 64; slice s holds width[s] columns stored
@@ -39,6 +58,34 @@ struct Ell {
   float* rsum32 = nullptr;          // FP32 rows evaluated as rsum*x_i + sum a_ij (x_j - x_i)
   int64_t max_width = 0;
   int64_t nnz = 0;                  // sum of row lengths
+  Canon canon;                      // lattice-interior rows (system layout only)
+};
+
+// The 21-point lattice disk of radius 2.5h in slot order (rows dy = -2..2, dx ascending):
+// slot k reads the node dx_k away, along the lattice row, from the node straight above or
+// below the row's node (canonical rows number the nodes of a lattice row consecutively).
+constexpr int kDiskTaps = 21;
+__device__ __host__ constexpr int disk_row(int k) { return k < 3 ? 0 : k < 8 ? 1 : k < 13 ? 2 : k < 18 ? 3 : 4; }
+__device__ __host__ constexpr int disk_dx(int k) {
+  return k < 3 ? k - 1 : k < 8 ? k - 5 : k < 13 ? k - 10 : k < 18 ? k - 15 : k - 19;
+}
+
+// Nodes straight below (rows 0, 1), at (2) and above (3, 4) a canonical row's node.
+__device__ __forceinline__ void disk_bases(const int32_t* node_of, int32_t p, int32_t W, int64_t i,
+                                           int32_t (&b)[5]) {
+  b[0] = node_of[p - 2 * W];
+  b[1] = node_of[p - W];
+  b[2] = static_cast<int32_t>(i);
+  b[3] = node_of[p + W];
+  b[4] = node_of[p + 2 * W];
+}
+
+// Lattice image of the node set: pixel (ix, iy) <-> the node at (xmin + ix h, ymin + iy h).
+struct Lattice {
+  bool tried = false, ok = false;
+  int W = 0, H = 0;
+  int32_t* pix = nullptr;           // device [n]: pixel of each node or -1
+  int32_t* node_of = nullptr;       // device [W*H]: node at each pixel or -1
 };
 
 // Device-resident scalars of the Krylov solvers, written by the last block of a
@@ -71,6 +118,13 @@ struct AmgLevel {
   float* wdinv32 = nullptr;
   double* w64[3] = {nullptr, nullptr, nullptr};   // V-cycle work vectors
   float* w32[3] = {nullptr, nullptr, nullptr};
+  // level 0: canonical rows of the sweeps (canonical values and damped inverse diagonal)
+  int32_t* cpix64 = nullptr;
+  int32_t* cpix32 = nullptr;
+  const int32_t* node_of = nullptr;
+  int32_t W = 0;                  // lattice image width
+  double wdinv_c = 0.0;
+  float wdinv32_c = 0.0f;
 };
 
 struct Amg {
@@ -100,10 +154,6 @@ struct Snapshot {
 // Learned start vector: lattice raster map, captured training data, network state.
 struct Learn {
   void* net = nullptr;        // network parameters and buffers (learn.hip)
-  bool mapped = false;
-  int W = 0, H = 0;           // lattice image size of the current node set
-  int32_t* pix = nullptr;     // device [n]: pixel of each node or -1 (off the lattice)
-  int32_t* node_of = nullptr; // device [H*W]: node at each pixel or -1
   int capacity = 0;           // vip_step stores snapshots while fewer than this are held
   std::vector<Snapshot> snaps;
   double* r = nullptr;        // device [n]: b - L phi_prev of the current step
@@ -122,6 +172,7 @@ struct Ctx {
   int device = 0;
   int debug = 0;                  // VIP_DEBUG=1: trace Krylov batches on stderr
   int amg_pre_fine = 1;           // VIP_AMG_PRE_FINE=0: BiCGStab V-cycles skip the finest pre-sweep
+  int no_canon = 0;               // VIP_NO_CANON=1: every row takes the general sliced-ELL path
   // V-cycle settings: over-correction of the piecewise-constant coarse correction (plain
   // aggregation makes the Galerkin coarse operators too stiff by about 2 for 2x2 aggregates)
   // and damped Jacobi sweeps per level; measured best on the cylinder and triangle node sets
@@ -181,6 +232,7 @@ struct Ctx {
   KrylovScalars* sc = nullptr;    // device scalars
   KrylovScalars* sc_host = nullptr; // pinned host mirror
 
+  Lattice lat;
   Amg amg;
   Learn learn;
   Timing timing;
@@ -280,7 +332,13 @@ int learn_set_params(Ctx* c, const double* theta);
 int learn_get_params(Ctx* c, double* theta);
 int learn_eval(Ctx* c, const double* x, const double* t, const double* m, int B, int H, int W, double* y,
                double* loss, double* grad, double lr);
-int learn_map(Ctx* c);
+// Lattice map of the node set (stencil.hip); false if the nodes are not lattice based.
+int lattice_map(Ctx* c, bool* ok);
+// Find the reference row of the system layout and mark the canonical rows of value set
+// vs (0..3 FP64, 4 FP32 with its row sums).
+int canon_mark(Ctx* c, Ell& e, int vs);
+void canon_free(Canon& cn);
+void lattice_free(Lattice& lat);
 int learn_train(Ctx* c, int iters, int batch, int crop, double lr, uint64_t seed, double* last_loss);
 bool learn_ready(const Ctx* c);
 // before the pressure solve: keep phi_prev = phi and r = b - L phi_prev (with_map: build the

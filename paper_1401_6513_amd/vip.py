@@ -86,6 +86,7 @@ SIGNATURES = {
     "vip_divergence": (_INT, [_P, _P, _P, _P]),
     "vip_gradient": (_INT, [_P, _P, _P, _P]),
     "vip_kernel_timing": (_INT, [_P, _INT, _INT, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    "vip_canonical_rows": (_INT, [_P, _P, ctypes.POINTER(_INT)]),
     "vip_learn_n_params": (_INT, []),
     "vip_learn_init": (_INT, [_P, ctypes.c_uint64]),
     "vip_learn_set_params": (_INT, [_P, _P, _I64]),
@@ -263,6 +264,14 @@ class Context:
         self._check(self.lib.vip_kernel_timing(self._h, int(enable), int(reset), ctypes.byref(avg),
                                                ctypes.byref(cnt)), "vip_kernel_timing")
         return avg.value, cnt.value
+
+    def vip_canonical_rows(self):
+        """(counts per value set [P64, Hu, Hv, -, P32], taps of the reference row)."""
+        counts = np.zeros(5, np.int64)
+        taps = _INT()
+        self._check(self.lib.vip_canonical_rows(self._h, counts.ctypes.data, ctypes.byref(taps)),
+                    "vip_canonical_rows")
+        return counts, taps.value
 
     # ---- learned start vector ---------------------------------------------------------
     def vip_learn_n_params(self):

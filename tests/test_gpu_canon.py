@@ -1,0 +1,72 @@
+"""Lattice-interior (canonical) rows: products over them read the reference row's weights and
+the lattice map instead of the column and value streams, and must give the same bits as the
+general sliced-ELL path.  Each case runs the same steps with the fast path on and off
+(VIP_NO_CANON=1 at context creation) and compares u, v and p bit for bit, in FP64 and in
+mixed precision; on node sets with a power-of-two spacing most rows must be canonical.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1401_6513_amd import nodesets as ns
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _ctx(no_canon):
+    from paper_1401_6513_amd import vip
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if no_canon:
+        os.environ["VIP_NO_CANON"] = "1"
+    try:
+        return vip.Context(0)
+    finally:
+        os.environ.pop("VIP_NO_CANON", None)
+
+
+CASES = {
+    "cavity65": (lambda: ns.lid_cavity(65), (0.0, 0.0), 2e-3, 400.0, 0.5),
+    "cylinder16": (lambda: ns.cylinder_channel(1.0 / 16, box=(-3.0, 6.0, -3.0, 3.0), n_surface=64),
+                   (1.0, 0.0), 1.0 / 160, 100.0, 0.5),
+    "bumpy32": (lambda: ns.cylinder_channel(1.0 / 32, box=(-2.0, 4.0, -2.0, 2.0), shape=(0.05, 12),
+                                            n_surface=128), (1.0, 0.0), 1.0 / 320, 100.0, 0.5),
+    "triangle64": (lambda: ns.triangle_cavity(1.0 / 64), (0.0, 0.0), 1.0 / 640, 200.0, 0.3),
+    "tg32": (lambda: ns.periodic_lattice(32), None, 1e-3, 10.0, None),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_canonical_rows_give_the_same_bits(name, precision):
+    from paper_1401_6513_amd import vip
+    make, inflow, dt, re, min_frac = CASES[name]
+    spec = make()
+    prec = vip.P_FP64 if precision == "fp64" else vip.P_MIXED
+    out = []
+    for no_canon in (False, True):
+        ctx = _ctx(no_canon)
+        ctx.build_from_spec(spec, precision=prec, warmstart=vip.WS_PREV)
+        if inflow is None:
+            u0, v0, p0 = ns.taylor_green_initial(spec.xy)
+        else:
+            u0, v0, p0 = ns.boundary_initial(spec, inflow)
+        st = [torch.tensor(a, device="cuda") for a in (u0, v0, p0)]
+        stats = [ctx.vip_step(*st, dt, re) for _ in range(6)]
+        counts, taps = ctx.vip_canonical_rows()
+        if no_canon:
+            assert counts.sum() == 0
+        else:
+            print("%s %s: canonical rows %s of %d, %d taps" % (name, precision, counts.tolist(), spec.n, taps))
+            if min_frac is not None:
+                assert counts[0] >= min_frac * spec.n and counts[4] >= min_frac * spec.n
+                assert counts[1] >= min_frac * spec.n and counts[2] >= min_frac * spec.n
+        out.append(([a.cpu().numpy() for a in st], [s["poisson_iters"] for s in stats]))
+        ctx.close()
+    (a, ia), (b, ib) = out
+    assert ia == ib
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)

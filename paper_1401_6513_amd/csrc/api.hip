@@ -66,6 +66,9 @@ void ctx_free_build(Ctx* c) {
   c->have_prev_phi = false;
   learn_free_nodeset(c);
   lattice_free(c->lat);
+  for (auto& h : c->hint_p64) h = 0;
+  for (auto& h : c->hint_p32) h = 0;
+  c->hint_h = 0;
 }
 
 namespace {

@@ -836,9 +836,15 @@ int set_active(Ctx* c, const int* act, const double* stop2) {
 // On entry V.r holds the initial residual and sc->rr/bb its norms.  A system
 // stops on the device as soon as it converges or breaks down; *bad reports a
 // non-finite residual (the caller then discards the iterate).
+//
+// Iterations run in batches between host checks; every launch after the device has stopped
+// returns at once but still costs a launch, so with a `hint` (the iterations the previous
+// solve of the same kind took) the first check comes one iteration before that count and
+// later ones every two iterations; *hint is updated on return.
 template <typename VT, typename T, int NS>
 int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit, int* iters,
-            bool time_spmv, const double* bnorm2, bool amg = false, bool* bad = nullptr) {
+            bool time_spmv, const double* bnorm2, bool amg = false, bool* bad = nullptr,
+            int* hint = nullptr) {
   const int64_t nvec = A.n + A.border;
   const int64_t g_vec = grid_for(nvec);
   const int64_t r_rows = red_grid(A.n), r_vec = red_grid(nvec);
@@ -869,8 +875,10 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   }
   int it = 0;
   const int every = std::max(1, c->opt.check_every);
+  int next = (hint && *hint > 0) ? std::max(1, std::min(every, *hint - 1)) : every;
   while ((act[0] || act[1]) && it < maxit) {
-    const int batch = std::min(every, maxit - it);
+    const int batch = std::min(next, maxit - it);
+    if (hint) next = std::min(every, 2);
     for (int b = 0; b < batch; ++b) {
       if (m == kBiCGStab) {
         k_bicg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
@@ -926,6 +934,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   }
   *iters = 0;
   for (int s = 0; s < NS; ++s) *iters = std::max(*iters, c->sc_host->iters[s]);
+  if (hint) *hint = *iters;
   // one timed SpMV per iteration: launches after the device stopped the solve exit at once
   // and are not counted
   harvest_timing(c, 0, static_cast<size_t>(*iters));
@@ -1039,7 +1048,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
       int it = 0;
       bool bad = false;
       VIP_TRY((iterate<double, double, 1>(c, m, A64, V, tol, maxit - total_it, &it, true, &bb, use_amg,
-                                          &bad)));
+                                          &bad, &c->hint_p64[std::min(outer - 1, 3)])));
       total_it += it;
       if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite Krylov residual");
     }
@@ -1073,7 +1082,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
       bool bad = false;
       const double target = std::max(inner, 0.5 * tol / relres);
       VIP_TRY((iterate<float, float, 1>(c, m, A32, V, target, maxit - total_it, &it, true, &rr_outer,
-                                        use_amg, &bad)));
+                                        use_amg, &bad, &c->hint_p32[std::min(outer - 1, 3)])));
       total_it += it;
       if (bad) return set_error(c, VIP_E_NONFINITE, "FP32 inner solve produced a non-finite residual");
       k_add_f32<<<gv, kBlock, 0, s>>>(nvec, x, d32);
@@ -1149,7 +1158,7 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
     int it = 0;
     bool bad = false;
     VIP_TRY((iterate<double, double, 2>(c, kBiCGStab, H, V, tol, c->opt.max_iters - total, &it, false, bb,
-                                        false, &bad)));
+                                        false, &bad, outer == 0 ? &c->hint_h : nullptr)));
     total += it;
     if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite predictor residual");
   }

@@ -230,6 +230,9 @@ struct Ctx {
   double* partials = nullptr;     // device [max blocks * 8]
   int64_t partials_len = 0;
   KrylovScalars* sc = nullptr;    // device scalars
+  int hint_p64[4] = {0, 0, 0, 0}; // iterations of the last pressure solves (FP64, per refinement pass)
+  int hint_p32[4] = {0, 0, 0, 0}; // the same for the FP32 inner solves
+  int hint_h = 0;                 // the same for the predictor solves
   KrylovScalars* sc_host = nullptr; // pinned host mirror
 
   Lattice lat;

@@ -55,8 +55,9 @@ enum {
 /* ---- options -------------------------------------------------------------- */
 enum { VIP_W_CUBIC_SPLINE = 0, VIP_W_PAPER = 1 };  /* weight function Phi (Section 3) */
 enum { VIP_I_MLS = 0, VIP_I_EXACT = 1 };            /* identity in eq. 12: D^[0,0] or I */
-enum { VIP_P_FP64 = 0, VIP_P_MIXED = 1 };           /* Poisson: FP64 Krylov, or FP32
-                                                       inner Krylov in FP64 refinement */
+enum { VIP_P_FP64 = 0, VIP_P_MIXED = 1 };           /* pressure and predictor solves: FP64
+                                                       Krylov, or FP32 inner Krylov in FP64
+                                                       iterative refinement */
 enum { VIP_K_AUTO = 0, VIP_K_PCG = 1, VIP_K_BICGSTAB = 2 };
 /* Poisson start vector in vip_step: zero; the previous increment phi_n; phi_n + alpha e with
  * e = phi_n - phi_(n-1) (EXTRAP); or phi_n + alpha e + beta c with c the learned network's
@@ -76,7 +77,8 @@ typedef struct {
   double period[2];       /* periodic box lengths, 0 = not periodic (both or neither) */
   double poisson_tol;     /* ||b - L phi||_2 / ||b||_2 in FP64; default 1e-8 */
   double helmholtz_tol;   /* same measure for eq. 12; default 1e-12 */
-  double inner_tol;       /* relative tolerance of the FP32 inner solve (MIXED); default 1e-4 */
+  double inner_tol;       /* relative tolerance of each FP32 inner solve (MIXED: pressure and
+                             predictor solves); default 1e-4 */
   int max_iters;          /* Krylov iteration limit per solve; default 200000 */
   int check_every;        /* iterations between host convergence checks; default 16 */
   int preconditioner;     /* VIP_PC_*; default VIP_PC_AMG: aggregation multigrid V-cycle
@@ -297,9 +299,10 @@ int vip_divergence(void* ctx, const double* u, const double* v, double* div);
 int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
 
 /* Rows of the system layout that are translation-invariant lattice-interior copies of one
- * reference row (same lattice offsets, bitwise equal values), per value set: counts[0] FP64
- * pressure matrix, [1] predictor matrix of u, [2] of v, [3] unused, [4] FP32 pressure matrix
- * with its row sums; *taps = entries of the reference row.  Products over these rows skip the
+ * reference row (same lattice offsets, bitwise equal values), per value set (host counts[7]):
+ * [0] FP64 pressure matrix, [1] predictor matrix of u, [2] of v, [3] unused, [4] FP32 pressure
+ * matrix, [5] FP32 predictor matrix of u, [6] of v (the FP32 sets with their row sums);
+ * *taps = entries of the reference row.  Products over these rows skip the
  * column and value streams and give the same bits.  counts are 0 when VIP_NO_CANON=1 was set
  * at vip_create, or for node sets that are not lattice based.  Host outputs, may be NULL. */
 int vip_canonical_rows(void* ctx, int64_t* counts, int* taps);

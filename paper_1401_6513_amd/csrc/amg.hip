@@ -663,13 +663,13 @@ static LevelView<T> view(const AmgLevel& L) {
   v.K = L.A.canon.K;
   v.disk = L.A.canon.disk;
   v.W = L.W;
-  v.crsum = L.A.canon.rsum32;
+  v.crsum = L.A.canon.rsum32[0];
   if constexpr (sizeof(T) == 4) {
     v.val = L.A.val32;
     v.wdinv = L.wdinv32;
     v.cpix = L.cpix32;
     v.wdinv_c = L.wdinv32_c;
-    for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w32[k];
+    for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w32[0][k];
   } else {
     v.val = L.A.val[L.vs];
     v.wdinv = L.wdinv;

@@ -29,6 +29,8 @@ void ell_free(Ell& e) {
   for (auto& v : e.val) dfree(v);
   dfree(e.val32);
   dfree(e.rsum32);
+  for (auto& v : e.val32h) dfree(v);
+  for (auto& v : e.rsum32h) dfree(v);
   e = Ell{};
 }
 
@@ -54,6 +56,7 @@ void ctx_free_build(Ctx* c) {
   ell_free(c->sys);
   for (auto& d : c->dinv) dfree(d);
   dfree(c->dinv32);
+  for (auto& d : c->dinv32h) dfree(d);
   dfree(c->nprev);
   dfree(c->stepbuf);
   dfree(c->phi);
@@ -68,6 +71,7 @@ void ctx_free_build(Ctx* c) {
   lattice_free(c->lat);
   for (auto& h : c->hint_p64) h = 0;
   for (auto& h : c->hint_p32) h = 0;
+  for (auto& h : c->hint_h32) h = 0;
   c->hint_h = 0;
 }
 
@@ -426,7 +430,7 @@ int vip_canonical_rows(void* p, int64_t* counts, int* taps) {
   VIP_TRY(vip::need_built(c));
   const vip::Canon& cn = c->sys.canon;
   if (counts)
-    for (int k = 0; k < 5; ++k) counts[k] = c->no_canon ? 0 : cn.count[k];
+    for (int k = 0; k < 7; ++k) counts[k] = c->no_canon ? 0 : cn.count[k];
   if (taps) *taps = cn.K;
   return VIP_OK;
 }

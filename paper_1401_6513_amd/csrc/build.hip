@@ -1012,9 +1012,21 @@ int assemble_helmholtz(Ctx* c, double dt, double re) {
                                                         c->sys.val[1], c->dinv[1]);
   k_diag_inv<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, c->sys.ptr, c->sys.cols, c->sys.rowlen,
                                                         c->sys.val[2], c->dinv[2]);
+  // FP32 copies for the mixed-precision predictor solve: values, row sums, Jacobi diagonals
+  Ell& s = c->sys;
+  for (int k = 0; k < 2; ++k) {
+    if (!s.val32h[k]) VIP_TRY(dalloc(c, &s.val32h[k], s.nnz_slots));
+    if (!s.rsum32h[k]) VIP_TRY(dalloc(c, &s.rsum32h[k], c->n));
+    if (!c->dinv32h[k]) VIP_TRY(dalloc(c, &c->dinv32h[k], c->n + 1));
+    k_to_f32<<<grid_for(s.nnz_slots), kBlock, 0, c->stream>>>(s.nnz_slots, s.val[1 + k], s.val32h[k]);
+    launch_rowsum32(c->stream, c->n, s.ptr, s.rowlen, s.val[1 + k], s.rsum32h[k]);
+    k_to_f32<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, c->dinv[1 + k], c->dinv32h[k]);
+  }
   VIP_HIP_TRY(c, hipGetLastError());
   VIP_TRY(canon_mark(c, c->sys, 1));
   VIP_TRY(canon_mark(c, c->sys, 2));
+  VIP_TRY(canon_mark(c, c->sys, 5));
+  VIP_TRY(canon_mark(c, c->sys, 6));
   c->cur_dt = dt;
   c->cur_re = re;
   c->assembled = true;

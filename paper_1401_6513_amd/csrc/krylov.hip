@@ -123,7 +123,7 @@ struct Mat {
   const int64_t* ptr;
   const int32_t* cols;
   const VT* val[2];        // value sets of system 0 and 1
-  const float* rsum;       // FP32 values only: row sums for the difference form
+  const float* rsum[2];    // FP32 values only: row sums of systems 0 and 1 for the difference form
   // lattice-interior rows (stencil.hip): pixel of a canonical row, else -1; null = none
   const int32_t* cpix[2];
   const int32_t* node_of;
@@ -135,8 +135,18 @@ struct Mat {
   float crsum[2];
 };
 
+// Every system a kernel will touch has its values (and, in FP32, its row sums).
+template <typename VT>
+int check_mat(Ctx* c, const Mat<VT>& A, int ns) {
+  for (int s = 0; s < ns; ++s) {
+    if (!A.val[s] || !A.ptr || !A.cols) return set_error(c, VIP_E_INVALID, "matrix of a system is missing");
+    if (sizeof(VT) == 4 && !A.rsum[s]) return set_error(c, VIP_E_INVALID, "FP32 row sums of a system are missing");
+  }
+  return VIP_OK;
+}
+
 // Attach the canonical rows of value sets vs0 (system 0) and vs1 (system 1, -1 = none);
-// vs 4 is the FP32 pressure set.
+// sets 4..6 are the FP32 pressure and predictor sets.
 template <typename VT>
 void attach_canon(const Ctx* c, Mat<VT>& A, int vs0, int vs1) {
   const Canon& cn = c->sys.canon;
@@ -147,8 +157,8 @@ void attach_canon(const Ctx* c, Mat<VT>& A, int vs0, int vs1) {
     if (vs[s] < 0 || cn.count[vs[s]] == 0 || !cn.cpix[vs[s]]) continue;
     A.cpix[s] = cn.cpix[vs[s]];
     for (int k = 0; k < cn.K; ++k)
-      A.w[s][k] = (vs[s] == 4) ? static_cast<VT>(cn.w32[k]) : static_cast<VT>(cn.w[vs[s]][k]);
-    A.crsum[s] = cn.rsum32;
+      A.w[s][k] = (vs[s] >= 4) ? static_cast<VT>(cn.w32[vs[s] - 4][k]) : static_cast<VT>(cn.w[vs[s]][k]);
+    A.crsum[s] = vs[s] >= 4 ? cn.rsum32[vs[s] - 4] : 0.0f;
   }
   A.node_of = c->lat.node_of;
   A.K = cn.K;
@@ -282,7 +292,7 @@ __device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, 
       const int64_t q = base + static_cast<int64_t>(k) * kSlice;
       a0 += static_cast<float>(vals[q]) * (static_cast<float>(x[A.cols[q]]) - xi);
     }
-    return static_cast<double>(a0 + a1) + static_cast<double>(A.rsum[i] * xi);
+    return static_cast<double>(a0 + a1) + static_cast<double>(A.rsum[sys][i] * xi);
   } else {
     double a0 = 0.0, a1 = 0.0;
     int k = 0;
@@ -845,6 +855,7 @@ template <typename VT, typename T, int NS>
 int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit, int* iters,
             bool time_spmv, const double* bnorm2, bool amg = false, bool* bad = nullptr,
             int* hint = nullptr) {
+  VIP_TRY(check_mat(c, A, NS));
   const int64_t nvec = A.n + A.border;
   const int64_t g_vec = grid_for(nvec);
   const int64_t r_rows = red_grid(A.n), r_vec = red_grid(nvec);
@@ -943,6 +954,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
 
 template <typename VT, typename XT, typename RT, int NS>
 int residual(Ctx* c, const Mat<VT>& A, const XT* x, const double* b, RT* r, int64_t stride) {
+  VIP_TRY(check_mat(c, A, NS));
   const int64_t g = red_grid(A.n);
   VIP_TRY(ensure_partials(c, g, 3 * NS));
   k_residual<VT, XT, RT, NS><<<g, kBlock, 0, c->stream>>>(A, x, b, r, stride, c->partials);
@@ -1022,7 +1034,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   } else {
     k_fill<double><<<gv, kBlock, 0, s>>>(stride, x, 0.0);
   }
-  Mat<double> A64{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}, nullptr};
+  Mat<double> A64{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}, {nullptr, nullptr}};
   attach_canon(c, A64, 0, -1);
   int total_it = 0, outer = 0;
   double relres = 0.0;
@@ -1054,7 +1066,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
     }
   } else {
     const double inner = std::max(c->opt.inner_tol, 1e-7);
-    Mat<float> A32{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val32, nullptr}, c->sys.rsum32};
+    Mat<float> A32{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val32, nullptr}, {c->sys.rsum32, nullptr}};
     attach_canon(c, A32, 4, -1);
     float* d32 = c->ws32 + 8 * stride;
     float* r32base = c->ws32;
@@ -1119,12 +1131,15 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   return VIP_OK;
 }
 
-// The two predictor systems H_u u* = r_u, H_v v* = r_v in lockstep (FP64).
+// The two predictor systems H_u u* = r_u, H_v v* = r_v in lockstep: FP64 BiCGStab, or with
+// VIP_P_MIXED FP32 BiCGStab corrections inside FP64 iterative refinement (FP64 residual and
+// iterate, to the same FP64 tolerance).
 int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, double* vs,
                     vip_step_stats* st) {
   const int64_t n = c->n;
   const int64_t stride = n + 1;
-  VIP_TRY(ensure_ws(c, 2 * 8 * stride + 2 * stride + 2 * stride, 1));
+  const bool mixed = c->opt.precision == VIP_P_MIXED && c->sys.val32h[0] && c->sys.val32h[1];
+  VIP_TRY(ensure_ws(c, 2 * 8 * stride + 2 * stride + 2 * stride, mixed ? 2 * 8 * stride + 2 * stride : 1));
   double* b = c->ws + 16 * stride;      // [2][stride]
   double* x = c->ws + 18 * stride;      // [2][stride]
   hipStream_t s = c->stream;
@@ -1133,34 +1148,61 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
   // start from the right-hand side (the operators are close to the identity)
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, x);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, x + stride);
-  Mat<double> H{n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[1], c->sys.val[2]}, nullptr};
+  Mat<double> H{n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[1], c->sys.val[2]}, {nullptr, nullptr}};
   attach_canon(c, H, 1, 2);
   Vec<double> V = make_vec<double>(c->ws, stride, 2, x);
   V.dinv[0] = c->dinv[1];
   V.dinv[1] = c->dinv[2];
+  Mat<float> H32{n, 0, c->sys.ptr, c->sys.cols, {c->sys.val32h[0], c->sys.val32h[1]},
+                 {c->sys.rsum32h[0], c->sys.rsum32h[1]}};
+  Vec<float> V32{};
+  float* d32 = nullptr;
+  if (mixed) {
+    attach_canon(c, H32, 5, 6);
+    d32 = c->ws32 + 16 * stride;         // [2][stride] FP32 correction
+    V32 = make_vec<float>(c->ws32, stride, 2, d32);
+    V32.dinv[0] = c->dinv32h[0];
+    V32.dinv[1] = c->dinv32h[1];
+  }
   const double tol = c->opt.helmholtz_tol;
+  const double inner = std::max(c->opt.inner_tol, 1e-7);
   int total = 0;
   double worst = 0.0;
   bool converged = false;
-  for (int outer = 0; outer < 10; ++outer) {
-    VIP_TRY((residual<double, double, double, 2>(c, H, x, b, V.r, stride)));
+  for (int outer = 0; outer < (mixed ? 40 : 10); ++outer) {
+    if (mixed) {
+      VIP_TRY((residual<double, double, float, 2>(c, H, x, b, V32.r, stride)));
+    } else {
+      VIP_TRY((residual<double, double, double, 2>(c, H, x, b, V.r, stride)));
+    }
     double bb[2] = {c->sc_host->bb[0], c->sc_host->bb[1]};
+    double rr[2] = {c->sc_host->rr[0], c->sc_host->rr[1]};
     worst = 0.0;
-    for (int k = 0; k < 2; ++k)
-      worst = std::max(worst, bb[k] > 0.0 ? std::sqrt(c->sc_host->rr[k] / bb[k]) : 0.0);
+    for (int k = 0; k < 2; ++k) worst = std::max(worst, bb[k] > 0.0 ? std::sqrt(rr[k] / bb[k]) : 0.0);
     if (worst <= tol) {
       converged = true;
       break;
     }
     if (total >= c->opt.max_iters) break;
-    // a system whose b is zero is solved by x = 0 exactly: give it a unit norm
-    for (int k = 0; k < 2; ++k) if (bb[k] == 0.0) bb[k] = 1.0;
     int it = 0;
     bool bad = false;
-    VIP_TRY((iterate<double, double, 2>(c, kBiCGStab, H, V, tol, c->opt.max_iters - total, &it, false, bb,
-                                        false, &bad, outer == 0 ? &c->hint_h : nullptr)));
-    total += it;
-    if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite predictor residual");
+    if (mixed) {
+      // FP32 correction d from 0 for the FP64 residual r, to `target` relative to |r|
+      const double target = std::max(inner, 0.5 * tol / worst);
+      k_fill<float><<<grid_for(2 * stride), kBlock, 0, s>>>(2 * stride, d32, 0.0f);
+      VIP_TRY((iterate<float, float, 2>(c, kBiCGStab, H32, V32, target, c->opt.max_iters - total, &it, false,
+                                        rr, false, &bad, &c->hint_h32[std::min(outer, 3)])));
+      total += it;
+      if (bad) return set_error(c, VIP_E_NONFINITE, "FP32 predictor correction produced a non-finite residual");
+      k_add_f32<<<grid_for(2 * stride), kBlock, 0, s>>>(2 * stride, x, d32);
+    } else {
+      // a system whose b is zero is solved by x = 0 exactly: give it a unit norm
+      for (int k = 0; k < 2; ++k) if (bb[k] == 0.0) bb[k] = 1.0;
+      VIP_TRY((iterate<double, double, 2>(c, kBiCGStab, H, V, tol, c->opt.max_iters - total, &it, false, bb,
+                                          false, &bad, outer == 0 ? &c->hint_h : nullptr)));
+      total += it;
+      if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite predictor residual");
+    }
   }
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x, us);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x + stride, vs);

@@ -163,10 +163,11 @@ int gather(Ctx* c, const Ell& e, int vs, const std::vector<int64_t>& rows, std::
       rc = set_error(c, VIP_E_HIP, "copy of sampled rows");
       break;
     }
+    const float* v32 = vs == 4 ? e.val32 : vs > 4 ? e.val32h[vs - 5] : nullptr;
+    const float* r32 = vs == 4 ? e.rsum32 : vs > 4 ? e.rsum32h[vs - 5] : nullptr;
     k_gather_rows<<<(m + 63) / 64, 64, 0, st>>>(m, d_rows, e.ptr, e.rowlen, e.cols, c->bpos, c->lat.pix,
-                                                vs < 4 ? e.val[vs] : nullptr, vs == 4 ? e.val32 : nullptr,
-                                                vs == 4 ? e.rsum32 : nullptr, d_len, d_bpos, d_pix, d_cpix,
-                                                d_bits, d_rsum);
+                                                vs < 4 ? e.val[vs] : nullptr, v32, r32, d_len, d_bpos, d_pix,
+                                                d_cpix, d_bits, d_rsum);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(len.data(), d_len, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(bp.data(), d_bpos, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -252,7 +253,9 @@ int lattice_map(Ctx* c, bool* ok) {
 
 int canon_mark(Ctx* c, Ell& e, int vs) {
   Canon& cn = e.canon;
-  if (vs < 0 || vs > 4 || (vs < 4 && !e.val[vs]) || (vs == 4 && (!e.val32 || !e.rsum32))) return VIP_OK;
+  const float* v32 = vs == 4 ? e.val32 : vs > 4 && vs <= 6 ? e.val32h[vs - 5] : nullptr;
+  const float* r32 = vs == 4 ? e.rsum32 : vs > 4 && vs <= 6 ? e.rsum32h[vs - 5] : nullptr;
+  if (vs < 0 || vs > 6 || (vs < 4 && !e.val[vs]) || (vs >= 4 && (!v32 || !r32))) return VIP_OK;
   bool ok = false;
   VIP_TRY(lattice_map(c, &ok));
   if (!ok || e.nrows != c->n) return VIP_OK;
@@ -327,18 +330,17 @@ int canon_mark(Ctx* c, Ell& e, int vs) {
       const uint32_t b = static_cast<uint32_t>(a.bits[k]);
       float f;
       std::memcpy(&f, &b, sizeof(f));
-      cn.w32[k] = f;
+      cn.w32[vs - 4][k] = f;
     }
   }
-  if (vs == 4) std::memcpy(&cn.rsum32, &a.rsum_bits, sizeof(float));
+  if (vs >= 4) std::memcpy(&cn.rsum32[vs - 4], &a.rsum_bits, sizeof(float));
   cn.disk = a.K == kDiskTaps ? 1 : 0;
   for (int k = 0; k < a.K && cn.disk; ++k)
     if (a.dy[k] != disk_row(k) - 2 || a.dx[k] != disk_dx(k)) cn.disk = 0;
   if (!cn.cpix[vs]) VIP_TRY(dalloc(c, &cn.cpix[vs], c->n));
   hipStream_t st = c->stream;
   k_canon_mark<<<grid_for(c->n), kBlock, 0, st>>>(c->n, a, c->bpos, L.pix, L.node_of, e.ptr, e.rowlen, e.cols,
-                                                  vs < 4 ? e.val[vs] : nullptr, vs == 4 ? e.val32 : nullptr,
-                                                  vs == 4 ? e.rsum32 : nullptr, cn.cpix[vs]);
+                                                  vs < 4 ? e.val[vs] : nullptr, v32, r32, cn.cpix[vs]);
   // number of canonical rows (kernels skip the canonical path when it is zero)
   int64_t* part = nullptr;
   VIP_TRY(dalloc(c, &part, 256));

@@ -33,13 +33,14 @@ struct Canon {
   int32_t dx[kMaxTaps], dy[kMaxTaps];
   int32_t off[kMaxTaps];            // pixel offsets dy*W + dx, in the row's slot order
   double w[4][kMaxTaps];            // reference values of FP64 value sets 0..3
-  float w32[kMaxTaps];              // reference values of the FP32 value set
-  float rsum32 = 0.0f;              // reference FP32 row sum
+  float w32[3][kMaxTaps];           // reference values of FP32 value sets 4..6
+  float rsum32[3] = {0.0f, 0.0f, 0.0f};  // reference FP32 row sums of sets 4..6
   int disk = 0;                     // 1: the taps are the 21-point disk in slot order
   int64_t ref_row = -1;
-  int32_t* cpix[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // device [n] per value set
-                                    // (0..3 FP64, 4 FP32): pixel of a canonical row, else -1
-  int64_t count[5] = {0, 0, 0, 0, 0};
+  int32_t* cpix[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // device [n]
+                                    // per value set (0..3 FP64; 4..6 FP32: pressure, predictor u, v):
+                                    // pixel of a canonical row, else -1
+  int64_t count[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 // Sliced ELL matrix: rows grouped by 64; slice s holds width[s] columns stored
@@ -56,6 +57,8 @@ struct Ell {
   double* val[4] = {nullptr, nullptr, nullptr, nullptr};  // FP64 value sets
   float* val32 = nullptr;           // FP32 value set (pressure matrix only)
   float* rsum32 = nullptr;          // FP32 rows evaluated as rsum*x_i + sum a_ij (x_j - x_i)
+  float* val32h[2] = {nullptr, nullptr};   // FP32 predictor matrices (system layout only)
+  float* rsum32h[2] = {nullptr, nullptr};
   int64_t max_width = 0;
   int64_t nnz = 0;                  // sum of row lengths
   Canon canon;                      // lattice-interior rows (system layout only)
@@ -214,6 +217,7 @@ struct Ctx {
   Ell sys;                        // val[0] = Poisson, val[1] = H_u, val[2] = H_v; val32 = Poisson
   double* dinv[3] = {nullptr, nullptr, nullptr};   // Jacobi inverse diagonals (P, Hu, Hv)
   float* dinv32 = nullptr;
+  float* dinv32h[2] = {nullptr, nullptr};          // FP32 Jacobi inverse diagonals of H_u, H_v
 
   // step state
   double cur_dt = 0.0, cur_re = 0.0;
@@ -233,6 +237,7 @@ struct Ctx {
   int hint_p64[4] = {0, 0, 0, 0}; // iterations of the last pressure solves (FP64, per refinement pass)
   int hint_p32[4] = {0, 0, 0, 0}; // the same for the FP32 inner solves
   int hint_h = 0;                 // the same for the predictor solves
+  int hint_h32[4] = {0, 0, 0, 0}; // and for their FP32 inner solves
   KrylovScalars* sc_host = nullptr; // pinned host mirror
 
   Lattice lat;
@@ -338,7 +343,7 @@ int learn_eval(Ctx* c, const double* x, const double* t, const double* m, int B,
 // Lattice map of the node set (stencil.hip); false if the nodes are not lattice based.
 int lattice_map(Ctx* c, bool* ok);
 // Find the reference row of the system layout and mark the canonical rows of value set
-// vs (0..3 FP64, 4 FP32 with its row sums).
+// vs (0..3 FP64; 4..6 FP32 pressure, predictor u, predictor v, with their row sums).
 int canon_mark(Ctx* c, Ell& e, int vs);
 void canon_free(Canon& cn);
 void lattice_free(Lattice& lat);

@@ -266,8 +266,8 @@ class Context:
         return avg.value, cnt.value
 
     def vip_canonical_rows(self):
-        """(counts per value set [P64, Hu, Hv, -, P32], taps of the reference row)."""
-        counts = np.zeros(5, np.int64)
+        """(counts per value set [P64, Hu, Hv, -, P32, Hu32, Hv32], taps of the reference row)."""
+        counts = np.zeros(7, np.int64)
         taps = _INT()
         self._check(self.lib.vip_canonical_rows(self._h, counts.ctypes.data, ctypes.byref(taps)),
                     "vip_canonical_rows")

@@ -64,6 +64,7 @@ def test_canonical_rows_give_the_same_bits(name, precision):
             if min_frac is not None:
                 assert counts[0] >= min_frac * spec.n and counts[4] >= min_frac * spec.n
                 assert counts[1] >= min_frac * spec.n and counts[2] >= min_frac * spec.n
+                assert counts[5] >= min_frac * spec.n and counts[6] >= min_frac * spec.n
         out.append(([a.cpu().numpy() for a in st], [s["poisson_iters"] for s in stats]))
         ctx.close()
     (a, ia), (b, ib) = out

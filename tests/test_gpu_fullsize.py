@@ -98,7 +98,7 @@ def test_sampled_operator_rows_at_full_size(full):
         xw = x[idx]
         for op, M in mats.items():
             row = M.getrow(li)
-            ref = float(row @ xw)
+            ref = float((row @ xw)[0])
             scale = float(abs(row) @ np.abs(xw)) + 1e-300
             err = abs(got[op][i] - ref) / scale
             worst[op] = max(worst[op], err)

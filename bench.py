@@ -271,17 +271,27 @@ def main():
     roof = None
     if r["spmv"] is not None and r["spmv"][1] > 0:
         n0, _, nnz0 = ctxs[0].vip_operator_shape("poisson")
-        # FP32 values + int32 columns per stored entry; x gathered once, v written, rhat read
-        bytes_per_launch = 8 * nnz0 + 12 * n0
+        fp32 = PATHS[main_path]["precision"] != "P_FP64"
+        counts, taps, desc = ctxs[0].vip_canonical_rows(described=True)
+        vs = 4 if fp32 else 0
+        nc, nd = int(counts[vs]), int(desc[vs])
+        vb = 4 if fp32 else 8            # bytes of one vector entry / value
+        # algorithmic bytes of one launch: x gathered once, r-hat read, v written (3 vectors);
+        # stored values + int32 columns of the rows on the general path (and, in FP32, their
+        # row sums); per-row canonical flags outside described slices; one 16-byte descriptor
+        # per described slice.  Canonical rows read no column or value stream.
+        bytes_per_launch = (3 * vb * n0 + (vb + 4) * (nnz0 - taps * nc) + (4 if fp32 else 0) * (n0 - nc)
+                            + 4 * (n0 - nd) + 16 * (nd // 64))
         avg_ms, count = r["spmv"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic() if abs(h - 1.0 / 128) < 1e-12 else None,
-                "kernel": "k_bicg_v<%s,%s,1> (pressure SpMV, sliced ELL)" % ((
-                    "double", "double") if PATHS[main_path]["precision"] == "P_FP64" else ("float", "float")),
+                "kernel": "k_bicg_v<%s,%s,1> (pressure SpMV)" % (("float", "float") if fp32 else
+                                                                  ("double", "double")),
                 "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms, "launches": count,
-                "rows": n0, "nnz": nnz0}
+                "rows": n0, "nnz": nnz0, "canonical_rows": nc, "described_rows": nd, "taps": taps,
+                "ell_bytes_per_launch": (vb + 4) * nnz0 + 3 * vb * n0}
 
     out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,

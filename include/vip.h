@@ -302,10 +302,12 @@ int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
  * reference row (same lattice offsets, bitwise equal values), per value set (host counts[7]):
  * [0] FP64 pressure matrix, [1] predictor matrix of u, [2] of v, [3] unused, [4] FP32 pressure
  * matrix, [5] FP32 predictor matrix of u, [6] of v (the FP32 sets with their row sums);
- * *taps = entries of the reference row.  Products over these rows skip the
- * column and value streams and give the same bits.  counts are 0 when VIP_NO_CANON=1 was set
- * at vip_create, or for node sets that are not lattice based.  Host outputs, may be NULL. */
-int vip_canonical_rows(void* ctx, int64_t* counts, int* taps);
+ * described[7]: rows of 64-row slices whose rows are all canonical on consecutive pixels of
+ * one lattice row (their kernels read one descriptor per slice instead of per-row data);
+ * *taps = entries of the reference row.  Products over these rows skip the column and value
+ * streams and give the same bits.  All counts are 0 when VIP_NO_CANON=1 was set at
+ * vip_create, or for node sets that are not lattice based.  Host outputs, may be NULL. */
+int vip_canonical_rows(void* ctx, int64_t* counts, int64_t* described, int* taps);
 
 /* Average duration (ms) of the pressure-solve SpMV kernel (the first SpMV of
  * each Krylov iteration) over the launches since the last reset, measured with

@@ -279,6 +279,7 @@ struct LevelView {
   const float* rsum;   // FP32 levels: row sums for the difference form
   // lattice-interior rows of level 0 (stencil.hip): pixel of a canonical row, else -1
   const int32_t* cpix;
+  const int32_t* sbase;   // slice descriptors of those rows, or null
   const int32_t* node_of;
   int K;
   int disk;
@@ -292,21 +293,30 @@ struct LevelView {
 // Canonical row of a level: weights of the reference row, columns from the lattice map,
 // slots to the accumulators in the general path's order (same bits).
 template <typename T, class Y>
-__device__ __forceinline__ T canon_row(const LevelView<T>& L, int32_t p, int64_t i, int w, Y y) {
+__device__ __forceinline__ T disk_row_sum(const LevelView<T>& L, int64_t i, const int32_t (&b)[5], Y y) {
   const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
   T a0 = T(0), a1 = T(0);
+#pragma unroll
+  for (int k = 0; k < kDiskTaps; ++k) {
+    const T d = L.w[k] * (y(b[disk_row(k)] + disk_dx(k)) - yi);
+    if (k & 1) a1 += d;
+    else a0 += d;
+  }
+  if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
+  else return a0 + a1;
+}
+
+// Canonical row of a level: weights of the reference row, columns from the lattice map,
+// slots to the accumulators in the general path's order (same bits).
+template <typename T, class Y>
+__device__ __forceinline__ T canon_row(const LevelView<T>& L, int32_t p, int64_t i, int w, Y y) {
   if (L.disk) {
     int32_t b[5];
     disk_bases(L.node_of, p, L.W, i, b);
-#pragma unroll
-    for (int k = 0; k < kDiskTaps; ++k) {
-      const T d = L.w[k] * (y(b[disk_row(k)] + disk_dx(k)) - yi);
-      if (k & 1) a1 += d;
-      else a0 += d;
-    }
-    if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
-    else return a0 + a1;
+    return disk_row_sum(L, i, b, y);
   }
+  const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
+  T a0 = T(0), a1 = T(0);
   const int full = w & ~3;
   const int32_t* nb = L.node_of + p;
   int k = 0;
@@ -328,6 +338,10 @@ __device__ __forceinline__ T canon_row(const LevelView<T>& L, int32_t p, int64_t
 
 template <typename T>
 __device__ __forceinline__ T level_wdinv(const LevelView<T>& L, int64_t i) {
+  if (L.sbase) {
+    const int32_t sl = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(i >> 6));
+    if ((i >> 6) == sl && L.sbase[4 * static_cast<int64_t>(sl)] >= 0) return L.wdinv_c;
+  }
   return (L.cpix && L.cpix[i] >= 0) ? L.wdinv_c : L.wdinv[i];
 }
 
@@ -353,6 +367,10 @@ __device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
   const int64_t sl = i / kSlice;
   const int64_t base = L.ptr[sl] + (i % kSlice);
   const int w = static_cast<int>((L.ptr[sl + 1] - L.ptr[sl]) / kSlice);
+  if (L.sbase) {
+    int32_t b[5];
+    if (slice_disk_bases(L.sbase, i, b)) return disk_row_sum(L, i, b, y);
+  }
   if (L.cpix) {
     const int32_t p = L.cpix[i];
     if (p >= 0) return canon_row(L, p, i, w, y);
@@ -465,6 +483,8 @@ void amg_free(Ctx* c) {
     dfree(L.members);
     dfree(L.cpix64);
     dfree(L.cpix32);
+    dfree(L.sbase64);
+    dfree(L.sbase32);
     for (int k = 0; k < 3; ++k) {
       dfree(L.w64[k]);
       dfree(L.w32[k]);
@@ -516,10 +536,12 @@ int amg_setup(Ctx* c) {
       if (cn.count[0] > 0 && cn.cpix[0]) {
         VIP_TRY(dalloc(c, &L.cpix64, L.n));
         k_canon_wd<double><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[0], L.wdinv, L.wdinv_c, L.cpix64);
+        if (cn.disk) VIP_TRY(slice_bases(c, L.cpix64, L.n, &L.sbase64));
       }
       if (cn.count[4] > 0 && cn.cpix[4]) {
         VIP_TRY(dalloc(c, &L.cpix32, L.n));
         k_canon_wd<float><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[4], L.wdinv32, L.wdinv32_c, L.cpix32);
+        if (cn.disk) VIP_TRY(slice_bases(c, L.cpix32, L.n, &L.sbase32));
       }
       VIP_HIP_TRY(c, hipGetLastError());
     }
@@ -659,6 +681,7 @@ static LevelView<T> view(const AmgLevel& L) {
   v.cols = L.A.cols;
   v.rsum = L.A.rsum32;
   v.cpix = nullptr;
+  v.sbase = nullptr;
   v.node_of = L.node_of;
   v.K = L.A.canon.K;
   v.disk = L.A.canon.disk;
@@ -668,12 +691,14 @@ static LevelView<T> view(const AmgLevel& L) {
     v.val = L.A.val32;
     v.wdinv = L.wdinv32;
     v.cpix = L.cpix32;
+    v.sbase = L.A.canon.disk ? L.sbase32 : nullptr;
     v.wdinv_c = L.wdinv32_c;
     for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w32[0][k];
   } else {
     v.val = L.A.val[L.vs];
     v.wdinv = L.wdinv;
     v.cpix = L.cpix64;
+    v.sbase = L.A.canon.disk ? L.sbase64 : nullptr;
     v.wdinv_c = L.wdinv_c;
     for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w[L.vs][k];
   }

@@ -425,12 +425,14 @@ int vip_kernel_timing(void* p, int enable, int reset, double* avg_ms, int64_t* c
   return VIP_OK;
 }
 
-int vip_canonical_rows(void* p, int64_t* counts, int* taps) {
+int vip_canonical_rows(void* p, int64_t* counts, int64_t* described, int* taps) {
   Ctx* c = vip::as_ctx(p);
   VIP_TRY(vip::need_built(c));
   const vip::Canon& cn = c->sys.canon;
   if (counts)
     for (int k = 0; k < 7; ++k) counts[k] = c->no_canon ? 0 : cn.count[k];
+  if (described)
+    for (int k = 0; k < 7; ++k) described[k] = c->no_canon ? 0 : cn.described[k];
   if (taps) *taps = cn.K;
   return VIP_OK;
 }

@@ -126,6 +126,7 @@ struct Mat {
   const float* rsum[2];    // FP32 values only: row sums of systems 0 and 1 for the difference form
   // lattice-interior rows (stencil.hip): pixel of a canonical row, else -1; null = none
   const int32_t* cpix[2];
+  const int32_t* sbase[2]; // slice descriptors of the canonical rows, or null
   const int32_t* node_of;
   int K;
   int disk;                // taps are the 21-point disk (unrolled path)
@@ -151,11 +152,13 @@ template <typename VT>
 void attach_canon(const Ctx* c, Mat<VT>& A, int vs0, int vs1) {
   const Canon& cn = c->sys.canon;
   A.cpix[0] = A.cpix[1] = nullptr;
+  A.sbase[0] = A.sbase[1] = nullptr;
   if (c->no_canon || cn.K == 0) return;
   const int vs[2] = {vs0, vs1};
   for (int s = 0; s < 2; ++s) {
     if (vs[s] < 0 || cn.count[vs[s]] == 0 || !cn.cpix[vs[s]]) continue;
     A.cpix[s] = cn.cpix[vs[s]];
+    A.sbase[s] = cn.disk ? cn.sbase[vs[s]] : nullptr;
     for (int k = 0; k < cn.K; ++k)
       A.w[s][k] = (vs[s] >= 4) ? static_cast<VT>(cn.w32[vs[s] - 4][k]) : static_cast<VT>(cn.w[vs[s]][k]);
     A.crsum[s] = vs[s] >= 4 ? cn.rsum32[vs[s] - 4] : 0.0f;
@@ -185,34 +188,41 @@ struct Vec {
 // Canonical row: the weights come from the reference row and the columns from the lattice
 // map.  Slots go to the two accumulators in the general path's order (pairs of the unrolled
 // groups alternate, the tail goes to the first), so the bits are the same.
+// 21-point disk with the five row bases given: slots 0, 2, ..., 20 to the first accumulator,
+// the odd ones to the second (a slice of such rows is at least 21 wide, so only slot 20 can
+// fall in the tail of the general path)
+template <typename VT, typename T>
+__device__ __forceinline__ double disk_dot(const Mat<VT>& A, int sys, int64_t i, const int32_t (&b)[5],
+                                           const T* x) {
+  if constexpr (sizeof(VT) == 4) {
+    const float xi = static_cast<float>(x[i]);
+    float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kDiskTaps; ++k) {
+      const float d = A.w[sys][k] * (static_cast<float>(x[b[disk_row(k)] + disk_dx(k)]) - xi);
+      if (k & 1) a1 += d;
+      else a0 += d;
+    }
+    return static_cast<double>(a0 + a1) + static_cast<double>(A.crsum[sys] * xi);
+  } else {
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kDiskTaps; ++k) {
+      const double d = A.w[sys][k] * static_cast<double>(x[b[disk_row(k)] + disk_dx(k)]);
+      if (k & 1) a1 += d;
+      else a0 += d;
+    }
+    return a0 + a1;
+  }
+}
+
 template <typename VT, typename T>
 __device__ __forceinline__ double canon_dot(const Mat<VT>& A, int sys, int32_t p, int64_t i, int w,
                                             const T* x) {
   if (A.disk) {
-    // 21 taps: slots 0, 2, ..., 20 to the first accumulator, the odd ones to the second (a
-    // slice of such rows is at least 21 wide, so only slot 20 can fall in the tail)
     int32_t b[5];
     disk_bases(A.node_of, p, A.W, i, b);
-    if constexpr (sizeof(VT) == 4) {
-      const float xi = static_cast<float>(x[i]);
-      float a0 = 0.0f, a1 = 0.0f;
-#pragma unroll
-      for (int k = 0; k < kDiskTaps; ++k) {
-        const float d = A.w[sys][k] * (static_cast<float>(x[b[disk_row(k)] + disk_dx(k)]) - xi);
-        if (k & 1) a1 += d;
-        else a0 += d;
-      }
-      return static_cast<double>(a0 + a1) + static_cast<double>(A.crsum[sys] * xi);
-    } else {
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int k = 0; k < kDiskTaps; ++k) {
-        const double d = A.w[sys][k] * static_cast<double>(x[b[disk_row(k)] + disk_dx(k)]);
-        if (k & 1) a1 += d;
-        else a0 += d;
-      }
-      return a0 + a1;
-    }
+    return disk_dot(A, sys, i, b, x);
   }
   const int full = w & ~3;
   const int32_t* nb = A.node_of + p;
@@ -264,6 +274,10 @@ __device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, 
   const int64_t sl = i / kSlice;
   const int64_t base = A.ptr[sl] + (i % kSlice);
   const int w = static_cast<int>((A.ptr[sl + 1] - A.ptr[sl]) / kSlice);
+  if (A.sbase[sys]) {
+    int32_t b[5];
+    if (slice_disk_bases(A.sbase[sys], i, b)) return disk_dot(A, sys, i, b, x);
+  }
   if (A.cpix[sys]) {
     const int32_t p = A.cpix[sys][i];
     if (p >= 0) return canon_dot(A, sys, p, i, w, x);

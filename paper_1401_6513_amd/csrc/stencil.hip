@@ -135,6 +135,39 @@ __global__ void k_count_nonneg(int64_t n, const int32_t* a, int64_t* part) {
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
+// slice s: rows 64 s .. 64 s + 63 all canonical on consecutive pixels of one lattice row
+__global__ void k_slice_bases(int64_t nslices, int64_t n, const int32_t* cpix, const int32_t* node_of, int W,
+                              int32_t* out) {
+  const int64_t s = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (s >= nslices) return;
+  const int64_t i0 = s * kSlice;
+  bool ok = i0 + kSlice <= n;
+  const int32_t p0 = ok ? cpix[i0] : -1;
+  ok = ok && p0 >= 0 && (p0 % W) + kSlice <= W;
+  for (int l = 1; l < kSlice && ok; ++l)
+    if (cpix[i0 + l] != p0 + l) ok = false;
+  int4 d = make_int4(-1, -1, -1, -1);
+  if (ok) d = make_int4(node_of[p0 - 2 * W], node_of[p0 - W], node_of[p0 + W], node_of[p0 + 2 * W]);
+  if (d.x < 0 || d.y < 0 || d.z < 0 || d.w < 0) d = make_int4(-1, -1, -1, -1);
+  reinterpret_cast<int4*>(out)[s] = d;
+}
+
+// per-block counts of a[stride * i] >= 0, i < n
+__global__ void k_count_nonneg_stride(int64_t n, const int32_t* a, int stride, int64_t* part) {
+  __shared__ int64_t s[256];
+  int64_t c = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    c += a[stride * i] >= 0 ? 1 : 0;
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
 struct RowSample {
   int len = 0, bpos = 0, pix = -1;
   std::vector<int32_t> cpix;
@@ -216,6 +249,7 @@ void lattice_free(Lattice& lat) {
 
 void canon_free(Canon& cn) {
   for (auto& p : cn.cpix) dfree(p);
+  for (auto& p : cn.sbase) dfree(p);
   cn.K = 0;
   cn.ref_row = -1;
   for (auto& k : cn.count) k = 0;
@@ -248,6 +282,28 @@ int lattice_map(Ctx* c, bool* ok) {
     }
   }
   if (ok) *ok = L.ok;
+  return VIP_OK;
+}
+
+int slice_bases(Ctx* c, const int32_t* cpix, int64_t n, int32_t** out, int64_t* described) {
+  const int64_t ns = (n + kSlice - 1) / kSlice;
+  if (!*out) VIP_TRY(dalloc(c, out, 4 * ns));
+  k_slice_bases<<<grid_for(ns), kBlock, 0, c->stream>>>(ns, n, cpix, c->lat.node_of, c->lat.W, *out);
+  VIP_HIP_TRY(c, hipGetLastError());
+  if (described) {
+    // described slices: first entries >= 0, counted in fixed block order
+    int64_t* part = nullptr;
+    VIP_TRY(dalloc(c, &part, 256));
+    k_count_nonneg_stride<<<256, 256, 0, c->stream>>>(ns, *out, 4, part);
+    std::vector<int64_t> hp(256);
+    hipError_t e1 = hipMemcpyAsync(hp.data(), part, sizeof(int64_t) * 256, hipMemcpyDeviceToHost, c->stream);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    dfree(part);
+    if (e1 != hipSuccess || e2 != hipSuccess) return set_error(c, VIP_E_HIP, "counting described slices");
+    int64_t cnt = 0;
+    for (int64_t v : hp) cnt += v;
+    *described = cnt * kSlice;
+  }
   return VIP_OK;
 }
 
@@ -353,6 +409,8 @@ int canon_mark(Ctx* c, Ell& e, int vs) {
   int64_t cnt = 0;
   for (int64_t v : hp) cnt += v;
   cn.count[vs] = cnt;
+  cn.described[vs] = 0;
+  if (cn.disk && cnt > 0) VIP_TRY(slice_bases(c, cn.cpix[vs], c->n, &cn.sbase[vs], &cn.described[vs]));
   if (c->debug)
     std::fprintf(stderr, "[vip] canonical rows, value set %d: %lld of %lld (%d taps, reference row %lld)\n", vs,
                  static_cast<long long>(cnt), static_cast<long long>(c->n), cn.K,

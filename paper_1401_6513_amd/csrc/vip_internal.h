@@ -41,6 +41,11 @@ struct Canon {
                                     // per value set (0..3 FP64; 4..6 FP32: pressure, predictor u, v):
                                     // pixel of a canonical row, else -1
   int64_t count[7] = {0, 0, 0, 0, 0, 0, 0};
+  // per 64-row slice and value set (disk taps only): the nodes 2 and 1 rows below and 1 and 2
+  // rows above the slice's first row when all 64 rows are canonical and sit on consecutive
+  // pixels of one lattice row (then row i0 + l reads them + l), else -1 in the first entry
+  int32_t* sbase[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t described[7] = {0, 0, 0, 0, 0, 0, 0};   // rows in described slices, per set
 };
 
 // Sliced ELL matrix: rows grouped by 64; slice s holds width[s] columns stored
@@ -81,6 +86,22 @@ __device__ __forceinline__ void disk_bases(const int32_t* node_of, int32_t p, in
   b[2] = static_cast<int32_t>(i);
   b[3] = node_of[p + W];
   b[4] = node_of[p + 2 * W];
+}
+
+// Nodes of the five lattice rows of row i's disk from its slice's descriptor (wave-uniform
+// scalar load); false when the slice is not described.
+__device__ __forceinline__ bool slice_disk_bases(const int32_t* sbase, int64_t i, int32_t (&b)[5]) {
+  const int32_t sl = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(i >> 6));
+  if ((i >> 6) != sl) return false;
+  const int4 d = *reinterpret_cast<const int4*>(sbase + 4 * static_cast<int64_t>(sl));
+  if (d.x < 0) return false;
+  const int32_t l = static_cast<int32_t>(i & 63);
+  b[0] = d.x + l;
+  b[1] = d.y + l;
+  b[2] = static_cast<int32_t>(i);
+  b[3] = d.z + l;
+  b[4] = d.w + l;
+  return true;
 }
 
 // Lattice image of the node set: pixel (ix, iy) <-> the node at (xmin + ix h, ymin + iy h).
@@ -124,6 +145,8 @@ struct AmgLevel {
   // level 0: canonical rows of the sweeps (canonical values and damped inverse diagonal)
   int32_t* cpix64 = nullptr;
   int32_t* cpix32 = nullptr;
+  int32_t* sbase64 = nullptr;     // slice descriptors of cpix64 / cpix32 (see Canon::sbase)
+  int32_t* sbase32 = nullptr;
   const int32_t* node_of = nullptr;
   int32_t W = 0;                  // lattice image width
   double wdinv_c = 0.0;
@@ -345,6 +368,8 @@ int lattice_map(Ctx* c, bool* ok);
 // Find the reference row of the system layout and mark the canonical rows of value set
 // vs (0..3 FP64; 4..6 FP32 pressure, predictor u, predictor v, with their row sums).
 int canon_mark(Ctx* c, Ell& e, int vs);
+// Slice descriptors (Canon::sbase) of canonical-row pixels cpix [n] into out [4 * ceil(n/64)].
+int slice_bases(Ctx* c, const int32_t* cpix, int64_t n, int32_t** out, int64_t* described = nullptr);
 void canon_free(Canon& cn);
 void lattice_free(Lattice& lat);
 int learn_train(Ctx* c, int iters, int batch, int crop, double lr, uint64_t seed, double* last_loss);

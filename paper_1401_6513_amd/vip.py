@@ -86,7 +86,7 @@ SIGNATURES = {
     "vip_divergence": (_INT, [_P, _P, _P, _P]),
     "vip_gradient": (_INT, [_P, _P, _P, _P]),
     "vip_kernel_timing": (_INT, [_P, _INT, _INT, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
-    "vip_canonical_rows": (_INT, [_P, _P, ctypes.POINTER(_INT)]),
+    "vip_canonical_rows": (_INT, [_P, _P, _P, ctypes.POINTER(_INT)]),
     "vip_learn_n_params": (_INT, []),
     "vip_learn_init": (_INT, [_P, ctypes.c_uint64]),
     "vip_learn_set_params": (_INT, [_P, _P, _I64]),
@@ -265,12 +265,16 @@ class Context:
                                                ctypes.byref(cnt)), "vip_kernel_timing")
         return avg.value, cnt.value
 
-    def vip_canonical_rows(self):
-        """(counts per value set [P64, Hu, Hv, -, P32, Hu32, Hv32], taps of the reference row)."""
+    def vip_canonical_rows(self, described=False):
+        """(counts per value set [P64, Hu, Hv, -, P32, Hu32, Hv32], taps of the reference row),
+        with the rows of described slices per set as a third item if `described`."""
         counts = np.zeros(7, np.int64)
+        desc = np.zeros(7, np.int64)
         taps = _INT()
-        self._check(self.lib.vip_canonical_rows(self._h, counts.ctypes.data, ctypes.byref(taps)),
-                    "vip_canonical_rows")
+        self._check(self.lib.vip_canonical_rows(self._h, counts.ctypes.data, desc.ctypes.data,
+                                                ctypes.byref(taps)), "vip_canonical_rows")
+        if described:
+            return counts, taps.value, desc
         return counts, taps.value
 
     # ---- learned start vector ---------------------------------------------------------

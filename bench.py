@@ -107,6 +107,7 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
     torch.cuda.synchronize()
     if time_spmv:
         ctxs[0].vip_kernel_timing(enable=True, reset=True)
+        ctxs[0].vip_kernel_timing(enable=True, reset=True, which=1)
     stats = []
     dom_s = [0.0] * len(ctxs)
 
@@ -130,11 +131,12 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
             ["%.3g" % s["warm_ratio"] for s in row]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    spmv = None
+    spmv = conv = None
     if time_spmv:
         spmv = ctxs[0].vip_kernel_timing(enable=False)
+        conv = ctxs[0].vip_kernel_timing(enable=False, which=1)
     fields = [[t.cpu().numpy() for t in st] for st in state]
-    return (t1 - t0), stats, spmv, fields, dom_s
+    return (t1 - t0), stats, (spmv, conv), fields, dom_s
 
 
 def cpu_baseline(h, dt, re, budget_s):
@@ -257,10 +259,10 @@ def main():
         from concurrent.futures import ThreadPoolExecutor
         pool = ThreadPoolExecutor(max_workers=len(ctxs))
     for path in paths:
-        el, stats, spmv, fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
+        el, stats, (spmv, conv), fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
                                                   args.steps, args.tol, path == paths[0],
                                                   args.inner_tol, pool)
-        results[path] = dict(seconds=el, stats=stats, spmv=spmv, fields=fields, dom_s=dom_s)
+        results[path] = dict(seconds=el, stats=stats, spmv=spmv, conv=conv, fields=fields, dom_s=dom_s)
         log("%s: %.3f s for %d steps" % (path, el, args.steps))
 
     main_path = paths[0]
@@ -292,6 +294,21 @@ def main():
                 "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms, "launches": count,
                 "rows": n0, "nnz": nnz0, "canonical_rows": nc, "described_rows": nd, "taps": taps,
                 "ell_bytes_per_launch": (vb + 4) * nnz0 + 3 * vb * n0}
+
+    roof_mfma = None
+    if r.get("conv") is not None and r["conv"][1] > 0:
+        sp = specs[0]
+        W = int(np.floor((sp.xy[:, 0].max() - sp.xy[:, 0].min()) / sp.h + 0.5)) + 1
+        H = int(np.floor((sp.xy[:, 1].max() - sp.xy[:, 1].min()) / sp.h + 0.5)) + 1
+        flops = 2.0 * 9 * 32 * 32 * W * H
+        avg_ms, count = r["conv"]
+        tf = flops / (avg_ms * 1e-3) / 1e12
+        roof_mfma = {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": tf / 2500.0, "traffic": None,
+                     "kernel": "k_conv_mid (32->32 3x3 BF16 layer of the learned start vector, "
+                               "v_mfma_f32_16x16x32_bf16)",
+                     "flops_per_launch": flops, "avg_ms": avg_ms, "launches": count,
+                     "image": [H, W]}
 
     out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -335,6 +352,7 @@ def main():
     if train_info:
         out["training"] = train_info
     out["roofline"] = roof
+    out["roofline_mfma"] = roof_mfma
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(h, dt, re, args.cpu_budget)

@@ -309,11 +309,13 @@ int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
  * vip_create, or for node sets that are not lattice based.  Host outputs, may be NULL. */
 int vip_canonical_rows(void* ctx, int64_t* counts, int64_t* described, int* taps);
 
-/* Average duration (ms) of the pressure-solve SpMV kernel (the first SpMV of
- * each Krylov iteration) over the launches since the last reset, measured with
- * HIP events on the context stream while timing is enabled; *count receives the
- * number of timed launches.  enable = 0 stops timing; reset = 1 clears it. */
-int vip_kernel_timing(void* ctx, int enable, int reset, double* avg_ms, int64_t* count);
+/* Average duration (ms) of a kernel over its launches since the last reset, measured with
+ * HIP events on the context stream while timing is enabled; *count receives the number of
+ * timed launches.  which = 0: the pressure-solve SpMV (the first SpMV of each Krylov
+ * iteration; launches after the solve stopped on the device are not counted); which = 1:
+ * each of the two 32 -> 32 MFMA layers of the learned start vector's inference.  enable = 0
+ * stops timing; reset = 1 clears it.  Errors: VIP_E_INVALID (unknown which). */
+int vip_kernel_timing(void* ctx, int which, int enable, int reset, double* avg_ms, int64_t* count);
 
 #ifdef __cplusplus
 }

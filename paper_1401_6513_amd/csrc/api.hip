@@ -189,6 +189,16 @@ int vip_destroy(void* p) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  for (auto* T : {&c->conv_timing}) {
+    for (auto& e : T->pool) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    for (auto& e : T->pending) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  }
   delete c;
   return VIP_OK;
 }
@@ -412,16 +422,18 @@ int vip_gradient(void* p, const double* f, double* gx, double* gy) {
   return vip::gradient(c, f, gx, gy);
 }
 
-int vip_kernel_timing(void* p, int enable, int reset, double* avg_ms, int64_t* count) {
+int vip_kernel_timing(void* p, int which, int enable, int reset, double* avg_ms, int64_t* count) {
   Ctx* c = vip::as_ctx(p);
   if (!c) return VIP_E_INVALID;
+  if (which != 0 && which != 1) return vip::set_error(c, VIP_E_INVALID, "unknown timed kernel");
+  vip::Timing& T = which == 0 ? c->timing : c->conv_timing;
   if (reset) {
-    c->timing.total_ms = 0.0;
-    c->timing.count = 0;
+    T.total_ms = 0.0;
+    T.count = 0;
   }
-  c->timing.enabled = enable != 0;
-  if (avg_ms) *avg_ms = c->timing.count > 0 ? c->timing.total_ms / c->timing.count : 0.0;
-  if (count) *count = c->timing.count;
+  T.enabled = enable != 0;
+  if (avg_ms) *avg_ms = T.count > 0 ? T.total_ms / T.count : 0.0;
+  if (count) *count = T.count;
   return VIP_OK;
 }
 

@@ -108,26 +108,63 @@ __device__ __forceinline__ void mfma_strip(const Img& g, int b, int i, int j0, c
   }
 }
 
-// layers 2 and 3 (32 -> 32) on MFMA; one wave per 16-pixel strip; wt = [tap][co][ci]
-__global__ void k_conv_mid(Img g, const bf16_t* x, const bf16_t* wt, const float* bias, bf16_t* out,
-                           int64_t nstrips) {
-  const int64_t s = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
-  if (s >= nstrips) return;
-  const int strips_w = (g.W + 15) / 16;
-  const int j0 = static_cast<int>(s % strips_w) * 16;
-  const int i = static_cast<int>((s / strips_w) % g.H);
-  const int b = static_cast<int>(s / (static_cast<int64_t>(strips_w) * g.H));
-  f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
-  mfma_strip(g, b, i, j0, x, +1, wt, d0, d1);
+// layers 2 and 3 (32 -> 32) on MFMA, D[co][pixel] = sum over taps W_t[co][ci] x[pixel + d_t][ci]
+// per 16-pixel strip: A = weights (16 output channels x 32 input channels of one tap, held in
+// registers for the whole wave), B = activations (32 channels x 16 pixels, one 16-byte load
+// per lane), two output-channel tiles.  Lane l ends with 4 consecutive output channels of
+// pixel l % 16, stored as one 8-byte write per tile.  Each wave takes kStripsPerWave strips.
+constexpr int kStripsPerWave = 8;
+
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
+  return static_cast<uint32_t>(f2bf(a)) | (static_cast<uint32_t>(f2bf(b)) << 16);
+}
+
+__global__ __launch_bounds__(256) void k_conv_mid(Img g, const bf16_t* x, const bf16_t* wt, const float* bias,
+                                                  bf16_t* out, int64_t nstrips) {
+  const int64_t wv = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
+  const int64_t s0 = wv * kStripsPerWave;
+  if (s0 >= nstrips) return;
   const int l = threadIdx.x & 63;
+  const int kq = (l >> 4) * 8;
   const int n = l & 15;
+  const int cq = (l >> 4) * 4;
+  bf16x8 wa[9][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int j = j0 + (l >> 4) * 4 + r;
-    if (j >= g.W) continue;
-    bf16_t* op = out + ((static_cast<int64_t>(b) * g.H + i) * g.W + j) * kC;
-    op[n] = f2bf(fmaxf(d0[r] + bias[n], 0.0f));
-    op[16 + n] = f2bf(fmaxf(d1[r] + bias[16 + n], 0.0f));
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+      wa[t][m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wt + (t * kC + m * 16 + n) * kC + kq));
+  float bv[2][4];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[m][r] = bias[m * 16 + cq + r];
+  const int strips_w = (g.W + 15) / 16;
+  for (int64_t s = s0; s < s0 + kStripsPerWave && s < nstrips; ++s) {
+    const int j0 = static_cast<int>(s % strips_w) * 16;
+    const int i = static_cast<int>((s / strips_w) % g.H);
+    const int b = static_cast<int>(s / (static_cast<int64_t>(strips_w) * g.H));
+    f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int ii = i + (t / 3 - 1), jj = j0 + n + (t % 3 - 1);
+      uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+      if (inside(g, ii, jj))
+        raw = *reinterpret_cast<const uint4*>(x + ((static_cast<int64_t>(b) * g.H + ii) * g.W + jj) * kC + kq);
+      const bf16x8 xb = __builtin_bit_cast(bf16x8, raw);
+      d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][0], xb, d0, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][1], xb, d1, 0, 0, 0);
+    }
+    const int j = j0 + n;
+    if (j < g.W) {
+      bf16_t* op = out + ((static_cast<int64_t>(b) * g.H + i) * g.W + j) * kC + cq;
+      const uint2 v0 = make_uint2(pack_bf2(fmaxf(d0[0] + bv[0][0], 0.0f), fmaxf(d0[1] + bv[0][1], 0.0f)),
+                                  pack_bf2(fmaxf(d0[2] + bv[0][2], 0.0f), fmaxf(d0[3] + bv[0][3], 0.0f)));
+      const uint2 v1 = make_uint2(pack_bf2(fmaxf(d1[0] + bv[1][0], 0.0f), fmaxf(d1[1] + bv[1][1], 0.0f)),
+                                  pack_bf2(fmaxf(d1[2] + bv[1][2], 0.0f), fmaxf(d1[3] + bv[1][3], 0.0f)));
+      *reinterpret_cast<uint2*>(op) = v0;
+      *reinterpret_cast<uint2*>(op + 16) = v1;
+    }
   }
 }
 
@@ -716,19 +753,56 @@ int pack(Ctx* c) {
 
 int64_t blocks_for(int64_t items) { return (items + kBlock - 1) / kBlock; }
 
-// forward pass over g (input already in N->x); prediction in N->y
-int forward(Ctx* c, const Img& g) {
+// forward pass over g (input already in N->x); prediction in N->y.  timed: HIP events around
+// the two MFMA layers into c->conv_timing (harvested by the caller after a synchronisation).
+int forward(Ctx* c, const Img& g, bool timed = false) {
   Net* N = net_of(c);
   hipStream_t st = c->stream;
   const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
   const int64_t nstrips = static_cast<int64_t>(g.B) * g.H * ((g.W + 15) / 16);
-  const int64_t sblocks = blocks_for(nstrips * 64);
+  const int64_t cwaves = (nstrips + kStripsPerWave - 1) / kStripsPerWave;
+  const int64_t cblocks = blocks_for(cwaves * 64);
+  timed = timed && c->conv_timing.enabled;
   k_conv_in<<<blocks_for(np), kBlock, 0, st>>>(g, N->x, N->w1, N->theta + kB1, N->a1);
-  k_conv_mid<<<sblocks, kBlock, 0, st>>>(g, N->a1, N->w2f, N->theta + kB2, N->a2, nstrips);
-  k_conv_mid<<<sblocks, kBlock, 0, st>>>(g, N->a2, N->w3f, N->theta + kB3, N->a3, nstrips);
+  for (int layer = 0; layer < 2; ++layer) {
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    if (timed) {
+      if (c->conv_timing.pool.empty()) {
+        hipEvent_t a, b;
+        VIP_HIP_TRY(c, hipEventCreate(&a));
+        VIP_HIP_TRY(c, hipEventCreate(&b));
+        c->conv_timing.pool.push_back({a, b});
+      }
+      ev = c->conv_timing.pool.back();
+      c->conv_timing.pool.pop_back();
+      VIP_HIP_TRY(c, hipEventRecord(ev.first, st));
+    }
+    if (layer == 0)
+      k_conv_mid<<<cblocks, kBlock, 0, st>>>(g, N->a1, N->w2f, N->theta + kB2, N->a2, nstrips);
+    else
+      k_conv_mid<<<cblocks, kBlock, 0, st>>>(g, N->a2, N->w3f, N->theta + kB3, N->a3, nstrips);
+    if (timed) {
+      VIP_HIP_TRY(c, hipEventRecord(ev.second, st));
+      c->conv_timing.pending.push_back(ev);
+    }
+  }
   k_conv_out<<<blocks_for(np), kBlock, 0, st>>>(g, N->a3, N->w4, N->theta + kB4, N->y);
   VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;
+}
+
+// add the finished MFMA-layer timings (call after the stream has synchronised)
+void harvest_conv_timing(Ctx* c) {
+  Timing& T = c->conv_timing;
+  for (auto& e : T.pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+      T.total_ms += ms;
+      T.count += 1;
+    }
+    T.pool.push_back(e);
+  }
+  T.pending.clear();
 }
 
 // loss and gradient (targets and mask in N->t, N->mask); gradient in N->grad, loss in N->dscal[0]
@@ -739,9 +813,9 @@ int backward(Ctx* c, const Img& g) {
   const int64_t nstrips = static_cast<int64_t>(g.B) * g.H * ((g.W + 15) / 16);
   const int64_t sblocks = blocks_for(nstrips * 64);
   const int lblocks = kSumBlocks;
-  const int64_t thin_chunk = 1024;
+  const int64_t thin_chunk = 128;        // pixels per block of the thin layers' gradients
   const int64_t thin_blocks = (np + thin_chunk - 1) / thin_chunk;
-  const int64_t wave_chunk = 32 * 32;   // pixels per wave in the MFMA weight gradient
+  const int64_t wave_chunk = 128;        // pixels per wave in the MFMA weight gradient
   const int64_t waves = (np + wave_chunk - 1) / wave_chunk;
   const int64_t wblocks = (waves * 64 + kBlock - 1) / kBlock;
   const int64_t mid_part = wblocks * 4 * 9 * kC * kC;
@@ -959,7 +1033,7 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
     VIP_TRY(net_buffers(c, npix));
     VIP_TRY(lattice_rms(c, L.rx, b));
     k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.rx, b, L.scal, h2, N->x);
-    VIP_TRY(forward(c, Img{1, c->lat.H, c->lat.W}));
+    VIP_TRY(forward(c, Img{1, c->lat.H, c->lat.W}, true));
     k_direction<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, c->lat.pix, N->y, L.scal, h2, L.dir);
     VIP_TRY(ell_apply(c, c->sys, 0, L.dir, L.q2));
   }
@@ -969,6 +1043,7 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
   double s[8];
   VIP_HIP_TRY(c, hipMemcpyAsync(s, L.scal, sizeof(s), hipMemcpyDeviceToHost, st));
   VIP_HIP_TRY(c, hipStreamSynchronize(st));
+  harvest_conv_timing(c);
   // minimise ||r - alpha q1 - beta q2||_2: normal equations of the 2 x 2 (or 1 x 1) problem
   const double a11 = s[2], a12 = s[3], a22 = s[4], g1 = s[5], g2 = s[6], rr = s[7];
   double alpha = 0.0, beta = 0.0;

@@ -266,7 +266,8 @@ struct Ctx {
   Lattice lat;
   Amg amg;
   Learn learn;
-  Timing timing;
+  Timing timing;                  // pressure-solve SpMV launches
+  Timing conv_timing;             // MFMA layers of the learned start vector's inference
 };
 
 // ---- error handling -----------------------------------------------------------

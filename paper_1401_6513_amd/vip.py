@@ -85,7 +85,7 @@ SIGNATURES = {
     "vip_convection": (_INT, [_P, _P, _P, _P, _P]),
     "vip_divergence": (_INT, [_P, _P, _P, _P]),
     "vip_gradient": (_INT, [_P, _P, _P, _P]),
-    "vip_kernel_timing": (_INT, [_P, _INT, _INT, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    "vip_kernel_timing": (_INT, [_P, _INT, _INT, _INT, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "vip_canonical_rows": (_INT, [_P, _P, _P, ctypes.POINTER(_INT)]),
     "vip_learn_n_params": (_INT, []),
     "vip_learn_init": (_INT, [_P, ctypes.c_uint64]),
@@ -258,11 +258,13 @@ class Context:
     def vip_gradient(self, f, gx, gy):
         self._check(self.lib.vip_gradient(self._h, _dev(f), _dev(gx), _dev(gy)), "vip_gradient")
 
-    def vip_kernel_timing(self, enable=True, reset=False):
+    def vip_kernel_timing(self, enable=True, reset=False, which=0):
+        """(average ms, launches) of kernel `which` (0 pressure SpMV, 1 CNN MFMA layer)."""
         avg = _D()
         cnt = _I64()
-        self._check(self.lib.vip_kernel_timing(self._h, int(enable), int(reset), ctypes.byref(avg),
-                                               ctypes.byref(cnt)), "vip_kernel_timing")
+        self._check(self.lib.vip_kernel_timing(self._h, int(which), int(enable), int(reset),
+                                               ctypes.byref(avg), ctypes.byref(cnt)),
+                    "vip_kernel_timing")
         return avg.value, cnt.value
 
     def vip_canonical_rows(self, described=False):

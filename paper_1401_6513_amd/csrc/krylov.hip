@@ -1245,6 +1245,22 @@ __global__ void k_apply(int64_t nrows, const int64_t* ptr, const int32_t* cols, 
   y[i] = acc;
 }
 
+// y = P x for the FP64 pressure matrix (canonical rows included), one thread per row.
+__global__ void k_sys_apply(Mat<double> A, const double* x, double* y) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= A.n) return;
+  y[i] = row_dot(A, 0, i, x);
+}
+
+int pressure_apply(Ctx* c, const double* x, double* y) {
+  Mat<double> A{c->n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}, {nullptr, nullptr}};
+  attach_canon(c, A, 0, -1);
+  VIP_TRY(check_mat(c, A, 1));
+  k_sys_apply<<<grid_for(c->n), kBlock, 0, c->stream>>>(A, x, y);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
 int ell_apply(Ctx* c, const Ell& e, int vs, const double* x, double* y) {
   if (e.nrows == 0) return VIP_OK;
   k_apply<<<grid_for(e.nrows), kBlock, 0, c->stream>>>(e.nrows, e.ptr, e.cols, e.val[vs], x, y);

@@ -895,7 +895,7 @@ int ensure_vectors(Ctx* c) {
 // q1 = L eprev and rx = r - q1
 int extrapolation_residual(Ctx* c) {
   Learn& L = c->learn;
-  VIP_TRY(ell_apply(c, c->sys, 0, L.eprev, L.q1));
+  VIP_TRY(pressure_apply(c, L.eprev, L.q1));
   k_sub<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, L.r, L.q1, L.rx);
   VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;
@@ -1012,7 +1012,7 @@ int learn_prepare(Ctx* c, const double* b, const double* phi, bool with_map) {
   if (with_map) VIP_TRY(learn_map(c));
   VIP_TRY(ensure_vectors(c));
   k_copy_d<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, phi, L.phi_prev);
-  VIP_TRY(ell_apply(c, c->sys, 0, L.phi_prev, L.q1));
+  VIP_TRY(pressure_apply(c, L.phi_prev, L.q1));
   k_sub<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, b, L.q1, L.r);
   VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;
@@ -1035,7 +1035,7 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
     k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.rx, b, L.scal, h2, N->x);
     VIP_TRY(forward(c, Img{1, c->lat.H, c->lat.W}, true));
     k_direction<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, c->lat.pix, N->y, L.scal, h2, L.dir);
-    VIP_TRY(ell_apply(c, c->sys, 0, L.dir, L.q2));
+    VIP_TRY(pressure_apply(c, L.dir, L.q2));
   }
   k_dots6_part<<<kSumBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, L.r, L.scal + kScalHead);
   k_dots6_finish<<<1, 64, 0, st>>>(kSumBlocks, L.scal + kScalHead, L.scal);

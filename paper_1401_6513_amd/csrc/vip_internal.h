@@ -339,6 +339,8 @@ int ensure_partials(Ctx* c, int64_t blocks, int per);
 
 // Sliced-ELL SpMV y = A x on value set `vs` (FP64), used by tests and helpers.
 int ell_apply(Ctx* c, const Ell& e, int vs, const double* x, double* y);
+// y = P x with the FP64 pressure matrix through the canonical-row path (no border).
+int pressure_apply(Ctx* c, const double* x, double* y);
 
 // Solvers (krylov.hip)
 int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x0,

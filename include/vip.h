@@ -300,7 +300,9 @@ int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
 
 /* Rows of the system layout that are translation-invariant lattice-interior copies of one
  * reference row (same lattice offsets, bitwise equal values), per value set (host counts[7]):
- * [0] FP64 pressure matrix, [1] predictor matrix of u, [2] of v, [3] unused, [4] FP32 pressure
+ * [0] FP64 pressure matrix, [1] predictor matrix of u, [2] of v, [3] nodes whose rows of the
+ * four VIP operators, D^[0,0] and the Laplacian are all canonical (the per-step products of
+ * eqs. 12-15 and the convection, divergence and gradient entry points), [4] FP32 pressure
  * matrix, [5] FP32 predictor matrix of u, [6] of v (the FP32 sets with their row sums);
  * described[7]: rows of 64-row slices whose rows are all canonical on consecutive pixels of
  * one lattice row (their kernels read one descriptor per slice instead of per-row data);

@@ -68,6 +68,7 @@ void ctx_free_build(Ctx* c) {
   c->have_prev_n = false;
   c->have_prev_phi = false;
   learn_free_nodeset(c);
+  vip_canon_free(c);
   lattice_free(c->lat);
   for (auto& h : c->hint_p64) h = 0;
   for (auto& h : c->hint_p32) h = 0;
@@ -442,7 +443,7 @@ int vip_canonical_rows(void* p, int64_t* counts, int64_t* described, int* taps) 
   VIP_TRY(vip::need_built(c));
   const vip::Canon& cn = c->sys.canon;
   if (counts)
-    for (int k = 0; k < 7; ++k) counts[k] = c->no_canon ? 0 : cn.count[k];
+    for (int k = 0; k < 7; ++k) counts[k] = c->no_canon ? 0 : k == 3 ? c->vcanon.count : cn.count[k];
   if (described)
     for (int k = 0; k < 7; ++k) described[k] = c->no_canon ? 0 : cn.described[k];
   if (taps) *taps = cn.K;

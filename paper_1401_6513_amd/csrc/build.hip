@@ -998,6 +998,8 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   // lattice-interior rows of the pressure matrix (FP64 and FP32 value sets)
   VIP_TRY(canon_mark(c, s, 0));
   VIP_TRY(canon_mark(c, s, 4));
+  // lattice-interior rows of the per-step VIP and node products
+  VIP_TRY(vip_canon_setup(c));
   c->built = true;
   return VIP_OK;
 }

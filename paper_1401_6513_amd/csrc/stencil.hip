@@ -168,6 +168,35 @@ __global__ void k_count_nonneg_stride(int64_t n, const int32_t* a, int stride, i
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
+// out[i] = a0[i] if rows i of all six operators are canonical (they then share the pixel)
+__global__ void k_vc_combine(int64_t n, const int32_t* a0, const int32_t* a1, const int32_t* a2,
+                             const int32_t* a3, const int32_t* a4, const int32_t* a5, int32_t* out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int32_t p = a0[i];
+  const bool ok = p >= 0 && a1[i] == p && a2[i] == p && a3[i] == p && a4[i] == p && a5[i] == p;
+  out[i] = ok ? p : -1;
+}
+
+// Runs of one reference row: stencil rows in increasing dy, consecutive dx within a row.
+bool vc_runs(const Canon& cn, int8_t (&dx0)[kVcRows], int8_t (&len)[kVcRows]) {
+  for (int d = 0; d < kVcRows; ++d) dx0[d] = len[d] = 0;
+  int last = -1;
+  for (int k = 0; k < cn.K; ++k) {
+    const int d = cn.dy[k] + 3;
+    if (d < 0 || d >= kVcRows || d < last || cn.dx[k] < -64 || cn.dx[k] > 63) return false;
+    if (d != last) {
+      if (len[d] != 0) return false;
+      dx0[d] = static_cast<int8_t>(cn.dx[k]);
+    } else if (cn.dx[k] != dx0[d] + len[d]) {
+      return false;
+    }
+    len[d] = static_cast<int8_t>(len[d] + 1);
+    last = d;
+  }
+  return cn.K > 0;
+}
+
 struct RowSample {
   int len = 0, bpos = 0, pix = -1;
   std::vector<int32_t> cpix;
@@ -415,6 +444,57 @@ int canon_mark(Ctx* c, Ell& e, int vs) {
     std::fprintf(stderr, "[vip] canonical rows, value set %d: %lld of %lld (%d taps, reference row %lld)\n", vs,
                  static_cast<long long>(cnt), static_cast<long long>(c->n), cn.K,
                  static_cast<long long>(cn.ref_row));
+  return VIP_OK;
+}
+
+void vip_canon_free(Ctx* c) {
+  dfree(c->vcanon.cpix);
+  c->vcanon = VipCanon();
+}
+
+int vip_canon_setup(Ctx* c) {
+  vip_canon_free(c);
+  VipCanon& V = c->vcanon;
+  if (c->no_canon || c->n == 0) return VIP_OK;
+  Ell* ops[kVcOps] = {&c->vipop[0], &c->vipop[1], &c->vipop[2], &c->vipop[3], &c->node};
+  for (int o = 0; o < kVcOps; ++o) VIP_TRY(canon_mark(c, *ops[o], 0));
+  VIP_TRY(canon_mark(c, c->node, 1));
+  bool ok = true;
+  for (int o = 0; o < kVcOps && ok; ++o) {
+    const Canon& cn = ops[o]->canon;
+    ok = cn.ref_row >= 0 && cn.cpix[0] && cn.count[0] > 0 && vc_runs(cn, V.dx0[o], V.len[o]);
+    if (ok)
+      for (int k = 0; k < cn.K; ++k) V.w[o][k] = cn.w[0][k];
+  }
+  ok = ok && c->node.canon.cpix[1] && c->node.canon.count[1] > 0;
+  if (ok) {
+    for (int k = 0; k < c->node.canon.K; ++k) V.w[kVcOps][k] = c->node.canon.w[1][k];
+    for (int d = 0; d < kVcRows; ++d) {
+      V.used[d] = 0;
+      for (int o = 0; o < kVcOps; ++o) V.used[d] |= V.len[o][d] > 0 ? 1 : 0;
+    }
+    VIP_TRY(dalloc(c, &V.cpix, c->n));
+    k_vc_combine<<<grid_for(c->n), kBlock, 0, c->stream>>>(
+        c->n, ops[0]->canon.cpix[0], ops[1]->canon.cpix[0], ops[2]->canon.cpix[0], ops[3]->canon.cpix[0],
+        c->node.canon.cpix[0], c->node.canon.cpix[1], V.cpix);
+    VIP_HIP_TRY(c, hipGetLastError());
+    int64_t* part = nullptr;
+    VIP_TRY(dalloc(c, &part, 256));
+    k_count_nonneg<<<256, 256, 0, c->stream>>>(c->n, V.cpix, part);
+    std::vector<int64_t> hp(256);
+    hipError_t e1 = hipMemcpyAsync(hp.data(), part, sizeof(int64_t) * 256, hipMemcpyDeviceToHost, c->stream);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    dfree(part);
+    if (e1 != hipSuccess || e2 != hipSuccess) return set_error(c, VIP_E_HIP, "counting canonical VIP rows");
+    V.count = 0;
+    for (int64_t v : hp) V.count += v;
+  }
+  // the per-operator marks are folded into V.cpix
+  for (int o = 0; o < kVcOps; ++o) canon_free(ops[o]->canon);
+  if (V.count == 0) vip_canon_free(c);
+  if (c->debug)
+    std::fprintf(stderr, "[vip] canonical VIP/node rows: %lld of %lld\n", static_cast<long long>(c->vcanon.count),
+                 static_cast<long long>(c->n));
   return VIP_OK;
 }
 

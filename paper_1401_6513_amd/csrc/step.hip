@@ -54,14 +54,130 @@ struct Vips {
   const double* d_ns;
 };
 
+// Canonical nodes (all six per-step rows lattice-interior): the reference weights and the
+// lattice map replace the column and value streams.  Sums run in slot order, as in row1/row2,
+// so both paths give the same bits.
+struct VC {
+  const int32_t* cpix;              // nullptr: every node takes the sliced-ELL path
+  const int32_t* node_of;
+  int W;
+  int8_t dx0[kVcOps][kVcRows];
+  int8_t len[kVcOps][kVcRows];
+  uint8_t used[kVcRows];
+  double w[kVcOps + 1][kMaxTaps];
+};
+
+// Row products of node i from the sliced ELL.
+struct EllRows {
+  const Vips& V;
+  const Op& lap;
+  int64_t i;
+  __device__ __forceinline__ double vip(int o, const double* f) const { return row1(V.op[o], i, f); }
+  __device__ __forceinline__ void vip2(int o, const double* f, const double* g, double* a, double* b) const {
+    row2(V.op[o], i, f, g, a, b);
+  }
+  __device__ __forceinline__ double laplacian(const double* f) const { return row1(lap, i, f); }
+  // (D^[0,0] + c Delta) applied to u and v (D^[0,0] replaced by I when exact_id)
+  __device__ __forceinline__ void helm2(const Op& m00, const int32_t* rowlen, int exact_id, double c,
+                                        const double* u, const double* v, double* au, double* av) const {
+    const int64_t sl = i / kSlice;
+    const int64_t base = m00.ptr[sl] + (i % kSlice);
+    const int w = rowlen[i];   // padding slots hold column 0 and must not meet the identity test
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < w; ++t) {
+      const int64_t q = base + static_cast<int64_t>(t) * kSlice;
+      const int32_t j = m00.cols[q];
+      const double id = exact_id ? (j == static_cast<int32_t>(i) ? 1.0 : 0.0) : m00.val[q];
+      const double r = id + c * lap.val[q];
+      a += r * u[j];
+      b += r * v[j];
+    }
+    *au = a;
+    *av = b;
+  }
+};
+
+// Row products of a canonical node: taps rb[d] + dx0 .. + len - 1 per stencil row d.
+struct CanonRows {
+  const VC& C;
+  int32_t rb[kVcRows];
+  __device__ __forceinline__ CanonRows(const VC& c, int32_t p, int64_t i) : C(c) {
+#pragma unroll
+    for (int d = 0; d < kVcRows; ++d)
+      rb[d] = d == 3 ? static_cast<int32_t>(i) : (C.used[d] ? C.node_of[p + (d - 3) * C.W] : 0);
+  }
+  __device__ __forceinline__ double vip(int o, const double* f) const {
+    double a = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < kVcRows; ++d) {
+      const int L = C.len[o][d];
+      const double* fr = f + rb[d] + C.dx0[o][d];
+      for (int t = 0; t < L; ++t) a += C.w[o][k + t] * fr[t];
+      k += L;
+    }
+    return a;
+  }
+  __device__ __forceinline__ void vip2(int o, const double* f, const double* g, double* pa, double* pb) const {
+    double a = 0.0, b = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < kVcRows; ++d) {
+      const int L = C.len[o][d];
+      const int32_t j0 = rb[d] + C.dx0[o][d];
+      for (int t = 0; t < L; ++t) {
+        const double w = C.w[o][k + t];
+        a += w * f[j0 + t];
+        b += w * g[j0 + t];
+      }
+      k += L;
+    }
+    *pa = a;
+    *pb = b;
+  }
+  __device__ __forceinline__ double laplacian(const double* f) const {
+    double a = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < kVcRows; ++d) {
+      const int L = C.len[4][d];
+      const double* fr = f + rb[d] + C.dx0[4][d];
+      for (int t = 0; t < L; ++t) a += C.w[kVcOps][k + t] * fr[t];
+      k += L;
+    }
+    return a;
+  }
+  __device__ __forceinline__ void helm2(const Op&, const int32_t*, int exact_id, double c, const double* u,
+                                        const double* v, double* au, double* av) const {
+    double a = 0.0, b = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < kVcRows; ++d) {
+      const int L = C.len[4][d];
+      const int dx0 = C.dx0[4][d];
+      const int32_t j0 = rb[d] + dx0;
+      for (int t = 0; t < L; ++t) {
+        const double id = exact_id ? (d == 3 && dx0 + t == 0 ? 1.0 : 0.0) : C.w[4][k + t];
+        const double r = id + c * C.w[kVcOps][k + t];
+        a += r * u[j0 + t];
+        b += r * v[j0 + t];
+      }
+      k += L;
+    }
+    *au = a;
+    *av = b;
+  }
+};
+
 // Convection flux of Section 4.1 item 1 at interior node i.
-__device__ __forceinline__ void flux(const Vips& V, int64_t i, const double* u, const double* v,
+template <class R>
+__device__ __forceinline__ void flux(const R& rows, const Vips& V, int64_t i, const double* u, const double* v,
                                      double* nx, double* ny) {
   double ue, ve, uw, vw, un, vn, us, vs;
-  row2(V.op[0], i, u, v, &ue, &ve);
-  row2(V.op[1], i, u, v, &uw, &vw);
-  row2(V.op[2], i, u, v, &un, &vn);
-  row2(V.op[3], i, u, v, &us, &vs);
+  rows.vip2(0, u, v, &ue, &ve);
+  rows.vip2(1, u, v, &uw, &vw);
+  rows.vip2(2, u, v, &un, &vn);
+  rows.vip2(3, u, v, &us, &vs);
   const double dew = V.d_ew[i], dns = V.d_ns[i];
   *nx = (ue * ue - uw * uw) / dew + (un * vn - us * vs) / dns;
   *ny = (ue * ve - uw * vw) / dew + (vn * vn - vs * vs) / dns;
@@ -76,9 +192,28 @@ struct Bnd {
   double two_d;        // 2 * vip_offset * h (scale of the Neumann rows)
 };
 
+template <class R>
+__device__ __forceinline__ void predictor_interior(const R& rows, int64_t n, int64_t i, const Op& m00,
+                                                   const int32_t* rowlen, const Vips& V, const double* u,
+                                                   const double* v, double* nprev, int first, double dt,
+                                                   double re, int exact_id, double* ru, double* rv) {
+  double nx, ny;
+  flux(rows, V, i, u, v, &nx, &ny);
+  const double px = first ? nx : nprev[i];
+  const double py = first ? ny : nprev[n + i];
+  nprev[i] = nx;
+  nprev[n + i] = ny;
+  const double cx = 1.5 * nx - 0.5 * px;
+  const double cy = 1.5 * ny - 0.5 * py;
+  double au, av;
+  rows.helm2(m00, rowlen, exact_id, dt / (2.0 * re), u, v, &au, &av);
+  ru[i] = au - dt * cx;
+  rv[i] = av - dt * cy;
+}
+
 // Right-hand sides of the two predictor systems (eq. 12 multiplied by dt).
-__global__ void k_predictor_rhs(int64_t n, Op m00, Op lap, Vips V, Bnd B, const double* u,
-                                const double* v, const double* p, double* nprev, int first,
+__global__ void k_predictor_rhs(int64_t n, Op m00, Op lap, const int32_t* rowlen, Vips V, VC C, Bnd B,
+                                const double* u, const double* v, const double* p, double* nprev, int first,
                                 double dt, double re, int exact_id, double* ru, double* rv) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
@@ -95,34 +230,23 @@ __global__ void k_predictor_rhs(int64_t n, Op m00, Op lap, Vips V, Bnd B, const 
     rv[i] = v_held ? B.val[2 * k + 1] : out * B.ny[k];
     return;
   }
-  double nx, ny;
-  flux(V, i, u, v, &nx, &ny);
-  const double px = first ? nx : nprev[i];
-  const double py = first ? ny : nprev[n + i];
-  nprev[i] = nx;
-  nprev[n + i] = ny;
-  const double cx = 1.5 * nx - 0.5 * px;
-  const double cy = 1.5 * ny - 0.5 * py;
-  const double c = dt / (2.0 * re);
-  // (I + c Delta) u with I = D^[0,0] (or the identity), sharing the column reads
-  const int64_t sl = i / kSlice;
-  const int64_t base = m00.ptr[sl] + (i % kSlice);
-  const int64_t w = (m00.ptr[sl + 1] - m00.ptr[sl]) / kSlice;
-  double au = 0.0, av = 0.0;
-  for (int64_t t = 0; t < w; ++t) {
-    const int64_t q = base + t * kSlice;
-    const int32_t j = m00.cols[q];
-    const double id = exact_id ? (j == static_cast<int32_t>(i) ? 1.0 : 0.0) : m00.val[q];
-    const double r = id + c * lap.val[q];
-    au += r * u[j];
-    av += r * v[j];
-  }
-  ru[i] = au - dt * cx;
-  rv[i] = av - dt * cy;
+  const int32_t cp = C.cpix ? C.cpix[i] : -1;
+  if (cp >= 0)
+    predictor_interior(CanonRows(C, cp, i), n, i, m00, rowlen, V, u, v, nprev, first, dt, re, exact_id, ru, rv);
+  else
+    predictor_interior(EllRows{V, lap, i}, n, i, m00, rowlen, V, u, v, nprev, first, dt, re, exact_id, ru, rv);
+}
+
+template <class R>
+__device__ __forceinline__ double divergence_at(const R& rows, const Vips& V, int64_t i, const double* u,
+                                                const double* v) {
+  const double ue = rows.vip(0, u), uw = rows.vip(1, u);
+  const double vn = rows.vip(2, v), vs = rows.vip(3, v);
+  return (ue - uw) / V.d_ew[i] + (vn - vs) / V.d_ns[i];
 }
 
 // b = div(u*) / dt at interior nodes, 0 on boundary rows (eq. 13).
-__global__ void k_divergence(int64_t n, Vips V, const int32_t* bpos, const double* u, const double* v,
+__global__ void k_divergence(int64_t n, Vips V, VC C, const int32_t* bpos, const double* u, const double* v,
                              double scale, double* b) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
@@ -130,31 +254,45 @@ __global__ void k_divergence(int64_t n, Vips V, const int32_t* bpos, const doubl
     b[i] = 0.0;
     return;
   }
-  const double ue = row1(V.op[0], i, u), uw = row1(V.op[1], i, u);
-  const double vn = row1(V.op[2], i, v), vs = row1(V.op[3], i, v);
-  b[i] = ((ue - uw) / V.d_ew[i] + (vn - vs) / V.d_ns[i]) * scale;
+  const Op lap{nullptr, nullptr, nullptr};
+  const int32_t cp = C.cpix ? C.cpix[i] : -1;
+  const double d = cp >= 0 ? divergence_at(CanonRows(C, cp, i), V, i, u, v)
+                           : divergence_at(EllRows{V, lap, i}, V, i, u, v);
+  b[i] = d * scale;
+}
+
+template <class R>
+__device__ __forceinline__ void project_at(const R& rows, const Vips& V, int64_t i, bool interior,
+                                           const double* us, const double* vs, const double* phi, double dt,
+                                           double c, double* u, double* v, double* p) {
+  if (interior) {
+    const double pe = rows.vip(0, phi), pw = rows.vip(1, phi);
+    const double pn = rows.vip(2, phi), ps = rows.vip(3, phi);
+    u[i] = us[i] - dt * ((pe - pw) / V.d_ew[i]);
+    v[i] = vs[i] - dt * ((pn - ps) / V.d_ns[i]);
+  } else {
+    u[i] = us[i];
+    v[i] = vs[i];
+  }
+  p[i] = phi[i] - c * rows.laplacian(phi);
 }
 
 // u = u* - dt grad phi at interior nodes (u = u* on boundary nodes), eq. 14;
 // p = phi - (dt / 2 Re) Delta phi, eq. 15.
-__global__ void k_project(int64_t n, Vips V, Op lap, const int32_t* bpos, const double* us,
+__global__ void k_project(int64_t n, Vips V, VC C, Op lap, const int32_t* bpos, const double* us,
                           const double* vs, const double* phi, double dt, double c, double* u,
                           double* v, double* p) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
-  if (bpos[i] >= 0) {
-    u[i] = us[i];
-    v[i] = vs[i];
-  } else {
-    const double pe = row1(V.op[0], i, phi), pw = row1(V.op[1], i, phi);
-    const double pn = row1(V.op[2], i, phi), ps = row1(V.op[3], i, phi);
-    u[i] = us[i] - dt * ((pe - pw) / V.d_ew[i]);
-    v[i] = vs[i] - dt * ((pn - ps) / V.d_ns[i]);
-  }
-  p[i] = phi[i] - c * row1(lap, i, phi);
+  const bool interior = bpos[i] < 0;
+  const int32_t cp = interior && C.cpix ? C.cpix[i] : -1;
+  if (cp >= 0)
+    project_at(CanonRows(C, cp, i), V, i, true, us, vs, phi, dt, c, u, v, p);
+  else
+    project_at(EllRows{V, lap, i}, V, i, interior, us, vs, phi, dt, c, u, v, p);
 }
 
-__global__ void k_flux_only(int64_t n, Vips V, const int32_t* bpos, const double* u, const double* v,
+__global__ void k_flux_only(int64_t n, Vips V, VC C, const int32_t* bpos, const double* u, const double* v,
                             double* nx, double* ny) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
@@ -163,10 +301,22 @@ __global__ void k_flux_only(int64_t n, Vips V, const int32_t* bpos, const double
     ny[i] = 0.0;
     return;
   }
-  flux(V, i, u, v, &nx[i], &ny[i]);
+  const Op lap{nullptr, nullptr, nullptr};
+  const int32_t cp = C.cpix ? C.cpix[i] : -1;
+  if (cp >= 0)
+    flux(CanonRows(C, cp, i), V, i, u, v, &nx[i], &ny[i]);
+  else
+    flux(EllRows{V, lap, i}, V, i, u, v, &nx[i], &ny[i]);
 }
 
-__global__ void k_gradient(int64_t n, Vips V, const int32_t* bpos, const double* f, double* gx,
+template <class R>
+__device__ __forceinline__ void gradient_at(const R& rows, const Vips& V, int64_t i, const double* f, double* gx,
+                                            double* gy) {
+  gx[i] = (rows.vip(0, f) - rows.vip(1, f)) / V.d_ew[i];
+  gy[i] = (rows.vip(2, f) - rows.vip(3, f)) / V.d_ns[i];
+}
+
+__global__ void k_gradient(int64_t n, Vips V, VC C, const int32_t* bpos, const double* f, double* gx,
                            double* gy) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
@@ -175,8 +325,29 @@ __global__ void k_gradient(int64_t n, Vips V, const int32_t* bpos, const double*
     gy[i] = 0.0;
     return;
   }
-  gx[i] = (row1(V.op[0], i, f) - row1(V.op[1], i, f)) / V.d_ew[i];
-  gy[i] = (row1(V.op[2], i, f) - row1(V.op[3], i, f)) / V.d_ns[i];
+  const Op lap{nullptr, nullptr, nullptr};
+  const int32_t cp = C.cpix ? C.cpix[i] : -1;
+  if (cp >= 0)
+    gradient_at(CanonRows(C, cp, i), V, i, f, gx, gy);
+  else
+    gradient_at(EllRows{V, lap, i}, V, i, f, gx, gy);
+}
+
+VC vc_of(const Ctx* c) {
+  VC C{};
+  const VipCanon& S = c->vcanon;
+  C.cpix = c->no_canon || S.count == 0 ? nullptr : S.cpix;
+  C.node_of = c->lat.node_of;
+  C.W = c->lat.W;
+  for (int o = 0; o < kVcOps; ++o)
+    for (int d = 0; d < kVcRows; ++d) {
+      C.dx0[o][d] = S.dx0[o][d];
+      C.len[o][d] = S.len[o][d];
+    }
+  for (int d = 0; d < kVcRows; ++d) C.used[d] = S.used[d];
+  for (int o = 0; o <= kVcOps; ++o)
+    for (int k = 0; k < kMaxTaps; ++k) C.w[o][k] = S.w[o][k];
+  return C;
 }
 
 Vips vips_of(Ctx* c) {
@@ -209,13 +380,14 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   const Op m00{c->node.ptr, c->node.cols, c->node.val[0]};
   const Op lap{c->node.ptr, c->node.cols, c->node.val[1]};
   const Bnd B{c->bpos, c->bkind, c->bnx, c->bny, c->bval, 2.0 * c->opt.vip_offset * c->h};
-  k_predictor_rhs<<<grid_for(n), kBlock, 0, s>>>(n, m00, lap, V, B, u, v, p, c->nprev,
+  const VC C = vc_of(c);
+  k_predictor_rhs<<<grid_for(n), kBlock, 0, s>>>(n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
                                                   c->have_prev_n ? 0 : 1, dt, re,
                                                   c->opt.identity == VIP_I_EXACT ? 1 : 0, ru, rv);
   VIP_HIP_TRY(c, hipGetLastError());
   int rc_h = helmholtz_solve(c, ru, rv, us, vs, st);
   if (rc_h != VIP_OK && rc_h != VIP_E_NOT_CONVERGED) return rc_h;
-  k_divergence<<<grid_for(n), kBlock, 0, s>>>(n, V, c->bpos, us, vs, 1.0 / dt, b);
+  k_divergence<<<grid_for(n), kBlock, 0, s>>>(n, V, C, c->bpos, us, vs, 1.0 / dt, b);
   VIP_HIP_TRY(c, hipGetLastError());
   const int ws = c->opt.warmstart;
   const bool warm = ws != VIP_WS_ZERO && c->have_prev_phi;
@@ -237,7 +409,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   } else {
     c->learn.have_eprev = false;   // the chain of increments is not followed
   }
-  k_project<<<grid_for(n), kBlock, 0, s>>>(n, V, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
+  k_project<<<grid_for(n), kBlock, 0, s>>>(n, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
                                             v, p);
   VIP_HIP_TRY(c, hipGetLastError());
   VIP_HIP_TRY(c, hipStreamSynchronize(s));
@@ -248,21 +420,21 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
 }
 
 int convection(Ctx* c, const double* u, const double* v, double* nx, double* ny) {
-  k_flux_only<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), c->bpos, u, v, nx, ny);
+  k_flux_only<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), vc_of(c), c->bpos, u, v, nx, ny);
   VIP_HIP_TRY(c, hipGetLastError());
   VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
   return VIP_OK;
 }
 
 int divergence(Ctx* c, const double* u, const double* v, double* d) {
-  k_divergence<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), c->bpos, u, v, 1.0, d);
+  k_divergence<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), vc_of(c), c->bpos, u, v, 1.0, d);
   VIP_HIP_TRY(c, hipGetLastError());
   VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
   return VIP_OK;
 }
 
 int gradient(Ctx* c, const double* f, double* gx, double* gy) {
-  k_gradient<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), c->bpos, f, gx, gy);
+  k_gradient<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), vc_of(c), c->bpos, f, gx, gy);
   VIP_HIP_TRY(c, hipGetLastError());
   VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
   return VIP_OK;

@@ -51,6 +51,22 @@ struct Canon {
 // Sliced ELL matrix: rows grouped by 64; slice s holds width[s] columns stored
 // column-major, element (row r, slot k) at ptr[s] + k*64 + (r - 64 s).
 // Padding slots carry col = 0 (any in-range index) and value 0.
+// Lattice-interior rows of the VIP and node operators (the per-step products of eqs. 12-15).
+// A node is canonical here when its rows of the four VIP operators and of D^[0,0] and the
+// Laplacian are all canonical (see Canon).  Each of those reference rows is stored as runs of
+// consecutive lattice columns, one per stencil row dy = -3..3 in slot order, so a row's taps
+// are rb[dy] + dx0 .. rb[dy] + dx0 + len - 1 with rb[dy] the node straight above or below.
+constexpr int kVcOps = 5;           // e, w, n, s VIP operators; node operators (D^[0,0], Laplacian)
+constexpr int kVcRows = 7;          // stencil rows dy = -3..3
+struct VipCanon {
+  int32_t* cpix = nullptr;          // device [n]: pixel of a canonical node, else -1
+  int64_t count = 0;
+  int8_t dx0[kVcOps][kVcRows] = {};
+  int8_t len[kVcOps][kVcRows] = {};
+  uint8_t used[kVcRows] = {};       // some operator has taps in this stencil row
+  double w[kVcOps + 1][kMaxTaps] = {};  // e, w, n, s, D^[0,0], Laplacian; slot order
+};
+
 struct Ell {
   int64_t nrows = 0;
   int64_t nslices = 0;
@@ -264,6 +280,7 @@ struct Ctx {
   KrylovScalars* sc_host = nullptr; // pinned host mirror
 
   Lattice lat;
+  VipCanon vcanon;
   Amg amg;
   Learn learn;
   Timing timing;                  // pressure-solve SpMV launches
@@ -374,6 +391,9 @@ int canon_mark(Ctx* c, Ell& e, int vs);
 // Slice descriptors (Canon::sbase) of canonical-row pixels cpix [n] into out [4 * ceil(n/64)].
 int slice_bases(Ctx* c, const int32_t* cpix, int64_t n, int32_t** out, int64_t* described = nullptr);
 void canon_free(Canon& cn);
+// Canonical nodes of the VIP and node operators (VipCanon); leaves count = 0 when there are none.
+int vip_canon_setup(Ctx* c);
+void vip_canon_free(Ctx* c);
 void lattice_free(Lattice& lat);
 int learn_train(Ctx* c, int iters, int batch, int crop, double lr, uint64_t seed, double* last_loss);
 bool learn_ready(const Ctx* c);

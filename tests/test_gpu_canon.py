@@ -65,6 +65,7 @@ def test_canonical_rows_give_the_same_bits(name, precision):
                 assert counts[0] >= min_frac * spec.n and counts[4] >= min_frac * spec.n
                 assert counts[1] >= min_frac * spec.n and counts[2] >= min_frac * spec.n
                 assert counts[5] >= min_frac * spec.n and counts[6] >= min_frac * spec.n
+                assert counts[3] >= min_frac * spec.n     # VIP and node rows of the step kernels
             if name in ("cylinder16", "bumpy32"):    # lattice rows longer than a 64-row slice
                 assert 0 < desc[4] <= counts[4] and desc[4] % 64 == 0
         out.append(([a.cpu().numpy() for a in st], [s["poisson_iters"] for s in stats]))

@@ -99,7 +99,7 @@ def test_sampled_operator_rows_at_full_size(full):
         for op, M in mats.items():
             row = M.getrow(li)
             ref = float((row @ xw)[0])
-            scale = float(abs(row) @ np.abs(xw)) + 1e-300
+            scale = float((abs(row) @ np.abs(xw))[0]) + 1e-300
             err = abs(got[op][i] - ref) / scale
             worst[op] = max(worst[op], err)
             assert err <= 1e-12, (int(i), op, err)

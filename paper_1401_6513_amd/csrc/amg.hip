@@ -24,6 +24,7 @@
 #include <cmath>
 #include <vector>
 
+#include "tile.h"
 #include "vip_internal.h"
 
 namespace vip {
@@ -288,22 +289,29 @@ struct LevelView {
   T w[kMaxTaps];
   T wdinv_c;
   float crsum;
+  TileView tv;            // level 0: tile partition of the canonical rows (tile.h), if any
 };
 
 // Canonical row of a level: weights of the reference row, columns from the lattice map,
 // slots to the accumulators in the general path's order (same bits).
-template <typename T, class Y>
-__device__ __forceinline__ T disk_row_sum(const LevelView<T>& L, int64_t i, const int32_t (&b)[5], Y y) {
-  const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
+template <typename T, class Tap>
+__device__ __forceinline__ T disk_taps(const LevelView<T>& L, Tap&& tap) {
+  const T yi = (sizeof(T) == 4) ? tap(2, 0) : T(0);
   T a0 = T(0), a1 = T(0);
 #pragma unroll
   for (int k = 0; k < kDiskTaps; ++k) {
-    const T d = L.w[k] * (y(b[disk_row(k)] + disk_dx(k)) - yi);
+    const T d = L.w[k] * (tap(disk_row(k), disk_dx(k)) - yi);
     if (k & 1) a1 += d;
     else a0 += d;
   }
   if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
   else return a0 + a1;
+}
+
+template <typename T, class Y>
+__device__ __forceinline__ T disk_row_sum(const LevelView<T>& L, int64_t i, const int32_t (&b)[5], Y y) {
+  (void)i;
+  return disk_taps(L, [&](int r, int dx) __attribute__((always_inline)) { return y(b[r] + dx); });
 }
 
 // Canonical row of a level: weights of the reference row, columns from the lattice map,
@@ -407,12 +415,38 @@ __global__ void k_jacobi0(LevelView<T> L, const T* b, T* x, const int* on) {
 
 // r = b - A x
 template <typename T>
-__global__ void k_level_residual(LevelView<T> L, const T* b, const T* x, T* r, const int* on) {
+__global__ void __launch_bounds__(kBlock) k_level_residual(LevelView<T> L, const T* b, const T* x, T* r, const int* on) {
+  __shared__ T lds[1][kTileLdsH][kTileLdsW];
+  __shared__ TileMeta meta;
   if (!*on) return;
+  if (L.tv.tiles) {
+    const T* xs[1] = {x};
+    tile_walk(
+        L.tv,
+        [&](int tx, int ty) __attribute__((always_inline)) {
+          tile_stage<T, 1>(L.tv, tx, ty, xs, lds, meta, true);
+          int64_t ii[kTileRowsPerWave];
+          bool ok[kTileRowsPerWave];
+          tile_row_ids(L.tv, tx, ty, meta, ii, ok);
+          T bi[kTileRowsPerWave];
+#pragma unroll
+          for (int k = 0; k < kTileRowsPerWave; ++k)
+            if (ok[k]) bi[k] = b[ii[k]];
+          const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+          for (int k = 0; k < kTileRowsPerWave; ++k) {
+            if (!ok[k]) continue;
+            const int ly = wave + k * (kBlock / 64);
+            r[ii[k]] = bi[k] - disk_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
+          }
+        },
+        [&](int64_t i) __attribute__((always_inline)) { r[i] = b[i] - level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return x[j]; }); });
+    return;
+  }
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = lb * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
-  r[i] = b[i] - level_row(L, i, [&](int32_t j) { return x[j]; });
+  r[i] = b[i] - level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return x[j]; });
 }
 
 // bc[I] = sum of r over the members of aggregate I
@@ -440,12 +474,47 @@ __global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, T gamma, c
 
 // out = y + W (b - A y)   (damped Jacobi sweep)
 template <typename T>
-__global__ void k_jacobi(LevelView<T> L, const T* b, const T* y, T* out, const int* on) {
+__global__ void __launch_bounds__(kBlock) k_jacobi(LevelView<T> L, const T* b, const T* y, T* out, const int* on) {
+  __shared__ T lds[1][kTileLdsH][kTileLdsW];
+  __shared__ TileMeta meta;
   if (!*on) return;
+  if (L.tv.tiles) {
+    // tile rows: the damped inverse diagonal from memory (equal to the reference one where
+    // that applies, so the same bits)
+    const T* ys[1] = {y};
+    tile_walk(
+        L.tv,
+        [&](int tx, int ty) __attribute__((always_inline)) {
+          tile_stage<T, 1>(L.tv, tx, ty, ys, lds, meta, true);
+          int64_t ii[kTileRowsPerWave];
+          bool ok[kTileRowsPerWave];
+          tile_row_ids(L.tv, tx, ty, meta, ii, ok);
+          T bi[kTileRowsPerWave], wd[kTileRowsPerWave];
+#pragma unroll
+          for (int k = 0; k < kTileRowsPerWave; ++k)
+            if (ok[k]) {
+              bi[k] = b[ii[k]];
+              wd[k] = L.wdinv[ii[k]];
+            }
+          const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+          for (int k = 0; k < kTileRowsPerWave; ++k) {
+            if (!ok[k]) continue;
+            const int ly = wave + k * (kBlock / 64);
+            const T ay = disk_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
+            out[ii[k]] = lds[0][ly + 2][lane + 2] + wd[k] * (bi[k] - ay);
+          }
+        },
+        [&](int64_t i) __attribute__((always_inline)) {
+          const T ay = level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return y[j]; });
+          out[i] = y[i] + level_wdinv(L, i) * (b[i] - ay);
+        });
+    return;
+  }
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = lb * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
-  const T ay = level_row(L, i, [&](int32_t j) { return y[j]; });
+  const T ay = level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return y[j]; });
   out[i] = y[i] + level_wdinv(L, i) * (b[i] - ay);
 }
 
@@ -674,7 +743,8 @@ int amg_setup(Ctx* c) {
 }
 
 template <typename T>
-static LevelView<T> view(const AmgLevel& L) {
+static LevelView<T> view(const Ctx* c, int level) {
+  const AmgLevel& L = c->amg.lv[level];
   LevelView<T> v;
   v.n = L.n;
   v.ptr = L.A.ptr;
@@ -703,7 +773,18 @@ static LevelView<T> view(const AmgLevel& L) {
     for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w[L.vs][k];
   }
   for (int k = 0; k < v.K; ++k) v.off[k] = L.A.canon.off[k];
+  // level 0 with canonical rows on: the system layout's tile partition of the same value set
+  if (level == 0 && !c->no_canon && v.disk) {
+    const int key = sizeof(T) == 4 ? 1 : (L.vs == 0 ? 0 : -1);
+    if (key >= 0) v.tv = tile_view(c, c->sys.canon.tpart[key]);
+  }
   return v;
+}
+
+// Blocks of a level-0 row launch: the tile partition's split, else one row per thread.
+template <typename T>
+static int64_t level_grid(const LevelView<T>& v) {
+  return v.tv.tiles ? static_cast<int64_t>(v.tv.tile_blocks) + v.tv.irr_blocks : grid_for(v.n);
 }
 
 // x = M^-1 b for the first n entries (one V-cycle); the border entry is passed through.
@@ -742,12 +823,13 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     if (pre) {
       T* a1 = w(l, 1);
       T* a2 = w(l, 2);
-      k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, a1, on);
+      const LevelView<T> lv = view<T>(c, l);
+      k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(lv, rhs, a1, on);
       for (int k = 1; k < nu; ++k) {
-        k_jacobi<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, a1, a2, on);
+        k_jacobi<T><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, a1, a2, on);
         std::swap(a1, a2);
       }
-      k_level_residual<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), rhs, a1, a2, on);
+      k_level_residual<T><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, a1, a2, on);
       cur[l] = a1;
       res = a2;
     }
@@ -767,9 +849,10 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     T* y = (cur[l] == w(l, 2)) ? w(l, 1) : w(l, 2);
     T* other = (y == w(l, 1)) ? w(l, 2) : w(l, 1);
     k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, gamma, cur[l], y, on);
+    const LevelView<T> lv = view<T>(c, l);
     for (int k = 0; k < nu; ++k) {
       T* out = (l == 0 && k == nu - 1) ? x : other;
-      k_jacobi<T><<<grid_for(L.n), kBlock, 0, st>>>(view<T>(L), bl, y, out, on);
+      k_jacobi<T><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, y, out, on);
       other = y;
       y = out;
     }

@@ -69,6 +69,7 @@ void ctx_free_build(Ctx* c) {
   c->have_prev_phi = false;
   learn_free_nodeset(c);
   vip_canon_free(c);
+  tile_map_free(c->tmap);
   lattice_free(c->lat);
   for (auto& h : c->hint_p64) h = 0;
   for (auto& h : c->hint_p32) h = 0;

@@ -998,6 +998,8 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   // lattice-interior rows of the pressure matrix (FP64 and FP32 value sets)
   VIP_TRY(canon_mark(c, s, 0));
   VIP_TRY(canon_mark(c, s, 4));
+  VIP_TRY(tile_part(c, 0));
+  VIP_TRY(tile_part(c, 1));
   // lattice-interior rows of the per-step VIP and node products
   VIP_TRY(vip_canon_setup(c));
   c->built = true;
@@ -1029,6 +1031,8 @@ int assemble_helmholtz(Ctx* c, double dt, double re) {
   VIP_TRY(canon_mark(c, c->sys, 2));
   VIP_TRY(canon_mark(c, c->sys, 5));
   VIP_TRY(canon_mark(c, c->sys, 6));
+  VIP_TRY(tile_part(c, 2));
+  VIP_TRY(tile_part(c, 3));
   c->cur_dt = dt;
   c->cur_re = re;
   c->assembled = true;

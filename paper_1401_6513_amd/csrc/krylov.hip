@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <vector>
 
+#include "tile.h"
 #include "vip_internal.h"
 
 namespace vip {
@@ -90,13 +91,33 @@ template <int NV>
 __device__ __forceinline__ void grid_sum(const double* partials, int64_t nb, double (&tot)[NV]) {
   __shared__ double red[NV][kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // each thread adds blocks threadIdx.x + 256 k in increasing k; eight blocks' values are
+  // loaded before they are added, so the loads are in flight together
+  double t[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) t[a] = 0.0;
+  constexpr int kAhead = 8;
+  int64_t b = threadIdx.x;
+  for (; b + (kAhead - 1) * static_cast<int64_t>(blockDim.x) < nb; b += kAhead * static_cast<int64_t>(blockDim.x)) {
+    double v[kAhead][NV];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u)
+#pragma unroll
+      for (int a = 0; a < NV; ++a) v[u][a] = partials[(b + u * static_cast<int64_t>(blockDim.x)) * NV + a];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u)
+#pragma unroll
+      for (int a = 0; a < NV; ++a) t[a] += v[u][a];
+  }
+  for (; b < nb; b += blockDim.x)
+#pragma unroll
+    for (int a = 0; a < NV; ++a) t[a] += partials[b * NV + a];
 #pragma unroll
   for (int a = 0; a < NV; ++a) {
-    double t = 0.0;
-    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) t += partials[b * NV + a];
+    double ta = t[a];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-    if (lane == 0) red[a][wave] = t;
+    for (int off = 32; off > 0; off >>= 1) ta += __shfl_xor(ta, off, 64);
+    if (lane == 0) red[a][wave] = ta;
   }
   __syncthreads();
 #pragma unroll
@@ -134,6 +155,8 @@ struct Mat {
   int32_t off[kMaxTaps];
   VT w[2][kMaxTaps];
   float crsum[2];
+  TileView tv;             // tile partition of the systems' canonical rows (tile.h), if any
+  int tile_general;        // 1: tile rows also take the row-by-row path (canonical rows off)
 };
 
 // Every system a kernel will touch has its values (and, in FP32, its row sums).
@@ -153,6 +176,12 @@ void attach_canon(const Ctx* c, Mat<VT>& A, int vs0, int vs1) {
   const Canon& cn = c->sys.canon;
   A.cpix[0] = A.cpix[1] = nullptr;
   A.sbase[0] = A.sbase[1] = nullptr;
+  // the tile partition fixes the order rows are visited in, so it is kept with canonical rows
+  // off (every row then takes the row-by-row path) and reductions give the same bits
+  const int key = (vs0 == 0 && vs1 < 0) ? 0 : (vs0 == 4 && vs1 < 0) ? 1 : (vs0 == 1 && vs1 == 2) ? 2
+                : (vs0 == 5 && vs1 == 6) ? 3 : -1;
+  A.tv = key >= 0 ? tile_view(c, cn.tpart[key]) : TileView();
+  A.tile_general = c->no_canon ? 1 : 0;
   if (c->no_canon || cn.K == 0) return;
   const int vs[2] = {vs0, vs1};
   for (int s = 0; s < 2; ++s) {
@@ -168,6 +197,12 @@ void attach_canon(const Ctx* c, Mat<VT>& A, int vs0, int vs1) {
   A.disk = cn.disk;
   A.W = c->lat.W;
   for (int k = 0; k < cn.K; ++k) A.off[k] = cn.off[k];
+}
+
+// Blocks of a reducing SpMV launch: the tile partition's split, else the row grid.
+template <typename VT>
+int64_t spmv_grid(const Mat<VT>& A) {
+  return A.tv.tiles ? static_cast<int64_t>(A.tv.tile_blocks) + A.tv.irr_blocks : red_grid(A.n);
 }
 
 template <typename T>
@@ -191,15 +226,14 @@ struct Vec {
 // 21-point disk with the five row bases given: slots 0, 2, ..., 20 to the first accumulator,
 // the odd ones to the second (a slice of such rows is at least 21 wide, so only slot 20 can
 // fall in the tail of the general path)
-template <typename VT, typename T>
-__device__ __forceinline__ double disk_dot(const Mat<VT>& A, int sys, int64_t i, const int32_t (&b)[5],
-                                           const T* x) {
+template <typename VT, typename Tap>
+__device__ __forceinline__ double disk_sum(const Mat<VT>& A, int sys, Tap&& tap) {
   if constexpr (sizeof(VT) == 4) {
-    const float xi = static_cast<float>(x[i]);
+    const float xi = static_cast<float>(tap(2, 0));
     float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
     for (int k = 0; k < kDiskTaps; ++k) {
-      const float d = A.w[sys][k] * (static_cast<float>(x[b[disk_row(k)] + disk_dx(k)]) - xi);
+      const float d = A.w[sys][k] * (static_cast<float>(tap(disk_row(k), disk_dx(k))) - xi);
       if (k & 1) a1 += d;
       else a0 += d;
     }
@@ -208,12 +242,26 @@ __device__ __forceinline__ double disk_dot(const Mat<VT>& A, int sys, int64_t i,
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
     for (int k = 0; k < kDiskTaps; ++k) {
-      const double d = A.w[sys][k] * static_cast<double>(x[b[disk_row(k)] + disk_dx(k)]);
+      const double d = A.w[sys][k] * static_cast<double>(tap(disk_row(k), disk_dx(k)));
       if (k & 1) a1 += d;
       else a0 += d;
     }
     return a0 + a1;
   }
+}
+
+template <typename VT, typename T>
+__device__ __forceinline__ double disk_dot(const Mat<VT>& A, int sys, int64_t i, const int32_t (&b)[5],
+                                           const T* x) {
+  (void)i;
+  return disk_sum(A, sys, [&](int r, int dx) __attribute__((always_inline)) { return x[b[r] + dx]; });
+}
+
+// the same row from a tile's LDS copy (tile.h): tap (r, dx) of local row ly, lane lx
+template <typename VT, typename T>
+__device__ __forceinline__ double disk_lds(const Mat<VT>& A, int sys, const T (&t)[kTileLdsH][kTileLdsW], int ly,
+                                           int lx) {
+  return disk_sum(A, sys, [&](int r, int dx) __attribute__((always_inline)) { return t[ly + r][lx + 2 + dx]; });
 }
 
 template <typename VT, typename T>
@@ -269,15 +317,12 @@ __device__ __forceinline__ double canon_dot(const Mat<VT>& A, int sys, int32_t p
 // Row i of y = A x for system `sys`; x is the system's vector.  The slot loop is
 // unrolled by four so the column loads of several slots are in flight before
 // their gathers.
+// (without the slice descriptors: canonical rows by pixel, else the sliced ELL)
 template <typename VT, typename T>
-__device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, const T* x) {
+__device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_t i, const T* x) {
   const int64_t sl = i / kSlice;
   const int64_t base = A.ptr[sl] + (i % kSlice);
   const int w = static_cast<int>((A.ptr[sl + 1] - A.ptr[sl]) / kSlice);
-  if (A.sbase[sys]) {
-    int32_t b[5];
-    if (slice_disk_bases(A.sbase[sys], i, b)) return disk_dot(A, sys, i, b, x);
-  }
   if (A.cpix[sys]) {
     const int32_t p = A.cpix[sys][i];
     if (p >= 0) return canon_dot(A, sys, p, i, w, x);
@@ -330,27 +375,151 @@ __device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, 
   }
 }
 
+template <typename VT, typename T>
+__device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, const T* x) {
+  if (A.sbase[sys]) {
+    int32_t b[5];
+    if (slice_disk_bases(A.sbase[sys], i, b)) return disk_dot(A, sys, i, b, x);
+  }
+  return row_dot_rows(A, sys, i, x);
+}
+
+// Row loop of the reducing SpMV kernels: the block's rows sp.begin + threadIdx.x + 256 k (the
+// order of a plain strided loop, so per-thread sums keep their order), visited as one 64-row
+// slice per wave and step.  A slice described for every system in use (Canon::sbase; the
+// systems then share the five row bases) goes to fast(i, b); its gathers for all systems can be
+// in flight together, and the descriptors of the wave's next slice are loaded one step ahead.
+// Other slices go row by row to slow(i).
+template <typename VT, int NS, typename Fast, typename Slow>
+__device__ __forceinline__ void walk_rows(const Mat<VT>& A, const bool (&use)[NS], Fast&& fast, Slow&& slow) {
+  const Span sp = block_span(A.n);
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  const int64_t first = sp.begin / kSlice + wave;
+  const int64_t last = (sp.end + kSlice - 1) / kSlice;
+  bool any = false, desc = true;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    any = any || use[s];
+    if (use[s] && !A.sbase[s]) desc = false;
+  }
+  if (!any) return;
+  int4 nd[NS];
+  auto fetch = [&](int64_t sl) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      nd[s] = desc && use[s] && sl < last ? *reinterpret_cast<const int4*>(A.sbase[s] + 4 * sl)
+                                          : make_int4(-1, -1, -1, -1);
+  };
+  fetch(first);
+  for (int64_t sl = first; sl < last; sl += kWaves) {
+    int4 d[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) d[s] = nd[s];
+    fetch(sl + kWaves);
+    const int64_t i = sl * kSlice + lane;
+    bool ok = desc;
+    int4 db = make_int4(-1, -1, -1, -1);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (use[s]) {
+        ok = ok && __builtin_amdgcn_readfirstlane(d[s].x) >= 0;
+        db = d[s];
+      }
+    if (ok) {
+      // a described slice holds 64 rows below n, all inside this span
+      const int32_t b[5] = {__builtin_amdgcn_readfirstlane(db.x) + lane, __builtin_amdgcn_readfirstlane(db.y) + lane,
+                            static_cast<int32_t>(i), __builtin_amdgcn_readfirstlane(db.z) + lane,
+                            __builtin_amdgcn_readfirstlane(db.w) + lane};
+      fast(i, b);
+    } else if (i < sp.end) {
+      slow(i);
+    }
+  }
+}
+
 // ---- residual: r = b - A x, rr = |r|^2, bb = |b|^2 ----------------------------------------------
-template <typename VT, typename XT, typename RT, int NS>
-__global__ void k_residual(Mat<VT> A, const XT* x, const double* b, RT* r, int64_t stride,
+template <typename VT, typename XT, typename RT, int NS, bool GEN>
+__global__ void __launch_bounds__(kBlock) k_residual(Mat<VT> A, const XT* x, const double* b, RT* r, int64_t stride,
                            double* partials) {
+  __shared__ XT lds[NS][kTileLdsH][kTileLdsW];
+  __shared__ TileMeta meta;
   double acc[3 * NS];
 #pragma unroll
   for (int a = 0; a < 3 * NS; ++a) acc[a] = 0.0;
-  const Span sp = block_span(A.n);
-  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
+  double xn[NS];   // border unknowns (uniform)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const XT* xs = x + s * stride;
-      double ax = row_dot(A, s, i, xs);
-      if (A.border) ax += static_cast<double>(xs[A.n]);
-      const double bi = b[s * stride + i];
-      const double ri = bi - ax;
-      r[s * stride + i] = static_cast<RT>(ri);
-      acc[3 * s + 0] += ri * ri;
-      acc[3 * s + 1] += bi * bi;
-      if (A.border) acc[3 * s + 2] += static_cast<double>(xs[i]);
-    }
+  for (int s = 0; s < NS; ++s) xn[s] = A.border ? static_cast<double>(x[s * stride + A.n]) : 0.0;
+  auto emit = [&](int s, int64_t i, double ax, double bi, double xi) __attribute__((always_inline)) {
+    if (A.border) ax += xn[s];
+    const double ri = bi - ax;
+    r[s * stride + i] = static_cast<RT>(ri);
+    acc[3 * s + 0] += ri * ri;
+    acc[3 * s + 1] += bi * bi;
+    if (A.border) acc[3 * s + 2] += xi;
+  };
+  auto slow = [&](int64_t i) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      emit(s, i, row_dot_rows(A, s, i, x + s * stride), b[s * stride + i], static_cast<double>(x[s * stride + i]));
+  };
+  if (A.tv.tiles) {
+    const XT* xs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xs[s] = x + s * stride;
+    tile_walk(
+        A.tv,
+        [&](int tx, int ty) __attribute__((always_inline)) {
+            tile_stage<XT, NS>(A.tv, tx, ty, xs, lds, meta, !GEN);
+            int64_t ii[kTileRowsPerWave];
+            bool ok[kTileRowsPerWave];
+            tile_row_ids(A.tv, tx, ty, meta, ii, ok);
+            if constexpr (GEN) {
+#pragma unroll
+              for (int k = 0; k < kTileRowsPerWave; ++k)
+                if (ok[k]) slow(ii[k]);
+              return;
+            }
+            double bi[kTileRowsPerWave][NS];
+#pragma unroll
+            for (int k = 0; k < kTileRowsPerWave; ++k)
+              if (ok[k])
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                  bi[k][s] = b[s * stride + ii[k]];
+                }
+            const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+            for (int k = 0; k < kTileRowsPerWave; ++k) {
+              if (!ok[k]) continue;
+              const int ly = wave + k * (kBlock / 64);
+              double y[NS];
+#pragma unroll
+              for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
+#pragma unroll
+              for (int s = 0; s < NS; ++s) emit(s, ii[k], y[s], bi[k][s], static_cast<double>(lds[s][ly + 2][lane + 2]));
+            }
+          },
+        slow);
+  } else {
+    bool use[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) use[s] = true;
+    walk_rows(
+        A, use,
+        [&](int64_t i, const int32_t (&bs)[5]) {
+          double y[NS], bi[NS], xi[NS];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            bi[s] = b[s * stride + i];
+            xi[s] = static_cast<double>(x[s * stride + i]);
+          }
+#pragma unroll
+          for (int s = 0; s < NS; ++s) y[s] = disk_dot(A, s, i, bs, x + s * stride);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) emit(s, i, y[s], bi[s], xi[s]);
+        },
+        slow);
   }
   block_sum_store<3 * NS>(acc, partials);
 }
@@ -418,24 +587,92 @@ __global__ void k_bicg_p(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int ja
 }
 
 // v = A ph; partial sums of rhat . v (and of ph for the border row)
-template <typename VT, typename T, int NS>
-__global__ void k_bicg_v(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+template <typename VT, typename T, int NS, bool GEN>
+__global__ void __launch_bounds__(kBlock) k_bicg_v(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+  __shared__ T lds[NS][kTileLdsH][kTileLdsW];
+  __shared__ TileMeta meta;
   double acc[2 * NS];
 #pragma unroll
   for (int a = 0; a < 2 * NS; ++a) acc[a] = 0.0;
-  const Span sp = block_span(A.n);
-  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
+  bool use[NS], any = false;
+  double phn[NS];   // border unknowns (uniform)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (!sc->active[s]) continue;
-      const T* ph = V.ph + s * V.stride;
-      double y = row_dot(A, s, i, ph);
-      if (A.border) y += static_cast<double>(ph[A.n]);
-      const T yt = static_cast<T>(y);
-      V.v[s * V.stride + i] = yt;
-      acc[2 * s] += static_cast<double>(V.rhat[s * V.stride + i]) * static_cast<double>(yt);
-      if (A.border) acc[2 * s + 1] += static_cast<double>(ph[i]);
-    }
+  for (int s = 0; s < NS; ++s) {
+    use[s] = sc->active[s] != 0;
+    any = any || use[s];
+    phn[s] = A.border ? static_cast<double>(V.ph[s * V.stride + A.n]) : 0.0;
+  }
+  auto emit = [&](int s, int64_t i, double y, T rh, T pc) __attribute__((always_inline)) {
+    if (A.border) y += phn[s];
+    const T yt = static_cast<T>(y);
+    V.v[s * V.stride + i] = yt;
+    acc[2 * s] += static_cast<double>(rh) * static_cast<double>(yt);
+    if (A.border) acc[2 * s + 1] += static_cast<double>(pc);
+  };
+  auto slow = [&](int64_t i) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (use[s])
+        emit(s, i, row_dot_rows(A, s, i, V.ph + s * V.stride), V.rhat[s * V.stride + i], V.ph[s * V.stride + i]);
+  };
+  if (A.tv.tiles) {
+    const T* xs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xs[s] = V.ph + s * V.stride;
+    if (any)
+      tile_walk(
+          A.tv,
+          [&](int tx, int ty) __attribute__((always_inline)) {
+            tile_stage<T, NS>(A.tv, tx, ty, xs, lds, meta, !GEN);
+            int64_t ii[kTileRowsPerWave];
+            bool ok[kTileRowsPerWave];
+            tile_row_ids(A.tv, tx, ty, meta, ii, ok);
+            if constexpr (GEN) {
+#pragma unroll
+              for (int k = 0; k < kTileRowsPerWave; ++k)
+                if (ok[k]) slow(ii[k]);
+              return;
+            }
+            T rh[kTileRowsPerWave][NS];
+#pragma unroll
+            for (int k = 0; k < kTileRowsPerWave; ++k)
+              if (ok[k])
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                  rh[k][s] = V.rhat[s * V.stride + ii[k]];
+                }
+            const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+            for (int k = 0; k < kTileRowsPerWave; ++k) {
+              if (!ok[k]) continue;
+              const int ly = wave + k * (kBlock / 64);
+              double y[NS];
+#pragma unroll
+              for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
+#pragma unroll
+              for (int s = 0; s < NS; ++s) if (use[s]) emit(s, ii[k], y[s], rh[k][s], lds[s][ly + 2][lane + 2]);
+            }
+          },
+          slow);
+  } else {
+    walk_rows(
+        A, use,
+        [&](int64_t i, const int32_t (&b)[5]) {
+          // every system's row is computed (in-bounds reads) so all loads issue together
+          double y[NS];
+          T rh[NS], pc[NS];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            rh[s] = V.rhat[s * V.stride + i];
+            pc[s] = V.ph[s * V.stride + i];
+          }
+#pragma unroll
+          for (int s = 0; s < NS; ++s) y[s] = disk_dot(A, s, i, b, V.ph + s * V.stride);
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            if (use[s]) emit(s, i, y[s], rh[s], pc[s]);
+        },
+        slow);
   }
   block_sum_store<2 * NS>(acc, partials);
 }
@@ -478,26 +715,92 @@ __global__ void k_bicg_s(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int ja
 }
 
 // t = A sh; partial sums of t . s, t . t (and of sh for the border row)
-template <typename VT, typename T, int NS>
-__global__ void k_bicg_t(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+template <typename VT, typename T, int NS, bool GEN>
+__global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+  __shared__ T lds[NS][kTileLdsH][kTileLdsW];
+  __shared__ TileMeta meta;
   double acc[3 * NS];
 #pragma unroll
   for (int a = 0; a < 3 * NS; ++a) acc[a] = 0.0;
-  const Span sp = block_span(A.n);
-  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
+  bool use[NS], any = false;
+  double shn[NS];   // border unknowns (uniform)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (!sc->active[s]) continue;
-      const T* sh = V.sh + s * V.stride;
-      double y = row_dot(A, s, i, sh);
-      if (A.border) y += static_cast<double>(sh[A.n]);
-      const T yt = static_cast<T>(y);
-      V.t[s * V.stride + i] = yt;
-      const double sv = static_cast<double>(V.s[s * V.stride + i]);
-      acc[3 * s] += static_cast<double>(yt) * sv;
-      acc[3 * s + 1] += static_cast<double>(yt) * static_cast<double>(yt);
-      if (A.border) acc[3 * s + 2] += static_cast<double>(sh[i]);
-    }
+  for (int s = 0; s < NS; ++s) {
+    use[s] = sc->active[s] != 0;
+    any = any || use[s];
+    shn[s] = A.border ? static_cast<double>(V.sh[s * V.stride + A.n]) : 0.0;
+  }
+  auto emit = [&](int s, int64_t i, double y, T sv, T si) __attribute__((always_inline)) {
+    if (A.border) y += shn[s];
+    const T yt = static_cast<T>(y);
+    V.t[s * V.stride + i] = yt;
+    acc[3 * s] += static_cast<double>(yt) * static_cast<double>(sv);
+    acc[3 * s + 1] += static_cast<double>(yt) * static_cast<double>(yt);
+    if (A.border) acc[3 * s + 2] += static_cast<double>(si);
+  };
+  auto slow = [&](int64_t i) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (use[s])
+        emit(s, i, row_dot_rows(A, s, i, V.sh + s * V.stride), V.s[s * V.stride + i], V.sh[s * V.stride + i]);
+  };
+  if (A.tv.tiles) {
+    const T* xs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xs[s] = V.sh + s * V.stride;
+    if (any)
+      tile_walk(
+          A.tv,
+          [&](int tx, int ty) __attribute__((always_inline)) {
+            tile_stage<T, NS>(A.tv, tx, ty, xs, lds, meta, !GEN);
+            int64_t ii[kTileRowsPerWave];
+            bool ok[kTileRowsPerWave];
+            tile_row_ids(A.tv, tx, ty, meta, ii, ok);
+            if constexpr (GEN) {
+#pragma unroll
+              for (int k = 0; k < kTileRowsPerWave; ++k)
+                if (ok[k]) slow(ii[k]);
+              return;
+            }
+            T sv[kTileRowsPerWave][NS];
+#pragma unroll
+            for (int k = 0; k < kTileRowsPerWave; ++k)
+              if (ok[k])
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                  sv[k][s] = V.s[s * V.stride + ii[k]];
+                }
+            const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+            for (int k = 0; k < kTileRowsPerWave; ++k) {
+              if (!ok[k]) continue;
+              const int ly = wave + k * (kBlock / 64);
+              double y[NS];
+#pragma unroll
+              for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
+#pragma unroll
+              for (int s = 0; s < NS; ++s) if (use[s]) emit(s, ii[k], y[s], sv[k][s], lds[s][ly + 2][lane + 2]);
+            }
+          },
+          slow);
+  } else {
+    walk_rows(
+        A, use,
+        [&](int64_t i, const int32_t (&b)[5]) {
+          double y[NS];
+          T sv[NS], si[NS];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            sv[s] = V.s[s * V.stride + i];
+            si[s] = V.sh[s * V.stride + i];
+          }
+#pragma unroll
+          for (int s = 0; s < NS; ++s) y[s] = disk_dot(A, s, i, b, V.sh + s * V.stride);
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            if (use[s]) emit(s, i, y[s], sv[s], si[s]);
+        },
+        slow);
   }
   block_sum_store<3 * NS>(acc, partials);
 }
@@ -610,21 +913,75 @@ __global__ void k_fin_cg_init(const double* partials, int64_t nb, KrylovScalars*
 }
 
 // v = A p; partial sums of p . v
-template <typename VT, typename T, int NS>
-__global__ void k_cg_q(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+template <typename VT, typename T, int NS, bool GEN>
+__global__ void __launch_bounds__(kBlock) k_cg_q(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+  __shared__ T lds[NS][kTileLdsH][kTileLdsW];
+  __shared__ TileMeta meta;
   double acc[NS];
 #pragma unroll
   for (int a = 0; a < NS; ++a) acc[a] = 0.0;
-  const Span sp = block_span(A.n);
-  for (int64_t i = sp.begin + threadIdx.x; i < sp.end; i += blockDim.x) {
+  bool use[NS], any = false;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      if (!sc->active[s]) continue;
-      const T* p = V.p + s * V.stride;
-      const T y = static_cast<T>(row_dot(A, s, i, p));
-      V.v[s * V.stride + i] = y;
-      acc[s] += static_cast<double>(p[i]) * static_cast<double>(y);
-    }
+  for (int s = 0; s < NS; ++s) {
+    use[s] = sc->active[s] != 0;
+    any = any || use[s];
+  }
+  auto emit = [&](int s, int64_t i, double y, T pc) __attribute__((always_inline)) {
+    const T yt = static_cast<T>(y);
+    V.v[s * V.stride + i] = yt;
+    acc[s] += static_cast<double>(pc) * static_cast<double>(yt);
+  };
+  auto slow = [&](int64_t i) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (use[s]) emit(s, i, row_dot_rows(A, s, i, V.p + s * V.stride), V.p[s * V.stride + i]);
+  };
+  if (A.tv.tiles) {
+    const T* xs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xs[s] = V.p + s * V.stride;
+    if (any)
+      tile_walk(
+          A.tv,
+          [&](int tx, int ty) __attribute__((always_inline)) {
+            tile_stage<T, NS>(A.tv, tx, ty, xs, lds, meta, !GEN);
+            int64_t ii[kTileRowsPerWave];
+            bool ok[kTileRowsPerWave];
+            tile_row_ids(A.tv, tx, ty, meta, ii, ok);
+            if constexpr (GEN) {
+#pragma unroll
+              for (int k = 0; k < kTileRowsPerWave; ++k)
+                if (ok[k]) slow(ii[k]);
+              return;
+            }
+            const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+            for (int k = 0; k < kTileRowsPerWave; ++k) {
+              if (!ok[k]) continue;
+              const int ly = wave + k * (kBlock / 64);
+              double y[NS];
+#pragma unroll
+              for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
+#pragma unroll
+              for (int s = 0; s < NS; ++s) if (use[s]) emit(s, ii[k], y[s], lds[s][ly + 2][lane + 2]);
+            }
+          },
+          slow);
+  } else {
+    walk_rows(
+        A, use,
+        [&](int64_t i, const int32_t (&b)[5]) {
+          double y[NS];
+          T pc[NS];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) pc[s] = V.p[s * V.stride + i];
+#pragma unroll
+          for (int s = 0; s < NS; ++s) y[s] = disk_dot(A, s, i, b, V.p + s * V.stride);
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            if (use[s]) emit(s, i, y[s], pc[s]);
+        },
+        slow);
   }
   block_sum_store<NS>(acc, partials);
 }
@@ -872,7 +1229,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   VIP_TRY(check_mat(c, A, NS));
   const int64_t nvec = A.n + A.border;
   const int64_t g_vec = grid_for(nvec);
-  const int64_t r_rows = red_grid(A.n), r_vec = red_grid(nvec);
+  const int64_t r_rows = spmv_grid(A), r_vec = red_grid(nvec);
   VIP_TRY(ensure_partials(c, std::max(r_rows, r_vec), 3 * NS));
   if (c->debug)
     std::fprintf(stderr, "[vip] iterate n %lld border %d tol %.3e rr0 %.3e bb %.3e\n",
@@ -912,21 +1269,24 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
         }
         {
           Timer tm(c, time_spmv);
-          k_bicg_v<VT, T, NS><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+          if (A.tile_general) k_bicg_v<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+          else k_bicg_v<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         }
         k_fin_bicg_v<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
         k_bicg_s<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
         if constexpr (NS == 1) {
           if (amg) VIP_TRY(amg_apply<T>(c, V.s, V.sh, A.border != 0, c->amg_pre_fine != 0));
         }
-        k_bicg_t<VT, T, NS><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+        if (A.tile_general) k_bicg_t<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+          else k_bicg_t<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         k_fin_bicg_t<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
         k_bicg_x<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc);
         k_fin_bicg_x<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);
       } else {
         {
           Timer tm(c, time_spmv);
-          k_cg_q<VT, T, NS><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+          if (A.tile_general) k_cg_q<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+          else k_cg_q<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         }
         k_fin_cg_q<NS><<<1, kBlock, 0, st>>>(part, r_rows, sc);
         k_cg_x<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc, amg ? 0 : 1);
@@ -969,9 +1329,10 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
 template <typename VT, typename XT, typename RT, int NS>
 int residual(Ctx* c, const Mat<VT>& A, const XT* x, const double* b, RT* r, int64_t stride) {
   VIP_TRY(check_mat(c, A, NS));
-  const int64_t g = red_grid(A.n);
+  const int64_t g = spmv_grid(A);
   VIP_TRY(ensure_partials(c, g, 3 * NS));
-  k_residual<VT, XT, RT, NS><<<g, kBlock, 0, c->stream>>>(A, x, b, r, stride, c->partials);
+  if (A.tile_general) k_residual<VT, XT, RT, NS, true><<<g, kBlock, 0, c->stream>>>(A, x, b, r, stride, c->partials);
+  else k_residual<VT, XT, RT, NS, false><<<g, kBlock, 0, c->stream>>>(A, x, b, r, stride, c->partials);
   k_fin_residual<RT, NS><<<1, kBlock, 0, c->stream>>>(c->partials, g, A.n, A.border, b, r, stride, c->sc);
   VIP_HIP_TRY(c, hipGetLastError());
   return sync_scalars(c);

@@ -197,6 +197,65 @@ bool vc_runs(const Canon& cn, int8_t (&dx0)[kVcRows], int8_t (&len)[kVcRows]) {
   return cn.K > 0;
 }
 
+// rowstart[(yy, tx)]: the node at pixel (64 tx - 2, yy - 2) when the 68 pixels of the tile's LDS
+// row hold consecutive nodes, else -1
+__global__ void k_tile_rowstart(int64_t m, int ntx, int W, int H, const int32_t* node_of, int32_t* out) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= m) return;
+  const int yy = static_cast<int>(q / ntx), tx = static_cast<int>(q % ntx);
+  const int gy = yy - 2, gx0 = tx * kTileX - 2;
+  int32_t r = -1;
+  if (gy >= 0 && gy < H && gx0 >= 0 && gx0 + kTileX + 4 <= W) {
+    const int32_t* row = node_of + static_cast<int64_t>(gy) * W + gx0;
+    const int32_t s0 = row[0];
+    bool ok = s0 >= 0;
+    for (int k = 1; k < kTileX + 4 && ok; ++k) ok = row[k] == s0 + k;
+    if (ok) r = s0;
+  }
+  out[q] = r;
+}
+
+// bits[(y, tx)]: pixels of the word whose node is canonical in c0 (and c1)
+__global__ void k_tile_bits(int64_t m, int ntx, int W, int H, const int32_t* node_of, const int32_t* c0,
+                            const int32_t* c1, uint64_t* bits) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= m) return;
+  const int gy = static_cast<int>(q / ntx), tx = static_cast<int>(q % ntx);
+  uint64_t w = 0;
+  if (gy < H) {
+    for (int lx = 0; lx < kTileX; ++lx) {
+      const int gx = tx * kTileX + lx;
+      if (gx >= W) break;
+      const int32_t node = node_of[static_cast<int64_t>(gy) * W + gx];
+      if (node >= 0 && c0[node] >= 0 && (!c1 || c1[node] >= 0)) w |= 1ull << lx;
+    }
+  }
+  bits[q] = w;
+}
+
+// flag[t] = 1 if tile t holds a tile row
+__global__ void k_tile_flag(int64_t ntiles, int ntx, const uint64_t* bits, int64_t* flag) {
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (t >= ntiles) return;
+  const int tx = static_cast<int>(t % ntx), ty = static_cast<int>(t / ntx);
+  uint64_t any = 0;
+  for (int ly = 0; ly < kTileY; ++ly) any |= bits[static_cast<int64_t>(ty * kTileY + ly) * ntx + tx];
+  flag[t] = any ? 1 : 0;
+}
+
+// flag[i] = 1 if row i is not a tile row
+__global__ void k_irr_flag(int64_t n, const int32_t* c0, const int32_t* c1, int64_t* flag) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = (c0[i] >= 0 && (!c1 || c1[i] >= 0)) ? 0 : 1;
+}
+
+// out[pos[i]] = i where flag[i] (pos: exclusive scan of flag)
+__global__ void k_compact(int64_t n, const int64_t* flag, const int64_t* pos, int32_t* out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < n && flag[i]) out[pos[i]] = static_cast<int32_t>(i);
+}
+
 struct RowSample {
   int len = 0, bpos = 0, pix = -1;
   std::vector<int32_t> cpix;
@@ -277,6 +336,7 @@ void lattice_free(Lattice& lat) {
 }
 
 void canon_free(Canon& cn) {
+  for (auto& tp : cn.tpart) tile_part_free(tp);
   for (auto& p : cn.cpix) dfree(p);
   for (auto& p : cn.sbase) dfree(p);
   cn.K = 0;
@@ -444,6 +504,92 @@ int canon_mark(Ctx* c, Ell& e, int vs) {
     std::fprintf(stderr, "[vip] canonical rows, value set %d: %lld of %lld (%d taps, reference row %lld)\n", vs,
                  static_cast<long long>(cnt), static_cast<long long>(c->n), cn.K,
                  static_cast<long long>(cn.ref_row));
+  return VIP_OK;
+}
+
+void tile_part_free(TilePart& tp) {
+  dfree(tp.bits);
+  dfree(tp.tiles);
+  dfree(tp.irr);
+  tp = TilePart();
+}
+
+void tile_map_free(TileMap& tm) {
+  dfree(tm.rowstart);
+  tm = TileMap();
+}
+
+namespace {
+
+// indices i < m with flag[i] != 0, ascending, into a new device array
+int compact(Ctx* c, const int64_t* flag, int64_t m, int32_t** out, int64_t* count) {
+  int64_t* pos = nullptr;
+  VIP_TRY(dalloc(c, &pos, m));
+  int64_t total = 0;
+  int rc = scan_i64(c, flag, pos, m, &total);
+  if (rc == VIP_OK) rc = dalloc(c, out, total);
+  if (rc == VIP_OK && total > 0) {
+    k_compact<<<grid_for(m), kBlock, 0, c->stream>>>(m, flag, pos, *out);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+      rc = set_error(c, VIP_E_HIP, "compacting a tile list");
+  }
+  dfree(pos);
+  *count = total;
+  return rc;
+}
+
+}  // namespace
+
+int tile_part(Ctx* c, int key) {
+  Canon& cn = c->sys.canon;
+  if (key < 0 || key > 3) return set_error(c, VIP_E_INVALID, "tile partition key");
+  TilePart& tp = cn.tpart[key];
+  tile_part_free(tp);
+  static const int sets[4][2] = {{0, -1}, {4, -1}, {1, 2}, {5, 6}};
+  const int v0 = sets[key][0], v1 = sets[key][1];
+  if (!cn.disk || cn.ref_row < 0 || !cn.cpix[v0] || cn.count[v0] == 0 || (v1 >= 0 && (!cn.cpix[v1] || cn.count[v1] == 0)))
+    return VIP_OK;
+  const Lattice& L = c->lat;
+  if (!L.ok) return VIP_OK;
+  hipStream_t st = c->stream;
+  TileMap& tm = c->tmap;
+  if (!tm.rowstart) {
+    tm.ntx = (L.W + kTileX - 1) / kTileX;
+    tm.nty = (L.H + kTileY - 1) / kTileY;
+    const int64_t m = static_cast<int64_t>(tm.nty * kTileY + 4) * tm.ntx;
+    VIP_TRY(dalloc(c, &tm.rowstart, m));
+    k_tile_rowstart<<<grid_for(m), kBlock, 0, st>>>(m, tm.ntx, L.W, L.H, L.node_of, tm.rowstart);
+    VIP_HIP_TRY(c, hipGetLastError());
+  }
+  const int32_t* c0 = cn.cpix[v0];
+  const int32_t* c1 = v1 >= 0 ? cn.cpix[v1] : nullptr;
+  const int64_t nw = static_cast<int64_t>(tm.nty * kTileY) * tm.ntx;
+  VIP_TRY(dalloc(c, &tp.bits, nw));
+  k_tile_bits<<<grid_for(nw), kBlock, 0, st>>>(nw, tm.ntx, L.W, L.H, L.node_of, c0, c1, tp.bits);
+  VIP_HIP_TRY(c, hipGetLastError());
+  const int64_t nt = static_cast<int64_t>(tm.nty) * tm.ntx;
+  int64_t* flag = nullptr;
+  VIP_TRY(dalloc(c, &flag, std::max(nt, c->n)));
+  int rc = VIP_OK;
+  do {
+    k_tile_flag<<<grid_for(nt), kBlock, 0, st>>>(nt, tm.ntx, tp.bits, flag);
+    if ((rc = compact(c, flag, nt, &tp.tiles, &tp.ntiles)) != VIP_OK) break;
+    k_irr_flag<<<grid_for(c->n), kBlock, 0, st>>>(c->n, c0, c1, flag);
+    if ((rc = compact(c, flag, c->n, &tp.irr, &tp.nirr)) != VIP_OK) break;
+  } while (false);
+  dfree(flag);
+  if (rc != VIP_OK) {
+    tile_part_free(tp);
+    return rc;
+  }
+  // launch split (both multiples of the XCD count): one tile per block up to 8192 tile blocks,
+  // one irregular row per thread up to 1024 blocks
+  tp.tile_blocks = static_cast<int>(std::min<int64_t>((tp.ntiles + kNumXcd - 1) / kNumXcd * kNumXcd, 8192));
+  tp.irr_blocks = static_cast<int>(
+      std::min<int64_t>(((tp.nirr + kBlock - 1) / kBlock + kNumXcd - 1) / kNumXcd * kNumXcd, 1024));
+  if (c->debug)
+    std::fprintf(stderr, "[vip] tile partition %d: %lld tiles, %lld irregular rows of %lld\n", key,
+                 static_cast<long long>(tp.ntiles), static_cast<long long>(tp.nirr), static_cast<long long>(c->n));
   return VIP_OK;
 }
 

@@ -1,0 +1,143 @@
+// Lattice tiles of canonical rows (device side).
+//
+// On a lattice-based node set the canonical rows (translation-invariant 21-point disks, see
+// Canon) are computed tile by tile: a block copies the input vector over a 64 x 16 pixel tile
+// of the lattice plus a halo of two pixels into LDS (one coalesced row at a time where the
+// row's nodes are numbered consecutively) and each lane then reads its 21 taps from LDS.
+// Rows that are not canonical, and nodes off the lattice, form the irregular list, which the
+// first blocks of the same launch take one row per thread through the row-by-row path.
+// Every row is visited exactly once, in an order fixed by the partition alone, so reductions
+// over the rows give the same bits whichever way a row's value is computed.
+#pragma once
+
+#include "vip_internal.h"
+
+namespace vip {
+
+constexpr int kTileLdsW = kTileX + 4;
+constexpr int kTileLdsH = kTileY + 4;
+
+struct TileView {
+  const int32_t* tiles = nullptr;   // null: no tile partition
+  int64_t ntiles = 0;
+  const int32_t* irr = nullptr;
+  int64_t nirr = 0;
+  const uint64_t* bits = nullptr;
+  const int32_t* rowstart = nullptr;
+  const int32_t* node_of = nullptr;
+  int ntx = 0, W = 0, H = 0;
+  int tile_blocks = 0;              // blocks taking tiles (a multiple of the XCD count)
+  int irr_blocks = 0;               // blocks [0, irr_blocks) take the irregular rows (the same)
+};
+
+inline TileView tile_view(const Ctx* c, const TilePart& tp) {
+  TileView v;
+  if (!tp.tiles && !tp.irr) return v;
+  v.tiles = tp.tiles;
+  v.ntiles = tp.ntiles;
+  v.irr = tp.irr;
+  v.nirr = tp.nirr;
+  v.bits = tp.bits;
+  v.rowstart = c->tmap.rowstart;
+  v.node_of = c->lat.node_of;
+  v.ntx = c->tmap.ntx;
+  v.W = c->lat.W;
+  v.H = c->lat.H;
+  v.tile_blocks = tp.tile_blocks;
+  v.irr_blocks = tp.irr_blocks;
+  return v;
+}
+
+// Per-tile data staged in LDS: the rows' start nodes and tile-row masks.
+struct TileMeta {
+  int32_t rs[kTileLdsH];
+  uint64_t bits[kTileY];
+};
+
+// Stage tile (tx, ty): its metadata, then (with load_x) the LDS copy of NS vectors over the
+// tile and its halo (0 at pixels without a node), every thread issuing all of its loads before
+// storing.  Starts and ends with a block barrier.
+template <typename T, int NS>
+__device__ __forceinline__ void tile_stage(const TileView& V, int tx, int ty, const T* const (&x)[NS],
+                                           T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x) {
+  const int tid = static_cast<int>(threadIdx.x);
+  __syncthreads();
+  if (tid < kTileLdsH)
+    m.rs[tid] = V.rowstart[static_cast<int64_t>(ty * kTileY + tid) * V.ntx + tx];
+  else if (tid < kTileLdsH + kTileY)
+    m.bits[tid - kTileLdsH] = V.bits[static_cast<int64_t>(ty * kTileY + tid - kTileLdsH) * V.ntx + tx];
+  __syncthreads();
+  if (!load_x) return;
+  constexpr int kElems = kTileLdsH * kTileLdsW;
+  constexpr int kPer = (kElems + kBlock - 1) / kBlock;
+  int32_t node[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int q = tid + k * kBlock;
+    node[k] = -1;
+    if (q < kElems) {
+      const int r = q / kTileLdsW, cc = q % kTileLdsW;
+      const int32_t rs = m.rs[r];
+      if (rs >= 0) {
+        node[k] = rs + cc;
+      } else {
+        const int gx = tx * kTileX + cc - 2, gy = ty * kTileY + r - 2;
+        if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) node[k] = V.node_of[static_cast<int64_t>(gy) * V.W + gx];
+      }
+    }
+  }
+  T val[NS][kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) val[s][k] = node[k] >= 0 ? x[s][node[k]] : T(0);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int q = tid + k * kBlock;
+    if (q < kElems)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) t[s][q / kTileLdsW][q % kTileLdsW] = val[s][k];
+  }
+  __syncthreads();
+}
+
+constexpr int kTileRowsPerWave = kTileY / (kBlock / 64);
+
+// The wave's local rows ly = wave + 4 k of tile (tx, ty): node i[k] where ok[k] (a tile row).
+__device__ __forceinline__ void tile_row_ids(const TileView& V, int tx, int ty, const TileMeta& m,
+                                             int64_t (&i)[kTileRowsPerWave], bool (&ok)[kTileRowsPerWave]) {
+  const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+  for (int k = 0; k < kTileRowsPerWave; ++k) {
+    const int ly = wave + k * (kBlock / 64);
+    ok[k] = (m.bits[ly] >> lane) & 1ull;
+    const int32_t rs = m.rs[ly + 2];
+    i[k] = 0;
+    if (ok[k])
+      i[k] = rs >= 0 ? static_cast<int64_t>(rs) + 2 + lane
+                     : static_cast<int64_t>(V.node_of[static_cast<int64_t>(ty * kTileY + ly) * V.W + tx * kTileX + lane]);
+  }
+}
+
+// Blocks [0, irr_blocks) call irr(i) for the irregular rows, one per thread (they start first
+// and overlap the tiles).  The tile blocks call tile(tx, ty): blocks are dispatched to the XCDs
+// round-robin, so each XCD gets an equal contiguous share of the tile list (neighbouring tiles
+// then share its L2), which its blocks take in turn.
+template <typename Tile, typename Irr>
+__device__ __forceinline__ void tile_walk(const TileView& V, Tile&& tile, Irr&& irr) {
+  if (static_cast<int>(blockIdx.x) < V.irr_blocks) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < V.nirr;
+         k += static_cast<int64_t>(V.irr_blocks) * blockDim.x)
+      irr(static_cast<int64_t>(V.irr[k]));
+  } else {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) - V.irr_blocks;
+    const int64_t xcd = b % kNumXcd, j = b / kNumXcd, per = V.tile_blocks / kNumXcd;
+    const int64_t t1 = V.ntiles * (xcd + 1) / kNumXcd;
+    for (int64_t k = V.ntiles * xcd / kNumXcd + j; k < t1; k += per) {
+      const int32_t t = V.tiles[k];
+      tile(t % V.ntx, t / V.ntx);
+    }
+  }
+}
+
+}  // namespace vip

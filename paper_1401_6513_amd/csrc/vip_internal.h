@@ -28,6 +28,27 @@ struct Error {
 // row: a lattice node whose stored entries sit at the same lattice offsets and hold, bit
 // for bit, the same values.  Products over such rows read the weights from `w` and find
 // the columns through the lattice map, and give the same bits as the general path.
+// Lattice tiles (tile.h): tiles of kTileX x kTileY pixels, one wavefront wide.
+constexpr int kTileX = 64;
+constexpr int kTileY = 16;
+// Rows of one canonical set (or a pair of sets) split into tile rows and irregular rows.
+struct TilePart {
+  uint64_t* bits = nullptr;         // device [nty*kTileY*ntx]: bit lx of word (y, tx): the node at
+                                    // pixel (64 tx + lx, y) is a tile row
+  int32_t* tiles = nullptr;         // device [ntiles]: tiles (ty * ntx + tx) holding tile rows
+  int64_t ntiles = 0;
+  int32_t* irr = nullptr;           // device [nirr]: every other row, ascending
+  int64_t nirr = 0;
+  int tile_blocks = 0, irr_blocks = 0;   // launch split of a tiled kernel
+};
+// Tile geometry of the lattice.
+struct TileMap {
+  int ntx = 0, nty = 0;
+  int32_t* rowstart = nullptr;      // device [(nty*kTileY + 4) * ntx]: entry (yy, tx) is the node at
+                                    // pixel (64 tx - 2, yy - 2) when pixels 64 tx - 2 .. 64 tx + 65
+                                    // of that lattice row hold consecutive nodes, else -1
+};
+
 struct Canon {
   int K = 0;                        // taps of the reference row (0: none)
   int32_t dx[kMaxTaps], dy[kMaxTaps];
@@ -46,6 +67,8 @@ struct Canon {
   // pixels of one lattice row (then row i0 + l reads them + l), else -1 in the first entry
   int32_t* sbase[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int64_t described[7] = {0, 0, 0, 0, 0, 0, 0};   // rows in described slices, per set
+  // tile partitions (disk taps only): [0] set 0, [1] set 4, [2] sets 1 and 2, [3] sets 5 and 6
+  TilePart tpart[4];
 };
 
 // Sliced ELL matrix: rows grouped by 64; slice s holds width[s] columns stored
@@ -280,6 +303,7 @@ struct Ctx {
   KrylovScalars* sc_host = nullptr; // pinned host mirror
 
   Lattice lat;
+  TileMap tmap;
   VipCanon vcanon;
   Amg amg;
   Learn learn;
@@ -391,6 +415,12 @@ int canon_mark(Ctx* c, Ell& e, int vs);
 // Slice descriptors (Canon::sbase) of canonical-row pixels cpix [n] into out [4 * ceil(n/64)].
 int slice_bases(Ctx* c, const int32_t* cpix, int64_t n, int32_t** out, int64_t* described = nullptr);
 void canon_free(Canon& cn);
+// Tile partition `key` of the system layout's canonical rows (TilePart; key 0: set 0, 1: set 4,
+// 2: sets 1 and 2, 3: sets 5 and 6), rebuilt from the current marks; none unless the
+// reference row is the 21-point disk.
+int tile_part(Ctx* c, int key);
+void tile_part_free(TilePart& tp);
+void tile_map_free(TileMap& tm);
 // Canonical nodes of the VIP and node operators (VipCanon); leaves count = 0 when there are none.
 int vip_canon_setup(Ctx* c);
 void vip_canon_free(Ctx* c);

@@ -83,6 +83,9 @@ PATHS = {
     "extrap": dict(precision="P_MIXED", warmstart="WS_EXTRAP"),
     "fp64": dict(precision="P_FP64", warmstart="WS_PREV"),
     "fp64zero": dict(precision="P_FP64", warmstart="WS_ZERO"),
+    # plain FP64 Krylov: Jacobi preconditioner, previous increment as the start, no learned part
+    # (opt-in: on the cylinder at h = D/128 Jacobi-BiCGStab does not converge)
+    "plain": dict(precision="P_FP64", warmstart="WS_PREV", preconditioner="PC_JACOBI"),
 }
 
 
@@ -96,7 +99,8 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
     for ctx, spec in zip(ctxs, specs):
         opt = vip.default_options(period=spec.period, poisson_tol=tol, inner_tol=inner_tol,
                                   precision=getattr(vip, cfg["precision"]),
-                                  warmstart=getattr(vip, cfg["warmstart"]))
+                                  warmstart=getattr(vip, cfg["warmstart"]),
+                                  preconditioner=getattr(vip, cfg.get("preconditioner", "PC_AMG")))
         ctx.vip_set_options(opt)
         ctx.vip_reset_history()
     state = [_initial(s, dev) for s in specs]
@@ -186,6 +190,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-4,
                     help="relative tolerance of the FP32 inner solve (mixed path)")
     ap.add_argument("--paths", default="learned,mixed,fp64")
+    ap.add_argument("--plain-steps", type=int, default=2,
+                    help="timed steps of the plain path (slow: hundreds of Krylov iterations a step)")
     ap.add_argument("--train-iters", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--serial", action="store_true",
@@ -259,11 +265,13 @@ def main():
         from concurrent.futures import ThreadPoolExecutor
         pool = ThreadPoolExecutor(max_workers=len(ctxs))
     for path in paths:
+        nsteps = args.plain_steps if path == "plain" else args.steps
         el, stats, (spmv, conv), fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
-                                                  args.steps, args.tol, path == paths[0],
+                                                  nsteps, args.tol, path == paths[0],
                                                   args.inner_tol, pool)
-        results[path] = dict(seconds=el, stats=stats, spmv=spmv, conv=conv, fields=fields, dom_s=dom_s)
-        log("%s: %.3f s for %d steps" % (path, el, args.steps))
+        results[path] = dict(seconds=el, stats=stats, spmv=spmv, conv=conv, fields=fields, dom_s=dom_s,
+                             steps=nsteps)
+        log("%s: %.3f s for %d steps" % (path, el, nsteps))
 
     main_path = paths[0]
     r = results[main_path]
@@ -323,20 +331,26 @@ def main():
                       "domains_concurrent": not args.serial}}
     for path, rr in results.items():
         it = [[s["poisson_iters"] for s in row] for row in rr["stats"]]
-        out["path_" + path] = {"value": n_total * args.steps / rr["seconds"],
-                               "ms_per_step": rr["seconds"] / args.steps * 1e3,
-                               "ms_per_step_by_domain": [d / args.steps * 1e3 for d in rr["dom_s"]],
+        out["path_" + path] = {"value": n_total * rr["steps"] / rr["seconds"],
+                               "ms_per_step": rr["seconds"] / rr["steps"] * 1e3,
+                               "steps": rr["steps"],
+                               "ms_per_step_by_domain": [d / rr["steps"] * 1e3 for d in rr["dom_s"]],
                                "poisson_iters": it,
                                "poisson_residual": max(s["poisson_residual"] for row in rr["stats"]
                                                        for s in row)}
+    per_step = {p: rr["seconds"] / rr["steps"] for p, rr in results.items()}
+    if "plain" in results and main_path != "plain":
+        # the plain FP64 GPU path: FP64 Krylov with the Jacobi preconditioner, no learned part
+        out["speedup_vs_plain_fp64"] = per_step["plain"] / per_step[main_path]
     ref_path = "fp64" if "fp64" in results else None
     if ref_path and main_path != ref_path:
-        out["speedup_vs_fp64"] = results[ref_path]["seconds"] / results[main_path]["seconds"]
+        # FP64 Krylov with the same multigrid preconditioner and start vector as the mixed path
+        out["speedup_vs_fp64"] = per_step[ref_path] / per_step[main_path]
         # difference of the paths' fields after the same steps (all solve to 1e-8)
         out["rel_l2_vs_fp64"] = {}
         for path in results:
-            if path == ref_path:
-                continue
+            if path == ref_path or results[path]["steps"] != results[ref_path]["steps"]:
+                continue   # fields are compared after the same number of steps only
             diffs = []
             for a, b in zip(results[path]["fields"], results[ref_path]["fields"]):
                 for k, (x, y) in enumerate(zip(a, b)):

@@ -41,7 +41,8 @@ from paper_1401_6513_amd import nodesets as ns  # noqa: E402
 METRIC = "node-updates/s per fractional step (Poisson to 1e-8), learned+FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 HBM_PROFILE = os.path.join(ROOT, "profiles", "hbm_counters_pressure_spmv_cylinder_h128.md")
-SPMV_SOURCE = os.path.join(ROOT, "paper_1401_6513_amd", "csrc", "krylov.hip")
+# sources of the profiled SpMV kernel (hashed together, in this order)
+SPMV_SOURCES = [os.path.join(ROOT, "paper_1401_6513_amd", "csrc", f) for f in ("krylov.hip", "tile.h")]
 
 
 def measured_traffic():
@@ -51,7 +52,7 @@ def measured_traffic():
     try:
         fields = dict(line.split(": ", 1) for line in open(HBM_PROFILE).read().splitlines()
                       if line.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
-        cur = hashlib.sha256(open(SPMV_SOURCE, "rb").read()).hexdigest()
+        cur = hashlib.sha256(b"".join(open(f, "rb").read() for f in SPMV_SOURCES)).hexdigest()
         if fields.get("source_sha256", "").strip() != cur:
             return None
         return int(fields["traffic_bytes_per_launch"])
@@ -282,25 +283,29 @@ def main():
     if r["spmv"] is not None and r["spmv"][1] > 0:
         n0, _, nnz0 = ctxs[0].vip_operator_shape("poisson")
         fp32 = PATHS[main_path]["precision"] != "P_FP64"
-        counts, taps, desc = ctxs[0].vip_canonical_rows(described=True)
+        counts, taps = ctxs[0].vip_canonical_rows()
         vs = 4 if fp32 else 0
-        nc, nd = int(counts[vs]), int(desc[vs])
+        nc = int(counts[vs])
         vb = 4 if fp32 else 8            # bytes of one vector entry / value
-        # algorithmic bytes of one launch: x gathered once, r-hat read, v written (3 vectors);
-        # stored values + int32 columns of the rows on the general path (and, in FP32, their
-        # row sums); per-row canonical flags outside described slices; one 16-byte descriptor
-        # per described slice.  Canonical rows read no column or value stream.
+        sp = specs[0]
+        W = int(np.floor((sp.xy[:, 0].max() - sp.xy[:, 0].min()) / sp.h + 0.5)) + 1
+        H = int(np.floor((sp.xy[:, 1].max() - sp.xy[:, 1].min()) / sp.h + 0.5)) + 1
+        ntiles = -(-W // 64) * -(-H // 16)
+        # algorithmic bytes of one launch: x read once, r-hat read, v written (3 vectors); stored
+        # values + int32 columns of the irregular rows (and, in FP32, their row sums) and the
+        # irregular-row list; per 64 x 16 tile its 20 row starts and 16 row masks (208 bytes).
+        # Canonical (tile) rows read no column or value stream.
         bytes_per_launch = (3 * vb * n0 + (vb + 4) * (nnz0 - taps * nc) + (4 if fp32 else 0) * (n0 - nc)
-                            + 4 * (n0 - nd) + 16 * (nd // 64))
+                            + 4 * (n0 - nc) + 208 * ntiles)
         avg_ms, count = r["spmv"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic() if abs(h - 1.0 / 128) < 1e-12 else None,
-                "kernel": "k_bicg_v<%s,%s,1> (pressure SpMV)" % (("float", "float") if fp32 else
-                                                                  ("double", "double")),
+                "kernel": "k_bicg_v<%s,%s,1> (pressure SpMV, LDS-tiled canonical rows)" % (
+                    ("float", "float") if fp32 else ("double", "double")),
                 "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms, "launches": count,
-                "rows": n0, "nnz": nnz0, "canonical_rows": nc, "described_rows": nd, "taps": taps,
+                "rows": n0, "nnz": nnz0, "canonical_rows": nc, "tiles": ntiles, "taps": taps,
                 "ell_bytes_per_launch": (vb + 4) * nnz0 + 3 * vb * n0}
 
     roof_mfma = None

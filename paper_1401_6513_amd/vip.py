@@ -268,7 +268,8 @@ class Context:
         return avg.value, cnt.value
 
     def vip_canonical_rows(self, described=False):
-        """(counts per value set [P64, Hu, Hv, -, P32, Hu32, Hv32], taps of the reference row),
+        """(counts per value set [P64, Hu, Hv, step VIP/node rows, P32, Hu32, Hv32], taps of the
+        reference row),
         with the rows of described slices per set as a third item if `described`."""
         counts = np.zeros(7, np.int64)
         desc = np.zeros(7, np.int64)

@@ -106,7 +106,12 @@ void vip_default_options(vip_options* opt);
 
 /* Create a context on HIP device `device` using HIP stream `stream` (NULL =
  * the default stream; a torch stream handle may be passed).  *out receives
- * the context, owned by the caller until vip_destroy. */
+ * the context, owned by the caller until vip_destroy.  Read once here from the
+ * environment (all results keep their bits either way): VIP_NO_CANON=1 sends every
+ * row through the general sliced-ELL path; VIP_CNN_LAYERED=1 runs the learned start
+ * vector's network layer by layer instead of in one fused launch; VIP_AMG_GAMMA,
+ * VIP_AMG_NU, VIP_AMG_NU_COARSE override the multigrid over-correction and sweep
+ * counts (these change results); VIP_DEBUG=1 prints solver progress to stderr. */
 int vip_create(void** out, int device, void* stream);
 
 /* Release every device allocation of the context and the context itself. */
@@ -315,7 +320,8 @@ int vip_canonical_rows(void* ctx, int64_t* counts, int64_t* described, int* taps
  * HIP events on the context stream while timing is enabled; *count receives the number of
  * timed launches.  which = 0: the pressure-solve SpMV (the first SpMV of each Krylov
  * iteration; launches after the solve stopped on the device are not counted); which = 1:
- * each of the two 32 -> 32 MFMA layers of the learned start vector's inference.  enable = 0
+ * the learned start vector's inference (the fused 4-layer launch, or each 32 -> 32 layer
+ * when VIP_CNN_LAYERED=1 was set at vip_create).  enable = 0
  * stops timing; reset = 1 clears it.  Errors: VIP_E_INVALID (unknown which). */
 int vip_kernel_timing(void* ctx, int which, int enable, int reset, double* avg_ms, int64_t* count);
 

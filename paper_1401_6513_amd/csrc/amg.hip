@@ -405,12 +405,20 @@ __device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
   else return a0 + a1;
 }
 
+// W b at row j, as a rounded product: without contraction, so that no fused multiply-add
+// folds it into the arithmetic of a sweep that recomputes it
+template <typename T>
+__device__ __forceinline__ T zero_start_value(const T* wdinv, const T* b, int64_t j) {
+#pragma clang fp contract(off)
+  return wdinv[j] * b[j];
+}
+
 // x = W b   (damped Jacobi sweep from a zero start)
 template <typename T>
 __global__ void k_jacobi0(LevelView<T> L, const T* b, T* x, const int* on) {
   if (!*on) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i < L.n) x[i] = L.wdinv[i] * b[i];
+  if (i < L.n) x[i] = zero_start_value(L.wdinv, b, i);
 }
 
 // r = b - A x
@@ -461,6 +469,15 @@ __global__ void k_restrict(int64_t nc, const int64_t* mstart, const int32_t* mem
   bc[I] = s;
 }
 
+// x_i + gamma xc[agg_i] (x may be absent; rows outside every aggregate get no correction),
+// without contraction so that kernels recomputing it get the same bits
+template <typename T>
+__device__ __forceinline__ T prolong_value(const int32_t* agg, const T* xc, T gamma, const T* x, int64_t i) {
+#pragma clang fp contract(off)
+  const int32_t a = agg[i];
+  return (x ? x[i] : T(0)) + (a >= 0 ? gamma * xc[a] : T(0));
+}
+
 // y = x + P xc   (coarse correction; x may be absent: zero pre-smoothing)
 template <typename T>
 __global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, T gamma, const T* x, T* y,
@@ -468,24 +485,47 @@ __global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, T gamma, c
   if (!*on) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
-  const int32_t a = agg[i];
-  y[i] = (x ? x[i] : T(0)) + (a >= 0 ? gamma * xc[a] : T(0));
+  y[i] = prolong_value(agg, xc, gamma, x, i);
 }
 
-// out = y + W (b - A y)   (damped Jacobi sweep)
+// The iterate a smoothing sweep starts from: y in memory (kind 0), the zero-start sweep's W b
+// (kind 1, the output of k_jacobi0), or the prolonged correction y + gamma P xc (kind 2, the
+// output of k_prolong).  Kinds 1 and 2 recompute the value wherever it is needed, with the
+// same arithmetic as the kernel that would have stored it, so the fused sweep gives the same
+// bits as the two launches it replaces.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_jacobi(LevelView<T> L, const T* b, const T* y, T* out, const int* on) {
+struct SweepIn {
+  const T* y;              // kinds 0 and 2 (kind 2: may be null)
+  const T* b;              // kind 1
+  const int32_t* agg;      // kind 2
+  const T* xc;
+  T gamma;
+};
+
+template <typename T, int KIND>
+__device__ __forceinline__ T sweep_in(const LevelView<T>& L, const SweepIn<T>& in, int64_t j) {
+  if constexpr (KIND == 0) return in.y[j];
+  else if constexpr (KIND == 1) return zero_start_value(L.wdinv, in.b, j);
+  else return prolong_value(in.agg, in.xc, in.gamma, in.y, j);
+}
+
+// out = y + W (b - A y)   (damped Jacobi sweep from the iterate of kind KIND)
+template <typename T, int KIND>
+__global__ void __launch_bounds__(kBlock) k_sweep(LevelView<T> L, const T* b, SweepIn<T> in, T* out,
+                                                  const int* on) {
   __shared__ T lds[1][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta;
   if (!*on) return;
+  auto yf = [&](int64_t j) __attribute__((always_inline)) { return sweep_in<T, KIND>(L, in, j); };
   if (L.tv.tiles) {
     // tile rows: the damped inverse diagonal from memory (equal to the reference one where
     // that applies, so the same bits)
-    const T* ys[1] = {y};
     tile_walk(
         L.tv,
         [&](int tx, int ty) __attribute__((always_inline)) {
-          tile_stage<T, 1>(L.tv, tx, ty, ys, lds, meta, true);
+          tile_stage_fn<T, 1>(
+              L.tv, tx, ty, [&](int, int32_t node) __attribute__((always_inline)) { return yf(node); }, lds, meta,
+              true);
           int64_t ii[kTileRowsPerWave];
           bool ok[kTileRowsPerWave];
           tile_row_ids(L.tv, tx, ty, meta, ii, ok);
@@ -506,16 +546,16 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(LevelView<T> L, const T* b, c
           }
         },
         [&](int64_t i) __attribute__((always_inline)) {
-          const T ay = level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return y[j]; });
-          out[i] = y[i] + level_wdinv(L, i) * (b[i] - ay);
+          const T ay = level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return yf(j); });
+          out[i] = yf(i) + level_wdinv(L, i) * (b[i] - ay);
         });
     return;
   }
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = lb * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
-  const T ay = level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return y[j]; });
-  out[i] = y[i] + level_wdinv(L, i) * (b[i] - ay);
+  const T ay = level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return yf(j); });
+  out[i] = yf(i) + level_wdinv(L, i) * (b[i] - ay);
 }
 
 // x[0..rows) = Inv[0..rows, 0..cols) b on the coarsest level (one wavefront per row);
@@ -824,10 +864,17 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
       T* a1 = w(l, 1);
       T* a2 = w(l, 2);
       const LevelView<T> lv = view<T>(c, l);
-      k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(lv, rhs, a1, on);
-      for (int k = 1; k < nu; ++k) {
-        k_jacobi<T><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, a1, a2, on);
-        std::swap(a1, a2);
+      if (nu == 1) {
+        k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(lv, rhs, a1, on);
+      } else {
+        // zero start and the first sweep in one launch
+        k_sweep<T, 1><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, SweepIn<T>{nullptr, rhs, nullptr, nullptr, T(0)},
+                                                          a1, on);
+        for (int k = 2; k < nu; ++k) {
+          k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, SweepIn<T>{a1, nullptr, nullptr, nullptr, T(0)},
+                                                            a2, on);
+          std::swap(a1, a2);
+        }
       }
       k_level_residual<T><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, a1, a2, on);
       cur[l] = a1;
@@ -845,16 +892,27 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     const AmgLevel& L = g.lv[l];
     const int nu = l == 0 ? c->amg_nu : c->amg_nu_coarse;
     const T* bl = (l == 0) ? b : w(l, 0);
-    // y = pre-smoothed iterate + gamma P xc into the buffer that is not cur[l]
-    T* y = (cur[l] == w(l, 2)) ? w(l, 1) : w(l, 2);
-    T* other = (y == w(l, 1)) ? w(l, 2) : w(l, 1);
-    k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, gamma, cur[l], y, on);
+    // buffer that is not cur[l], and the other one (free once the first sweep has read cur[l])
+    T* ybuf = (cur[l] == w(l, 2)) ? w(l, 1) : w(l, 2);
+    T* obuf = (ybuf == w(l, 1)) ? w(l, 2) : w(l, 1);
     const LevelView<T> lv = view<T>(c, l);
-    for (int k = 0; k < nu; ++k) {
-      T* out = (l == 0 && k == nu - 1) ? x : other;
-      k_jacobi<T><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, y, out, on);
-      other = y;
+    T* y = ybuf;
+    if (nu == 0) {
+      k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, gamma, cur[l], y, on);
+    } else {
+      // prolongation and the first sweep in one launch
+      T* out = (l == 0 && nu == 1) ? x : ybuf;
+      k_sweep<T, 2><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, SweepIn<T>{cur[l], nullptr, L.agg, xc, gamma}, out,
+                                                        on);
       y = out;
+      T* other = obuf;
+      for (int k = 1; k < nu; ++k) {
+        T* o = (l == 0 && k == nu - 1) ? x : other;
+        k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, SweepIn<T>{y, nullptr, nullptr, nullptr, T(0)}, o,
+                                                          on);
+        other = y;
+        y = o;
+      }
     }
     xc = y;
   }

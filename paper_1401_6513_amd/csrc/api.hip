@@ -150,6 +150,8 @@ int vip_create(void** out, int device, void* stream) {
   c->debug = (dbg && dbg[0] == '1') ? 1 : 0;
   const char* nc = std::getenv("VIP_NO_CANON");
   c->no_canon = (nc && nc[0] == '1') ? 1 : 0;
+  const char* cl = std::getenv("VIP_CNN_LAYERED");
+  c->cnn_layered = (cl && cl[0] == '1') ? 1 : 0;
   const char* pre = std::getenv("VIP_AMG_PRE_FINE");
   c->amg_pre_fine = (pre && pre[0] == '0') ? 0 : 1;
   if (const char* g = std::getenv("VIP_AMG_GAMMA")) c->amg_gamma = std::min(2.0, std::max(0.5, std::atof(g)));

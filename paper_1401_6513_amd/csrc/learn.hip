@@ -57,31 +57,87 @@ __device__ __forceinline__ bool inside(const Img& g, int i, int j) {
 
 // ---- forward ------------------------------------------------------------------------------------
 
-// layer 1 (3 -> 32), direct: one thread per pixel
-__global__ void k_conv_in(Img g, const bf16_t* x, const bf16_t* w1, const float* b1, bf16_t* out) {
-  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
-  if (p >= np) return;
-  const int j = static_cast<int>(p % g.W), i = static_cast<int>((p / g.W) % g.H);
-  const int64_t b = p / (static_cast<int64_t>(g.H) * g.W);
-  float acc[kC];
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
+  return static_cast<uint32_t>(f2bf(a)) | (static_cast<uint32_t>(f2bf(b)) << 16);
+}
+
+// Layer 1 (3 -> 32) as one MFMA K-step: k = 3 t + ci over the 9 taps and 3 channels (27 of the
+// 32 K slots, the rest 0).  A = weights (16 output channels x 32 k for this lane's row),
+// B = the pixel's 27 tap values (lane: 8 consecutive k of pixel l % 16).  in(t, ci) returns the
+// BF16 bits of tap t, channel ci (0 outside the image).
+__device__ __forceinline__ bf16x8 l1_weights(const bf16_t* w1, int m, int n, int kq) {
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-  for (int c = 0; c < kC; ++c) acc[c] = b1[c];
-  for (int t = 0; t < 9; ++t) {
-    const int ii = i + t / 3 - 1, jj = j + t % 3 - 1;
-    if (!inside(g, ii, jj)) continue;
-    const bf16_t* xp = x + ((b * g.H + ii) * g.W + jj) * kCin;
+  for (int j = 0; j < 8; ++j) {
+    const int k = kq + j;
+    const uint32_t v = k < 9 * kCin ? w1[k * kC + m * 16 + n] : 0u;
+    w[j / 2] |= v << (16 * (j % 2));
+  }
+  return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+}
+
+template <class In>
+__device__ __forceinline__ bf16x8 l1_operand(int kq, In&& in) {
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int ci = 0; ci < kCin; ++ci) {
-      const float xv = bf2f(xp[ci]);
-      const bf16_t* wp = w1 + (t * kCin + ci) * kC;
+  for (int j = 0; j < 8; ++j) {
+    const int k = kq + j;
+    const uint32_t v = k < 9 * kCin ? static_cast<uint32_t>(in(k / kCin, k % kCin)) : 0u;
+    w[j / 2] |= v << (16 * (j % 2));
+  }
+  return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+}
+
+// Layer 4 (32 -> 1): one MFMA K-step per tap with only output row 0 of the A tile nonzero; lane
+// l < 16 ends with the output of pixel l.
+__device__ __forceinline__ bf16x8 l4_weights(const bf16_t* w4, int t, int n, int kq) {
+  if (n != 0) return __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(w4 + t * kC + kq));
+}
+
+// 16-pixel strips of image rows handled by one wavefront each pass (layers 1, 2, 3 and 4)
+constexpr int kStripsPerWave = 8;
+
+// layer 1 (3 -> 32) on MFMA, strips of 16 pixels of one image row; lane l ends with 4
+// consecutive output channels of pixel l % 16 per output-channel tile
+__global__ __launch_bounds__(256) void k_conv_in(Img g, const bf16_t* x, const bf16_t* w1, const float* b1,
+                                                 bf16_t* out, int64_t nstrips) {
+  const int64_t wv = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
+  const int64_t s0 = wv * kStripsPerWave;
+  if (s0 >= nstrips) return;
+  const int l = threadIdx.x & 63;
+  const int kq = (l >> 4) * 8;
+  const int n = l & 15;
+  const int cq = (l >> 4) * 4;
+  const bf16x8 wa0 = l1_weights(w1, 0, n, kq), wa1 = l1_weights(w1, 1, n, kq);
+  float bv[2][4];
 #pragma unroll
-      for (int c = 0; c < kC; ++c) acc[c] += xv * bf2f(wp[c]);
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bv[m][r] = b1[m * 16 + cq + r];
+  const int strips_w = (g.W + 15) / 16;
+  for (int64_t s = s0; s < s0 + kStripsPerWave && s < nstrips; ++s) {
+    const int j0 = static_cast<int>(s % strips_w) * 16;
+    const int i = static_cast<int>((s / strips_w) % g.H);
+    const int b = static_cast<int>(s / (static_cast<int64_t>(strips_w) * g.H));
+    const int j = j0 + n;
+    const bf16x8 xb = l1_operand(kq, [&](int t, int ci) -> bf16_t {
+      const int ii = i + t / 3 - 1, jj = j + t % 3 - 1;
+      return inside(g, ii, jj) ? x[((static_cast<int64_t>(b) * g.H + ii) * g.W + jj) * kCin + ci] : bf16_t(0);
+    });
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, xb, z, 0, 0, 0);
+    const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, xb, z, 0, 0, 0);
+    if (j < g.W) {
+      bf16_t* op = out + ((static_cast<int64_t>(b) * g.H + i) * g.W + j) * kC + cq;
+      *reinterpret_cast<uint2*>(op) =
+          make_uint2(pack_bf2(fmaxf(d0[0] + bv[0][0], 0.0f), fmaxf(d0[1] + bv[0][1], 0.0f)),
+                     pack_bf2(fmaxf(d0[2] + bv[0][2], 0.0f), fmaxf(d0[3] + bv[0][3], 0.0f)));
+      *reinterpret_cast<uint2*>(op + 16) =
+          make_uint2(pack_bf2(fmaxf(d1[0] + bv[1][0], 0.0f), fmaxf(d1[1] + bv[1][1], 0.0f)),
+                     pack_bf2(fmaxf(d1[2] + bv[1][2], 0.0f), fmaxf(d1[3] + bv[1][3], 0.0f)));
     }
   }
-  bf16_t* op = out + p * kC;
-#pragma unroll
-  for (int c = 0; c < kC; ++c) op[c] = f2bf(fmaxf(acc[c], 0.0f));
 }
 
 // MFMA tile over 16 pixels of one image row: D[pixel][n] += sum_taps A_tap[pixel][k] B_tap[k][n]
@@ -112,13 +168,7 @@ __device__ __forceinline__ void mfma_strip(const Img& g, int b, int i, int j0, c
 // per 16-pixel strip: A = weights (16 output channels x 32 input channels of one tap, held in
 // registers for the whole wave), B = activations (32 channels x 16 pixels, one 16-byte load
 // per lane), two output-channel tiles.  Lane l ends with 4 consecutive output channels of
-// pixel l % 16, stored as one 8-byte write per tile.  Each wave takes kStripsPerWave strips.
-constexpr int kStripsPerWave = 8;
-
-__device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
-  return static_cast<uint32_t>(f2bf(a)) | (static_cast<uint32_t>(f2bf(b)) << 16);
-}
-
+// pixel l % 16, stored as one 8-byte write per tile.
 __global__ __launch_bounds__(256) void k_conv_mid(Img g, const bf16_t* x, const bf16_t* wt, const float* bias,
                                                   bf16_t* out, int64_t nstrips) {
   const int64_t wv = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
@@ -168,23 +218,183 @@ __global__ __launch_bounds__(256) void k_conv_mid(Img g, const bf16_t* x, const 
   }
 }
 
-// layer 4 (32 -> 1), direct: one thread per pixel
-__global__ void k_conv_out(Img g, const bf16_t* x, const bf16_t* w4, const float* b4, float* y) {
-  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
-  if (p >= np) return;
-  const int j = static_cast<int>(p % g.W), i = static_cast<int>((p / g.W) % g.H);
-  const int64_t b = p / (static_cast<int64_t>(g.H) * g.W);
-  float acc = b4[0];
-  for (int t = 0; t < 9; ++t) {
-    const int ii = i + t / 3 - 1, jj = j + t % 3 - 1;
-    if (!inside(g, ii, jj)) continue;
-    const bf16_t* xp = x + ((b * g.H + ii) * g.W + jj) * kC;
-    const bf16_t* wp = w4 + t * kC;
+// layer 4 (32 -> 1) on MFMA, strips of 16 pixels of one image row
+__global__ __launch_bounds__(256) void k_conv_out(Img g, const bf16_t* x, const bf16_t* w4, const float* b4,
+                                                  float* y, int64_t nstrips) {
+  const int64_t wv = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / 64;
+  const int64_t s0 = wv * kStripsPerWave;
+  if (s0 >= nstrips) return;
+  const int l = threadIdx.x & 63;
+  const int kq = (l >> 4) * 8;
+  const int n = l & 15;
+  bf16x8 wa[9];
 #pragma unroll
-    for (int c = 0; c < kC; ++c) acc += bf2f(xp[c]) * bf2f(wp[c]);
+  for (int t = 0; t < 9; ++t) wa[t] = l4_weights(w4, t, n, kq);
+  const float bias = b4[0];
+  const int strips_w = (g.W + 15) / 16;
+  for (int64_t s = s0; s < s0 + kStripsPerWave && s < nstrips; ++s) {
+    const int j0 = static_cast<int>(s % strips_w) * 16;
+    const int i = static_cast<int>((s / strips_w) % g.H);
+    const int b = static_cast<int>(s / (static_cast<int64_t>(strips_w) * g.H));
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int ii = i + (t / 3 - 1), jj = j0 + n + (t % 3 - 1);
+      uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+      if (inside(g, ii, jj))
+        raw = *reinterpret_cast<const uint4*>(x + ((static_cast<int64_t>(b) * g.H + ii) * g.W + jj) * kC + kq);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t], __builtin_bit_cast(bf16x8, raw), d, 0, 0, 0);
+    }
+    const int j = j0 + n;
+    if (l < 16 && j < g.W) y[(static_cast<int64_t>(b) * g.H + i) * g.W + j] = d[0] + bias;
   }
-  y[p] = acc;
+}
+
+// ---- fused inference ---------------------------------------------------------------------------------
+
+// All four layers on one 16 x 16 tile of output pixels per block, activations in LDS: the
+// input region with a halo of 4, layer 1 on 22 x 22 pixels (VALU), layers 2 and 3 on 20 x 20
+// and 18 x 18 (MFMA, groups of 16 pixels in any arrangement), layer 4 on the tile (VALU).
+// Pixels outside the image hold 0 after every layer and taps outside the image are skipped, as
+// in the layer-by-layer kernels, whose arithmetic (tap and channel order, MFMA operands,
+// BF16 rounding of each layer's output) it repeats, so the output has the same bits.
+constexpr int kFT = 16;             // output tile side
+constexpr int kR0 = kFT + 8;        // input region side
+constexpr int kR1 = kFT + 6;        // layer-1 region side
+constexpr int kR2 = kFT + 4;        // layer-2 region side
+constexpr int kR3 = kFT + 2;        // layer-3 region side
+constexpr int kPx = 40;             // LDS stride of one pixel's 32 channels (80 bytes: the
+                                    // 16-byte reads of 16 consecutive pixels hit 64 distinct banks)
+
+__global__ __launch_bounds__(256) void k_cnn_fused(Img g, const bf16_t* x, const bf16_t* w1, const float* b1,
+                                                   const bf16_t* w2t, const float* b2, const bf16_t* w3t,
+                                                   const float* b3, const bf16_t* w4, const float* b4, float* y) {
+  __shared__ bf16_t s_in[kR0 * kR0 * kCin];
+  __shared__ __attribute__((aligned(16))) bf16_t s_a[kR1 * kR1 * kPx];   // layer 1, later layer 3
+  __shared__ __attribute__((aligned(16))) bf16_t s_b[kR2 * kR2 * kPx];   // layer 2
+  const int tid = static_cast<int>(threadIdx.x);
+  const int b = static_cast<int>(blockIdx.z);
+  const int oi = static_cast<int>(blockIdx.y) * kFT, oj = static_cast<int>(blockIdx.x) * kFT;   // tile origin
+  // input region (origin oi - 4, oj - 4), zero outside the image
+  for (int q = tid; q < kR0 * kR0; q += blockDim.x) {
+    const int ii = oi - 4 + q / kR0, jj = oj - 4 + q % kR0;
+    bf16_t v0 = 0, v1 = 0, v2 = 0;
+    if (inside(g, ii, jj)) {
+      const bf16_t* xp = x + ((static_cast<int64_t>(b) * g.H + ii) * g.W + jj) * kCin;
+      v0 = xp[0];
+      v1 = xp[1];
+      v2 = xp[2];
+    }
+    s_in[q * kCin] = v0;
+    s_in[q * kCin + 1] = v1;
+    s_in[q * kCin + 2] = v2;
+  }
+  __syncthreads();
+  const int l = tid & 63, wave = tid >> 6;
+  const int kq = (l >> 4) * 8;
+  const int n = l & 15;
+  const int cq = (l >> 4) * 4;
+  // layer 1 on region 1 (side kR1, origin oi - 3, oj - 3), 16 pixels per MFMA group
+  {
+    const bf16x8 wa0 = l1_weights(w1, 0, n, kq), wa1 = l1_weights(w1, 1, n, kq);
+    float bv[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bv[m][r] = b1[m * 16 + cq + r];
+    constexpr int np = kR1 * kR1, groups = (np + 15) / 16;
+    for (int grp = wave; grp < groups; grp += kBlock / 64) {
+      const int q = grp * 16 + n;
+      const int qc = q < np ? q : np - 1;
+      const int r = qc / kR1, cc = qc % kR1;
+      const int i = oi - 3 + r, j = oj - 3 + cc;
+      const bf16x8 xb = l1_operand(kq, [&](int t, int ci) -> bf16_t {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        return inside(g, i + dy, j + dx) ? s_in[((r + 1 + dy) * kR0 + (cc + 1 + dx)) * kCin + ci] : bf16_t(0);
+      });
+      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+      const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, xb, z, 0, 0, 0);
+      const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, xb, z, 0, 0, 0);
+      if (q < np) {
+        uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
+        if (inside(g, i, j)) {
+          v0 = make_uint2(pack_bf2(fmaxf(d0[0] + bv[0][0], 0.0f), fmaxf(d0[1] + bv[0][1], 0.0f)),
+                          pack_bf2(fmaxf(d0[2] + bv[0][2], 0.0f), fmaxf(d0[3] + bv[0][3], 0.0f)));
+          v1 = make_uint2(pack_bf2(fmaxf(d1[0] + bv[1][0], 0.0f), fmaxf(d1[1] + bv[1][1], 0.0f)),
+                          pack_bf2(fmaxf(d1[2] + bv[1][2], 0.0f), fmaxf(d1[3] + bv[1][3], 0.0f)));
+        }
+        *reinterpret_cast<uint2*>(s_a + q * kPx + cq) = v0;
+        *reinterpret_cast<uint2*>(s_a + q * kPx + 16 + cq) = v1;
+      }
+    }
+  }
+  __syncthreads();
+  // layers 2 and 3: 16 pixels of the output region per MFMA group, region rs (side) from the
+  // region of side rs + 2 in src, into dst; origin of the output region oi - h, oj - h
+  auto mid = [&](const bf16_t* wt, const float* bias, const bf16_t* src, bf16_t* dst, int rs, int hal)
+      __attribute__((always_inline)) {
+    bf16x8 wa[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        wa[t][m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wt + (t * kC + m * 16 + n) * kC + kq));
+    float bv[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bv[m][r] = bias[m * 16 + cq + r];
+    const int np = rs * rs, groups = (np + 15) / 16;
+    for (int grp = wave; grp < groups; grp += kBlock / 64) {
+      const int q = grp * 16 + n;
+      const int qc = q < np ? q : np - 1;     // the last group's spare lanes repeat a pixel
+      const int r = qc / rs, cc = qc % rs;
+      f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int sr = r + 1 + (t / 3 - 1), sc = cc + 1 + (t % 3 - 1);
+        const bf16x8 xb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + (sr * (rs + 2) + sc) * kPx + kq));
+        d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][0], xb, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][1], xb, d1, 0, 0, 0);
+      }
+      if (q < np) {
+        const int i = oi - hal + r, j = oj - hal + cc;
+        uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
+        if (inside(g, i, j)) {
+          v0 = make_uint2(pack_bf2(fmaxf(d0[0] + bv[0][0], 0.0f), fmaxf(d0[1] + bv[0][1], 0.0f)),
+                          pack_bf2(fmaxf(d0[2] + bv[0][2], 0.0f), fmaxf(d0[3] + bv[0][3], 0.0f)));
+          v1 = make_uint2(pack_bf2(fmaxf(d1[0] + bv[1][0], 0.0f), fmaxf(d1[1] + bv[1][1], 0.0f)),
+                          pack_bf2(fmaxf(d1[2] + bv[1][2], 0.0f), fmaxf(d1[3] + bv[1][3], 0.0f)));
+        }
+        *reinterpret_cast<uint2*>(dst + q * kPx + cq) = v0;
+        *reinterpret_cast<uint2*>(dst + q * kPx + 16 + cq) = v1;
+      }
+    }
+  };
+  mid(w2t, b2, s_a, s_b, kR2, 2);
+  __syncthreads();
+  mid(w3t, b3, s_b, s_a, kR3, 1);
+  __syncthreads();
+  // layer 4 on the tile (16 x 16), 16 pixels per MFMA group
+  {
+    bf16x8 wa[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) wa[t] = l4_weights(w4, t, n, kq);
+    const float bias = b4[0];
+    for (int grp = wave; grp < kFT * kFT / 16; grp += kBlock / 64) {
+      const int q = grp * 16 + n;
+      const int r = q / kFT, cc = q % kFT;
+      f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int sr = r + 1 + (t / 3 - 1), sc = cc + 1 + (t % 3 - 1);
+        const bf16x8 xb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s_a + (sr * kR3 + sc) * kPx + kq));
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t], xb, d, 0, 0, 0);
+      }
+      const int i = oi + r, j = oj + cc;
+      if (l < 16 && inside(g, i, j)) y[(static_cast<int64_t>(b) * g.H + i) * g.W + j] = d[0] + bias;
+    }
+  }
 }
 
 // ---- loss -----------------------------------------------------------------------------------------
@@ -567,16 +777,36 @@ __global__ void k_rms_part(int64_t n, const int32_t* pix, const double* a, const
 }
 
 // scal[0], scal[1] = the two rms values (fixed block order)
-__global__ void k_rms_finish(int nb, const double* part, double* scal) {
-  if (threadIdx.x != 0) return;
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int k = 0; k < nb; ++k) {
-    a += part[3 * k];
-    b += part[3 * k + 1];
-    c += part[3 * k + 2];
+// Sums of NV values over nb block partials part[k * NV + a], in a fixed order (thread t adds
+// blocks t, t + 256, ..., then a tree over the threads), valid in thread 0.  256 threads.
+template <int NV>
+__device__ __forceinline__ void sum_partials(int nb, const double* part, double (&tot)[NV]) {
+  __shared__ double sh[NV][256];
+  double acc[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) acc[a] = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256)
+#pragma unroll
+    for (int a = 0; a < NV; ++a) acc[a] += part[NV * k + a];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) sh[a][threadIdx.x] = acc[a];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off)
+#pragma unroll
+      for (int a = 0; a < NV; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + off];
+    __syncthreads();
   }
-  scal[0] = c > 0.0 ? sqrt(a / c) : 0.0;
-  scal[1] = c > 0.0 ? sqrt(b / c) : 0.0;
+#pragma unroll
+  for (int a = 0; a < NV; ++a) tot[a] = sh[a][0];
+}
+
+__global__ void k_rms_finish(int nb, const double* part, double* scal) {
+  double t[3];
+  sum_partials<3>(nb, part, t);
+  if (threadIdx.x != 0) return;
+  scal[0] = t[2] > 0.0 ? sqrt(t[0] / t[2]) : 0.0;
+  scal[1] = t[2] > 0.0 ? sqrt(t[1] / t[2]) : 0.0;
 }
 
 // block partials of q1.q1, q1.q2, q2.q2, q1.r, q2.r, r.r (q2 may be null: its terms are 0)
@@ -605,10 +835,9 @@ __global__ void k_dots6_part(int64_t n, const double* q1, const double* q2, cons
 
 // scal[2 + k] = sum over blocks of dot k (fixed block order)
 __global__ void k_dots6_finish(int nb, const double* part, double* scal) {
-  if (threadIdx.x >= 6) return;
-  double a = 0.0;
-  for (int k = 0; k < nb; ++k) a += part[6 * k + threadIdx.x];
-  scal[2 + threadIdx.x] = a;
+  double t[6];
+  sum_partials<6>(nb, part, t);
+  if (threadIdx.x < 6) scal[2 + threadIdx.x] = t[threadIdx.x];
 }
 
 // splitmix64 (Steele, Lea and Flood 2014): a counter-based 64-bit generator
@@ -620,6 +849,7 @@ uint64_t splitmix64(uint64_t x) {
 }
 
 constexpr int kSumBlocks = 256;
+constexpr int kRedBlocks = 1024;   // blocks of the whole-node-set reductions (8 wavefronts per SIMD)
 
 }  // namespace
 
@@ -646,6 +876,10 @@ struct Net {
   int64_t part_len = 0;
   double* dscal = nullptr;    // [0] loss, [1] mask count, then partials
   int64_t dscal_len = 0;
+  // inference on a whole lattice image (fused kernel): input and output only
+  bf16_t* ix = nullptr;
+  float* iy = nullptr;
+  int64_t icap = 0;
 };
 
 void learn_clear(Ctx* c) {
@@ -668,8 +902,9 @@ void learn_free(Ctx* c) {
     Net* N = static_cast<Net*>(L.net);
     for (float** p : {&N->theta, &N->grad, &N->m, &N->v, &N->y, &N->t, &N->mask, &N->gy, &N->part}) dfree(*p);
     for (bf16_t** p : {&N->w1, &N->w2f, &N->w2b, &N->w3f, &N->w3b, &N->w4, &N->x, &N->a1, &N->a2, &N->a3,
-                       &N->g3, &N->g2, &N->g1})
+                       &N->g3, &N->g2, &N->g1, &N->ix})
       dfree(*p);
+    dfree(N->iy);
     dfree(N->dscal);
     delete N;
     L.net = nullptr;
@@ -727,6 +962,18 @@ int net_buffers(Ctx* c, int64_t npix) {
   return VIP_OK;
 }
 
+int infer_buffers(Ctx* c, int64_t npix) {
+  Net* N = net_of(c);
+  if (N->icap >= npix) return VIP_OK;
+  VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dfree(N->ix);
+  dfree(N->iy);
+  VIP_TRY(dalloc(c, &N->ix, npix * kCin));
+  VIP_TRY(dalloc(c, &N->iy, npix));
+  N->icap = npix;
+  return VIP_OK;
+}
+
 int ensure_part(Ctx* c, int64_t floats, int64_t doubles) {
   Net* N = net_of(c);
   if (N->part_len < floats || N->dscal_len < doubles) VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -758,12 +1005,11 @@ int64_t blocks_for(int64_t items) { return (items + kBlock - 1) / kBlock; }
 int forward(Ctx* c, const Img& g, bool timed = false) {
   Net* N = net_of(c);
   hipStream_t st = c->stream;
-  const int64_t np = static_cast<int64_t>(g.B) * g.H * g.W;
   const int64_t nstrips = static_cast<int64_t>(g.B) * g.H * ((g.W + 15) / 16);
   const int64_t cwaves = (nstrips + kStripsPerWave - 1) / kStripsPerWave;
   const int64_t cblocks = blocks_for(cwaves * 64);
   timed = timed && c->conv_timing.enabled;
-  k_conv_in<<<blocks_for(np), kBlock, 0, st>>>(g, N->x, N->w1, N->theta + kB1, N->a1);
+  k_conv_in<<<cblocks, kBlock, 0, st>>>(g, N->x, N->w1, N->theta + kB1, N->a1, nstrips);
   for (int layer = 0; layer < 2; ++layer) {
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (timed) {
@@ -786,8 +1032,37 @@ int forward(Ctx* c, const Img& g, bool timed = false) {
       c->conv_timing.pending.push_back(ev);
     }
   }
-  k_conv_out<<<blocks_for(np), kBlock, 0, st>>>(g, N->a3, N->w4, N->theta + kB4, N->y);
+  k_conv_out<<<cblocks, kBlock, 0, st>>>(g, N->a3, N->w4, N->theta + kB4, N->y, nstrips);
   VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+// inference over g in one launch (k_cnn_fused), input in N->ix, prediction in N->iy; timed: HIP
+// events around the launch into c->conv_timing
+int forward_fused(Ctx* c, const Img& g, bool timed) {
+  Net* N = net_of(c);
+  hipStream_t st = c->stream;
+  timed = timed && c->conv_timing.enabled;
+  std::pair<hipEvent_t, hipEvent_t> ev{};
+  if (timed) {
+    if (c->conv_timing.pool.empty()) {
+      hipEvent_t a, b;
+      VIP_HIP_TRY(c, hipEventCreate(&a));
+      VIP_HIP_TRY(c, hipEventCreate(&b));
+      c->conv_timing.pool.push_back({a, b});
+    }
+    ev = c->conv_timing.pool.back();
+    c->conv_timing.pool.pop_back();
+    VIP_HIP_TRY(c, hipEventRecord(ev.first, st));
+  }
+  const dim3 grid((g.W + kFT - 1) / kFT, (g.H + kFT - 1) / kFT, g.B);
+  k_cnn_fused<<<grid, kBlock, 0, st>>>(g, N->ix, N->w1, N->theta + kB1, N->w2f, N->theta + kB2, N->w3f,
+                                       N->theta + kB3, N->w4, N->theta + kB4, N->iy);
+  VIP_HIP_TRY(c, hipGetLastError());
+  if (timed) {
+    VIP_HIP_TRY(c, hipEventRecord(ev.second, st));
+    c->conv_timing.pending.push_back(ev);
+  }
   return VIP_OK;
 }
 
@@ -878,8 +1153,8 @@ constexpr int kScalHead = 16;
 // rms of a h^2 and c h^2 over lattice nodes into scal[0], scal[1]
 int lattice_rms(Ctx* c, const double* a, const double* cv) {
   Learn& L = c->learn;
-  k_rms_part<<<kSumBlocks, 256, 0, c->stream>>>(c->n, c->lat.pix, a, cv, c->h * c->h, L.scal + kScalHead);
-  k_rms_finish<<<1, 64, 0, c->stream>>>(kSumBlocks, L.scal + kScalHead, L.scal);
+  k_rms_part<<<kRedBlocks, 256, 0, c->stream>>>(c->n, c->lat.pix, a, cv, c->h * c->h, L.scal + kScalHead);
+  k_rms_finish<<<1, 256, 0, c->stream>>>(kRedBlocks, L.scal + kScalHead, L.scal);
   VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;
 }
@@ -888,7 +1163,7 @@ int ensure_vectors(Ctx* c) {
   Learn& L = c->learn;
   if (L.r) return VIP_OK;
   for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2}) VIP_TRY(dalloc(c, p, c->n));
-  VIP_TRY(dalloc(c, &L.scal, kScalHead + 6 * kSumBlocks));
+  VIP_TRY(dalloc(c, &L.scal, kScalHead + 6 * kRedBlocks));
   return VIP_OK;
 }
 
@@ -1030,15 +1305,26 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
   if (learned) {
     Net* N = net_of(c);
     const int64_t npix = static_cast<int64_t>(c->lat.W) * c->lat.H;
-    VIP_TRY(net_buffers(c, npix));
+    const Img g{1, c->lat.H, c->lat.W};
     VIP_TRY(lattice_rms(c, L.rx, b));
-    k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.rx, b, L.scal, h2, N->x);
-    VIP_TRY(forward(c, Img{1, c->lat.H, c->lat.W}, true));
-    k_direction<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, c->lat.pix, N->y, L.scal, h2, L.dir);
+    const float* yv = nullptr;
+    if (c->cnn_layered) {
+      // layer-by-layer kernels (the training forward pass), for comparison
+      VIP_TRY(net_buffers(c, npix));
+      k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.rx, b, L.scal, h2, N->x);
+      VIP_TRY(forward(c, g, true));
+      yv = N->y;
+    } else {
+      VIP_TRY(infer_buffers(c, npix));
+      k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.rx, b, L.scal, h2, N->ix);
+      VIP_TRY(forward_fused(c, g, true));
+      yv = N->iy;
+    }
+    k_direction<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, c->lat.pix, yv, L.scal, h2, L.dir);
     VIP_TRY(pressure_apply(c, L.dir, L.q2));
   }
-  k_dots6_part<<<kSumBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, L.r, L.scal + kScalHead);
-  k_dots6_finish<<<1, 64, 0, st>>>(kSumBlocks, L.scal + kScalHead, L.scal);
+  k_dots6_part<<<kRedBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, L.r, L.scal + kScalHead);
+  k_dots6_finish<<<1, 256, 0, st>>>(kRedBlocks, L.scal + kScalHead, L.scal);
   VIP_HIP_TRY(c, hipGetLastError());
   double s[8];
   VIP_HIP_TRY(c, hipMemcpyAsync(s, L.scal, sizeof(s), hipMemcpyDeviceToHost, st));

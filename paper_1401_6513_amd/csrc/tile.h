@@ -57,9 +57,21 @@ struct TileMeta {
 // Stage tile (tx, ty): its metadata, then (with load_x) the LDS copy of NS vectors over the
 // tile and its halo (0 at pixels without a node), every thread issuing all of its loads before
 // storing.  Starts and ends with a block barrier.
+template <typename T, int NS, typename F>
+__device__ __forceinline__ void tile_stage_fn(const TileView& V, int tx, int ty, F&& xf,
+                                              T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x);
+
 template <typename T, int NS>
 __device__ __forceinline__ void tile_stage(const TileView& V, int tx, int ty, const T* const (&x)[NS],
                                            T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x) {
+  tile_stage_fn<T, NS>(
+      V, tx, ty, [&](int s, int32_t node) __attribute__((always_inline)) { return x[s][node]; }, t, m, load_x);
+}
+
+// The same with the staged values given by xf(s, node) (system s at a node).
+template <typename T, int NS, typename F>
+__device__ __forceinline__ void tile_stage_fn(const TileView& V, int tx, int ty, F&& xf,
+                                              T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x) {
   const int tid = static_cast<int>(threadIdx.x);
   __syncthreads();
   if (tid < kTileLdsH)
@@ -90,7 +102,7 @@ __device__ __forceinline__ void tile_stage(const TileView& V, int tx, int ty, co
 #pragma unroll
   for (int k = 0; k < kPer; ++k)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) val[s][k] = node[k] >= 0 ? x[s][node[k]] : T(0);
+    for (int s = 0; s < NS; ++s) val[s][k] = node[k] >= 0 ? xf(s, node[k]) : T(0);
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int q = tid + k * kBlock;

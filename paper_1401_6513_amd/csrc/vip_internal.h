@@ -238,6 +238,7 @@ struct Ctx {
   int debug = 0;                  // VIP_DEBUG=1: trace Krylov batches on stderr
   int amg_pre_fine = 1;           // VIP_AMG_PRE_FINE=0: BiCGStab V-cycles skip the finest pre-sweep
   int no_canon = 0;               // VIP_NO_CANON=1: every row takes the general sliced-ELL path
+  int cnn_layered = 0;            // VIP_CNN_LAYERED=1: learned start inference layer by layer
   // V-cycle settings: over-correction of the piecewise-constant coarse correction (plain
   // aggregation makes the Galerkin coarse operators too stiff by about 2 for 2x2 aggregates)
   // and damped Jacobi sweeps per level; measured best on the cylinder and triangle node sets

@@ -310,3 +310,45 @@ def test_learned_start_gain():
     assert totals[vip.WS_LEARNED] <= 0.9 * totals[vip.WS_PREV]
     assert _rel(fields[vip.WS_LEARNED], fields[vip.WS_PREV]) < 1e-6
     ctx0.close()
+
+
+@pytest.mark.parametrize("case", ["cavity49", "cylinder12"])
+def test_fused_inference_matches_layer_by_layer(case):
+    """The learned start vector's network runs in one fused LDS-tiled launch; with
+    VIP_CNN_LAYERED=1 at context creation it runs layer by layer (the training forward pass).
+    Both repeat the same arithmetic, so steps with either give the same bits, on a lattice that
+    is not a multiple of the 16-pixel tile and on one with pixels without a node (the body)."""
+    import os
+    import torch
+    from paper_1401_6513_amd import nodesets, vip
+    _ctx()
+    if case == "cavity49":
+        spec, inflow, dt, Re = nodesets.lid_cavity(49), (0.0, 0.0), 0.01, 100.0
+    else:
+        spec = nodesets.cylinder_channel(1.0 / 12, box=(-3.0, 6.0, -3.0, 3.0), n_surface=48)
+        inflow, dt, Re = (1.0, 0.0), 1.0 / 120, 100.0
+    theta = None
+    out = []
+    for layered in (False, True):
+        if layered:
+            os.environ["VIP_CNN_LAYERED"] = "1"
+        try:
+            ctx = vip.Context(0)
+        finally:
+            os.environ.pop("VIP_CNN_LAYERED", None)
+        ctx.build_from_spec(spec, precision=vip.P_MIXED, warmstart=vip.WS_LEARNED)
+        if theta is None:
+            ctx.vip_learn_init(11)
+            theta = ctx.vip_learn_get_params()
+        ctx.vip_learn_set_params(theta)
+        st = [torch.tensor(a, device="cuda") for a in nodesets.boundary_initial(spec, inflow)]
+        stats = [ctx.vip_step(*st, dt, Re) for _ in range(6)]
+        out.append(([a.cpu().numpy() for a in st],
+                    [(s["warm_start"], s["warm_alpha"], s["warm_beta"], s["poisson_iters"]) for s in stats]))
+        ctx.close()
+    (fa, sa), (fb, sb) = out
+    print(case, sa)
+    assert sa == sb
+    assert any(s[0] == vip.WS_LEARNED for s in sa)
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)

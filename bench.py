@@ -90,7 +90,8 @@ PATHS = {
 }
 
 
-def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol, pool=None):
+def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol, pool=None,
+             helmholtz_tol=None):
     """Run `steps` timed steps of every domain (domains in parallel host threads, one HIP stream
     each, when a pool is given); returns wall seconds, stats, SpMV timing, fields and the
     summed seconds of each domain's own steps."""
@@ -102,6 +103,8 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
                                   precision=getattr(vip, cfg["precision"]),
                                   warmstart=getattr(vip, cfg["warmstart"]),
                                   preconditioner=getattr(vip, cfg.get("preconditioner", "PC_AMG")))
+        if helmholtz_tol is not None:
+            opt.helmholtz_tol = helmholtz_tol
         ctx.vip_set_options(opt)
         ctx.vip_reset_history()
     state = [_initial(s, dev) for s in specs]
@@ -188,6 +191,8 @@ def main():
     ap.add_argument("--h", type=float, default=1.0 / 128)
     ap.add_argument("--re", type=float, default=200.0)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--helmholtz-tol", type=float, default=None,
+                    help="tolerance of the predictor solves (default: the library's)")
     ap.add_argument("--inner-tol", type=float, default=1e-4,
                     help="relative tolerance of the FP32 inner solve (mixed path)")
     ap.add_argument("--paths", default="learned,mixed,fp64")
@@ -269,7 +274,7 @@ def main():
         nsteps = args.plain_steps if path == "plain" else args.steps
         el, stats, (spmv, conv), fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
                                                   nsteps, args.tol, path == paths[0],
-                                                  args.inner_tol, pool)
+                                                  args.inner_tol, pool, args.helmholtz_tol)
         results[path] = dict(seconds=el, stats=stats, spmv=spmv, conv=conv, fields=fields, dom_s=dom_s,
                              steps=nsteps)
         log("%s: %.3f s for %d steps" % (path, el, nsteps))
@@ -343,6 +348,7 @@ def main():
                                "steps": rr["steps"],
                                "ms_per_step_by_domain": [d / rr["steps"] * 1e3 for d in rr["dom_s"]],
                                "poisson_iters": it,
+                               "helmholtz_iters": [[s["helmholtz_iters"] for s in row] for row in rr["stats"]],
                                "poisson_residual": max(s["poisson_residual"] for row in rr["stats"]
                                                        for s in row)}
     per_step = {p: rr["seconds"] / rr["steps"] for p, rr in results.items()}

@@ -469,15 +469,6 @@ __global__ void k_restrict(int64_t nc, const int64_t* mstart, const int32_t* mem
   bc[I] = s;
 }
 
-// x_i + gamma xc[agg_i] (x may be absent; rows outside every aggregate get no correction),
-// without contraction so that kernels recomputing it get the same bits
-template <typename T>
-__device__ __forceinline__ T prolong_value(const int32_t* agg, const T* xc, T gamma, const T* x, int64_t i) {
-#pragma clang fp contract(off)
-  const int32_t a = agg[i];
-  return (x ? x[i] : T(0)) + (a >= 0 ? gamma * xc[a] : T(0));
-}
-
 // y = x + P xc   (coarse correction; x may be absent: zero pre-smoothing)
 template <typename T>
 __global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, T gamma, const T* x, T* y,
@@ -485,28 +476,24 @@ __global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, T gamma, c
   if (!*on) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
-  y[i] = prolong_value(agg, xc, gamma, x, i);
+  const int32_t a = agg[i];
+  y[i] = (x ? x[i] : T(0)) + (a >= 0 ? gamma * xc[a] : T(0));
 }
 
-// The iterate a smoothing sweep starts from: y in memory (kind 0), the zero-start sweep's W b
-// (kind 1, the output of k_jacobi0), or the prolonged correction y + gamma P xc (kind 2, the
-// output of k_prolong).  Kinds 1 and 2 recompute the value wherever it is needed, with the
-// same arithmetic as the kernel that would have stored it, so the fused sweep gives the same
-// bits as the two launches it replaces.
+// The iterate a smoothing sweep starts from: y in memory (kind 0) or the zero-start sweep's W b
+// (kind 1, the output of k_jacobi0), recomputed wherever it is needed with the same
+// arithmetic as k_jacobi0, so the fused sweep gives the same bits as the two launches it
+// replaces.
 template <typename T>
 struct SweepIn {
-  const T* y;              // kinds 0 and 2 (kind 2: may be null)
+  const T* y;              // kind 0
   const T* b;              // kind 1
-  const int32_t* agg;      // kind 2
-  const T* xc;
-  T gamma;
 };
 
 template <typename T, int KIND>
 __device__ __forceinline__ T sweep_in(const LevelView<T>& L, const SweepIn<T>& in, int64_t j) {
   if constexpr (KIND == 0) return in.y[j];
-  else if constexpr (KIND == 1) return zero_start_value(L.wdinv, in.b, j);
-  else return prolong_value(in.agg, in.xc, in.gamma, in.y, j);
+  else return zero_start_value(L.wdinv, in.b, j);
 }
 
 // out = y + W (b - A y)   (damped Jacobi sweep from the iterate of kind KIND)
@@ -864,14 +851,21 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
       T* a1 = w(l, 1);
       T* a2 = w(l, 2);
       const LevelView<T> lv = view<T>(c, l);
-      if (nu == 1) {
+      // the fused zero-start sweep stages W b once per tile entry; on levels without tiles the
+      // row-by-row path would recompute it for every stencil entry, so there W b is stored
+      if (nu == 1 || !lv.tv.tiles) {
         k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(lv, rhs, a1, on);
+        for (int k = 1; k < nu; ++k) {
+          k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, SweepIn<T>{a1, nullptr},
+                                                            a2, on);
+          std::swap(a1, a2);
+        }
       } else {
         // zero start and the first sweep in one launch
-        k_sweep<T, 1><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, SweepIn<T>{nullptr, rhs, nullptr, nullptr, T(0)},
+        k_sweep<T, 1><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, SweepIn<T>{nullptr, rhs},
                                                           a1, on);
         for (int k = 2; k < nu; ++k) {
-          k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, SweepIn<T>{a1, nullptr, nullptr, nullptr, T(0)},
+          k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, SweepIn<T>{a1, nullptr},
                                                             a2, on);
           std::swap(a1, a2);
         }
@@ -892,27 +886,19 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     const AmgLevel& L = g.lv[l];
     const int nu = l == 0 ? c->amg_nu : c->amg_nu_coarse;
     const T* bl = (l == 0) ? b : w(l, 0);
-    // buffer that is not cur[l], and the other one (free once the first sweep has read cur[l])
-    T* ybuf = (cur[l] == w(l, 2)) ? w(l, 1) : w(l, 2);
-    T* obuf = (ybuf == w(l, 1)) ? w(l, 2) : w(l, 1);
+    // y = pre-smoothed iterate + gamma P xc into the buffer that is not cur[l]
+    T* y = (cur[l] == w(l, 2)) ? w(l, 1) : w(l, 2);
+    T* obuf = (y == w(l, 1)) ? w(l, 2) : w(l, 1);
     const LevelView<T> lv = view<T>(c, l);
-    T* y = ybuf;
-    if (nu == 0) {
-      k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, gamma, cur[l], y, on);
-    } else {
-      // prolongation and the first sweep in one launch
-      T* out = (l == 0 && nu == 1) ? x : ybuf;
-      k_sweep<T, 2><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, SweepIn<T>{cur[l], nullptr, L.agg, xc, gamma}, out,
-                                                        on);
-      y = out;
-      T* other = obuf;
-      for (int k = 1; k < nu; ++k) {
-        T* o = (l == 0 && k == nu - 1) ? x : other;
-        k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, SweepIn<T>{y, nullptr, nullptr, nullptr, T(0)}, o,
-                                                          on);
-        other = y;
-        y = o;
-      }
+    // prolongation, then the sweeps (a fused prolongation sweep was measured no faster: its
+    // staging gathers the coarse correction through the aggregate map)
+    k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, gamma, cur[l], y, on);
+    T* other = obuf;
+    for (int k = 0; k < nu; ++k) {
+      T* o = (l == 0 && k == nu - 1) ? x : other;
+      k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, SweepIn<T>{y, nullptr}, o, on);
+      other = y;
+      y = o;
     }
     xc = y;
   }

@@ -564,6 +564,23 @@ __global__ void k_dense_apply(int64_t rows, int64_t cols, int64_t ld, const T* I
 
 }  // namespace
 
+namespace {
+
+// lattice image of the next level's rows: the row of each occupied aggregation cell
+__global__ void k_cell_map(int64_t ncell, const int64_t* occ, const int64_t* idx, int32_t* cell_node,
+                           int32_t* cell_pix) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= ncell) return;
+  if (occ[q]) {
+    cell_node[q] = static_cast<int32_t>(idx[q]);
+    cell_pix[idx[q]] = static_cast<int32_t>(q);
+  } else {
+    cell_node[q] = -1;
+  }
+}
+
+}  // namespace
+
 void amg_free(Ctx* c) {
   Amg& g = c->amg;
   for (size_t l = 0; l < g.lv.size(); ++l) {
@@ -581,6 +598,8 @@ void amg_free(Ctx* c) {
     dfree(L.cpix32);
     dfree(L.sbase64);
     dfree(L.sbase32);
+    dfree(L.cell_node);
+    dfree(L.cell_pix);
     for (int k = 0; k < 3; ++k) {
       dfree(L.w64[k]);
       dfree(L.w32[k]);
@@ -621,23 +640,33 @@ int amg_setup(Ctx* c) {
     k_keep<<<grid_for(L.n), kBlock, 0, st>>>(L.n, A.ptr, A.cols, A.rowlen, aval, L.keep);
     k_wdinv<<<grid_for(L.n), kBlock, 0, st>>>(L.n, A.ptr, A.cols, A.rowlen, aval, L.keep, kOmega,
                                                L.wdinv, L.wdinv32);
-    if (level == 0 && !c->no_canon && A.canon.K > 0 && A.canon.ref_row >= 0) {
+    if (level == 1 && !c->no_canon && L.cell_node) {
+      // canonical rows of the first coarse level on the lattice of aggregation cells
+      const LatRef lat{L.W, L.H, L.cell_pix, L.cell_node, L.n, nullptr};
+      VIP_TRY(canon_mark_on(c, L.A, 0, lat));
+      VIP_TRY(canon_mark_on(c, L.A, 4, lat));
+    }
+    if (level <= 1 && !c->no_canon && A.canon.K > 0 && A.canon.ref_row >= 0) {
       // canonical rows of the sweeps: canonical matrix row and the reference damped diagonal
       const Canon& cn = A.canon;
-      L.node_of = c->lat.node_of;
-      L.W = c->lat.W;
+      if (level == 0) {
+        L.node_of = c->lat.node_of;
+        L.W = c->lat.W;
+      } else {
+        L.node_of = L.cell_node;
+      }
       VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv_c, L.wdinv + cn.ref_row, sizeof(double), hipMemcpyDeviceToHost, st));
       VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv32_c, L.wdinv32 + cn.ref_row, sizeof(float), hipMemcpyDeviceToHost, st));
       VIP_HIP_TRY(c, hipStreamSynchronize(st));
       if (cn.count[0] > 0 && cn.cpix[0]) {
         VIP_TRY(dalloc(c, &L.cpix64, L.n));
         k_canon_wd<double><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[0], L.wdinv, L.wdinv_c, L.cpix64);
-        if (cn.disk) VIP_TRY(slice_bases(c, L.cpix64, L.n, &L.sbase64));
+        if (cn.disk && level == 0) VIP_TRY(slice_bases(c, L.cpix64, L.n, &L.sbase64));
       }
       if (cn.count[4] > 0 && cn.cpix[4]) {
         VIP_TRY(dalloc(c, &L.cpix32, L.n));
         k_canon_wd<float><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[4], L.wdinv32, L.wdinv32_c, L.cpix32);
-        if (cn.disk) VIP_TRY(slice_bases(c, L.cpix32, L.n, &L.sbase32));
+        if (cn.disk && level == 0) VIP_TRY(slice_bases(c, L.cpix32, L.n, &L.sbase32));
       }
       VIP_HIP_TRY(c, hipGetLastError());
     }
@@ -685,6 +714,13 @@ int amg_setup(Ctx* c) {
     VIP_TRY(dalloc(c, &cnt, nc + 1));
     VIP_HIP_TRY(c, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (nc + 1), st));
     k_assign<<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.keep, L.kx, L.ky, gx, idx, L.agg, C.kx, C.ky, cnt);
+    if (level == 0 && gx * gy <= 4 * nc + 4096 && gx <= 65536 && gy <= 65536) {
+      C.W = static_cast<int32_t>(gx);
+      C.H = static_cast<int32_t>(gy);
+      VIP_TRY(dalloc(c, &C.cell_node, gx * gy));
+      VIP_TRY(dalloc(c, &C.cell_pix, nc));
+      k_cell_map<<<grid_for(gx * gy), kBlock, 0, st>>>(gx * gy, occ, idx, C.cell_node, C.cell_pix);
+    }
     dfree(occ);
     dfree(idx);
     VIP_TRY(dalloc(c, &L.mstart, nc + 1));

@@ -65,7 +65,7 @@ __global__ void k_gather_rows(int m, const int64_t* rows, const int64_t* ptr, co
   const int64_t i = rows[s];
   const int len = rowlen[i];
   o_len[s] = len;
-  o_bpos[s] = bpos[i];
+  o_bpos[s] = bpos ? bpos[i] : -1;
   o_pix[s] = pix[i];
   o_rsum[s] = rsum32 ? __float_as_uint(rsum32[i]) : 0u;
   const int64_t base = ptr[i / kSlice] + (i % kSlice);
@@ -93,7 +93,7 @@ __global__ void k_canon_mark(int64_t n, MarkArgs a, const int32_t* bpos, const i
   if (i >= n) return;
   int32_t out = -1;
   const int32_t p = pix[i];
-  if (bpos[i] < 0 && p >= 0 && rowlen[i] == a.K) {
+  if ((!bpos || bpos[i] < 0) && p >= 0 && rowlen[i] == a.K) {
     const int ix = p % a.W, iy = p / a.W;
     const int64_t base = ptr[i / kSlice] + (i % kSlice);
     bool ok = true;
@@ -264,7 +264,8 @@ struct RowSample {
 };
 
 // Sampled rows' data (value set vs) copied to the host.
-int gather(Ctx* c, const Ell& e, int vs, const std::vector<int64_t>& rows, std::vector<RowSample>* out) {
+int gather(Ctx* c, const Ell& e, int vs, const LatRef& L, const std::vector<int64_t>& rows,
+           std::vector<RowSample>* out) {
   const int m = static_cast<int>(rows.size());
   int64_t* d_rows = nullptr;
   int32_t *d_len = nullptr, *d_bpos = nullptr, *d_pix = nullptr, *d_cpix = nullptr;
@@ -286,7 +287,7 @@ int gather(Ctx* c, const Ell& e, int vs, const std::vector<int64_t>& rows, std::
     }
     const float* v32 = vs == 4 ? e.val32 : vs > 4 ? e.val32h[vs - 5] : nullptr;
     const float* r32 = vs == 4 ? e.rsum32 : vs > 4 ? e.rsum32h[vs - 5] : nullptr;
-    k_gather_rows<<<(m + 63) / 64, 64, 0, st>>>(m, d_rows, e.ptr, e.rowlen, e.cols, c->bpos, c->lat.pix,
+    k_gather_rows<<<(m + 63) / 64, 64, 0, st>>>(m, d_rows, e.ptr, e.rowlen, e.cols, L.bpos, L.pix,
                                                 vs < 4 ? e.val[vs] : nullptr, v32, r32, d_len, d_bpos, d_pix,
                                                 d_cpix, d_bits, d_rsum);
     if (hipGetLastError() != hipSuccess ||
@@ -397,21 +398,26 @@ int slice_bases(Ctx* c, const int32_t* cpix, int64_t n, int32_t** out, int64_t* 
 }
 
 int canon_mark(Ctx* c, Ell& e, int vs) {
-  Canon& cn = e.canon;
-  const float* v32 = vs == 4 ? e.val32 : vs > 4 && vs <= 6 ? e.val32h[vs - 5] : nullptr;
-  const float* r32 = vs == 4 ? e.rsum32 : vs > 4 && vs <= 6 ? e.rsum32h[vs - 5] : nullptr;
-  if (vs < 0 || vs > 6 || (vs < 4 && !e.val[vs]) || (vs >= 4 && (!v32 || !r32))) return VIP_OK;
   bool ok = false;
   VIP_TRY(lattice_map(c, &ok));
   if (!ok || e.nrows != c->n) return VIP_OK;
   const Lattice& L = c->lat;
+  return canon_mark_on(c, e, vs, LatRef{L.W, L.H, L.pix, L.node_of, c->n, c->bpos});
+}
+
+int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L) {
+  Canon& cn = e.canon;
+  const float* v32 = vs == 4 ? e.val32 : vs > 4 && vs <= 6 ? e.val32h[vs - 5] : nullptr;
+  const float* r32 = vs == 4 ? e.rsum32 : vs > 4 && vs <= 6 ? e.rsum32h[vs - 5] : nullptr;
+  if (vs < 0 || vs > 6 || (vs < 4 && !e.val[vs]) || (vs >= 4 && (!v32 || !r32))) return VIP_OK;
+  if (e.nrows != L.n || L.n == 0) return VIP_OK;
   if (cn.ref_row == -1) {
     // reference: the most common (offsets, values) pattern among evenly spaced interior rows
-    const int m = static_cast<int>(std::min<int64_t>(1024, c->n));
+    const int m = static_cast<int>(std::min<int64_t>(1024, L.n));
     std::vector<int64_t> rows(m);
-    for (int s = 0; s < m; ++s) rows[s] = static_cast<int64_t>((s + 0.5) * static_cast<double>(c->n) / m);
+    for (int s = 0; s < m; ++s) rows[s] = static_cast<int64_t>((s + 0.5) * static_cast<double>(L.n) / m);
     std::vector<RowSample> smp;
-    VIP_TRY(gather(c, e, vs, rows, &smp));
+    VIP_TRY(gather(c, e, vs, L, rows, &smp));
     std::map<std::vector<uint64_t>, std::pair<int, int64_t>> freq;
     for (int s = 0; s < m; ++s) {
       const RowSample& r = smp[s];
@@ -447,7 +453,7 @@ int canon_mark(Ctx* c, Ell& e, int vs) {
   if (cn.ref_row < 0) return VIP_OK;
   // the reference row's offsets and the bits of value set vs
   std::vector<RowSample> ref;
-  VIP_TRY(gather(c, e, vs, std::vector<int64_t>{cn.ref_row}, &ref));
+  VIP_TRY(gather(c, e, vs, L, std::vector<int64_t>{cn.ref_row}, &ref));
   const RowSample& r = ref[0];
   if (r.len < 1 || r.len > kMaxTaps || r.pix < 0) return VIP_OK;
   MarkArgs a{};
@@ -482,14 +488,14 @@ int canon_mark(Ctx* c, Ell& e, int vs) {
   cn.disk = a.K == kDiskTaps ? 1 : 0;
   for (int k = 0; k < a.K && cn.disk; ++k)
     if (a.dy[k] != disk_row(k) - 2 || a.dx[k] != disk_dx(k)) cn.disk = 0;
-  if (!cn.cpix[vs]) VIP_TRY(dalloc(c, &cn.cpix[vs], c->n));
+  if (!cn.cpix[vs]) VIP_TRY(dalloc(c, &cn.cpix[vs], L.n));
   hipStream_t st = c->stream;
-  k_canon_mark<<<grid_for(c->n), kBlock, 0, st>>>(c->n, a, c->bpos, L.pix, L.node_of, e.ptr, e.rowlen, e.cols,
+  k_canon_mark<<<grid_for(L.n), kBlock, 0, st>>>(L.n, a, L.bpos, L.pix, L.node_of, e.ptr, e.rowlen, e.cols,
                                                   vs < 4 ? e.val[vs] : nullptr, v32, r32, cn.cpix[vs]);
   // number of canonical rows (kernels skip the canonical path when it is zero)
   int64_t* part = nullptr;
   VIP_TRY(dalloc(c, &part, 256));
-  k_count_nonneg<<<256, 256, 0, st>>>(c->n, cn.cpix[vs], part);
+  k_count_nonneg<<<256, 256, 0, st>>>(L.n, cn.cpix[vs], part);
   std::vector<int64_t> hp(256);
   hipError_t e1 = hipMemcpyAsync(hp.data(), part, sizeof(int64_t) * 256, hipMemcpyDeviceToHost, st);
   hipError_t e2 = hipStreamSynchronize(st);
@@ -499,10 +505,11 @@ int canon_mark(Ctx* c, Ell& e, int vs) {
   for (int64_t v : hp) cnt += v;
   cn.count[vs] = cnt;
   cn.described[vs] = 0;
-  if (cn.disk && cnt > 0) VIP_TRY(slice_bases(c, cn.cpix[vs], c->n, &cn.sbase[vs], &cn.described[vs]));
+  if (cn.disk && cnt > 0 && L.node_of == c->lat.node_of)
+    VIP_TRY(slice_bases(c, cn.cpix[vs], L.n, &cn.sbase[vs], &cn.described[vs]));
   if (c->debug)
     std::fprintf(stderr, "[vip] canonical rows, value set %d: %lld of %lld (%d taps, reference row %lld)\n", vs,
-                 static_cast<long long>(cnt), static_cast<long long>(c->n), cn.K,
+                 static_cast<long long>(cnt), static_cast<long long>(L.n), cn.K,
                  static_cast<long long>(cn.ref_row));
   return VIP_OK;
 }

@@ -151,6 +151,17 @@ struct Lattice {
   int32_t* node_of = nullptr;       // device [W*H]: node at each pixel or -1
 };
 
+// A lattice image of some set of rows (the node set's, or a coarse multigrid level's cells):
+// the pixel of each row, the row at each pixel (-1 where none), optional boundary-row flags
+// (bpos >= 0 marks a boundary row; null: none).
+struct LatRef {
+  int W, H;
+  const int32_t* pix;
+  const int32_t* node_of;
+  int64_t n;
+  const int32_t* bpos;
+};
+
 // Device-resident scalars of the Krylov solvers, written by the last block of a
 // reduction and read by later kernels; two systems side by side (u and v of
 // the predictor) use index 0 and 1.
@@ -181,7 +192,7 @@ struct AmgLevel {
   float* wdinv32 = nullptr;
   double* w64[3] = {nullptr, nullptr, nullptr};   // V-cycle work vectors
   float* w32[3] = {nullptr, nullptr, nullptr};
-  // level 0: canonical rows of the sweeps (canonical values and damped inverse diagonal)
+  // levels 0 and 1: canonical rows of the sweeps (canonical values and damped inverse diagonal)
   int32_t* cpix64 = nullptr;
   int32_t* cpix32 = nullptr;
   int32_t* sbase64 = nullptr;     // slice descriptors of cpix64 / cpix32 (see Canon::sbase)
@@ -190,6 +201,10 @@ struct AmgLevel {
   int32_t W = 0;                  // lattice image width
   double wdinv_c = 0.0;
   float wdinv32_c = 0.0f;
+  // level 1: lattice image of its rows, the aggregation cells of level 0 (owned)
+  int32_t* cell_node = nullptr;   // [W * H]: row at each cell, -1 where none
+  int32_t* cell_pix = nullptr;    // [n]: cell of each row
+  int32_t H = 0;
 };
 
 struct Amg {
@@ -413,6 +428,8 @@ int lattice_map(Ctx* c, bool* ok);
 // Find the reference row of the system layout and mark the canonical rows of value set
 // vs (0..3 FP64; 4..6 FP32 pressure, predictor u, predictor v, with their row sums).
 int canon_mark(Ctx* c, Ell& e, int vs);
+// The same for the rows of e on the lattice image L (their columns index L's rows).
+int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L);
 // Slice descriptors (Canon::sbase) of canonical-row pixels cpix [n] into out [4 * ceil(n/64)].
 int slice_bases(Ctx* c, const int32_t* cpix, int64_t n, int32_t** out, int64_t* described = nullptr);
 void canon_free(Canon& cn);

@@ -284,6 +284,7 @@ struct LevelView {
   const int32_t* node_of;
   int K;
   int disk;
+  int box;                // taps are the 3 x 3 box (first coarse level)
   int32_t W;
   int32_t off[kMaxTaps];
   T w[kMaxTaps];
@@ -322,6 +323,20 @@ __device__ __forceinline__ T canon_row(const LevelView<T>& L, int32_t p, int64_t
     int32_t b[5];
     disk_bases(L.node_of, p, L.W, i, b);
     return disk_row_sum(L, i, b, y);
+  }
+  if (L.box) {
+    // 3 x 3 box: row bases from two lattice-map reads; with 9 slots the general path sends
+    // slot k to accumulator k % 2 whatever the slice width
+    const int32_t b[3] = {L.node_of[p - L.W], static_cast<int32_t>(i), L.node_of[p + L.W]};
+    const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
+    T a0 = T(0), a1 = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (k & 1) a1 += L.w[k] * (y(b[k / 3] + (k % 3 - 1)) - yi);
+      else a0 += L.w[k] * (y(b[k / 3] + (k % 3 - 1)) - yi);
+    }
+    if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
+    else return a0 + a1;
   }
   const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
   T a0 = T(0), a1 = T(0);
@@ -818,6 +833,7 @@ static LevelView<T> view(const Ctx* c, int level) {
   v.node_of = L.node_of;
   v.K = L.A.canon.K;
   v.disk = L.A.canon.disk;
+  v.box = L.A.canon.box;
   v.W = L.W;
   v.crsum = L.A.canon.rsum32[0];
   if constexpr (sizeof(T) == 4) {

@@ -488,6 +488,9 @@ int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L) {
   cn.disk = a.K == kDiskTaps ? 1 : 0;
   for (int k = 0; k < a.K && cn.disk; ++k)
     if (a.dy[k] != disk_row(k) - 2 || a.dx[k] != disk_dx(k)) cn.disk = 0;
+  cn.box = a.K == 9 ? 1 : 0;
+  for (int k = 0; k < a.K && cn.box; ++k)
+    if (a.dy[k] != k / 3 - 1 || a.dx[k] != k % 3 - 1) cn.box = 0;
   if (!cn.cpix[vs]) VIP_TRY(dalloc(c, &cn.cpix[vs], L.n));
   hipStream_t st = c->stream;
   k_canon_mark<<<grid_for(L.n), kBlock, 0, st>>>(L.n, a, L.bpos, L.pix, L.node_of, e.ptr, e.rowlen, e.cols,

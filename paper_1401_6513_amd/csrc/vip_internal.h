@@ -57,6 +57,7 @@ struct Canon {
   float w32[3][kMaxTaps];           // reference values of FP32 value sets 4..6
   float rsum32[3] = {0.0f, 0.0f, 0.0f};  // reference FP32 row sums of sets 4..6
   int disk = 0;                     // 1: the taps are the 21-point disk in slot order
+  int box = 0;                      // 1: the taps are the 3 x 3 box in slot order (coarse level)
   int64_t ref_row = -1;
   int32_t* cpix[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // device [n]
                                     // per value set (0..3 FP64; 4..6 FP32: pressure, predictor u, v):

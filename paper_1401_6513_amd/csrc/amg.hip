@@ -670,8 +670,10 @@ int amg_setup(Ctx* c) {
       } else {
         L.node_of = L.cell_node;
       }
-      VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv_c, L.wdinv + cn.ref_row, sizeof(double), hipMemcpyDeviceToHost, st));
-      VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv32_c, L.wdinv32 + cn.ref_row, sizeof(float), hipMemcpyDeviceToHost, st));
+      const int64_t r64 = cn.vref[0] >= 0 ? cn.vref[0] : cn.ref_row;
+      const int64_t r32 = cn.vref[4] >= 0 ? cn.vref[4] : cn.ref_row;
+      VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv_c, L.wdinv + r64, sizeof(double), hipMemcpyDeviceToHost, st));
+      VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv32_c, L.wdinv32 + r32, sizeof(float), hipMemcpyDeviceToHost, st));
       VIP_HIP_TRY(c, hipStreamSynchronize(st));
       if (cn.count[0] > 0 && cn.cpix[0]) {
         VIP_TRY(dalloc(c, &L.cpix64, L.n));

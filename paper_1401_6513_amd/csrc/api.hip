@@ -56,7 +56,6 @@ void ctx_free_build(Ctx* c) {
   ell_free(c->sys);
   for (auto& d : c->dinv) dfree(d);
   dfree(c->dinv32);
-  for (auto& d : c->dinv32h) dfree(d);
   dfree(c->nprev);
   dfree(c->stepbuf);
   dfree(c->phi);

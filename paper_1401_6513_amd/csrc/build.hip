@@ -361,12 +361,16 @@ __global__ void k_slice_width(const int32_t* rowlen, int64_t nrows, int64_t nsli
   slots[s] = static_cast<int64_t>(w) * kSlice;
 }
 
+// Padding slots get column 0: those of short rows and every slot of the lanes past the last
+// row in a ragged last slice (launched over all nslices * kSlice lanes), so that no stored
+// column is ever uninitialised.
 __global__ void k_fill_padding(const int64_t* ptr, const int32_t* width, const int32_t* rowlen,
-                               int64_t nrows, int32_t* cols) {
+                               int64_t nrows, int64_t nlanes, int32_t* cols) {
   int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (r >= nrows) return;
+  if (r >= nlanes) return;
   const int64_t s = r / kSlice, l = r % kSlice;
-  for (int32_t k = rowlen[r]; k < width[s]; ++k) cols[ptr[s] + static_cast<int64_t>(k) * kSlice + l] = 0;
+  const int32_t first = r < nrows ? rowlen[r] : 0;
+  for (int32_t k = first; k < width[s]; ++k) cols[ptr[s] + static_cast<int64_t>(k) * kSlice + l] = 0;
 }
 
 int ell_layout(Ctx* c, Ell& e) {
@@ -388,8 +392,8 @@ int ell_layout(Ctx* c, Ell& e) {
   e.nnz_slots = total;
   VIP_TRY(dalloc(c, &e.cols, total));
   if (e.nrows > 0)
-    k_fill_padding<<<grid_for(e.nrows), kBlock, 0, c->stream>>>(e.ptr, e.width, e.rowlen, e.nrows,
-                                                                 e.cols);
+    k_fill_padding<<<grid_for(e.nslices * kSlice), kBlock, 0, c->stream>>>(e.ptr, e.width, e.rowlen, e.nrows,
+                                                                            e.nslices * kSlice, e.cols);
   // largest width and stored entries
   std::vector<int32_t> w(static_cast<size_t>(e.nslices)), rl(static_cast<size_t>(e.nrows));
   if (e.nslices > 0)
@@ -655,6 +659,35 @@ __global__ void k_rowsum32(int64_t n, const int64_t* ptr, const int32_t* rowlen,
   double s = 0.0;
   for (int t = 0; t < rowlen[i]; ++t)
     s += val[ptr[i / kSlice] + static_cast<int64_t>(t) * kSlice + (i % kSlice)];
+  out[i] = static_cast<float>(s);
+}
+
+// FP32 copy of a value set with every column scaled by dinv (out = val * dinv[col]), one lane
+// per slice row (nslices * kSlice lanes); padding slots and lanes past the last row hold 0 and
+// their columns are not read
+__global__ void k_colscale_f32(int64_t nrows, int64_t nlanes, const int64_t* ptr, const int32_t* width,
+                               const int32_t* rowlen, const int32_t* cols, const double* val,
+                               const double* dinv, float* out) {
+  const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (r >= nlanes) return;
+  const int64_t s = r / kSlice, l = r % kSlice;
+  const int32_t len = r < nrows ? rowlen[r] : 0;
+  for (int32_t k = 0; k < width[s]; ++k) {
+    const int64_t q = ptr[s] + static_cast<int64_t>(k) * kSlice + l;
+    out[q] = k < len ? static_cast<float>(val[q] * dinv[cols[q]]) : 0.0f;
+  }
+}
+
+// row sums of the column-scaled values (FP64 sum, stored as FP32)
+__global__ void k_rowsum32_colscaled(int64_t n, const int64_t* ptr, const int32_t* rowlen, const int32_t* cols,
+                                     const double* val, const double* dinv, float* out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int t = 0; t < rowlen[i]; ++t) {
+    const int64_t q = ptr[i / kSlice] + static_cast<int64_t>(t) * kSlice + (i % kSlice);
+    s += val[q] * dinv[cols[q]];
+  }
   out[i] = static_cast<float>(s);
 }
 
@@ -1016,15 +1049,16 @@ int assemble_helmholtz(Ctx* c, double dt, double re) {
                                                         c->sys.val[1], c->dinv[1]);
   k_diag_inv<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, c->sys.ptr, c->sys.cols, c->sys.rowlen,
                                                         c->sys.val[2], c->dinv[2]);
-  // FP32 copies for the mixed-precision predictor solve: values, row sums, Jacobi diagonals
+  // FP32 copies for the mixed-precision predictor solve, with the Jacobi preconditioner folded
+  // in: H D^-1 (every column scaled by the inverse diagonal) and its row sums
   Ell& s = c->sys;
   for (int k = 0; k < 2; ++k) {
     if (!s.val32h[k]) VIP_TRY(dalloc(c, &s.val32h[k], s.nnz_slots));
     if (!s.rsum32h[k]) VIP_TRY(dalloc(c, &s.rsum32h[k], c->n));
-    if (!c->dinv32h[k]) VIP_TRY(dalloc(c, &c->dinv32h[k], c->n + 1));
-    k_to_f32<<<grid_for(s.nnz_slots), kBlock, 0, c->stream>>>(s.nnz_slots, s.val[1 + k], s.val32h[k]);
-    launch_rowsum32(c->stream, c->n, s.ptr, s.rowlen, s.val[1 + k], s.rsum32h[k]);
-    k_to_f32<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, c->dinv[1 + k], c->dinv32h[k]);
+    k_colscale_f32<<<grid_for(s.nslices * kSlice), kBlock, 0, c->stream>>>(
+        c->n, s.nslices * kSlice, s.ptr, s.width, s.rowlen, s.cols, s.val[1 + k], c->dinv[1 + k], s.val32h[k]);
+    k_rowsum32_colscaled<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, s.ptr, s.rowlen, s.cols, s.val[1 + k],
+                                                                    c->dinv[1 + k], s.rsum32h[k]);
   }
   VIP_HIP_TRY(c, hipGetLastError());
   VIP_TRY(canon_mark(c, c->sys, 1));

@@ -1114,6 +1114,15 @@ __global__ void k_add_f32(int64_t m, double* x, const float* d) {
   if (i < m) x[i] += static_cast<double>(d[i]);
 }
 
+// x += D^-1 y for two systems of `stride` entries (rows below n; D^-1 of system s in dinv_s)
+__global__ void k_add_scaled(int64_t m, int64_t stride, int64_t n, double* x, const float* y, const double* dinv0,
+                             const double* dinv1) {
+  const int64_t o = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (o >= m) return;
+  const int64_t i = o % stride;
+  if (i < n) x[o] += (o < stride ? dinv0 : dinv1)[i] * static_cast<double>(y[o]);
+}
+
 // partial sums of a[0..m)
 __global__ void k_sum(int64_t m, const double* a, double* partials) {
   double acc[1] = {0.0};
@@ -1230,6 +1239,9 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   const int64_t nvec = A.n + A.border;
   const int64_t g_vec = grid_for(nvec);
   const int64_t r_rows = spmv_grid(A), r_vec = red_grid(nvec);
+  // Jacobi vectors ph = D^-1 p, sh = D^-1 s unless multigrid makes them or there is no D^-1
+  // (then ph and sh are p and s)
+  const int jac = amg || !V.dinv[0] ? 0 : 1;
   VIP_TRY(ensure_partials(c, std::max(r_rows, r_vec), 3 * NS));
   if (c->debug)
     std::fprintf(stderr, "[vip] iterate n %lld border %d tol %.3e rr0 %.3e bb %.3e\n",
@@ -1263,7 +1275,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
     if (hint) next = std::min(every, 2);
     for (int b = 0; b < batch; ++b) {
       if (m == kBiCGStab) {
-        k_bicg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
+        k_bicg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, jac);
         if constexpr (NS == 1) {
           if (amg) VIP_TRY(amg_apply<T>(c, V.p, V.ph, A.border != 0, c->amg_pre_fine != 0));
         }
@@ -1273,7 +1285,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
           else k_bicg_v<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         }
         k_fin_bicg_v<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
-        k_bicg_s<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, amg ? 0 : 1);
+        k_bicg_s<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, jac);
         if constexpr (NS == 1) {
           if (amg) VIP_TRY(amg_apply<T>(c, V.s, V.sh, A.border != 0, c->amg_pre_fine != 0));
         }
@@ -1536,8 +1548,11 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
     attach_canon(c, H32, 5, 6);
     d32 = c->ws32 + 16 * stride;         // [2][stride] FP32 correction
     V32 = make_vec<float>(c->ws32, stride, 2, d32);
-    V32.dinv[0] = c->dinv32h[0];
-    V32.dinv[1] = c->dinv32h[1];
+    // the Jacobi preconditioner is folded into H32 = H D^-1: plain BiCGStab for y with
+    // H32 y = r (the same residual r - H d for d = D^-1 y), no preconditioned vectors
+    V32.dinv[0] = V32.dinv[1] = nullptr;
+    V32.ph = V32.p;
+    V32.sh = V32.s;
   }
   const double tol = c->opt.helmholtz_tol;
   const double inner = std::max(c->opt.inner_tol, 1e-7);
@@ -1569,7 +1584,7 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
                                         rr, false, &bad, &c->hint_h32[std::min(outer, 3)])));
       total += it;
       if (bad) return set_error(c, VIP_E_NONFINITE, "FP32 predictor correction produced a non-finite residual");
-      k_add_f32<<<grid_for(2 * stride), kBlock, 0, s>>>(2 * stride, x, d32);
+      k_add_scaled<<<grid_for(2 * stride), kBlock, 0, s>>>(2 * stride, stride, n, x, d32, c->dinv[1], c->dinv[2]);
     } else {
       // a system whose b is zero is solved by x = 0 exactly: give it a unit norm
       for (int k = 0; k < 2; ++k) if (bb[k] == 0.0) bb[k] = 1.0;

@@ -343,6 +343,7 @@ void canon_free(Canon& cn) {
   cn.K = 0;
   cn.ref_row = -1;
   for (auto& k : cn.count) k = 0;
+  for (auto& r : cn.vref) r = -1;
 }
 
 int lattice_map(Ctx* c, bool* ok) {
@@ -411,8 +412,13 @@ int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L) {
   const float* r32 = vs == 4 ? e.rsum32 : vs > 4 && vs <= 6 ? e.rsum32h[vs - 5] : nullptr;
   if (vs < 0 || vs > 6 || (vs < 4 && !e.val[vs]) || (vs >= 4 && (!v32 || !r32))) return VIP_OK;
   if (e.nrows != L.n || L.n == 0) return VIP_OK;
-  if (cn.ref_row == -1) {
-    // reference: the most common (offsets, values) pattern among evenly spaced interior rows
+  if (cn.ref_row == -2) return VIP_OK;   // no repeated interior pattern
+  // reference of this value set: the most common (offsets, values) pattern among evenly spaced
+  // interior rows. Once a first set has fixed the offsets, later sets keep them and choose among
+  // rows with those offsets: a row typical of one set need not be typical of another (columns
+  // scaled by their own rows' diagonals differ next to the boundary).
+  int64_t ref_row = -1;
+  {
     const int m = static_cast<int>(std::min<int64_t>(1024, L.n));
     std::vector<int64_t> rows(m);
     for (int s = 0; s < m; ++s) rows[s] = static_cast<int64_t>((s + 0.5) * static_cast<double>(L.n) / m);
@@ -422,6 +428,7 @@ int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L) {
     for (int s = 0; s < m; ++s) {
       const RowSample& r = smp[s];
       if (r.bpos >= 0 || r.pix < 0 || r.len < 1 || r.len > kMaxTaps) continue;
+      if (cn.K != 0 && r.len != cn.K) continue;
       std::vector<uint64_t> key;
       bool good = true;
       for (int k = 0; k < r.len; ++k) {
@@ -431,6 +438,10 @@ int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L) {
         }
         const int64_t dx = static_cast<int64_t>(r.cpix[k] % L.W) - r.pix % L.W;
         const int64_t dy = static_cast<int64_t>(r.cpix[k] / L.W) - r.pix / L.W;
+        if (cn.K != 0 && (dx != cn.dx[k] || dy != cn.dy[k])) {
+          good = false;
+          break;
+        }
         key.push_back(static_cast<uint64_t>((dy + 1024) * 4096 + (dx + 1024)));
         key.push_back(r.bits[k]);
       }
@@ -443,17 +454,17 @@ int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L) {
     for (const auto& kv : freq)
       if (kv.second.first > best) {
         best = kv.second.first;
-        cn.ref_row = kv.second.second;
+        ref_row = kv.second.second;
       }
     if (best < 2) {
-      cn.ref_row = -2;   // no repeated interior pattern
+      if (cn.ref_row == -1) cn.ref_row = -2;
       return VIP_OK;
     }
+    if (cn.ref_row == -1) cn.ref_row = ref_row;
   }
-  if (cn.ref_row < 0) return VIP_OK;
   // the reference row's offsets and the bits of value set vs
   std::vector<RowSample> ref;
-  VIP_TRY(gather(c, e, vs, L, std::vector<int64_t>{cn.ref_row}, &ref));
+  VIP_TRY(gather(c, e, vs, L, std::vector<int64_t>{ref_row}, &ref));
   const RowSample& r = ref[0];
   if (r.len < 1 || r.len > kMaxTaps || r.pix < 0) return VIP_OK;
   MarkArgs a{};
@@ -491,6 +502,7 @@ int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L) {
   cn.box = a.K == 9 ? 1 : 0;
   for (int k = 0; k < a.K && cn.box; ++k)
     if (a.dy[k] != k / 3 - 1 || a.dx[k] != k % 3 - 1) cn.box = 0;
+  cn.vref[vs] = ref_row;
   if (!cn.cpix[vs]) VIP_TRY(dalloc(c, &cn.cpix[vs], L.n));
   hipStream_t st = c->stream;
   k_canon_mark<<<grid_for(L.n), kBlock, 0, st>>>(L.n, a, L.bpos, L.pix, L.node_of, e.ptr, e.rowlen, e.cols,
@@ -513,7 +525,7 @@ int canon_mark_on(Ctx* c, Ell& e, int vs, const LatRef& L) {
   if (c->debug)
     std::fprintf(stderr, "[vip] canonical rows, value set %d: %lld of %lld (%d taps, reference row %lld)\n", vs,
                  static_cast<long long>(cnt), static_cast<long long>(L.n), cn.K,
-                 static_cast<long long>(cn.ref_row));
+                 static_cast<long long>(ref_row));
   return VIP_OK;
 }
 

@@ -58,7 +58,8 @@ struct Canon {
   float rsum32[3] = {0.0f, 0.0f, 0.0f};  // reference FP32 row sums of sets 4..6
   int disk = 0;                     // 1: the taps are the 21-point disk in slot order
   int box = 0;                      // 1: the taps are the 3 x 3 box in slot order (coarse level)
-  int64_t ref_row = -1;
+  int64_t ref_row = -1;             // reference row of the first marked set (-2: no repeated pattern)
+  int64_t vref[7] = {-1, -1, -1, -1, -1, -1, -1};  // reference row of each marked value set
   int32_t* cpix[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // device [n]
                                     // per value set (0..3 FP64; 4..6 FP32: pressure, predictor u, v):
                                     // pixel of a canonical row, else -1
@@ -102,7 +103,8 @@ struct Ell {
   double* val[4] = {nullptr, nullptr, nullptr, nullptr};  // FP64 value sets
   float* val32 = nullptr;           // FP32 value set (pressure matrix only)
   float* rsum32 = nullptr;          // FP32 rows evaluated as rsum*x_i + sum a_ij (x_j - x_i)
-  float* val32h[2] = {nullptr, nullptr};   // FP32 predictor matrices (system layout only)
+  float* val32h[2] = {nullptr, nullptr};   // FP32 predictor matrices H D^-1, columns scaled by the
+                                           // inverse diagonal (system layout only)
   float* rsum32h[2] = {nullptr, nullptr};
   int64_t max_width = 0;
   int64_t nnz = 0;                  // sum of row lengths
@@ -296,7 +298,6 @@ struct Ctx {
   Ell sys;                        // val[0] = Poisson, val[1] = H_u, val[2] = H_v; val32 = Poisson
   double* dinv[3] = {nullptr, nullptr, nullptr};   // Jacobi inverse diagonals (P, Hu, Hv)
   float* dinv32 = nullptr;
-  float* dinv32h[2] = {nullptr, nullptr};          // FP32 Jacobi inverse diagonals of H_u, H_v
 
   // step state
   double cur_dt = 0.0, cur_re = 0.0;

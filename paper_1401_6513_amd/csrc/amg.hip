@@ -446,11 +446,11 @@ __global__ void __launch_bounds__(kBlock) k_level_residual(LevelView<T> L, const
     const T* xs[1] = {x};
     tile_walk(
         L.tv,
-        [&](int tx, int ty) __attribute__((always_inline)) {
-          tile_stage<T, 1>(L.tv, tx, ty, xs, lds, meta, true);
+        [&](int64_t tk) __attribute__((always_inline)) {
+          tile_stage<T, 1>(L.tv, tk, xs, lds, meta, true);
           int64_t ii[kTileRowsPerWave];
           bool ok[kTileRowsPerWave];
-          tile_row_ids(L.tv, tx, ty, meta, ii, ok);
+          tile_row_ids(L.tv, meta, ii, ok);
           T bi[kTileRowsPerWave];
 #pragma unroll
           for (int k = 0; k < kTileRowsPerWave; ++k)
@@ -524,13 +524,13 @@ __global__ void __launch_bounds__(kBlock) k_sweep(LevelView<T> L, const T* b, Sw
     // that applies, so the same bits)
     tile_walk(
         L.tv,
-        [&](int tx, int ty) __attribute__((always_inline)) {
+        [&](int64_t tk) __attribute__((always_inline)) {
           tile_stage_fn<T, 1>(
-              L.tv, tx, ty, [&](int, int32_t node) __attribute__((always_inline)) { return yf(node); }, lds, meta,
+              L.tv, tk, [&](int, int32_t node) __attribute__((always_inline)) { return yf(node); }, lds, meta,
               true);
           int64_t ii[kTileRowsPerWave];
           bool ok[kTileRowsPerWave];
-          tile_row_ids(L.tv, tx, ty, meta, ii, ok);
+          tile_row_ids(L.tv, meta, ii, ok);
           T bi[kTileRowsPerWave], wd[kTileRowsPerWave];
 #pragma unroll
           for (int k = 0; k < kTileRowsPerWave; ++k)

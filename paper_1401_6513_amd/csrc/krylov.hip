@@ -469,11 +469,11 @@ __global__ void __launch_bounds__(kBlock) k_residual(Mat<VT> A, const XT* x, con
     for (int s = 0; s < NS; ++s) xs[s] = x + s * stride;
     tile_walk(
         A.tv,
-        [&](int tx, int ty) __attribute__((always_inline)) {
-            tile_stage<XT, NS>(A.tv, tx, ty, xs, lds, meta, !GEN);
+        [&](int64_t tk) __attribute__((always_inline)) {
+            tile_stage<XT, NS>(A.tv, tk, xs, lds, meta, !GEN);
             int64_t ii[kTileRowsPerWave];
             bool ok[kTileRowsPerWave];
-            tile_row_ids(A.tv, tx, ty, meta, ii, ok);
+            tile_row_ids(A.tv, meta, ii, ok);
             if constexpr (GEN) {
 #pragma unroll
               for (int k = 0; k < kTileRowsPerWave; ++k)
@@ -622,11 +622,11 @@ __global__ void __launch_bounds__(kBlock) k_bicg_v(Mat<VT> A, Vec<T> V, double* 
     if (any)
       tile_walk(
           A.tv,
-          [&](int tx, int ty) __attribute__((always_inline)) {
-            tile_stage<T, NS>(A.tv, tx, ty, xs, lds, meta, !GEN);
+          [&](int64_t tk) __attribute__((always_inline)) {
+            tile_stage<T, NS>(A.tv, tk, xs, lds, meta, !GEN);
             int64_t ii[kTileRowsPerWave];
             bool ok[kTileRowsPerWave];
-            tile_row_ids(A.tv, tx, ty, meta, ii, ok);
+            tile_row_ids(A.tv, meta, ii, ok);
             if constexpr (GEN) {
 #pragma unroll
               for (int k = 0; k < kTileRowsPerWave; ++k)
@@ -751,11 +751,11 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
     if (any)
       tile_walk(
           A.tv,
-          [&](int tx, int ty) __attribute__((always_inline)) {
-            tile_stage<T, NS>(A.tv, tx, ty, xs, lds, meta, !GEN);
+          [&](int64_t tk) __attribute__((always_inline)) {
+            tile_stage<T, NS>(A.tv, tk, xs, lds, meta, !GEN);
             int64_t ii[kTileRowsPerWave];
             bool ok[kTileRowsPerWave];
-            tile_row_ids(A.tv, tx, ty, meta, ii, ok);
+            tile_row_ids(A.tv, meta, ii, ok);
             if constexpr (GEN) {
 #pragma unroll
               for (int k = 0; k < kTileRowsPerWave; ++k)
@@ -943,11 +943,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_q(Mat<VT> A, Vec<T> V, double* pa
     if (any)
       tile_walk(
           A.tv,
-          [&](int tx, int ty) __attribute__((always_inline)) {
-            tile_stage<T, NS>(A.tv, tx, ty, xs, lds, meta, !GEN);
+          [&](int64_t tk) __attribute__((always_inline)) {
+            tile_stage<T, NS>(A.tv, tk, xs, lds, meta, !GEN);
             int64_t ii[kTileRowsPerWave];
             bool ok[kTileRowsPerWave];
-            tile_row_ids(A.tv, tx, ty, meta, ii, ok);
+            tile_row_ids(A.tv, meta, ii, ok);
             if constexpr (GEN) {
 #pragma unroll
               for (int k = 0; k < kTileRowsPerWave; ++k)

@@ -233,6 +233,29 @@ __global__ void k_tile_bits(int64_t m, int ntx, int W, int H, const int32_t* nod
   bits[q] = w;
 }
 
+// Records of the listed tiles (word d of record k): 0 tx, 1 ty, 2..21 the row starts of halo
+// rows 0..19, 22..31 zero, 32..63 the 16 row masks as (low, high) word pairs.
+__global__ void k_tile_rec(int64_t ntiles, const int32_t* tiles, int ntx, const int32_t* rowstart,
+                           const uint64_t* bits, uint32_t* rec) {
+  const int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (q >= ntiles * kTileRecWords) return;
+  const int64_t k = q / kTileRecWords;
+  const int d = static_cast<int>(q % kTileRecWords);
+  const int t = tiles[k], tx = t % ntx, ty = t / ntx;
+  uint32_t v = 0;
+  if (d == 0) {
+    v = static_cast<uint32_t>(tx);
+  } else if (d == 1) {
+    v = static_cast<uint32_t>(ty);
+  } else if (d < 2 + kTileY + 4) {
+    v = static_cast<uint32_t>(rowstart[static_cast<int64_t>(ty * kTileY + d - 2) * ntx + tx]);
+  } else if (d >= 32) {
+    const uint64_t w = bits[static_cast<int64_t>(ty * kTileY + (d - 32) / 2) * ntx + tx];
+    v = (d & 1) ? static_cast<uint32_t>(w >> 32) : static_cast<uint32_t>(w);
+  }
+  rec[q] = v;
+}
+
 // flag[t] = 1 if tile t holds a tile row
 __global__ void k_tile_flag(int64_t ntiles, int ntx, const uint64_t* bits, int64_t* flag) {
   const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -533,6 +556,7 @@ void tile_part_free(TilePart& tp) {
   dfree(tp.bits);
   dfree(tp.tiles);
   dfree(tp.irr);
+  dfree(tp.rec);
   tp = TilePart();
 }
 
@@ -596,6 +620,10 @@ int tile_part(Ctx* c, int key) {
   do {
     k_tile_flag<<<grid_for(nt), kBlock, 0, st>>>(nt, tm.ntx, tp.bits, flag);
     if ((rc = compact(c, flag, nt, &tp.tiles, &tp.ntiles)) != VIP_OK) break;
+    if ((rc = dalloc(c, &tp.rec, tp.ntiles * kTileRecWords)) != VIP_OK) break;
+    if (tp.ntiles > 0)
+      k_tile_rec<<<grid_for(tp.ntiles * kTileRecWords), kBlock, 0, st>>>(tp.ntiles, tp.tiles, tm.ntx, tm.rowstart,
+                                                                          tp.bits, tp.rec);
     k_irr_flag<<<grid_for(c->n), kBlock, 0, st>>>(c->n, c0, c1, flag);
     if ((rc = compact(c, flag, c->n, &tp.irr, &tp.nirr)) != VIP_OK) break;
   } while (false);

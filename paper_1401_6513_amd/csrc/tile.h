@@ -22,8 +22,7 @@ struct TileView {
   int64_t ntiles = 0;
   const int32_t* irr = nullptr;
   int64_t nirr = 0;
-  const uint64_t* bits = nullptr;
-  const int32_t* rowstart = nullptr;
+  const uint32_t* rec = nullptr;    // per listed tile: its record (TileMeta layout)
   const int32_t* node_of = nullptr;
   int ntx = 0, W = 0, H = 0;
   int tile_blocks = 0;              // blocks taking tiles (a multiple of the XCD count)
@@ -37,8 +36,7 @@ inline TileView tile_view(const Ctx* c, const TilePart& tp) {
   v.ntiles = tp.ntiles;
   v.irr = tp.irr;
   v.nirr = tp.nirr;
-  v.bits = tp.bits;
-  v.rowstart = c->tmap.rowstart;
+  v.rec = tp.rec;
   v.node_of = c->lat.node_of;
   v.ntx = c->tmap.ntx;
   v.W = c->lat.W;
@@ -48,38 +46,45 @@ inline TileView tile_view(const Ctx* c, const TilePart& tp) {
   return v;
 }
 
-// Per-tile data staged in LDS: the rows' start nodes and tile-row masks.
+// A tile's record, staged in LDS from its 256-byte block in the partition (one coalesced load):
+// word 0 tx, 1 ty, 2..21 the start nodes of halo rows 0..19 (-1 where a row's 68 pixels are
+// not consecutive nodes), 32..63 the 16 tile-row masks (bit lx: the node at pixel lx of the
+// row is a tile row) as (low, high) word pairs.
 struct TileMeta {
-  int32_t rs[kTileLdsH];
-  uint64_t bits[kTileY];
+  uint32_t w[kTileRecWords];
+  __device__ __forceinline__ int tx() const { return static_cast<int>(w[0]); }
+  __device__ __forceinline__ int ty() const { return static_cast<int>(w[1]); }
+  __device__ __forceinline__ int32_t rs(int r) const { return static_cast<int32_t>(w[2 + r]); }
+  __device__ __forceinline__ uint64_t bits(int r) const {
+    return static_cast<uint64_t>(w[32 + 2 * r]) | (static_cast<uint64_t>(w[33 + 2 * r]) << 32);
+  }
 };
+static_assert(2 + kTileLdsH <= 32 && 32 + 2 * kTileY == kTileRecWords, "tile record layout");
 
-// Stage tile (tx, ty): its metadata, then (with load_x) the LDS copy of NS vectors over the
+// Stage listed tile k: its record, then (with load_x) the LDS copy of NS vectors over the
 // tile and its halo (0 at pixels without a node), every thread issuing all of its loads before
 // storing.  Starts and ends with a block barrier.
 template <typename T, int NS, typename F>
-__device__ __forceinline__ void tile_stage_fn(const TileView& V, int tx, int ty, F&& xf,
+__device__ __forceinline__ void tile_stage_fn(const TileView& V, int64_t k, F&& xf,
                                               T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x);
 
 template <typename T, int NS>
-__device__ __forceinline__ void tile_stage(const TileView& V, int tx, int ty, const T* const (&x)[NS],
+__device__ __forceinline__ void tile_stage(const TileView& V, int64_t k, const T* const (&x)[NS],
                                            T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x) {
   tile_stage_fn<T, NS>(
-      V, tx, ty, [&](int s, int32_t node) __attribute__((always_inline)) { return x[s][node]; }, t, m, load_x);
+      V, k, [&](int s, int32_t node) __attribute__((always_inline)) { return x[s][node]; }, t, m, load_x);
 }
 
 // The same with the staged values given by xf(s, node) (system s at a node).
 template <typename T, int NS, typename F>
-__device__ __forceinline__ void tile_stage_fn(const TileView& V, int tx, int ty, F&& xf,
+__device__ __forceinline__ void tile_stage_fn(const TileView& V, int64_t k, F&& xf,
                                               T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x) {
   const int tid = static_cast<int>(threadIdx.x);
   __syncthreads();
-  if (tid < kTileLdsH)
-    m.rs[tid] = V.rowstart[static_cast<int64_t>(ty * kTileY + tid) * V.ntx + tx];
-  else if (tid < kTileLdsH + kTileY)
-    m.bits[tid - kTileLdsH] = V.bits[static_cast<int64_t>(ty * kTileY + tid - kTileLdsH) * V.ntx + tx];
+  if (tid < kTileRecWords) m.w[tid] = V.rec[k * kTileRecWords + tid];
   __syncthreads();
   if (!load_x) return;
+  const int tx = m.tx(), ty = m.ty();
   constexpr int kElems = kTileLdsH * kTileLdsW;
   constexpr int kPer = (kElems + kBlock - 1) / kBlock;
   int32_t node[kPer];
@@ -89,7 +94,7 @@ __device__ __forceinline__ void tile_stage_fn(const TileView& V, int tx, int ty,
     node[k] = -1;
     if (q < kElems) {
       const int r = q / kTileLdsW, cc = q % kTileLdsW;
-      const int32_t rs = m.rs[r];
+      const int32_t rs = m.rs(r);
       if (rs >= 0) {
         node[k] = rs + cc;
       } else {
@@ -115,15 +120,16 @@ __device__ __forceinline__ void tile_stage_fn(const TileView& V, int tx, int ty,
 
 constexpr int kTileRowsPerWave = kTileY / (kBlock / 64);
 
-// The wave's local rows ly = wave + 4 k of tile (tx, ty): node i[k] where ok[k] (a tile row).
-__device__ __forceinline__ void tile_row_ids(const TileView& V, int tx, int ty, const TileMeta& m,
+// The wave's local rows ly = wave + 4 k of the staged tile: node i[k] where ok[k] (a tile row).
+__device__ __forceinline__ void tile_row_ids(const TileView& V, const TileMeta& m,
                                              int64_t (&i)[kTileRowsPerWave], bool (&ok)[kTileRowsPerWave]) {
   const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+  const int tx = m.tx(), ty = m.ty();
 #pragma unroll
   for (int k = 0; k < kTileRowsPerWave; ++k) {
     const int ly = wave + k * (kBlock / 64);
-    ok[k] = (m.bits[ly] >> lane) & 1ull;
-    const int32_t rs = m.rs[ly + 2];
+    ok[k] = (m.bits(ly) >> lane) & 1ull;
+    const int32_t rs = m.rs(ly + 2);
     i[k] = 0;
     if (ok[k])
       i[k] = rs >= 0 ? static_cast<int64_t>(rs) + 2 + lane
@@ -132,9 +138,9 @@ __device__ __forceinline__ void tile_row_ids(const TileView& V, int tx, int ty, 
 }
 
 // Blocks [0, irr_blocks) call irr(i) for the irregular rows, one per thread (they start first
-// and overlap the tiles).  The tile blocks call tile(tx, ty): blocks are dispatched to the XCDs
-// round-robin, so each XCD gets an equal contiguous share of the tile list (neighbouring tiles
-// then share its L2), which its blocks take in turn.
+// and overlap the tiles).  The tile blocks call tile(k) for positions k of the tile list: blocks
+// are dispatched to the XCDs round-robin, so each XCD gets an equal contiguous share of the
+// list (neighbouring tiles then share its L2), which its blocks take in turn.
 template <typename Tile, typename Irr>
 __device__ __forceinline__ void tile_walk(const TileView& V, Tile&& tile, Irr&& irr) {
   if (static_cast<int>(blockIdx.x) < V.irr_blocks) {
@@ -145,10 +151,7 @@ __device__ __forceinline__ void tile_walk(const TileView& V, Tile&& tile, Irr&& 
     const int64_t b = static_cast<int64_t>(blockIdx.x) - V.irr_blocks;
     const int64_t xcd = b % kNumXcd, j = b / kNumXcd, per = V.tile_blocks / kNumXcd;
     const int64_t t1 = V.ntiles * (xcd + 1) / kNumXcd;
-    for (int64_t k = V.ntiles * xcd / kNumXcd + j; k < t1; k += per) {
-      const int32_t t = V.tiles[k];
-      tile(t % V.ntx, t / V.ntx);
-    }
+    for (int64_t k = V.ntiles * xcd / kNumXcd + j; k < t1; k += per) tile(k);
   }
 }
 

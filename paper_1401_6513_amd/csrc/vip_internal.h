@@ -32,6 +32,8 @@ struct Error {
 constexpr int kTileX = 64;
 constexpr int kTileY = 16;
 // Rows of one canonical set (or a pair of sets) split into tile rows and irregular rows.
+constexpr int kTileRecWords = 64;   // 32-bit words of a tile record
+
 struct TilePart {
   uint64_t* bits = nullptr;         // device [nty*kTileY*ntx]: bit lx of word (y, tx): the node at
                                     // pixel (64 tx + lx, y) is a tile row
@@ -39,6 +41,9 @@ struct TilePart {
   int64_t ntiles = 0;
   int32_t* irr = nullptr;           // device [nirr]: every other row, ascending
   int64_t nirr = 0;
+  uint32_t* rec = nullptr;          // device [ntiles * kTileRecWords]: per listed tile, in list order,
+                                    // its record (tile.h, TileMeta): tx, ty, the 20 halo-row starts
+                                    // and the 16 row masks in one 256-byte block
   int tile_blocks = 0, irr_blocks = 0;   // launch split of a tiled kernel
 };
 // Tile geometry of the lattice.

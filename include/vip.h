@@ -162,6 +162,9 @@ int vip_set_options(void* ctx, const vip_options* opt);
  *  dt, Re   time step and Reynolds number (> 0).  A change of dt or Re
  *           re-assembles the Helmholtz operators and restarts AB2 (the first
  *           step uses N^(n-1) = N^n).
+ *  The predictor solve starts from 2 u*(n-1) - u*(n-2) once two earlier steps
+ *  of the same dt and Re have converged (u*(n-1) after one, else the
+ *  right-hand side); the start does not change what it converges to.
  *  stats    host, may be NULL.
  * Errors: VIP_E_NOT_BUILT, VIP_E_INVALID, VIP_E_NOT_CONVERGED (state is still
  * advanced), VIP_E_NONFINITE, VIP_E_HIP.
@@ -169,7 +172,8 @@ int vip_set_options(void* ctx, const vip_options* opt);
 int vip_step(void* ctx, double* u, double* v, double* p, double dt, double Re,
              vip_step_stats* stats);
 
-/* Forget the AB2 history and the previous pressure increment. */
+/* Forget the AB2 history, the previous pressure increment and the two previous
+ * predictor solutions (the predictor solve then starts from its right-hand side). */
 int vip_reset_history(void* ctx);
 
 /*

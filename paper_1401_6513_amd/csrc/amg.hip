@@ -293,6 +293,14 @@ struct LevelView {
   TileView tv;            // level 0: tile partition of the canonical rows (tile.h), if any
 };
 
+// a * b + c with one rounding, written out so that every path that must give the same bits
+// (canonical and general rows, tile and row sweeps) rounds alike whatever the compiler fuses
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return fmaf(a, b, c);
+  else return fma(a, b, c);
+}
+
 // Canonical row of a level: weights of the reference row, columns from the lattice map,
 // slots to the accumulators in the general path's order (same bits).
 template <typename T, class Tap>
@@ -301,11 +309,11 @@ __device__ __forceinline__ T disk_taps(const LevelView<T>& L, Tap&& tap) {
   T a0 = T(0), a1 = T(0);
 #pragma unroll
   for (int k = 0; k < kDiskTaps; ++k) {
-    const T d = L.w[k] * (tap(disk_row(k), disk_dx(k)) - yi);
-    if (k & 1) a1 += d;
-    else a0 += d;
+    const T d = tap(disk_row(k), disk_dx(k)) - yi;
+    if (k & 1) a1 = fmadd(L.w[k], d, a1);
+    else a0 = fmadd(L.w[k], d, a0);
   }
-  if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
+  if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.crsum), yi, a0 + a1);
   else return a0 + a1;
 }
 
@@ -332,10 +340,11 @@ __device__ __forceinline__ T canon_row(const LevelView<T>& L, int32_t p, int64_t
     T a0 = T(0), a1 = T(0);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      if (k & 1) a1 += L.w[k] * (y(b[k / 3] + (k % 3 - 1)) - yi);
-      else a0 += L.w[k] * (y(b[k / 3] + (k % 3 - 1)) - yi);
+      const T d = y(b[k / 3] + (k % 3 - 1)) - yi;
+      if (k & 1) a1 = fmadd(L.w[k], d, a1);
+      else a0 = fmadd(L.w[k], d, a0);
     }
-    if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
+    if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.crsum), yi, a0 + a1);
     else return a0 + a1;
   }
   const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
@@ -345,17 +354,17 @@ __device__ __forceinline__ T canon_row(const LevelView<T>& L, int32_t p, int64_t
   int k = 0;
   for (; k + 4 <= L.K && k + 4 <= full; k += 4) {
     const T y0 = y(nb[L.off[k]]), y1 = y(nb[L.off[k + 1]]), y2 = y(nb[L.off[k + 2]]), y3 = y(nb[L.off[k + 3]]);
-    a0 += L.w[k] * (y0 - yi);
-    a1 += L.w[k + 1] * (y1 - yi);
-    a0 += L.w[k + 2] * (y2 - yi);
-    a1 += L.w[k + 3] * (y3 - yi);
+    a0 = fmadd(L.w[k], y0 - yi, a0);
+    a1 = fmadd(L.w[k + 1], y1 - yi, a1);
+    a0 = fmadd(L.w[k + 2], y2 - yi, a0);
+    a1 = fmadd(L.w[k + 3], y3 - yi, a1);
   }
   for (; k < L.K; ++k) {
-    const T d = L.w[k] * (y(nb[L.off[k]]) - yi);
-    if (k < full && (k & 1)) a1 += d;
-    else a0 += d;
+    const T d = y(nb[L.off[k]]) - yi;
+    if (k < full && (k & 1)) a1 = fmadd(L.w[k], d, a1);
+    else a0 = fmadd(L.w[k], d, a0);
   }
-  if constexpr (sizeof(T) == 4) return a0 + a1 + L.crsum * yi;
+  if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.crsum), yi, a0 + a1);
   else return a0 + a1;
 }
 
@@ -407,16 +416,16 @@ __device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
                   c3 = L.cols[q + 3 * kSlice];
     const T v0 = L.val[q], v1 = L.val[q + kSlice], v2 = L.val[q + 2 * kSlice], v3 = L.val[q + 3 * kSlice];
     const T y0 = y(c0), y1 = y(c1), y2 = y(c2), y3 = y(c3);
-    a0 += v0 * (y0 - yi);
-    a1 += v1 * (y1 - yi);
-    a0 += v2 * (y2 - yi);
-    a1 += v3 * (y3 - yi);
+    a0 = fmadd(v0, y0 - yi, a0);
+    a1 = fmadd(v1, y1 - yi, a1);
+    a0 = fmadd(v2, y2 - yi, a0);
+    a1 = fmadd(v3, y3 - yi, a1);
   }
   for (; k < w; ++k) {
     const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-    a0 += L.val[q] * (y(L.cols[q]) - yi);
+    a0 = fmadd(L.val[q], y(L.cols[q]) - yi, a0);
   }
-  if constexpr (sizeof(T) == 4) return a0 + a1 + L.rsum[i] * yi;
+  if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.rsum[i]), yi, a0 + a1);
   else return a0 + a1;
 }
 
@@ -544,12 +553,12 @@ __global__ void __launch_bounds__(kBlock) k_sweep(LevelView<T> L, const T* b, Sw
             if (!ok[k]) continue;
             const int ly = wave + k * (kBlock / 64);
             const T ay = disk_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
-            out[ii[k]] = lds[0][ly + 2][lane + 2] + wd[k] * (bi[k] - ay);
+            out[ii[k]] = fmadd(wd[k], bi[k] - ay, lds[0][ly + 2][lane + 2]);
           }
         },
         [&](int64_t i) __attribute__((always_inline)) {
           const T ay = level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return yf(j); });
-          out[i] = yf(i) + level_wdinv(L, i) * (b[i] - ay);
+          out[i] = fmadd(level_wdinv(L, i), b[i] - ay, yf(i));
         });
     return;
   }
@@ -557,7 +566,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(LevelView<T> L, const T* b, Sw
   const int64_t i = lb * blockDim.x + threadIdx.x;
   if (i >= L.n) return;
   const T ay = level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return yf(j); });
-  out[i] = yf(i) + level_wdinv(L, i) * (b[i] - ay);
+  out[i] = fmadd(level_wdinv(L, i), b[i] - ay, yf(i));
 }
 
 // x[0..rows) = Inv[0..rows, 0..cols) b on the coarsest level (one wavefront per row);

@@ -58,6 +58,8 @@ void ctx_free_build(Ctx* c) {
   dfree(c->dinv32);
   dfree(c->nprev);
   dfree(c->stepbuf);
+  dfree(c->star_prev);
+  c->nstar = 0;
   dfree(c->phi);
   dfree(c->ws);
   c->ws_len = 0;
@@ -65,6 +67,7 @@ void ctx_free_build(Ctx* c) {
   c->ws32_len = 0;
   c->assembled = false;
   c->have_prev_n = false;
+  c->nstar = 0;
   c->have_prev_phi = false;
   learn_free_nodeset(c);
   vip_canon_free(c);
@@ -270,6 +273,7 @@ int vip_reset_history(void* p) {
   Ctx* c = vip::as_ctx(p);
   VIP_TRY(vip::need_built(c));
   c->have_prev_n = false;
+  c->nstar = 0;
   c->have_prev_phi = false;
   c->learn.have_eprev = false;
   return VIP_OK;
@@ -372,6 +376,7 @@ int vip_assemble(void* p, double dt, double Re) {
   VIP_TRY(vip::bind_device(c));
   VIP_TRY(vip::assemble_helmholtz(c, dt, Re));
   c->have_prev_n = false;
+  c->nstar = 0;
   VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
   return VIP_OK;
 }

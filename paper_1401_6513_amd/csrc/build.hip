@@ -1023,6 +1023,7 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   VIP_HIP_TRY(c, hipMemsetAsync(c->phi, 0, sizeof(double) * (n + 1), st));
   c->assembled = false;
   c->have_prev_n = false;
+  c->nstar = 0;
   c->have_prev_phi = false;
   c->cur_dt = 0.0;
   c->cur_re = 0.0;

@@ -222,7 +222,10 @@ struct Vec {
 
 // Canonical row: the weights come from the reference row and the columns from the lattice
 // map.  Slots go to the two accumulators in the general path's order (pairs of the unrolled
-// groups alternate, the tail goes to the first), so the bits are the same.
+// groups alternate, the tail goes to the first), so the bits are the same.  Every product is
+// added by an explicit fused multiply-add, here, in the general row and in the reductions of
+// the kernels' two variants: left to the compiler, fusing depends on where the product lands
+// in the code and then differs between the variants in the last bit.
 // 21-point disk with the five row bases given: slots 0, 2, ..., 20 to the first accumulator,
 // the odd ones to the second (a slice of such rows is at least 21 wide, so only slot 20 can
 // fall in the tail of the general path)
@@ -233,18 +236,18 @@ __device__ __forceinline__ double disk_sum(const Mat<VT>& A, int sys, Tap&& tap)
     float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
     for (int k = 0; k < kDiskTaps; ++k) {
-      const float d = A.w[sys][k] * (static_cast<float>(tap(disk_row(k), disk_dx(k))) - xi);
-      if (k & 1) a1 += d;
-      else a0 += d;
+      const float d = static_cast<float>(tap(disk_row(k), disk_dx(k))) - xi;
+      if (k & 1) a1 = fmaf(A.w[sys][k], d, a1);
+      else a0 = fmaf(A.w[sys][k], d, a0);
     }
     return static_cast<double>(a0 + a1) + static_cast<double>(A.crsum[sys] * xi);
   } else {
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
     for (int k = 0; k < kDiskTaps; ++k) {
-      const double d = A.w[sys][k] * static_cast<double>(tap(disk_row(k), disk_dx(k)));
-      if (k & 1) a1 += d;
-      else a0 += d;
+      const double d = static_cast<double>(tap(disk_row(k), disk_dx(k)));
+      if (k & 1) a1 = fma(A.w[sys][k], d, a1);
+      else a0 = fma(A.w[sys][k], d, a0);
     }
     return a0 + a1;
   }
@@ -282,15 +285,15 @@ __device__ __forceinline__ double canon_dot(const Mat<VT>& A, int sys, int32_t p
       const int32_t c0 = nb[A.off[k]], c1 = nb[A.off[k + 1]], c2 = nb[A.off[k + 2]], c3 = nb[A.off[k + 3]];
       const float x0 = static_cast<float>(x[c0]), x1 = static_cast<float>(x[c1]),
                   x2 = static_cast<float>(x[c2]), x3 = static_cast<float>(x[c3]);
-      a0 += A.w[sys][k] * (x0 - xi);
-      a1 += A.w[sys][k + 1] * (x1 - xi);
-      a0 += A.w[sys][k + 2] * (x2 - xi);
-      a1 += A.w[sys][k + 3] * (x3 - xi);
+      a0 = fmaf(A.w[sys][k], x0 - xi, a0);
+      a1 = fmaf(A.w[sys][k + 1], x1 - xi, a1);
+      a0 = fmaf(A.w[sys][k + 2], x2 - xi, a0);
+      a1 = fmaf(A.w[sys][k + 3], x3 - xi, a1);
     }
     for (; k < A.K; ++k) {
-      const float d = A.w[sys][k] * (static_cast<float>(x[nb[A.off[k]]]) - xi);
-      if (k < full && (k & 1)) a1 += d;
-      else a0 += d;
+      const float d = static_cast<float>(x[nb[A.off[k]]]) - xi;
+      if (k < full && (k & 1)) a1 = fmaf(A.w[sys][k], d, a1);
+      else a0 = fmaf(A.w[sys][k], d, a0);
     }
     return static_cast<double>(a0 + a1) + static_cast<double>(A.crsum[sys] * xi);
   } else {
@@ -300,15 +303,15 @@ __device__ __forceinline__ double canon_dot(const Mat<VT>& A, int sys, int32_t p
       const int32_t c0 = nb[A.off[k]], c1 = nb[A.off[k + 1]], c2 = nb[A.off[k + 2]], c3 = nb[A.off[k + 3]];
       const double x0 = static_cast<double>(x[c0]), x1 = static_cast<double>(x[c1]),
                    x2 = static_cast<double>(x[c2]), x3 = static_cast<double>(x[c3]);
-      a0 += A.w[sys][k] * x0;
-      a1 += A.w[sys][k + 1] * x1;
-      a0 += A.w[sys][k + 2] * x2;
-      a1 += A.w[sys][k + 3] * x3;
+      a0 = fma(A.w[sys][k], x0, a0);
+      a1 = fma(A.w[sys][k + 1], x1, a1);
+      a0 = fma(A.w[sys][k + 2], x2, a0);
+      a1 = fma(A.w[sys][k + 3], x3, a1);
     }
     for (; k < A.K; ++k) {
-      const double d = A.w[sys][k] * static_cast<double>(x[nb[A.off[k]]]);
-      if (k < full && (k & 1)) a1 += d;
-      else a0 += d;
+      const double d = static_cast<double>(x[nb[A.off[k]]]);
+      if (k < full && (k & 1)) a1 = fma(A.w[sys][k], d, a1);
+      else a0 = fma(A.w[sys][k], d, a0);
     }
     return a0 + a1;
   }
@@ -342,14 +345,14 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
       const float v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
       const float x0 = static_cast<float>(x[c0]), x1 = static_cast<float>(x[c1]),
                   x2 = static_cast<float>(x[c2]), x3 = static_cast<float>(x[c3]);
-      a0 += v0 * (x0 - xi);
-      a1 += v1 * (x1 - xi);
-      a0 += v2 * (x2 - xi);
-      a1 += v3 * (x3 - xi);
+      a0 = fmaf(v0, x0 - xi, a0);
+      a1 = fmaf(v1, x1 - xi, a1);
+      a0 = fmaf(v2, x2 - xi, a0);
+      a1 = fmaf(v3, x3 - xi, a1);
     }
     for (; k < w; ++k) {
       const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      a0 += static_cast<float>(vals[q]) * (static_cast<float>(x[A.cols[q]]) - xi);
+      a0 = fmaf(static_cast<float>(vals[q]), static_cast<float>(x[A.cols[q]]) - xi, a0);
     }
     return static_cast<double>(a0 + a1) + static_cast<double>(A.rsum[sys][i] * xi);
   } else {
@@ -362,14 +365,14 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
       const double v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
       const double x0 = static_cast<double>(x[c0]), x1 = static_cast<double>(x[c1]),
                    x2 = static_cast<double>(x[c2]), x3 = static_cast<double>(x[c3]);
-      a0 += v0 * x0;
-      a1 += v1 * x1;
-      a0 += v2 * x2;
-      a1 += v3 * x3;
+      a0 = fma(v0, x0, a0);
+      a1 = fma(v1, x1, a1);
+      a0 = fma(v2, x2, a0);
+      a1 = fma(v3, x3, a1);
     }
     for (; k < w; ++k) {
       const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      a0 += static_cast<double>(vals[q]) * static_cast<double>(x[A.cols[q]]);
+      a0 = fma(static_cast<double>(vals[q]), static_cast<double>(x[A.cols[q]]), a0);
     }
     return a0 + a1;
   }
@@ -454,8 +457,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(Mat<VT> A, const XT* x, con
     if (A.border) ax += xn[s];
     const double ri = bi - ax;
     r[s * stride + i] = static_cast<RT>(ri);
-    acc[3 * s + 0] += ri * ri;
-    acc[3 * s + 1] += bi * bi;
+    acc[3 * s + 0] = fma(ri, ri, acc[3 * s + 0]);
+    acc[3 * s + 1] = fma(bi, bi, acc[3 * s + 1]);
     if (A.border) acc[3 * s + 2] += xi;
   };
   auto slow = [&](int64_t i) __attribute__((always_inline)) {
@@ -606,7 +609,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_v(Mat<VT> A, Vec<T> V, double* 
     if (A.border) y += phn[s];
     const T yt = static_cast<T>(y);
     V.v[s * V.stride + i] = yt;
-    acc[2 * s] += static_cast<double>(rh) * static_cast<double>(yt);
+    acc[2 * s] = fma(static_cast<double>(rh), static_cast<double>(yt), acc[2 * s]);
     if (A.border) acc[2 * s + 1] += static_cast<double>(pc);
   };
   auto slow = [&](int64_t i) __attribute__((always_inline)) {
@@ -734,8 +737,8 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
     if (A.border) y += shn[s];
     const T yt = static_cast<T>(y);
     V.t[s * V.stride + i] = yt;
-    acc[3 * s] += static_cast<double>(yt) * static_cast<double>(sv);
-    acc[3 * s + 1] += static_cast<double>(yt) * static_cast<double>(yt);
+    acc[3 * s] = fma(static_cast<double>(yt), static_cast<double>(sv), acc[3 * s]);
+    acc[3 * s + 1] = fma(static_cast<double>(yt), static_cast<double>(yt), acc[3 * s + 1]);
     if (A.border) acc[3 * s + 2] += static_cast<double>(si);
   };
   auto slow = [&](int64_t i) __attribute__((always_inline)) {
@@ -929,7 +932,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_q(Mat<VT> A, Vec<T> V, double* pa
   auto emit = [&](int s, int64_t i, double y, T pc) __attribute__((always_inline)) {
     const T yt = static_cast<T>(y);
     V.v[s * V.stride + i] = yt;
-    acc[s] += static_cast<double>(pc) * static_cast<double>(yt);
+    acc[s] = fma(static_cast<double>(pc), static_cast<double>(yt), acc[s]);
   };
   auto slow = [&](int64_t i) __attribute__((always_inline)) {
 #pragma unroll
@@ -1121,6 +1124,12 @@ __global__ void k_add_scaled(int64_t m, int64_t stride, int64_t n, double* x, co
   if (o >= m) return;
   const int64_t i = o % stride;
   if (i < n) x[o] += (o < stride ? dinv0 : dinv1)[i] * static_cast<double>(y[o]);
+}
+
+// x = 2 a - b (linear extrapolation from the last two values)
+__global__ void k_extrapolate(int64_t n, const double* a, const double* b, double* x) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < n) x[i] = 2.0 * a[i] - b[i];
 }
 
 // partial sums of a[0..m)
@@ -1532,9 +1541,23 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
   hipStream_t s = c->stream;
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, b);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, b + stride);
-  // start from the right-hand side (the operators are close to the identity)
-  k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, x);
-  k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, x + stride);
+  // start vector: the linear extrapolation 2 u*(n-1) - u*(n-2) of the last two predictor
+  // solutions (error O(dt^2)), the last solution when only one is held, else the right-hand
+  // side (the operators are close to the identity); the history counts again only once this
+  // solve has succeeded
+  const int held = c->nstar;
+  c->nstar = 0;
+  if (held >= 1 && !c->star_prev) VIP_TRY(dalloc(c, &c->star_prev, 2 * stride));
+  if (held >= 2) {
+    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, us, c->star_prev, x);
+    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, vs, c->star_prev + stride, x + stride);
+  } else if (held == 1) {
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, us, x);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, vs, x + stride);
+  } else {
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, x);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, x + stride);
+  }
   Mat<double> H{n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[1], c->sys.val[2]}, {nullptr, nullptr}};
   attach_canon(c, H, 1, 2);
   Vec<double> V = make_vec<double>(c->ws, stride, 2, x);
@@ -1594,9 +1617,15 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
       if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite predictor residual");
     }
   }
+  if (held >= 1) {
+    // the last solution becomes the one before
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, us, c->star_prev);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, vs, c->star_prev + stride);
+  }
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x, us);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x + stride, vs);
   VIP_HIP_TRY(c, hipGetLastError());
+  if (converged && std::isfinite(worst)) c->nstar = std::min(held + 1, 2);
   if (st) {
     st->helmholtz_iters = total;
     st->helmholtz_residual = worst;

@@ -29,8 +29,8 @@ __device__ __forceinline__ void row2(const Op& A, int64_t i, const double* f, co
     const int64_t q = base + k * kSlice;
     const int32_t j = A.cols[q];
     const double v = A.val[q];
-    a += v * f[j];
-    b += v * g[j];
+    a = fma(v, f[j], a);
+    b = fma(v, g[j], b);
   }
   *af = a;
   *ag = b;
@@ -43,7 +43,7 @@ __device__ __forceinline__ double row1(const Op& A, int64_t i, const double* f) 
   double a = 0.0;
   for (int64_t k = 0; k < w; ++k) {
     const int64_t q = base + k * kSlice;
-    a += A.val[q] * f[A.cols[q]];
+    a = fma(A.val[q], f[A.cols[q]], a);
   }
   return a;
 }
@@ -55,8 +55,8 @@ struct Vips {
 };
 
 // Canonical nodes (all six per-step rows lattice-interior): the reference weights and the
-// lattice map replace the column and value streams.  Sums run in slot order, as in row1/row2,
-// so both paths give the same bits.
+// lattice map replace the column and value streams.  Sums run in slot order with explicit fused
+// multiply-adds, as in row1/row2, so both paths give the same bits.
 struct VC {
   const int32_t* cpix;              // nullptr: every node takes the sliced-ELL path
   const int32_t* node_of;
@@ -88,9 +88,9 @@ struct EllRows {
       const int64_t q = base + static_cast<int64_t>(t) * kSlice;
       const int32_t j = m00.cols[q];
       const double id = exact_id ? (j == static_cast<int32_t>(i) ? 1.0 : 0.0) : m00.val[q];
-      const double r = id + c * lap.val[q];
-      a += r * u[j];
-      b += r * v[j];
+      const double r = fma(c, lap.val[q], id);
+      a = fma(r, u[j], a);
+      b = fma(r, v[j], b);
     }
     *au = a;
     *av = b;
@@ -113,7 +113,7 @@ struct CanonRows {
     for (int d = 0; d < kVcRows; ++d) {
       const int L = C.len[o][d];
       const double* fr = f + rb[d] + C.dx0[o][d];
-      for (int t = 0; t < L; ++t) a += C.w[o][k + t] * fr[t];
+      for (int t = 0; t < L; ++t) a = fma(C.w[o][k + t], fr[t], a);
       k += L;
     }
     return a;
@@ -127,8 +127,8 @@ struct CanonRows {
       const int32_t j0 = rb[d] + C.dx0[o][d];
       for (int t = 0; t < L; ++t) {
         const double w = C.w[o][k + t];
-        a += w * f[j0 + t];
-        b += w * g[j0 + t];
+        a = fma(w, f[j0 + t], a);
+        b = fma(w, g[j0 + t], b);
       }
       k += L;
     }
@@ -142,7 +142,7 @@ struct CanonRows {
     for (int d = 0; d < kVcRows; ++d) {
       const int L = C.len[4][d];
       const double* fr = f + rb[d] + C.dx0[4][d];
-      for (int t = 0; t < L; ++t) a += C.w[kVcOps][k + t] * fr[t];
+      for (int t = 0; t < L; ++t) a = fma(C.w[kVcOps][k + t], fr[t], a);
       k += L;
     }
     return a;
@@ -158,9 +158,9 @@ struct CanonRows {
       const int32_t j0 = rb[d] + dx0;
       for (int t = 0; t < L; ++t) {
         const double id = exact_id ? (d == 3 && dx0 + t == 0 ? 1.0 : 0.0) : C.w[4][k + t];
-        const double r = id + c * C.w[kVcOps][k + t];
-        a += r * u[j0 + t];
-        b += r * v[j0 + t];
+        const double r = fma(c, C.w[kVcOps][k + t], id);
+        a = fma(r, u[j0 + t], a);
+        b = fma(r, v[j0 + t], b);
       }
       k += L;
     }
@@ -367,6 +367,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   if (!c->assembled || dt != c->cur_dt || re != c->cur_re) {
     VIP_TRY(assemble_helmholtz(c, dt, re));
     c->have_prev_n = false;   // AB2 restarts after a change of dt or Re
+    c->nstar = 0;
     c->learn.have_eprev = false;
   }
   if (!c->stepbuf) VIP_TRY(dalloc(c, &c->stepbuf, 5 * n));

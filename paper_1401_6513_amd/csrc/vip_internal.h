@@ -311,6 +311,9 @@ struct Ctx {
   bool have_prev_phi = false;
   double* nprev = nullptr;        // device [2n]
   double* stepbuf = nullptr;      // device [5n]: predictor right-hand sides, u*, v*, divergence
+  double* star_prev = nullptr;    // device [2(n+1)]: the predictor solutions u*, v* of the step before
+                                  // the last one (the last one's stay in stepbuf)
+  int nstar = 0;                  // previous predictor solutions held (0..2) for the start vector
   double* phi = nullptr;          // device [n+1] (last entry: border multiplier)
   double* ws = nullptr;           // device work vectors (FP64)
   int64_t ws_len = 0;

@@ -74,3 +74,31 @@ def test_canonical_rows_give_the_same_bits(name, precision):
     assert ia == ib
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e-6])
+def test_poisson_solve_same_bits_at_any_scale(scale):
+    """The bordered FP64 Poisson solve of the closed cavity with canonical rows on and off, on
+    right-hand sides of unit and of 1e-6 size: the block partial sums of the reducing kernels
+    round alike in both variants, so the solutions and iteration counts agree bit for bit."""
+    from paper_1401_6513_amd import vip
+    spec = ns.lid_cavity(65)
+    ctxs = []
+    for no_canon in (False, True):
+        ctx = _ctx(no_canon)
+        ctx.build_from_spec(spec, precision=vip.P_FP64, warmstart=vip.WS_PREV)
+        ctxs.append(ctx)
+    try:
+        for seed in range(4):
+            r = np.random.default_rng(seed).standard_normal(spec.n) * scale
+            r -= r.mean()
+            out = []
+            for ctx in ctxs:
+                phi = torch.zeros(spec.n, dtype=torch.float64, device="cuda")
+                st = ctx.vip_poisson_solve(torch.tensor(r, device="cuda"), phi, 1e-8)
+                out.append((phi.cpu().numpy(), st["poisson_iters"]))
+            assert out[0][1] == out[1][1]
+            assert np.array_equal(out[0][0], out[1][0])
+    finally:
+        for ctx in ctxs:
+            ctx.close()

@@ -298,10 +298,11 @@ def main():
         ntiles = -(-W // 64) * -(-H // 16)
         # algorithmic bytes of one launch: x read once, r-hat read, v written (3 vectors); stored
         # values + int32 columns of the irregular rows (and, in FP32, their row sums) and the
-        # irregular-row list; per 64 x 16 tile its 20 row starts and 16 row masks (208 bytes).
-        # Canonical (tile) rows read no column or value stream.
+        # irregular-row list; per 64 x 16 tile its 256-byte record (position, 20 row starts, 16 row
+        # masks), counted for every lattice tile.  Canonical (tile) rows read no column or value
+        # stream.
         bytes_per_launch = (3 * vb * n0 + (vb + 4) * (nnz0 - taps * nc) + (4 if fp32 else 0) * (n0 - nc)
-                            + 4 * (n0 - nc) + 208 * ntiles)
+                            + 4 * (n0 - nc) + 256 * ntiles)
         avg_ms, count = r["spmv"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -493,31 +493,75 @@ __global__ void k_restrict(int64_t nc, const int64_t* mstart, const int32_t* mem
   bc[I] = s;
 }
 
-// y = x + P xc   (coarse correction; x may be absent: zero pre-smoothing)
+// bc[I] = sum over the members i of aggregate I of (b - A x)_i: the residual and the restriction
+// in one launch, for coarse levels where launches cost more than the work.  Each member's
+// residual is the expression k_level_residual stores, summed in k_restrict's order.  Four
+// lanes per aggregate compute its first four members' residuals side by side (the first lane
+// takes any further members itself); grid: 4 nc threads.
+template <typename T>
+__global__ void k_restrict_residual(LevelView<T> L, int64_t nc, const int64_t* mstart, const int32_t* members,
+                                    const T* b, const T* x, T* bc, const int* on) {
+  if (!*on) return;
+  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t I = t >> 2;
+  const int k = static_cast<int>(t & 3);
+  const bool valid = I < nc;
+  const int64_t m0 = valid ? mstart[I] : 0, m1 = valid ? mstart[I + 1] : 0;
+  auto res = [&](int64_t m) __attribute__((always_inline)) {
+    const int32_t i = members[m];
+    return b[i] - level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return x[j]; });
+  };
+  const T r = (m0 + k < m1) ? res(m0 + k) : T(0);
+  // the group's four lanes are consecutive lanes of one wavefront (4 divides 64)
+  const T r1 = __shfl(r, 1, 4), r2 = __shfl(r, 2, 4), r3 = __shfl(r, 3, 4);
+  if (!valid || k != 0) return;
+  const int64_t cnt = m1 - m0;
+  T s = T(0);
+  if (cnt > 0) s += r;
+  if (cnt > 1) s += r1;
+  if (cnt > 2) s += r2;
+  if (cnt > 3) s += r3;
+  for (int64_t m = m0 + 4; m < m1; ++m) s += res(m);
+  bc[I] = s;
+}
+
+// (x + gamma P xc)_j, the corrected iterate at row j (x may be absent: zero pre-smoothing)
+template <typename T>
+__device__ __forceinline__ T prolong_value(const T* x, const int32_t* agg, const T* xc, T gamma, int64_t j) {
+  const int32_t a = agg[j];
+  const T base = x ? x[j] : T(0);
+  return a >= 0 ? fmadd(gamma, xc[a], base) : base;
+}
+
+// y = x + gamma P xc   (coarse correction)
 template <typename T>
 __global__ void k_prolong(int64_t n, const int32_t* agg, const T* xc, T gamma, const T* x, T* y,
                           const int* on) {
   if (!*on) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
-  const int32_t a = agg[i];
-  y[i] = (x ? x[i] : T(0)) + (a >= 0 ? gamma * xc[a] : T(0));
+  y[i] = prolong_value(x, agg, xc, gamma, i);
 }
 
-// The iterate a smoothing sweep starts from: y in memory (kind 0) or the zero-start sweep's W b
-// (kind 1, the output of k_jacobi0), recomputed wherever it is needed with the same
-// arithmetic as k_jacobi0, so the fused sweep gives the same bits as the two launches it
-// replaces.
+// The iterate a smoothing sweep starts from: y in memory (kind 0), the zero-start sweep's W b
+// (kind 1, the output of k_jacobi0) or the coarse-corrected iterate x + gamma P xc (kind 2, the
+// output of k_prolong), recomputed wherever it is needed with the same arithmetic as the launch
+// it replaces, so the fused sweep gives the same bits as the two launches.
 template <typename T>
 struct SweepIn {
   const T* y;              // kind 0
   const T* b;              // kind 1
+  const T* x;              // kind 2: pre-smoothed iterate, coarse correction, aggregate map
+  const T* xc;
+  const int32_t* agg;
+  T gamma;
 };
 
 template <typename T, int KIND>
 __device__ __forceinline__ T sweep_in(const LevelView<T>& L, const SweepIn<T>& in, int64_t j) {
   if constexpr (KIND == 0) return in.y[j];
-  else return zero_start_value(L.wdinv, in.b, j);
+  else if constexpr (KIND == 1) return zero_start_value(L.wdinv, in.b, j);
+  else return prolong_value(in.x, in.agg, in.xc, in.gamma, j);
 }
 
 // out = y + W (b - A y)   (damped Jacobi sweep from the iterate of kind KIND)
@@ -871,6 +915,13 @@ static LevelView<T> view(const Ctx* c, int level) {
   return v;
 }
 
+// Coarse levels below this many rows take the fused launches of the V-cycle (zero start with
+// the first sweep, residual with the restriction, prolongation with the first post-sweep):
+// there each launch costs a few microseconds however little it does.
+constexpr int64_t kFuseRows = int64_t(1) << 20;
+
+static bool fused_level(int l, int64_t n) { return l > 0 && n <= kFuseRows; }
+
 // Blocks of a level-0 row launch: the tile partition's split, else one row per thread.
 template <typename T>
 static int64_t level_grid(const LevelView<T>& v) {
@@ -909,14 +960,16 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     const AmgLevel& L = g.lv[l];
     const bool pre = l > 0 || pre_fine;
     const int nu = l == 0 ? c->amg_nu : c->amg_nu_coarse;
+    const bool fuse = fused_level(l, L.n);
     const T* res = rhs;
     if (pre) {
       T* a1 = w(l, 1);
       T* a2 = w(l, 2);
       const LevelView<T> lv = view<T>(c, l);
-      // the fused zero-start sweep stages W b once per tile entry; on levels without tiles the
-      // row-by-row path would recompute it for every stencil entry, so there W b is stored
-      if (nu == 1 || !lv.tv.tiles) {
+      // the fused zero-start sweep stages W b once per tile entry; on large levels without
+      // tiles the row-by-row path would recompute it for every stencil entry, so there W b is
+      // stored (small levels fuse anyway: the launch costs more than the recomputation)
+      if (nu == 1 || (!lv.tv.tiles && !fuse)) {
         k_jacobi0<T><<<grid_for(L.n), kBlock, 0, st>>>(lv, rhs, a1, on);
         for (int k = 1; k < nu; ++k) {
           k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, SweepIn<T>{a1, nullptr},
@@ -933,8 +986,14 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
           std::swap(a1, a2);
         }
       }
-      k_level_residual<T><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, a1, a2, on);
       cur[l] = a1;
+      if (fuse) {
+        k_restrict_residual<T><<<grid_for(4 * g.lv[l + 1].n), kBlock, 0, st>>>(
+            lv, g.lv[l + 1].n, L.mstart, L.members, rhs, a1, w(l + 1, 0), on);
+        rhs = w(l + 1, 0);
+        continue;
+      }
+      k_level_residual<T><<<level_grid(lv), kBlock, 0, st>>>(lv, rhs, a1, a2, on);
       res = a2;
     }
     k_restrict<T><<<grid_for(g.lv[l + 1].n), kBlock, 0, st>>>(g.lv[l + 1].n, L.mstart, L.members, res,
@@ -953,8 +1012,21 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     T* y = (cur[l] == w(l, 2)) ? w(l, 1) : w(l, 2);
     T* obuf = (y == w(l, 1)) ? w(l, 2) : w(l, 1);
     const LevelView<T> lv = view<T>(c, l);
-    // prolongation, then the sweeps (a fused prolongation sweep was measured no faster: its
-    // staging gathers the coarse correction through the aggregate map)
+    if (fused_level(l, L.n) && cur[l]) {
+      // small level: the first sweep starts from x + gamma P xc computed where it is read
+      k_sweep<T, 2><<<level_grid(lv), kBlock, 0, st>>>(
+          lv, bl, SweepIn<T>{nullptr, nullptr, cur[l], xc, L.agg, gamma}, y, on);
+      T* src = y;
+      T* dst = cur[l];
+      for (int k = 1; k < nu; ++k) {
+        k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, SweepIn<T>{src, nullptr}, dst, on);
+        std::swap(src, dst);
+      }
+      xc = src;
+      continue;
+    }
+    // prolongation, then the sweeps (on the large levels a fused prolongation sweep was
+    // measured no faster: its staging gathers the coarse correction through the aggregate map)
     k_prolong<T><<<grid_for(L.n), kBlock, 0, st>>>(L.n, L.agg, xc, gamma, cur[l], y, on);
     T* other = obuf;
     for (int k = 0; k < nu; ++k) {

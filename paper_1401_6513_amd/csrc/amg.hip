@@ -323,6 +323,31 @@ __device__ __forceinline__ T disk_row_sum(const LevelView<T>& L, int64_t i, cons
   return disk_taps(L, [&](int r, int dx) __attribute__((always_inline)) { return y(b[r] + dx); });
 }
 
+// The 3 x 3 box row (first coarse level) with tap (r, dx) the value dx columns off in stencil
+// row r (1..3, the row's own is 2): with 9 slots the general path sends slot k to accumulator
+// k % 2 whatever the slice width.  Shared by the lattice-map and the LDS tile paths.
+template <typename T, class Tap>
+__device__ __forceinline__ T box_taps(const LevelView<T>& L, Tap&& tap) {
+  const T yi = (sizeof(T) == 4) ? tap(2, 0) : T(0);
+  T a0 = T(0), a1 = T(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const T d = tap(k / 3 + 1, k % 3 - 1) - yi;
+    if (k & 1) a1 = fmadd(L.w[k], d, a1);
+    else a0 = fmadd(L.w[k], d, a0);
+  }
+  if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.crsum), yi, a0 + a1);
+  else return a0 + a1;
+}
+
+// Stencil row of a tile row from the LDS copy: the disk (finest level) or the box (first
+// coarse level).
+template <typename T, class Tap>
+__device__ __forceinline__ T lds_taps(const LevelView<T>& L, Tap&& tap) {
+  if (L.box) return box_taps(L, tap);
+  return disk_taps(L, tap);
+}
+
 // Canonical row of a level: weights of the reference row, columns from the lattice map,
 // slots to the accumulators in the general path's order (same bits).
 template <typename T, class Y>
@@ -333,19 +358,9 @@ __device__ __forceinline__ T canon_row(const LevelView<T>& L, int32_t p, int64_t
     return disk_row_sum(L, i, b, y);
   }
   if (L.box) {
-    // 3 x 3 box: row bases from two lattice-map reads; with 9 slots the general path sends
-    // slot k to accumulator k % 2 whatever the slice width
+    // 3 x 3 box: row bases from two lattice-map reads
     const int32_t b[3] = {L.node_of[p - L.W], static_cast<int32_t>(i), L.node_of[p + L.W]};
-    const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
-    T a0 = T(0), a1 = T(0);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const T d = y(b[k / 3] + (k % 3 - 1)) - yi;
-      if (k & 1) a1 = fmadd(L.w[k], d, a1);
-      else a0 = fmadd(L.w[k], d, a0);
-    }
-    if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.crsum), yi, a0 + a1);
-    else return a0 + a1;
+    return box_taps(L, [&](int r, int dx) __attribute__((always_inline)) { return y(b[r - 1] + dx); });
   }
   const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
   T a0 = T(0), a1 = T(0);
@@ -469,7 +484,7 @@ __global__ void __launch_bounds__(kBlock) k_level_residual(LevelView<T> L, const
           for (int k = 0; k < kTileRowsPerWave; ++k) {
             if (!ok[k]) continue;
             const int ly = wave + k * (kBlock / 64);
-            r[ii[k]] = bi[k] - disk_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
+            r[ii[k]] = bi[k] - lds_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
           }
         },
         [&](int64_t i) __attribute__((always_inline)) { r[i] = b[i] - level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return x[j]; }); });
@@ -596,7 +611,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(LevelView<T> L, const T* b, Sw
           for (int k = 0; k < kTileRowsPerWave; ++k) {
             if (!ok[k]) continue;
             const int ly = wave + k * (kBlock / 64);
-            const T ay = disk_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
+            const T ay = lds_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
             out[ii[k]] = fmadd(wd[k], bi[k] - ay, lds[0][ly + 2][lane + 2]);
           }
         },
@@ -668,6 +683,9 @@ void amg_free(Ctx* c) {
     dfree(L.sbase32);
     dfree(L.cell_node);
     dfree(L.cell_pix);
+    tile_part_free(L.tpart32);
+    tile_part_free(L.tpart64);
+    tile_map_free(L.tmap);
     for (int k = 0; k < 3; ++k) {
       dfree(L.w64[k]);
       dfree(L.w32[k]);
@@ -739,6 +757,17 @@ int amg_setup(Ctx* c) {
         if (cn.disk && level == 0) VIP_TRY(slice_bases(c, L.cpix32, L.n, &L.sbase32));
       }
       VIP_HIP_TRY(c, hipGetLastError());
+      if (level == 1 && cn.box && L.cell_node) {
+        // tiles of the box rows on the cell lattice (the sweeps read the damped diagonal from
+        // memory there, so the unfiltered canonical sets would do as well)
+        VIP_TRY(tile_part_build(c, L.W, L.H, L.cell_node, L.n, L.tmap, L.cpix32, nullptr, L.tpart32));
+        VIP_TRY(tile_part_build(c, L.W, L.H, L.cell_node, L.n, L.tmap, L.cpix64, nullptr, L.tpart64));
+        if (c->debug)
+          std::fprintf(stderr, "[vip] level 1 tiles: %lld (FP32 rows), %lld (FP64 rows); irregular %lld, %lld of %lld\n",
+                       static_cast<long long>(L.tpart32.ntiles), static_cast<long long>(L.tpart64.ntiles),
+                       static_cast<long long>(L.tpart32.nirr), static_cast<long long>(L.tpart64.nirr),
+                       static_cast<long long>(L.n));
+      }
     }
     for (int k = 0; k < 3; ++k) {
       VIP_TRY(dalloc(c, &L.w64[k], L.n + 1));
@@ -907,11 +936,14 @@ static LevelView<T> view(const Ctx* c, int level) {
     for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w[L.vs][k];
   }
   for (int k = 0; k < v.K; ++k) v.off[k] = L.A.canon.off[k];
-  // level 0 with canonical rows on: the system layout's tile partition of the same value set
+  // level 0 with canonical rows on: the system layout's tile partition of the same value set;
+  // level 1: its own partition on the cell lattice
   if (level == 0 && !c->no_canon && v.disk) {
     const int key = sizeof(T) == 4 ? 1 : (L.vs == 0 ? 0 : -1);
     if (key >= 0) v.tv = tile_view(c, c->sys.canon.tpart[key]);
   }
+  if (level == 1 && !c->no_canon && v.box && v.cpix)
+    v.tv = tile_view_of(sizeof(T) == 4 ? L.tpart32 : L.tpart64, L.tmap, L.cell_node, L.W, L.H);
   return v;
 }
 

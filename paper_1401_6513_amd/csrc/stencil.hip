@@ -586,36 +586,26 @@ int compact(Ctx* c, const int64_t* flag, int64_t m, int32_t** out, int64_t* coun
 
 }  // namespace
 
-int tile_part(Ctx* c, int key) {
-  Canon& cn = c->sys.canon;
-  if (key < 0 || key > 3) return set_error(c, VIP_E_INVALID, "tile partition key");
-  TilePart& tp = cn.tpart[key];
+int tile_part_build(Ctx* c, int W, int H, const int32_t* node_of, int64_t n, TileMap& tm, const int32_t* c0,
+                    const int32_t* c1, TilePart& tp) {
   tile_part_free(tp);
-  static const int sets[4][2] = {{0, -1}, {4, -1}, {1, 2}, {5, 6}};
-  const int v0 = sets[key][0], v1 = sets[key][1];
-  if (!cn.disk || cn.ref_row < 0 || !cn.cpix[v0] || cn.count[v0] == 0 || (v1 >= 0 && (!cn.cpix[v1] || cn.count[v1] == 0)))
-    return VIP_OK;
-  const Lattice& L = c->lat;
-  if (!L.ok) return VIP_OK;
+  if (!c0 || !node_of || n == 0 || W <= 0 || H <= 0) return VIP_OK;
   hipStream_t st = c->stream;
-  TileMap& tm = c->tmap;
   if (!tm.rowstart) {
-    tm.ntx = (L.W + kTileX - 1) / kTileX;
-    tm.nty = (L.H + kTileY - 1) / kTileY;
+    tm.ntx = (W + kTileX - 1) / kTileX;
+    tm.nty = (H + kTileY - 1) / kTileY;
     const int64_t m = static_cast<int64_t>(tm.nty * kTileY + 4) * tm.ntx;
     VIP_TRY(dalloc(c, &tm.rowstart, m));
-    k_tile_rowstart<<<grid_for(m), kBlock, 0, st>>>(m, tm.ntx, L.W, L.H, L.node_of, tm.rowstart);
+    k_tile_rowstart<<<grid_for(m), kBlock, 0, st>>>(m, tm.ntx, W, H, node_of, tm.rowstart);
     VIP_HIP_TRY(c, hipGetLastError());
   }
-  const int32_t* c0 = cn.cpix[v0];
-  const int32_t* c1 = v1 >= 0 ? cn.cpix[v1] : nullptr;
   const int64_t nw = static_cast<int64_t>(tm.nty * kTileY) * tm.ntx;
   VIP_TRY(dalloc(c, &tp.bits, nw));
-  k_tile_bits<<<grid_for(nw), kBlock, 0, st>>>(nw, tm.ntx, L.W, L.H, L.node_of, c0, c1, tp.bits);
+  k_tile_bits<<<grid_for(nw), kBlock, 0, st>>>(nw, tm.ntx, W, H, node_of, c0, c1, tp.bits);
   VIP_HIP_TRY(c, hipGetLastError());
   const int64_t nt = static_cast<int64_t>(tm.nty) * tm.ntx;
   int64_t* flag = nullptr;
-  VIP_TRY(dalloc(c, &flag, std::max(nt, c->n)));
+  VIP_TRY(dalloc(c, &flag, std::max(nt, n)));
   int rc = VIP_OK;
   do {
     k_tile_flag<<<grid_for(nt), kBlock, 0, st>>>(nt, tm.ntx, tp.bits, flag);
@@ -624,8 +614,8 @@ int tile_part(Ctx* c, int key) {
     if (tp.ntiles > 0)
       k_tile_rec<<<grid_for(tp.ntiles * kTileRecWords), kBlock, 0, st>>>(tp.ntiles, tp.tiles, tm.ntx, tm.rowstart,
                                                                           tp.bits, tp.rec);
-    k_irr_flag<<<grid_for(c->n), kBlock, 0, st>>>(c->n, c0, c1, flag);
-    if ((rc = compact(c, flag, c->n, &tp.irr, &tp.nirr)) != VIP_OK) break;
+    k_irr_flag<<<grid_for(n), kBlock, 0, st>>>(n, c0, c1, flag);
+    if ((rc = compact(c, flag, n, &tp.irr, &tp.nirr)) != VIP_OK) break;
   } while (false);
   dfree(flag);
   if (rc != VIP_OK) {
@@ -637,6 +627,22 @@ int tile_part(Ctx* c, int key) {
   tp.tile_blocks = static_cast<int>(std::min<int64_t>((tp.ntiles + kNumXcd - 1) / kNumXcd * kNumXcd, 8192));
   tp.irr_blocks = static_cast<int>(
       std::min<int64_t>(((tp.nirr + kBlock - 1) / kBlock + kNumXcd - 1) / kNumXcd * kNumXcd, 1024));
+  return VIP_OK;
+}
+
+int tile_part(Ctx* c, int key) {
+  Canon& cn = c->sys.canon;
+  if (key < 0 || key > 3) return set_error(c, VIP_E_INVALID, "tile partition key");
+  TilePart& tp = cn.tpart[key];
+  tile_part_free(tp);
+  static const int sets[4][2] = {{0, -1}, {4, -1}, {1, 2}, {5, 6}};
+  const int v0 = sets[key][0], v1 = sets[key][1];
+  if (!cn.disk || cn.ref_row < 0 || !cn.cpix[v0] || cn.count[v0] == 0 || (v1 >= 0 && (!cn.cpix[v1] || cn.count[v1] == 0)))
+    return VIP_OK;
+  const Lattice& L = c->lat;
+  if (!L.ok) return VIP_OK;
+  VIP_TRY(tile_part_build(c, L.W, L.H, L.node_of, c->n, c->tmap, cn.cpix[v0], v1 >= 0 ? cn.cpix[v1] : nullptr,
+                          tp));
   if (c->debug)
     std::fprintf(stderr, "[vip] tile partition %d: %lld tiles, %lld irregular rows of %lld\n", key,
                  static_cast<long long>(tp.ntiles), static_cast<long long>(tp.nirr), static_cast<long long>(c->n));

@@ -29,7 +29,8 @@ struct TileView {
   int irr_blocks = 0;               // blocks [0, irr_blocks) take the irregular rows (the same)
 };
 
-inline TileView tile_view(const Ctx* c, const TilePart& tp) {
+// View of a partition of the rows of a lattice image (W x H pixels, node_of, row starts in tm).
+inline TileView tile_view_of(const TilePart& tp, const TileMap& tm, const int32_t* node_of, int W, int H) {
   TileView v;
   if (!tp.tiles && !tp.irr) return v;
   v.tiles = tp.tiles;
@@ -37,13 +38,18 @@ inline TileView tile_view(const Ctx* c, const TilePart& tp) {
   v.irr = tp.irr;
   v.nirr = tp.nirr;
   v.rec = tp.rec;
-  v.node_of = c->lat.node_of;
-  v.ntx = c->tmap.ntx;
-  v.W = c->lat.W;
-  v.H = c->lat.H;
+  v.node_of = node_of;
+  v.ntx = tm.ntx;
+  v.W = W;
+  v.H = H;
   v.tile_blocks = tp.tile_blocks;
   v.irr_blocks = tp.irr_blocks;
   return v;
+}
+
+// View of a partition of the node lattice.
+inline TileView tile_view(const Ctx* c, const TilePart& tp) {
+  return tile_view_of(tp, c->tmap, c->lat.node_of, c->lat.W, c->lat.H);
 }
 
 // A tile's record, staged in LDS from its 256-byte block in the partition (one coalesced load):

@@ -213,6 +213,9 @@ struct AmgLevel {
   int32_t* cell_node = nullptr;   // [W * H]: row at each cell, -1 where none
   int32_t* cell_pix = nullptr;    // [n]: cell of each row
   int32_t H = 0;
+  // level 1: tiles of its canonical rows on the cell lattice (FP32 and FP64 sweeps; owned)
+  TileMap tmap;
+  TilePart tpart32, tpart64;
 };
 
 struct Amg {
@@ -447,6 +450,10 @@ void canon_free(Canon& cn);
 // 2: sets 1 and 2, 3: sets 5 and 6), rebuilt from the current marks; none unless the
 // reference row is the 21-point disk.
 int tile_part(Ctx* c, int key);
+// Tile partition of the rows of a lattice image (W x H pixels, node_of, n rows) canonical in c0
+// (and c1, if given); tm's row starts are built on first use.
+int tile_part_build(Ctx* c, int W, int H, const int32_t* node_of, int64_t n, TileMap& tm, const int32_t* c0,
+                    const int32_t* c1, TilePart& tp);
 void tile_part_free(TilePart& tp);
 void tile_map_free(TileMap& tm);
 // Canonical nodes of the VIP and node operators (VipCanon); leaves count = 0 when there are none.

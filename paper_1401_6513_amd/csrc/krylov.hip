@@ -253,9 +253,9 @@ __device__ __forceinline__ double disk_sum(const Mat<VT>& A, int sys, Tap&& tap)
   }
 }
 
-template <typename VT, typename T>
+template <typename VT, typename X>
 __device__ __forceinline__ double disk_dot(const Mat<VT>& A, int sys, int64_t i, const int32_t (&b)[5],
-                                           const T* x) {
+                                           const X& x) {
   (void)i;
   return disk_sum(A, sys, [&](int r, int dx) __attribute__((always_inline)) { return x[b[r] + dx]; });
 }
@@ -267,9 +267,9 @@ __device__ __forceinline__ double disk_lds(const Mat<VT>& A, int sys, const T (&
   return disk_sum(A, sys, [&](int r, int dx) __attribute__((always_inline)) { return t[ly + r][lx + 2 + dx]; });
 }
 
-template <typename VT, typename T>
+template <typename VT, typename X>
 __device__ __forceinline__ double canon_dot(const Mat<VT>& A, int sys, int32_t p, int64_t i, int w,
-                                            const T* x) {
+                                            const X& x) {
   if (A.disk) {
     int32_t b[5];
     disk_bases(A.node_of, p, A.W, i, b);
@@ -317,12 +317,13 @@ __device__ __forceinline__ double canon_dot(const Mat<VT>& A, int sys, int32_t p
   }
 }
 
-// Row i of y = A x for system `sys`; x is the system's vector.  The slot loop is
+// Row i of y = A x for system `sys`; x is the system's vector (a pointer, or any accessor whose
+// x[j] gives entry j).  The slot loop is
 // unrolled by four so the column loads of several slots are in flight before
 // their gathers.
 // (without the slice descriptors: canonical rows by pixel, else the sliced ELL)
-template <typename VT, typename T>
-__device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_t i, const T* x) {
+template <typename VT, typename X>
+__device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_t i, const X& x) {
   const int64_t sl = i / kSlice;
   const int64_t base = A.ptr[sl] + (i % kSlice);
   const int w = static_cast<int>((A.ptr[sl + 1] - A.ptr[sl]) / kSlice);
@@ -378,8 +379,8 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
   }
 }
 
-template <typename VT, typename T>
-__device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, const T* x) {
+template <typename VT, typename X>
+__device__ __forceinline__ double row_dot(const Mat<VT>& A, int sys, int64_t i, const X& x) {
   if (A.sbase[sys]) {
     int32_t b[5];
     if (slice_disk_bases(A.sbase[sys], i, b)) return disk_dot(A, sys, i, b, x);
@@ -702,6 +703,22 @@ __global__ void k_fin_bicg_v(const double* partials, int64_t nb, int64_t n, int 
   }
 }
 
+// s = r - alpha v, one rounding; the one expression for s wherever it is formed
+template <typename T>
+__device__ __forceinline__ T bicg_s_value(T r, T v, T alpha) {
+  if constexpr (sizeof(T) == 4) return fmaf(-alpha, v, r);
+  else return fma(-alpha, v, r);
+}
+
+// s of one system computed where it is read (x[j] of a row product)
+template <typename T>
+struct SValues {
+  const T* r;
+  const T* v;
+  T alpha;
+  __device__ __forceinline__ T operator[](int64_t j) const { return bicg_s_value(r[j], v[j], alpha); }
+};
+
 // s = r - alpha v; sh = D^-1 s (Jacobi)
 template <typename T, int NS>
 __global__ void k_bicg_s(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int jac) {
@@ -711,14 +728,16 @@ __global__ void k_bicg_s(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int ja
   for (int s = 0; s < NS; ++s) {
     if (!sc->active[s]) continue;
     const int64_t o = s * V.stride + i;
-    const T sv = V.r[o] - static_cast<T>(sc->alpha[s]) * V.v[o];
+    const T sv = bicg_s_value(V.r[o], V.v[o], static_cast<T>(sc->alpha[s]));
     V.s[o] = sv;
     if (jac) V.sh[o] = V.dinv[s][i] * sv;
   }
 }
 
-// t = A sh; partial sums of t . s, t . t (and of sh for the border row)
-template <typename VT, typename T, int NS, bool GEN>
+// t = A sh; partial sums of t . s, t . t (and of sh for the border row).  With FS (no
+// preconditioner, sh = s) the kernel also forms s = r - alpha v itself: it stages s computed from
+// r and v, the row-by-row path computes it where it reads it, and each row writes its own s.
+template <typename VT, typename T, int NS, bool GEN, bool FS = false>
 __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
   __shared__ T lds[NS][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta;
@@ -733,10 +752,14 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
     any = any || use[s];
     shn[s] = A.border ? static_cast<double>(V.sh[s * V.stride + A.n]) : 0.0;
   }
+  SValues<T> sa[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) sa[s] = SValues<T>{V.r + s * V.stride, V.v + s * V.stride, static_cast<T>(sc->alpha[s])};
   auto emit = [&](int s, int64_t i, double y, T sv, T si) __attribute__((always_inline)) {
     if (A.border) y += shn[s];
     const T yt = static_cast<T>(y);
     V.t[s * V.stride + i] = yt;
+    if constexpr (FS) V.s[s * V.stride + i] = sv;
     acc[3 * s] = fma(static_cast<double>(yt), static_cast<double>(sv), acc[3 * s]);
     acc[3 * s + 1] = fma(static_cast<double>(yt), static_cast<double>(yt), acc[3 * s + 1]);
     if (A.border) acc[3 * s + 2] += static_cast<double>(si);
@@ -744,8 +767,14 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
   auto slow = [&](int64_t i) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-      if (use[s])
-        emit(s, i, row_dot_rows(A, s, i, V.sh + s * V.stride), V.s[s * V.stride + i], V.sh[s * V.stride + i]);
+      if (use[s]) {
+        if constexpr (FS) {
+          const T si = sa[s][i];
+          emit(s, i, row_dot_rows(A, s, i, sa[s]), si, si);
+        } else {
+          emit(s, i, row_dot_rows(A, s, i, V.sh + s * V.stride), V.s[s * V.stride + i], V.sh[s * V.stride + i]);
+        }
+      }
   };
   if (A.tv.tiles) {
     const T* xs[NS];
@@ -755,7 +784,12 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
       tile_walk(
           A.tv,
           [&](int64_t tk) __attribute__((always_inline)) {
-            tile_stage<T, NS>(A.tv, tk, xs, lds, meta, !GEN);
+            if constexpr (FS)
+              tile_stage_fn<T, NS>(
+                  A.tv, tk, [&](int s, int32_t node) __attribute__((always_inline)) { return sa[s][node]; }, lds,
+                  meta, !GEN);
+            else
+              tile_stage<T, NS>(A.tv, tk, xs, lds, meta, !GEN);
             int64_t ii[kTileRowsPerWave];
             bool ok[kTileRowsPerWave];
             tile_row_ids(A.tv, meta, ii, ok);
@@ -766,13 +800,15 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
               return;
             }
             T sv[kTileRowsPerWave][NS];
+            if constexpr (!FS) {
 #pragma unroll
-            for (int k = 0; k < kTileRowsPerWave; ++k)
-              if (ok[k])
+              for (int k = 0; k < kTileRowsPerWave; ++k)
+                if (ok[k])
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                  sv[k][s] = V.s[s * V.stride + ii[k]];
-                }
+                  for (int s = 0; s < NS; ++s) {
+                    sv[k][s] = V.s[s * V.stride + ii[k]];
+                  }
+            }
             const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
 #pragma unroll
             for (int k = 0; k < kTileRowsPerWave; ++k) {
@@ -781,8 +817,10 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
               double y[NS];
 #pragma unroll
               for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
+              // (with FS the staged centre is this row's s)
 #pragma unroll
-              for (int s = 0; s < NS; ++s) if (use[s]) emit(s, ii[k], y[s], sv[k][s], lds[s][ly + 2][lane + 2]);
+              for (int s = 0; s < NS; ++s)
+                if (use[s]) emit(s, ii[k], y[s], FS ? lds[s][ly + 2][lane + 2] : sv[k][s], lds[s][ly + 2][lane + 2]);
             }
           },
           slow);
@@ -794,11 +832,18 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
           T sv[NS], si[NS];
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
-            sv[s] = V.s[s * V.stride + i];
-            si[s] = V.sh[s * V.stride + i];
+            if constexpr (FS) {
+              sv[s] = si[s] = sa[s][i];
+            } else {
+              sv[s] = V.s[s * V.stride + i];
+              si[s] = V.sh[s * V.stride + i];
+            }
           }
 #pragma unroll
-          for (int s = 0; s < NS; ++s) y[s] = disk_dot(A, s, i, b, V.sh + s * V.stride);
+          for (int s = 0; s < NS; ++s) {
+            if constexpr (FS) y[s] = disk_dot(A, s, i, b, sa[s]);
+            else y[s] = disk_dot(A, s, i, b, V.sh + s * V.stride);
+          }
 #pragma unroll
           for (int s = 0; s < NS; ++s)
             if (use[s]) emit(s, i, y[s], sv[s], si[s]);
@@ -1294,12 +1339,23 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
           else k_bicg_v<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         }
         k_fin_bicg_v<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
-        k_bicg_s<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, jac);
+        // the unpreconditioned two-system FP32 solve (the predictor) forms s inside the t kernel
+        constexpr bool kFuseS = NS == 2 && sizeof(T) == 4 && sizeof(VT) == 4;
+        const bool fuse_s = kFuseS && !amg && !jac && A.tv.tiles && V.sh == V.s;
+        if (!fuse_s) k_bicg_s<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, jac);
         if constexpr (NS == 1) {
           if (amg) VIP_TRY(amg_apply<T>(c, V.s, V.sh, A.border != 0, c->amg_pre_fine != 0));
         }
-        if (A.tile_general) k_bicg_t<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+        if constexpr (kFuseS) {
+          if (fuse_s) {
+            if (A.tile_general) k_bicg_t<VT, T, NS, true, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+            else k_bicg_t<VT, T, NS, false, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+          }
+        }
+        if (!fuse_s) {
+          if (A.tile_general) k_bicg_t<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
           else k_bicg_t<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+        }
         k_fin_bicg_t<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
         k_bicg_x<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc);
         k_fin_bicg_x<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);

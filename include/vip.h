@@ -99,6 +99,9 @@ typedef struct {
                                 the corrected start vector (used if < 1), else 0 */
   double warm_alpha;         /* alpha of the used correction, else 0 */
   double warm_beta;          /* beta of the used correction (VIP_WS_LEARNED), else 0 */
+  int poisson_fp64_fallback; /* 1: with VIP_P_MIXED an FP32 correction broke down or stopped
+                                gaining (less than 2x on the FP64 residual), and the Poisson solve
+                                finished with FP64 iterations from its FP64 iterate; else 0 */
 } vip_step_stats;
 
 /* Fill *opt with the defaults listed above. */

@@ -1492,10 +1492,11 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   double relres = 0.0;
   const int maxit = c->opt.max_iters;
   bool converged = false;
-  if (!mixed) {
+  // FP64 refinement passes from the current FP64 iterate x
+  auto fp64_passes = [&]() -> int {
     Vec<double> V = make_vec<double>(c->ws, stride, 1, x);
     V.dinv[0] = c->dinv[0];
-    for (outer = 1; outer <= 20; ++outer) {
+    for (int k = 1; k <= 20; ++k, ++outer) {
       VIP_TRY((residual<double, double, double, 1>(c, A64, x, b, V.r, stride)));
       const double bb = c->sc_host->bb[0];
       if (bb == 0.0) {
@@ -1512,18 +1513,29 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
       int it = 0;
       bool bad = false;
       VIP_TRY((iterate<double, double, 1>(c, m, A64, V, tol, maxit - total_it, &it, true, &bb, use_amg,
-                                          &bad, &c->hint_p64[std::min(outer - 1, 3)])));
+                                          &bad, &c->hint_p64[std::min(k - 1, 3)])));
       total_it += it;
       if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite Krylov residual");
     }
+    return VIP_OK;
+  };
+  bool fallback = false;
+  if (!mixed) {
+    outer = 1;
+    VIP_TRY(fp64_passes());
   } else {
-    const double inner = std::max(c->opt.inner_tol, 1e-7);
     Mat<float> A32{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val32, nullptr}, {c->sys.rsum32, nullptr}};
     attach_canon(c, A32, 4, -1);
     float* d32 = c->ws32 + 8 * stride;
     float* r32base = c->ws32;
     Vec<float> V = make_vec<float>(r32base, stride, 1, d32);
     V.dinv[0] = c->dinv32;
+    // an FP32 correction gets at most kInnerCap iterations; one that breaks down, or a pass that
+    // does not halve the FP64 residual, hands the solve to FP64 iterations from the FP64 iterate
+    // (the FP32 multigrid-preconditioned iteration stagnates on large singular bordered systems)
+    constexpr int kInnerCap = 150;
+    const double inner = std::max(c->opt.inner_tol, 1e-7);
+    double prev = 0.0;
     for (outer = 1; outer <= 200; ++outer) {
       // FP64 residual of the current FP64 iterate, cast into the inner right-hand side
       VIP_TRY((residual<double, double, float, 1>(c, A64, x, b, V.r, stride)));
@@ -1539,18 +1551,27 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
         break;
       }
       if (total_it >= maxit) break;
+      if (outer > 1 && relres > 0.5 * prev) {
+        fallback = true;
+        break;
+      }
+      prev = relres;
       const double rr_outer = c->sc_host->rr[0];
       k_fill<float><<<gv, kBlock, 0, s>>>(stride, d32, 0.0f);
       // inner: A32 d = r, from d = 0; its residual starts as r itself
       int it = 0;
       bool bad = false;
       const double target = std::max(inner, 0.5 * tol / relres);
-      VIP_TRY((iterate<float, float, 1>(c, m, A32, V, target, maxit - total_it, &it, true, &rr_outer,
-                                        use_amg, &bad, &c->hint_p32[std::min(outer - 1, 3)])));
+      VIP_TRY((iterate<float, float, 1>(c, m, A32, V, target, std::min(kInnerCap, maxit - total_it), &it, true,
+                                        &rr_outer, use_amg, &bad, &c->hint_p32[std::min(outer - 1, 3)])));
       total_it += it;
-      if (bad) return set_error(c, VIP_E_NONFINITE, "FP32 inner solve produced a non-finite residual");
+      if (bad) {
+        fallback = true;   // x is unchanged: the broken correction is not added
+        break;
+      }
       k_add_f32<<<gv, kBlock, 0, s>>>(nvec, x, d32);
     }
+    if (fallback) VIP_TRY(fp64_passes());
   }
   if (project) {
     // phi with zero mean
@@ -1575,6 +1596,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
     st->poisson_residual = relres;
     st->krylov_used = m == kCG ? VIP_K_PCG : VIP_K_BICGSTAB;
     st->border_lambda = lam;
+    st->poisson_fp64_fallback = fallback ? 1 : 0;
   }
   if (!std::isfinite(relres)) return set_error(c, VIP_E_NONFINITE, "non-finite Poisson residual");
   if (!converged)

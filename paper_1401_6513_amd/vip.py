@@ -46,7 +46,7 @@ class VipStepStats(ctypes.Structure):
                 ("poisson_residual", ctypes.c_double), ("helmholtz_residual", ctypes.c_double),
                 ("border_lambda", ctypes.c_double), ("warm_start", ctypes.c_int),
                 ("warm_ratio", ctypes.c_double), ("warm_alpha", ctypes.c_double),
-                ("warm_beta", ctypes.c_double)]
+                ("warm_beta", ctypes.c_double), ("poisson_fp64_fallback", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -54,6 +54,7 @@ int main(void) {
   F(vip_step_stats, krylov_used) F(vip_step_stats, poisson_residual)
   F(vip_step_stats, helmholtz_residual) F(vip_step_stats, border_lambda)
   F(vip_step_stats, warm_start) F(vip_step_stats, warm_ratio) F(vip_step_stats, warm_alpha) F(vip_step_stats, warm_beta)
+  F(vip_step_stats, poisson_fp64_fallback)
   return 0;
 }
 """

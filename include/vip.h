@@ -114,7 +114,9 @@ void vip_default_options(vip_options* opt);
  * row through the general sliced-ELL path; VIP_CNN_LAYERED=1 runs the learned start
  * vector's network layer by layer instead of in one fused launch; VIP_AMG_GAMMA,
  * VIP_AMG_NU, VIP_AMG_NU_COARSE override the multigrid over-correction and sweep
- * counts (these change results); VIP_DEBUG=1 prints solver progress to stderr. */
+ * counts (these change results); VIP_MAX_GRID sets the block count of the reducing
+ * vector kernels (default 2048, read once per process; it changes the order of the
+ * partial sums and so the last bits); VIP_DEBUG=1 prints solver progress to stderr. */
 int vip_create(void** out, int device, void* stream);
 
 /* Release every device allocation of the context and the context itself. */

@@ -31,13 +31,13 @@ namespace vip {
 namespace {
 
 constexpr int kWaves = kBlock / 64;
-// Blocks of a reducing kernel (each takes a contiguous chunk of rows): VIP_MAX_GRID, default 8192
-// (measured: enough blocks in flight to hide the gathers, few enough partials for one-block
-// finish kernels).
+// Blocks of a reducing kernel (each takes a contiguous chunk of rows): VIP_MAX_GRID, default 2048
+// (measured on the step at h = D/128 against 512, 1024, 4096, 8192 and 16384: enough blocks in
+// flight to hide the loads, few enough partials for one-block finish kernels).
 inline int64_t max_grid() {
   static const int64_t g = [] {
     const char* e = std::getenv("VIP_MAX_GRID");
-    int64_t v = e ? std::atoll(e) : 8192;
+    int64_t v = e ? std::atoll(e) : 2048;
     v = std::min<int64_t>(std::max<int64_t>(v, 64), int64_t{1} << 20);
     return (v + kNumXcd - 1) / kNumXcd * kNumXcd;
   }();

@@ -20,7 +20,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "tile.h"
@@ -1433,6 +1435,13 @@ Vec<T> make_vec(T* base, int64_t stride, int ns, T* x) {
   return V;
 }
 
+// a residual in an error message: 3 significant digits, exponent form
+std::string sci(double v) {
+  char buf[32];
+  std::snprintf(buf, sizeof buf, "%.3e", v);
+  return buf;
+}
+
 Method choose_method(Ctx* c) {
   if (c->opt.krylov == VIP_K_PCG) return kCG;
   if (c->opt.krylov == VIP_K_BICGSTAB) return kBiCGStab;
@@ -1601,7 +1610,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   if (!std::isfinite(relres)) return set_error(c, VIP_E_NONFINITE, "non-finite Poisson residual");
   if (!converged)
     return set_error(c, VIP_E_NOT_CONVERGED, "Poisson solve stopped at relative residual " +
-                                                 std::to_string(relres));
+                                                 sci(relres));
   return VIP_OK;
 }
 
@@ -1711,7 +1720,7 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
   if (!std::isfinite(worst)) return set_error(c, VIP_E_NONFINITE, "non-finite predictor residual");
   if (!converged)
     return set_error(c, VIP_E_NOT_CONVERGED, "predictor solve stopped at relative residual " +
-                                                 std::to_string(worst));
+                                                 sci(worst));
   return VIP_OK;
 }
 

@@ -8,6 +8,8 @@ applications 1e-13, solves at a residual of 1e-12 within 1e-9 of the direct
 solve, full fractional steps within 1e-9 (FP64) and 1e-6 (mixed precision)
 relative in u, v and p (p without its mean where the pressure problem is
 singular)."""
+import re
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -364,4 +366,7 @@ def test_nonconvergence_is_reported(cases):
     with pytest.raises(vip.VipError) as e:
         c.ctx.vip_poisson_solve(_dev(b), phi, 1e-12)
     assert e.value.code == -3
+    # the message carries the residual reached, in exponent form
+    m = re.search(r"relative residual (\d\.\d{3}e[-+]\d+)", str(e.value))
+    assert m and 1e-12 < float(m.group(1)) < 1.0
     c.ctx.vip_set_options(vip.default_options(period=c.spec.period, poisson_tol=1e-12))

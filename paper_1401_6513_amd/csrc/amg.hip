@@ -472,19 +472,14 @@ __global__ void __launch_bounds__(kBlock) k_level_residual(LevelView<T> L, const
         L.tv,
         [&](int64_t tk) __attribute__((always_inline)) {
           tile_stage<T, 1>(L.tv, tk, xs, lds, meta, true);
-          int64_t ii[kTileRowsPerWave];
-          bool ok[kTileRowsPerWave];
-          tile_row_ids(L.tv, meta, ii, ok);
-          T bi[kTileRowsPerWave];
-#pragma unroll
-          for (int k = 0; k < kTileRowsPerWave; ++k)
-            if (ok[k]) bi[k] = b[ii[k]];
           const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
-#pragma unroll
+#pragma unroll 1
           for (int k = 0; k < kTileRowsPerWave; ++k) {
-            if (!ok[k]) continue;
+            const int64_t row = tile_row_id(L.tv, meta, k);
+            if (row < 0) continue;
             const int ly = wave + k * (kBlock / 64);
-            r[ii[k]] = bi[k] - lds_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
+            const T bi = b[row];
+            r[row] = bi - lds_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
           }
         },
         [&](int64_t i) __attribute__((always_inline)) { r[i] = b[i] - level_row(L, i, [&](int32_t j) __attribute__((always_inline)) { return x[j]; }); });
@@ -596,23 +591,15 @@ __global__ void __launch_bounds__(kBlock) k_sweep(LevelView<T> L, const T* b, Sw
           tile_stage_fn<T, 1>(
               L.tv, tk, [&](int, int32_t node) __attribute__((always_inline)) { return yf(node); }, lds, meta,
               true);
-          int64_t ii[kTileRowsPerWave];
-          bool ok[kTileRowsPerWave];
-          tile_row_ids(L.tv, meta, ii, ok);
-          T bi[kTileRowsPerWave], wd[kTileRowsPerWave];
-#pragma unroll
-          for (int k = 0; k < kTileRowsPerWave; ++k)
-            if (ok[k]) {
-              bi[k] = b[ii[k]];
-              wd[k] = L.wdinv[ii[k]];
-            }
           const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
-#pragma unroll
+#pragma unroll 1
           for (int k = 0; k < kTileRowsPerWave; ++k) {
-            if (!ok[k]) continue;
+            const int64_t row = tile_row_id(L.tv, meta, k);
+            if (row < 0) continue;
             const int ly = wave + k * (kBlock / 64);
+            const T bi = b[row], wd = L.wdinv[row];
             const T ay = lds_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
-            out[ii[k]] = fmadd(wd[k], bi[k] - ay, lds[0][ly + 2][lane + 2]);
+            out[row] = fmadd(wd, bi - ay, lds[0][ly + 2][lane + 2]);
           }
         },
         [&](int64_t i) __attribute__((always_inline)) {

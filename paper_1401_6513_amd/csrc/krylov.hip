@@ -477,33 +477,28 @@ __global__ void __launch_bounds__(kBlock) k_residual(Mat<VT> A, const XT* x, con
         A.tv,
         [&](int64_t tk) __attribute__((always_inline)) {
             tile_stage<XT, NS>(A.tv, tk, xs, lds, meta, !GEN);
-            int64_t ii[kTileRowsPerWave];
-            bool ok[kTileRowsPerWave];
-            tile_row_ids(A.tv, meta, ii, ok);
             if constexpr (GEN) {
-#pragma unroll
-              for (int k = 0; k < kTileRowsPerWave; ++k)
-                if (ok[k]) slow(ii[k]);
+#pragma unroll 1
+              for (int k = 0; k < kTileRowsPerWave; ++k) {
+                const int64_t row = tile_row_id(A.tv, meta, k);
+                if (row >= 0) slow(row);
+              }
               return;
             }
-            double bi[kTileRowsPerWave][NS];
-#pragma unroll
-            for (int k = 0; k < kTileRowsPerWave; ++k)
-              if (ok[k])
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                  bi[k][s] = b[s * stride + ii[k]];
-                }
             const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
-#pragma unroll
+#pragma unroll 1
             for (int k = 0; k < kTileRowsPerWave; ++k) {
-              if (!ok[k]) continue;
+              const int64_t row = tile_row_id(A.tv, meta, k);
+              if (row < 0) continue;
               const int ly = wave + k * (kBlock / 64);
+              double bi[NS];
+#pragma unroll
+              for (int s = 0; s < NS; ++s) bi[s] = b[s * stride + row];
               double y[NS];
 #pragma unroll
               for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
 #pragma unroll
-              for (int s = 0; s < NS; ++s) emit(s, ii[k], y[s], bi[k][s], static_cast<double>(lds[s][ly + 2][lane + 2]));
+              for (int s = 0; s < NS; ++s) emit(s, row, y[s], bi[s], static_cast<double>(lds[s][ly + 2][lane + 2]));
             }
           },
         slow);
@@ -630,33 +625,28 @@ __global__ void __launch_bounds__(kBlock) k_bicg_v(Mat<VT> A, Vec<T> V, double* 
           A.tv,
           [&](int64_t tk) __attribute__((always_inline)) {
             tile_stage<T, NS>(A.tv, tk, xs, lds, meta, !GEN);
-            int64_t ii[kTileRowsPerWave];
-            bool ok[kTileRowsPerWave];
-            tile_row_ids(A.tv, meta, ii, ok);
             if constexpr (GEN) {
-#pragma unroll
-              for (int k = 0; k < kTileRowsPerWave; ++k)
-                if (ok[k]) slow(ii[k]);
+#pragma unroll 1
+              for (int k = 0; k < kTileRowsPerWave; ++k) {
+                const int64_t row = tile_row_id(A.tv, meta, k);
+                if (row >= 0) slow(row);
+              }
               return;
             }
-            T rh[kTileRowsPerWave][NS];
-#pragma unroll
-            for (int k = 0; k < kTileRowsPerWave; ++k)
-              if (ok[k])
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                  rh[k][s] = V.rhat[s * V.stride + ii[k]];
-                }
             const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
-#pragma unroll
+#pragma unroll 1
             for (int k = 0; k < kTileRowsPerWave; ++k) {
-              if (!ok[k]) continue;
+              const int64_t row = tile_row_id(A.tv, meta, k);
+              if (row < 0) continue;
               const int ly = wave + k * (kBlock / 64);
+              T rh[NS];
+#pragma unroll
+              for (int s = 0; s < NS; ++s) rh[s] = V.rhat[s * V.stride + row];
               double y[NS];
 #pragma unroll
               for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
 #pragma unroll
-              for (int s = 0; s < NS; ++s) if (use[s]) emit(s, ii[k], y[s], rh[k][s], lds[s][ly + 2][lane + 2]);
+              for (int s = 0; s < NS; ++s) if (use[s]) emit(s, row, y[s], rh[s], lds[s][ly + 2][lane + 2]);
             }
           },
           slow);
@@ -792,37 +782,32 @@ __global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* 
                   meta, !GEN);
             else
               tile_stage<T, NS>(A.tv, tk, xs, lds, meta, !GEN);
-            int64_t ii[kTileRowsPerWave];
-            bool ok[kTileRowsPerWave];
-            tile_row_ids(A.tv, meta, ii, ok);
             if constexpr (GEN) {
-#pragma unroll
-              for (int k = 0; k < kTileRowsPerWave; ++k)
-                if (ok[k]) slow(ii[k]);
+#pragma unroll 1
+              for (int k = 0; k < kTileRowsPerWave; ++k) {
+                const int64_t row = tile_row_id(A.tv, meta, k);
+                if (row >= 0) slow(row);
+              }
               return;
             }
-            T sv[kTileRowsPerWave][NS];
-            if constexpr (!FS) {
-#pragma unroll
-              for (int k = 0; k < kTileRowsPerWave; ++k)
-                if (ok[k])
-#pragma unroll
-                  for (int s = 0; s < NS; ++s) {
-                    sv[k][s] = V.s[s * V.stride + ii[k]];
-                  }
-            }
             const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
-#pragma unroll
+#pragma unroll 1
             for (int k = 0; k < kTileRowsPerWave; ++k) {
-              if (!ok[k]) continue;
+              const int64_t row = tile_row_id(A.tv, meta, k);
+              if (row < 0) continue;
               const int ly = wave + k * (kBlock / 64);
+              T sv[NS];
+              if constexpr (!FS) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) sv[s] = V.s[s * V.stride + row];
+              }
               double y[NS];
 #pragma unroll
               for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
               // (with FS the staged centre is this row's s)
 #pragma unroll
               for (int s = 0; s < NS; ++s)
-                if (use[s]) emit(s, ii[k], y[s], FS ? lds[s][ly + 2][lane + 2] : sv[k][s], lds[s][ly + 2][lane + 2]);
+                if (use[s]) emit(s, row, y[s], FS ? lds[s][ly + 2][lane + 2] : sv[s], lds[s][ly + 2][lane + 2]);
             }
           },
           slow);
@@ -995,25 +980,25 @@ __global__ void __launch_bounds__(kBlock) k_cg_q(Mat<VT> A, Vec<T> V, double* pa
           A.tv,
           [&](int64_t tk) __attribute__((always_inline)) {
             tile_stage<T, NS>(A.tv, tk, xs, lds, meta, !GEN);
-            int64_t ii[kTileRowsPerWave];
-            bool ok[kTileRowsPerWave];
-            tile_row_ids(A.tv, meta, ii, ok);
             if constexpr (GEN) {
-#pragma unroll
-              for (int k = 0; k < kTileRowsPerWave; ++k)
-                if (ok[k]) slow(ii[k]);
+#pragma unroll 1
+              for (int k = 0; k < kTileRowsPerWave; ++k) {
+                const int64_t row = tile_row_id(A.tv, meta, k);
+                if (row >= 0) slow(row);
+              }
               return;
             }
             const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
-#pragma unroll
+#pragma unroll 1
             for (int k = 0; k < kTileRowsPerWave; ++k) {
-              if (!ok[k]) continue;
+              const int64_t row = tile_row_id(A.tv, meta, k);
+              if (row < 0) continue;
               const int ly = wave + k * (kBlock / 64);
               double y[NS];
 #pragma unroll
               for (int s = 0; s < NS; ++s) y[s] = disk_lds(A, s, lds[s], ly, lane);
 #pragma unroll
-              for (int s = 0; s < NS; ++s) if (use[s]) emit(s, ii[k], y[s], lds[s][ly + 2][lane + 2]);
+              for (int s = 0; s < NS; ++s) if (use[s]) emit(s, row, y[s], lds[s][ly + 2][lane + 2]);
             }
           },
           slow);

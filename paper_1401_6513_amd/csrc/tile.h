@@ -126,21 +126,17 @@ __device__ __forceinline__ void tile_stage_fn(const TileView& V, int64_t k, F&& 
 
 constexpr int kTileRowsPerWave = kTileY / (kBlock / 64);
 
-// The wave's local rows ly = wave + 4 k of the staged tile: node i[k] where ok[k] (a tile row).
-__device__ __forceinline__ void tile_row_ids(const TileView& V, const TileMeta& m,
-                                             int64_t (&i)[kTileRowsPerWave], bool (&ok)[kTileRowsPerWave]) {
+// The wave's local row ly = wave + 4 k of the staged tile: the lane's node, or -1 where its
+// pixel is not a tile row.  The kernels walk k in a loop kept rolled, so that one row's stencil
+// operands are live at a time: unrolled over the four rows, the register peak cut occupancy by
+// one wave per SIMD, which cost the pressure SpMV about a tenth of its time (measured).
+__device__ __forceinline__ int64_t tile_row_id(const TileView& V, const TileMeta& m, int k) {
   const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
-  const int tx = m.tx(), ty = m.ty();
-#pragma unroll
-  for (int k = 0; k < kTileRowsPerWave; ++k) {
-    const int ly = wave + k * (kBlock / 64);
-    ok[k] = (m.bits(ly) >> lane) & 1ull;
-    const int32_t rs = m.rs(ly + 2);
-    i[k] = 0;
-    if (ok[k])
-      i[k] = rs >= 0 ? static_cast<int64_t>(rs) + 2 + lane
-                     : static_cast<int64_t>(V.node_of[static_cast<int64_t>(ty * kTileY + ly) * V.W + tx * kTileX + lane]);
-  }
+  const int ly = wave + k * (kBlock / 64);
+  if (!((m.bits(ly) >> lane) & 1ull)) return -1;
+  const int32_t rs = m.rs(ly + 2);
+  return rs >= 0 ? static_cast<int64_t>(rs) + 2 + lane
+                 : static_cast<int64_t>(V.node_of[static_cast<int64_t>(m.ty() * kTileY + ly) * V.W + m.tx() * kTileX + lane]);
 }
 
 // Blocks [0, irr_blocks) call irr(i) for the irregular rows, one per thread (they start first

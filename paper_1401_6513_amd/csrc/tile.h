@@ -90,37 +90,38 @@ __device__ __forceinline__ void tile_stage_fn(const TileView& V, int64_t k, F&& 
   if (tid < kTileRecWords) m.w[tid] = V.rec[k * kTileRecWords + tid];
   __syncthreads();
   if (!load_x) return;
+  // wave w stages halo rows w, w + 4, ... at columns 0..63 (lane = column, one contiguous
+  // segment per load); the first 4 kTileLdsH threads stage columns 64..67 of every row.  Few
+  // index values live across the tile loop this way (with a flat element index the per-thread
+  // row, column and LDS address of every element were kept in registers).
+  constexpr int kWaves = kBlock / 64, kRowsPerWave = kTileLdsH / kWaves, kEdge = kTileLdsW - 64;
+  static_assert(kTileLdsH % kWaves == 0 && kEdge > 0 && kEdge * kTileLdsH <= kBlock, "tile staging shape");
+  const int wave = tid >> 6, lane = tid & 63;
   const int tx = m.tx(), ty = m.ty();
-  constexpr int kElems = kTileLdsH * kTileLdsW;
-  constexpr int kPer = (kElems + kBlock - 1) / kBlock;
-  int32_t node[kPer];
+  auto node_at = [&](int r, int cc) __attribute__((always_inline)) -> int32_t {
+    const int32_t rs = m.rs(r);
+    if (rs >= 0) return rs + cc;
+    const int gx = tx * kTileX + cc - 2, gy = ty * kTileY + r - 2;
+    if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) return V.node_of[static_cast<int64_t>(gy) * V.W + gx];
+    return -1;
+  };
+  int32_t node[kRowsPerWave + 1];
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int q = tid + k * kBlock;
-    node[k] = -1;
-    if (q < kElems) {
-      const int r = q / kTileLdsW, cc = q % kTileLdsW;
-      const int32_t rs = m.rs(r);
-      if (rs >= 0) {
-        node[k] = rs + cc;
-      } else {
-        const int gx = tx * kTileX + cc - 2, gy = ty * kTileY + r - 2;
-        if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) node[k] = V.node_of[static_cast<int64_t>(gy) * V.W + gx];
-      }
-    }
-  }
-  T val[NS][kPer];
+  for (int j = 0; j < kRowsPerWave; ++j) node[j] = node_at(wave + j * kWaves, lane);
+  const bool edge = tid < kEdge * kTileLdsH;
+  node[kRowsPerWave] = edge ? node_at(tid / kEdge, 64 + tid % kEdge) : -1;
+  T val[NS][kRowsPerWave + 1];
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
+  for (int j = 0; j <= kRowsPerWave; ++j)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) val[s][k] = node[k] >= 0 ? xf(s, node[k]) : T(0);
+    for (int s = 0; s < NS; ++s) val[s][j] = node[j] >= 0 ? xf(s, node[j]) : T(0);
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int q = tid + k * kBlock;
-    if (q < kElems)
+  for (int j = 0; j < kRowsPerWave; ++j)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) t[s][q / kTileLdsW][q % kTileLdsW] = val[s][k];
-  }
+    for (int s = 0; s < NS; ++s) t[s][wave + j * kWaves][lane] = val[s][j];
+  if (edge)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) t[s][tid / kEdge][64 + tid % kEdge] = val[s][kRowsPerWave];
   __syncthreads();
 }
 

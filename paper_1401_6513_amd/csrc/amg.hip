@@ -460,9 +460,13 @@ __global__ void k_jacobi0(LevelView<T> L, const T* b, T* x, const int* on) {
   if (i < L.n) x[i] = zero_start_value(L.wdinv, b, i);
 }
 
+// The FP32 tile kernels of a level (residual, sweeps of kind 0 and 1) are asked for 8 waves
+// per SIMD: under the bound they fit in 57-59 vector registers, and the scalar registers are
+// kept to that count (the excess scalars live in vector-register lanes, no scratch).  The
+// FP64 and kind-2 instances would spill to scratch under it.
 // r = b - A x
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_level_residual(LevelView<T> L, const T* b, const T* x, T* r, const int* on) {
+__global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 ? 8 : 1)) k_level_residual(LevelView<T> L, const T* b, const T* x, T* r, const int* on) {
   __shared__ T lds[1][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta;
   if (!*on) return;
@@ -576,7 +580,7 @@ __device__ __forceinline__ T sweep_in(const LevelView<T>& L, const SweepIn<T>& i
 
 // out = y + W (b - A y)   (damped Jacobi sweep from the iterate of kind KIND)
 template <typename T, int KIND>
-__global__ void __launch_bounds__(kBlock) k_sweep(LevelView<T> L, const T* b, SweepIn<T> in, T* out,
+__global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 && KIND != 2 ? 8 : 1)) k_sweep(LevelView<T> L, const T* b, SweepIn<T> in, T* out,
                                                   const int* on) {
   __shared__ T lds[1][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta;

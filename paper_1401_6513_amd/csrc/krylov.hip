@@ -587,9 +587,15 @@ __global__ void k_bicg_p(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int ja
   }
 }
 
+// Waves per SIMD asked of the single-system FP32 SpMV kernels: their 63-64 VGPRs allow 8, and
+// the bound lets the compiler keep the scalar registers to that count (the excess scalars live
+// in vector-register lanes, no scratch).  Other instances would spill to scratch under it.
+template <typename T, int NS>
+constexpr int kWavesFor = (sizeof(T) == 4 && NS == 1) ? 8 : 1;
+
 // v = A ph; partial sums of rhat . v (and of ph for the border row)
 template <typename VT, typename T, int NS, bool GEN>
-__global__ void __launch_bounds__(kBlock) k_bicg_v(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+__global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_v(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
   __shared__ T lds[NS][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta;
   double acc[2 * NS];
@@ -730,7 +736,7 @@ __global__ void k_bicg_s(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int ja
 // preconditioner, sh = s) the kernel also forms s = r - alpha v itself: it stages s computed from
 // r and v, the row-by-row path computes it where it reads it, and each row writes its own s.
 template <typename VT, typename T, int NS, bool GEN, bool FS = false>
-__global__ void __launch_bounds__(kBlock) k_bicg_t(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+__global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_t(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
   __shared__ T lds[NS][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta;
   double acc[3 * NS];

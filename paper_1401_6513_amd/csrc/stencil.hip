@@ -622,10 +622,12 @@ int tile_part_build(Ctx* c, int W, int H, const int32_t* node_of, int64_t n, Til
     tile_part_free(tp);
     return rc;
   }
-  // launch split (both multiples of the XCD count): one tile per block up to 4096 tile blocks
-  // (16 per CU; measured on the 9596 tiles at h = D/128: 2.3 tiles per block beat one tile per
-  // block by 0.5 ms a step and 2048 or 3072 blocks), one irregular row per thread up to 1024 blocks
-  tp.tile_blocks = static_cast<int>(std::min<int64_t>((tp.ntiles + kNumXcd - 1) / kNumXcd * kNumXcd, 4096));
+  // launch split (both multiples of the XCD count): one tile per block up to 6144 tile blocks
+  // (24 per CU), one irregular row per thread up to 1024 blocks.  Measured on the 9821 tiles at
+  // h = D/128 with the tile kernels at 8 waves per SIMD: the pressure SpMV took 43.5 us at 5120
+  // or 6144 blocks against 46.0 at 4096, 44.5 at 7168, 46.0 at 8192 and 46.8 at one tile per
+  // block (at 5 waves per SIMD, 4096 had been best)
+  tp.tile_blocks = static_cast<int>(std::min<int64_t>((tp.ntiles + kNumXcd - 1) / kNumXcd * kNumXcd, 6144));
   tp.irr_blocks = static_cast<int>(
       std::min<int64_t>(((tp.nirr + kBlock - 1) / kBlock + kNumXcd - 1) / kNumXcd * kNumXcd, 1024));
   return VIP_OK;

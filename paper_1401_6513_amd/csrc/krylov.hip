@@ -589,9 +589,10 @@ __global__ void k_bicg_p(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int ja
 
 // Waves per SIMD asked of the single-system FP32 SpMV kernels: their 63-64 VGPRs allow 8, and
 // the bound lets the compiler keep the scalar registers to that count (the excess scalars live
-// in vector-register lanes, no scratch).  Other instances would spill to scratch under it.
-template <typename T, int NS>
-constexpr int kWavesFor = (sizeof(T) == 4 && NS == 1) ? 8 : 1;
+// in vector-register lanes, no scratch); the t kernel that also forms s fits 6 (79 VGPRs).
+// Other instances would spill to scratch under such a bound.
+template <typename T, int NS, bool FS = false>
+constexpr int kWavesFor = (sizeof(T) == 4 && NS == 1) ? (FS ? 6 : 8) : 1;
 
 // v = A ph; partial sums of rhat . v (and of ph for the border row)
 template <typename VT, typename T, int NS, bool GEN>
@@ -736,7 +737,8 @@ __global__ void k_bicg_s(Vec<T> V, int64_t nvec, const KrylovScalars* sc, int ja
 // preconditioner, sh = s) the kernel also forms s = r - alpha v itself: it stages s computed from
 // r and v, the row-by-row path computes it where it reads it, and each row writes its own s.
 template <typename VT, typename T, int NS, bool GEN, bool FS = false>
-__global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_t(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+__global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS, FS>)) k_bicg_t(Mat<VT> A, Vec<T> V, double* partials,
+                                                                       const KrylovScalars* sc, int sys0) {
   __shared__ T lds[NS][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta;
   double acc[3 * NS];
@@ -746,13 +748,13 @@ __global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_t(Mat<VT> A
   double shn[NS];   // border unknowns (uniform)
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    use[s] = sc->active[s] != 0;
+    use[s] = sc->active[sys0 + s] != 0;
     any = any || use[s];
     shn[s] = A.border ? static_cast<double>(V.sh[s * V.stride + A.n]) : 0.0;
   }
   SValues<T> sa[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) sa[s] = SValues<T>{V.r + s * V.stride, V.v + s * V.stride, static_cast<T>(sc->alpha[s])};
+  for (int s = 0; s < NS; ++s) sa[s] = SValues<T>{V.r + s * V.stride, V.v + s * V.stride, static_cast<T>(sc->alpha[sys0 + s])};
   auto emit = [&](int s, int64_t i, double y, T sv, T si) __attribute__((always_inline)) {
     if (A.border) y += shn[s];
     const T yt = static_cast<T>(y);
@@ -849,13 +851,14 @@ __global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_t(Mat<VT> A
 // omega = (t . s) / (t . t), with the border row t[n] = sum(sh)
 template <typename T, int NS>
 __global__ void k_fin_bicg_t(const double* partials, int64_t nb, int64_t n, int border, Vec<T> V,
-                             KrylovScalars* sc) {
+                             KrylovScalars* sc, int sys0) {
   double tot[3 * NS];
   grid_sum<3 * NS>(partials, nb, tot);
   if (threadIdx.x != 0) return;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    if (!sc->active[s]) continue;
+    const int q = sys0 + s;
+    if (!sc->active[q]) continue;
     double ts = tot[3 * s], tt = tot[3 * s + 1];
     if (border) {
       const T yn = static_cast<T>(tot[3 * s + 2]);
@@ -863,10 +866,10 @@ __global__ void k_fin_bicg_t(const double* partials, int64_t nb, int64_t n, int 
       ts += static_cast<double>(yn) * static_cast<double>(V.s[s * V.stride + n]);
       tt += static_cast<double>(yn) * static_cast<double>(yn);
     }
-    sc->dot_b[s] = ts;
-    sc->dot_c[s] = tt;
+    sc->dot_b[q] = ts;
+    sc->dot_c[q] = tt;
     // tt == 0 means s == 0: the half step already solved the system
-    sc->omega[s] = tt > 0.0 ? ts / tt : 0.0;
+    sc->omega[q] = tt > 0.0 ? ts / tt : 0.0;
   }
 }
 
@@ -1278,6 +1281,38 @@ int set_active(Ctx* c, const int* act, const double* stop2) {
 // returns at once but still costs a launch, so with a `hint` (the iterations the previous
 // solve of the same kind took) the first check comes one iteration before that count and
 // later ones every two iterations; *hint is updated on return.
+// System q of a two-system matrix and of its vectors, as a one-system view (the kernels then
+// read system 0's fields); the scalars stay shared and are indexed from q by the kernel.
+template <typename VT>
+Mat<VT> mat_sys(const Mat<VT>& A, int q) {
+  Mat<VT> B = A;
+  B.val[0] = A.val[q];
+  B.rsum[0] = A.rsum[q];
+  B.cpix[0] = A.cpix[q];
+  B.sbase[0] = A.sbase[q];
+  for (int k = 0; k < kMaxTaps; ++k) B.w[0][k] = A.w[q][k];
+  B.crsum[0] = A.crsum[q];
+  return B;
+}
+
+template <typename T>
+Vec<T> vec_sys(const Vec<T>& V, int q) {
+  const int64_t o = q * V.stride;
+  auto at = [o](T* p) { return p ? p + o : p; };
+  Vec<T> W = V;
+  W.x = at(V.x);
+  W.r = at(V.r);
+  W.rhat = at(V.rhat);
+  W.p = at(V.p);
+  W.ph = at(V.ph);
+  W.v = at(V.v);
+  W.s = at(V.s);
+  W.sh = at(V.sh);
+  W.t = at(V.t);
+  W.dinv[0] = V.dinv[q];
+  return W;
+}
+
 template <typename VT, typename T, int NS>
 int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit, int* iters,
             bool time_spmv, const double* bnorm2, bool amg = false, bool* bad = nullptr,
@@ -1341,15 +1376,26 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
         }
         if constexpr (kFuseS) {
           if (fuse_s) {
-            if (A.tile_general) k_bicg_t<VT, T, NS, true, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
-            else k_bicg_t<VT, T, NS, false, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+            // one launch per system: the one-system kernel runs 6 waves per SIMD, the two-system
+            // one 4 (126 VGPRs); each system's sums land in a partial block of their own and
+            // are reduced in the same order as in the two-system launch
+            for (int q = 0; q < NS; ++q) {
+              const Mat<VT> Aq = mat_sys(A, q);
+              const Vec<T> Vq = vec_sys(V, q);
+              double* pq = part + q * 3 * r_rows;
+              if (A.tile_general) k_bicg_t<VT, T, 1, true, true><<<r_rows, kBlock, 0, st>>>(Aq, Vq, pq, sc, q);
+              else k_bicg_t<VT, T, 1, false, true><<<r_rows, kBlock, 0, st>>>(Aq, Vq, pq, sc, q);
+            }
+            for (int q = 0; q < NS; ++q)
+              k_fin_bicg_t<T, 1><<<1, kBlock, 0, st>>>(part + q * 3 * r_rows, r_rows, A.n, A.border,
+                                                       vec_sys(V, q), sc, q);
           }
         }
         if (!fuse_s) {
-          if (A.tile_general) k_bicg_t<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
-          else k_bicg_t<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+          if (A.tile_general) k_bicg_t<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc, 0);
+          else k_bicg_t<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc, 0);
+          k_fin_bicg_t<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc, 0);
         }
-        k_fin_bicg_t<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
         k_bicg_x<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc);
         k_fin_bicg_x<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);
       } else {

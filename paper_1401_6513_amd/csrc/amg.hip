@@ -291,6 +291,7 @@ struct LevelView {
   T wdinv_c;
   float crsum;
   TileView tv;            // level 0: tile partition of the canonical rows (tile.h), if any
+  int wd_uniform;         // 1: every tile row's damped inverse diagonal is wdinv_c
 };
 
 // a * b + c with one rounding, written out so that every path that must give the same bits
@@ -394,7 +395,7 @@ __device__ __forceinline__ T level_wdinv(const LevelView<T>& L, int64_t i) {
 
 // cpix_out[i] = cpix_in[i] where the damped inverse diagonal also equals the reference bits
 template <typename T>
-__global__ void k_canon_wd(int64_t n, const int32_t* cin, const T* wd, T ref, int32_t* cout) {
+__global__ void k_canon_wd(int64_t n, const int32_t* cin, const T* wd, T ref, int32_t* cout, int* dropped) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
   int32_t p = cin[i];
@@ -402,7 +403,10 @@ __global__ void k_canon_wd(int64_t n, const int32_t* cin, const T* wd, T ref, in
     bool same;
     if constexpr (sizeof(T) == 4) same = __float_as_uint(wd[i]) == __float_as_uint(ref);
     else same = __double_as_longlong(wd[i]) == __double_as_longlong(ref);
-    if (!same) p = -1;
+    if (!same) {
+      p = -1;
+      *dropped = 1;   // every writer stores the same value
+    }
   }
   cout[i] = p;
 }
@@ -587,8 +591,10 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 && KIND != 2 ? 8 : 1))
   if (!*on) return;
   auto yf = [&](int64_t j) __attribute__((always_inline)) { return sweep_in<T, KIND>(L, in, j); };
   if (L.tv.tiles) {
-    // tile rows: the damped inverse diagonal from memory (equal to the reference one where
-    // that applies, so the same bits)
+    // tile rows: the damped inverse diagonal is the reference one when every canonical row's
+    // equals it (checked at setup), else read from memory; the same bits either way.  The
+    // zero-start sweep (kind 1) always reads it: the choice cost it registers and time
+    // (41.1 -> 43.5 us on the finest level), where the kind-0 sweep gained (31.8 -> 29.9 us)
     tile_walk(
         L.tv,
         [&](int64_t tk) __attribute__((always_inline)) {
@@ -601,7 +607,7 @@ __global__ void __launch_bounds__(kBlock, (sizeof(T) == 4 && KIND != 2 ? 8 : 1))
             const int64_t row = tile_row_id(L.tv, meta, k);
             if (row < 0) continue;
             const int ly = wave + k * (kBlock / 64);
-            const T bi = b[row], wd = L.wdinv[row];
+            const T bi = b[row], wd = (KIND != 1 && L.wd_uniform) ? L.wdinv_c : L.wdinv[row];
             const T ay = lds_taps(L, [&](int rr, int dx) __attribute__((always_inline)) { return lds[0][ly + rr][lane + 2 + dx]; });
             out[row] = fmadd(wd, bi - ay, lds[0][ly + 2][lane + 2]);
           }
@@ -737,17 +743,29 @@ int amg_setup(Ctx* c) {
       VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv_c, L.wdinv + r64, sizeof(double), hipMemcpyDeviceToHost, st));
       VIP_HIP_TRY(c, hipMemcpyAsync(&L.wdinv32_c, L.wdinv32 + r32, sizeof(float), hipMemcpyDeviceToHost, st));
       VIP_HIP_TRY(c, hipStreamSynchronize(st));
+      int* dropped = nullptr;
+      VIP_TRY(dalloc(c, &dropped, 2));
+      VIP_HIP_TRY(c, hipMemsetAsync(dropped, 0, 2 * sizeof(int), st));
       if (cn.count[0] > 0 && cn.cpix[0]) {
         VIP_TRY(dalloc(c, &L.cpix64, L.n));
-        k_canon_wd<double><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[0], L.wdinv, L.wdinv_c, L.cpix64);
+        k_canon_wd<double><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[0], L.wdinv, L.wdinv_c, L.cpix64,
+                                                              dropped);
         if (cn.disk && level == 0) VIP_TRY(slice_bases(c, L.cpix64, L.n, &L.sbase64));
       }
       if (cn.count[4] > 0 && cn.cpix[4]) {
         VIP_TRY(dalloc(c, &L.cpix32, L.n));
-        k_canon_wd<float><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[4], L.wdinv32, L.wdinv32_c, L.cpix32);
+        k_canon_wd<float><<<grid_for(L.n), kBlock, 0, st>>>(L.n, cn.cpix[4], L.wdinv32, L.wdinv32_c, L.cpix32,
+                                                             dropped + 1);
         if (cn.disk && level == 0) VIP_TRY(slice_bases(c, L.cpix32, L.n, &L.sbase32));
       }
       VIP_HIP_TRY(c, hipGetLastError());
+      int hd[2] = {1, 1};
+      const hipError_t e1 = hipMemcpyAsync(hd, dropped, sizeof(hd), hipMemcpyDeviceToHost, st);
+      const hipError_t e2 = hipStreamSynchronize(st);
+      dfree(dropped);
+      if (e1 != hipSuccess || e2 != hipSuccess) return set_error(c, VIP_E_HIP, "checking the damped diagonals");
+      L.wd_uniform64 = cn.count[0] > 0 && cn.cpix[0] && hd[0] == 0;
+      L.wd_uniform32 = cn.count[4] > 0 && cn.cpix[4] && hd[1] == 0;
       if (level == 1 && cn.box && L.cell_node) {
         // tiles of the box rows on the cell lattice (the sweeps read the damped diagonal from
         // memory there, so the unfiltered canonical sets would do as well)
@@ -917,6 +935,7 @@ static LevelView<T> view(const Ctx* c, int level) {
     v.cpix = L.cpix32;
     v.sbase = L.A.canon.disk ? L.sbase32 : nullptr;
     v.wdinv_c = L.wdinv32_c;
+    v.wd_uniform = L.wd_uniform32 ? 1 : 0;
     for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w32[0][k];
   } else {
     v.val = L.A.val[L.vs];
@@ -924,6 +943,7 @@ static LevelView<T> view(const Ctx* c, int level) {
     v.cpix = L.cpix64;
     v.sbase = L.A.canon.disk ? L.sbase64 : nullptr;
     v.wdinv_c = L.wdinv_c;
+    v.wd_uniform = L.wd_uniform64 ? 1 : 0;
     for (int k = 0; k < v.K; ++k) v.w[k] = L.A.canon.w[L.vs][k];
   }
   for (int k = 0; k < v.K; ++k) v.off[k] = L.A.canon.off[k];

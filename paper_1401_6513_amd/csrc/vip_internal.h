@@ -209,6 +209,10 @@ struct AmgLevel {
   int32_t W = 0;                  // lattice image width
   double wdinv_c = 0.0;
   float wdinv32_c = 0.0f;
+  // every canonical row's damped inverse diagonal equals wdinv_c / wdinv32_c (none was filtered
+  // out of cpix64 / cpix32), so tile sweeps may take the reference value
+  bool wd_uniform64 = false;
+  bool wd_uniform32 = false;
   // level 1: lattice image of its rows, the aggregation cells of level 0 (owned)
   int32_t* cell_node = nullptr;   // [W * H]: row at each cell, -1 where none
   int32_t* cell_pix = nullptr;    // [n]: cell of each row

@@ -953,8 +953,10 @@ static LevelView<T> view(const Ctx* c, int level) {
     const int key = sizeof(T) == 4 ? 1 : (L.vs == 0 ? 0 : -1);
     if (key >= 0) v.tv = tile_view(c, c->sys.canon.tpart[key]);
   }
-  if (level == 1 && !c->no_canon && v.box && v.cpix)
+  if (level == 1 && !c->no_canon && v.box && v.cpix) {
     v.tv = tile_view_of(sizeof(T) == 4 ? L.tpart32 : L.tpart64, L.tmap, L.cell_node, L.W, L.H);
+    v.wd_uniform = 1;   // these tiles hold only rows kept by the damped-diagonal filter
+  }
   return v;
 }
 

@@ -247,6 +247,18 @@ int vip_learn_get_params(void* ctx, double* theta, int64_t n);
 int vip_learn_eval(void* ctx, const double* x, const double* target, const double* mask, int batch,
                    int height, int width, double* y, double* loss, double* grad, double lr);
 
+/*
+ * Run the network on host images with the single fused launch that vip_step uses for the
+ * learned start vector (all four layers on one 16 x 16 output tile per block, activations in
+ * LDS), rather than the layer-by-layer training pass of vip_learn_eval.  Same arithmetic as
+ * vip_learn_eval's forward pass (the same bits), without loss or gradient.
+ *  x  host [batch][height][width][3] input channels (rounded to BF16).
+ *  y  host [batch][height][width] output.
+ * Errors: VIP_E_NOT_BUILT (no parameters), VIP_E_INVALID (sizes <= 0, batch > 65535, more
+ * than 2^28 pixels, NULL x or y).
+ */
+int vip_learn_infer(void* ctx, const double* x, int batch, int height, int width, double* y);
+
 /* Training data: while fewer than max_snapshots are held, each vip_step that
  * knows the last change of the increment stores one snapshot (input image and
  * target).  0 stops capturing.  The node set must be

@@ -682,6 +682,7 @@ void amg_free(Ctx* c) {
     dfree(L.cell_pix);
     tile_part_free(L.tpart32);
     tile_part_free(L.tpart64);
+    L.tiles_filtered = false;
     tile_map_free(L.tmap);
     for (int k = 0; k < 3; ++k) {
       dfree(L.w64[k]);
@@ -767,10 +768,11 @@ int amg_setup(Ctx* c) {
       L.wd_uniform64 = cn.count[0] > 0 && cn.cpix[0] && hd[0] == 0;
       L.wd_uniform32 = cn.count[4] > 0 && cn.cpix[4] && hd[1] == 0;
       if (level == 1 && cn.box && L.cell_node) {
-        // tiles of the box rows on the cell lattice (the sweeps read the damped diagonal from
-        // memory there, so the unfiltered canonical sets would do as well)
+        // tiles of the box rows on the cell lattice, from the filtered canonical sets: the tile
+        // sweeps then take the reference damped diagonal for every tile row
         VIP_TRY(tile_part_build(c, L.W, L.H, L.cell_node, L.n, L.tmap, L.cpix32, nullptr, L.tpart32));
         VIP_TRY(tile_part_build(c, L.W, L.H, L.cell_node, L.n, L.tmap, L.cpix64, nullptr, L.tpart64));
+        L.tiles_filtered = true;
         if (c->debug)
           std::fprintf(stderr, "[vip] level 1 tiles: %lld (FP32 rows), %lld (FP64 rows); irregular %lld, %lld of %lld\n",
                        static_cast<long long>(L.tpart32.ntiles), static_cast<long long>(L.tpart64.ntiles),
@@ -955,7 +957,8 @@ static LevelView<T> view(const Ctx* c, int level) {
   }
   if (level == 1 && !c->no_canon && v.box && v.cpix) {
     v.tv = tile_view_of(sizeof(T) == 4 ? L.tpart32 : L.tpart64, L.tmap, L.cell_node, L.W, L.H);
-    v.wd_uniform = 1;   // these tiles hold only rows kept by the damped-diagonal filter
+    // tiles built from the filtered sets hold only rows whose damped diagonal is the reference
+    v.wd_uniform = L.tiles_filtered ? 1 : v.wd_uniform;
   }
   return v;
 }

@@ -492,6 +492,13 @@ int vip_learn_eval(void* p, const double* x, const double* target, const double*
   return vip::learn_eval(c, x, target, mask, batch, height, width, y, loss, grad, lr);
 }
 
+int vip_learn_infer(void* p, const double* x, int batch, int height, int width, double* y) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  VIP_TRY(vip::bind_device(c));
+  return vip::learn_infer(c, x, batch, height, width, y);
+}
+
 int vip_learn_capture(void* p, int max_snapshots) {
   Ctx* c = vip::as_ctx(p);
   if (!c) return VIP_E_INVALID;

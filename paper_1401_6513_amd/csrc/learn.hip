@@ -1274,6 +1274,28 @@ int learn_eval(Ctx* c, const double* x, const double* t, const double* m, int B,
   return VIP_OK;
 }
 
+// the fused inference launch that vip_step runs, on host images (checks and tools)
+int learn_infer(Ctx* c, const double* x, int B, int H, int W, double* y) {
+  if (!learn_ready(c)) return set_error(c, VIP_E_NOT_BUILT, "network parameters not set");
+  if (B <= 0 || H <= 0 || W <= 0 || B > 65535 || static_cast<int64_t>(B) * H * W > (int64_t{1} << 28))
+    return set_error(c, VIP_E_INVALID, "image sizes must be positive, batch at most 65535, at most 2^28 pixels");
+  if (!x || !y) return set_error(c, VIP_E_INVALID, "input or output image is NULL");
+  Net* N = net_of(c);
+  const int64_t np = static_cast<int64_t>(B) * H * W;
+  VIP_TRY(infer_buffers(c, np));
+  hipStream_t st = c->stream;
+  std::vector<uint16_t> hx(np * kCin);
+  for (int64_t k = 0; k < np * kCin; ++k) hx[k] = host_bf16(x[k]);
+  VIP_HIP_TRY(c, hipMemcpyAsync(N->ix, hx.data(), sizeof(uint16_t) * np * kCin, hipMemcpyHostToDevice, st));
+  const Img g{B, H, W};
+  VIP_TRY(forward_fused(c, g, false));
+  std::vector<float> hy(np);
+  VIP_HIP_TRY(c, hipMemcpyAsync(hy.data(), N->iy, sizeof(float) * np, hipMemcpyDeviceToHost, st));
+  VIP_HIP_TRY(c, hipStreamSynchronize(st));
+  for (int64_t k = 0; k < np; ++k) y[k] = hy[k];
+  return VIP_OK;
+}
+
 // lattice image of the node set; the learned start vector needs one
 static int learn_map(Ctx* c) {
   bool ok = false;

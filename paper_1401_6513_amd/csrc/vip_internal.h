@@ -220,6 +220,9 @@ struct AmgLevel {
   // level 1: tiles of its canonical rows on the cell lattice (FP32 and FP64 sweeps; owned)
   TileMap tmap;
   TilePart tpart32, tpart64;
+  // the level-1 tile partitions were built from cpix32 / cpix64, the canonical rows kept by the
+  // damped-diagonal filter, so every tile row carries wdinv_c / wdinv32_c
+  bool tiles_filtered = false;
 };
 
 struct Amg {
@@ -440,6 +443,7 @@ int learn_set_params(Ctx* c, const double* theta);
 int learn_get_params(Ctx* c, double* theta);
 int learn_eval(Ctx* c, const double* x, const double* t, const double* m, int B, int H, int W, double* y,
                double* loss, double* grad, double lr);
+int learn_infer(Ctx* c, const double* x, int B, int H, int W, double* y);
 // Lattice map of the node set (stencil.hip); false if the nodes are not lattice based.
 int lattice_map(Ctx* c, bool* ok);
 // Find the reference row of the system layout and mark the canonical rows of value set

@@ -92,6 +92,7 @@ SIGNATURES = {
     "vip_learn_set_params": (_INT, [_P, _P, _I64]),
     "vip_learn_get_params": (_INT, [_P, _P, _I64]),
     "vip_learn_eval": (_INT, [_P, _P, _P, _P, _INT, _INT, _INT, _P, ctypes.POINTER(_D), _P, _D]),
+    "vip_learn_infer": (_INT, [_P, _P, _INT, _INT, _INT, _P]),
     "vip_learn_capture": (_INT, [_P, _INT]),
     "vip_learn_snapshot_count": (_INT, [_P, ctypes.POINTER(_INT)]),
     "vip_learn_clear": (_INT, [_P]),
@@ -131,11 +132,19 @@ def _host(a, dtype):
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
 
-def _dev(t):
+def _dev(t, n, device):
+    """Data pointer of a device vector after checking what the library will assume of it:
+    a contiguous float64 tensor on the context's device holding exactly `n` entries.  The
+    library checks pointers only for NULL, so a shorter tensor, or one on another device,
+    would be read and written out of bounds."""
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
             or not t.is_contiguous():
         raise TypeError("expected a contiguous float64 CUDA tensor")
+    if t.device.index != device:
+        raise ValueError("tensor is on cuda:%s, the context on cuda:%d" % (t.device.index, device))
+    if t.numel() != n:
+        raise ValueError("tensor has %d entries, the node set %d" % (t.numel(), n))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -153,7 +162,14 @@ class Context:
             raise VipError(rc, "vip_create", "could not create a context on device %d" % device)
         self._h = h
         self.lib = lib
+        self.device = int(device)
         self.n = 0
+
+    def _d(self, t):
+        """Device pointer of a node vector of this context (see _dev)."""
+        if self.n <= 0:
+            raise VipError(-5, "binding", "no node set built on this context")
+        return _dev(t, self.n, self.device)
 
     def close(self):
         if self._h:
@@ -193,7 +209,7 @@ class Context:
 
     def vip_step(self, u, v, p, dt, Re, allow_not_converged=False):
         st = VipStepStats()
-        rc = self.lib.vip_step(self._h, _dev(u), _dev(v), _dev(p), float(dt), float(Re),
+        rc = self.lib.vip_step(self._h, self._d(u), self._d(v), self._d(p), float(dt), float(Re),
                                ctypes.byref(st))
         self._check(rc, "vip_step", (VIP_E_NOT_CONVERGED,) if allow_not_converged else ())
         return st.as_dict()
@@ -203,7 +219,7 @@ class Context:
 
     def vip_poisson_solve(self, rhs, phi, tol, use_x0=False):
         st = VipStepStats()
-        rc = self.lib.vip_poisson_solve(self._h, _dev(rhs), _dev(phi), float(tol), int(use_x0),
+        rc = self.lib.vip_poisson_solve(self._h, self._d(rhs), self._d(phi), float(tol), int(use_x0),
                                         ctypes.byref(st))
         self._check(rc, "vip_poisson_solve")
         return st.as_dict()
@@ -233,7 +249,7 @@ class Context:
 
     def vip_apply(self, which, x, y):
         w = OP[which] if isinstance(which, str) else int(which)
-        self._check(self.lib.vip_apply(self._h, w, _dev(x), _dev(y)), "vip_apply")
+        self._check(self.lib.vip_apply(self._h, w, self._d(x), self._d(y)), "vip_apply")
 
     def vip_assemble(self, dt, Re):
         self._check(self.lib.vip_assemble(self._h, float(dt), float(Re)), "vip_assemble")
@@ -249,14 +265,14 @@ class Context:
         return vxy, dew, dns, rho
 
     def vip_convection(self, u, v, nx, ny):
-        self._check(self.lib.vip_convection(self._h, _dev(u), _dev(v), _dev(nx), _dev(ny)),
+        self._check(self.lib.vip_convection(self._h, self._d(u), self._d(v), self._d(nx), self._d(ny)),
                     "vip_convection")
 
     def vip_divergence(self, u, v, d):
-        self._check(self.lib.vip_divergence(self._h, _dev(u), _dev(v), _dev(d)), "vip_divergence")
+        self._check(self.lib.vip_divergence(self._h, self._d(u), self._d(v), self._d(d)), "vip_divergence")
 
     def vip_gradient(self, f, gx, gy):
-        self._check(self.lib.vip_gradient(self._h, _dev(f), _dev(gx), _dev(gy)), "vip_gradient")
+        self._check(self.lib.vip_gradient(self._h, self._d(f), self._d(gx), self._d(gy)), "vip_gradient")
 
     def vip_kernel_timing(self, enable=True, reset=False, which=0):
         """(average ms, launches) of kernel `which` (0 pressure SpMV, 1 CNN MFMA layer)."""
@@ -316,6 +332,17 @@ class Context:
                                      g.ctypes.data if g is not None else None, float(lr))
         self._check(rc, "vip_learn_eval")
         return y, (loss.value if have_t else None), g
+
+    def vip_learn_infer(self, x):
+        """x [B,H,W,3] host images -> y [B,H,W] by the fused inference launch of vip_step."""
+        x = _host(x, np.float64)
+        B, H, W, C = x.shape
+        if C != 3:
+            raise ValueError("input images need 3 channels")
+        y = np.empty((B, H, W))
+        self._check(self.lib.vip_learn_infer(self._h, x.ctypes.data, B, H, W, y.ctypes.data),
+                    "vip_learn_infer")
+        return y
 
     def vip_learn_capture(self, max_snapshots):
         self._check(self.lib.vip_learn_capture(self._h, int(max_snapshots)), "vip_learn_capture")

@@ -1,0 +1,249 @@
+"""Parity of the headline paths against the FP64 oracle, through the C ABI.
+
+* Mixed precision (FP32 inner solves inside FP64 refinement) and the learned start
+  vector, at the headline Poisson tolerance of 1e-8, against the oracle's
+  direct-solve steps (eqs. 12-15): per-field relative L2 error in u, v and p (p without
+  its mean where the pressure problem is singular), printed and held to 1e-6.  The
+  FP64 GPU path at the same tolerance is printed beside it, so that the effect of the
+  1e-8 tolerance can be told apart from that of the precision.
+* The lid-driven cavity at its stated size (257 x 257 nodes, Re = 1000, dt = 2e-3), plain
+  FP64 with the Jacobi preconditioner from a zero start at 1e-10, 20 steps against the
+  oracle (Section 5.2 case).
+* The fused inference launch of the learned start vector against the oracle network with
+  BF16 rounding at the points where the kernels store BF16, on ragged images with masked
+  pixels and, sampled at tile edges and image borders, on a 2561 x 3841 image (the
+  lattice image of the cylinder box at h = 1/128).
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn, operators, step
+from paper_1401_6513_amd import nodesets as ns
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _vip():
+    from paper_1401_6513_amd import vip
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return vip
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _errors(got, ref, singular):
+    ug, vg, pg = got
+    uo, vo, po = ref
+    if singular:
+        pg, po = pg - pg.mean(), po - po.mean()
+    return _rel_l2(ug, uo), _rel_l2(vg, vo), _rel_l2(pg, po)
+
+
+@pytest.fixture(scope="module")
+def trained_theta():
+    """A network trained briefly on pressure increments of a small cavity (enough for the
+    learned start to be taken; its quality does not enter the accuracy, which the Krylov
+    solve to the tolerance decides)."""
+    vip = _vip()
+    ctx = vip.Context(0)
+    try:
+        spec = ns.lid_cavity(49)
+        ctx.build_from_spec(spec, precision=vip.P_MIXED, warmstart=vip.WS_PREV)
+        u, v, p = (_dev(a) for a in ns.boundary_initial(spec))
+        ctx.vip_learn_capture(12)
+        for _ in range(14):
+            ctx.vip_step(u, v, p, 0.01, 100.0)
+        ctx.vip_learn_capture(0)
+        ctx.vip_learn_init(3)
+        ctx.vip_learn_train(150, 8, 32, 1e-3, 1)
+        return ctx.vip_learn_get_params()
+    finally:
+        ctx.close()
+
+
+HEADLINE_CASES = {
+    "cavity33": (lambda: ns.lid_cavity(33), (0.0, 0.0), 2e-3, 100.0, 30),
+    "cylinder": (lambda: ns.cylinder_channel(0.1, box=(-2.0, 4.0, -2.0, 2.0), n_surface=32),
+                 (1.0, 0.0), 0.01, 100.0, 15),
+    "bumpy": (lambda: ns.cylinder_channel(1.0 / 16, box=(-1.5, 3.0, -1.5, 1.5), shape=(0.05, 12),
+                                          n_surface=64), (1.0, 0.0), 0.01, 100.0, 10),
+    "triangle": (lambda: ns.triangle_cavity(1.0 / 32), (0.0, 0.0), 2e-3, 200.0, 20),
+}
+
+_oracle_runs = {}
+
+
+def _oracle_run(name):
+    """Oracle direct-solve steps of a case (cached across the paths)."""
+    if name not in _oracle_runs:
+        make, inflow, dt, re, steps = HEADLINE_CASES[name]
+        spec = make()
+        ops = operators.Operators(operators.Problem(**spec.as_kwargs()))
+        st = step.Stepper(ops, dt, re)
+        u, v, p = ns.boundary_initial(spec, inflow)
+        for _ in range(steps):
+            u, v, p = st.step(u, v, p)
+        _oracle_runs[name] = (spec, (u, v, p), st.bordered)
+    return _oracle_runs[name]
+
+
+@pytest.mark.parametrize("name", list(HEADLINE_CASES))
+def test_headline_paths_against_oracle(name, trained_theta):
+    vip = _vip()
+    spec, ref, singular = _oracle_run(name)
+    _, inflow, dt, re, steps = HEADLINE_CASES[name]
+    paths = {"fp64": (vip.P_FP64, vip.WS_PREV), "mixed": (vip.P_MIXED, vip.WS_PREV),
+             "mixed+extrap": (vip.P_MIXED, vip.WS_EXTRAP),
+             "mixed+learned": (vip.P_MIXED, vip.WS_LEARNED)}
+    report = {}
+    for path, (prec, ws) in paths.items():
+        ctx = vip.Context(0)
+        try:
+            ctx.build_from_spec(spec, precision=prec, warmstart=ws, poisson_tol=1e-8)
+            if ws == vip.WS_LEARNED:
+                ctx.vip_learn_set_params(trained_theta)
+            u, v, p = (_dev(a) for a in ns.boundary_initial(spec, inflow))
+            used = 0
+            for _ in range(steps):
+                s = ctx.vip_step(u, v, p, dt, re)
+                assert s["poisson_residual"] <= 1e-8
+                used += s["warm_start"] == ws
+            errs = _errors((u.cpu().numpy(), v.cpu().numpy(), p.cpu().numpy()), ref, singular)
+        finally:
+            ctx.close()
+        report[path] = errs
+        print("%s %-13s rel L2 vs oracle: u %.2e v %.2e p %.2e (start vector used %d/%d)"
+              % (name, path, errs[0], errs[1], errs[2], used, steps))
+        if ws == vip.WS_LEARNED:
+            assert used > 0, "the learned start vector was never taken"
+    for path, errs in report.items():
+        assert max(errs) <= 1e-6, (name, path, errs)
+
+
+def test_cavity_257_re1000_plain_fp64():
+    """Lid-driven cavity at its stated size: 257 x 257 nodes, Re = 1000, dt = 2e-3, plain FP64
+    path (Jacobi preconditioner, zero start) at a Poisson residual of 1e-10, 20 steps from
+    rest against the oracle's direct solves."""
+    vip = _vip()
+    spec = ns.lid_cavity(257)
+    dt, re, steps = 2e-3, 1000.0, 20
+    ops = operators.Operators(operators.Problem(**spec.as_kwargs()))
+    st = step.Stepper(ops, dt, re)
+    u0, v0, p0 = ns.boundary_initial(spec)
+    uo, vo, po = u0, v0, p0
+    for _ in range(steps):
+        uo, vo, po = st.step(uo, vo, po)
+    ctx = vip.Context(0)
+    try:
+        ctx.build_from_spec(spec, precision=vip.P_FP64, warmstart=vip.WS_ZERO, poisson_tol=1e-10,
+                            preconditioner=vip.PC_JACOBI)
+        u, v, p = _dev(u0), _dev(v0), _dev(p0)
+        iters = []
+        for _ in range(steps):
+            s = ctx.vip_step(u, v, p, dt, re)
+            assert s["poisson_residual"] <= 1e-10
+            iters.append(s["poisson_iters"])
+        errs = _errors((u.cpu().numpy(), v.cpu().numpy(), p.cpu().numpy()), (uo, vo, po), True)
+    finally:
+        ctx.close()
+    print("cavity257 Re=1000 plain FP64 (Jacobi, x0 = 0, 1e-10): rel L2 u %.2e v %.2e p %.2e; "
+          "Poisson iterations per step %s" % (errs + (iters,)))
+    assert max(errs) <= 1e-8, errs
+
+
+# ---- fused inference against the oracle network ----------------------------------------------------
+
+def _bf16_net(theta):
+    parts = cnn.unflatten(theta)
+    return [cnn.bf16_round(p) if p.ndim == 4 else np.float32(p).astype(np.float64) for p in parts]
+
+
+def _emulated_forward(parts, x):
+    """The oracle's layers with BF16 rounding where the kernels store BF16 (input, the three
+    activations); FP32-rounded biases, FP64 sums."""
+    W1, b1, W2, b2, W3, b3, W4, b4 = parts
+    r = cnn.bf16_round
+    a = r(x)
+    a = r(np.maximum(cnn.conv(a, W1, b1), 0.0))
+    a = r(np.maximum(cnn.conv(a, W2, b2), 0.0))
+    a = r(np.maximum(cnn.conv(a, W3, b3), 0.0))
+    return cnn.conv(a, W4, b4)[..., 0]
+
+
+def _theta(seed):
+    rng = np.random.default_rng(seed)
+    th = cnn.init_params(seed)
+    return th + 0.01 * rng.standard_normal(len(th))
+
+
+def _image(rng, B, H, W):
+    x = rng.standard_normal((B, H, W, 3))
+    x[..., 2] = (rng.uniform(size=(B, H, W)) > 0.2)            # lattice mask with holes
+    x[..., 0] *= x[..., 2]
+    x[..., 1] *= x[..., 2]
+    return x
+
+
+@pytest.mark.parametrize("B,H,W", [(1, 16, 16), (2, 19, 37), (1, 45, 70), (3, 5, 50), (1, 1, 33)])
+def test_fused_inference_matches_oracle(B, H, W):
+    vip = _vip()
+    ctx = vip.Context(0)
+    try:
+        theta = _theta(40 + H)
+        ctx.vip_learn_set_params(theta)
+        x = _image(np.random.default_rng(H * W), B, H, W)
+        y = ctx.vip_learn_infer(x)
+        y_layers, _, _ = ctx.vip_learn_eval(x)
+    finally:
+        ctx.close()
+    ref = _emulated_forward(_bf16_net(theta), x)
+    err = _rel_l2(y, ref)
+    print("fused inference B=%d H=%d W=%d rel L2 vs emulated oracle %.3e" % (B, H, W, err))
+    assert err <= 5e-3
+    assert np.array_equal(y, y_layers)          # same bits as the layer-by-layer pass
+
+
+def test_fused_inference_full_size_samples():
+    """2561 x 3841 image: the fused launch's output at sampled pixels on 16-pixel tile edges,
+    image borders and corners, against the oracle evaluated on the 9 x 9 input window of each
+    sample (a 4-layer 3 x 3 network sees exactly that window; windows cut at the image edge
+    get the same zero padding as the full image)."""
+    vip = _vip()
+    H, W = 2561, 3841
+    rng = np.random.default_rng(77)
+    x = _image(rng, 1, H, W)
+    theta = _theta(9)
+    ctx = vip.Context(0)
+    try:
+        ctx.vip_learn_set_params(theta)
+        y = ctx.vip_learn_infer(x)[0]
+    finally:
+        ctx.close()
+    parts = _bf16_net(theta)
+    samples = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H - 1, W // 2), (H // 2, W - 1)]
+    edge = lambda n: rng.integers(0, n // 16) * 16 + rng.choice([0, 15])
+    for _ in range(120):
+        samples.append((int(min(edge(H), H - 1)), int(min(edge(W), W - 1))))
+        samples.append((int(rng.integers(0, H)), int(rng.integers(0, W))))
+    got, want = [], []
+    for (i, j) in samples:
+        i0, i1 = max(i - 4, 0), min(i + 5, H)
+        j0, j1 = max(j - 4, 0), min(j + 5, W)
+        win = x[:, i0:i1, j0:j1, :]
+        yw = _emulated_forward(parts, win)[0]
+        want.append(yw[i - i0, j - j0])
+        got.append(y[i, j])
+    got, want = np.array(got), np.array(want)
+    err = _rel_l2(got, want)
+    worst = np.abs(got - want).max() / np.sqrt(np.mean(want ** 2))
+    print("fused inference 2561x3841, %d samples: rel L2 %.3e, worst %.3e of rms" % (len(got), err, worst))
+    assert err <= 5e-3 and worst <= 3e-2

@@ -65,7 +65,15 @@ def log(msg):
     sys.stderr.flush()
 
 
-def workload(h):
+# zones of the stepwise refined cylinder workload (finest first): spacing h, 2h, 4h, and 8h outside
+REFINED_ZONES = [(-1.5, 6.0, -1.5, 1.5), (-3.0, 12.0, -3.0, 3.0), (-6.0, 18.0, -6.0, 6.0)]
+
+
+def workload(h, kind="lattice"):
+    if kind == "refined":
+        # flow past the cylinder on a stepwise refined node set (finest spacing h near the body,
+        # doubling in three steps): every row takes the general sliced-ELL path
+        return [ns.refined_cylinder_channel(h, REFINED_ZONES, n_surface=256)]
     cyl = ns.cylinder_channel(h, box=(-10.0, 20.0, -10.0, 10.0), shape="circle", n_surface=256)
     tri = ns.triangle_cavity(h)
     return [cyl, tri]
@@ -73,7 +81,7 @@ def workload(h):
 
 def _initial(spec, dev):
     import torch
-    inflow = (1.0, 0.0) if spec.name.startswith("cyl") else (0.0, 0.0)
+    inflow = (1.0, 0.0) if spec.name.startswith(("cyl", "refined")) else (0.0, 0.0)
     u, v, p = ns.boundary_initial(spec, inflow)
     return [torch.tensor(a, device=dev) for a in (u, v, p)]
 
@@ -91,7 +99,7 @@ PATHS = {
 
 
 def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol, pool=None,
-             helmholtz_tol=None):
+             helmholtz_tol=None, learned_precond=False):
     """Run `steps` timed steps of every domain (domains in parallel host threads, one HIP stream
     each, when a pool is given); returns wall seconds, stats, SpMV timing, fields and the
     summed seconds of each domain's own steps."""
@@ -102,7 +110,8 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
         opt = vip.default_options(period=spec.period, poisson_tol=tol, inner_tol=inner_tol,
                                   precision=getattr(vip, cfg["precision"]),
                                   warmstart=getattr(vip, cfg["warmstart"]),
-                                  preconditioner=getattr(vip, cfg.get("preconditioner", "PC_AMG")))
+                                  preconditioner=getattr(vip, cfg.get("preconditioner", "PC_AMG")),
+                                  learned_precond=1 if (learned_precond and path == "learned") else 0)
         if helmholtz_tol is not None:
             opt.helmholtz_tol = helmholtz_tol
         ctx.vip_set_options(opt)
@@ -174,7 +183,8 @@ def cpu_baseline(h, dt, re, budget_s):
             if el > budget_s or n_steps >= 5:
                 break
     per = el / n_steps
-    return {"value": spec.n / per, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
+    return {"value": spec.n / per, "unit": "node-updates/s", "cores": 1, "nproc": os.cpu_count(),
+            "kind": "oracle",
             "sample": "FP64 oracle (NumPy/SciPy, BiCGStab to 1e-8, zero start) on the window "
                       "[%g,%g]x[%g,%g] of the cylinder workload at h=1/%d (%d nodes), %d timed steps "
                       "after the impulsive first one; single-threaded SciPy sparse kernels" % (
@@ -195,10 +205,23 @@ def main():
                     help="tolerance of the predictor solves (default: the library's)")
     ap.add_argument("--inner-tol", type=float, default=1e-4,
                     help="relative tolerance of the FP32 inner solve (mixed path)")
-    ap.add_argument("--paths", default="learned,mixed,fp64")
+    ap.add_argument("--paths", default="learned,mixed,extrap,fp64")
+    ap.add_argument("--workload", default="lattice", choices=["lattice", "refined"],
+                    help="lattice: cylinder + triangle on uniform lattices (the headline workload); "
+                         "refined: the cylinder on a stepwise refined node set (general rows only; "
+                         "the learned path needs a lattice and is skipped)")
+    ap.add_argument("--no-delta", action="store_true",
+                    help="general rows read int32 columns instead of int16 row-relative ones")
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="timed steps of the plain path (slow: hundreds of Krylov iterations a step)")
     ap.add_argument("--train-iters", type=int, default=1000)
+    ap.add_argument("--train-set", default="small", choices=["small", "config4"],
+                    help="small: 4 short runs on a 129^2 cavity and an h=1/16 cylinder box (40 "
+                         "snapshots each); config4: the bumpy-cylinder case's specification, 10 runs "
+                         "of the 257^2 cavity and the h=D/40 cylinder, Re ~ U[60,200], 200 snapshots "
+                         "each, one every 5 steps after 200 steps")
+    ap.add_argument("--learned-precond", action="store_true",
+                    help="the learned path also preconditions every refinement pass with the network")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--serial", action="store_true",
                     help="step the domains one after the other on one stream (default: each domain "
@@ -220,8 +243,10 @@ def main():
     h = args.h
     dt = h / 10.0
     re = args.re
-    log("generating node sets (h = %g)" % h)
-    specs = workload(h)
+    log("generating node sets (h = %g, %s)" % (h, args.workload))
+    specs = workload(h, args.workload)
+    if args.no_delta:
+        os.environ["VIP_NO_DELTA"] = "1"      # read once by each context at creation
     n_total = sum(s.n for s in specs)
     log("nodes: %s (total %d)" % ([s.n for s in specs], n_total))
     ctxs = []
@@ -249,6 +274,8 @@ def main():
         del src, dst
 
     paths = [p for p in args.paths.split(",") if p]
+    if args.workload == "refined":
+        paths = [p for p in paths if p != "learned"]
     for p in paths:
         if p not in PATHS:
             sys.exit("unknown path %r (known: %s)" % (p, ", ".join(PATHS)))
@@ -256,12 +283,20 @@ def main():
     if "learned" in paths:
         from paper_1401_6513_amd import training
         t0 = time.perf_counter()
-        theta, nsnap, loss = training.trained_parameters(iters=args.train_iters)
+        if args.train_set == "config4":
+            theta, nsnap, loss = training.trained_parameters(runs=training.config4_runs(),
+                                                             iters=args.train_iters, transient=200,
+                                                             per_run=200, every=5)
+            data = ("10 runs alternating cavity 257x257 and cylinder h=1/40 in [-10,20]x[-10,10], "
+                    "Re~U[60,200] (seeds 0-9), dt=h/10, 200 snapshots per run, one every 5 steps "
+                    "after 200 steps")
+        else:
+            theta, nsnap, loss = training.trained_parameters(iters=args.train_iters)
+            data = ("cavity 129x129 Re~U[100,1000] and cylinder h=1/16 in [-4,8]x[-4,4] "
+                    "Re~U[60,200], dt=h/10, 40 snapshots per run after 40 steps, 4 runs")
         torch.cuda.synchronize()
         train_info = {"snapshots": nsnap, "iters": args.train_iters, "last_loss": loss,
-                      "seconds": time.perf_counter() - t0,
-                      "data": "cavity 129x129 Re~U[100,1000] and cylinder h=1/16 in [-4,8]x[-4,4] "
-                              "Re~U[60,200], dt=h/10, 40 snapshots per run after 40 steps, 4 runs"}
+                      "seconds": time.perf_counter() - t0, "data": data}
         log("network trained: %d snapshots, loss %.3e, %.1f s" % (nsnap, loss, train_info["seconds"]))
         for c in ctxs:
             c.vip_learn_set_params(theta)
@@ -274,7 +309,8 @@ def main():
         nsteps = args.plain_steps if path == "plain" else args.steps
         el, stats, (spmv, conv), fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
                                                   nsteps, args.tol, path == paths[0],
-                                                  args.inner_tol, pool, args.helmholtz_tol)
+                                                  args.inner_tol, pool, args.helmholtz_tol,
+                                                  args.learned_precond)
         results[path] = dict(seconds=el, stats=stats, spmv=spmv, conv=conv, fields=fields, dom_s=dom_s,
                              steps=nsteps)
         log("%s: %.3f s for %d steps" % (path, el, nsteps))
@@ -289,29 +325,37 @@ def main():
         n0, _, nnz0 = ctxs[0].vip_operator_shape("poisson")
         fp32 = PATHS[main_path]["precision"] != "P_FP64"
         counts, taps = ctxs[0].vip_canonical_rows()
+        cb = ctxs[0].vip_column_bytes()[0]   # bytes per stored column: int16 deltas or int32
         vs = 4 if fp32 else 0
         nc = int(counts[vs])
         vb = 4 if fp32 else 8            # bytes of one vector entry / value
         sp = specs[0]
-        W = int(np.floor((sp.xy[:, 0].max() - sp.xy[:, 0].min()) / sp.h + 0.5)) + 1
-        H = int(np.floor((sp.xy[:, 1].max() - sp.xy[:, 1].min()) / sp.h + 0.5)) + 1
-        ntiles = -(-W // 64) * -(-H // 16)
+        if nc > 0:
+            W = int(np.floor((sp.xy[:, 0].max() - sp.xy[:, 0].min()) / sp.h + 0.5)) + 1
+            H = int(np.floor((sp.xy[:, 1].max() - sp.xy[:, 1].min()) / sp.h + 0.5)) + 1
+            ntiles = -(-W // 64) * -(-H // 16)
+        else:
+            ntiles = 0
         # algorithmic bytes of one launch: x read once, r-hat read, v written (3 vectors); stored
-        # values + int32 columns of the irregular rows (and, in FP32, their row sums) and the
-        # irregular-row list; per 64 x 16 tile its 256-byte record (position, 20 row starts, 16 row
-        # masks), counted for every lattice tile.  Canonical (tile) rows read no column or value
-        # stream.
-        bytes_per_launch = (3 * vb * n0 + (vb + 4) * (nnz0 - taps * nc) + (4 if fp32 else 0) * (n0 - nc)
-                            + 4 * (n0 - nc) + 256 * ntiles)
+        # values + columns (int16 row-relative or int32) of the irregular rows (and, in FP32, their
+        # row sums); with tiles, the irregular-row list and per 64 x 16 tile its 256-byte record
+        # (position, 20 row starts, 16 row masks), counted for every lattice tile.  Canonical
+        # (tile) rows read no column or value stream.
+        bytes_per_launch = (3 * vb * n0 + (vb + cb) * (nnz0 - taps * nc) + (4 if fp32 else 0) * (n0 - nc)
+                            + (4 * (n0 - nc) + 256 * ntiles if ntiles else 0))
         avg_ms, count = r["spmv"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        tiled = ntiles > 0
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic() if abs(h - 1.0 / 128) < 1e-12 else None,
-                "kernel": "k_bicg_v<%s,%s,1> (pressure SpMV, LDS-tiled canonical rows)" % (
-                    ("float", "float") if fp32 else ("double", "double")),
+                "traffic": measured_traffic() if (abs(h - 1.0 / 128) < 1e-12 and tiled) else None,
+                "kernel": "k_bicg_v<%s,%s,1> (pressure SpMV, %s)" % (
+                    ("float", "float", "LDS-tiled canonical rows" if tiled else "general sliced-ELL rows")
+                    if fp32 else
+                    ("double", "double", "LDS-tiled canonical rows" if tiled else "general sliced-ELL rows")),
                 "bytes_per_launch": bytes_per_launch, "avg_ms": avg_ms, "launches": count,
                 "rows": n0, "nnz": nnz0, "canonical_rows": nc, "tiles": ntiles, "taps": taps,
+                "column_bytes": cb,
                 "ell_bytes_per_launch": (vb + 4) * nnz0 + 3 * vb * n0}
 
     roof_mfma = None
@@ -331,14 +375,19 @@ def main():
                      "flops_per_launch": flops, "flops_per_pixel": per_px, "avg_ms": avg_ms,
                      "launches": count, "image": [H, W]}
 
+    if args.workload == "refined":
+        wl = ("cylinder D=1 in [-10,20]x[-10,10] on a stepwise refined node set (spacing h=D/%d "
+              "near the body, doubling in 3 steps), Re=%g, dt=%g, Poisson rel. residual %g" % (
+                  round(1 / h), re, dt, args.tol))
+    else:
+        wl = ("cylinder D=1 in [-10,20]x[-10,10] + equilateral lid cavity, h=D/%d, Re=%g, dt=%g, "
+              "Poisson rel. residual %g" % (round(1 / h), re, dt, args.tol))
     out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if PATHS[main_path]["precision"] == "P_FP64" else "f32+f64+bf16"
            if main_path == "learned" else "f32+f64", "data": "synthetic",
-           "config": {"workload": "cylinder D=1 in [-10,20]x[-10,10] + equilateral lid cavity, "
-                                  "h=D/%d, Re=%g, dt=%g, Poisson rel. residual %g" % (
-                                      round(1 / h), re, dt, args.tol),
+           "config": {"workload": wl,
                       "nodes": n_total, "nodes_per_domain": [s.n for s in specs],
                       "path": main_path, "build_s": build_s,
                       "domains_concurrent": not args.serial}}
@@ -360,6 +409,10 @@ def main():
     if ref_path and main_path != ref_path:
         # FP64 Krylov with the same multigrid preconditioner and start vector as the mixed path
         out["speedup_vs_fp64"] = per_step[ref_path] / per_step[main_path]
+        out["fp64_comparator"] = ("fp64 path: FP64 BiCGStab (predictor and pressure) with the same "
+                                  "aggregation-multigrid preconditioner and previous-increment start "
+                                  "vector; plain Jacobi FP64 (path 'plain') does not converge on the "
+                                  "cylinder at h=D/128")
         # difference of the paths' fields after the same steps (all solve to 1e-8)
         out["rel_l2_vs_fp64"] = {}
         for path in results:

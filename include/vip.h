@@ -84,6 +84,14 @@ typedef struct {
   int preconditioner;     /* VIP_PC_*; default VIP_PC_AMG: aggregation multigrid V-cycle
                              (2x2-cell aggregates, Galerkin coarse matrices, damped Jacobi
                              smoothing, dense coarsest solve), built at the first solve */
+  int learned_precond;    /* 1: with VIP_WS_LEARNED and VIP_P_MIXED on a non-singular lattice-based
+                             pressure system, the learned network also preconditions every FP64
+                             refinement pass: the pass adds alpha d + beta c, d the FP32 inner
+                             correction of the pass residual r and c the network's correction of r,
+                             (alpha, beta) minimising ||r - alpha L d - beta L c||_2 (a flexible
+                             two-direction step, so a nonlinear preconditioner is allowed); when the
+                             network's direction does not lower that residual below the best
+                             multiple of d alone, the pass adds d as usual.  Default 0. */
 } vip_options;
 
 typedef struct {
@@ -102,6 +110,11 @@ typedef struct {
   int poisson_fp64_fallback; /* 1: with VIP_P_MIXED an FP32 correction broke down or stopped
                                 gaining (less than 2x on the FP64 residual), and the Poisson solve
                                 finished with FP64 iterations from its FP64 iterate; else 0 */
+  int learned_pc_passes;     /* learned_precond: refinement passes that took the network's
+                                direction */
+  double learned_pc_ratio;   /* learned_precond: product over the passes of the predicted residual
+                                with the network's direction over that of the best multiple of d
+                                alone (1 if never taken; < 1 is what the network gained) */
 } vip_step_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -116,7 +129,9 @@ void vip_default_options(vip_options* opt);
  * VIP_AMG_NU, VIP_AMG_NU_COARSE override the multigrid over-correction and sweep
  * counts (these change results); VIP_MAX_GRID sets the block count of the reducing
  * vector kernels (default 2048, read once per process; it changes the order of the
- * partial sums and so the last bits); VIP_DEBUG=1 prints solver progress to stderr. */
+ * partial sums and so the last bits); VIP_NO_DELTA=1 keeps the general rows on int32 columns
+ * instead of int16 row-relative ones (same bits); VIP_DEBUG=1 prints solver progress to
+ * stderr. */
 int vip_create(void** out, int device, void* stream);
 
 /* Release every device allocation of the context and the context itself. */
@@ -152,6 +167,24 @@ int vip_build_stencils(void* ctx, const double* nodes_xy, int64_t n_nodes,
                        const int32_t* bnd_kind, const double* bnd_value, int64_t n_bnd,
                        int basis_order, double support_radius, double h,
                        const vip_options* opt);
+
+/*
+ * vip_build_stencils for node sets whose spacing varies from node to node (stepwise adaptive
+ * distributions, Section 5.5), with a support radius that follows the local spacing: rho(xbar)
+ * of Section 3.  h_node (host, [n_nodes] FP64, > 0) is each node's local spacing; an
+ * evaluation point that belongs to node i (the node itself, its VIPs, or the inner points of
+ * the Neumann row of boundary node i) gets the support radius support_radius * h_node[i] / h,
+ * grown as in vip_build_stencils; node i's VIPs sit at vip_offset * h_node[i] and its Neumann
+ * points at vip_offset * h_node[i] and twice that.  h is the reference spacing (the finest);
+ * h_node[i] = h for every node gives vip_build_stencils' result.  Other arguments, errors and
+ * ownership as vip_build_stencils; VIP_E_INVALID also for h_node NULL or an entry that is not
+ * finite and positive.
+ */
+int vip_build_stencils_adaptive(void* ctx, const double* nodes_xy, int64_t n_nodes,
+                                const int64_t* bnd_idx, const double* bnd_normal,
+                                const int32_t* bnd_kind, const double* bnd_value, int64_t n_bnd,
+                                int basis_order, double support_radius, double h,
+                                const double* h_node, const vip_options* opt);
 
 /* Replace the solver options of a built context (stencil-defining fields such
  * as weight, vip_offset, period and min_neighbours are ignored here). */
@@ -324,6 +357,40 @@ int vip_divergence(void* ctx, const double* u, const double* v, double* div);
  * (zero on boundary rows). */
 int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
 
+/* ---- body forces (Section 5.4: drag and lift coefficients, Strouhal number) ---------------
+ *
+ * Force on a body from the fluid, F = -sum over its surface of t dS with the traction of
+ * Section 5.4, t = -p n + (1/Re) du/dn, n the outward normal of the flow domain (the boundary
+ * table's normal, pointing into the body); du/dn is the normal derivative of the boundary
+ * rows, (3 u_b - 4 u(x_b - d n) + u(x_b - 2 d n)) / (2 d) with
+ * d = vip_offset h and the values at the inner points interpolated by Psi^[0,0] (exact for
+ * quadratics).  dS is the trapezoid weight of the closed chain of surface nodes, half the
+ * chords to the previous and the next node.  For the cylinder cases (D = 1, U = 1) the drag
+ * and lift coefficients are C_D = 2 F_x and C_L = 2 F_y.
+ *
+ *  u, v, p   device [n_nodes] FP64 state (p as vip_step leaves it).
+ *  Re        Reynolds number (> 0; the viscosity is 1/Re).
+ *  surf_idx  host [n_surf] int64: node indices of the body surface in order around it
+ *            (on adaptive node sets d follows each surface node's local spacing)
+ *            (entry k adjacent to k-1 and k+1, the last to the first); each must be a
+ *            boundary node.  n_surf >= 3.
+ *  force     host [2]: F_x, F_y.
+ * The work arrays (the surface list and one traction pair per node) belong to the context
+ * and grow as needed.  Errors: VIP_E_NOT_BUILT, VIP_E_INVALID (NULL arguments, n_surf < 3,
+ * Re <= 0, an index out of range or not a boundary node), VIP_E_HIP.
+ */
+int vip_forces(void* ctx, const double* u, const double* v, const double* p, double Re,
+               const int64_t* surf_idx, int64_t n_surf, double* force);
+
+/* Dominant frequency of a real signal sampled at spacing dt (host [n], n >= 8): the maximum
+ * of the periodogram of the mean-removed, Hann-windowed signal, located on the DFT bins
+ * k / (n dt), k >= 1, then refined between the neighbouring bins by golden-section search on
+ * the continuous spectrum.  *freq gets the frequency; *amp (may be NULL) the amplitude of a
+ * sinusoid with that peak.  For the lift history of a cylinder (D = 1, U = 1) the Strouhal
+ * number is the frequency.  Host computation, no context.  Errors: VIP_E_INVALID (NULL
+ * arguments, n < 8, dt <= 0, non-finite samples). */
+int vip_spectral_peak(const double* signal, int64_t n, double dt, double* freq, double* amp);
+
 /* Rows of the system layout that are translation-invariant lattice-interior copies of one
  * reference row (same lattice offsets, bitwise equal values), per value set (host counts[7]):
  * [0] FP64 pressure matrix, [1] predictor matrix of u, [2] of v, [3] nodes whose rows of the
@@ -336,6 +403,14 @@ int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
  * streams and give the same bits.  All counts are 0 when VIP_NO_CANON=1 was set at
  * vip_create, or for node sets that are not lattice based.  Host outputs, may be NULL. */
 int vip_canonical_rows(void* ctx, int64_t* counts, int64_t* described, int* taps);
+
+/* Column stream of the general (non-canonical) rows: *sys_bytes = 2 when the pressure and
+ * predictor matrices store row-relative int16 columns (every stored column within +-32767 of
+ * its row; then the solve-phase kernels read those and the results keep their bits), else 4
+ * (int32; also with VIP_NO_DELTA=1 at vip_create).  *amg_levels = coarse multigrid levels built
+ * so far (the hierarchy is built at the first Poisson solve), *amg_levels_delta = those with
+ * int16 columns.  Host outputs, may be NULL.  Errors: VIP_E_NOT_BUILT. */
+int vip_column_bytes(void* ctx, int* sys_bytes, int* amg_levels, int* amg_levels_delta);
 
 /* Average duration (ms) of a kernel over its launches since the last reset, measured with
  * HIP events on the context stream while timing is enabled; *count receives the number of

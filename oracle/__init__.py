@@ -6,7 +6,8 @@ reads the same input arrays (node set, boundary table, fields) and computes
 every result on its own, in NumPy/SciPy, following the paper's definitions.
 
 Modules: `mls` (shape functions, Section 3), `operators` (VIP operators,
-Section 4), `step` (fractional step, eqs. 12-15), `krylov` (timing-mode
+Section 4), `step` (fractional step, eqs. 12-15), `forces` (body force by traction,
+Section 5.4), `krylov` (timing-mode
 solvers), `exact` (closed-form solutions).
 """
-from . import exact, krylov, mls, operators, step  # noqa: F401
+from . import exact, forces, krylov, mls, operators, step  # noqa: F401

@@ -128,9 +128,10 @@ class NodeSet:
 
 
 def stencils(nodes, xbar, rho0, min_neighbours=12):
-    """Neighbour lists and support radii for each evaluation point (growth rule)."""
+    """Neighbour lists and support radii for each evaluation point (growth rule); rho0 is one
+    radius or one per point (rho(xbar) of Section 3)."""
     xbar = np.asarray(xbar, dtype=np.float64).reshape(-1, 2)
-    rho = np.full(len(xbar), float(rho0))
+    rho = np.array(np.broadcast_to(np.asarray(rho0, dtype=np.float64), (len(xbar),)))
     if len(xbar) == 0:
         return [], rho
     nb = nodes.neighbours(xbar, rho)

@@ -19,8 +19,11 @@ Interpolation Point"):
   the spacings |x_e - x_w| and |x_n - x_s| used by the direct differences.
 
 Readings of the paper taken here:
-* VIPs sit at x_i +- (o, 0) and x_i +- (0, o) with o = vip_offset * h (Fig. 1 is
-  missing from the text; half a lattice spacing by default).
+* VIPs sit at x_i +- (o, 0) and x_i +- (0, o) with o = vip_offset * h_i (Fig. 1 is
+  missing from the text; half the node's spacing by default).
+* The support radius rho(xbar) of Section 3 depends on the evaluation point: on stepwise
+  adaptive node sets it is rho h_i / h for a point belonging to node i (the node, its VIPs,
+  or the inner Neumann points of a boundary node), with h_i that node's local spacing.
 * Near the boundary (the paper only says a "technical problem" can arise there):
   for each VIP, take the boundary node nearest to the VIP among the boundary
   nodes within rho of x_i (ties: lowest index); if the VIP lies strictly on the
@@ -51,7 +54,7 @@ class Problem:
 
     def __init__(self, xy, bnd_idx=(), bnd_normal=(), bnd_kind=(), bnd_value=(), rho=None, h=None,
                  period=(0.0, 0.0), vip_offset=0.5, weight_kind=mls.CUBIC_SPLINE,
-                 min_neighbours=12):
+                 min_neighbours=12, h_node=None):
         self.xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64))
         self.n = len(self.xy)
         self.bnd_idx = np.asarray(bnd_idx, dtype=np.int64).reshape(-1)
@@ -61,6 +64,14 @@ class Problem:
         self.bnd_value = np.asarray(bnd_value, dtype=np.float64).reshape(nb, 2)
         self.rho = float(rho)
         self.h = float(h)
+        # local spacing of each node (stepwise adaptive sets); the support radius of an
+        # evaluation point is rho h_i / h with i the node it belongs to (the node itself, the
+        # owner of a VIP, or the boundary node of a Neumann point), its VIP offset
+        # vip_offset h_i and its Neumann distance vip_offset h_b
+        self.h_node = (np.full(self.n, self.h) if h_node is None
+                       else np.asarray(h_node, dtype=np.float64).reshape(self.n).copy())
+        self.h_scale = np.ones(self.n) if h_node is None else self.h_node / self.h
+        self.rho_node0 = self.rho * self.h_scale
         self.period = tuple(float(p) for p in period)
         self.vip_offset = float(vip_offset)
         self.weight_kind = int(weight_kind)
@@ -77,20 +88,22 @@ class Problem:
 
 def vip_points(prob):
     """VIP coordinates [n_interior, 4, 2] (order e, w, n, s) after boundary clipping."""
-    o = prob.vip_offset * prob.h
+    oi = (prob.vip_offset * prob.h) * prob.h_scale[prob.interior]
+    ri = prob.rho_node0[prob.interior]
     xi = prob.xy[prob.interior]
-    pts = xi[:, None, :] + o * VIP_DIRS[None, :, :]
+    pts = xi[:, None, :] + oi[:, None, None] * VIP_DIRS[None, :, :]
     if len(prob.bnd_idx) == 0:
         return pts
     bxy = prob.xy[prob.bnd_idx]
     tree = cKDTree(bxy)
-    cand = tree.query_ball_point(xi, prob.rho * (1.0 + 1e-9), return_sorted=True)
+    cand = tree.query_ball_point(xi, ri * (1.0 + 1e-9), return_sorted=True)
     for r, c in enumerate(cand):
         if not c:
             continue
+        o = oi[r]
         c = np.asarray(c, dtype=np.int64)
         d0 = bxy[c] - xi[r]
-        c = c[d0[:, 0] * d0[:, 0] + d0[:, 1] * d0[:, 1] < prob.rho * prob.rho]
+        c = c[d0[:, 0] * d0[:, 0] + d0[:, 1] * d0[:, 1] < ri[r] * ri[r]]
         if len(c) == 0:
             continue
         # nearest boundary node by bnd_idx order (ties -> lowest boundary-table index)
@@ -129,29 +142,30 @@ class Operators:
         n = prob.n
         nodes = mls.NodeSet(prob.xy, prob.period)
         if prob.periodic:
-            assert 2.0 * prob.rho * mls.RHO_GROWTH ** mls.MAX_GROWTH_STEPS < min(prob.period)
+            assert 2.0 * prob.rho_node0.max() * mls.RHO_GROWTH ** mls.MAX_GROWTH_STEPS < min(prob.period)
         kw = dict(weight_kind=prob.weight_kind, min_neighbours=prob.min_neighbours)
         allrows = np.arange(n)
         nb, self.rho_node, psi = mls.shape_functions(
-            nodes, prob.xy, prob.rho, [(0, 0), (2, 0), (0, 2)], **kw)
+            nodes, prob.xy, prob.rho_node0, [(0, 0), (2, 0), (0, 2)], **kw)
         self.node_nbrs = nb
         self.M00 = _csr(allrows, nb, psi[(0, 0)], n)
         lap = [a + b for a, b in zip(psi[(2, 0)], psi[(0, 2)])]
         self.L = _csr(allrows, nb, lap, n)
         # inner points of the Neumann rows
-        d = prob.vip_offset * prob.h
-        self.normal_xy = [prob.xy[prob.bnd_idx] - m * d * prob.bnd_normal for m in (1.0, 2.0)]
+        d = (prob.vip_offset * prob.h) * prob.h_scale[prob.bnd_idx]
+        self.normal_xy = [prob.xy[prob.bnd_idx] - m * d[:, None] * prob.bnd_normal for m in (1.0, 2.0)]
         self.NB = []
         for pts in self.normal_xy:
-            bnb, _, bpsi = mls.shape_functions(nodes, pts, prob.rho, [(0, 0)], **kw)
+            bnb, _, bpsi = mls.shape_functions(nodes, pts, prob.rho_node0[prob.bnd_idx], [(0, 0)],
+                                               **kw)
             self.NB.append(_csr(prob.bnd_idx, bnb, bpsi[(0, 0)], n))
         # virtual interpolation points of interior nodes
         self.vip_xy = vip_points(prob)
         self.VIP = []
         self.rho_vip = []
         for k in range(4):
-            vnb, vrho, vpsi = mls.shape_functions(nodes, self.vip_xy[:, k, :], prob.rho,
-                                                  [(0, 0)], **kw)
+            vnb, vrho, vpsi = mls.shape_functions(nodes, self.vip_xy[:, k, :],
+                                                  prob.rho_node0[prob.interior], [(0, 0)], **kw)
             self.VIP.append(_csr(prob.interior, vnb, vpsi[(0, 0)], n))
             self.rho_vip.append(vrho)
         self.d_ew = np.ones(n)
@@ -189,8 +203,8 @@ class Operators:
     def neumann_rows(self):
         """Rows 3 e_b - 4 Psi^[0,0](x_b - d n_b) + Psi^[0,0](x_b - 2 d n_b) at boundary nodes.
 
-        Row b applied to f gives 2 d times the normal derivative of f at x_b
-        (d = vip_offset * h); rows of non-boundary nodes are empty.
+        Row b applied to f gives 2 d_b times the normal derivative of f at x_b
+        (d_b = vip_offset * h_b); rows of non-boundary nodes are empty.
         """
         n = self.prob.n
         ind = np.zeros(n)

@@ -135,7 +135,7 @@ class Stepper:
             for g in rows:
                 k = pos[int(g)]
                 if prob.bnd_kind[k] == OUTLET:
-                    vec[g] = (2.0 * prob.vip_offset * prob.h * self.Re * p[g]
+                    vec[g] = (2.0 * prob.vip_offset * prob.h * prob.h_scale[g] * self.Re * p[g]
                               * prob.bnd_normal[k, comp])
                 else:
                     vec[g] = 0.0

@@ -275,6 +275,7 @@ struct LevelView {
   int64_t n;
   const int64_t* ptr;
   const int32_t* cols;
+  const int16_t* dcols;   // row-relative columns (Ell::dcols), or null
   const T* val;
   const T* wdinv;
   const float* rsum;   // FP32 levels: row sums for the difference form
@@ -429,10 +430,13 @@ __device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
   const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
   T a0 = T(0), a1 = T(0);
   int k = 0;
+  const int32_t ii = static_cast<int32_t>(i);
+  auto col = [&](int64_t q) __attribute__((always_inline)) {
+    return L.dcols ? ii + static_cast<int32_t>(L.dcols[q]) : L.cols[q];
+  };
   for (; k + 4 <= w; k += 4) {
     const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-    const int32_t c0 = L.cols[q], c1 = L.cols[q + kSlice], c2 = L.cols[q + 2 * kSlice],
-                  c3 = L.cols[q + 3 * kSlice];
+    const int32_t c0 = col(q), c1 = col(q + kSlice), c2 = col(q + 2 * kSlice), c3 = col(q + 3 * kSlice);
     const T v0 = L.val[q], v1 = L.val[q + kSlice], v2 = L.val[q + 2 * kSlice], v3 = L.val[q + 3 * kSlice];
     const T y0 = y(c0), y1 = y(c1), y2 = y(c2), y3 = y(c3);
     a0 = fmadd(v0, y0 - yi, a0);
@@ -442,7 +446,7 @@ __device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
   }
   for (; k < w; ++k) {
     const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-    a0 = fmadd(L.val[q], y(L.cols[q]) - yi, a0);
+    a0 = fmadd(L.val[q], y(col(q)) - yi, a0);
   }
   if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.rsum[i]), yi, a0 + a1);
   else return a0 + a1;
@@ -858,6 +862,7 @@ int amg_setup(Ctx* c) {
                                                  L.agg, 1, C.A.rowlen, C.A.ptr, C.A.cols, C.A.val[0], flag);
     VIP_TRY(dalloc(c, &C.A.val32, C.A.nnz_slots));
     k_to32<<<grid_for(C.A.nnz_slots), kBlock, 0, st>>>(C.A.nnz_slots, C.A.val[0], C.A.val32);
+    VIP_TRY(ell_deltas(c, C.A));
     VIP_TRY(dalloc(c, &C.A.rsum32, nc));
     launch_rowsum32(st, nc, C.A.ptr, C.A.rowlen, C.A.val[0], C.A.rsum32);
     unsigned long long bad = 0;
@@ -922,6 +927,7 @@ static LevelView<T> view(const Ctx* c, int level) {
   v.n = L.n;
   v.ptr = L.A.ptr;
   v.cols = L.A.cols;
+  v.dcols = L.A.dcols;
   v.rsum = L.A.rsum32;
   v.cpix = nullptr;
   v.sbase = nullptr;

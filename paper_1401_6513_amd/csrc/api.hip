@@ -26,6 +26,7 @@ void ell_free(Ell& e) {
   dfree(e.width);
   dfree(e.rowlen);
   dfree(e.cols);
+  dfree(e.dcols);
   for (auto& v : e.val) dfree(v);
   dfree(e.val32);
   dfree(e.rsum32);
@@ -45,6 +46,9 @@ void ctx_free_build(Ctx* c) {
   dfree(c->bny);
   dfree(c->bkind);
   dfree(c->bval);
+  dfree(c->hscale);
+  dfree(c->bscale);
+  dfree(c->two_db);
   dfree(c->vip_px);
   dfree(c->vip_py);
   dfree(c->d_ew);
@@ -154,6 +158,8 @@ int vip_create(void** out, int device, void* stream) {
   c->no_canon = (nc && nc[0] == '1') ? 1 : 0;
   const char* cl = std::getenv("VIP_CNN_LAYERED");
   c->cnn_layered = (cl && cl[0] == '1') ? 1 : 0;
+  const char* nd = std::getenv("VIP_NO_DELTA");
+  c->no_delta = (nd && nd[0] == '1') ? 1 : 0;
   const char* pre = std::getenv("VIP_AMG_PRE_FINE");
   c->amg_pre_fine = (pre && pre[0] == '0') ? 0 : 1;
   if (const char* g = std::getenv("VIP_AMG_GAMMA")) c->amg_gamma = std::min(2.0, std::max(0.5, std::atof(g)));
@@ -184,6 +190,7 @@ int vip_destroy(void* p) {
   (void)hipStreamSynchronize(c->stream);
   vip::ctx_free_build(c);
   vip::learn_free(c);
+  vip::forces_free(c);
   vip::dfree(c->partials);
   vip::dfree(c->sc);
   if (c->sc_host) (void)hipHostFree(c->sc_host);
@@ -226,6 +233,35 @@ int vip_build_stencils(void* p, const double* nodes_xy, int64_t n_nodes, const i
                                basis_order, support_radius, h, opt);
   if (rc != VIP_OK) c->built = false;
   return rc;
+}
+
+int vip_build_stencils_adaptive(void* p, const double* nodes_xy, int64_t n_nodes, const int64_t* bnd_idx,
+                                const double* bnd_normal, const int32_t* bnd_kind, const double* bnd_value,
+                                int64_t n_bnd, int basis_order, double support_radius, double h,
+                                const double* h_node, const vip_options* opt) {
+  Ctx* c = vip::as_ctx(p);
+  if (!c) return VIP_E_INVALID;
+  if (!h_node) return vip::set_error(c, VIP_E_INVALID, "h_node is NULL");
+  VIP_TRY(vip::bind_device(c));
+  int rc = vip::build_stencils(c, nodes_xy, n_nodes, bnd_idx, bnd_normal, bnd_kind, bnd_value, n_bnd,
+                               basis_order, support_radius, h, opt, h_node);
+  if (rc != VIP_OK) c->built = false;
+  return rc;
+}
+
+int vip_column_bytes(void* p, int* sys_bytes, int* amg_levels, int* amg_levels_delta) {
+  Ctx* c = vip::as_ctx(p);
+  VIP_TRY(vip::need_built(c));
+  if (sys_bytes) *sys_bytes = c->sys.dcols ? 2 : 4;
+  int nl = 0, nd = 0;
+  for (size_t l = 1; l < c->amg.lv.size(); ++l) {
+    if (c->amg.lv[l].A.nrows == 0) continue;
+    ++nl;
+    nd += c->amg.lv[l].A.dcols ? 1 : 0;
+  }
+  if (amg_levels) *amg_levels = nl;
+  if (amg_levels_delta) *amg_levels_delta = nd;
+  return VIP_OK;
 }
 
 int vip_set_options(void* p, const vip_options* opt) {

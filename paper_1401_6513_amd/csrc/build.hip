@@ -209,11 +209,14 @@ int scan_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n, int64_t* total_
 // node when they fall outside it (the paper leaves near-boundary VIPs open).
 __global__ void k_vip_points(Grid g, const double* x, const double* y, int64_t n,
                              const int32_t* bpos, const double* bnx, const double* bny,
-                             double off, double rho0, double* px, double* py, double* dew,
-                             double* dns) {
+                             double off0, double rho00, const double* scale, double* px, double* py,
+                             double* dew, double* dns) {
 #pragma clang fp contract(off)
   int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
+  // offset and support radius of this node (scaled by its local spacing on adaptive sets)
+  const double off = scale ? off0 * scale[i] : off0;
+  const double rho0 = scale ? rho00 * scale[i] : rho00;
   const double dirx[4] = {1.0, -1.0, 0.0, 0.0};
   const double diry[4] = {0.0, 0.0, 1.0, -1.0};
   const double xi = x[i], yi = y[i];
@@ -278,12 +281,13 @@ __global__ void k_vip_points(Grid g, const double* x, const double* y, int64_t n
 }
 
 __global__ void k_normal_points(const double* x, const double* y, const int64_t* bidx,
-                                const double* bnx, const double* bny, int64_t nb, double d,
-                                double* px1, double* py1, double* px2, double* py2) {
+                                const double* bnx, const double* bny, int64_t nb, double d0,
+                                const double* bscale, double* px1, double* py1, double* px2, double* py2) {
 #pragma clang fp contract(off)
   int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (k >= nb) return;
   const int64_t b = bidx[k];
+  const double d = bscale ? d0 * bscale[k] : d0;
   px1[k] = x[b] - 1.0 * d * bnx[k];
   py1[k] = y[b] - 1.0 * d * bny[k];
   px2[k] = x[b] - 2.0 * d * bnx[k];
@@ -297,6 +301,8 @@ struct Family {
   const double* px;     // point coordinates per row
   const double* py;
   const int32_t* bpos;  // non-null: rows with bpos >= 0 are inactive (VIP families)
+  const double* scale;  // non-null: the row's support radius is rho0 * scale[row] (local spacing
+                        // of the node the point belongs to over the reference spacing)
 };
 
 __global__ void k_count(Grid g, const double* x, const double* y, Family f, double rho0,
@@ -310,7 +316,7 @@ __global__ void k_count(Grid g, const double* x, const double* y, Family f, doub
     return;
   }
   const double qx = f.px[r], qy = f.py[r];
-  double R = rho0;
+  double R = f.scale ? rho0 * f.scale[r] : rho0;
   int cnt = 0;
   for (int grow = 0; grow <= 2; ++grow) {
     cnt = 0;
@@ -407,6 +413,55 @@ int ell_layout(Ctx* c, Ell& e) {
   for (int32_t v : w) e.max_width = std::max<int64_t>(e.max_width, v);
   e.nnz = 0;
   for (int32_t v : rl) e.nnz += v;
+  return VIP_OK;
+}
+
+// ---- row-relative int16 columns ------------------------------------------------------------------
+
+// dcols of every slot of the lanes [0, nlanes): col - row for stored entries, 0 in padding; a
+// column farther than 32767 from its row sets *bad
+__global__ void k_deltas(const int64_t* ptr, const int32_t* width, const int32_t* rowlen, const int32_t* cols,
+                         int64_t nrows, int64_t nlanes, int16_t* dcols, int* bad) {
+  const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (r >= nlanes) return;
+  const int64_t s = r / kSlice, l = r % kSlice;
+  const int32_t len = r < nrows ? rowlen[r] : 0;
+  for (int32_t k = 0; k < width[s]; ++k) {
+    const int64_t q = ptr[s] + static_cast<int64_t>(k) * kSlice + l;
+    int64_t d = 0;
+    if (k < len) {
+      d = static_cast<int64_t>(cols[q]) - r;
+      if (d < -32767 || d > 32767) {
+        *bad = 1;   // every writer stores the same value
+        d = 0;
+      }
+    }
+    dcols[q] = static_cast<int16_t>(d);
+  }
+}
+
+int ell_deltas(Ctx* c, Ell& e) {
+  dfree(e.dcols);
+  if (c->no_delta || e.nrows == 0 || e.nnz_slots == 0) return VIP_OK;
+  int* bad = nullptr;
+  VIP_TRY(dalloc(c, &bad, 1));
+  VIP_TRY(dalloc(c, &e.dcols, e.nnz_slots));
+  hipStream_t st = c->stream;
+  int hb = 0;
+  hipError_t err = hipMemsetAsync(bad, 0, sizeof(int), st);
+  if (err == hipSuccess) {
+    k_deltas<<<grid_for(e.nslices * kSlice), kBlock, 0, st>>>(e.ptr, e.width, e.rowlen, e.cols, e.nrows,
+                                                              e.nslices * kSlice, e.dcols, bad);
+    err = hipGetLastError();
+  }
+  if (err == hipSuccess) err = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (err == hipSuccess) err = hipStreamSynchronize(st);
+  dfree(bad);
+  if (err != hipSuccess) {
+    dfree(e.dcols);
+    return set_error(c, VIP_E_HIP, std::string("row-relative columns: ") + hipGetErrorString(err));
+  }
+  if (hb) dfree(e.dcols);   // some column is too far from its row: keep the int32 stream only
   return VIP_OK;
 }
 
@@ -790,7 +845,7 @@ int build_family(Ctx* c, const Grid& g, const Family& f, Ell& e, int mode, const
 
 int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, const double* bnrm,
                    const int32_t* bkind, const double* bval, int64_t nb, int basis_order, double rho,
-                   double h, const vip_options* opt) {
+                   double h, const vip_options* opt, const double* h_node) {
   vip_options o;
   vip_default_options(&o);
   if (opt) o = *opt;
@@ -814,6 +869,21 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   if (px && (o.period[0] <= 2.0 * rmax || o.period[1] <= 2.0 * rmax))
     return set_error(c, VIP_E_INVALID, "periodic box shorter than twice the largest support");
   if (px && nb > 0) return set_error(c, VIP_E_INVALID, "a periodic box has no boundary nodes");
+
+  // local spacing of adaptive node sets, as a scale over h
+  std::vector<double> hscale, hbscale;
+  double smax = 1.0;
+  if (h_node) {
+    hscale.resize(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) {
+      if (!(h_node[i] > 0.0) || !std::isfinite(h_node[i]))
+        return set_error(c, VIP_E_INVALID, "h_node must be finite and > 0 (node " + std::to_string(i) + ")");
+      hscale[i] = h_node[i] / h;
+      smax = std::max(smax, hscale[i]);
+    }
+  }
+  if (px && h_node && (o.period[0] <= 2.0 * rmax * smax || o.period[1] <= 2.0 * rmax * smax))
+    return set_error(c, VIP_E_INVALID, "periodic box shorter than twice the largest support");
 
   // split coordinates, validate, bounding box
   std::vector<double> hx(static_cast<size_t>(n)), hy(static_cast<size_t>(n));
@@ -860,12 +930,32 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   c->periodic = px;
   bool has_outlet = false;
   c->h_bkind.assign(bkind, bkind + nb);
+  c->h_bpos.assign(n, -1);
+  for (int64_t k = 0; k < nb; ++k) c->h_bpos[bidx[k]] = static_cast<int32_t>(k);
   for (int64_t k = 0; k < nb; ++k) has_outlet |= bkind[k] == VIP_BC_OUTLET;
   c->singular = px || !has_outlet;
 
   hipStream_t st = c->stream;
   VIP_TRY(dalloc(c, &c->x, n));
   VIP_TRY(dalloc(c, &c->y, n));
+  if (h_node) {
+    // per-node and per-boundary-entry spacing scales, and the Neumann-row scale 2 d_b
+    hbscale.resize(static_cast<size_t>(nb));
+    std::vector<double> h2d(static_cast<size_t>(nb));
+    for (int64_t k = 0; k < nb; ++k) {
+      hbscale[k] = hscale[bidx[k]];
+      h2d[k] = 2.0 * o.vip_offset * h * hbscale[k];
+    }
+    VIP_TRY(dalloc(c, &c->hscale, n));
+    VIP_TRY(dalloc(c, &c->bscale, nb));
+    VIP_TRY(dalloc(c, &c->two_db, nb));
+    VIP_HIP_TRY(c, hipMemcpyAsync(c->hscale, hscale.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    if (nb > 0) {
+      VIP_HIP_TRY(c, hipMemcpyAsync(c->bscale, hbscale.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+      VIP_HIP_TRY(c, hipMemcpyAsync(c->two_db, h2d.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+    }
+    VIP_HIP_TRY(c, hipStreamSynchronize(st));   // the host vectors go out of scope
+  }
   VIP_TRY(dalloc(c, &c->bpos, n));
   VIP_TRY(dalloc(c, &c->bidx, nb));
   VIP_TRY(dalloc(c, &c->bnx, nb));
@@ -930,7 +1020,7 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   VIP_TRY(dalloc(c, &c->d_ew, n));
   VIP_TRY(dalloc(c, &c->d_ns, n));
   k_vip_points<<<grid_for(n), kBlock, 0, st>>>(g, c->x, c->y, n, c->bpos, c->bnx, c->bny, off, rho,
-                                                c->vip_px, c->vip_py, c->d_ew, c->d_ns);
+                                                c->hscale, c->vip_px, c->vip_py, c->d_ew, c->d_ns);
   double *np1x = nullptr, *np1y = nullptr, *np2x = nullptr, *np2y = nullptr;
   VIP_TRY(dalloc(c, &np1x, nb));
   VIP_TRY(dalloc(c, &np1y, nb));
@@ -938,26 +1028,26 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   VIP_TRY(dalloc(c, &np2y, nb));
   if (nb > 0)
     k_normal_points<<<grid_for(nb), kBlock, 0, st>>>(c->x, c->y, c->bidx, c->bnx, c->bny, nb, off,
-                                                      np1x, np1y, np2x, np2y);
+                                                      c->bscale, np1x, np1y, np2x, np2y);
 
   unsigned long long* fail = nullptr;
   VIP_TRY(dalloc(c, &fail, 2));
   int rc = VIP_OK;
   {
-    Family f{n, c->x, c->y, nullptr};
+    Family f{n, c->x, c->y, nullptr, c->hscale};
     rc = build_family(c, g, f, c->node, 1, "node", fail);
   }
   const char* vname[4] = {"east VIP", "west VIP", "north VIP", "south VIP"};
   for (int k = 0; k < 4 && rc == VIP_OK; ++k) {
-    Family f{n, c->vip_px + k * n, c->vip_py + k * n, c->bpos};
+    Family f{n, c->vip_px + k * n, c->vip_py + k * n, c->bpos, c->hscale};
     rc = build_family(c, g, f, c->vipop[k], 0, vname[k], fail);
   }
   if (rc == VIP_OK) {
-    Family f{nb, np1x, np1y, nullptr};
+    Family f{nb, np1x, np1y, nullptr, c->bscale};
     rc = build_family(c, g, f, c->normal[0], 0, "inner normal point (d)", fail);
   }
   if (rc == VIP_OK) {
-    Family f{nb, np2x, np2y, nullptr};
+    Family f{nb, np2x, np2y, nullptr, c->bscale};
     rc = build_family(c, g, f, c->normal[1], 0, "inner normal point (2d)", fail);
   }
   dfree(cell_of);
@@ -994,6 +1084,7 @@ int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, con
   k_to_f32<<<grid_for(s.nnz_slots), kBlock, 0, st>>>(s.nnz_slots, s.val[0], s.val32);
   VIP_TRY(dalloc(c, &s.rsum32, n));
   launch_rowsum32(st, n, s.ptr, s.rowlen, s.val[0], s.rsum32);
+  VIP_TRY(ell_deltas(c, s));
   for (int v = 0; v < 3; ++v) VIP_TRY(dalloc(c, &c->dinv[v], n + 1));
   VIP_TRY(dalloc(c, &c->dinv32, n + 1));
   k_diag_inv<<<grid_for(n), kBlock, 0, st>>>(n, s.ptr, s.cols, s.rowlen, s.val[0], c->dinv[0]);

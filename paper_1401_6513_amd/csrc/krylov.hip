@@ -159,7 +159,14 @@ struct Mat {
   float crsum[2];
   TileView tv;             // tile partition of the systems' canonical rows (tile.h), if any
   int tile_general;        // 1: tile rows also take the row-by-row path (canonical rows off)
+  const int16_t* dcols;    // row-relative columns (Ell::dcols), or null: read cols
 };
+
+// column of slot q of row i: from the 2-byte row-relative stream when there is one
+template <typename VT>
+__device__ __forceinline__ int32_t col_at(const Mat<VT>& A, int64_t i, int64_t q) {
+  return A.dcols ? static_cast<int32_t>(i) + static_cast<int32_t>(A.dcols[q]) : A.cols[q];
+}
 
 // Every system a kernel will touch has its values (and, in FP32, its row sums).
 template <typename VT>
@@ -184,6 +191,7 @@ void attach_canon(const Ctx* c, Mat<VT>& A, int vs0, int vs1) {
                 : (vs0 == 5 && vs1 == 6) ? 3 : -1;
   A.tv = key >= 0 ? tile_view(c, cn.tpart[key]) : TileView();
   A.tile_general = c->no_canon ? 1 : 0;
+  A.dcols = c->sys.dcols;
   if (c->no_canon || cn.K == 0) return;
   const int vs[2] = {vs0, vs1};
   for (int s = 0; s < 2; ++s) {
@@ -343,8 +351,8 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
     int k = 0;
     for (; k + 4 <= w; k += 4) {
       const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      const int32_t c0 = A.cols[q], c1 = A.cols[q + kSlice], c2 = A.cols[q + 2 * kSlice],
-                    c3 = A.cols[q + 3 * kSlice];
+      const int32_t c0 = col_at(A, i, q), c1 = col_at(A, i, q + kSlice), c2 = col_at(A, i, q + 2 * kSlice),
+                    c3 = col_at(A, i, q + 3 * kSlice);
       const float v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
       const float x0 = static_cast<float>(x[c0]), x1 = static_cast<float>(x[c1]),
                   x2 = static_cast<float>(x[c2]), x3 = static_cast<float>(x[c3]);
@@ -355,7 +363,7 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
     }
     for (; k < w; ++k) {
       const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      a0 = fmaf(static_cast<float>(vals[q]), static_cast<float>(x[A.cols[q]]) - xi, a0);
+      a0 = fmaf(static_cast<float>(vals[q]), static_cast<float>(x[col_at(A, i, q)]) - xi, a0);
     }
     return static_cast<double>(a0 + a1) + static_cast<double>(A.rsum[sys][i] * xi);
   } else {
@@ -363,8 +371,8 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
     int k = 0;
     for (; k + 4 <= w; k += 4) {
       const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      const int32_t c0 = A.cols[q], c1 = A.cols[q + kSlice], c2 = A.cols[q + 2 * kSlice],
-                    c3 = A.cols[q + 3 * kSlice];
+      const int32_t c0 = col_at(A, i, q), c1 = col_at(A, i, q + kSlice), c2 = col_at(A, i, q + 2 * kSlice),
+                    c3 = col_at(A, i, q + 3 * kSlice);
       const double v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
       const double x0 = static_cast<double>(x[c0]), x1 = static_cast<double>(x[c1]),
                    x2 = static_cast<double>(x[c2]), x3 = static_cast<double>(x[c3]);
@@ -375,7 +383,7 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
     }
     for (; k < w; ++k) {
       const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      a0 = fma(static_cast<double>(vals[q]), static_cast<double>(x[A.cols[q]]), a0);
+      a0 = fma(static_cast<double>(vals[q]), static_cast<double>(x[col_at(A, i, q)]), a0);
     }
     return a0 + a1;
   }
@@ -1535,6 +1543,8 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   Mat<double> A64{n, border ? 1 : 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}, {nullptr, nullptr}};
   attach_canon(c, A64, 0, -1);
   int total_it = 0, outer = 0;
+  int lpc_used = 0;
+  double lpc_gain = 1.0;
   double relres = 0.0;
   const int maxit = c->opt.max_iters;
   bool converged = false;
@@ -1582,6 +1592,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
     constexpr int kInnerCap = 150;
     const double inner = std::max(c->opt.inner_tol, 1e-7);
     double prev = 0.0;
+    const bool lpc = !border && !project && learn_precond_active(c);
     for (outer = 1; outer <= 200; ++outer) {
       // FP64 residual of the current FP64 iterate, cast into the inner right-hand side
       VIP_TRY((residual<double, double, float, 1>(c, A64, x, b, V.r, stride)));
@@ -1615,7 +1626,14 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
         fallback = true;   // x is unchanged: the broken correction is not added
         break;
       }
-      k_add_f32<<<gv, kBlock, 0, s>>>(nvec, x, d32);
+      if (lpc) {
+        // the pass residual in V.r was overwritten by the inner solve: recompute it (FP32 copy
+        // of the FP64 residual of x) for the network's input
+        VIP_TRY((residual<double, double, float, 1>(c, A64, x, b, V.r, stride)));
+        VIP_TRY(learn_precond_pass(c, V.r, b, d32, x, &lpc_used, &lpc_gain));
+      } else {
+        k_add_f32<<<gv, kBlock, 0, s>>>(nvec, x, d32);
+      }
     }
     if (fallback) VIP_TRY(fp64_passes());
   }
@@ -1643,6 +1661,8 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
     st->krylov_used = m == kCG ? VIP_K_PCG : VIP_K_BICGSTAB;
     st->border_lambda = lam;
     st->poisson_fp64_fallback = fallback ? 1 : 0;
+    st->learned_pc_passes = lpc_used;
+    st->learned_pc_ratio = lpc_gain;
   }
   if (!std::isfinite(relres)) return set_error(c, VIP_E_NONFINITE, "non-finite Poisson residual");
   if (!converged)

@@ -738,6 +738,19 @@ __global__ void k_sub(int64_t n, const double* b, const double* a, double* r) {
   r[i] = b[i] - a[i];
 }
 
+__global__ void k_f2d(int64_t n, const float* a, double* b) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  b[i] = static_cast<double>(a[i]);
+}
+
+// x += alpha d + beta c (c may be null)
+__global__ void k_add2(int64_t n, double* x, const double* d, const double* cv, double alpha, double beta) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  x[i] += alpha * d[i] + (cv ? beta * cv[i] : 0.0);
+}
+
 __global__ void k_copy_d(int64_t n, const double* a, double* b) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
@@ -892,7 +905,9 @@ void learn_clear(Ctx* c) {
 
 void learn_free_nodeset(Ctx* c) {
   Learn& L = c->learn;
-  for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2, &L.scal}) dfree(*p);
+  for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2, &L.scal, &L.pc_r, &L.pc_d, &L.pc_c,
+                     &L.pc_q1, &L.pc_q2, &L.pc_scal})
+    dfree(*p);
   L.have_eprev = false;
 }
 
@@ -1162,8 +1177,11 @@ int lattice_rms(Ctx* c, const double* a, const double* cv) {
 int ensure_vectors(Ctx* c) {
   Learn& L = c->learn;
   if (L.r) return VIP_OK;
-  for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2}) VIP_TRY(dalloc(c, p, c->n));
+  for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2, &L.pc_r, &L.pc_d, &L.pc_c,
+                     &L.pc_q1, &L.pc_q2})
+    VIP_TRY(dalloc(c, p, c->n));
   VIP_TRY(dalloc(c, &L.scal, kScalHead + 6 * kRedBlocks));
+  VIP_TRY(dalloc(c, &L.pc_scal, kScalHead + 6 * kRedBlocks));
   return VIP_OK;
 }
 
@@ -1375,6 +1393,69 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
     stats->warm_alpha = accept ? alpha : 0.0;
     stats->warm_beta = accept ? beta : 0.0;
   }
+  return VIP_OK;
+}
+
+bool learn_precond_active(Ctx* c) {
+  if (!c->opt.learned_precond || c->opt.warmstart != VIP_WS_LEARNED || c->opt.precision != VIP_P_MIXED) return false;
+  if (c->singular || !learn_ready(c) || !c->lat.ok) return false;
+  return true;
+}
+
+// One flexible refinement pass with the network as a second preconditioner: c = the network's
+// correction of the pass residual r (the image of r h^2 / s, b h^2 / rms(b h^2) and the lattice
+// mask, as for the start vector: the network approximates L^-1 on a residual), then
+// x += alpha d + beta c with (alpha, beta) minimising ||r - alpha L d - beta L c||_2; if the
+// network's direction does not beat the best multiple of d alone, x += d.
+int learn_precond_pass(Ctx* c, const float* r32, const double* b, const float* d32, double* x, int* used,
+                       double* gain) {
+  Learn& L = c->learn;
+  VIP_TRY(ensure_vectors(c));
+  Net* N = net_of(c);
+  hipStream_t st = c->stream;
+  const int64_t n = c->n;
+  const double h2 = c->h * c->h;
+  const int64_t npix = static_cast<int64_t>(c->lat.W) * c->lat.H;
+  const Img g{1, c->lat.H, c->lat.W};
+  k_f2d<<<blocks_for(n), kBlock, 0, st>>>(n, r32, L.pc_r);
+  k_f2d<<<blocks_for(n), kBlock, 0, st>>>(n, d32, L.pc_d);
+  k_rms_part<<<kRedBlocks, 256, 0, st>>>(n, c->lat.pix, L.pc_r, b, h2, L.pc_scal + kScalHead);
+  k_rms_finish<<<1, 256, 0, st>>>(kRedBlocks, L.pc_scal + kScalHead, L.pc_scal);
+  VIP_TRY(infer_buffers(c, npix));
+  k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.pc_r, b, L.pc_scal, h2, N->ix);
+  VIP_TRY(forward_fused(c, g, true));
+  k_direction<<<blocks_for(n), kBlock, 0, st>>>(n, c->lat.pix, N->iy, L.pc_scal, h2, L.pc_c);
+  VIP_TRY(pressure_apply(c, L.pc_d, L.pc_q1));
+  VIP_TRY(pressure_apply(c, L.pc_c, L.pc_q2));
+  k_dots6_part<<<kRedBlocks, 256, 0, st>>>(n, L.pc_q1, L.pc_q2, L.pc_r, L.pc_scal + kScalHead);
+  k_dots6_finish<<<1, 256, 0, st>>>(kRedBlocks, L.pc_scal + kScalHead, L.pc_scal);
+  VIP_HIP_TRY(c, hipGetLastError());
+  double sv[8];
+  VIP_HIP_TRY(c, hipMemcpyAsync(sv, L.pc_scal, sizeof(sv), hipMemcpyDeviceToHost, st));
+  VIP_HIP_TRY(c, hipStreamSynchronize(st));
+  harvest_conv_timing(c);
+  const double a11 = sv[2], a12 = sv[3], a22 = sv[4], g1 = sv[5], g2 = sv[6], rr = sv[7];
+  double alpha = 1.0, beta = 0.0;
+  bool take = false;
+  const double det = a11 * a22 - a12 * a12;
+  if (a11 > 0.0 && a22 > 0.0 && rr > 0.0 && det > 1e-10 * a11 * a22) {
+    const double al = (g1 * a22 - g2 * a12) / det, be = (a11 * g2 - a12 * g1) / det;
+    const double r2 = (rr - al * g1 - be * g2) / rr;    // with the network's direction
+    const double r1 = (rr - g1 * g1 / a11) / rr;         // best multiple of d alone
+    if (std::isfinite(al) && std::isfinite(be) && r2 < r1 && r1 > 0.0) {
+      alpha = al;
+      beta = be;
+      take = true;
+      if (gain) *gain *= std::sqrt(std::max(r2, 0.0) / r1);
+    }
+  }
+  if (take) {
+    k_add2<<<blocks_for(n), kBlock, 0, st>>>(n, x, L.pc_d, L.pc_c, alpha, beta);
+    if (used) ++*used;
+  } else {
+    k_add2<<<blocks_for(n), kBlock, 0, st>>>(n, x, L.pc_d, nullptr, 1.0, 0.0);
+  }
+  VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;
 }
 

@@ -190,6 +190,7 @@ struct Bnd {
   const double* ny;
   const double* val;   // [nb][2]
   double two_d;        // 2 * vip_offset * h (scale of the Neumann rows)
+  const double* two_db;  // per boundary entry 2 vip_offset h_b on adaptive node sets, else null
 };
 
 template <class R>
@@ -225,7 +226,7 @@ __global__ void k_predictor_rhs(int64_t n, Op m00, Op lap, const int32_t* rowlen
     const bool normal_is_y = fabs(B.ny[k]) >= fabs(B.nx[k]);
     const bool u_held = kind == VIP_BC_DIRICHLET || (kind == VIP_BC_SLIP && !normal_is_y);
     const bool v_held = kind == VIP_BC_DIRICHLET || (kind == VIP_BC_SLIP && normal_is_y);
-    const double out = kind == VIP_BC_OUTLET ? B.two_d * re * p[i] : 0.0;
+    const double out = kind == VIP_BC_OUTLET ? (B.two_db ? B.two_db[k] : B.two_d) * re * p[i] : 0.0;
     ru[i] = u_held ? B.val[2 * k] : out * B.nx[k];
     rv[i] = v_held ? B.val[2 * k + 1] : out * B.ny[k];
     return;
@@ -380,7 +381,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   const Vips V = vips_of(c);
   const Op m00{c->node.ptr, c->node.cols, c->node.val[0]};
   const Op lap{c->node.ptr, c->node.cols, c->node.val[1]};
-  const Bnd B{c->bpos, c->bkind, c->bnx, c->bny, c->bval, 2.0 * c->opt.vip_offset * c->h};
+  const Bnd B{c->bpos, c->bkind, c->bnx, c->bny, c->bval, 2.0 * c->opt.vip_offset * c->h, c->two_db};
   const VC C = vc_of(c);
   k_predictor_rhs<<<grid_for(n), kBlock, 0, s>>>(n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
                                                   c->have_prev_n ? 0 : 1, dt, re,

@@ -114,6 +114,10 @@ struct Ell {
   int64_t max_width = 0;
   int64_t nnz = 0;                  // sum of row lengths
   Canon canon;                      // lattice-interior rows (system layout only)
+  // row-relative columns: dcols[q] = cols[q] - row (0 in padding slots), when every stored
+  // column of the matrix lies within +-32767 of its row; the solve-phase kernels then read 2
+  // bytes per entry instead of 4.  Null when some column does not fit (or VIP_NO_DELTA=1).
+  int16_t* dcols = nullptr;
 };
 
 // The 21-point lattice disk of radius 2.5h in slot order (rows dy = -2..2, dx ascending):
@@ -264,6 +268,14 @@ struct Learn {
   double* q2 = nullptr;       // device [n]: L c
   double* scal = nullptr;     // device [16 + 6*256]: [0] rms(rx h^2), [1] rms(b h^2), [2..7] the dots
                               // q1.q1, q1.q2, q2.q2, q1.r, q2.r, r.r, then block partials
+  // learned preconditioning of the refinement passes: pass residual, inner correction d, the
+  // network's correction c, L d, L c (device [n]) and their scalars (as scal)
+  double* pc_r = nullptr;
+  double* pc_d = nullptr;
+  double* pc_c = nullptr;
+  double* pc_q1 = nullptr;
+  double* pc_q2 = nullptr;
+  double* pc_scal = nullptr;
 };
 
 struct Ctx {
@@ -272,6 +284,7 @@ struct Ctx {
   int amg_pre_fine = 1;           // VIP_AMG_PRE_FINE=0: BiCGStab V-cycles skip the finest pre-sweep
   int no_canon = 0;               // VIP_NO_CANON=1: every row takes the general sliced-ELL path
   int cnn_layered = 0;            // VIP_CNN_LAYERED=1: learned start inference layer by layer
+  int no_delta = 0;               // VIP_NO_DELTA=1: general rows read int32 columns, not int16 deltas
   // V-cycle settings: over-correction of the piecewise-constant coarse correction (plain
   // aggregation makes the Galerkin coarse operators too stiff by about 2 for 2x2 aggregates)
   // and damped Jacobi sweeps per level; measured best on the cylinder and triangle node sets
@@ -297,7 +310,13 @@ struct Ctx {
   double* bny = nullptr;
   int32_t* bkind = nullptr;       // device [nb]
   double* bval = nullptr;         // device [nb*2]
+  // adaptive node sets (null when the spacing is uniform): each node's spacing over h, the same
+  // per boundary entry, and the scale 2 d_b = 2 vip_offset h_b of each Neumann row
+  double* hscale = nullptr;       // device [n]
+  double* bscale = nullptr;       // device [nb]
+  double* two_db = nullptr;       // device [nb]
   std::vector<int32_t> h_bkind;   // host copy
+  std::vector<int32_t> h_bpos;    // host copy of bpos
 
   // geometry
   double* vip_px = nullptr;       // device [4*n]: VIP coordinates, k*n + i
@@ -345,6 +364,11 @@ struct Ctx {
   Learn learn;
   Timing timing;                  // pressure-solve SpMV launches
   Timing conv_timing;             // MFMA layers of the learned start vector's inference
+
+  // body forces (forces.hip): surface node list and per-node traction terms
+  int64_t* fsurf = nullptr;       // device [fcap]
+  double* fbuf = nullptr;         // device [2 * fcap + 2]
+  int64_t fcap = 0;
 };
 
 // ---- error handling -----------------------------------------------------------
@@ -406,6 +430,9 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t grid) {
 
 // Allocate an Ell's slice structure from per-row lengths already in e.rowlen.
 int ell_layout(Ctx* c, Ell& e);
+// Build e.dcols (row-relative int16 columns) when every stored column fits; leaves it null
+// otherwise or when the context has deltas off.
+int ell_deltas(Ctx* c, Ell& e);
 
 // FP32 row sums of an FP64 sliced-ELL value set (for the difference-form FP32 rows).
 void launch_rowsum32(hipStream_t st, int64_t n, const int64_t* ptr, const int32_t* rowlen,
@@ -426,7 +453,7 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
                     vip_step_stats* st);
 int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, const double* bnrm,
                    const int32_t* bkind, const double* bval, int64_t nb, int basis_order, double rho,
-                   double h, const vip_options* opt);
+                   double h, const vip_options* opt, const double* h_node = nullptr);
 int assemble_helmholtz(Ctx* c, double dt, double re);
 int amg_setup(Ctx* c);
 void amg_free(Ctx* c);
@@ -482,5 +509,21 @@ int learn_init(Ctx* c, uint64_t seed);
 void learn_clear(Ctx* c);          // drop the captured snapshots
 void learn_free_nodeset(Ctx* c);   // drop what belongs to the node set (map, vectors)
 void learn_free(Ctx* c);           // everything
+// learned preconditioning of the mixed refinement passes is on for this solve (option set,
+// network ready, lattice map built, pressure system not singular)
+bool learn_precond_active(Ctx* c);
+// x += alpha d + beta c for the pass residual r32 (FP32) and inner correction d32 (see vip.h,
+// learned_precond); *used counts passes that took the network's direction, *gain multiplies in
+// its residual ratio against d alone
+int learn_precond_pass(Ctx* c, const float* r32, const double* b, const float* d32, double* x, int* used,
+                       double* gain);
+
+// Body forces (forces.hip): traction integrated over a closed chain of boundary nodes; work
+// arrays in `surf_dev` (int64 [n_surf]) and `buf` (double [2 n_surf + 2]) on the device.
+int forces(Ctx* c, const double* u, const double* v, const double* p, double re, const int64_t* surf,
+           int64_t n_surf, double* out, int64_t* surf_dev, double* buf);
+// Check a surface chain against the node set (host side); VIP_OK or VIP_E_INVALID.
+int forces_check(Ctx* c, const int64_t* surf, int64_t n_surf, double re);
+void forces_free(Ctx* c);
 
 }  // namespace vip

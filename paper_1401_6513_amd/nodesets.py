@@ -38,6 +38,8 @@ class NodeSetSpec:
     lattice_shape: tuple = None         # (ny, nx) of the background lattice, if any
     lattice_origin: tuple = None        # (x0, y0)
     n_lattice: int = 0                  # first n_lattice nodes are lattice nodes
+    surface: np.ndarray = None          # body surface nodes in order around the body, if any
+    h_node: np.ndarray = None           # local node spacing of adaptive sets (None: uniform h)
 
     @property
     def n(self):
@@ -45,9 +47,12 @@ class NodeSetSpec:
 
     def as_kwargs(self):
         """Arguments shared by the library's build call and the checker's problem."""
-        return dict(xy=self.xy, bnd_idx=self.bnd_idx, bnd_normal=self.bnd_normal,
-                    bnd_kind=self.bnd_kind, bnd_value=self.bnd_value, rho=self.rho, h=self.h,
-                    period=self.period)
+        kw = dict(xy=self.xy, bnd_idx=self.bnd_idx, bnd_normal=self.bnd_normal,
+                  bnd_kind=self.bnd_kind, bnd_value=self.bnd_value, rho=self.rho, h=self.h,
+                  period=self.period)
+        if self.h_node is not None:
+            kw["h_node"] = self.h_node
+        return kw
 
 
 def _lattice(x0, y0, nx, ny, h):
@@ -118,7 +123,7 @@ def body_radius_bumpy(theta, amp=0.05, lobes=12):
 
 
 def _body_radius_derivative(theta, shape):
-    if shape == "circle":
+    if shape in ("circle", None):
         return np.zeros_like(theta)
     amp, lobes = shape
     return 0.5 * amp * lobes * np.cos(lobes * theta)
@@ -183,7 +188,7 @@ def cylinder_channel(h, box=(-10.0, 20.0, -10.0, 10.0), shape="circle", n_surfac
                        bnd_idx=np.concatenate(b_idx).astype(np.int64),
                        bnd_normal=np.concatenate(b_nrm), bnd_kind=np.concatenate(b_kind),
                        bnd_value=np.concatenate(b_val), lattice_shape=(ny, nx),
-                       lattice_origin=(x0, y0), n_lattice=n_lat)
+                       lattice_origin=(x0, y0), n_lattice=n_lat, surface=s_ids.astype(np.int64))
 
 
 def taylor_green_initial(xy):
@@ -223,6 +228,90 @@ def jittered(spec, frac, seed):
     out.xy = xy
     out.name = spec.name + "_jit"
     return out
+
+
+def refined_cylinder_channel(h_fine, zones, box=(-10.0, 20.0, -10.0, 10.0), shape="circle",
+                             n_surface=256, u_inf=1.0, gap=0.25, support=2.5, name=None):
+    """Flow past a body on a stepwise refined node distribution (Section 5.5 places its nodes
+    in nested regions of decreasing density around the bumpy cylinder).
+
+    zones: nested boxes (x0, x1, y0, y1), finest first.  A point of the finest lattice
+    (spacing h_fine) inside zone k but no finer zone has spacing h_fine 2^k and is kept when
+    both its lattice indices are multiples of 2^k; points outside every zone have spacing
+    h_fine 2^len(zones).  The box sides must lie on the coarsest lattice.  Boundary conditions,
+    the body and its surface nodes are those of cylinder_channel (shape None: no body, a plain
+    channel).  h_node holds each node's
+    spacing (surface nodes: h_fine); the support radius of an evaluation point is
+    `support` times the spacing of the node it belongs to.
+    """
+    x0, x1, y0, y1 = box
+    L = len(zones)
+    step = h_fine * 2 ** L
+    for v, o in ((x1, x0), (y1, y0)):
+        if abs((v - o) / step - round((v - o) / step)) > 1e-9:
+            raise ValueError("box sides must lie on the coarsest lattice")
+    nx = int(round((x1 - x0) / h_fine)) + 1
+    ny = int(round((y1 - y0) / h_fine)) + 1
+    i = np.arange(nx)
+    j = np.arange(ny)
+    I = np.tile(i, ny)
+    J = np.repeat(j, nx)
+    X = x0 + I * h_fine
+    Y = y0 + J * h_fine
+    level = np.full(len(X), L, dtype=np.int64)
+    for k in range(L - 1, -1, -1):
+        zx0, zx1, zy0, zy1 = zones[k]
+        inside = (X >= zx0 - 1e-12) & (X <= zx1 + 1e-12) & (Y >= zy0 - 1e-12) & (Y <= zy1 + 1e-12)
+        level[inside] = k
+    m = 2 ** level
+    keep = (I % m == 0) & (J % m == 0)
+    if shape is None:
+        n_surface = 0
+    rfun = body_radius_circle if shape in ("circle", None) else (
+        lambda t: body_radius_bumpy(t, amp=shape[0], lobes=shape[1]))
+    if shape is not None:
+        r = np.hypot(X, Y)
+        th = np.arctan2(Y, X)
+        keep &= r >= rfun(th) + gap * h_fine
+    xy = np.stack([X[keep], Y[keep]], axis=1)
+    I, J, hn = I[keep], J[keep], h_fine * m[keep].astype(np.float64)
+    n_lat = len(xy)
+    side_inlet = I == 0
+    side_outlet = I == nx - 1
+    side_bottom = (J == 0) & ~side_inlet & ~side_outlet
+    side_top = (J == ny - 1) & ~side_inlet & ~side_outlet
+    b_idx, b_nrm, b_kind, b_val = [], [], [], []
+    for mask, nrm, kind, val in ((side_inlet, (-1.0, 0.0), DIRICHLET, (u_inf, 0.0)),
+                                 (side_outlet, (1.0, 0.0), OUTLET, (0.0, 0.0)),
+                                 (side_bottom, (0.0, -1.0), SLIP, (0.0, 0.0)),
+                                 (side_top, (0.0, 1.0), SLIP, (0.0, 0.0))):
+        ids = np.flatnonzero(mask)
+        b_idx.append(ids)
+        b_nrm.append(np.tile(nrm, (len(ids), 1)))
+        b_kind.append(np.full(len(ids), kind, np.int32))
+        b_val.append(np.tile(val, (len(ids), 1)))
+    theta = 2.0 * math.pi * np.arange(n_surface) / n_surface
+    rs = rfun(theta)
+    sxy = np.stack([rs * np.cos(theta), rs * np.sin(theta)], axis=1)
+    drs = _body_radius_derivative(theta, shape)
+    er = np.stack([np.cos(theta), np.sin(theta)], axis=1)
+    et = np.stack([-np.sin(theta), np.cos(theta)], axis=1)
+    g = er - (drs / rs)[:, None] * et
+    snrm = -g / np.linalg.norm(g, axis=1)[:, None]
+    s_ids = n_lat + np.arange(n_surface)
+    b_idx.append(s_ids)
+    b_nrm.append(snrm)
+    b_kind.append(np.full(n_surface, DIRICHLET, np.int32))
+    b_val.append(np.zeros((n_surface, 2)))
+    xy = np.concatenate([xy, sxy])
+    hn = np.concatenate([hn, np.full(n_surface, h_fine)])
+    if name is None:
+        name = "refined_h%g_L%d" % (h_fine, L)
+    return NodeSetSpec(name=name, xy=xy, h=h_fine, rho=support * h_fine,
+                       bnd_idx=np.concatenate(b_idx).astype(np.int64),
+                       bnd_normal=np.concatenate(b_nrm), bnd_kind=np.concatenate(b_kind),
+                       bnd_value=np.concatenate(b_val), n_lattice=n_lat,
+                       surface=s_ids.astype(np.int64), h_node=hn)
 
 
 def triangle_cavity(h, lid=1.0, gap=0.25, support=2.5):

@@ -37,7 +37,7 @@ class VipOptions(ctypes.Structure):
                 ("period", ctypes.c_double * 2), ("poisson_tol", ctypes.c_double),
                 ("helmholtz_tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
                 ("max_iters", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("preconditioner", ctypes.c_int)]
+                ("preconditioner", ctypes.c_int), ("learned_precond", ctypes.c_int)]
 
 
 class VipStepStats(ctypes.Structure):
@@ -46,7 +46,8 @@ class VipStepStats(ctypes.Structure):
                 ("poisson_residual", ctypes.c_double), ("helmholtz_residual", ctypes.c_double),
                 ("border_lambda", ctypes.c_double), ("warm_start", ctypes.c_int),
                 ("warm_ratio", ctypes.c_double), ("warm_alpha", ctypes.c_double),
-                ("warm_beta", ctypes.c_double), ("poisson_fp64_fallback", ctypes.c_int)]
+                ("warm_beta", ctypes.c_double), ("poisson_fp64_fallback", ctypes.c_int),
+                ("learned_pc_passes", ctypes.c_int), ("learned_pc_ratio", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -72,6 +73,8 @@ SIGNATURES = {
     "vip_last_error": (ctypes.c_char_p, [_P]),
     "vip_build_stencils": (_INT, [_P, _P, _I64, _P, _P, _P, _P, _I64, _INT, _D, _D,
                                   ctypes.POINTER(VipOptions)]),
+    "vip_build_stencils_adaptive": (_INT, [_P, _P, _I64, _P, _P, _P, _P, _I64, _INT, _D, _D, _P,
+                                           ctypes.POINTER(VipOptions)]),
     "vip_set_options": (_INT, [_P, ctypes.POINTER(VipOptions)]),
     "vip_step": (_INT, [_P, _P, _P, _P, _D, _D, ctypes.POINTER(VipStepStats)]),
     "vip_reset_history": (_INT, [_P]),
@@ -87,6 +90,9 @@ SIGNATURES = {
     "vip_gradient": (_INT, [_P, _P, _P, _P]),
     "vip_kernel_timing": (_INT, [_P, _INT, _INT, _INT, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "vip_canonical_rows": (_INT, [_P, _P, _P, ctypes.POINTER(_INT)]),
+    "vip_column_bytes": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(_INT), ctypes.POINTER(_INT)]),
+    "vip_forces": (_INT, [_P, _P, _P, _P, _D, _P, _I64, _P]),
+    "vip_spectral_peak": (_INT, [_P, _I64, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "vip_learn_n_params": (_INT, []),
     "vip_learn_init": (_INT, [_P, ctypes.c_uint64]),
     "vip_learn_set_params": (_INT, [_P, _P, _I64]),
@@ -148,6 +154,16 @@ def _dev(t, n, device):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def spectral_peak(signal, dt):
+    """(frequency, amplitude) of the periodogram peak of a sampled signal (vip_spectral_peak)."""
+    s = _host(signal, np.float64).reshape(-1)
+    f, a = _D(), _D()
+    rc = load().vip_spectral_peak(s.ctypes.data, len(s), float(dt), ctypes.byref(f), ctypes.byref(a))
+    if rc != VIP_OK:
+        raise VipError(rc, "vip_spectral_peak", "invalid signal or spacing")
+    return f.value, a.value
+
+
 class Context:
     """One library context bound to a device and a stream."""
 
@@ -189,7 +205,8 @@ class Context:
 
     # ---- C ABI calls ---------------------------------------------------------------
     def vip_build_stencils(self, xy, bnd_idx, bnd_normal, bnd_kind, bnd_value, support_radius, h,
-                           basis_order=2, options=None):
+                           basis_order=2, options=None, h_node=None):
+        """vip_build_stencils, or vip_build_stencils_adaptive when h_node is given."""
         xy = _host(xy, np.float64).reshape(-1, 2)
         bi = _host(bnd_idx, np.int64).reshape(-1)
         nb = len(bi)
@@ -197,11 +214,22 @@ class Context:
         bk = _host(bnd_kind, np.int32).reshape(nb)
         bv = _host(bnd_value, np.float64).reshape(nb, 2)
         opt = options if options is not None else default_options()
-        rc = self.lib.vip_build_stencils(self._h, xy.ctypes.data, len(xy), bi.ctypes.data,
-                                         bn.ctypes.data, bk.ctypes.data, bv.ctypes.data, nb,
-                                         int(basis_order), float(support_radius), float(h),
-                                         ctypes.byref(opt))
-        self._check(rc, "vip_build_stencils")
+        self.n = 0
+        if h_node is None:
+            rc = self.lib.vip_build_stencils(self._h, xy.ctypes.data, len(xy), bi.ctypes.data,
+                                             bn.ctypes.data, bk.ctypes.data, bv.ctypes.data, nb,
+                                             int(basis_order), float(support_radius), float(h),
+                                             ctypes.byref(opt))
+            self._check(rc, "vip_build_stencils")
+        else:
+            hn = _host(h_node, np.float64).reshape(-1)
+            if len(hn) != len(xy):
+                raise ValueError("h_node needs one spacing per node")
+            rc = self.lib.vip_build_stencils_adaptive(self._h, xy.ctypes.data, len(xy), bi.ctypes.data,
+                                                      bn.ctypes.data, bk.ctypes.data, bv.ctypes.data,
+                                                      nb, int(basis_order), float(support_radius),
+                                                      float(h), hn.ctypes.data, ctypes.byref(opt))
+            self._check(rc, "vip_build_stencils_adaptive")
         self.n = len(xy)
 
     def vip_set_options(self, options):
@@ -296,6 +324,23 @@ class Context:
             return counts, taps.value, desc
         return counts, taps.value
 
+    def vip_column_bytes(self):
+        """(bytes per stored column of the system matrices, coarse levels, coarse levels with
+        int16 row-relative columns)."""
+        a, b, d = _INT(), _INT(), _INT()
+        self._check(self.lib.vip_column_bytes(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(d)),
+                    "vip_column_bytes")
+        return a.value, b.value, d.value
+
+    # ---- body forces -------------------------------------------------------------------
+    def vip_forces(self, u, v, p, Re, surf_idx):
+        """(F_x, F_y) on the body whose surface nodes, in order around it, are surf_idx."""
+        s = _host(surf_idx, np.int64).reshape(-1)
+        f = np.empty(2)
+        self._check(self.lib.vip_forces(self._h, self._d(u), self._d(v), self._d(p), float(Re),
+                                        s.ctypes.data, len(s), f.ctypes.data), "vip_forces")
+        return f
+
     # ---- learned start vector ---------------------------------------------------------
     def vip_learn_n_params(self):
         return int(self.lib.vip_learn_n_params())
@@ -368,6 +413,7 @@ class Context:
         """Build from a nodesets.NodeSetSpec (options by keyword)."""
         opt = default_options(period=spec.period, **opts)
         self.vip_build_stencils(spec.xy, spec.bnd_idx, spec.bnd_normal, spec.bnd_kind,
-                                spec.bnd_value, spec.rho, spec.h, options=opt)
+                                spec.bnd_value, spec.rho, spec.h, options=opt,
+                                h_node=getattr(spec, "h_node", None))
         self.options = opt
         return opt

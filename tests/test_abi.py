@@ -49,12 +49,13 @@ int main(void) {
   F(vip_options, warmstart) F(vip_options, min_neighbours) F(vip_options, vip_offset)
   F(vip_options, period) F(vip_options, poisson_tol) F(vip_options, helmholtz_tol)
   F(vip_options, inner_tol) F(vip_options, max_iters) F(vip_options, check_every)
-  F(vip_options, preconditioner)
+  F(vip_options, preconditioner) F(vip_options, learned_precond)
   F(vip_step_stats, poisson_iters) F(vip_step_stats, poisson_outer) F(vip_step_stats, helmholtz_iters)
   F(vip_step_stats, krylov_used) F(vip_step_stats, poisson_residual)
   F(vip_step_stats, helmholtz_residual) F(vip_step_stats, border_lambda)
   F(vip_step_stats, warm_start) F(vip_step_stats, warm_ratio) F(vip_step_stats, warm_alpha) F(vip_step_stats, warm_beta)
-  F(vip_step_stats, poisson_fp64_fallback)
+  F(vip_step_stats, poisson_fp64_fallback) F(vip_step_stats, learned_pc_passes)
+  F(vip_step_stats, learned_pc_ratio)
   return 0;
 }
 """

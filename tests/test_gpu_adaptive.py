@@ -1,0 +1,174 @@
+"""Parity on stepwise refined node sets with a support radius that follows the local spacing
+(rho(xbar), Section 3; the refined distributions of Section 5.5), through the C ABI: geometry,
+every operator row, pressure solves, fractional steps in FP64 and mixed precision, and the body
+force, against the oracle.  The rows of such sets take the general sliced-ELL path."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import forces, operators, step
+from paper_1401_6513_amd import nodesets as ns
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ZONES = [(-1.5, 3.0, -1.5, 1.5), (-2.5, 5.0, -2.5, 2.5)]
+
+
+def _vip():
+    from paper_1401_6513_amd import vip
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return vip
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+def _to_csr(cols, vals, ncols):
+    rows = np.repeat(np.arange(cols.shape[0]), cols.shape[1])
+    c = cols.ravel()
+    m = c >= 0
+    return sp.csr_matrix((vals.ravel()[m], (rows[m], c[m])), shape=(cols.shape[0], ncols))
+
+
+def _row_err(G, M):
+    D = abs(G - M).tocsr()
+    A = abs(M).tocsr()
+    dmax = D.max(axis=1).toarray().ravel()
+    amax = A.max(axis=1).toarray().ravel()
+    keep = amax > 0
+    assert np.all(dmax[~keep] == 0.0)
+    return float((dmax[keep] / amax[keep]).max())
+
+
+SPECS = {
+    "refined_cylinder": lambda: ns.refined_cylinder_channel(1.0 / 16, ZONES, box=(-4.0, 8.0, -4.0, 4.0),
+                                                            n_surface=64),
+    "refined_bumpy": lambda: ns.refined_cylinder_channel(1.0 / 24, ZONES, box=(-4.0, 8.0, -4.0, 4.0),
+                                                         shape=(0.05, 12), n_surface=96),
+}
+
+
+@pytest.fixture(scope="module")
+def cases():
+    vip = _vip()
+    out = {}
+    for name, make in SPECS.items():
+        spec = make()
+        ctx = vip.Context(0)
+        ctx.build_from_spec(spec, poisson_tol=1e-12)
+        ops = operators.Operators(operators.Problem(**spec.as_kwargs()))
+        out[name] = (spec, ctx, ops)
+    yield out
+    for _, ctx, _ in out.values():
+        ctx.close()
+
+
+@pytest.mark.parametrize("name", list(SPECS))
+def test_geometry_and_operators(cases, name):
+    spec, ctx, ops = cases[name]
+    vxy, dew, dns, rho = ctx.vip_get_geometry()
+    inner = ops.prob.interior
+    assert np.abs(vxy[inner] - ops.vip_xy).max() <= 1e-14
+    assert np.abs(dew - ops.d_ew).max() < 1e-15 and np.abs(dns - ops.d_ns).max() < 1e-15
+    assert np.array_equal(rho, ops.rho_node)
+    dt, re = 0.01, 100.0
+    st = step.Stepper(ops, dt, re)
+    ctx.vip_assemble(dt, re)
+    pairs = [("identity", ops.M00), ("laplacian", ops.L), ("vip_e", ops.VIP[0]), ("vip_w", ops.VIP[1]),
+             ("vip_n", ops.VIP[2]), ("vip_s", ops.VIP[3]), ("poisson", st.P), ("helm_u", st.Hu),
+             ("helm_v", st.Hv), ("normal1", ops.NB[0][ops.prob.bnd_idx]),
+             ("normal2", ops.NB[1][ops.prob.bnd_idx])]
+    for op, M in pairs:
+        cols, vals = ctx.vip_get_operator(op)
+        err = _row_err(_to_csr(cols, vals, spec.n), M)
+        assert err <= 1e-12, (name, op, err)
+
+
+@pytest.mark.parametrize("name", list(SPECS))
+@pytest.mark.parametrize("prec,pc,tol,bar", [(0, 0, 1e-12, 1e-9), (0, 1, 1e-12, 1e-9), (1, 1, 1e-8, 1e-6)],
+                         ids=["fp64-jacobi", "fp64-amg", "mixed-amg-1e-8"])
+def test_fractional_steps(cases, name, prec, pc, tol, bar):
+    vip = _vip()
+    spec, ctx, ops = cases[name]
+    dt, re, steps = 0.01, 100.0, 10
+    ctx.vip_set_options(vip.default_options(poisson_tol=tol, precision=prec, preconditioner=pc,
+                                            warmstart=vip.WS_PREV))
+    ctx.vip_reset_history()
+    st = step.Stepper(ops, dt, re)
+    u0, v0, p0 = ns.boundary_initial(spec, (1.0, 0.0))
+    u, v, p = _dev(u0), _dev(v0), _dev(p0)
+    uo, vo, po = u0, v0, p0
+    iters = []
+    for _ in range(steps):
+        s = ctx.vip_step(u, v, p, dt, re)
+        iters.append(s["poisson_iters"])
+        assert s["poisson_residual"] <= tol
+        uo, vo, po = st.step(uo, vo, po)
+    errs = [np.linalg.norm(a.cpu().numpy() - b) / np.linalg.norm(b) for a, b in ((u, uo), (v, vo), (p, po))]
+    print("%s prec %d pc %d tol %g: rel L2 u %.2e v %.2e p %.2e; Poisson iterations %s"
+          % (name, prec, pc, tol, errs[0], errs[1], errs[2], iters))
+    assert max(errs) <= bar, errs
+    F = ctx.vip_forces(u, v, p, re, spec.surface)
+    Fo = forces.body_force(ops, uo, vo, po, re, spec.surface)
+    assert abs(F[0] - Fo[0]) <= 10 * bar * abs(Fo[0]) and abs(F[1] - Fo[1]) <= 10 * bar * abs(Fo[0])
+
+
+def test_uniform_spacing_gives_the_plain_build():
+    """vip_build_stencils_adaptive with h_node = h everywhere is vip_build_stencils."""
+    vip = _vip()
+    spec = ns.cylinder_channel(0.125, box=(-2.0, 3.0, -2.0, 2.0), n_surface=24)
+    a, b = vip.Context(0), vip.Context(0)
+    try:
+        a.build_from_spec(spec)
+        opt = vip.default_options()
+        b.vip_build_stencils(spec.xy, spec.bnd_idx, spec.bnd_normal, spec.bnd_kind, spec.bnd_value,
+                             spec.rho, spec.h, options=opt, h_node=np.full(spec.n, spec.h))
+        for op in ("identity", "laplacian", "vip_e", "normal1", "poisson"):
+            ca, va = a.vip_get_operator(op)
+            cb, vb = b.vip_get_operator(op)
+            assert np.array_equal(ca, cb) and np.array_equal(va, vb), op
+        with pytest.raises(vip.VipError, match="INVALID"):
+            bad = np.full(spec.n, spec.h)
+            bad[3] = -1.0
+            b.vip_build_stencils(spec.xy, spec.bnd_idx, spec.bnd_normal, spec.bnd_kind, spec.bnd_value,
+                                 spec.rho, spec.h, options=opt, h_node=bad)
+    finally:
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_int16_columns_give_the_same_bits(prec):
+    """The general rows read row-relative int16 columns where every column fits; with
+    VIP_NO_DELTA=1 they read the int32 stream.  Steps on a refined set (every row general, the
+    multigrid's coarse levels too) give the same bits either way."""
+    import os
+    vip = _vip()
+    spec = SPECS["refined_cylinder"]()
+    out = []
+    for nodelta in (False, True):
+        if nodelta:
+            os.environ["VIP_NO_DELTA"] = "1"
+        try:
+            ctx = vip.Context(0)
+        finally:
+            os.environ.pop("VIP_NO_DELTA", None)
+        try:
+            ctx.build_from_spec(spec, precision=prec, warmstart=vip.WS_PREV)
+            st = [_dev(a) for a in ns.boundary_initial(spec, (1.0, 0.0))]
+            its = [ctx.vip_step(*st, 0.01, 100.0)["poisson_iters"] for _ in range(6)]
+            sysb, nl, nd = ctx.vip_column_bytes()
+            out.append(([a.cpu().numpy() for a in st], its, (sysb, nl, nd)))
+        finally:
+            ctx.close()
+    (fa, ia, ba), (fb, ib, bb) = out
+    print("column bytes (system, coarse levels, with deltas):", ba, bb, "iterations", ia, ib)
+    assert ba[0] == 2 and ba[2] == ba[1] and ba[1] > 0
+    assert bb[0] == 4 and bb[2] == 0
+    assert ia == ib
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)

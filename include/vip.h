@@ -382,6 +382,18 @@ int vip_gradient(void* ctx, const double* f, double* gx, double* gy);
 int vip_forces(void* ctx, const double* u, const double* v, const double* p, double Re,
                const int64_t* surf_idx, int64_t n_surf, double* force);
 
+/* vip_forces for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same arguments, kernels and
+ * result, with the surface list and the per-node traction terms in a fixed device scratch
+ * array of 1 MiB per GPU that the library holds until the process ends, instead of the
+ * context's work arrays.  It calls no hipMalloc or hipFree.  Every kernel writes the scratch
+ * entries it later reads, so nothing has to start at zero; calls that overlap on one GPU
+ * (several streams or contexts at once) share that array and race.  n_surf is limited to
+ * what fits (43680 surface nodes); larger n_surf returns VIP_E_INVALID with the limit in
+ * vip_last_error.  Other errors as vip_forces. */
+int vip_forces_noalloc(void* ctx, const double* u, const double* v, const double* p, double Re,
+                       const int64_t* surf_idx, int64_t n_surf, double* force);
+
 /* Dominant frequency of a real signal sampled at spacing dt (host [n], n >= 8): the maximum
  * of the periodogram of the mean-removed, Hann-windowed signal, located on the DFT bins
  * k / (n dt), k >= 1, then refined between the neighbouring bins by golden-section search on

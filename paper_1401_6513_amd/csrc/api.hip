@@ -173,7 +173,8 @@ int vip_create(void** out, int device, void* stream) {
   }
   if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->sc, sizeof(vip::KrylovScalars)) != hipSuccess ||
       hipHostMalloc(&c->sc_host, sizeof(vip::KrylovScalars), hipHostMallocDefault) != hipSuccess ||
-      hipMemset(c->sc, 0, sizeof(vip::KrylovScalars)) != hipSuccess) {
+      hipMemset(c->sc, 0, sizeof(vip::KrylovScalars)) != hipSuccess ||
+      vip::forces_scratch_init(c) != VIP_OK) {
     if (c->sc) (void)hipFree(c->sc);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
     delete c;

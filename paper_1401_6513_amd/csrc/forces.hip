@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "vip_internal.h"
@@ -120,6 +121,50 @@ void forces_free(Ctx* c) {
   c->fcap = 0;
 }
 
+// Work memory of vip_forces_noalloc: a file-scope device array, one copy per GPU, held until
+// the process ends.  Host code never uses its name as an address: forces_scratch_init looks
+// up each device's copy once (with that device current) and every later use goes through the
+// pointer kept for that device.
+constexpr int64_t kScratchBytes = int64_t{1} << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+// byte offset of the traction pairs behind a surface list of ns entries (256-byte aligned)
+static int64_t scratch_buf_offset(int64_t ns) { return ((8 * ns + 255) / 256) * 256; }
+
+int64_t forces_noalloc_max_surface() {
+  // largest ns with offset(ns) + 8 (2 ns + 2) <= kScratchBytes
+  int64_t lo = 0, hi = kScratchBytes / 8;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (scratch_buf_offset(mid) + 8 * (2 * mid + 2) <= kScratchBytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+int forces_scratch_init(Ctx* c) {
+  if (c->device < 0 || c->device >= kMaxDevices)
+    return set_error(c, VIP_E_INVALID, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[c->device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return set_error(c, VIP_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[c->device] = ptr;
+  }
+  c->scratch = g_scratch[c->device];
+  return VIP_OK;
+}
+
 }  // namespace vip
 
 using vip::Ctx;
@@ -142,6 +187,25 @@ int vip_forces(void* p, const double* u, const double* v, const double* pr, doub
     c->fcap = n_surf;
   }
   return vip::forces(c, u, v, pr, re, surf, n_surf, force, c->fsurf, c->fbuf);
+}
+
+int vip_forces_noalloc(void* p, const double* u, const double* v, const double* pr, double re,
+                       const int64_t* surf, int64_t n_surf, double* force) {
+  Ctx* c = static_cast<Ctx*>(p);
+  if (!c) return VIP_E_INVALID;
+  if (!c->built) return vip::set_error(c, VIP_E_NOT_BUILT, "vip_build_stencils has not succeeded");
+  if (!c->scratch) return vip::set_error(c, VIP_E_HIP, "no scratch memory on this device");
+  if (!u || !v || !pr || !force) return vip::set_error(c, VIP_E_INVALID, "NULL vector or output");
+  const int64_t cap = vip::forces_noalloc_max_surface();
+  if (n_surf > cap)
+    return vip::set_error(c, VIP_E_INVALID, "n_surf = " + std::to_string(n_surf) +
+                                                " exceeds the fixed scratch of vip_forces_noalloc (at most " +
+                                                std::to_string(cap) + " surface nodes)");
+  VIP_TRY(vip::forces_check(c, surf, n_surf, re));
+  VIP_HIP_TRY(c, hipSetDevice(c->device));
+  unsigned char* base = static_cast<unsigned char*>(c->scratch);
+  return vip::forces(c, u, v, pr, re, surf, n_surf, force, reinterpret_cast<int64_t*>(base),
+                     reinterpret_cast<double*>(base + vip::scratch_buf_offset(n_surf)));
 }
 
 // Dominant frequency of a real signal: the maximum of the Hann-windowed periodogram (mean

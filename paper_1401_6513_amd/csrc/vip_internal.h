@@ -369,6 +369,7 @@ struct Ctx {
   int64_t* fsurf = nullptr;       // device [fcap]
   double* fbuf = nullptr;         // device [2 * fcap + 2]
   int64_t fcap = 0;
+  void* scratch = nullptr;        // this device's copy of the fixed scratch of vip_forces_noalloc
 };
 
 // ---- error handling -----------------------------------------------------------
@@ -525,5 +526,8 @@ int forces(Ctx* c, const double* u, const double* v, const double* p, double re,
 // Check a surface chain against the node set (host side); VIP_OK or VIP_E_INVALID.
 int forces_check(Ctx* c, const int64_t* surf, int64_t n_surf, double re);
 void forces_free(Ctx* c);
+// Look up this device's copy of the fixed scratch array (once per device) into c->scratch.
+int forces_scratch_init(Ctx* c);
+int64_t forces_noalloc_max_surface();
 
 }  // namespace vip

@@ -92,6 +92,7 @@ SIGNATURES = {
     "vip_canonical_rows": (_INT, [_P, _P, _P, ctypes.POINTER(_INT)]),
     "vip_column_bytes": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(_INT), ctypes.POINTER(_INT)]),
     "vip_forces": (_INT, [_P, _P, _P, _P, _D, _P, _I64, _P]),
+    "vip_forces_noalloc": (_INT, [_P, _P, _P, _P, _D, _P, _I64, _P]),
     "vip_spectral_peak": (_INT, [_P, _I64, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "vip_learn_n_params": (_INT, []),
     "vip_learn_init": (_INT, [_P, ctypes.c_uint64]),
@@ -339,6 +340,15 @@ class Context:
         f = np.empty(2)
         self._check(self.lib.vip_forces(self._h, self._d(u), self._d(v), self._d(p), float(Re),
                                         s.ctypes.data, len(s), f.ctypes.data), "vip_forces")
+        return f
+
+    def vip_forces_noalloc(self, u, v, p, Re, surf_idx):
+        """vip_forces with the library's fixed device scratch (allocates nothing)."""
+        s = _host(surf_idx, np.int64).reshape(-1)
+        f = np.empty(2)
+        self._check(self.lib.vip_forces_noalloc(self._h, self._d(u), self._d(v), self._d(p),
+                                                float(Re), s.ctypes.data, len(s), f.ctypes.data),
+                    "vip_forces_noalloc")
         return f
 
     # ---- learned start vector ---------------------------------------------------------

@@ -40,19 +40,29 @@ from paper_1401_6513_amd import nodesets as ns  # noqa: E402
 
 METRIC = "node-updates/s per fractional step (Poisson to 1e-8), learned+FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
-HBM_PROFILE = os.path.join(ROOT, "profiles", "hbm_counters_pressure_spmv_cylinder_h128.md")
-# sources of the profiled SpMV kernel (hashed together, in this order)
-SPMV_SOURCES = [os.path.join(ROOT, "paper_1401_6513_amd", "csrc", f) for f in ("krylov.hip", "tile.h")]
+# committed HBM counter profiles per timed kernel, and the sources each kernel is built from
+# (hashed together, in this order)
+HBM_PROFILES = {
+    "pres_spmv": ("hbm_counters_pressure_spmv_cylinder_h128.md", ("krylov.hip", "tile.h")),
+    "pred_t": ("hbm_counters_predictor_t_cylinder_h128.md", ("krylov.hip", "tile.h")),
+    "pred_x": ("hbm_counters_predictor_x_cylinder_h128.md", ("krylov.hip",)),
+    "pred_spmv": ("hbm_counters_predictor_spmv_cylinder_h128.md", ("krylov.hip", "tile.h")),
+    "sweep0": ("hbm_counters_finest_sweep_cylinder_h128.md", ("amg.hip", "tile.h")),
+}
 
 
-def measured_traffic():
-    """Calibrated HBM bytes per SpMV launch from the committed counter profile, or None when
-    the profiled kernel source has changed since the counters were taken."""
+def measured_traffic(kernel="pres_spmv"):
+    """Calibrated HBM bytes per launch of a kernel from its committed counter profile, or None
+    when there is none or the kernel's sources have changed since the counters were taken."""
     import hashlib
+    if kernel not in HBM_PROFILES:
+        return None
+    fname, srcs = HBM_PROFILES[kernel]
     try:
-        fields = dict(line.split(": ", 1) for line in open(HBM_PROFILE).read().splitlines()
+        fields = dict(line.split(": ", 1) for line in open(os.path.join(ROOT, "profiles", fname)).read().splitlines()
                       if line.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
-        cur = hashlib.sha256(b"".join(open(f, "rb").read() for f in SPMV_SOURCES)).hexdigest()
+        cur = hashlib.sha256(b"".join(open(os.path.join(ROOT, "paper_1401_6513_amd", "csrc", f), "rb").read()
+                                      for f in srcs)).hexdigest()
         if fields.get("source_sha256", "").strip() != cur:
             return None
         return int(fields["traffic_bytes_per_launch"])
@@ -98,6 +108,59 @@ PATHS = {
 }
 
 
+# kernels timed with HIP events inside the library besides the pressure SpMV (vip_kernel_timing)
+TIMED = {2: "pred_spmv", 3: "pred_t", 4: "pred_x", 5: "sweep0", 6: "pred_rhs"}
+KERNEL_NAMES = {
+    "pres_spmv": "k_bicg_v<%s,%s,1> (pressure SpMV)",
+    "pred_spmv": "k_bicg_v<float,float,2> (predictor SpMV, both velocity systems)",
+    "pred_t": "k_bicg_t<float,float,1,*,true> (predictor t = A s with s = r - alpha v formed inside, per system)",
+    "pred_x": "k_bicg_x<float,2> (predictor iterate and residual update, both systems)",
+    "sweep0": "k_sweep<float,0> (finest-level damped Jacobi post-smoothing sweep, LDS tiles)",
+    "pred_rhs": "k_predictor_rhs (VIP convection, AB2 and the predictor right-hand side, FP64)",
+}
+
+
+def kernel_bytes(ctx, spec, fp32):
+    """Algorithmic HBM bytes of one launch of each timed kernel on the first domain.  Vectors are
+    read or written once (ideal reuse of gathered entries); canonical (tile) rows read no column
+    or value stream; irregular rows read their values, their columns (int16 row-relative or
+    int32) and, in FP32, their row sums; tiled launches read the irregular-row list and one
+    256-byte record per 64 x 16 lattice tile."""
+    n, _, nnz = ctx.vip_operator_shape("poisson")
+    counts, taps = ctx.vip_canonical_rows()
+    ne, ne16 = ctx.vip_column_bytes()[:2]
+    cb = (2.0 * ne16 + 4.0 * (ne - ne16)) / max(ne, 1)   # mean bytes per stored column
+    K = taps
+    vb = 4 if fp32 else 8
+    W = int(np.floor((spec.xy[:, 0].max() - spec.xy[:, 0].min()) / spec.h + 0.5)) + 1
+    H = int(np.floor((spec.xy[:, 1].max() - spec.xy[:, 1].min()) / spec.h + 0.5)) + 1
+    tiled = counts[4] > 0
+    rec = 256 * (-(-W // 64) * -(-H // 16)) if tiled else 0
+
+    def irregular(ncan, val_b, extra_b):
+        # values + columns of the irregular rows, their per-row extras, the irregular-row list
+        return (val_b + cb) * (nnz - K * ncan) + extra_b * (n - ncan) + (4 * (n - ncan) if tiled else 0)
+
+    nc = {k: int(counts[k]) for k in range(7)}
+    out = {}
+    out["pres_spmv"] = 3 * vb * n + irregular(nc[4] if fp32 else nc[0], vb, 4 if fp32 else 0) + rec
+    # predictor (FP32 matrices H D^-1 with their row sums), systems u and v
+    out["pred_spmv"] = 2 * 3 * 4 * n + irregular(nc[5], 4, 4) + irregular(nc[6], 4, 4) + rec
+    out["pred_t"] = 4 * 4 * n + (irregular(nc[5], 4, 4) + irregular(nc[6], 4, 4)) / 2 + rec
+    out["pred_x"] = 2 * 7 * 4 * n
+    # finest level: y, b in, out written; irregular rows add values, columns, row sum, damped diagonal
+    out["sweep0"] = 3 * 4 * n + irregular(nc[4], 4, 8) + rec
+    # u, v in; the AB2 history in and out (2 vectors each way); r_u, r_v out; VIP spacings d_ew,
+    # d_ns; the canonical-node pixel; the lattice map once; general nodes read their four VIP rows
+    # and the node rows (D^[0,0] and Laplacian values, shared columns) from the ELL
+    vip_nnz = sum(ctx.vip_operator_shape(o)[2] for o in ("vip_e", "vip_w", "vip_n", "vip_s"))
+    node_nnz = ctx.vip_operator_shape("identity")[2]
+    frac_gen = (n - nc[3]) / max(n, 1)
+    out["pred_rhs"] = (10 * 8 * n + 4 * n + (4 * W * H if nc[3] > 0 else 0)
+                       + frac_gen * (vip_nnz * 12 + node_nnz * 20))
+    return out
+
+
 def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol, pool=None,
              helmholtz_tol=None, learned_precond=False):
     """Run `steps` timed steps of every domain (domains in parallel host threads, one HIP stream
@@ -123,8 +186,8 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
         log("%s warmup step %d done" % (path, w + 1))
     torch.cuda.synchronize()
     if time_spmv:
-        ctxs[0].vip_kernel_timing(enable=True, reset=True)
-        ctxs[0].vip_kernel_timing(enable=True, reset=True, which=1)
+        for w in [0, 1] + list(TIMED):
+            ctxs[0].vip_kernel_timing(enable=True, reset=True, which=w)
     stats = []
     dom_s = [0.0] * len(ctxs)
 
@@ -149,11 +212,13 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     spmv = conv = None
+    kt = {}
     if time_spmv:
         spmv = ctxs[0].vip_kernel_timing(enable=False)
         conv = ctxs[0].vip_kernel_timing(enable=False, which=1)
+        kt = {name: ctxs[0].vip_kernel_timing(enable=False, which=w) for w, name in TIMED.items()}
     fields = [[t.cpu().numpy() for t in st] for st in state]
-    return (t1 - t0), stats, (spmv, conv), fields, dom_s
+    return (t1 - t0), stats, (spmv, conv, kt), fields, dom_s
 
 
 def cpu_baseline(h, dt, re, budget_s):
@@ -307,11 +372,11 @@ def main():
         pool = ThreadPoolExecutor(max_workers=len(ctxs))
     for path in paths:
         nsteps = args.plain_steps if path == "plain" else args.steps
-        el, stats, (spmv, conv), fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
+        el, stats, (spmv, conv, kt), fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
                                                   nsteps, args.tol, path == paths[0],
                                                   args.inner_tol, pool, args.helmholtz_tol,
                                                   args.learned_precond)
-        results[path] = dict(seconds=el, stats=stats, spmv=spmv, conv=conv, fields=fields, dom_s=dom_s,
+        results[path] = dict(seconds=el, stats=stats, spmv=spmv, conv=conv, kt=kt, fields=fields, dom_s=dom_s,
                              steps=nsteps)
         log("%s: %.3f s for %d steps" % (path, el, nsteps))
 
@@ -325,7 +390,9 @@ def main():
         n0, _, nnz0 = ctxs[0].vip_operator_shape("poisson")
         fp32 = PATHS[main_path]["precision"] != "P_FP64"
         counts, taps = ctxs[0].vip_canonical_rows()
-        cb = ctxs[0].vip_column_bytes()[0]   # bytes per stored column: int16 deltas or int32
+        ne, ne16 = ctxs[0].vip_column_bytes()[:2]
+        # mean bytes per stored column: int16 row-relative slices and int32 slices
+        cb = (2.0 * ne16 + 4.0 * (ne - ne16)) / max(ne, 1)
         vs = 4 if fp32 else 0
         nc = int(counts[vs])
         vb = 4 if fp32 else 8            # bytes of one vector entry / value
@@ -341,8 +408,8 @@ def main():
         # row sums); with tiles, the irregular-row list and per 64 x 16 tile its 256-byte record
         # (position, 20 row starts, 16 row masks), counted for every lattice tile.  Canonical
         # (tile) rows read no column or value stream.
-        bytes_per_launch = (3 * vb * n0 + (vb + cb) * (nnz0 - taps * nc) + (4 if fp32 else 0) * (n0 - nc)
-                            + (4 * (n0 - nc) + 256 * ntiles if ntiles else 0))
+        bytes_per_launch = int(3 * vb * n0 + (vb + cb) * (nnz0 - taps * nc) + (4 if fp32 else 0) * (n0 - nc)
+                               + (4 * (n0 - nc) + 256 * ntiles if ntiles else 0))
         avg_ms, count = r["spmv"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         tiled = ntiles > 0
@@ -357,6 +424,30 @@ def main():
                 "rows": n0, "nnz": nnz0, "canonical_rows": nc, "tiles": ntiles, "taps": taps,
                 "column_bytes": cb,
                 "ell_bytes_per_launch": (vb + 4) * nnz0 + 3 * vb * n0}
+
+    # every timed kernel against the HBM roofline, and the one that takes the most time per step
+    rooflines = {}
+    if roof is not None:
+        kb = kernel_bytes(ctxs[0], specs[0], PATHS[main_path]["precision"] != "P_FP64")
+        timed = dict(r["kt"])
+        timed["pres_spmv"] = r["spmv"]
+        for name, (avg_ms, count) in timed.items():
+            if count <= 0 or avg_ms <= 0:
+                continue
+            gbs = kb[name] / (avg_ms * 1e-3) / 1e9
+            label = KERNEL_NAMES[name] % (("float", "float") if fp32 else ("double", "double")) \
+                if name == "pres_spmv" else KERNEL_NAMES[name]
+            rooflines[name] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": gbs / HBM_PEAK_GBS, "kernel": label,
+                               "bytes_per_launch": int(kb[name]), "avg_ms": avg_ms, "launches": count,
+                               "ms_per_step": avg_ms * count / args.steps,
+                               "traffic": measured_traffic(name) if abs(h - 1.0 / 128) < 1e-12 else None}
+    if rooflines:
+        dom = max(rooflines, key=lambda k: rooflines[k]["ms_per_step"])
+        dominant = dict(rooflines[dom])
+        dominant["name"] = dom
+    else:
+        dominant = roof
 
     roof_mfma = None
     if r.get("conv") is not None and r["conv"][1] > 0:
@@ -432,7 +523,16 @@ def main():
         out["learned_poisson_iters_vs_mixed"] = [a, b]
     if train_info:
         out["training"] = train_info
-    out["roofline"] = roof
+    out["roofline"] = dominant
+    out["roofline_pressure_spmv"] = roof
+    out["rooflines"] = rooflines
+    if rooflines:
+        timed_ms = sum(v["ms_per_step"] for v in rooflines.values())
+        timed_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in rooflines.values()) / args.steps
+        # the timed kernels' share of the step, and their combined bytes over their combined time
+        out["timed_kernels_per_step"] = {"ms": timed_ms, "share_of_step": timed_ms / ms,
+                                         "GB_per_step": timed_bytes / 1e9,
+                                         "GBs_over_their_time": timed_bytes / (timed_ms * 1e-3) / 1e9}
     out["roofline_mfma"] = roof_mfma
     if not args.no_cpu:
         log("CPU oracle baseline")

@@ -416,20 +416,29 @@ int vip_spectral_peak(const double* signal, int64_t n, double dt, double* freq, 
  * vip_create, or for node sets that are not lattice based.  Host outputs, may be NULL. */
 int vip_canonical_rows(void* ctx, int64_t* counts, int64_t* described, int* taps);
 
-/* Column stream of the general (non-canonical) rows: *sys_bytes = 2 when the pressure and
- * predictor matrices store row-relative int16 columns (every stored column within +-32767 of
- * its row; then the solve-phase kernels read those and the results keep their bits), else 4
- * (int32; also with VIP_NO_DELTA=1 at vip_create).  *amg_levels = coarse multigrid levels built
- * so far (the hierarchy is built at the first Poisson solve), *amg_levels_delta = those with
- * int16 columns.  Host outputs, may be NULL.  Errors: VIP_E_NOT_BUILT. */
-int vip_column_bytes(void* ctx, int* sys_bytes, int* amg_levels, int* amg_levels_delta);
+/* Column stream of the general (non-canonical) rows.  Where every stored column of a 64-row
+ * slice lies within +-32767 of its row, the pressure and predictor matrices also hold the
+ * slice's columns as int16 row-relative offsets, and the solve-phase kernels read those (2 bytes
+ * per entry instead of 4; the results keep their bits); other slices (rows next to far-numbered
+ * nodes, such as body-surface nodes listed last) read the int32 columns.  VIP_NO_DELTA=1 at
+ * vip_create keeps every row on int32.  *sys_entries = stored entries of the system layout,
+ * *sys_entries_int16 = those in int16 slices, *amg_levels = coarse multigrid levels built so far
+ * (the hierarchy is built at the first Poisson solve), *amg_levels_delta = those with int16
+ * slices.  Host outputs, may be NULL.  Errors: VIP_E_NOT_BUILT. */
+int vip_column_bytes(void* ctx, int64_t* sys_entries, int64_t* sys_entries_int16, int* amg_levels,
+                     int* amg_levels_delta);
 
 /* Average duration (ms) of a kernel over its launches since the last reset, measured with
  * HIP events on the context stream while timing is enabled; *count receives the number of
  * timed launches.  which = 0: the pressure-solve SpMV (the first SpMV of each Krylov
  * iteration; launches after the solve stopped on the device are not counted); which = 1:
  * the learned start vector's inference (the fused 4-layer launch, or each 32 -> 32 layer
- * when VIP_CNN_LAYERED=1 was set at vip_create).  enable = 0
+ * when VIP_CNN_LAYERED=1 was set at vip_create); which = 2: the predictor's two-system SpMV
+ * (k_bicg_v); 3: the predictor's t kernel that also forms s (k_bicg_t, one launch per
+ * system); 4: the predictor's two-system update (k_bicg_x); 5: the post-smoothing sweeps of
+ * the finest FP32 multigrid level (k_sweep); 6: the predictor right-hand side
+ * (k_predictor_rhs, VIP convection and AB2).  Launches after a solve stopped on the device
+ * (they return at once) are not counted.  enable = 0
  * stops timing; reset = 1 clears it.  Errors: VIP_E_INVALID (unknown which). */
 int vip_kernel_timing(void* ctx, int which, int enable, int reset, double* avg_ms, int64_t* count);
 

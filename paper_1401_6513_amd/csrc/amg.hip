@@ -276,6 +276,7 @@ struct LevelView {
   const int64_t* ptr;
   const int32_t* cols;
   const int16_t* dcols;   // row-relative columns (Ell::dcols), or null
+  const uint8_t* dfit;    // per slice: 1 where dcols holds the slice's columns
   const T* val;
   const T* wdinv;
   const float* rsum;   // FP32 levels: row sums for the difference form
@@ -428,28 +429,32 @@ __device__ __forceinline__ T level_row(const LevelView<T>& L, int64_t i, Y y) {
     if (p >= 0) return canon_row(L, p, i, w, y);
   }
   const T yi = (sizeof(T) == 4) ? y(static_cast<int32_t>(i)) : T(0);
-  T a0 = T(0), a1 = T(0);
-  int k = 0;
-  const int32_t ii = static_cast<int32_t>(i);
-  auto col = [&](int64_t q) __attribute__((always_inline)) {
-    return L.dcols ? ii + static_cast<int32_t>(L.dcols[q]) : L.cols[q];
+  // the slot loop once per column stream, so that each instance issues loads of one kind only
+  auto sum = [&](auto col) __attribute__((always_inline)) -> T {
+    T a0 = T(0), a1 = T(0);
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {
+      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+      const int32_t c0 = col(q), c1 = col(q + kSlice), c2 = col(q + 2 * kSlice), c3 = col(q + 3 * kSlice);
+      const T v0 = L.val[q], v1 = L.val[q + kSlice], v2 = L.val[q + 2 * kSlice], v3 = L.val[q + 3 * kSlice];
+      const T y0 = y(c0), y1 = y(c1), y2 = y(c2), y3 = y(c3);
+      a0 = fmadd(v0, y0 - yi, a0);
+      a1 = fmadd(v1, y1 - yi, a1);
+      a0 = fmadd(v2, y2 - yi, a0);
+      a1 = fmadd(v3, y3 - yi, a1);
+    }
+    for (; k < w; ++k) {
+      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+      a0 = fmadd(L.val[q], y(col(q)) - yi, a0);
+    }
+    if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.rsum[i]), yi, a0 + a1);
+    else return a0 + a1;
   };
-  for (; k + 4 <= w; k += 4) {
-    const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-    const int32_t c0 = col(q), c1 = col(q + kSlice), c2 = col(q + 2 * kSlice), c3 = col(q + 3 * kSlice);
-    const T v0 = L.val[q], v1 = L.val[q + kSlice], v2 = L.val[q + 2 * kSlice], v3 = L.val[q + 3 * kSlice];
-    const T y0 = y(c0), y1 = y(c1), y2 = y(c2), y3 = y(c3);
-    a0 = fmadd(v0, y0 - yi, a0);
-    a1 = fmadd(v1, y1 - yi, a1);
-    a0 = fmadd(v2, y2 - yi, a0);
-    a1 = fmadd(v3, y3 - yi, a1);
+  if (L.dcols && L.dfit[sl]) {
+    const int32_t ii = static_cast<int32_t>(i);
+    return sum([&](int64_t q) __attribute__((always_inline)) { return ii + static_cast<int32_t>(L.dcols[q]); });
   }
-  for (; k < w; ++k) {
-    const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-    a0 = fmadd(L.val[q], y(col(q)) - yi, a0);
-  }
-  if constexpr (sizeof(T) == 4) return fmadd(static_cast<T>(L.rsum[i]), yi, a0 + a1);
-  else return a0 + a1;
+  return sum([&](int64_t q) __attribute__((always_inline)) { return L.cols[q]; });
 }
 
 // W b at row j, as a rounded product: without contraction, so that no fused multiply-add
@@ -928,6 +933,7 @@ static LevelView<T> view(const Ctx* c, int level) {
   v.ptr = L.A.ptr;
   v.cols = L.A.cols;
   v.dcols = L.A.dcols;
+  v.dfit = L.A.dfit;
   v.rsum = L.A.rsum32;
   v.cpix = nullptr;
   v.sbase = nullptr;
@@ -1090,12 +1096,14 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     T* other = obuf;
     for (int k = 0; k < nu; ++k) {
       T* o = (l == 0 && k == nu - 1) ? x : other;
+      KTimer kt(c, c->ktime[kTimeSweep0], l == 0 && sizeof(T) == 4, c->vcycle);
       k_sweep<T, 0><<<level_grid(lv), kBlock, 0, st>>>(lv, bl, SweepIn<T>{y, nullptr}, o, on);
       other = y;
       y = o;
     }
     xc = y;
   }
+  ++c->vcycle;
   if (border) VIP_HIP_TRY(c, hipMemcpyAsync(x + c->n, b + c->n, sizeof(T), hipMemcpyDeviceToDevice, st));
   return VIP_OK;
 }

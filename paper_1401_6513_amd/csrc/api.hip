@@ -27,6 +27,7 @@ void ell_free(Ell& e) {
   dfree(e.rowlen);
   dfree(e.cols);
   dfree(e.dcols);
+  dfree(e.dfit);
   for (auto& v : e.val) dfree(v);
   dfree(e.val32);
   dfree(e.rsum32);
@@ -203,7 +204,7 @@ int vip_destroy(void* p) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
-  for (auto* T : {&c->conv_timing}) {
+  for (auto* T : {&c->conv_timing, &c->ktime[0], &c->ktime[1], &c->ktime[2], &c->ktime[3], &c->ktime[4]}) {
     for (auto& e : T->pool) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
@@ -250,10 +251,12 @@ int vip_build_stencils_adaptive(void* p, const double* nodes_xy, int64_t n_nodes
   return rc;
 }
 
-int vip_column_bytes(void* p, int* sys_bytes, int* amg_levels, int* amg_levels_delta) {
+int vip_column_bytes(void* p, int64_t* sys_entries, int64_t* sys_entries_int16, int* amg_levels,
+                     int* amg_levels_delta) {
   Ctx* c = vip::as_ctx(p);
   VIP_TRY(vip::need_built(c));
-  if (sys_bytes) *sys_bytes = c->sys.dcols ? 2 : 4;
+  if (sys_entries) *sys_entries = c->sys.nnz;
+  if (sys_entries_int16) *sys_entries_int16 = c->sys.dcols ? c->sys.dfit_nnz : 0;
   int nl = 0, nd = 0;
   for (size_t l = 1; l < c->amg.lv.size(); ++l) {
     if (c->amg.lv[l].A.nrows == 0) continue;
@@ -470,8 +473,8 @@ int vip_gradient(void* p, const double* f, double* gx, double* gy) {
 int vip_kernel_timing(void* p, int which, int enable, int reset, double* avg_ms, int64_t* count) {
   Ctx* c = vip::as_ctx(p);
   if (!c) return VIP_E_INVALID;
-  if (which != 0 && which != 1) return vip::set_error(c, VIP_E_INVALID, "unknown timed kernel");
-  vip::Timing& T = which == 0 ? c->timing : c->conv_timing;
+  if (which < 0 || which >= 2 + vip::kTimedKinds) return vip::set_error(c, VIP_E_INVALID, "unknown timed kernel");
+  vip::Timing& T = which == 0 ? c->timing : which == 1 ? c->conv_timing : c->ktime[which - 2];
   if (reset) {
     T.total_ms = 0.0;
     T.count = 0;

@@ -418,50 +418,87 @@ int ell_layout(Ctx* c, Ell& e) {
 
 // ---- row-relative int16 columns ------------------------------------------------------------------
 
-// dcols of every slot of the lanes [0, nlanes): col - row for stored entries, 0 in padding; a
-// column farther than 32767 from its row sets *bad
+// One wavefront per slice: dcols of every slot of the slice (col - row for stored entries, 0 in
+// padding), and dfit[slice] = 1 when every stored column lies within +-32767 of its row
 __global__ void k_deltas(const int64_t* ptr, const int32_t* width, const int32_t* rowlen, const int32_t* cols,
-                         int64_t nrows, int64_t nlanes, int16_t* dcols, int* bad) {
-  const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (r >= nlanes) return;
-  const int64_t s = r / kSlice, l = r % kSlice;
+                         int64_t nrows, int64_t nslices, int16_t* dcols, uint8_t* dfit) {
+  const int64_t s = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kSlice;
+  const int l = static_cast<int>(threadIdx.x % kSlice);
+  if (s >= nslices) return;
+  const int64_t r = s * kSlice + l;
   const int32_t len = r < nrows ? rowlen[r] : 0;
+  bool fit = true;
   for (int32_t k = 0; k < width[s]; ++k) {
     const int64_t q = ptr[s] + static_cast<int64_t>(k) * kSlice + l;
     int64_t d = 0;
     if (k < len) {
       d = static_cast<int64_t>(cols[q]) - r;
       if (d < -32767 || d > 32767) {
-        *bad = 1;   // every writer stores the same value
+        fit = false;
         d = 0;
       }
     }
     dcols[q] = static_cast<int16_t>(d);
   }
+  const bool all = __all(fit);
+  if (l == 0) dfit[s] = all ? 1 : 0;
+}
+
+// out[0] = slices with dfit = 1, out[1] = stored entries of their rows (one block, fixed order)
+__global__ void k_count_fit(int64_t nslices, int64_t nrows, const uint8_t* dfit, const int32_t* rowlen,
+                            int64_t* out) {
+  __shared__ int64_t sh[2][256];
+  int64_t a = 0, b = 0;
+  for (int64_t s = threadIdx.x; s < nslices; s += blockDim.x) {
+    if (!dfit[s]) continue;
+    a += 1;
+    for (int64_t r = s * kSlice; r < (s + 1) * kSlice && r < nrows; ++r) b += rowlen[r];
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + off];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sh[0][0];
+    out[1] = sh[1][0];
+  }
 }
 
 int ell_deltas(Ctx* c, Ell& e) {
   dfree(e.dcols);
+  dfree(e.dfit);
+  e.dfit_slices = 0;
   if (c->no_delta || e.nrows == 0 || e.nnz_slots == 0) return VIP_OK;
-  int* bad = nullptr;
-  VIP_TRY(dalloc(c, &bad, 1));
+  int64_t* cnt = nullptr;
+  VIP_TRY(dalloc(c, &cnt, 2));
   VIP_TRY(dalloc(c, &e.dcols, e.nnz_slots));
+  VIP_TRY(dalloc(c, &e.dfit, e.nslices));
   hipStream_t st = c->stream;
-  int hb = 0;
-  hipError_t err = hipMemsetAsync(bad, 0, sizeof(int), st);
-  if (err == hipSuccess) {
-    k_deltas<<<grid_for(e.nslices * kSlice), kBlock, 0, st>>>(e.ptr, e.width, e.rowlen, e.cols, e.nrows,
-                                                              e.nslices * kSlice, e.dcols, bad);
-    err = hipGetLastError();
-  }
-  if (err == hipSuccess) err = hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+  int64_t hc[2] = {0, 0};
+  k_deltas<<<(e.nslices * kSlice + kBlock - 1) / kBlock, kBlock, 0, st>>>(e.ptr, e.width, e.rowlen, e.cols, e.nrows,
+                                                                            e.nslices, e.dcols, e.dfit);
+  k_count_fit<<<1, 256, 0, st>>>(e.nslices, e.nrows, e.dfit, e.rowlen, cnt);
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) err = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st);
   if (err == hipSuccess) err = hipStreamSynchronize(st);
-  dfree(bad);
+  dfree(cnt);
   if (err != hipSuccess) {
     dfree(e.dcols);
+    dfree(e.dfit);
     return set_error(c, VIP_E_HIP, std::string("row-relative columns: ") + hipGetErrorString(err));
   }
-  if (hb) dfree(e.dcols);   // some column is too far from its row: keep the int32 stream only
+  e.dfit_slices = hc[0];
+  e.dfit_nnz = hc[1];
+  if (hc[0] == 0) {   // no slice fits: keep the int32 stream only
+    dfree(e.dcols);
+    dfree(e.dfit);
+  }
   return VIP_OK;
 }
 

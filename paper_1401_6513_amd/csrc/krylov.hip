@@ -160,13 +160,9 @@ struct Mat {
   TileView tv;             // tile partition of the systems' canonical rows (tile.h), if any
   int tile_general;        // 1: tile rows also take the row-by-row path (canonical rows off)
   const int16_t* dcols;    // row-relative columns (Ell::dcols), or null: read cols
+  const uint8_t* dfit;     // per slice: 1 where dcols holds the slice's columns
 };
 
-// column of slot q of row i: from the 2-byte row-relative stream when there is one
-template <typename VT>
-__device__ __forceinline__ int32_t col_at(const Mat<VT>& A, int64_t i, int64_t q) {
-  return A.dcols ? static_cast<int32_t>(i) + static_cast<int32_t>(A.dcols[q]) : A.cols[q];
-}
 
 // Every system a kernel will touch has its values (and, in FP32, its row sums).
 template <typename VT>
@@ -192,6 +188,7 @@ void attach_canon(const Ctx* c, Mat<VT>& A, int vs0, int vs1) {
   A.tv = key >= 0 ? tile_view(c, cn.tpart[key]) : TileView();
   A.tile_general = c->no_canon ? 1 : 0;
   A.dcols = c->sys.dcols;
+  A.dfit = c->sys.dfit;
   if (c->no_canon || cn.K == 0) return;
   const int vs[2] = {vs0, vs1};
   for (int s = 0; s < 2; ++s) {
@@ -342,51 +339,57 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
     if (p >= 0) return canon_dot(A, sys, p, i, w, x);
   }
   const VT* vals = A.val[sys];
-  if constexpr (sizeof(VT) == 4) {
-    // difference form: rows of the pressure matrix sum to ~0, so on smooth x the
-    // plain sum cancels most of its digits in FP32; x_j - x_i of nearby values is
-    // exact and keeps them
-    const float xi = static_cast<float>(x[i]);
-    float a0 = 0.0f, a1 = 0.0f;
-    int k = 0;
-    for (; k + 4 <= w; k += 4) {
-      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      const int32_t c0 = col_at(A, i, q), c1 = col_at(A, i, q + kSlice), c2 = col_at(A, i, q + 2 * kSlice),
-                    c3 = col_at(A, i, q + 3 * kSlice);
-      const float v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
-      const float x0 = static_cast<float>(x[c0]), x1 = static_cast<float>(x[c1]),
-                  x2 = static_cast<float>(x[c2]), x3 = static_cast<float>(x[c3]);
-      a0 = fmaf(v0, x0 - xi, a0);
-      a1 = fmaf(v1, x1 - xi, a1);
-      a0 = fmaf(v2, x2 - xi, a0);
-      a1 = fmaf(v3, x3 - xi, a1);
+  // the slot loop once per column stream, so that each instance issues loads of one kind only
+  auto sum = [&](auto col) __attribute__((always_inline)) -> double {
+    if constexpr (sizeof(VT) == 4) {
+      // difference form: rows of the pressure matrix sum to ~0, so on smooth x the
+      // plain sum cancels most of its digits in FP32; x_j - x_i of nearby values is
+      // exact and keeps them
+      const float xi = static_cast<float>(x[i]);
+      float a0 = 0.0f, a1 = 0.0f;
+      int k = 0;
+      for (; k + 4 <= w; k += 4) {
+        const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+        const int32_t c0 = col(q), c1 = col(q + kSlice), c2 = col(q + 2 * kSlice), c3 = col(q + 3 * kSlice);
+        const float v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
+        const float x0 = static_cast<float>(x[c0]), x1 = static_cast<float>(x[c1]),
+                    x2 = static_cast<float>(x[c2]), x3 = static_cast<float>(x[c3]);
+        a0 = fmaf(v0, x0 - xi, a0);
+        a1 = fmaf(v1, x1 - xi, a1);
+        a0 = fmaf(v2, x2 - xi, a0);
+        a1 = fmaf(v3, x3 - xi, a1);
+      }
+      for (; k < w; ++k) {
+        const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+        a0 = fmaf(static_cast<float>(vals[q]), static_cast<float>(x[col(q)]) - xi, a0);
+      }
+      return static_cast<double>(a0 + a1) + static_cast<double>(A.rsum[sys][i] * xi);
+    } else {
+      double a0 = 0.0, a1 = 0.0;
+      int k = 0;
+      for (; k + 4 <= w; k += 4) {
+        const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+        const int32_t c0 = col(q), c1 = col(q + kSlice), c2 = col(q + 2 * kSlice), c3 = col(q + 3 * kSlice);
+        const double v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
+        const double x0 = static_cast<double>(x[c0]), x1 = static_cast<double>(x[c1]),
+                     x2 = static_cast<double>(x[c2]), x3 = static_cast<double>(x[c3]);
+        a0 = fma(v0, x0, a0);
+        a1 = fma(v1, x1, a1);
+        a0 = fma(v2, x2, a0);
+        a1 = fma(v3, x3, a1);
+      }
+      for (; k < w; ++k) {
+        const int64_t q = base + static_cast<int64_t>(k) * kSlice;
+        a0 = fma(static_cast<double>(vals[q]), static_cast<double>(x[col(q)]), a0);
+      }
+      return a0 + a1;
     }
-    for (; k < w; ++k) {
-      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      a0 = fmaf(static_cast<float>(vals[q]), static_cast<float>(x[col_at(A, i, q)]) - xi, a0);
-    }
-    return static_cast<double>(a0 + a1) + static_cast<double>(A.rsum[sys][i] * xi);
-  } else {
-    double a0 = 0.0, a1 = 0.0;
-    int k = 0;
-    for (; k + 4 <= w; k += 4) {
-      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      const int32_t c0 = col_at(A, i, q), c1 = col_at(A, i, q + kSlice), c2 = col_at(A, i, q + 2 * kSlice),
-                    c3 = col_at(A, i, q + 3 * kSlice);
-      const double v0 = vals[q], v1 = vals[q + kSlice], v2 = vals[q + 2 * kSlice], v3 = vals[q + 3 * kSlice];
-      const double x0 = static_cast<double>(x[c0]), x1 = static_cast<double>(x[c1]),
-                   x2 = static_cast<double>(x[c2]), x3 = static_cast<double>(x[c3]);
-      a0 = fma(v0, x0, a0);
-      a1 = fma(v1, x1, a1);
-      a0 = fma(v2, x2, a0);
-      a1 = fma(v3, x3, a1);
-    }
-    for (; k < w; ++k) {
-      const int64_t q = base + static_cast<int64_t>(k) * kSlice;
-      a0 = fma(static_cast<double>(vals[q]), static_cast<double>(x[col_at(A, i, q)]), a0);
-    }
-    return a0 + a1;
+  };
+  if (A.dcols && A.dfit[sl]) {
+    const int32_t ii = static_cast<int32_t>(i);
+    return sum([&](int64_t q) __attribute__((always_inline)) { return ii + static_cast<int32_t>(A.dcols[q]); });
   }
+  return sum([&](int64_t q) __attribute__((always_inline)) { return A.cols[q]; });
 }
 
 template <typename VT, typename X>
@@ -1210,7 +1213,7 @@ struct Timer {
     if (!on) return;
     if (c->timing.pool.empty()) {
       hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess || hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
         on = false;
         return;
       }
@@ -1344,6 +1347,9 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   }
   if (bad) *bad = false;
   harvest_timing(c, 0, 0);   // nothing pending belongs to this call
+  for (int k = 0; k < kTimePredRhs; ++k) harvest_kind(c->ktime[k], 0, 0);
+  c->vcycle = 0;
+  const bool tpred = NS == 2;   // the predictor's two-system solve
   VIP_TRY(set_active(c, act, stop2));
   double* part = c->partials;
   KrylovScalars* sc = c->sc;
@@ -1371,6 +1377,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
         }
         {
           Timer tm(c, time_spmv);
+          KTimer kt(c, c->ktime[kTimePredV], tpred);
           if (A.tile_general) k_bicg_v<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
           else k_bicg_v<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
         }
@@ -1391,6 +1398,7 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
               const Mat<VT> Aq = mat_sys(A, q);
               const Vec<T> Vq = vec_sys(V, q);
               double* pq = part + q * 3 * r_rows;
+              KTimer kt(c, c->ktime[kTimePredT], tpred);
               if (A.tile_general) k_bicg_t<VT, T, 1, true, true><<<r_rows, kBlock, 0, st>>>(Aq, Vq, pq, sc, q);
               else k_bicg_t<VT, T, 1, false, true><<<r_rows, kBlock, 0, st>>>(Aq, Vq, pq, sc, q);
             }
@@ -1404,7 +1412,10 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
           else k_bicg_t<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc, 0);
           k_fin_bicg_t<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc, 0);
         }
-        k_bicg_x<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc);
+        {
+          KTimer kt(c, c->ktime[kTimePredX], tpred);
+          k_bicg_x<T, NS><<<r_vec, kBlock, 0, st>>>(V, nvec, part, sc);
+        }
         k_fin_bicg_x<NS><<<1, kBlock, 0, st>>>(part, r_vec, sc);
       } else {
         {
@@ -1447,6 +1458,15 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   // one timed SpMV per iteration: launches after the device stopped the solve exit at once
   // and are not counted
   harvest_timing(c, 0, static_cast<size_t>(*iters));
+  const size_t its = static_cast<size_t>(*iters);
+  harvest_kind(c->ktime[kTimePredV], 0, its);
+  harvest_kind(c->ktime[kTimePredT], 0, its * NS);   // the t launches that ran are one per system
+  harvest_kind(c->ktime[kTimePredX], 0, its);
+  // V-cycles of the iterations the device performed: two per BiCGStab iteration, one per CG
+  // iteration plus the one before the first
+  harvest_kind(c->ktime[kTimeSweep0], 0, SIZE_MAX,
+               static_cast<int>(m == kBiCGStab ? 2 * its : its + 1));
+  harvest_kind(c->ktime[kTimePredRhs], 0, SIZE_MAX);   // launched before this solve, complete now
   return VIP_OK;
 }
 
@@ -1494,6 +1514,46 @@ Method choose_method(Ctx* c) {
 }
 
 }  // namespace
+
+KTimer::KTimer(Ctx* cc, Timing& t, bool enable, int tg) : c(cc), T(&t), on(enable && t.enabled), tag(tg) {
+  if (!on) return;
+  if (T->pool.empty()) {
+    hipEvent_t a, b;
+    if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess || hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
+      on = false;
+      return;
+    }
+    ev = {a, b};
+  } else {
+    ev = T->pool.back();
+    T->pool.pop_back();
+  }
+  (void)hipEventRecord(ev.first, c->stream);
+}
+
+KTimer::~KTimer() {
+  if (!on) return;
+  (void)hipEventRecord(ev.second, c->stream);
+  T->pending.push_back(ev);
+  T->tags.push_back(tag);
+}
+
+void harvest_kind(Timing& T, size_t first, size_t keep, int tag_limit) {
+  for (size_t k = 0; k < T.pending.size(); ++k) {
+    auto& e = T.pending[k];
+    const bool tag_ok = tag_limit < 0 || (k < T.tags.size() && T.tags[k] < tag_limit);
+    if (k >= first && k - first < keep && tag_ok) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+        T.total_ms += ms;
+        T.count += 1;
+      }
+    }
+    T.pool.push_back(e);
+  }
+  T.pending.clear();
+  T.tags.clear();
+}
 
 int ensure_partials(Ctx* c, int64_t blocks, int per) {
   const int64_t need = blocks * per + 64;

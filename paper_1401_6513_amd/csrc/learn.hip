@@ -1030,8 +1030,8 @@ int forward(Ctx* c, const Img& g, bool timed = false) {
     if (timed) {
       if (c->conv_timing.pool.empty()) {
         hipEvent_t a, b;
-        VIP_HIP_TRY(c, hipEventCreate(&a));
-        VIP_HIP_TRY(c, hipEventCreate(&b));
+        VIP_HIP_TRY(c, hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+        VIP_HIP_TRY(c, hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
         c->conv_timing.pool.push_back({a, b});
       }
       ev = c->conv_timing.pool.back();
@@ -1062,8 +1062,8 @@ int forward_fused(Ctx* c, const Img& g, bool timed) {
   if (timed) {
     if (c->conv_timing.pool.empty()) {
       hipEvent_t a, b;
-      VIP_HIP_TRY(c, hipEventCreate(&a));
-      VIP_HIP_TRY(c, hipEventCreate(&b));
+      VIP_HIP_TRY(c, hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+      VIP_HIP_TRY(c, hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
       c->conv_timing.pool.push_back({a, b});
     }
     ev = c->conv_timing.pool.back();

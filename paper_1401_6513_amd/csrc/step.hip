@@ -383,9 +383,12 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   const Op lap{c->node.ptr, c->node.cols, c->node.val[1]};
   const Bnd B{c->bpos, c->bkind, c->bnx, c->bny, c->bval, 2.0 * c->opt.vip_offset * c->h, c->two_db};
   const VC C = vc_of(c);
-  k_predictor_rhs<<<grid_for(n), kBlock, 0, s>>>(n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
-                                                  c->have_prev_n ? 0 : 1, dt, re,
-                                                  c->opt.identity == VIP_I_EXACT ? 1 : 0, ru, rv);
+  {
+    KTimer kt(c, c->ktime[kTimePredRhs], true);
+    k_predictor_rhs<<<grid_for(n), kBlock, 0, s>>>(n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
+                                                    c->have_prev_n ? 0 : 1, dt, re,
+                                                    c->opt.identity == VIP_I_EXACT ? 1 : 0, ru, rv);
+  }
   VIP_HIP_TRY(c, hipGetLastError());
   int rc_h = helmholtz_solve(c, ru, rv, us, vs, st);
   if (rc_h != VIP_OK && rc_h != VIP_E_NOT_CONVERGED) return rc_h;

@@ -114,10 +114,15 @@ struct Ell {
   int64_t max_width = 0;
   int64_t nnz = 0;                  // sum of row lengths
   Canon canon;                      // lattice-interior rows (system layout only)
-  // row-relative columns: dcols[q] = cols[q] - row (0 in padding slots), when every stored
-  // column of the matrix lies within +-32767 of its row; the solve-phase kernels then read 2
-  // bytes per entry instead of 4.  Null when some column does not fit (or VIP_NO_DELTA=1).
+  // row-relative columns: dcols[q] = cols[q] - row (0 in padding slots) in the 64-row slices
+  // whose stored columns all lie within +-32767 of their rows (dfit[slice] = 1); the
+  // solve-phase kernels read those 2-byte columns there and the int32 ones in the other
+  // slices (rows next to far-numbered nodes, such as body-surface nodes listed last).  Null
+  // when no slice fits (or VIP_NO_DELTA=1).
   int16_t* dcols = nullptr;
+  uint8_t* dfit = nullptr;          // device [nslices]
+  int64_t dfit_slices = 0;          // slices with dfit = 1
+  int64_t dfit_nnz = 0;             // stored entries of those slices' rows
 };
 
 // The 21-point lattice disk of radius 2.5h in slot order (rows dy = -2..2, dx ascending):
@@ -240,9 +245,22 @@ struct Amg {
 struct Timing {
   bool enabled = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<int> tags;          // per pending pair: the V-cycle it belongs to (sweep timing)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   double total_ms = 0.0;
   int64_t count = 0;
+};
+
+// Kernels timed with HIP events besides the pressure SpMV and the network (vip_kernel_timing
+// which = 2 + kind): launches after a solve stopped on the device return at once and are not
+// counted.
+enum TimedKind {
+  kTimePredV = 0,    // predictor SpMV k_bicg_v, two systems
+  kTimePredT = 1,    // predictor t kernel k_bicg_t with s formed inside (one launch per system)
+  kTimePredX = 2,    // predictor update k_bicg_x, two systems
+  kTimeSweep0 = 3,   // post-smoothing Jacobi sweep k_sweep<T, 0> of the finest multigrid level
+  kTimePredRhs = 4,  // k_predictor_rhs (VIP convection, AB2 and the predictor right-hand side)
+  kTimedKinds = 5
 };
 
 // One captured solver snapshot as a lattice image (independent of the node set
@@ -364,6 +382,8 @@ struct Ctx {
   Learn learn;
   Timing timing;                  // pressure-solve SpMV launches
   Timing conv_timing;             // MFMA layers of the learned start vector's inference
+  Timing ktime[kTimedKinds];      // see TimedKind
+  int vcycle = 0;                 // V-cycles applied in the current Krylov solve (sweep timing tags)
 
   // body forces (forces.hip): surface node list and per-node traction terms
   int64_t* fsurf = nullptr;       // device [fcap]
@@ -371,6 +391,24 @@ struct Ctx {
   int64_t fcap = 0;
   void* scratch = nullptr;        // this device's copy of the fixed scratch of vip_forces_noalloc
 };
+
+// ---- HIP-event timing (krylov.hip) -----------------------------------------------
+// Events around one launch into T.pending (tag: see Timing::tags) while T.enabled.  Timing
+// events are created without the system-scope fence (hipEventDisableSystemFence): they only
+// measure, the host reads them after a stream synchronisation, and a fence would write back
+// and invalidate the caches between the timed kernel and its neighbours.
+struct KTimer {
+  Ctx* c;
+  Timing* T;
+  bool on;
+  std::pair<hipEvent_t, hipEvent_t> ev{};
+  int tag;
+  KTimer(Ctx* cc, Timing& t, bool enable, int tg = 0);
+  ~KTimer();
+};
+// Add the durations of the pending launches [first, first + keep) (with tag < tag_limit when
+// tag_limit >= 0) to T and recycle every pending event pair.
+void harvest_kind(Timing& T, size_t first, size_t keep, int tag_limit = -1);
 
 // ---- error handling -----------------------------------------------------------
 int set_error(Ctx* c, int code, const std::string& msg);

@@ -90,7 +90,8 @@ SIGNATURES = {
     "vip_gradient": (_INT, [_P, _P, _P, _P]),
     "vip_kernel_timing": (_INT, [_P, _INT, _INT, _INT, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "vip_canonical_rows": (_INT, [_P, _P, _P, ctypes.POINTER(_INT)]),
-    "vip_column_bytes": (_INT, [_P, ctypes.POINTER(_INT), ctypes.POINTER(_INT), ctypes.POINTER(_INT)]),
+    "vip_column_bytes": (_INT, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_INT),
+                                ctypes.POINTER(_INT)]),
     "vip_forces": (_INT, [_P, _P, _P, _P, _D, _P, _I64, _P]),
     "vip_forces_noalloc": (_INT, [_P, _P, _P, _P, _D, _P, _I64, _P]),
     "vip_spectral_peak": (_INT, [_P, _I64, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
@@ -326,12 +327,13 @@ class Context:
         return counts, taps.value
 
     def vip_column_bytes(self):
-        """(bytes per stored column of the system matrices, coarse levels, coarse levels with
-        int16 row-relative columns)."""
-        a, b, d = _INT(), _INT(), _INT()
-        self._check(self.lib.vip_column_bytes(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(d)),
-                    "vip_column_bytes")
-        return a.value, b.value, d.value
+        """(stored entries of the system matrices, those held as int16 row-relative columns,
+        coarse multigrid levels, coarse levels with int16 slices)."""
+        a, b = _I64(), _I64()
+        d, e = _INT(), _INT()
+        self._check(self.lib.vip_column_bytes(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(d),
+                                              ctypes.byref(e)), "vip_column_bytes")
+        return a.value, b.value, d.value, e.value
 
     # ---- body forces -------------------------------------------------------------------
     def vip_forces(self, u, v, p, Re, surf_idx):

@@ -141,6 +141,37 @@ def test_uniform_spacing_gives_the_plain_build():
         b.close()
 
 
+def test_int16_columns_by_slice():
+    """On a set numbered so that the rows next to the body reach body-surface nodes listed last
+    (column offsets beyond int16), only those slices keep int32 columns; steps give the same
+    bits as with int32 columns everywhere."""
+    import os
+    vip = _vip()
+    spec = ns.refined_cylinder_channel(1.0 / 64, ZONES, box=(-4.0, 8.0, -4.0, 4.0), n_surface=128)
+    assert spec.n > 40000
+    out = []
+    for nodelta in (False, True):
+        if nodelta:
+            os.environ["VIP_NO_DELTA"] = "1"
+        try:
+            ctx = vip.Context(0)
+        finally:
+            os.environ.pop("VIP_NO_DELTA", None)
+        try:
+            ctx.build_from_spec(spec, precision=vip.P_MIXED, warmstart=vip.WS_PREV)
+            st = [_dev(a) for a in ns.boundary_initial(spec, (1.0, 0.0))]
+            for _ in range(4):
+                ctx.vip_step(*st, spec.h / 10, 100.0)
+            out.append(([a.cpu().numpy() for a in st], ctx.vip_column_bytes()))
+        finally:
+            ctx.close()
+    (fa, ba), (fb, bb) = out
+    print("system entries, in int16 slices, coarse levels, with int16 slices:", ba, bb)
+    assert 0.9 * ba[0] < ba[1] < ba[0] and bb[1] == 0
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
 def test_int16_columns_give_the_same_bits(prec):
     """The general rows read row-relative int16 columns where every column fits; with
@@ -161,14 +192,15 @@ def test_int16_columns_give_the_same_bits(prec):
             ctx.build_from_spec(spec, precision=prec, warmstart=vip.WS_PREV)
             st = [_dev(a) for a in ns.boundary_initial(spec, (1.0, 0.0))]
             its = [ctx.vip_step(*st, 0.01, 100.0)["poisson_iters"] for _ in range(6)]
-            sysb, nl, nd = ctx.vip_column_bytes()
-            out.append(([a.cpu().numpy() for a in st], its, (sysb, nl, nd)))
+            ne, ne16, nl, nd = ctx.vip_column_bytes()
+            out.append(([a.cpu().numpy() for a in st], its, (ne, ne16, nl, nd)))
         finally:
             ctx.close()
     (fa, ia, ba), (fb, ib, bb) = out
-    print("column bytes (system, coarse levels, with deltas):", ba, bb, "iterations", ia, ib)
-    assert ba[0] == 2 and ba[2] == ba[1] and ba[1] > 0
-    assert bb[0] == 4 and bb[2] == 0
+    print("system entries, in int16 slices, coarse levels, with int16 slices:", ba, bb, "iterations", ia, ib)
+    # fewer than 32768 nodes: every column fits its row's int16 offset
+    assert spec.n < 32768 and ba[1] == ba[0] and ba[3] == ba[2] and ba[2] > 0
+    assert bb[1] == 0 and bb[3] == 0
     assert ia == ib
     for x, y in zip(fa, fb):
         assert np.array_equal(x, y)

@@ -101,14 +101,17 @@ def test_headline_paths_against_oracle(name, trained_theta):
     vip = _vip()
     spec, ref, singular = _oracle_run(name)
     _, inflow, dt, re, steps = HEADLINE_CASES[name]
-    paths = {"fp64": (vip.P_FP64, vip.WS_PREV), "mixed": (vip.P_MIXED, vip.WS_PREV),
-             "mixed+extrap": (vip.P_MIXED, vip.WS_EXTRAP),
-             "mixed+learned": (vip.P_MIXED, vip.WS_LEARNED)}
+    # the last path also loosens the predictor solves to 1e-10 (passes here; at h = 1/128 the
+    # precision paths then differ by 1.4e-6 in p, so the benchmark keeps 1e-12)
+    paths = {"fp64": (vip.P_FP64, vip.WS_PREV, 1e-12), "mixed": (vip.P_MIXED, vip.WS_PREV, 1e-12),
+             "mixed+extrap": (vip.P_MIXED, vip.WS_EXTRAP, 1e-12),
+             "mixed+learned": (vip.P_MIXED, vip.WS_LEARNED, 1e-12),
+             "mixed+learned, predictor 1e-10": (vip.P_MIXED, vip.WS_LEARNED, 1e-10)}
     report = {}
-    for path, (prec, ws) in paths.items():
+    for path, (prec, ws, htol) in paths.items():
         ctx = vip.Context(0)
         try:
-            ctx.build_from_spec(spec, precision=prec, warmstart=ws, poisson_tol=1e-8)
+            ctx.build_from_spec(spec, precision=prec, warmstart=ws, poisson_tol=1e-8, helmholtz_tol=htol)
             if ws == vip.WS_LEARNED:
                 ctx.vip_learn_set_params(trained_theta)
             u, v, p = (_dev(a) for a in ns.boundary_initial(spec, inflow))
@@ -121,7 +124,7 @@ def test_headline_paths_against_oracle(name, trained_theta):
         finally:
             ctx.close()
         report[path] = errs
-        print("%s %-13s rel L2 vs oracle: u %.2e v %.2e p %.2e (start vector used %d/%d)"
+        print("%s %-30s rel L2 vs oracle: u %.2e v %.2e p %.2e (start vector used %d/%d)"
               % (name, path, errs[0], errs[1], errs[2], used, steps))
         if ws == vip.WS_LEARNED:
             assert used > 0, "the learned start vector was never taken"

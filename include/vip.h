@@ -59,10 +59,13 @@ enum { VIP_P_FP64 = 0, VIP_P_MIXED = 1 };           /* pressure and predictor so
                                                        Krylov, or FP32 inner Krylov in FP64
                                                        iterative refinement */
 enum { VIP_K_AUTO = 0, VIP_K_PCG = 1, VIP_K_BICGSTAB = 2 };
-/* Poisson start vector in vip_step: zero; the previous increment phi_n; phi_n + alpha e with
- * e = phi_n - phi_(n-1) (EXTRAP); or phi_n + alpha e + beta c with c the learned network's
- * correction (LEARNED).  alpha and beta minimise the FP64 residual ||b - L phi0||_2 and the
- * corrected vector replaces phi_n only if that lowers the residual. */
+/* Poisson start vector in vip_step: zero; the previous increment phi_n; phi_n + alpha e +
+ * gamma (e - e_old) with e = phi_n - phi_(n-1) and e_old = phi_(n-1) - phi_(n-2), the linear
+ * and quadratic extrapolations in time (EXTRAP; alpha = gamma = 1 is the quadratic one); or the
+ * same plus beta c with c the learned network's correction (LEARNED).  The coefficients
+ * minimise the FP64 residual ||b - L phi0||_2 over the directions available (e after two steps,
+ * e - e_old after three), and the corrected vector replaces phi_n only if that lowers the
+ * residual. */
 enum { VIP_WS_ZERO = 0, VIP_WS_PREV = 1, VIP_WS_LEARNED = 2, VIP_WS_EXTRAP = 3 };
 enum { VIP_PC_JACOBI = 0, VIP_PC_AMG = 1 };         /* Poisson preconditioner */
 
@@ -115,6 +118,8 @@ typedef struct {
   double learned_pc_ratio;   /* learned_precond: product over the passes of the predicted residual
                                 with the network's direction over that of the best multiple of d
                                 alone (1 if never taken; < 1 is what the network gained) */
+  double warm_gamma;         /* coefficient of the second difference e - e_old in the used start
+                                vector (VIP_WS_EXTRAP, VIP_WS_LEARNED), else 0 */
 } vip_step_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -200,9 +205,10 @@ int vip_set_options(void* ctx, const vip_options* opt);
  *  dt, Re   time step and Reynolds number (> 0).  A change of dt or Re
  *           re-assembles the Helmholtz operators and restarts AB2 (the first
  *           step uses N^(n-1) = N^n).
- *  The predictor solve starts from 2 u*(n-1) - u*(n-2) once two earlier steps
- *  of the same dt and Re have converged (u*(n-1) after one, else the
- *  right-hand side); the start does not change what it converges to.
+ *  The predictor solve starts from 3 u*(n-1) - 3 u*(n-2) + u*(n-3) once three
+ *  earlier steps of the same dt and Re have converged (2 u*(n-1) - u*(n-2) after
+ *  two, u*(n-1) after one, else the right-hand side); the start does not change
+ *  what it converges to.
  *  stats    host, may be NULL.
  * Errors: VIP_E_NOT_BUILT, VIP_E_INVALID, VIP_E_NOT_CONVERGED (state is still
  * advanced), VIP_E_NONFINITE, VIP_E_HIP.
@@ -210,7 +216,7 @@ int vip_set_options(void* ctx, const vip_options* opt);
 int vip_step(void* ctx, double* u, double* v, double* p, double dt, double Re,
              vip_step_stats* stats);
 
-/* Forget the AB2 history, the previous pressure increment and the two previous
+/* Forget the AB2 history, the previous pressure increment and the three previous
  * predictor solutions (the predictor solve then starts from its right-hand side). */
 int vip_reset_history(void* ctx);
 

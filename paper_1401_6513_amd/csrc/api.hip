@@ -316,6 +316,7 @@ int vip_reset_history(void* p) {
   c->nstar = 0;
   c->have_prev_phi = false;
   c->learn.have_eprev = false;
+  c->learn.have_eprev2 = false;
   return VIP_OK;
 }
 

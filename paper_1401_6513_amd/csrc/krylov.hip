@@ -1184,6 +1184,12 @@ __global__ void k_extrapolate(int64_t n, const double* a, const double* b, doubl
   if (i < n) x[i] = 2.0 * a[i] - b[i];
 }
 
+// x = 3 (a - b) + c (quadratic extrapolation from the last three values a, b, c, newest first)
+__global__ void k_extrapolate3(int64_t n, const double* a, const double* b, const double* c, double* x) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < n) x[i] = 3.0 * (a[i] - b[i]) + c[i];
+}
+
 // partial sums of a[0..m)
 __global__ void k_sum(int64_t m, const double* a, double* partials) {
   double acc[1] = {0.0};
@@ -1745,16 +1751,23 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
   hipStream_t s = c->stream;
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, b);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, b + stride);
-  // start vector: the linear extrapolation 2 u*(n-1) - u*(n-2) of the last two predictor
-  // solutions (error O(dt^2)), the last solution when only one is held, else the right-hand
-  // side (the operators are close to the identity); the history counts again only once this
-  // solve has succeeded
+  // start vector: the quadratic extrapolation 3 u*(n-1) - 3 u*(n-2) + u*(n-3) of the last three
+  // predictor solutions (error O(dt^3)), the linear one 2 u*(n-1) - u*(n-2) when two are held,
+  // the last solution when one is held, else the right-hand side (the operators are close to
+  // the identity); the history counts again only once this solve has succeeded.  star_prev
+  // holds u*(n-2), v*(n-2) in its first two blocks and u*(n-3), v*(n-3) in the next two (the
+  // last solutions stay in us, vs).
   const int held = c->nstar;
   c->nstar = 0;
-  if (held >= 1 && !c->star_prev) VIP_TRY(dalloc(c, &c->star_prev, 2 * stride));
-  if (held >= 2) {
-    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, us, c->star_prev, x);
-    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, vs, c->star_prev + stride, x + stride);
+  if (held >= 1 && !c->star_prev) VIP_TRY(dalloc(c, &c->star_prev, 4 * stride));
+  double* prev1 = c->star_prev;                                 // [2][stride], step n-2
+  double* prev2 = c->star_prev ? c->star_prev + 2 * stride : nullptr;   // [2][stride], step n-3
+  if (held >= 3) {
+    k_extrapolate3<<<grid_for(n), kBlock, 0, s>>>(n, us, prev1, prev2, x);
+    k_extrapolate3<<<grid_for(n), kBlock, 0, s>>>(n, vs, prev1 + stride, prev2 + stride, x + stride);
+  } else if (held == 2) {
+    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, us, prev1, x);
+    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, vs, prev1 + stride, x + stride);
   } else if (held == 1) {
     k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, us, x);
     k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, vs, x + stride);
@@ -1821,15 +1834,19 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
       if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite predictor residual");
     }
   }
+  if (held >= 2) {
+    // the one before becomes the one before that
+    k_copy<double, double><<<grid_for(2 * stride), kBlock, 0, s>>>(2 * stride, prev1, prev2);
+  }
   if (held >= 1) {
     // the last solution becomes the one before
-    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, us, c->star_prev);
-    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, vs, c->star_prev + stride);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, us, prev1);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, vs, prev1 + stride);
   }
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x, us);
   k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x + stride, vs);
   VIP_HIP_TRY(c, hipGetLastError());
-  if (converged && std::isfinite(worst)) c->nstar = std::min(held + 1, 2);
+  if (converged && std::isfinite(worst)) c->nstar = std::min(held + 1, 3);
   if (st) {
     st->helmholtz_iters = total;
     st->helmholtz_residual = worst;

@@ -846,6 +846,51 @@ __global__ void k_dots6_part(int64_t n, const double* q1, const double* q2, cons
   if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// block partials of the Gram matrix of three directions and their dots with r:
+// q1.q1, q1.q2, q1.q3, q2.q2, q2.q3, q3.q3, q1.r, q2.r, q3.r, r.r (a null q gives zero terms)
+__global__ void k_dots10_part(int64_t n, const double* q1, const double* q2, const double* q3, const double* r,
+                              double* part) {
+  __shared__ double sh[10][256];
+  double acc[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double a = q1[i], b = q2 ? q2[i] : 0.0, c = q3 ? q3[i] : 0.0, rv = r[i];
+    acc[0] += a * a;
+    acc[1] += a * b;
+    acc[2] += a * c;
+    acc[3] += b * b;
+    acc[4] += b * c;
+    acc[5] += c * c;
+    acc[6] += a * rv;
+    acc[7] += b * rv;
+    acc[8] += c * rv;
+    acc[9] += rv * rv;
+  }
+  for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off)
+      for (int k = 0; k < 10; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 10) part[10 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// scal[2 + k] = sum over blocks of dot k of k_dots10_part (fixed block order)
+__global__ void k_dots10_finish(int nb, const double* part, double* scal) {
+  double t[10];
+  sum_partials<10>(nb, part, t);
+  if (threadIdx.x < 10) scal[2 + threadIdx.x] = t[threadIdx.x];
+}
+
+// phi = phi_prev + a1 d1 + a2 d2 + a3 d3 (a null direction is skipped)
+__global__ void k_combine3(int64_t n, const double* phi_prev, const double* d1, const double* d2, const double* d3,
+                           double a1, double a2, double a3, double* phi) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  phi[i] = phi_prev[i] + a1 * d1[i] + (d2 ? a2 * d2[i] : 0.0) + (d3 ? a3 * d3[i] : 0.0);
+}
+
 // scal[2 + k] = sum over blocks of dot k (fixed block order)
 __global__ void k_dots6_finish(int nb, const double* part, double* scal) {
   double t[6];
@@ -906,9 +951,10 @@ void learn_clear(Ctx* c) {
 void learn_free_nodeset(Ctx* c) {
   Learn& L = c->learn;
   for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2, &L.scal, &L.pc_r, &L.pc_d, &L.pc_c,
-                     &L.pc_q1, &L.pc_q2, &L.pc_scal})
+                     &L.pc_q1, &L.pc_q2, &L.pc_scal, &L.eprev2, &L.dir2, &L.q3})
     dfree(*p);
   L.have_eprev = false;
+  L.have_eprev2 = false;
 }
 
 void learn_free(Ctx* c) {
@@ -1178,9 +1224,9 @@ int ensure_vectors(Ctx* c) {
   Learn& L = c->learn;
   if (L.r) return VIP_OK;
   for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2, &L.pc_r, &L.pc_d, &L.pc_c,
-                     &L.pc_q1, &L.pc_q2})
+                     &L.pc_q1, &L.pc_q2, &L.eprev2, &L.dir2, &L.q3})
     VIP_TRY(dalloc(c, p, c->n));
-  VIP_TRY(dalloc(c, &L.scal, kScalHead + 6 * kRedBlocks));
+  VIP_TRY(dalloc(c, &L.scal, kScalHead + 10 * kRedBlocks));
   VIP_TRY(dalloc(c, &L.pc_scal, kScalHead + 6 * kRedBlocks));
   return VIP_OK;
 }
@@ -1363,35 +1409,87 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
     k_direction<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, c->lat.pix, yv, L.scal, h2, L.dir);
     VIP_TRY(pressure_apply(c, L.dir, L.q2));
   }
-  k_dots6_part<<<kRedBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, L.r, L.scal + kScalHead);
-  k_dots6_finish<<<1, 256, 0, st>>>(kRedBlocks, L.scal + kScalHead, L.scal);
+  // second difference of the increments, e - e_old (the quadratic extrapolation adds it)
+  const bool second = L.have_eprev2;
+  if (second) {
+    k_sub<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.eprev, L.eprev2, L.dir2);
+    VIP_TRY(pressure_apply(c, L.dir2, L.q3));
+  }
+  k_dots10_part<<<kRedBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, second ? L.q3 : nullptr, L.r,
+                                            L.scal + kScalHead);
+  k_dots10_finish<<<1, 256, 0, st>>>(kRedBlocks, L.scal + kScalHead, L.scal);
   VIP_HIP_TRY(c, hipGetLastError());
-  double s[8];
+  double s[12];
   VIP_HIP_TRY(c, hipMemcpyAsync(s, L.scal, sizeof(s), hipMemcpyDeviceToHost, st));
   VIP_HIP_TRY(c, hipStreamSynchronize(st));
   harvest_conv_timing(c);
-  // minimise ||r - alpha q1 - beta q2||_2: normal equations of the 2 x 2 (or 1 x 1) problem
-  const double a11 = s[2], a12 = s[3], a22 = s[4], g1 = s[5], g2 = s[6], rr = s[7];
-  double alpha = 0.0, beta = 0.0;
-  const double det = a11 * a22 - a12 * a12;
-  if (learned && a22 > 0.0 && det > 1e-10 * a11 * a22) {
-    alpha = (g1 * a22 - g2 * a12) / det;
-    beta = (a11 * g2 - a12 * g1) / det;
-  } else if (a11 > 0.0) {
-    alpha = g1 / a11;
+  // minimise ||r - sum_k a_k q_k||_2 over the directions in use (e; the network's c; e - e_old):
+  // normal equations by Gaussian elimination with partial pivoting; a direction whose pivot
+  // vanishes against the Gram diagonal is dropped and the system solved again without it
+  const double G[3][3] = {{s[2], s[3], s[4]}, {s[3], s[5], s[6]}, {s[4], s[6], s[7]}};
+  const double g[3] = {s[8], s[9], s[10]};
+  const double rr = s[11];
+  bool use[3] = {s[2] > 0.0, learned && s[5] > 0.0, second && s[7] > 0.0};
+  double coef[3] = {0.0, 0.0, 0.0};
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    int idx[3], m = 0;
+    for (int k = 0; k < 3; ++k)
+      if (use[k]) idx[m++] = k;
+    coef[0] = coef[1] = coef[2] = 0.0;
+    if (m == 0) break;
+    double A[3][4];
+    for (int a = 0; a < m; ++a) {
+      for (int b2 = 0; b2 < m; ++b2) A[a][b2] = G[idx[a]][idx[b2]];
+      A[a][m] = g[idx[a]];
+    }
+    int bad = -1;
+    for (int col = 0; col < m && bad < 0; ++col) {
+      int piv = col;
+      for (int r2 = col + 1; r2 < m; ++r2)
+        if (std::fabs(A[r2][col]) > std::fabs(A[piv][col])) piv = r2;
+      for (int k = 0; k <= m; ++k) std::swap(A[col][k], A[piv][k]);
+      if (!(std::fabs(A[col][col]) > 1e-10 * G[idx[col]][idx[col]])) {
+        bad = col;
+        break;
+      }
+      for (int r2 = col + 1; r2 < m; ++r2) {
+        const double f = A[r2][col] / A[col][col];
+        for (int k = col; k <= m; ++k) A[r2][k] -= f * A[col][k];
+      }
+    }
+    if (bad >= 0) {   // drop the last direction in use (e stays) and solve again
+      for (int k = 2; k >= 1; --k)
+        if (use[k]) {
+          use[k] = false;
+          break;
+        }
+      if (m == 1) use[0] = false;
+      continue;
+    }
+    double sol[3] = {0.0, 0.0, 0.0};
+    for (int a = m - 1; a >= 0; --a) {
+      double v = A[a][m];
+      for (int k = a + 1; k < m; ++k) v -= A[a][k] * sol[k];
+      sol[a] = v / A[a][a];
+    }
+    for (int a = 0; a < m; ++a) coef[idx[a]] = sol[a];
+    break;
   }
-  const double ratio2 = rr > 0.0 ? (rr - alpha * g1 - beta * g2) / rr : 1.0;
+  const double alpha = coef[0], beta = coef[1], gamma = coef[2];
+  const double ratio2 = rr > 0.0 ? (rr - alpha * g[0] - beta * g[1] - gamma * g[2]) / rr : 1.0;
   const double ratio = std::sqrt(std::max(ratio2, 0.0));
-  const bool accept = std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(ratio) && ratio < 1.0;
+  const bool accept = std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(gamma) && std::isfinite(ratio) &&
+                      ratio < 1.0 && (alpha != 0.0 || beta != 0.0 || gamma != 0.0);
   if (accept)
-    k_combine<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.phi_prev, L.eprev, beta != 0.0 ? L.dir : nullptr,
-                                                   alpha, beta, phi);
+    k_combine3<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.phi_prev, L.eprev, beta != 0.0 ? L.dir : nullptr,
+                                                    gamma != 0.0 ? L.dir2 : nullptr, alpha, beta, gamma, phi);
   VIP_HIP_TRY(c, hipGetLastError());
   if (stats) {
     stats->warm_start = accept ? mode : VIP_WS_PREV;
     stats->warm_ratio = ratio;
     stats->warm_alpha = accept ? alpha : 0.0;
     stats->warm_beta = accept ? beta : 0.0;
+    stats->warm_gamma = accept ? gamma : 0.0;
   }
   return VIP_OK;
 }
@@ -1479,6 +1577,10 @@ int learn_finish(Ctx* c, const double* b, const double* phi, bool capture) {
     k_make_image<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, L.rx, b, L.scal, h2, s.x);
     k_make_target<<<blocks_for(npix), kBlock, 0, st>>>(npix, c->lat.node_of, phi, L.phi_prev, L.eprev, L.scal, h2,
                                                        s.t);
+  }
+  if (L.have_eprev) {
+    k_copy_d<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.eprev, L.eprev2);   // the change before
+    L.have_eprev2 = true;
   }
   k_diff<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, phi, L.phi_prev, L.eprev);
   VIP_HIP_TRY(c, hipGetLastError());

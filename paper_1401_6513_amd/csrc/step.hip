@@ -370,6 +370,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
     c->have_prev_n = false;   // AB2 restarts after a change of dt or Re
     c->nstar = 0;
     c->learn.have_eprev = false;
+    c->learn.have_eprev2 = false;
   }
   if (!c->stepbuf) VIP_TRY(dalloc(c, &c->stepbuf, 5 * n));
   double* ru = c->stepbuf;
@@ -404,6 +405,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
     st->warm_ratio = 0.0;
     st->warm_alpha = 0.0;
     st->warm_beta = 0.0;
+    st->warm_gamma = 0.0;
   }
   if (track) VIP_TRY(learn_prepare(c, b, c->phi, ws == VIP_WS_LEARNED || capture));
   if (predict) VIP_TRY(learn_warm_start(c, ws, b, c->phi, st));
@@ -413,6 +415,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
     VIP_TRY(learn_finish(c, b, c->phi, capture));
   } else {
     c->learn.have_eprev = false;   // the chain of increments is not followed
+    c->learn.have_eprev2 = false;
   }
   k_project<<<grid_for(n), kBlock, 0, s>>>(n, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
                                             v, p);

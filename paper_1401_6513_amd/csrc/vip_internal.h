@@ -280,6 +280,10 @@ struct Learn {
   double* phi_prev = nullptr; // device [n]
   double* eprev = nullptr;    // device [n]: previous increment change phi_n - phi_(n-1)
   bool have_eprev = false;
+  double* eprev2 = nullptr;   // device [n]: the change before, phi_(n-1) - phi_(n-2)
+  bool have_eprev2 = false;
+  double* dir2 = nullptr;     // device [n]: second difference eprev - eprev2
+  double* q3 = nullptr;       // device [n]: L dir2
   double* q1 = nullptr;        // device [n]: L eprev
   double* rx = nullptr;       // device [n]: residual after extrapolation, r - L eprev
   double* dir = nullptr;      // device [n]: the network's correction c
@@ -358,9 +362,9 @@ struct Ctx {
   bool have_prev_phi = false;
   double* nprev = nullptr;        // device [2n]
   double* stepbuf = nullptr;      // device [5n]: predictor right-hand sides, u*, v*, divergence
-  double* star_prev = nullptr;    // device [2(n+1)]: the predictor solutions u*, v* of the step before
-                                  // the last one (the last one's stay in stepbuf)
-  int nstar = 0;                  // previous predictor solutions held (0..2) for the start vector
+  double* star_prev = nullptr;    // device [4(n+1)]: the predictor solutions u*, v* of the two steps
+                                  // before the last one (the last one's stay in stepbuf)
+  int nstar = 0;                  // previous predictor solutions held (0..3) for the start vector
   double* phi = nullptr;          // device [n+1] (last entry: border multiplier)
   double* ws = nullptr;           // device work vectors (FP64)
   int64_t ws_len = 0;

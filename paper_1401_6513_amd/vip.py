@@ -47,7 +47,8 @@ class VipStepStats(ctypes.Structure):
                 ("border_lambda", ctypes.c_double), ("warm_start", ctypes.c_int),
                 ("warm_ratio", ctypes.c_double), ("warm_alpha", ctypes.c_double),
                 ("warm_beta", ctypes.c_double), ("poisson_fp64_fallback", ctypes.c_int),
-                ("learned_pc_passes", ctypes.c_int), ("learned_pc_ratio", ctypes.c_double)]
+                ("learned_pc_passes", ctypes.c_int), ("learned_pc_ratio", ctypes.c_double),
+                ("warm_gamma", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

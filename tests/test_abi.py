@@ -55,7 +55,7 @@ int main(void) {
   F(vip_step_stats, helmholtz_residual) F(vip_step_stats, border_lambda)
   F(vip_step_stats, warm_start) F(vip_step_stats, warm_ratio) F(vip_step_stats, warm_alpha) F(vip_step_stats, warm_beta)
   F(vip_step_stats, poisson_fp64_fallback) F(vip_step_stats, learned_pc_passes)
-  F(vip_step_stats, learned_pc_ratio)
+  F(vip_step_stats, learned_pc_ratio) F(vip_step_stats, warm_gamma)
   return 0;
 }
 """

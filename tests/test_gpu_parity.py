@@ -248,7 +248,9 @@ def _field_errors(got, ref, singular):
 def test_fractional_steps_fp64(cases, name, steps, pc):
     c = cases[name]
     dt, re = RUNS[name]
-    got, ref, st, stats = _run_pair(c, steps, dt, re, poisson_tol=1e-12, precision=0,
+    # predictor solves to 1e-13: p inherits the predictor's tolerance amplified by 1/dt through
+    # the divergence of u*, so at the default 1e-12 the start vector alone moves p by ~1e-9
+    got, ref, st, stats = _run_pair(c, steps, dt, re, poisson_tol=1e-12, helmholtz_tol=1e-13, precision=0,
                                     preconditioner=pc)
     errs = _field_errors(got, ref, st.bordered)
     assert max(errs) <= 1e-9, (name, errs)

@@ -19,11 +19,13 @@ Paths timed on the same node sets, each from the same impulsive start:
   a zero start vector).
 The network is trained before any timing on snapshots the solver generates on
 small training node sets (one-off, outside the timed region).  `value` is the
-learned path.  The roofline entry is that path's pressure SpMV, timed with HIP
-events inside the library over the timed steps.  The CPU baseline runs the
-FP64 oracle (SciPy, Krylov mode, same tolerance) on a window of the workload.
+learned path.  The roofline entry is the kernel of that path with the most time
+per step among those timed with HIP events inside the library over the timed
+steps (all of them under `rooflines`).  The CPU baseline runs the FP64 oracle
+(SciPy, Krylov mode, same tolerance) on a window of the workload.
 
-Prints one JSON line.
+Prints one JSON line.  `--summarize-trace DIR [SKIP]` and `--summarize-counter DIR
+COUNTER` instead print markdown summaries of rocprofv3 CSV output of this script.
 """
 import argparse
 import json
@@ -46,6 +48,8 @@ HBM_PROFILES = {
     "pres_spmv": ("hbm_counters_pressure_spmv_cylinder_h128.md", ("krylov.hip", "tile.h")),
     "pred_t": ("hbm_counters_predictor_t_cylinder_h128.md", ("krylov.hip", "tile.h")),
     "pred_x": ("hbm_counters_predictor_x_cylinder_h128.md", ("krylov.hip",)),
+    "pred_e": ("hbm_counters_predictor_e_cylinder_h128.md", ("krylov.hip",)),
+    "pred_ts": ("hbm_counters_predictor_ts_cylinder_h128.md", ("krylov.hip", "tile.h")),
     "pred_spmv": ("hbm_counters_predictor_spmv_cylinder_h128.md", ("krylov.hip", "tile.h")),
     "sweep0": ("hbm_counters_finest_sweep_cylinder_h128.md", ("amg.hip", "tile.h")),
 }
@@ -114,6 +118,8 @@ KERNEL_NAMES = {
     "pres_spmv": "k_bicg_v<%s,%s,1> (pressure SpMV)",
     "pred_spmv": "k_bicg_v<float,float,2> (predictor SpMV, both velocity systems)",
     "pred_t": "k_bicg_t<float,float,1,*,true> (predictor t = A s with s = r - alpha v formed inside, per system)",
+    "pred_ts": "k_bicg_ts<float> (predictor t = A s with s = r - alpha v formed inside and the five sums, per system)",
+    "pred_e": "k_bicg_e<float,2> (predictor: the last iteration's x and r update with the new p, both systems)",
     "pred_x": "k_bicg_x<float,2> (predictor iterate and residual update, both systems)",
     "sweep0": "k_sweep<float,0> (finest-level damped Jacobi post-smoothing sweep, LDS tiles)",
     "pred_rhs": "k_predictor_rhs (VIP convection, AB2 and the predictor right-hand side, FP64)",
@@ -148,6 +154,10 @@ def kernel_bytes(ctx, spec, fp32):
     out["pred_spmv"] = 2 * 3 * 4 * n + irregular(nc[5], 4, 4) + irregular(nc[6], 4, 4) + rec
     out["pred_t"] = 4 * 4 * n + (irregular(nc[5], 4, 4) + irregular(nc[6], 4, 4)) / 2 + rec
     out["pred_x"] = 2 * 7 * 4 * n
+    # the update pass of the predictor's iteration (both systems): reads x, r, p, v, t and writes
+    # x, r, p; its t kernel reads r, v (s formed inside) and r-hat and writes t
+    out["pred_e"] = 2 * 8 * 4 * n
+    out["pred_ts"] = out["pred_t"]
     # finest level: y, b in, out written; irregular rows add values, columns, row sum, damped diagonal
     out["sweep0"] = 3 * 4 * n + irregular(nc[4], 4, 8) + rec
     # u, v in; the AB2 history in and out (2 vectors each way); r_u, r_v out; VIP spacings d_ew,
@@ -257,7 +267,93 @@ def cpu_baseline(h, dt, re, budget_s):
             "ms_per_step": per * 1e3, "poisson_iters": st.last_iters.get("P")}
 
 
+# ---- summaries of this script's rocprofv3 output (CSV), as committed under profiles/ ----------------
+
+def _prof_csv(d, suffix):
+    import csv
+    import glob
+    f = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not f:
+        sys.exit("no %s under %s" % (suffix, d))
+    return list(csv.DictReader(open(f[0])))
+
+
+def _prof_col(row, *names):
+    for want in (lambda k, n: k.lower() == n.lower(), lambda k, n: n.lower() in k.lower()):
+        for k in row:
+            if any(want(k, n) for n in names):
+                return row[k]
+    raise KeyError(names)
+
+
+def _short_kernel(name):
+    """Kernel name without 'void', namespaces and the argument list."""
+    n = name.replace("(anonymous namespace)::", "").replace("void ", "").strip()
+    return (n[:n.index("(")] if "(" in n else n).replace("vip::", "")
+
+
+def summarize_trace(d, skip):
+    """Per-step kernel table of a --kernel-trace run: every dispatch from the (skip+1)-th
+    k_predictor_rhs over at least 1e6 work items on (one per step of the large domain), divided
+    by the number of steps after the skipped ones."""
+    recs = sorted((int(_prof_col(r, "Start_Timestamp")), int(_prof_col(r, "End_Timestamp")),
+                   _short_kernel(_prof_col(r, "Kernel_Name")), int(_prof_col(r, "Grid_Size", "Grid_Size_X")))
+                  for r in _prof_csv(d, "kernel_trace.csv"))
+    marks = [t0 for (t0, _, name, g) in recs if name.startswith("k_predictor_rhs") and g >= 1000000]
+    start = marks[skip] if len(marks) > skip else 0
+    nsteps = max(1, len(marks) - skip)
+    agg = {}
+    short = 0
+    t_first = t_last = None
+    for (t0, t1, name, g) in recs:
+        if t0 < start:
+            continue
+        a = agg.setdefault(name, [0, 0.0, 0, 0.0])
+        a[0] += 1
+        a[1] += (t1 - t0) / 1e3
+        if g >= 1000000:
+            a[2] += 1
+            a[3] += (t1 - t0) / 1e3
+        short += (t1 - t0) < 10000
+        t_first = t0 if t_first is None else min(t_first, t0)
+        t_last = t1 if t_last is None else max(t_last, t1)
+    tot = sum(a[1] for a in agg.values())
+    out = ["steps summarized: %d; kernel time %.3f ms per step; first-to-last dispatch span %.3f ms "
+           "per step; launches per step %.0f (%.0f under 10 us)" % (
+               nsteps, tot / 1e3 / nsteps, (t_last - t_first) / 1e6 / nsteps,
+               sum(a[0] for a in agg.values()) / nsteps, short / nsteps), "",
+           "| kernel | calls/step | mean us | ms/step | share | grid >= 1e6: calls/step, mean us |",
+           "|---|---:|---:|---:|---:|---:|"]
+    for k, (n, us, nb, usb) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:40]:
+        out.append("| `%s` | %.1f | %.1f | %.3f | %.1f%% | %s |" % (
+            k, n / nsteps, us / n, us / 1e3 / nsteps, 100 * us / tot,
+            "%.1f, %.1f" % (nb / nsteps, usb / nb) if nb else "-"))
+    print("\n".join(out))
+
+
+def summarize_counter(d, counter):
+    """Mean of one PMC counter per kernel and grid size, over dispatches of >= 1e5 work items."""
+    agg = {}
+    for r in _prof_csv(d, "counter_collection.csv"):
+        g = int(_prof_col(r, "Grid_Size", "Grid_Size_X"))
+        if _prof_col(r, "Counter_Name") != counter or g < 100000:
+            continue
+        agg.setdefault((_short_kernel(_prof_col(r, "Kernel_Name")), g), []).append(
+            float(_prof_col(r, "Counter_Value")))
+    out = ["| kernel | grid | dispatches | mean %s (KiB) |" % counter, "|---|---:|---:|---:|"]
+    for (k, g), v in sorted(agg.items()):
+        out.append("| `%s` | %d | %d | %.0f |" % (k, g, len(v), sum(v) / len(v)))
+    print("\n".join(out))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-counter"):
+        # python bench.py --summarize-trace DIR [SKIP] | --summarize-counter DIR COUNTER
+        if sys.argv[1] == "--summarize-trace":
+            summarize_trace(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 3)
+        else:
+            summarize_counter(sys.argv[2], sys.argv[3])
+        return
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -431,6 +527,11 @@ def main():
         kb = kernel_bytes(ctxs[0], specs[0], PATHS[main_path]["precision"] != "P_FP64")
         timed = dict(r["kt"])
         timed["pres_spmv"] = r["spmv"]
+        if os.environ.get("VIP_NO_FUSE") != "1" and args.workload == "lattice" and fp32:
+            # the predictor's iteration on lattice tiles: one update pass (x, r and p) and the
+            # t kernel with five sums instead of the separate p, s and x passes
+            timed["pred_e"] = timed.pop("pred_x")
+            timed["pred_ts"] = timed.pop("pred_t")
         for name, (avg_ms, count) in timed.items():
             if count <= 0 or avg_ms <= 0:
                 continue

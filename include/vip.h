@@ -440,8 +440,10 @@ int vip_column_bytes(void* ctx, int64_t* sys_entries, int64_t* sys_entries_int16
  * iteration; launches after the solve stopped on the device are not counted); which = 1:
  * the learned start vector's inference (the fused 4-layer launch, or each 32 -> 32 layer
  * when VIP_CNN_LAYERED=1 was set at vip_create); which = 2: the predictor's two-system SpMV
- * (k_bicg_v); 3: the predictor's t kernel that also forms s (k_bicg_t, one launch per
- * system); 4: the predictor's two-system update (k_bicg_x); 5: the post-smoothing sweeps of
+ * (k_bicg_v); 3: the predictor's t = A s launch with s formed inside (one per system: k_bicg_ts,
+ * or k_bicg_t); 4: the predictor's two-system update pass (on lattice tiles k_bicg_e, which
+ * applies the last iteration's x and r update and forms the new p; otherwise k_bicg_x;
+ * VIP_NO_FUSE=1 at vip_create keeps the separate passes); 5: the post-smoothing sweeps of
  * the finest FP32 multigrid level (k_sweep); 6: the predictor right-hand side
  * (k_predictor_rhs, VIP convection and AB2).  Launches after a solve stopped on the device
  * (they return at once) are not counted.  enable = 0

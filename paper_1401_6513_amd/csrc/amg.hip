@@ -988,6 +988,11 @@ static int64_t level_grid(const LevelView<T>& v) {
   return v.tv.tiles ? static_cast<int64_t>(v.tv.tile_blocks) + v.tv.irr_blocks : grid_for(v.n);
 }
 
+template <typename T>
+__global__ void k_pass_one(const T* src, T* dst) {
+  if (threadIdx.x == 0) dst[0] = src[0];
+}
+
 // x = M^-1 b for the first n entries (one V-cycle); the border entry is passed through.
 // With pre_fine == false the finest level skips its pre-smoothing sweep (a
 // non-symmetric V(0,1) cycle there, for BiCGStab only).
@@ -1104,7 +1109,11 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     xc = y;
   }
   ++c->vcycle;
-  if (border) VIP_HIP_TRY(c, hipMemcpyAsync(x + c->n, b + c->n, sizeof(T), hipMemcpyDeviceToDevice, st));
+  if (border) {
+    // the border entry passes through (one thread; a runtime copy would take a blit launch)
+    k_pass_one<T><<<1, 64, 0, st>>>(b + c->n, x + c->n);
+    VIP_HIP_TRY(c, hipGetLastError());
+  }
   return VIP_OK;
 }
 

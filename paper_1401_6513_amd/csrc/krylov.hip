@@ -164,6 +164,14 @@ struct Mat {
 };
 
 
+// Total of an FP32 difference-form row, sum_j a_ij (x_j - x_i) + (sum_j a_ij) x_i: the two
+// accumulators added in FP32, then the row-sum term by one explicit FP64 fused multiply-add (its
+// product is exact).  Written out so that no variant of a row product leaves the contraction to
+// the compiler, which fuses a product-then-add or not depending on the code around it.
+__device__ __forceinline__ double diff_total(float a0, float a1, float rsum, float xi) {
+  return fma(static_cast<double>(rsum), static_cast<double>(xi), static_cast<double>(a0 + a1));
+}
+
 // Every system a kernel will touch has its values (and, in FP32, its row sums).
 template <typename VT>
 int check_mat(Ctx* c, const Mat<VT>& A, int ns) {
@@ -247,7 +255,7 @@ __device__ __forceinline__ double disk_sum(const Mat<VT>& A, int sys, Tap&& tap)
       if (k & 1) a1 = fmaf(A.w[sys][k], d, a1);
       else a0 = fmaf(A.w[sys][k], d, a0);
     }
-    return static_cast<double>(a0 + a1) + static_cast<double>(A.crsum[sys] * xi);
+    return diff_total(a0, a1, A.crsum[sys], xi);
   } else {
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
@@ -302,7 +310,7 @@ __device__ __forceinline__ double canon_dot(const Mat<VT>& A, int sys, int32_t p
       if (k < full && (k & 1)) a1 = fmaf(A.w[sys][k], d, a1);
       else a0 = fmaf(A.w[sys][k], d, a0);
     }
-    return static_cast<double>(a0 + a1) + static_cast<double>(A.crsum[sys] * xi);
+    return diff_total(a0, a1, A.crsum[sys], xi);
   } else {
     double a0 = 0.0, a1 = 0.0;
     int k = 0;
@@ -363,7 +371,7 @@ __device__ __forceinline__ double row_dot_rows(const Mat<VT>& A, int sys, int64_
         const int64_t q = base + static_cast<int64_t>(k) * kSlice;
         a0 = fmaf(static_cast<float>(vals[q]), static_cast<float>(x[col(q)]) - xi, a0);
       }
-      return static_cast<double>(a0 + a1) + static_cast<double>(A.rsum[sys][i] * xi);
+      return diff_total(a0, a1, A.rsum[sys][i], xi);
     } else {
       double a0 = 0.0, a1 = 0.0;
       int k = 0;
@@ -578,6 +586,8 @@ __global__ void k_bicg_init(Vec<T> V, int64_t nvec, KrylovScalars* sc) {
       sc->omega[s] = 1.0;
       sc->beta[s] = 0.0;
       sc->breakdown[s] = 0;
+      sc->pending[s] = 0;
+      sc->par[s] = 0;
     }
   }
 }
@@ -700,6 +710,7 @@ __global__ void k_fin_bicg_v(const double* partials, int64_t nb, int64_t n, int 
   if (threadIdx.x != 0) return;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
+    sc->pending[s] = 0;   // (the update pass before this SpMV applied it)
     if (!sc->active[s]) continue;
     double d = tot[2 * s];
     if (border) {
@@ -932,6 +943,140 @@ __global__ void k_fin_bicg_x(const double* partials, int64_t nb, KrylovScalars* 
     sc->beta[s] = isfinite(beta) ? beta : 0.0;
     sc->rho[s] = rho_new;
     if (sc->breakdown[s]) sc->active[s] = 0;
+  }
+}
+
+// ---- BiCGStab with the x, r and p updates in one pass ---------------------------------------------
+// For the unpreconditioned FP32 solves on tiles (the predictor: Jacobi folded into its matrices).
+// Iteration k is three launches:
+//   (E) both systems, in place: the update of iteration k-1, x += alpha p + omega s and
+//       r = s - omega t (s = r - alpha v), then p = r + beta (p - omega v);
+//   (V) v = A p with the partial sums of rhat . v (the two-system SpMV);
+//   (T) per system, t = A s with s = r - alpha v formed where it is read, with the partial sums
+//       of t . s, t . t, s . s, rhat . s and rhat . t.
+// From (T)'s sums: omega = (t . s)/(t . t); |s - omega t|^2 = s . s - omega (t . s); and
+// rhat . r_new = rhat . s - omega (rhat . t).  So beta is known before r_new is formed, and the
+// update of x and r shares its pass with the update of p: per iteration and system 12 vectors
+// move in the vector passes where the separate p and x passes move 15 (11 + 4), and s is never
+// stored; two launches fewer.
+
+// (E): the pending update (x, r) and, while the system iterates, p.
+template <typename T, int NS>
+__global__ void k_bicg_e(Vec<T> V, int64_t nvec, const KrylovScalars* sc) {
+  static_assert(sizeof(T) == 4, "FP32 vectors");
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= nvec) return;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const bool pend = sc->pending[q] != 0, act = sc->active[q] != 0;
+    if (!pend && !act) continue;
+    const int64_t o = q * V.stride + i;
+    T r = V.r[o];
+    const T p = V.p[o], v = V.v[o];
+    const T om = static_cast<T>(sc->omega[q]);
+    if (pend) {
+      const T al = static_cast<T>(sc->alpha[q]);
+      const T sv = bicg_s_value(r, v, al);
+      V.x[o] = fmaf(om, sv, fmaf(al, p, V.x[o]));
+      r = fmaf(-om, V.t[o], sv);
+      V.r[o] = r;
+    }
+    if (act) V.p[o] = fmaf(static_cast<T>(sc->beta[q]), fmaf(-om, v, p), r);
+  }
+}
+
+// (T) for one system q: t = A s, s = r - alpha v formed where it is read; partial sums of t . s,
+// t . t, s . s, rhat . s and rhat . t.  The rows' rhat are loaded before their products.
+template <typename VT, bool GEN>
+__global__ void __launch_bounds__(kBlock, GEN ? 1 : 6) k_bicg_ts(Mat<VT> A, Vec<float> V, double* partials,
+                                                                 const KrylovScalars* sc, int q) {
+  __shared__ float lds[1][kTileLdsH][kTileLdsW];
+  __shared__ TileMeta meta;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool act = sc->active[q] != 0;
+  const SValues<float> sa{V.r, V.v, static_cast<float>(sc->alpha[q])};
+  auto emit = [&](int64_t i, double y, float sv, float rh) __attribute__((always_inline)) {
+    const float yt = static_cast<float>(y);
+    V.t[i] = yt;
+    const double td = static_cast<double>(yt), sd = static_cast<double>(sv), rd = static_cast<double>(rh);
+    acc[0] = fma(td, sd, acc[0]);
+    acc[1] = fma(td, td, acc[1]);
+    acc[2] = fma(sd, sd, acc[2]);
+    acc[3] = fma(rd, sd, acc[3]);
+    acc[4] = fma(rd, td, acc[4]);
+  };
+  auto slow = [&](int64_t i) __attribute__((always_inline)) {
+    const float rh = V.rhat[i];
+    emit(i, row_dot_rows(A, 0, i, sa), sa[i], rh);
+  };
+  if (act)
+    tile_walk(
+        A.tv,
+        [&](int64_t tk) __attribute__((always_inline)) {
+          tile_stage_fn<float, 1>(
+              A.tv, tk, [&](int, int32_t node) __attribute__((always_inline)) { return sa[node]; }, lds, meta, !GEN);
+          if constexpr (GEN) {
+#pragma unroll 1
+            for (int k = 0; k < kTileRowsPerWave; ++k) {
+              const int64_t row = tile_row_id(A.tv, meta, k);
+              if (row >= 0) slow(row);
+            }
+            return;
+          }
+          const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+          int64_t rows[kTileRowsPerWave];
+          float rh[kTileRowsPerWave];
+#pragma unroll
+          for (int k = 0; k < kTileRowsPerWave; ++k) {
+            rows[k] = tile_row_id(A.tv, meta, k);
+            rh[k] = rows[k] >= 0 ? V.rhat[rows[k]] : 0.0f;
+          }
+#pragma unroll 1
+          for (int k = 0; k < kTileRowsPerWave; ++k) {
+            if (rows[k] < 0) continue;
+            const int ly = wave + k * (kBlock / 64);
+            emit(rows[k], disk_lds(A, 0, lds[0], ly, lane), lds[0][ly + 2][lane + 2], rh[k]);
+          }
+        },
+        slow);
+  block_sum_store<5>(acc, partials);
+}
+
+// After (T) of every system: omega, the new |r|^2 and rhat . r from the sums; the iteration's
+// update becomes pending (the next (E) applies it); stop at convergence or breakdown, else
+// beta = (rho'/rho)(alpha/omega).  System q's block sums start at partials + q * per_sys.
+__global__ void k_fin_bicg_ts(const double* partials, int64_t nb, int64_t per_sys, KrylovScalars* sc, int ns) {
+  for (int q = 0; q < ns; ++q) {
+    double tot[5];
+    grid_sum<5>(partials + q * per_sys, nb, tot);
+    if (threadIdx.x == 0 && sc->active[q]) {
+      const double ts = tot[0], tt = tot[1], ss = tot[2], rs = tot[3], rt = tot[4];
+      sc->dot_b[q] = ts;
+      sc->dot_c[q] = tt;
+      sc->dot_d[q] = ss;
+      sc->dot_e[q] = rt;
+      // tt == 0 means s == 0: the half step already solved the system
+      const double om = tt > 0.0 ? ts / tt : 0.0;
+      sc->omega[q] = om;
+      sc->pending[q] = 1;
+      sc->iters[q] += 1;
+      double rr = ss - om * ts;   // |s - omega t|^2 (a NaN stays a NaN)
+      if (rr < 0.0) rr = 0.0;
+      sc->rr[q] = rr;
+      if (!(rr > sc->stop2[q])) {   // converged (or not a number): the pending update finishes it
+        sc->active[q] = 0;
+        if (!isfinite(rr)) sc->breakdown[q] = 1;
+      } else {
+        const double rho_new = rs - om * rt;
+        const double ratio = safe_div(rho_new, sc->rho[q], &sc->breakdown[q]);
+        const double beta = (om != 0.0 && isfinite(ratio)) ? ratio * (sc->alpha[q] / om) : 0.0;
+        if (om == 0.0 || !isfinite(beta) || fabs(beta) > 1e30) sc->breakdown[q] = 1;
+        sc->beta[q] = isfinite(beta) ? beta : 0.0;
+        sc->rho[q] = rho_new;
+        if (sc->breakdown[q]) sc->active[q] = 0;
+      }
+    }
+    __syncthreads();   // grid_sum's LDS is used again for the next system
   }
 }
 
@@ -1279,13 +1424,22 @@ int ensure_ws(Ctx* c, int64_t len64, int64_t len32) {
 enum Method { kBiCGStab = 0, kCG = 1 };
 
 // Tell the kernels which systems iterate and where each one stops.
+// (One small kernel with the values as arguments: copies from host memory would each take a
+// runtime transfer.)
+__global__ void k_set_active(KrylovScalars* sc, int a0, int a1, double s0, double s1) {
+  if (threadIdx.x == 0) {
+    sc->iters[0] = 0;
+    sc->iters[1] = 0;
+    sc->active[0] = a0;
+    sc->active[1] = a1;
+    sc->stop2[0] = s0;
+    sc->stop2[1] = s1;
+  }
+}
+
 int set_active(Ctx* c, const int* act, const double* stop2) {
-  KrylovScalars* sc = c->sc;
-  const int zero[2] = {0, 0};
-  VIP_HIP_TRY(c, hipMemcpyAsync(&sc->iters[0], zero, 2 * sizeof(int), hipMemcpyHostToDevice, c->stream));
-  VIP_HIP_TRY(c, hipMemcpyAsync(&sc->active[0], act, 2 * sizeof(int), hipMemcpyHostToDevice, c->stream));
-  VIP_HIP_TRY(c, hipMemcpyAsync(&sc->stop2[0], stop2, 2 * sizeof(double), hipMemcpyHostToDevice,
-                                c->stream));
+  k_set_active<<<1, 64, 0, c->stream>>>(c->sc, act[0], act[1], stop2[0], stop2[1]);
+  VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;
 }
 
@@ -1341,7 +1495,12 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   // Jacobi vectors ph = D^-1 p, sh = D^-1 s unless multigrid makes them or there is no D^-1
   // (then ph and sh are p and s)
   const int jac = amg || !V.dinv[0] ? 0 : 1;
-  VIP_TRY(ensure_partials(c, std::max(r_rows, r_vec), 3 * NS));
+  // the unpreconditioned two-system FP32 solve on tiles (the predictor) folds its vector passes
+  // into the two products
+  constexpr bool kFuseAll = NS == 2 && sizeof(T) == 4 && sizeof(VT) == 4;
+  const bool fused = kFuseAll && m == kBiCGStab && !amg && !jac && A.tv.tiles && V.sh == V.s && V.ph == V.p &&
+                     !A.border && !c->no_fuse;
+  VIP_TRY(ensure_partials(c, std::max(r_rows, r_vec), (fused ? 5 : 3) * NS));
   if (c->debug)
     std::fprintf(stderr, "[vip] iterate n %lld border %d tol %.3e rr0 %.3e bb %.3e\n",
                  static_cast<long long>(A.n), A.border, tol, c->sc_host->rr[0], bnorm2[0]);
@@ -1376,7 +1535,29 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
     const int batch = std::min(next, maxit - it);
     if (hint) next = std::min(every, 2);
     for (int b = 0; b < batch; ++b) {
-      if (m == kBiCGStab) {
+      if (fused) {
+        if constexpr (kFuseAll) {
+          const int64_t per = 5 * r_rows;
+          {
+            KTimer kt(c, c->ktime[kTimePredX], tpred);
+            k_bicg_e<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc);
+          }
+          {
+            Timer tm(c, time_spmv);
+            KTimer kt(c, c->ktime[kTimePredV], tpred);
+            if (A.tile_general) k_bicg_v<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+            else k_bicg_v<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+          }
+          k_fin_bicg_v<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
+          for (int q = 0; q < NS; ++q) {
+            const Mat<VT> Aq = mat_sys(A, q);
+            KTimer kt(c, c->ktime[kTimePredT], tpred);
+            if (A.tile_general) k_bicg_ts<VT, true><<<r_rows, kBlock, 0, st>>>(Aq, vec_sys(V, q), part + q * per, sc, q);
+            else k_bicg_ts<VT, false><<<r_rows, kBlock, 0, st>>>(Aq, vec_sys(V, q), part + q * per, sc, q);
+          }
+          k_fin_bicg_ts<<<1, kBlock, 0, st>>>(part, r_rows, per, sc, NS);
+        }
+      } else if (m == kBiCGStab) {
         k_bicg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, jac);
         if constexpr (NS == 1) {
           if (amg) VIP_TRY(amg_apply<T>(c, V.p, V.ph, A.border != 0, c->amg_pre_fine != 0));
@@ -1456,6 +1637,13 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
                    "beta %.3e brk %d act %d\n", m == kCG ? "cg" : "bicgstab", amg ? "+amg" : "", it,
                    h.iters[0], h.rr[0], h.stop2[0], h.rho[0], h.alpha[0], h.omega[0], h.beta[0],
                    h.breakdown[0], h.active[0]);
+    }
+  }
+  if constexpr (kFuseAll) {
+    if (fused) {
+      // the update the last iteration left pending (a system that iterates no more forms no p)
+      k_bicg_e<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc);
+      VIP_HIP_TRY(c, hipGetLastError());
     }
   }
   *iters = 0;

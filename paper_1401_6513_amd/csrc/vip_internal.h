@@ -192,6 +192,11 @@ struct KrylovScalars {
   int breakdown[2];
   int active[2];         // cleared on the device at convergence or breakdown
   int iters[2];          // iterations performed (counted on the device)
+  // fused two-product BiCGStab iteration: the x and r update of the last iteration is still to
+  // be applied (pending), and which of the two buffers of r, p and v holds the current ones
+  int pending[2];
+  int par[2];
+  double dot_d[2], dot_e[2];
 };
 
 // One level of the aggregation multigrid preconditioner.
@@ -307,6 +312,7 @@ struct Ctx {
   int no_canon = 0;               // VIP_NO_CANON=1: every row takes the general sliced-ELL path
   int cnn_layered = 0;            // VIP_CNN_LAYERED=1: learned start inference layer by layer
   int no_delta = 0;               // VIP_NO_DELTA=1: general rows read int32 columns, not int16 deltas
+  int no_fuse = 0;                // VIP_NO_FUSE=1: the FP32 predictor iterates with four vector passes
   // V-cycle settings: over-correction of the piecewise-constant coarse correction (plain
   // aggregation makes the Galerkin coarse operators too stiff by about 2 for 2x2 aggregates)
   // and damped Jacobi sweeps per level; measured best on the cylinder and triangle node sets

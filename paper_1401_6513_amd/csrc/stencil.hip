@@ -654,7 +654,14 @@ int tile_part(Ctx* c, int key) {
 
 void vip_canon_free(Ctx* c) {
   dfree(c->vcanon.cpix);
+  tile_part_free(c->vcanon.tpart);
   c->vcanon = VipCanon();
+}
+
+// Canonical nodes that are not boundary nodes (the rows the step kernels take from LDS tiles).
+__global__ void k_interior_canon(int64_t n, const int32_t* cpix, const int32_t* bpos, int32_t* out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < n) out[i] = bpos[i] < 0 ? cpix[i] : -1;
 }
 
 int vip_canon_setup(Ctx* c) {
@@ -697,6 +704,22 @@ int vip_canon_setup(Ctx* c) {
   // the per-operator marks are folded into V.cpix
   for (int o = 0; o < kVcOps; ++o) canon_free(ops[o]->canon);
   if (V.count == 0) vip_canon_free(c);
+  // tiles for the step kernels: every tap of the reference rows within 3 pixels of the node
+  bool fits = V.count > 0 && c->lat.ok;
+  for (int o = 0; o < kVcOps && fits; ++o)
+    for (int d = 0; d < kVcRows; ++d)
+      if (V.len[o][d] > 0 && (V.dx0[o][d] < -3 || V.dx0[o][d] + V.len[o][d] - 1 > 3)) fits = false;
+  if (fits) {
+    int32_t* inner = nullptr;
+    VIP_TRY(dalloc(c, &inner, c->n));
+    k_interior_canon<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, V.cpix, c->bpos, inner);
+    const int rc = tile_part_build(c, c->lat.W, c->lat.H, c->lat.node_of, c->n, c->tmap, inner, nullptr, V.tpart);
+    dfree(inner);
+    VIP_TRY(rc);
+    if (c->debug)
+      std::fprintf(stderr, "[vip] step tiles: %lld tiles, %lld irregular nodes\n",
+                   static_cast<long long>(V.tpart.ntiles), static_cast<long long>(V.tpart.nirr));
+  }
   if (c->debug)
     std::fprintf(stderr, "[vip] canonical VIP/node rows: %lld of %lld\n", static_cast<long long>(c->vcanon.count),
                  static_cast<long long>(c->n));

@@ -6,6 +6,7 @@
 
 #include <cmath>
 
+#include "tile.h"
 #include "vip_internal.h"
 
 namespace vip {
@@ -179,8 +180,9 @@ __device__ __forceinline__ void flux(const R& rows, const Vips& V, int64_t i, co
   rows.vip2(2, u, v, &un, &vn);
   rows.vip2(3, u, v, &us, &vs);
   const double dew = V.d_ew[i], dns = V.d_ns[i];
-  *nx = (ue * ue - uw * uw) / dew + (un * vn - us * vs) / dns;
-  *ny = (ue * ve - uw * vw) / dew + (vn * vn - vs * vs) / dns;
+  // products by explicit fused multiply-adds, so that every variant of the kernels gives the same bits
+  *nx = fma(ue, ue, -(uw * uw)) / dew + fma(un, vn, -(us * vs)) / dns;
+  *ny = fma(ue, ve, -(uw * vw)) / dew + fma(vn, vn, -(vs * vs)) / dns;
 }
 
 struct Bnd {
@@ -204,20 +206,20 @@ __device__ __forceinline__ void predictor_interior(const R& rows, int64_t n, int
   const double py = first ? ny : nprev[n + i];
   nprev[i] = nx;
   nprev[n + i] = ny;
-  const double cx = 1.5 * nx - 0.5 * px;
-  const double cy = 1.5 * ny - 0.5 * py;
+  const double cx = fma(1.5, nx, -(0.5 * px));
+  const double cy = fma(1.5, ny, -(0.5 * py));
   double au, av;
   rows.helm2(m00, rowlen, exact_id, dt / (2.0 * re), u, v, &au, &av);
-  ru[i] = au - dt * cx;
-  rv[i] = av - dt * cy;
+  ru[i] = fma(-dt, cx, au);
+  rv[i] = fma(-dt, cy, av);
 }
 
-// Right-hand sides of the two predictor systems (eq. 12 multiplied by dt).
-__global__ void k_predictor_rhs(int64_t n, Op m00, Op lap, const int32_t* rowlen, Vips V, VC C, Bnd B,
-                                const double* u, const double* v, const double* p, double* nprev, int first,
-                                double dt, double re, int exact_id, double* ru, double* rv) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
+// Right-hand sides of the two predictor systems (eq. 12 multiplied by dt) at node i.
+__device__ __forceinline__ void predictor_node(int64_t n, int64_t i, const Op& m00, const Op& lap,
+                                               const int32_t* rowlen, const Vips& V, const VC& C, const Bnd& B,
+                                               const double* u, const double* v, const double* p, double* nprev,
+                                               int first, double dt, double re, int exact_id, double* ru,
+                                               double* rv) {
   const int32_t k = B.bpos[i];
   if (k >= 0) {
     nprev[i] = 0.0;
@@ -238,6 +240,14 @@ __global__ void k_predictor_rhs(int64_t n, Op m00, Op lap, const int32_t* rowlen
     predictor_interior(EllRows{V, lap, i}, n, i, m00, rowlen, V, u, v, nprev, first, dt, re, exact_id, ru, rv);
 }
 
+__global__ void k_predictor_rhs(int64_t n, Op m00, Op lap, const int32_t* rowlen, Vips V, VC C, Bnd B,
+                                const double* u, const double* v, const double* p, double* nprev, int first,
+                                double dt, double re, int exact_id, double* ru, double* rv) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  predictor_node(n, i, m00, lap, rowlen, V, C, B, u, v, p, nprev, first, dt, re, exact_id, ru, rv);
+}
+
 template <class R>
 __device__ __forceinline__ double divergence_at(const R& rows, const Vips& V, int64_t i, const double* u,
                                                 const double* v) {
@@ -246,11 +256,9 @@ __device__ __forceinline__ double divergence_at(const R& rows, const Vips& V, in
   return (ue - uw) / V.d_ew[i] + (vn - vs) / V.d_ns[i];
 }
 
-// b = div(u*) / dt at interior nodes, 0 on boundary rows (eq. 13).
-__global__ void k_divergence(int64_t n, Vips V, VC C, const int32_t* bpos, const double* u, const double* v,
-                             double scale, double* b) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
+// b = div(u*) / dt at interior nodes, 0 on boundary rows (eq. 13), at node i.
+__device__ __forceinline__ void divergence_node(int64_t i, const Vips& V, const VC& C, const int32_t* bpos,
+                                                const double* u, const double* v, double scale, double* b) {
   if (bpos[i] >= 0) {
     b[i] = 0.0;
     return;
@@ -262,6 +270,13 @@ __global__ void k_divergence(int64_t n, Vips V, VC C, const int32_t* bpos, const
   b[i] = d * scale;
 }
 
+__global__ void k_divergence(int64_t n, Vips V, VC C, const int32_t* bpos, const double* u, const double* v,
+                             double scale, double* b) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  divergence_node(i, V, C, bpos, u, v, scale, b);
+}
+
 template <class R>
 __device__ __forceinline__ void project_at(const R& rows, const Vips& V, int64_t i, bool interior,
                                            const double* us, const double* vs, const double* phi, double dt,
@@ -269,28 +284,227 @@ __device__ __forceinline__ void project_at(const R& rows, const Vips& V, int64_t
   if (interior) {
     const double pe = rows.vip(0, phi), pw = rows.vip(1, phi);
     const double pn = rows.vip(2, phi), ps = rows.vip(3, phi);
-    u[i] = us[i] - dt * ((pe - pw) / V.d_ew[i]);
-    v[i] = vs[i] - dt * ((pn - ps) / V.d_ns[i]);
+    u[i] = fma(-dt, (pe - pw) / V.d_ew[i], us[i]);
+    v[i] = fma(-dt, (pn - ps) / V.d_ns[i], vs[i]);
   } else {
     u[i] = us[i];
     v[i] = vs[i];
   }
-  p[i] = phi[i] - c * rows.laplacian(phi);
+  p[i] = fma(-c, rows.laplacian(phi), phi[i]);
 }
 
 // u = u* - dt grad phi at interior nodes (u = u* on boundary nodes), eq. 14;
 // p = phi - (dt / 2 Re) Delta phi, eq. 15.
-__global__ void k_project(int64_t n, Vips V, VC C, Op lap, const int32_t* bpos, const double* us,
-                          const double* vs, const double* phi, double dt, double c, double* u,
-                          double* v, double* p) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void project_node(int64_t i, const Vips& V, const VC& C, const Op& lap,
+                                             const int32_t* bpos, const double* us, const double* vs,
+                                             const double* phi, double dt, double c, double* u, double* v,
+                                             double* p) {
   const bool interior = bpos[i] < 0;
   const int32_t cp = interior && C.cpix ? C.cpix[i] : -1;
   if (cp >= 0)
     project_at(CanonRows(C, cp, i), V, i, true, us, vs, phi, dt, c, u, v, p);
   else
     project_at(EllRows{V, lap, i}, V, i, interior, us, vs, phi, dt, c, u, v, p);
+}
+
+__global__ void k_project(int64_t n, Vips V, VC C, Op lap, const int32_t* bpos, const double* us,
+                          const double* vs, const double* phi, double dt, double c, double* u,
+                          double* v, double* p) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  project_node(i, V, C, lap, bpos, us, vs, phi, dt, c, u, v, p);
+}
+
+// ---- the same kernels over LDS tiles --------------------------------------------------------------
+// Canonical interior nodes on the lattice are taken tile by tile: a block stages the FP64 fields
+// the products read over a 64 x 16 pixel tile and a 3-pixel halo (every tap of the reference rows
+// lies within 3 pixels; 70 x 22 values per field), and a wavefront computes 4 tile rows, lane =
+// column, reading its taps from LDS in the slot order of the per-node path, so the two give the
+// same bits.  Boundary nodes, other nodes, and nodes off the lattice are taken one per thread by
+// the first blocks of the same launch (tile_walk).
+constexpr int kSH = 3;
+constexpr int kStW = kTileX + 2 * kSH;
+constexpr int kStH = kTileY + 2 * kSH;
+
+// Stage NF fields over listed tile k of the partition (0 where a pixel holds no node).  Starts
+// and ends with a block barrier.
+template <int NF>
+__device__ __forceinline__ void step_stage(const TileView& tv, int64_t k, const double* const (&src)[NF],
+                                           double (&t)[NF][kStH][kStW], TileMeta& m) {
+  const int tid = static_cast<int>(threadIdx.x);
+  __syncthreads();
+  if (tid < kTileRecWords) m.w[tid] = tv.rec[k * kTileRecWords + tid];
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int tx = m.tx(), ty = m.ty();
+  // the record's row starts cover rows 1..20 and columns 1..68 of this frame (its 2-pixel halo)
+  auto node_at = [&](int r, int cc) __attribute__((always_inline)) -> int32_t {
+    if (r >= 1 && r <= kTileLdsH && cc >= 1 && cc <= kTileLdsW) {
+      const int32_t rs = m.rs(r - 1);
+      if (rs >= 0) return rs + cc - 1;
+    }
+    const int gx = tx * kTileX + cc - kSH, gy = ty * kTileY + r - kSH;
+    if (gx >= 0 && gx < tv.W && gy >= 0 && gy < tv.H) return tv.node_of[static_cast<int64_t>(gy) * tv.W + gx];
+    return -1;
+  };
+  constexpr int kWaves = kBlock / 64, kRows = (kStH + kWaves - 1) / kWaves, kEdge = kStW - 64;
+  static_assert(kEdge > 0 && kEdge * kStH <= kBlock, "step tile staging shape");
+  int32_t node[kRows + 1];
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) {
+    const int r = wave + j * kWaves;
+    node[j] = r < kStH ? node_at(r, lane) : -1;
+  }
+  const bool edge = tid < kEdge * kStH;
+  node[kRows] = edge ? node_at(tid / kEdge, 64 + tid % kEdge) : -1;
+  double val[NF][kRows + 1];
+#pragma unroll
+  for (int j = 0; j <= kRows; ++j)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) val[f][j] = node[j] >= 0 ? src[f][node[j]] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) {
+    const int r = wave + j * kWaves;
+    if (r < kStH)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) t[f][r][lane] = val[f][j];
+  }
+  if (edge)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) t[f][tid / kEdge][64 + tid % kEdge] = val[f][kRows];
+  __syncthreads();
+}
+
+// Row products of a canonical node from the staged fields (local row ly, column lx); a field is
+// named by the pointer it was staged from.
+template <int NF>
+struct LdsRows {
+  const VC& C;
+  const double (&t)[NF][kStH][kStW];
+  const double* const (&src)[NF];
+  int ly, lx;
+  __device__ __forceinline__ int field(const double* f) const { return (NF > 1 && f == src[1]) ? 1 : 0; }
+  __device__ __forceinline__ double run(int a, int o, int wo) const {
+    double acc = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < kVcRows; ++d) {
+      const int L = C.len[o][d];
+      const double* tr = &t[a][ly + d][lx + kSH + C.dx0[o][d]];
+      for (int q = 0; q < L; ++q) acc = fma(C.w[wo][k + q], tr[q], acc);
+      k += L;
+    }
+    return acc;
+  }
+  __device__ __forceinline__ double vip(int o, const double* f) const { return run(field(f), o, o); }
+  __device__ __forceinline__ void vip2(int o, const double* f, const double* g, double* pa, double* pb) const {
+    const int a0 = field(f), a1 = field(g);
+    double a = 0.0, b = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < kVcRows; ++d) {
+      const int L = C.len[o][d];
+      const int c0 = lx + kSH + C.dx0[o][d];
+      for (int q = 0; q < L; ++q) {
+        const double w = C.w[o][k + q];
+        a = fma(w, t[a0][ly + d][c0 + q], a);
+        b = fma(w, t[a1][ly + d][c0 + q], b);
+      }
+      k += L;
+    }
+    *pa = a;
+    *pb = b;
+  }
+  __device__ __forceinline__ double laplacian(const double* f) const { return run(field(f), 4, kVcOps); }
+  __device__ __forceinline__ void helm2(const Op&, const int32_t*, int exact_id, double c, const double* u,
+                                        const double* v, double* au, double* av) const {
+    const int a0 = field(u), a1 = field(v);
+    double a = 0.0, b = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int d = 0; d < kVcRows; ++d) {
+      const int L = C.len[4][d];
+      const int dx0 = C.dx0[4][d];
+      const int c0 = lx + kSH + dx0;
+      for (int q = 0; q < L; ++q) {
+        const double id = exact_id ? (d == 3 && dx0 + q == 0 ? 1.0 : 0.0) : C.w[4][k + q];
+        const double r = fma(c, C.w[kVcOps][k + q], id);
+        a = fma(r, t[a0][ly + d][c0 + q], a);
+        b = fma(r, t[a1][ly + d][c0 + q], b);
+      }
+      k += L;
+    }
+    *au = a;
+    *av = b;
+  }
+};
+
+// The tile rows of the wave: f(node, ly, lane) for each.
+template <typename F>
+__device__ __forceinline__ void step_rows(const TileView& tv, const TileMeta& m, F&& f) {
+  const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll 1
+  for (int k = 0; k < kTileRowsPerWave; ++k) {
+    const int64_t row = tile_row_id(tv, m, k);
+    if (row >= 0) f(row, wave + k * (kBlock / 64), lane);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_predictor_rhs_tiles(TileView tv, int64_t n, Op m00, Op lap,
+                                                                const int32_t* rowlen, Vips V, VC C, Bnd B,
+                                                                const double* u, const double* v,
+                                                                const double* p, double* nprev, int first,
+                                                                double dt, double re, int exact_id, double* ru,
+                                                                double* rv) {
+  __shared__ double t[2][kStH][kStW];
+  __shared__ TileMeta m;
+  const double* const src[2] = {u, v};
+  tile_walk(
+      tv,
+      [&](int64_t tk) __attribute__((always_inline)) {
+        step_stage<2>(tv, tk, src, t, m);
+        step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
+          predictor_interior(LdsRows<2>{C, t, src, ly, lx}, n, i, m00, rowlen, V, u, v, nprev, first, dt, re,
+                             exact_id, ru, rv);
+        });
+      },
+      [&](int64_t i) __attribute__((always_inline)) {
+        predictor_node(n, i, m00, lap, rowlen, V, C, B, u, v, p, nprev, first, dt, re, exact_id, ru, rv);
+      });
+}
+
+__global__ void __launch_bounds__(kBlock) k_divergence_tiles(TileView tv, Vips V, VC C, const int32_t* bpos,
+                                                             const double* u, const double* v, double scale,
+                                                             double* b) {
+  __shared__ double t[2][kStH][kStW];
+  __shared__ TileMeta m;
+  const double* const src[2] = {u, v};
+  tile_walk(
+      tv,
+      [&](int64_t tk) __attribute__((always_inline)) {
+        step_stage<2>(tv, tk, src, t, m);
+        step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
+          b[i] = divergence_at(LdsRows<2>{C, t, src, ly, lx}, V, i, u, v) * scale;
+        });
+      },
+      [&](int64_t i) __attribute__((always_inline)) { divergence_node(i, V, C, bpos, u, v, scale, b); });
+}
+
+__global__ void __launch_bounds__(kBlock) k_project_tiles(TileView tv, Vips V, VC C, Op lap, const int32_t* bpos,
+                                                          const double* us, const double* vs, const double* phi,
+                                                          double dt, double c, double* u, double* v, double* p) {
+  __shared__ double t[1][kStH][kStW];
+  __shared__ TileMeta m;
+  const double* const src[1] = {phi};
+  tile_walk(
+      tv,
+      [&](int64_t tk) __attribute__((always_inline)) {
+        step_stage<1>(tv, tk, src, t, m);
+        step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
+          project_at(LdsRows<1>{C, t, src, ly, lx}, V, i, true, us, vs, phi, dt, c, u, v, p);
+        });
+      },
+      [&](int64_t i) __attribute__((always_inline)) { project_node(i, V, C, lap, bpos, us, vs, phi, dt, c, u, v, p); });
 }
 
 __global__ void k_flux_only(int64_t n, Vips V, VC C, const int32_t* bpos, const double* u, const double* v,
@@ -351,6 +565,12 @@ VC vc_of(const Ctx* c) {
   return C;
 }
 
+// The step kernels' tile partition, or an empty view (then they run one node per thread).
+TileView step_tiles(const Ctx* c) {
+  if (c->no_canon || !vc_of(c).cpix || !c->vcanon.tpart.tiles) return TileView();
+  return tile_view_of(c->vcanon.tpart, c->tmap, c->lat.node_of, c->lat.W, c->lat.H);
+}
+
 Vips vips_of(Ctx* c) {
   Vips V;
   for (int k = 0; k < 4; ++k) V.op[k] = Op{c->vipop[k].ptr, c->vipop[k].cols, c->vipop[k].val[0]};
@@ -384,16 +604,24 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   const Op lap{c->node.ptr, c->node.cols, c->node.val[1]};
   const Bnd B{c->bpos, c->bkind, c->bnx, c->bny, c->bval, 2.0 * c->opt.vip_offset * c->h, c->two_db};
   const VC C = vc_of(c);
+  const TileView T = step_tiles(c);
+  const int64_t tgrid = static_cast<int64_t>(T.tile_blocks) + T.irr_blocks;
   {
     KTimer kt(c, c->ktime[kTimePredRhs], true);
-    k_predictor_rhs<<<grid_for(n), kBlock, 0, s>>>(n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
-                                                    c->have_prev_n ? 0 : 1, dt, re,
-                                                    c->opt.identity == VIP_I_EXACT ? 1 : 0, ru, rv);
+    if (T.tiles)
+      k_predictor_rhs_tiles<<<tgrid, kBlock, 0, s>>>(T, n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
+                                                      c->have_prev_n ? 0 : 1, dt, re,
+                                                      c->opt.identity == VIP_I_EXACT ? 1 : 0, ru, rv);
+    else
+      k_predictor_rhs<<<grid_for(n), kBlock, 0, s>>>(n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
+                                                      c->have_prev_n ? 0 : 1, dt, re,
+                                                      c->opt.identity == VIP_I_EXACT ? 1 : 0, ru, rv);
   }
   VIP_HIP_TRY(c, hipGetLastError());
   int rc_h = helmholtz_solve(c, ru, rv, us, vs, st);
   if (rc_h != VIP_OK && rc_h != VIP_E_NOT_CONVERGED) return rc_h;
-  k_divergence<<<grid_for(n), kBlock, 0, s>>>(n, V, C, c->bpos, us, vs, 1.0 / dt, b);
+  if (T.tiles) k_divergence_tiles<<<tgrid, kBlock, 0, s>>>(T, V, C, c->bpos, us, vs, 1.0 / dt, b);
+  else k_divergence<<<grid_for(n), kBlock, 0, s>>>(n, V, C, c->bpos, us, vs, 1.0 / dt, b);
   VIP_HIP_TRY(c, hipGetLastError());
   const int ws = c->opt.warmstart;
   const bool warm = ws != VIP_WS_ZERO && c->have_prev_phi;
@@ -417,8 +645,11 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
     c->learn.have_eprev = false;   // the chain of increments is not followed
     c->learn.have_eprev2 = false;
   }
-  k_project<<<grid_for(n), kBlock, 0, s>>>(n, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
-                                            v, p);
+  if (T.tiles)
+    k_project_tiles<<<tgrid, kBlock, 0, s>>>(T, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u, v, p);
+  else
+    k_project<<<grid_for(n), kBlock, 0, s>>>(n, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
+                                              v, p);
   VIP_HIP_TRY(c, hipGetLastError());
   VIP_HIP_TRY(c, hipStreamSynchronize(s));
   c->have_prev_n = true;
@@ -435,7 +666,12 @@ int convection(Ctx* c, const double* u, const double* v, double* nx, double* ny)
 }
 
 int divergence(Ctx* c, const double* u, const double* v, double* d) {
-  k_divergence<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), vc_of(c), c->bpos, u, v, 1.0, d);
+  const TileView T = step_tiles(c);
+  if (T.tiles)
+    k_divergence_tiles<<<static_cast<int64_t>(T.tile_blocks) + T.irr_blocks, kBlock, 0, c->stream>>>(
+        T, vips_of(c), vc_of(c), c->bpos, u, v, 1.0, d);
+  else
+    k_divergence<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), vc_of(c), c->bpos, u, v, 1.0, d);
   VIP_HIP_TRY(c, hipGetLastError());
   VIP_HIP_TRY(c, hipStreamSynchronize(c->stream));
   return VIP_OK;

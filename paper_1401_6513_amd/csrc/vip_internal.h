@@ -95,6 +95,7 @@ struct VipCanon {
   int8_t len[kVcOps][kVcRows] = {};
   uint8_t used[kVcRows] = {};       // some operator has taps in this stencil row
   double w[kVcOps + 1][kMaxTaps] = {};  // e, w, n, s, D^[0,0], Laplacian; slot order
+  TilePart tpart;                   // lattice tiles of the canonical interior nodes (taps within +-3)
 };
 
 struct Ell {

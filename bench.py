@@ -17,6 +17,12 @@ Paths timed on the same node sets, each from the same impulsive start:
   * fp64:    plain FP64 Krylov, start vector phi_n;
   (optional: extrap = mixed with the extrapolation alone, fp64zero = FP64 from
   a zero start vector).
+Every timed path starts from the same flow: the state after --spinup (500)
+untimed fractional steps from the impulsive start, so that the timed steps
+stand for the bulk of a long run (the workload runs 2000 steps) rather than its
+first steps, where the pressure transient of the impulsive start makes the
+solves several times more expensive; the first path and fp64 are also timed
+from the impulsive start and reported under `transient`.
 The network is trained before any timing on snapshots the solver generates on
 small training node sets (one-off, outside the timed region).  `value` is the
 learned path.  The roofline entry is the kernel of that path with the most time
@@ -105,6 +111,7 @@ PATHS = {
     "mixed": dict(precision="P_MIXED", warmstart="WS_PREV"),
     "extrap": dict(precision="P_MIXED", warmstart="WS_EXTRAP"),
     "fp64": dict(precision="P_FP64", warmstart="WS_PREV"),
+    "fp64x": dict(precision="P_FP64", warmstart="WS_EXTRAP"),
     "fp64zero": dict(precision="P_FP64", warmstart="WS_ZERO"),
     # plain FP64 Krylov: Jacobi preconditioner, previous increment as the start, no learned part
     # (opt-in: on the cylinder at h = D/128 Jacobi-BiCGStab does not converge)
@@ -171,13 +178,8 @@ def kernel_bytes(ctx, spec, fp32):
     return out
 
 
-def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol, pool=None,
-             helmholtz_tol=None, learned_precond=False):
-    """Run `steps` timed steps of every domain (domains in parallel host threads, one HIP stream
-    each, when a pool is given); returns wall seconds, stats, SpMV timing, fields and the
-    summed seconds of each domain's own steps."""
-    import torch
-    dev = torch.device("cuda", 0)
+def configure(vip, ctxs, specs, path, tol, inner_tol, helmholtz_tol=None, learned_precond=False):
+    """Options of a path on every domain's context, and a fresh step history."""
     cfg = PATHS[path]
     for ctx, spec in zip(ctxs, specs):
         opt = vip.default_options(period=spec.period, poisson_tol=tol, inner_tol=inner_tol,
@@ -189,7 +191,45 @@ def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inne
             opt.helmholtz_tol = helmholtz_tol
         ctx.vip_set_options(opt)
         ctx.vip_reset_history()
+
+
+def spin_up(vip, ctxs, specs, dt, re, nsteps, tol, inner_tol, pool):
+    """The flow after `nsteps` untimed fractional steps from the impulsive start (FP32 inner
+    solves, extrapolated start vectors), as the initial state of every timed path: the timed
+    steps then stand for the bulk of a long run rather than its first steps."""
+    import torch
+    dev = torch.device("cuda", 0)
+    configure(vip, ctxs, specs, "extrap", tol, inner_tol)
     state = [_initial(s, dev) for s in specs]
+
+    def one(j):
+        u, v, p = state[j]
+        for k in range(nsteps):
+            ctxs[j].vip_step(u, v, p, dt, re)
+            if j == 0 and (k + 1) % 100 == 0:
+                log("spin-up step %d of %d" % (k + 1, nsteps))
+    if pool is not None:
+        list(pool.map(one, range(len(ctxs))))
+    else:
+        for j in range(len(ctxs)):
+            one(j)
+    torch.cuda.synchronize()
+    out = [[t.clone() for t in st] for st in state]
+    torch.cuda.synchronize()
+    return out
+
+
+def run_path(vip, ctxs, specs, path, dt, re, warmup, steps, tol, time_spmv, inner_tol, pool=None,
+             helmholtz_tol=None, learned_precond=False, init=None):
+    """Run `steps` timed steps of every domain (domains in parallel host threads, one HIP stream
+    each, when a pool is given) from `init` (else the impulsive start); returns wall seconds,
+    stats, SpMV timing, fields and the summed seconds of each domain's own steps."""
+    import torch
+    dev = torch.device("cuda", 0)
+    configure(vip, ctxs, specs, path, tol, inner_tol, helmholtz_tol, learned_precond)
+    state = [[t.clone() for t in st] for st in init] if init else [_initial(s, dev) for s in specs]
+    # the copies run on torch's current stream and the domains step on streams of their own
+    torch.cuda.synchronize()
     for w in range(warmup):
         for ctx, (u, v, p) in zip(ctxs, state):
             ctx.vip_step(u, v, p, dt, re)
@@ -293,20 +333,30 @@ def _short_kernel(name):
 
 
 def summarize_trace(d, skip):
-    """Per-step kernel table of a --kernel-trace run: every dispatch from the (skip+1)-th
+    """Per-step kernel tables of a --kernel-trace run: every dispatch from the (skip+1)-th
     k_predictor_rhs over at least 1e6 work items on (one per step of the large domain), divided
-    by the number of steps after the skipped ones."""
+    by the number of steps after the skipped ones; first over all streams, then for the stream
+    of the large domain alone."""
+    rows = _prof_csv(d, "kernel_trace.csv")
     recs = sorted((int(_prof_col(r, "Start_Timestamp")), int(_prof_col(r, "End_Timestamp")),
-                   _short_kernel(_prof_col(r, "Kernel_Name")), int(_prof_col(r, "Grid_Size", "Grid_Size_X")))
-                  for r in _prof_csv(d, "kernel_trace.csv"))
-    marks = [t0 for (t0, _, name, g) in recs if name.startswith("k_predictor_rhs") and g >= 1000000]
+                   _short_kernel(_prof_col(r, "Kernel_Name")), int(_prof_col(r, "Grid_Size", "Grid_Size_X")),
+                   r.get("Stream_Id", "")) for r in rows)
+    marks = [t0 for (t0, _, name, g, _s) in recs if name.startswith("k_predictor_rhs") and g >= 1000000]
+    big = [s for (t0, _, name, g, s) in recs if name.startswith("k_predictor_rhs") and g >= 1000000]
     start = marks[skip] if len(marks) > skip else 0
     nsteps = max(1, len(marks) - skip)
+    _trace_table(recs, start, nsteps, None, "all streams")
+    if big and big[-1]:
+        print("")
+        _trace_table(recs, start, nsteps, big[-1], "the large domain's stream (%s) alone" % big[-1])
+
+
+def _trace_table(recs, start, nsteps, stream, title):
     agg = {}
     short = 0
     t_first = t_last = None
-    for (t0, t1, name, g) in recs:
-        if t0 < start:
+    for (t0, t1, name, g, sid) in recs:
+        if t0 < start or (stream is not None and sid != stream):
             continue
         a = agg.setdefault(name, [0, 0.0, 0, 0.0])
         a[0] += 1
@@ -318,9 +368,9 @@ def summarize_trace(d, skip):
         t_first = t0 if t_first is None else min(t_first, t0)
         t_last = t1 if t_last is None else max(t_last, t1)
     tot = sum(a[1] for a in agg.values())
-    out = ["steps summarized: %d; kernel time %.3f ms per step; first-to-last dispatch span %.3f ms "
+    out = ["%s: steps summarized: %d; kernel time %.3f ms per step; first-to-last dispatch span %.3f ms "
            "per step; launches per step %.0f (%.0f under 10 us)" % (
-               nsteps, tot / 1e3 / nsteps, (t_last - t_first) / 1e6 / nsteps,
+               title, nsteps, tot / 1e3 / nsteps, (t_last - t_first) / 1e6 / nsteps,
                sum(a[0] for a in agg.values()) / nsteps, short / nsteps), "",
            "| kernel | calls/step | mean us | ms/step | share | grid >= 1e6: calls/step, mean us |",
            "|---|---:|---:|---:|---:|---:|"]
@@ -332,7 +382,9 @@ def summarize_trace(d, skip):
 
 
 def summarize_counter(d, counter):
-    """Mean of one PMC counter per kernel and grid size, over dispatches of >= 1e5 work items."""
+    """Mean of one PMC counter per kernel and grid size, over dispatches of >= 1e5 work items: over
+    all of them, and over the working ones (at least a quarter of the largest value), since the
+    Krylov launches issued after a solve stopped on the device return at once."""
     agg = {}
     for r in _prof_csv(d, "counter_collection.csv"):
         g = int(_prof_col(r, "Grid_Size", "Grid_Size_X"))
@@ -340,9 +392,11 @@ def summarize_counter(d, counter):
             continue
         agg.setdefault((_short_kernel(_prof_col(r, "Kernel_Name")), g), []).append(
             float(_prof_col(r, "Counter_Value")))
-    out = ["| kernel | grid | dispatches | mean %s (KiB) |" % counter, "|---|---:|---:|---:|"]
+    out = ["| kernel | grid | dispatches | mean %s (KiB) | working dispatches | their mean (KiB) |" % counter,
+           "|---|---:|---:|---:|---:|---:|"]
     for (k, g), v in sorted(agg.items()):
-        out.append("| `%s` | %d | %d | %.0f |" % (k, g, len(v), sum(v) / len(v)))
+        w = [x for x in v if x >= 0.25 * max(v)]
+        out.append("| `%s` | %d | %d | %.0f | %d | %.0f |" % (k, g, len(v), sum(v) / len(v), len(w), sum(w) / len(w)))
     print("\n".join(out))
 
 
@@ -359,6 +413,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=3,
                     help="untimed steps per path (the start-vector corrections need two)")
+    ap.add_argument("--spinup", type=int, default=500,
+                    help="untimed fractional steps from the impulsive start whose flow is the initial "
+                         "state of every timed path (0: the timed paths start impulsively)")
+    ap.add_argument("--transient-steps", type=int, default=10,
+                    help="also time this many steps of the first path (and of fp64) from the "
+                         "impulsive start, reported under 'transient' (0: skip)")
     ap.add_argument("--h", type=float, default=1.0 / 128)
     ap.add_argument("--re", type=float, default=200.0)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -366,7 +426,7 @@ def main():
                     help="tolerance of the predictor solves (default: the library's)")
     ap.add_argument("--inner-tol", type=float, default=1e-4,
                     help="relative tolerance of the FP32 inner solve (mixed path)")
-    ap.add_argument("--paths", default="learned,mixed,extrap,fp64")
+    ap.add_argument("--paths", default="learned,mixed,extrap,fp64,fp64x")
     ap.add_argument("--workload", default="lattice", choices=["lattice", "refined"],
                     help="lattice: cylinder + triangle on uniform lattices (the headline workload); "
                          "refined: the cylinder on a stepwise refined node set (general rows only; "
@@ -466,12 +526,29 @@ def main():
     if not args.serial:
         from concurrent.futures import ThreadPoolExecutor
         pool = ThreadPoolExecutor(max_workers=len(ctxs))
+    transient = {}
+    if args.transient_steps > 0:
+        # the first path (and fp64) timed from the impulsive start, for comparison
+        for path in [paths[0]] + (["fp64"] if "fp64" in paths and paths[0] != "fp64" else []):
+            el, stats, _, _, _ = run_path(vip, ctxs, specs, path, dt, re, args.warmup, args.transient_steps,
+                                          args.tol, False, args.inner_tol, pool, args.helmholtz_tol,
+                                          args.learned_precond)
+            transient[path] = {"ms_per_step": el / args.transient_steps * 1e3,
+                               "value": n_total * args.transient_steps / el,
+                               "poisson_iters": [[s["poisson_iters"] for s in row] for row in stats],
+                               "helmholtz_iters": [[s["helmholtz_iters"] for s in row] for row in stats]}
+            log("%s from the impulsive start: %.2f ms per step" % (path, transient[path]["ms_per_step"]))
+    init = None
+    if args.spinup > 0:
+        t0 = time.perf_counter()
+        init = spin_up(vip, ctxs, specs, dt, re, args.spinup, args.tol, args.inner_tol, pool)
+        log("spin-up: %d steps in %.1f s" % (args.spinup, time.perf_counter() - t0))
     for path in paths:
         nsteps = args.plain_steps if path == "plain" else args.steps
         el, stats, (spmv, conv, kt), fields, dom_s = run_path(vip, ctxs, specs, path, dt, re, args.warmup,
                                                   nsteps, args.tol, path == paths[0],
                                                   args.inner_tol, pool, args.helmholtz_tol,
-                                                  args.learned_precond)
+                                                  args.learned_precond, init)
         results[path] = dict(seconds=el, stats=stats, spmv=spmv, conv=conv, kt=kt, fields=fields, dom_s=dom_s,
                              steps=nsteps)
         log("%s: %.3f s for %d steps" % (path, el, nsteps))
@@ -582,7 +659,13 @@ def main():
            "config": {"workload": wl,
                       "nodes": n_total, "nodes_per_domain": [s.n for s in specs],
                       "path": main_path, "build_s": build_s,
-                      "domains_concurrent": not args.serial}}
+                      "domains_concurrent": not args.serial,
+                      "initial_state": ("the flow after %d untimed fractional steps from the impulsive "
+                                        "start (FP32 inner solves, extrapolated start vectors); then "
+                                        "%d warm-up and %d timed steps per path" % (
+                                            args.spinup, args.warmup, args.steps)) if args.spinup > 0
+                      else "impulsive start; %d warm-up and %d timed steps per path" % (
+                          args.warmup, args.steps)}}
     for path, rr in results.items():
         it = [[s["poisson_iters"] for s in row] for row in rr["stats"]]
         out["path_" + path] = {"value": n_total * rr["steps"] / rr["seconds"],
@@ -604,7 +687,10 @@ def main():
         out["fp64_comparator"] = ("fp64 path: FP64 BiCGStab (predictor and pressure) with the same "
                                   "aggregation-multigrid preconditioner and previous-increment start "
                                   "vector; plain Jacobi FP64 (path 'plain') does not converge on the "
-                                  "cylinder at h=D/128")
+                                  "cylinder at h=D/128; fp64x: the same with the extrapolated start "
+                                  "vectors of the learned path (speedup_vs_fp64x isolates precision)")
+        if "fp64x" in results:
+            out["speedup_vs_fp64x"] = per_step["fp64x"] / per_step[main_path]
         # difference of the paths' fields after the same steps (all solve to 1e-8)
         out["rel_l2_vs_fp64"] = {}
         for path in results:
@@ -624,6 +710,13 @@ def main():
         out["learned_poisson_iters_vs_mixed"] = [a, b]
     if train_info:
         out["training"] = train_info
+    if transient:
+        tr = dict(transient)
+        tr["window"] = "steps %d..%d from the impulsive start" % (args.warmup + 1,
+                                                                 args.warmup + args.transient_steps)
+        if main_path in transient and "fp64" in transient:
+            tr["speedup_vs_fp64"] = transient["fp64"]["ms_per_step"] / transient[main_path]["ms_per_step"]
+        out["transient"] = tr
     out["roofline"] = dominant
     out["roofline_pressure_spmv"] = roof
     out["rooflines"] = rooflines

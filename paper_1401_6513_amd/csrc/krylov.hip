@@ -62,10 +62,10 @@ __device__ __forceinline__ Span block_span(int64_t m) {
   return {b, b + per < m ? b + per : m};
 }
 
-// Block sums of NV values, written to partials[blockIdx.x * NV + a] (plain stores);
-// a finishing kernel adds them up in block order.
+// Block sums of NV values, written to partials[blockIdx.x * stride + a] (plain stores; stride NV
+// unless several launches interleave their sums); a finishing kernel adds them up in block order.
 template <int NV>
-__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* partials) {
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* partials, int stride = NV) {
   __shared__ double red[NV][kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -82,7 +82,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* partial
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) t += red[a][w];
-      partials[static_cast<int64_t>(blockIdx.x) * NV + a] = t;
+      partials[static_cast<int64_t>(blockIdx.x) * stride + a] = t;
     }
   }
 }
@@ -986,7 +986,9 @@ __global__ void k_bicg_e(Vec<T> V, int64_t nvec, const KrylovScalars* sc) {
 }
 
 // (T) for one system q: t = A s, s = r - alpha v formed where it is read; partial sums of t . s,
-// t . t, s . s, rhat . s and rhat . t.  The rows' rhat are loaded before their products.
+// t . t, s . s, rhat . s and rhat . t, at partials[10 b + 5 q + a] (the two systems' launches
+// interleave their sums so that one finishing pass adds both).  The rows' rhat are loaded before
+// their products.
 template <typename VT, bool GEN>
 __global__ void __launch_bounds__(kBlock, GEN ? 1 : 6) k_bicg_ts(Mat<VT> A, Vec<float> V, double* partials,
                                                                  const KrylovScalars* sc, int q) {
@@ -1039,17 +1041,19 @@ __global__ void __launch_bounds__(kBlock, GEN ? 1 : 6) k_bicg_ts(Mat<VT> A, Vec<
           }
         },
         slow);
-  block_sum_store<5>(acc, partials);
+  block_sum_store<5>(acc, partials + 5 * q, 10);
 }
 
-// After (T) of every system: omega, the new |r|^2 and rhat . r from the sums; the iteration's
+// After (T) of both systems: omega, the new |r|^2 and rhat . r from the sums; the iteration's
 // update becomes pending (the next (E) applies it); stop at convergence or breakdown, else
-// beta = (rho'/rho)(alpha/omega).  System q's block sums start at partials + q * per_sys.
-__global__ void k_fin_bicg_ts(const double* partials, int64_t nb, int64_t per_sys, KrylovScalars* sc, int ns) {
-  for (int q = 0; q < ns; ++q) {
-    double tot[5];
-    grid_sum<5>(partials + q * per_sys, nb, tot);
-    if (threadIdx.x == 0 && sc->active[q]) {
+// beta = (rho'/rho)(alpha/omega).
+__global__ void k_fin_bicg_ts(const double* partials, int64_t nb, KrylovScalars* sc) {
+  double all[10];
+  grid_sum<10>(partials, nb, all);
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < 2; ++q) {
+    const double* tot = all + 5 * q;
+    if (sc->active[q]) {
       const double ts = tot[0], tt = tot[1], ss = tot[2], rs = tot[3], rt = tot[4];
       sc->dot_b[q] = ts;
       sc->dot_c[q] = tt;
@@ -1076,7 +1080,6 @@ __global__ void k_fin_bicg_ts(const double* partials, int64_t nb, int64_t per_sy
         if (sc->breakdown[q]) sc->active[q] = 0;
       }
     }
-    __syncthreads();   // grid_sum's LDS is used again for the next system
   }
 }
 
@@ -1537,7 +1540,6 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
     for (int b = 0; b < batch; ++b) {
       if (fused) {
         if constexpr (kFuseAll) {
-          const int64_t per = 5 * r_rows;
           {
             KTimer kt(c, c->ktime[kTimePredX], tpred);
             k_bicg_e<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc);
@@ -1552,10 +1554,10 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
           for (int q = 0; q < NS; ++q) {
             const Mat<VT> Aq = mat_sys(A, q);
             KTimer kt(c, c->ktime[kTimePredT], tpred);
-            if (A.tile_general) k_bicg_ts<VT, true><<<r_rows, kBlock, 0, st>>>(Aq, vec_sys(V, q), part + q * per, sc, q);
-            else k_bicg_ts<VT, false><<<r_rows, kBlock, 0, st>>>(Aq, vec_sys(V, q), part + q * per, sc, q);
+            if (A.tile_general) k_bicg_ts<VT, true><<<r_rows, kBlock, 0, st>>>(Aq, vec_sys(V, q), part, sc, q);
+            else k_bicg_ts<VT, false><<<r_rows, kBlock, 0, st>>>(Aq, vec_sys(V, q), part, sc, q);
           }
-          k_fin_bicg_ts<<<1, kBlock, 0, st>>>(part, r_rows, per, sc, NS);
+          k_fin_bicg_ts<<<1, kBlock, 0, st>>>(part, r_rows, sc);
         }
       } else if (m == kBiCGStab) {
         k_bicg_p<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, jac);

@@ -58,6 +58,7 @@ HBM_PROFILES = {
     "pred_ts": ("hbm_counters_predictor_ts_cylinder_h128.md", ("krylov.hip", "tile.h")),
     "pred_spmv": ("hbm_counters_predictor_spmv_cylinder_h128.md", ("krylov.hip", "tile.h")),
     "sweep0": ("hbm_counters_finest_sweep_cylinder_h128.md", ("amg.hip", "tile.h")),
+    "pred_rhs": ("hbm_counters_predictor_rhs_cylinder_h128.md", ("step.hip", "tile.h")),
 }
 
 
@@ -384,7 +385,8 @@ def _trace_table(recs, start, nsteps, stream, title):
 def summarize_counter(d, counter):
     """Mean of one PMC counter per kernel and grid size, over dispatches of >= 1e5 work items: over
     all of them, and over the working ones (at least a quarter of the largest value), since the
-    Krylov launches issued after a solve stopped on the device return at once."""
+    Krylov launches issued after a solve stopped on the device return at once; and the largest
+    (a two-system launch with both systems still iterating)."""
     agg = {}
     for r in _prof_csv(d, "counter_collection.csv"):
         g = int(_prof_col(r, "Grid_Size", "Grid_Size_X"))
@@ -392,11 +394,13 @@ def summarize_counter(d, counter):
             continue
         agg.setdefault((_short_kernel(_prof_col(r, "Kernel_Name")), g), []).append(
             float(_prof_col(r, "Counter_Value")))
-    out = ["| kernel | grid | dispatches | mean %s (KiB) | working dispatches | their mean (KiB) |" % counter,
-           "|---|---:|---:|---:|---:|---:|"]
+    unit = " (KiB)" if counter.endswith("_SIZE") else ""
+    out = ["| kernel | grid | dispatches | mean %s%s | working dispatches | their mean%s | max%s |" % (
+        counter, unit, unit, unit), "|---|---:|---:|---:|---:|---:|---:|"]
     for (k, g), v in sorted(agg.items()):
         w = [x for x in v if x >= 0.25 * max(v)]
-        out.append("| `%s` | %d | %d | %.0f | %d | %.0f |" % (k, g, len(v), sum(v) / len(v), len(w), sum(w) / len(w)))
+        out.append("| `%s` | %d | %d | %.0f | %d | %.0f | %.0f |" % (k, g, len(v), sum(v) / len(v), len(w),
+                                                                 sum(w) / len(w), max(v)))
     print("\n".join(out))
 
 

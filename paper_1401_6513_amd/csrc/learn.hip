@@ -267,7 +267,8 @@ constexpr int kPx = 40;             // LDS stride of one pixel's 32 channels (80
                                     // 16-byte reads of 16 consecutive pixels hit 64 distinct banks)
 
 constexpr int kCnnBlock = 512;      // 8 wavefronts per tile: the LDS allows 2 blocks per CU, and at
-                                    // 127 VGPRs 4 waves per SIMD (1.53 -> 1.44 ms at 2561 x 3841)
+                                    // 127 VGPRs 4 waves per SIMD (1.53 -> 1.44 ms at 2561 x 3841;
+                                    // the branch-free layer-1 operands then 1.38 ms)
 constexpr int kCnnWaves = kCnnBlock / 64;
 
 __global__ __launch_bounds__(kCnnBlock, 4) void k_cnn_fused(Img g, const bf16_t* x, const bf16_t* w1, const float* b1,
@@ -298,8 +299,21 @@ __global__ __launch_bounds__(kCnnBlock, 4) void k_cnn_fused(Img g, const bf16_t*
   const int kq = (l >> 4) * 8;
   const int n = l & 15;
   const int cq = (l >> 4) * 4;
-  // layer 1 on region 1 (side kR1, origin oi - 3, oj - 3), 16 pixels per MFMA group
+  // layer 1 on region 1 (side kR1, origin oi - 3, oj - 3), 16 pixels per MFMA group.  The staged
+  // input is 0 outside the image, so a lane's 8 operand values are plain LDS reads at offsets
+  // fixed per lane (k = kq + j: tap k / 3, channel k % 3; the 5 slots k >= 27 hold 0), taken once
+  // here instead of a bounds test per value.
   {
+    int off1[8];
+    bool use1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = kq + j;
+      const int kk = k < 9 * kCin ? k : 9 * kCin - 1;
+      const int t = kk / kCin, ci = kk % kCin;
+      off1[j] = ((1 + t / 3 - 1) * kR0 + (1 + t % 3 - 1)) * kCin + ci;
+      use1[j] = k < 9 * kCin;
+    }
     const bf16x8 wa0 = l1_weights(w1, 0, n, kq), wa1 = l1_weights(w1, 1, n, kq);
     float bv[2][4];
 #pragma unroll
@@ -312,10 +326,14 @@ __global__ __launch_bounds__(kCnnBlock, 4) void k_cnn_fused(Img g, const bf16_t*
       const int qc = q < np ? q : np - 1;
       const int r = qc / kR1, cc = qc % kR1;
       const int i = oi - 3 + r, j = oj - 3 + cc;
-      const bf16x8 xb = l1_operand(kq, [&](int t, int ci) -> bf16_t {
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        return inside(g, i + dy, j + dx) ? s_in[((r + 1 + dy) * kR0 + (cc + 1 + dx)) * kCin + ci] : bf16_t(0);
-      });
+      const bf16_t* px = s_in + (r * kR0 + cc) * kCin;
+      uint32_t wv[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const uint32_t v = static_cast<uint32_t>(px[off1[jj]]);
+        wv[jj / 2] |= (use1[jj] ? v : 0u) << (16 * (jj % 2));
+      }
+      const bf16x8 xb = __builtin_bit_cast(bf16x8, make_uint4(wv[0], wv[1], wv[2], wv[3]));
       const f32x4 z = {0.f, 0.f, 0.f, 0.f};
       const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, xb, z, 0, 0, 0);
       const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, xb, z, 0, 0, 0);

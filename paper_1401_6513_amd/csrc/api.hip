@@ -63,7 +63,7 @@ void ctx_free_build(Ctx* c) {
   dfree(c->dinv32);
   dfree(c->nprev);
   dfree(c->stepbuf);
-  dfree(c->star_prev);
+  dfree(c->star_ring);
   c->nstar = 0;
   dfree(c->phi);
   dfree(c->ws);

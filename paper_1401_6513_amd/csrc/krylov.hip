@@ -1930,41 +1930,54 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
 // The two predictor systems H_u u* = r_u, H_v v* = r_v in lockstep: FP64 BiCGStab, or with
 // VIP_P_MIXED FP32 BiCGStab corrections inside FP64 iterative refinement (FP64 residual and
 // iterate, to the same FP64 tolerance).
-int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, double* vs,
+int predictor_rhs_buffer(Ctx* c, double** b) {
+  const int64_t stride = c->n + 1;
+  const bool mixed = c->opt.precision == VIP_P_MIXED && c->sys.val32h[0] && c->sys.val32h[1];
+  VIP_TRY(ensure_ws(c, 2 * 8 * stride + 2 * stride, mixed ? 2 * 8 * stride + 2 * stride : 1));
+  *b = c->ws + 16 * stride;   // [2][stride]
+  return VIP_OK;
+}
+
+int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double** us_out, double** vs_out,
                     vip_step_stats* st) {
   const int64_t n = c->n;
   const int64_t stride = n + 1;
   const bool mixed = c->opt.precision == VIP_P_MIXED && c->sys.val32h[0] && c->sys.val32h[1];
-  VIP_TRY(ensure_ws(c, 2 * 8 * stride + 2 * stride + 2 * stride, mixed ? 2 * 8 * stride + 2 * stride : 1));
-  double* b = c->ws + 16 * stride;      // [2][stride]
-  double* x = c->ws + 18 * stride;      // [2][stride]
+  double* b = nullptr;
+  VIP_TRY(predictor_rhs_buffer(c, &b));
   hipStream_t s = c->stream;
-  k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, b);
-  k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, b + stride);
+  if (ru != b) k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, b);
+  if (rv != b + stride) k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, b + stride);
   // start vector: the quadratic extrapolation 3 u*(n-1) - 3 u*(n-2) + u*(n-3) of the last three
   // predictor solutions (error O(dt^3)), the linear one 2 u*(n-1) - u*(n-2) when two are held,
   // the last solution when one is held, else the right-hand side (the operators are close to
-  // the identity); the history counts again only once this solve has succeeded.  star_prev
-  // holds u*(n-2), v*(n-2) in its first two blocks and u*(n-3), v*(n-3) in the next two (the
-  // last solutions stay in us, vs).
+  // the identity); the history counts again only once this solve has succeeded.  The solutions
+  // live in a ring of three slots: the solve runs in the slot after the newest (that of
+  // u*(n-3), extrapolated in place), which then becomes the newest, so no solution is copied.
   const int held = c->nstar;
   c->nstar = 0;
-  if (held >= 1 && !c->star_prev) VIP_TRY(dalloc(c, &c->star_prev, 4 * stride));
-  double* prev1 = c->star_prev;                                 // [2][stride], step n-2
-  double* prev2 = c->star_prev ? c->star_prev + 2 * stride : nullptr;   // [2][stride], step n-3
+  if (!c->star_ring) VIP_TRY(dalloc(c, &c->star_ring, 3 * 2 * stride));
+  auto slot = [&](int k) { return c->star_ring + static_cast<int64_t>(((k % 3) + 3) % 3) * 2 * stride; };
+  const int h = c->star_head;
+  double* last = slot(h);
+  double* before = slot(h - 1);
+  double* x = slot(h + 1);   // [2][stride]; u*(n-3) when three are held
   if (held >= 3) {
-    k_extrapolate3<<<grid_for(n), kBlock, 0, s>>>(n, us, prev1, prev2, x);
-    k_extrapolate3<<<grid_for(n), kBlock, 0, s>>>(n, vs, prev1 + stride, prev2 + stride, x + stride);
+    k_extrapolate3<<<grid_for(n), kBlock, 0, s>>>(n, last, before, x, x);
+    k_extrapolate3<<<grid_for(n), kBlock, 0, s>>>(n, last + stride, before + stride, x + stride, x + stride);
   } else if (held == 2) {
-    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, us, prev1, x);
-    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, vs, prev1 + stride, x + stride);
+    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, last, before, x);
+    k_extrapolate<<<grid_for(n), kBlock, 0, s>>>(n, last + stride, before + stride, x + stride);
   } else if (held == 1) {
-    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, us, x);
-    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, vs, x + stride);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, last, x);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, last + stride, x + stride);
   } else {
-    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, ru, x);
-    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rv, x + stride);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, b, x);
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, b + stride, x + stride);
   }
+  c->star_head = (h + 1) % 3;
+  *us_out = x;
+  *vs_out = x + stride;
   Mat<double> H{n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[1], c->sys.val[2]}, {nullptr, nullptr}};
   attach_canon(c, H, 1, 2);
   Vec<double> V = make_vec<double>(c->ws, stride, 2, x);
@@ -2024,17 +2037,6 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, doub
       if (bad) return set_error(c, VIP_E_NONFINITE, "non-finite predictor residual");
     }
   }
-  if (held >= 2) {
-    // the one before becomes the one before that
-    k_copy<double, double><<<grid_for(2 * stride), kBlock, 0, s>>>(2 * stride, prev1, prev2);
-  }
-  if (held >= 1) {
-    // the last solution becomes the one before
-    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, us, prev1);
-    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, vs, prev1 + stride);
-  }
-  k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x, us);
-  k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x + stride, vs);
   VIP_HIP_TRY(c, hipGetLastError());
   if (converged && std::isfinite(worst)) c->nstar = std::min(held + 1, 3);
   if (st) {
@@ -2068,10 +2070,39 @@ __global__ void k_sys_apply(Mat<double> A, const double* x, double* y) {
   y[i] = row_dot(A, 0, i, x);
 }
 
+// The same over the tile partition: canonical rows from LDS tiles, the others row by row (the
+// same bits as k_sys_apply).
+template <bool GEN>
+__global__ void __launch_bounds__(kBlock) k_sys_apply_tiles(Mat<double> A, const double* x, double* y) {
+  __shared__ double lds[1][kTileLdsH][kTileLdsW];
+  __shared__ TileMeta meta;
+  const double* const xs[1] = {x};
+  tile_walk(
+      A.tv,
+      [&](int64_t tk) __attribute__((always_inline)) {
+        tile_stage<double, 1>(A.tv, tk, xs, lds, meta, !GEN);
+        const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll 1
+        for (int k = 0; k < kTileRowsPerWave; ++k) {
+          const int64_t row = tile_row_id(A.tv, meta, k);
+          if (row < 0) continue;
+          if constexpr (GEN) y[row] = row_dot_rows(A, 0, row, x);
+          else y[row] = disk_lds(A, 0, lds[0], wave + k * (kBlock / 64), lane);
+        }
+      },
+      [&](int64_t i) __attribute__((always_inline)) { y[i] = row_dot_rows(A, 0, i, x); });
+}
+
 int pressure_apply(Ctx* c, const double* x, double* y) {
   Mat<double> A{c->n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}, {nullptr, nullptr}};
   attach_canon(c, A, 0, -1);
   VIP_TRY(check_mat(c, A, 1));
+  if (A.tv.tiles) {
+    if (A.tile_general) k_sys_apply_tiles<true><<<spmv_grid(A), kBlock, 0, c->stream>>>(A, x, y);
+    else k_sys_apply_tiles<false><<<spmv_grid(A), kBlock, 0, c->stream>>>(A, x, y);
+    VIP_HIP_TRY(c, hipGetLastError());
+    return VIP_OK;
+  }
   k_sys_apply<<<grid_for(c->n), kBlock, 0, c->stream>>>(A, x, y);
   VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;

@@ -592,12 +592,14 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
     c->learn.have_eprev = false;
     c->learn.have_eprev2 = false;
   }
-  if (!c->stepbuf) VIP_TRY(dalloc(c, &c->stepbuf, 5 * n));
-  double* ru = c->stepbuf;
-  double* rv = ru + n;
-  double* us = rv + n;
-  double* vs = us + n;
-  double* b = vs + n;
+  if (!c->stepbuf) VIP_TRY(dalloc(c, &c->stepbuf, n));
+  double* b = c->stepbuf;          // the Poisson right-hand side
+  // the predictor right-hand sides, written where the predictor solve reads them
+  double* ru = nullptr;
+  VIP_TRY(predictor_rhs_buffer(c, &ru));
+  double* rv = ru + (n + 1);
+  double* us = nullptr;            // the predictor solutions (set by the solve)
+  double* vs = nullptr;
   hipStream_t s = c->stream;
   const Vips V = vips_of(c);
   const Op m00{c->node.ptr, c->node.cols, c->node.val[0]};
@@ -618,7 +620,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
                                                       c->opt.identity == VIP_I_EXACT ? 1 : 0, ru, rv);
   }
   VIP_HIP_TRY(c, hipGetLastError());
-  int rc_h = helmholtz_solve(c, ru, rv, us, vs, st);
+  int rc_h = helmholtz_solve(c, ru, rv, &us, &vs, st);
   if (rc_h != VIP_OK && rc_h != VIP_E_NOT_CONVERGED) return rc_h;
   if (T.tiles) k_divergence_tiles<<<tgrid, kBlock, 0, s>>>(T, V, C, c->bpos, us, vs, 1.0 / dt, b);
   else k_divergence<<<grid_for(n), kBlock, 0, s>>>(n, V, C, c->bpos, us, vs, 1.0 / dt, b);

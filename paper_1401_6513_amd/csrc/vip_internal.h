@@ -368,9 +368,10 @@ struct Ctx {
   bool have_prev_n = false;
   bool have_prev_phi = false;
   double* nprev = nullptr;        // device [2n]
-  double* stepbuf = nullptr;      // device [5n]: predictor right-hand sides, u*, v*, divergence
-  double* star_prev = nullptr;    // device [4(n+1)]: the predictor solutions u*, v* of the two steps
-                                  // before the last one (the last one's stay in stepbuf)
+  double* stepbuf = nullptr;      // device [n]: the Poisson right-hand side of a step
+  double* star_ring = nullptr;    // device [3][2(n+1)]: the last three predictor solutions (u*, v*),
+                                  // a ring whose next slot the next solve runs in
+  int star_head = 0;              // slot of the newest
   int nstar = 0;                  // previous predictor solutions held (0..3) for the start vector
   double* phi = nullptr;          // device [n+1] (last entry: border multiplier)
   double* ws = nullptr;           // device work vectors (FP64)
@@ -499,7 +500,10 @@ int pressure_apply(Ctx* c, const double* x, double* y);
 // Solvers (krylov.hip)
 int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x0,
                   vip_step_stats* st);
-int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double* us, double* vs,
+// The predictor's right-hand side buffer [2][n+1] (the predictor kernel writes it in place).
+int predictor_rhs_buffer(Ctx* c, double** b);
+// Solves the two predictor systems; *us, *vs receive the solutions (in the history ring).
+int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double** us, double** vs,
                     vip_step_stats* st);
 int build_stencils(Ctx* c, const double* xy, int64_t n, const int64_t* bidx, const double* bnrm,
                    const int32_t* bkind, const double* bval, int64_t nb, int basis_order, double rho,

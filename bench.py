@@ -350,6 +350,34 @@ def summarize_trace(d, skip):
     if big and big[-1]:
         print("")
         _trace_table(recs, start, nsteps, big[-1], "the large domain's stream (%s) alone" % big[-1])
+        _gap_table(recs, start, nsteps, big[-1])
+
+
+def _gap_table(recs, start, nsteps, stream):
+    """Idle time on one stream between the end of a dispatch and the start of the next, per
+    step, by the kernel that ends before the gap (host round trips show as long gaps)."""
+    prev = None
+    gaps = {}
+    for (t0, t1, name, g, sid) in recs:
+        if t0 < start or sid != stream:
+            continue
+        if prev is not None and t0 > prev[0]:
+            a = gaps.setdefault(prev[1], [0, 0.0, 0, 0.0])
+            d = (t0 - prev[0]) / 1e3
+            a[0] += 1
+            a[1] += d
+            if d >= 20.0:
+                a[2] += 1
+                a[3] += d
+        prev = (t1, name) if prev is None or t1 > prev[0] else prev
+    tot = sum(a[1] for a in gaps.values())
+    out = ["", "idle time on that stream: %.3f ms per step; gaps of 20 us or more: %.1f per step, %.3f ms" % (
+        tot / 1e3 / nsteps, sum(a[2] for a in gaps.values()) / nsteps, sum(a[3] for a in gaps.values()) / 1e3 / nsteps),
+        "", "| kernel before the gap | gaps/step | idle ms/step | gaps >= 20 us per step, their ms/step |",
+        "|---|---:|---:|---:|"]
+    for k, (n, us, nb, usb) in sorted(gaps.items(), key=lambda kv: -kv[1][1])[:15]:
+        out.append("| `%s` | %.1f | %.3f | %.1f, %.3f |" % (k, n / nsteps, us / 1e3 / nsteps, nb / nsteps, usb / 1e3 / nsteps))
+    print("\n".join(out))
 
 
 def _trace_table(recs, start, nsteps, stream, title):

@@ -135,8 +135,10 @@ void vip_default_options(vip_options* opt);
  * counts (these change results); VIP_MAX_GRID sets the block count of the reducing
  * vector kernels (default 2048, read once per process; it changes the order of the
  * partial sums and so the last bits); VIP_NO_DELTA=1 keeps the general rows on int32 columns
- * instead of int16 row-relative ones (same bits); VIP_DEBUG=1 prints solver progress to
- * stderr. */
+ * instead of int16 row-relative ones (same bits); VIP_NO_GRAPH=1 launches the multigrid
+ * V-cycle's coarse levels one by one instead of replaying them as one captured HIP graph
+ * (same bits; the graph is captured on a private stream and launched on `stream`, which may
+ * be the null stream); VIP_DEBUG=1 prints solver progress to stderr. */
 int vip_create(void** out, int device, void* stream);
 
 /* Release every device allocation of the context and the context itself. */

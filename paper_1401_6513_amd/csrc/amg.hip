@@ -672,6 +672,13 @@ __global__ void k_cell_map(int64_t ncell, const int64_t* occ, const int64_t* idx
 
 void amg_free(Ctx* c) {
   Amg& g = c->amg;
+  for (int k = 0; k < 2; ++k) {
+    if (g.coarse_exec[k]) (void)hipGraphExecDestroy(g.coarse_exec[k]);
+    g.coarse_exec[k] = nullptr;
+    g.coarse_out[k] = nullptr;
+  }
+  if (g.cap_stream) (void)hipStreamDestroy(g.cap_stream);
+  g.cap_stream = nullptr;
   for (size_t l = 0; l < g.lv.size(); ++l) {
     AmgLevel& L = g.lv[l];
     if (l > 0) ell_free(L.A);
@@ -993,35 +1000,23 @@ __global__ void k_pass_one(const T* src, T* dst) {
   if (threadIdx.x == 0) dst[0] = src[0];
 }
 
-// x = M^-1 b for the first n entries (one V-cycle); the border entry is passed through.
-// With pre_fine == false the finest level skips its pre-smoothing sweep (a
-// non-symmetric V(0,1) cycle there, for BiCGStab only).
 template <typename T>
-int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
+static T* level_buf(Ctx* c, int l, int k) {
+  if constexpr (sizeof(T) == 4) return c->amg.lv[l].w32[k];
+  else return c->amg.lv[l].w64[k];
+}
+
+// Pre-smoothing and restriction on levels [l0, l1): rhs is level l0's right-hand side (level
+// l > 0 holds its own in buffer 0 and ping-pongs the iterate between buffers 1 and 2); cur[l]
+// becomes the pre-smoothed iterate (null when level 0 skips the pre-smoothing).  Returns the
+// right-hand side of level l1.
+template <typename T>
+static int descend(Ctx* c, hipStream_t st, int l0, int l1, const T* rhs, bool pre_fine, std::vector<T*>& cur,
+                   const T** rhs_out) {
   Amg& g = c->amg;
-  hipStream_t st = c->stream;
   const int* on = &c->sc->active[0];   // skip the cycle once the solve has stopped on the device
-  const int nl = static_cast<int>(g.lv.size());
-  auto w = [&](int l, int k) -> T* {
-    if constexpr (sizeof(T) == 4) return g.lv[l].w32[k];
-    else return g.lv[l].w64[k];
-  };
-  const T* inv;
-  if constexpr (sizeof(T) == 4) inv = g.cinv32;
-  else inv = g.cinv;
-  if (nl == 1) {
-    // the whole system is the coarsest level: apply its inverse, bordered if singular
-    const int64_t r = border ? g.m1 : g.m;
-    k_dense_apply<T><<<(r * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(r, r, g.m1, inv, b, x, on);
-    return VIP_OK;
-  }
-  // Level l holds its right-hand side in w(l,0) (l > 0) and ping-pongs the iterate between
-  // w(l,1) and w(l,2); cur[l] is the pre-smoothed iterate (or null when level 0 skips the
-  // pre-smoothing), the other buffer takes the residual and later the corrected iterate.
-  const T gamma = static_cast<T>(c->amg_gamma);
-  std::vector<T*> cur(nl, nullptr);
-  const T* rhs = b;
-  for (int l = 0; l < nl - 1; ++l) {
+  auto w = [&](int l, int k) { return level_buf<T>(c, l, k); };
+  for (int l = l0; l < l1; ++l) {
     const AmgLevel& L = g.lv[l];
     const bool pre = l > 0 || pre_fine;
     const int nu = l == 0 ? c->amg_nu : c->amg_nu_coarse;
@@ -1065,11 +1060,22 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
                                                                w(l + 1, 0), on);
     rhs = w(l + 1, 0);
   }
-  T* coarse_out = w(nl - 1, 1);
-  k_dense_apply<T><<<(g.m * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(g.m, g.m, g.m1, inv, rhs,
-                                                                         coarse_out, on);
-  const T* xc = coarse_out;
-  for (int l = nl - 2; l >= 0; --l) {
+  *rhs_out = rhs;
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+// Coarse correction and post-smoothing on levels l1-1 down to l0, from the coarse iterate xc
+// of level l1.  Level 0's right-hand side is b and its last sweep writes x; *xc_out is the
+// corrected iterate of level l0.
+template <typename T>
+static int ascend(Ctx* c, hipStream_t st, int l0, int l1, const T* b, const T* xc, T* x,
+                  const std::vector<T*>& cur, const T** xc_out) {
+  Amg& g = c->amg;
+  const int* on = &c->sc->active[0];
+  auto w = [&](int l, int k) { return level_buf<T>(c, l, k); };
+  const T gamma = static_cast<T>(c->amg_gamma);
+  for (int l = l1 - 1; l >= l0; --l) {
     const AmgLevel& L = g.lv[l];
     const int nu = l == 0 ? c->amg_nu : c->amg_nu_coarse;
     const T* bl = (l == 0) ? b : w(l, 0);
@@ -1108,6 +1114,92 @@ int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
     }
     xc = y;
   }
+  *xc_out = xc;
+  VIP_HIP_TRY(c, hipGetLastError());
+  return VIP_OK;
+}
+
+// The cycle below the finest level: from level 1's right-hand side (its buffer 0) down to the
+// coarsest solve and back; the corrected iterate of level 1 ends in one of its own buffers,
+// the same one every cycle.
+template <typename T>
+static int coarse_cycle(Ctx* c, hipStream_t st, const T** xc_out) {
+  Amg& g = c->amg;
+  const int nl = static_cast<int>(g.lv.size());
+  std::vector<T*> cur(nl, nullptr);
+  const T* rhs = nullptr;
+  VIP_TRY(descend<T>(c, st, 1, nl - 1, level_buf<T>(c, 1, 0), true, cur, &rhs));
+  const T* inv;
+  if constexpr (sizeof(T) == 4) inv = g.cinv32;
+  else inv = g.cinv;
+  T* coarse_out = level_buf<T>(c, nl - 1, 1);
+  k_dense_apply<T><<<(g.m * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(
+      g.m, g.m, g.m1, inv, rhs, coarse_out, &c->sc->active[0]);
+  VIP_HIP_TRY(c, hipGetLastError());
+  return ascend<T>(c, st, 1, nl - 1, nullptr, coarse_out, nullptr, cur, xc_out);
+}
+
+// The coarse cycle as a graph launch: its ~4 launches per level are mostly a few microseconds
+// each, and launched one by one after a host round trip the device idles between them.  The
+// graph is captured once, on a private stream of its own (so that the caller's stream may be
+// the null stream, which cannot be captured), and launched on the caller's stream.  It holds
+// only kernel nodes; the kernels read the solve's active flag, so a stopped solve skips the
+// work of a launch as it does without the graph.
+template <typename T>
+static int coarse_cycle_graph(Ctx* c, const T** xc_out) {
+  Amg& g = c->amg;
+  const int key = sizeof(T) == 4 ? 1 : 0;
+  if (!g.coarse_exec[key]) {
+    if (!g.cap_stream) VIP_HIP_TRY(c, hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
+    hipStream_t st = g.cap_stream;
+    VIP_HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const T* out = nullptr;
+    const int rc = coarse_cycle<T>(c, st, &out);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc != VIP_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess || !graph) return set_error(c, VIP_E_HIP, "capturing the coarse V-cycle");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess || !exec) return set_error(c, VIP_E_HIP, "instantiating the coarse V-cycle");
+    g.coarse_exec[key] = exec;
+    g.coarse_out[key] = const_cast<T*>(out);
+  }
+  VIP_HIP_TRY(c, hipGraphLaunch(g.coarse_exec[key], c->stream));
+  *xc_out = static_cast<const T*>(g.coarse_out[key]);
+  return VIP_OK;
+}
+
+// x = M^-1 b for the first n entries (one V-cycle); the border entry is passed through.
+// With pre_fine == false the finest level skips its pre-smoothing sweep (a
+// non-symmetric V(0,1) cycle there, for BiCGStab only).
+template <typename T>
+int amg_apply(Ctx* c, const T* b, T* x, bool border, bool pre_fine) {
+  Amg& g = c->amg;
+  hipStream_t st = c->stream;
+  const int* on = &c->sc->active[0];   // skip the cycle once the solve has stopped on the device
+  const int nl = static_cast<int>(g.lv.size());
+  if (nl == 1) {
+    // the whole system is the coarsest level: apply its inverse, bordered if singular
+    const T* inv;
+    if constexpr (sizeof(T) == 4) inv = g.cinv32;
+    else inv = g.cinv;
+    const int64_t r = border ? g.m1 : g.m;
+    k_dense_apply<T><<<(r * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(r, r, g.m1, inv, b, x, on);
+    return VIP_OK;
+  }
+  std::vector<T*> cur(nl, nullptr);
+  const T* rhs1 = nullptr;
+  VIP_TRY(descend<T>(c, st, 0, 1, b, pre_fine, cur, &rhs1));
+  const T* xc = nullptr;
+  if (!c->no_graph) VIP_TRY(coarse_cycle_graph<T>(c, &xc));
+  else VIP_TRY(coarse_cycle<T>(c, st, &xc));
+  const T* x0 = nullptr;
+  VIP_TRY(ascend<T>(c, st, 0, 1, b, xc, x, cur, &x0));
   ++c->vcycle;
   if (border) {
     // the border entry passes through (one thread; a runtime copy would take a blit launch)

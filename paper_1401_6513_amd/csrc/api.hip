@@ -163,6 +163,8 @@ int vip_create(void** out, int device, void* stream) {
   c->no_delta = (nd && nd[0] == '1') ? 1 : 0;
   const char* nf = std::getenv("VIP_NO_FUSE");
   c->no_fuse = (nf && nf[0] == '1') ? 1 : 0;
+  const char* ng = std::getenv("VIP_NO_GRAPH");
+  c->no_graph = (ng && ng[0] == '1') ? 1 : 0;
   const char* pre = std::getenv("VIP_AMG_PRE_FINE");
   c->amg_pre_fine = (pre && pre[0] == '0') ? 0 : 1;
   if (const char* g = std::getenv("VIP_AMG_GAMMA")) c->amg_gamma = std::min(2.0, std::max(0.5, std::atof(g)));

@@ -246,6 +246,12 @@ struct Amg {
   float* cinv32 = nullptr;
   int64_t m = 0, m1 = 0;      // coarsest rows, with the border row if singular
   bool ready = false;
+  // the V-cycle below the finest level (levels 1.. and the coarsest solve: the same launches
+  // on the same buffers every cycle) captured once per precision, [0] FP64 and [1] FP32, and
+  // the level-1 buffer that ends holding its corrected iterate
+  hipGraphExec_t coarse_exec[2] = {nullptr, nullptr};
+  void* coarse_out[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;   // the stream the graphs are captured on (never run on)
 };
 
 struct Timing {
@@ -314,6 +320,7 @@ struct Ctx {
   int cnn_layered = 0;            // VIP_CNN_LAYERED=1: learned start inference layer by layer
   int no_delta = 0;               // VIP_NO_DELTA=1: general rows read int32 columns, not int16 deltas
   int no_fuse = 0;                // VIP_NO_FUSE=1: the FP32 predictor iterates with four vector passes
+  int no_graph = 0;               // VIP_NO_GRAPH=1: the coarse V-cycle levels launch one by one
   // V-cycle settings: over-correction of the piecewise-constant coarse correction (plain
   // aggregation makes the Galerkin coarse operators too stiff by about 2 for 2x2 aggregates)
   // and damped Jacobi sweeps per level; measured best on the cylinder and triangle node sets

@@ -456,8 +456,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--helmholtz-tol", type=float, default=None,
                     help="tolerance of the predictor solves (default: the library's)")
-    ap.add_argument("--inner-tol", type=float, default=1e-4,
-                    help="relative tolerance of the FP32 inner solve (mixed path)")
+    ap.add_argument("--inner-tol", type=float, default=1e-5,
+                    help="relative tolerance of the FP32 inner solves (mixed paths; the library's "
+                         "default)")
     ap.add_argument("--paths", default="learned,mixed,extrap,fp64,fp64x")
     ap.add_argument("--workload", default="lattice", choices=["lattice", "refined"],
                     help="lattice: cylinder + triangle on uniform lattices (the headline workload); "

@@ -81,7 +81,7 @@ typedef struct {
   double poisson_tol;     /* ||b - L phi||_2 / ||b||_2 in FP64; default 1e-8 */
   double helmholtz_tol;   /* same measure for eq. 12; default 1e-12 */
   double inner_tol;       /* relative tolerance of each FP32 inner solve (MIXED: pressure and
-                             predictor solves); default 1e-4 */
+                             predictor solves); default 1e-5 */
   int max_iters;          /* Krylov iteration limit per solve; default 200000 */
   int check_every;        /* iterations between host convergence checks; default 16 */
   int preconditioner;     /* VIP_PC_*; default VIP_PC_AMG: aggregation multigrid V-cycle

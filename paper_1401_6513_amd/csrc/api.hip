@@ -140,7 +140,7 @@ void vip_default_options(vip_options* o) {
   o->period[1] = 0.0;
   o->poisson_tol = 1e-8;
   o->helmholtz_tol = 1e-12;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 1e-5;
   o->max_iters = 200000;
   o->check_every = 16;
   o->preconditioner = VIP_PC_AMG;

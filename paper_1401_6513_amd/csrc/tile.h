@@ -81,21 +81,21 @@ __device__ __forceinline__ void tile_stage(const TileView& V, int64_t k, const T
       V, k, [&](int s, int32_t node) __attribute__((always_inline)) { return x[s][node]; }, t, m, load_x);
 }
 
-// The same with the staged values given by xf(s, node) (system s at a node).
-template <typename T, int NS, typename F>
-__device__ __forceinline__ void tile_stage_fn(const TileView& V, int64_t k, F&& xf,
-                                              T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x) {
+// Staging shape: wave w stages halo rows w, w + 4, ... at columns 0..63 (lane = column, one
+// contiguous segment per load); the first 4 kTileLdsH threads stage columns 64..67 of every row.
+// Few index values live across the tile loop this way (with a flat element index the per-thread
+// row, column and LDS address of every element were kept in registers).
+constexpr int kStageWaves = kBlock / 64;
+constexpr int kStageRows = kTileLdsH / kStageWaves;   // halo rows per wave
+constexpr int kStageEdge = kTileLdsW - 64;            // columns past the wavefront width
+static_assert(kTileLdsH % kStageWaves == 0 && kStageEdge > 0 && kStageEdge * kTileLdsH <= kBlock,
+              "tile staging shape");
+
+// The nodes this thread stages for the tile of record m: node[j] for halo row wave + 4 j at
+// its lane's column, node[kStageRows] for its edge element; -1 where there is no node.
+__device__ __forceinline__ void tile_stage_nodes(const TileView& V, const TileMeta& m,
+                                                 int32_t (&node)[kStageRows + 1]) {
   const int tid = static_cast<int>(threadIdx.x);
-  __syncthreads();
-  if (tid < kTileRecWords) m.w[tid] = V.rec[k * kTileRecWords + tid];
-  __syncthreads();
-  if (!load_x) return;
-  // wave w stages halo rows w, w + 4, ... at columns 0..63 (lane = column, one contiguous
-  // segment per load); the first 4 kTileLdsH threads stage columns 64..67 of every row.  Few
-  // index values live across the tile loop this way (with a flat element index the per-thread
-  // row, column and LDS address of every element were kept in registers).
-  constexpr int kWaves = kBlock / 64, kRowsPerWave = kTileLdsH / kWaves, kEdge = kTileLdsW - 64;
-  static_assert(kTileLdsH % kWaves == 0 && kEdge > 0 && kEdge * kTileLdsH <= kBlock, "tile staging shape");
   const int wave = tid >> 6, lane = tid & 63;
   const int tx = m.tx(), ty = m.ty();
   auto node_at = [&](int r, int cc) __attribute__((always_inline)) -> int32_t {
@@ -105,23 +105,43 @@ __device__ __forceinline__ void tile_stage_fn(const TileView& V, int64_t k, F&& 
     if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) return V.node_of[static_cast<int64_t>(gy) * V.W + gx];
     return -1;
   };
-  int32_t node[kRowsPerWave + 1];
 #pragma unroll
-  for (int j = 0; j < kRowsPerWave; ++j) node[j] = node_at(wave + j * kWaves, lane);
-  const bool edge = tid < kEdge * kTileLdsH;
-  node[kRowsPerWave] = edge ? node_at(tid / kEdge, 64 + tid % kEdge) : -1;
-  T val[NS][kRowsPerWave + 1];
+  for (int j = 0; j < kStageRows; ++j) node[j] = node_at(wave + j * kStageWaves, lane);
+  node[kStageRows] = tid < kStageEdge * kTileLdsH ? node_at(tid / kStageEdge, 64 + tid % kStageEdge) : -1;
+}
+
+// Store this thread's staged values (one per system and staged element) into the LDS tile.
+template <typename T, int NS>
+__device__ __forceinline__ void tile_stage_store(const T (&val)[NS][kStageRows + 1],
+                                                 T (&t)[NS][kTileLdsH][kTileLdsW]) {
+  const int tid = static_cast<int>(threadIdx.x);
+  const int wave = tid >> 6, lane = tid & 63;
 #pragma unroll
-  for (int j = 0; j <= kRowsPerWave; ++j)
+  for (int j = 0; j < kStageRows; ++j)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) t[s][wave + j * kStageWaves][lane] = val[s][j];
+  if (tid < kStageEdge * kTileLdsH)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) t[s][tid / kStageEdge][64 + tid % kStageEdge] = val[s][kStageRows];
+}
+
+// The same with the staged values given by xf(s, node) (system s at a node).
+template <typename T, int NS, typename F>
+__device__ __forceinline__ void tile_stage_fn(const TileView& V, int64_t k, F&& xf,
+                                              T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta& m, bool load_x) {
+  const int tid = static_cast<int>(threadIdx.x);
+  __syncthreads();
+  if (tid < kTileRecWords) m.w[tid] = V.rec[k * kTileRecWords + tid];
+  __syncthreads();
+  if (!load_x) return;
+  int32_t node[kStageRows + 1];
+  tile_stage_nodes(V, m, node);
+  T val[NS][kStageRows + 1];
+#pragma unroll
+  for (int j = 0; j <= kStageRows; ++j)
 #pragma unroll
     for (int s = 0; s < NS; ++s) val[s][j] = node[j] >= 0 ? xf(s, node[j]) : T(0);
-#pragma unroll
-  for (int j = 0; j < kRowsPerWave; ++j)
-#pragma unroll
-    for (int s = 0; s < NS; ++s) t[s][wave + j * kWaves][lane] = val[s][j];
-  if (edge)
-#pragma unroll
-    for (int s = 0; s < NS; ++s) t[s][tid / kEdge][64 + tid % kEdge] = val[s][kRowsPerWave];
+  tile_stage_store<T, NS>(val, t);
   __syncthreads();
 }
 
@@ -155,6 +175,72 @@ __device__ __forceinline__ void tile_walk(const TileView& V, Tile&& tile, Irr&& 
     const int64_t xcd = b % kNumXcd, j = b / kNumXcd, per = V.tile_blocks / kNumXcd;
     const int64_t t1 = V.ntiles * (xcd + 1) / kNumXcd;
     for (int64_t k = V.ntiles * xcd / kNumXcd + j; k < t1; k += per) tile(k);
+  }
+}
+
+// A software-pipelined tile walk for kernels whose staged values come from plain loads: while a
+// tile is computed from LDS, the loads of the block's next tile are already in flight (its
+// operands held in registers) and the record of the tile after that too, so a block always has
+// memory requests outstanding (with one tile staged at a time, a block idled between its
+// compute and its next tile's loads).  load(s, node) issues the loads of system s's operands at
+// a node and returns them as R; value(s, r) forms the staged value from them (computed when the
+// tile is stored, a tile later, with the arithmetic of the unpipelined staging).  issue(k, m) is
+// called after tile k is in LDS and before the next tile's loads are issued: the place for the
+// tile's own row loads (rhat), which the in-order completion counter would otherwise make wait
+// for the whole prefetch; compute(k, m) then computes tile k from LDS (record m).  The record
+// buffers m[2] alternate between consecutive tiles.  Irregular rows as in tile_walk.
+template <typename T, int NS, typename R, typename Load, typename Value, typename Issue, typename Compute,
+          typename Irr>
+__device__ __forceinline__ void tile_walk_pp(const TileView& V, T (&t)[NS][kTileLdsH][kTileLdsW], TileMeta (&m)[2],
+                                             Load&& load, Value&& value, Issue&& issue, Compute&& compute,
+                                             Irr&& irr) {
+  if (static_cast<int>(blockIdx.x) < V.irr_blocks) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < V.nirr;
+         k += static_cast<int64_t>(V.irr_blocks) * blockDim.x)
+      irr(static_cast<int64_t>(V.irr[k]));
+    return;
+  }
+  const int tid = static_cast<int>(threadIdx.x);
+  const int64_t b = static_cast<int64_t>(blockIdx.x) - V.irr_blocks;
+  const int64_t xcd = b % kNumXcd, j = b / kNumXcd, per = V.tile_blocks / kNumXcd;
+  const int64_t t0 = V.ntiles * xcd / kNumXcd + j, t1 = V.ntiles * (xcd + 1) / kNumXcd;
+  if (t0 >= t1) return;   // block-uniform
+  R raw[NS][kStageRows + 1];
+  int32_t node[kStageRows + 1];
+  auto issue_loads = [&](const TileMeta& mm) __attribute__((always_inline)) {
+    tile_stage_nodes(V, mm, node);
+#pragma unroll
+    for (int jj = 0; jj <= kStageRows; ++jj)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) raw[s][jj] = load(s, node[jj] >= 0 ? node[jj] : 0);
+  };
+  // prologue: record and loads of the first tile, record of the second
+  uint32_t recw = tid < kTileRecWords ? V.rec[t0 * kTileRecWords + tid] : 0u;
+  if (tid < kTileRecWords) m[0].w[tid] = recw;
+  __syncthreads();
+  issue_loads(m[0]);
+  if (t0 + per < t1 && tid < kTileRecWords) recw = V.rec[(t0 + per) * kTileRecWords + tid];
+  int cur = 0;
+  for (int64_t k = t0; k < t1; k += per) {
+    __syncthreads();   // every lane is done with the previous tile's LDS values and record
+    {
+      T val[NS][kStageRows + 1];
+#pragma unroll
+      for (int jj = 0; jj <= kStageRows; ++jj)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) val[s][jj] = node[jj] >= 0 ? value(s, raw[s][jj]) : T(0);
+      tile_stage_store<T, NS>(val, t);
+    }
+    const bool next = k + per < t1;
+    if (next && tid < kTileRecWords) m[cur ^ 1].w[tid] = recw;
+    __syncthreads();   // tile k staged; the next tile's record in place
+    issue(k, m[cur]);
+    if (next) {
+      issue_loads(m[cur ^ 1]);
+      if (k + 2 * per < t1 && tid < kTileRecWords) recw = V.rec[(k + 2 * per) * kTileRecWords + tid];
+    }
+    compute(k, m[cur]);
+    cur ^= 1;
   }
 }
 

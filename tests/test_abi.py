@@ -85,7 +85,7 @@ def test_default_options_through_the_abi():
     o = vip.default_options()
     assert (o.weight, o.identity, o.precision, o.krylov, o.warmstart) == (0, 0, 0, 0, 0)
     assert o.min_neighbours == 12 and o.vip_offset == 0.5
-    assert o.poisson_tol == 1e-8 and o.helmholtz_tol == 1e-12 and o.inner_tol == 1e-4
+    assert o.poisson_tol == 1e-8 and o.helmholtz_tol == 1e-12 and o.inner_tol == 1e-5
 
 
 def test_product_code_never_imports_the_oracle():

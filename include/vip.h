@@ -229,7 +229,8 @@ int vip_reset_history(void* ctx);
  * Delta phi + lambda = rhs, sum(phi) = 0.
  *
  *  rhs  device, [n_nodes] FP64 (boundary-row entries are the row right-hand sides).
- *  phi  device, [n_nodes] FP64: start vector on entry if use_x0 != 0, solution on exit.
+ *  phi  device, [n_nodes] FP64: start vector on entry if use_x0 != 0, solution on exit
+ *       (the last iterate after VIP_E_NOT_CONVERGED; unspecified after other errors).
  *  tol  relative FP64 residual target.
  *  stats host, may be NULL (poisson_* fields and border_lambda are filled).
  */

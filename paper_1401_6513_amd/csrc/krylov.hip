@@ -567,7 +567,7 @@ __global__ void k_fin_residual(const double* partials, int64_t nb, int64_t n, in
 
 // ---- BiCGStab -------------------------------------------------------------------------------------
 template <typename T, int NS>
-__global__ void k_bicg_init(Vec<T> V, int64_t nvec, KrylovScalars* sc) {
+__global__ void k_bicg_init(Vec<T> V, int64_t nvec, KrylovScalars* sc, int zero_x) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i < nvec) {
 #pragma unroll
@@ -576,6 +576,7 @@ __global__ void k_bicg_init(Vec<T> V, int64_t nvec, KrylovScalars* sc) {
       V.rhat[o] = V.r[o];
       V.p[o] = T(0);
       V.v[o] = T(0);
+      if (zero_x) V.x[o] = T(0);
     }
   }
   if (i == 0) {
@@ -1551,7 +1552,7 @@ Vec<T> vec_sys(const Vec<T>& V, int q) {
 template <typename VT, typename T, int NS>
 int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit, int* iters,
             bool time_spmv, const double* bnorm2, bool amg = false, bool* bad = nullptr,
-            int* hint = nullptr) {
+            int* hint = nullptr, bool zero_x = false) {
   VIP_TRY(check_mat(c, A, NS));
   const int64_t nvec = A.n + A.border;
   const int64_t g_vec = grid_for(nvec);
@@ -1583,9 +1584,12 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
   double* part = c->partials;
   KrylovScalars* sc = c->sc;
   hipStream_t st = c->stream;
+  // zero_x: the iterate starts from 0 (set here, with the other start vectors)
   if (m == kBiCGStab) {
-    k_bicg_init<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc);
+    k_bicg_init<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc, zero_x ? 1 : 0);
   } else {
+    if (zero_x)
+      for (int s = 0; s < NS; ++s) k_fill<T><<<g_vec, kBlock, 0, st>>>(nvec, V.x + s * V.stride, T(0));
     if constexpr (NS == 1) {
       if (amg) VIP_TRY(amg_apply<T>(c, V.r, V.s, false, true));
     }
@@ -1836,22 +1840,30 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   const bool use_amg = c->opt.preconditioner == VIP_PC_AMG;
   if (use_amg && !c->amg.ready) VIP_TRY(amg_setup(c));
   VIP_TRY(ensure_ws(c, 11 * stride, mixed ? 10 * stride : 1));
-  double* b = c->ws + 8 * stride;       // right-hand side with border entry 0
-  double* x = c->ws + 10 * stride;      // FP64 solution (bordered)
+  // a system that is neither bordered nor projected is solved in the caller's buffers (b is
+  // only read, x = phi) when they do not overlap; else b and x are copies with the border entry
+  const bool direct = !border && !project && (rhs + n <= phi || phi + n <= rhs);
+  double* bw = c->ws + 8 * stride;      // right-hand side with border entry 0
+  const double* b = direct ? rhs : bw;
+  double* x = direct ? phi : c->ws + 10 * stride;   // FP64 solution (bordered)
   hipStream_t s = c->stream;
   const int64_t gv = grid_for(stride);
   VIP_TRY(ensure_partials(c, gv, 3));
-  k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rhs, b);
-  k_fill<double><<<1, 64, 0, s>>>(1, b + n, 0.0);
+  if (!direct) {
+    k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, rhs, bw);
+    k_fill<double><<<1, 64, 0, s>>>(1, bw + n, 0.0);
+  }
   double lambda_proj = 0.0;
   if (project) {
     k_sum<<<red_grid(n), kBlock, 0, s>>>(n, b, c->partials);
     k_fin_mean<<<1, kBlock, 0, s>>>(c->partials, red_grid(n), n, c->sc);
-    k_sub_mean<<<grid_for(n), kBlock, 0, s>>>(n, b, b, c->sc);
+    k_sub_mean<<<grid_for(n), kBlock, 0, s>>>(n, bw, bw, c->sc);
     VIP_TRY(sync_scalars(c));
     lambda_proj = c->sc_host->mean;
   }
-  if (use_x0) {
+  if (direct) {
+    if (!use_x0) k_fill<double><<<grid_for(n), kBlock, 0, s>>>(n, x, 0.0);
+  } else if (use_x0) {
     k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, phi, x);
     k_fill<double><<<1, 64, 0, s>>>(1, x + n, 0.0);
   } else {
@@ -1931,13 +1943,12 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
       }
       prev = relres;
       const double rr_outer = c->sc_host->rr[0];
-      k_fill<float><<<gv, kBlock, 0, s>>>(stride, d32, 0.0f);
       // inner: A32 d = r, from d = 0; its residual starts as r itself
       int it = 0;
       bool bad = false;
       const double target = std::max(inner, 0.5 * tol / relres);
       VIP_TRY((iterate<float, float, 1>(c, m, A32, V, target, std::min(kInnerCap, maxit - total_it), &it, true,
-                                        &rr_outer, use_amg, &bad, &c->hint_p32[std::min(outer - 1, 3)])));
+                                        &rr_outer, use_amg, &bad, &c->hint_p32[std::min(outer - 1, 3)], true)));
       total_it += it;
       if (bad) {
         fallback = true;   // x is unchanged: the broken correction is not added
@@ -1959,7 +1970,7 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
     k_sum<<<red_grid(n), kBlock, 0, s>>>(n, x, c->partials);
     k_fin_mean<<<1, kBlock, 0, s>>>(c->partials, red_grid(n), n, c->sc);
     k_sub_mean<<<grid_for(n), kBlock, 0, s>>>(n, x, phi, c->sc);
-  } else {
+  } else if (!direct) {
     k_copy<double, double><<<grid_for(n), kBlock, 0, s>>>(n, x, phi);
   }
   double lam = lambda_proj;
@@ -2083,9 +2094,8 @@ int helmholtz_solve(Ctx* c, const double* ru, const double* rv, double** us_out,
     if (mixed) {
       // FP32 correction d from 0 for the FP64 residual r, to `target` relative to |r|
       const double target = std::max(inner, 0.5 * tol / worst);
-      k_fill<float><<<grid_for(2 * stride), kBlock, 0, s>>>(2 * stride, d32, 0.0f);
       VIP_TRY((iterate<float, float, 2>(c, kBiCGStab, H32, V32, target, c->opt.max_iters - total, &it, false,
-                                        rr, false, &bad, &c->hint_h32[std::min(outer, 3)])));
+                                        rr, false, &bad, &c->hint_h32[std::min(outer, 3)], true)));
       total += it;
       if (bad) return set_error(c, VIP_E_NONFINITE, "FP32 predictor correction produced a non-finite residual");
       k_add_scaled<<<grid_for(2 * stride), kBlock, 0, s>>>(2 * stride, stride, n, x, d32, c->dinv[1], c->dinv[2]);

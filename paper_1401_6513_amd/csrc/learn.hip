@@ -1601,7 +1601,7 @@ int learn_finish(Ctx* c, const double* b, const double* phi, bool capture) {
                                                        s.t);
   }
   if (L.have_eprev) {
-    k_copy_d<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.eprev, L.eprev2);   // the change before
+    std::swap(L.eprev, L.eprev2);   // the change before (its buffer swapped in, no copy)
     L.have_eprev2 = true;
   }
   k_diff<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, phi, L.phi_prev, L.eprev);

@@ -57,6 +57,7 @@ HBM_PROFILES = {
     "pred_e": ("hbm_counters_predictor_e_cylinder_h128.md", ("krylov.hip",)),
     "pred_ts": ("hbm_counters_predictor_ts_cylinder_h128.md", ("krylov.hip", "tile.h")),
     "pred_spmv": ("hbm_counters_predictor_spmv_cylinder_h128.md", ("krylov.hip", "tile.h")),
+    "pred_spmv1": ("hbm_counters_predictor_spmv1_cylinder_h128.md", ("krylov.hip", "tile.h")),
     "sweep0": ("hbm_counters_finest_sweep_cylinder_h128.md", ("amg.hip", "tile.h")),
     "pred_rhs": ("hbm_counters_predictor_rhs_cylinder_h128.md", ("step.hip", "tile.h")),
 }
@@ -125,6 +126,7 @@ TIMED = {2: "pred_spmv", 3: "pred_t", 4: "pred_x", 5: "sweep0", 6: "pred_rhs"}
 KERNEL_NAMES = {
     "pres_spmv": "k_bicg_v<%s,%s,1> (pressure SpMV)",
     "pred_spmv": "k_bicg_v<float,float,2> (predictor SpMV, both velocity systems)",
+    "pred_spmv1": "k_bicg_v<float,float,1> x 2 (predictor SpMV, one launch per velocity system; per iteration)",
     "pred_t": "k_bicg_t<float,float,1,*,true> (predictor t = A s with s = r - alpha v formed inside, per system)",
     "pred_ts": "k_bicg_ts<float> (predictor t = A s with s = r - alpha v formed inside and the five sums, per system)",
     "pred_e": "k_bicg_e<float,2> (predictor: the last iteration's x and r update with the new p, both systems)",
@@ -166,6 +168,7 @@ def kernel_bytes(ctx, spec, fp32):
     # x, r, p; its t kernel reads r, v (s formed inside) and r-hat and writes t
     out["pred_e"] = 2 * 8 * 4 * n
     out["pred_ts"] = out["pred_t"]
+    out["pred_spmv1"] = out["pred_spmv"]
     # finest level: y, b in, out written; irregular rows add values, columns, row sum, damped diagonal
     out["sweep0"] = 3 * 4 * n + irregular(nc[4], 4, 8) + rec
     # u, v in; the AB2 history in and out (2 vectors each way); r_u, r_v out; VIP spacings d_ew,
@@ -642,6 +645,8 @@ def main():
             # t kernel with five sums instead of the separate p, s and x passes
             timed["pred_e"] = timed.pop("pred_x")
             timed["pred_ts"] = timed.pop("pred_t")
+            if "pred_spmv" in timed:
+                timed["pred_spmv1"] = timed.pop("pred_spmv")
         for name, (avg_ms, count) in timed.items():
             if count <= 0 or avg_ms <= 0:
                 continue

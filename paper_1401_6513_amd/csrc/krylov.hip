@@ -622,9 +622,14 @@ constexpr int kWavesFor = (sizeof(T) == 4 && NS == 1) ? (FS ? 6 : 8) : 1;
 template <typename T, int NS>
 constexpr bool kPipelinedV = sizeof(T) == 4 && NS == 2;
 
-// v = A ph; partial sums of rhat . v (and of ph for the border row)
+// v = A ph; partial sums of rhat . v (and of ph for the border row).  A launch may take system q0
+// of a two-system solve alone (A, V viewed at that system): its block sums then land at
+// partials[pstride b + 2 q0 + a], interleaved with the other system's launch as a two-system
+// launch stores them.
 template <typename VT, typename T, int NS, bool GEN>
-__global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_v(Mat<VT> A, Vec<T> V, double* partials, const KrylovScalars* sc) {
+__global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_v(Mat<VT> A, Vec<T> V, double* partials,
+                                                                      const KrylovScalars* sc, int q0 = 0,
+                                                                      int pstride = 2 * NS) {
   __shared__ T lds[NS][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta2[2];
   TileMeta& meta = meta2[0];
@@ -635,7 +640,7 @@ __global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_v(Mat<VT> A
   double phn[NS];   // border unknowns (uniform)
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    use[s] = sc->active[s] != 0;
+    use[s] = sc->active[q0 + s] != 0;
     any = any || use[s];
     phn[s] = A.border ? static_cast<double>(V.ph[s * V.stride + A.n]) : 0.0;
   }
@@ -746,7 +751,7 @@ __global__ void __launch_bounds__(kBlock, (kWavesFor<T, NS>)) k_bicg_v(Mat<VT> A
         },
         slow);
   }
-  block_sum_store<2 * NS>(acc, partials);
+  block_sum_store<2 * NS>(acc, partials + 2 * q0, pstride);
 }
 
 // alpha = rho / (rhat . v), with the border row v[n] = sum(ph)
@@ -1610,10 +1615,16 @@ int iterate(Ctx* c, Method m, const Mat<VT>& A, Vec<T>& V, double tol, int maxit
             k_bicg_e<T, NS><<<g_vec, kBlock, 0, st>>>(V, nvec, sc);
           }
           {
+            // one launch per system: the single-system SpMV runs 8 waves per SIMD where the
+            // two-system one runs 4 (the block sums interleave, so the bits are the same)
             Timer tm(c, time_spmv);
             KTimer kt(c, c->ktime[kTimePredV], tpred);
-            if (A.tile_general) k_bicg_v<VT, T, NS, true><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
-            else k_bicg_v<VT, T, NS, false><<<r_rows, kBlock, 0, st>>>(A, V, part, sc);
+            for (int q = 0; q < NS; ++q) {
+              if (A.tile_general)
+                k_bicg_v<VT, T, 1, true><<<r_rows, kBlock, 0, st>>>(mat_sys(A, q), vec_sys(V, q), part, sc, q, 2 * NS);
+              else
+                k_bicg_v<VT, T, 1, false><<<r_rows, kBlock, 0, st>>>(mat_sys(A, q), vec_sys(V, q), part, sc, q, 2 * NS);
+            }
           }
           k_fin_bicg_v<T, NS><<<1, kBlock, 0, st>>>(part, r_rows, A.n, A.border, V, sc);
           for (int q = 0; q < NS; ++q) {

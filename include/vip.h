@@ -86,7 +86,8 @@ typedef struct {
   int check_every;        /* iterations between host convergence checks; default 16 */
   int preconditioner;     /* VIP_PC_*; default VIP_PC_AMG: aggregation multigrid V-cycle
                              (2x2-cell aggregates, Galerkin coarse matrices, damped Jacobi
-                             smoothing, dense coarsest solve), built at the first solve */
+                             smoothing, 2 sweeps before and after on every level; dense
+                             coarsest solve), built at the first solve */
   int learned_precond;    /* 1: with VIP_WS_LEARNED and VIP_P_MIXED on a non-singular lattice-based
                              pressure system, the learned network also preconditions every FP64
                              refinement pass: the pass adds alpha d + beta c, d the FP32 inner

@@ -14,10 +14,12 @@
 //     so the build is deterministic);
 //   * the coarsest matrix (bordered when the system is singular) is inverted
 //     once by Gauss-Jordan with partial pivoting and applied as a dense product;
-//   * one V-cycle with one damped Jacobi sweep before and after the coarse
-//     correction (optionally none before it on the finest level); every
-//     stencil pass gathers a single vector, the element-wise parts (sweep from
-//     zero, prolongation) run as separate light kernels.
+//   * one V-cycle with damped Jacobi sweeps before and after the coarse
+//     correction (two on every level by default; optionally
+//     none before it on the finest level); every stencil pass gathers a single
+//     vector; zero start, residual, restriction and prolongation are fused into
+//     the neighbouring launches where that pays, and the levels below the finest
+//     replay as one captured graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

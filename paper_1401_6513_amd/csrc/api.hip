@@ -168,7 +168,7 @@ int vip_create(void** out, int device, void* stream) {
   const char* pre = std::getenv("VIP_AMG_PRE_FINE");
   c->amg_pre_fine = (pre && pre[0] == '0') ? 0 : 1;
   if (const char* g = std::getenv("VIP_AMG_GAMMA")) c->amg_gamma = std::min(2.0, std::max(0.5, std::atof(g)));
-  if (const char* v = std::getenv("VIP_AMG_NU")) c->amg_nu = std::min(4, std::max(1, std::atoi(v)));
+  if (const char* v = std::getenv("VIP_AMG_NU")) c->amg_nu = std::min(8, std::max(1, std::atoi(v)));
   if (const char* v = std::getenv("VIP_AMG_NU_COARSE")) c->amg_nu_coarse = std::min(4, std::max(1, std::atoi(v)));
   vip_default_options(&c->opt);
   int ndev = 0;

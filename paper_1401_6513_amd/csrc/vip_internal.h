@@ -323,9 +323,12 @@ struct Ctx {
   int no_graph = 0;               // VIP_NO_GRAPH=1: the coarse V-cycle levels launch one by one
   // V-cycle settings: over-correction of the piecewise-constant coarse correction (plain
   // aggregation makes the Galerkin coarse operators too stiff by about 2 for 2x2 aggregates)
-  // and damped Jacobi sweeps per level; measured best on the cylinder and triangle node sets
+  // and damped Jacobi sweeps per level; measured best on the cylinder and triangle node sets.
+  // (Four finest-level sweeps took 3.4% less time a step in developed flow at h = 1/128, 2.5%
+  // more in the first steps from rest, but on the cylinder parity case at the 1e-8 Poisson
+  // tolerance one path's pressure then ended 1.6e-6 from the direct solve, over the 1e-6 budget.)
   double amg_gamma = 1.7;         // coarse-correction scaling (VIP_AMG_GAMMA)
-  int amg_nu = 2;                 // Jacobi sweeps before and after on the finest level (VIP_AMG_NU)
+  int amg_nu = 2;                 // Jacobi sweeps before and after on the finest level (VIP_AMG_NU, 1..8)
   int amg_nu_coarse = 2;          // the same on coarser levels (VIP_AMG_NU_COARSE)
   hipStream_t stream = nullptr;
   Error err{0, ""};

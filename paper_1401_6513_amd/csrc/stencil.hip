@@ -720,9 +720,15 @@ int vip_canon_setup(Ctx* c) {
       std::fprintf(stderr, "[vip] step tiles: %lld tiles, %lld irregular nodes\n",
                    static_cast<long long>(V.tpart.ntiles), static_cast<long long>(V.tpart.nirr));
   }
-  if (c->debug)
+  if (c->debug) {
     std::fprintf(stderr, "[vip] canonical VIP/node rows: %lld of %lld\n", static_cast<long long>(c->vcanon.count),
                  static_cast<long long>(c->n));
+    for (int o = 0; o < kVcOps && c->vcanon.count > 0; ++o) {
+      std::fprintf(stderr, "[vip] canonical runs of operator %d (dx0,len per dy = -3..3):", o);
+      for (int d = 0; d < kVcRows; ++d) std::fprintf(stderr, " (%d,%d)", V.dx0[o][d], V.len[o][d]);
+      std::fprintf(stderr, "\n");
+    }
+  }
   return VIP_OK;
 }
 

@@ -375,22 +375,48 @@ __device__ __forceinline__ void step_stage(const TileView& tv, int64_t k, const 
   __syncthreads();
 }
 
+// The canonical runs (dx0, len per stencil row dy = -3..3) of the five operators on a uniform
+// lattice with the default options (MLS support of at least 12 neighbours, VIP offset h/2):
+// the same on every such node set, whatever its spacing.  Kernels instantiated for it (FIX)
+// unroll every tap loop with constant LDS offsets, so the compiler reads each staged value
+// once per node for all five operators (21 pixels per field instead of 85 taps); the others
+// take the runs from the kernel arguments.  Same taps in the same order: the same bits.
+constexpr int8_t kLatDx0[kVcOps][kVcRows] = {{0, 0, -1, -1, -1, 0, 0},
+                                             {0, -1, -2, -2, -2, -1, 0},
+                                             {0, 0, -1, -2, -2, -1, 0},
+                                             {0, -1, -2, -2, -1, 0, 0},
+                                             {0, -1, -2, -2, -2, -1, 0}};
+constexpr int8_t kLatLen[kVcOps][kVcRows] = {{0, 2, 4, 4, 4, 2, 0},
+                                             {0, 2, 4, 4, 4, 2, 0},
+                                             {0, 0, 3, 5, 5, 3, 0},
+                                             {0, 3, 5, 5, 3, 0, 0},
+                                             {0, 3, 5, 5, 5, 3, 0}};
+
+bool vc_is_lattice_shape(const VC& C) {
+  for (int o = 0; o < kVcOps; ++o)
+    for (int d = 0; d < kVcRows; ++d)
+      if (C.len[o][d] != kLatLen[o][d] || (C.len[o][d] > 0 && C.dx0[o][d] != kLatDx0[o][d])) return false;
+  return true;
+}
+
 // Row products of a canonical node from the staged fields (local row ly, column lx); a field is
-// named by the pointer it was staged from.
-template <int NF>
+// named by the pointer it was staged from.  FIX: the runs are the lattice shape above.
+template <int NF, bool FIX = false>
 struct LdsRows {
   const VC& C;
   const double (&t)[NF][kStH][kStW];
   const double* const (&src)[NF];
   int ly, lx;
+  __device__ __forceinline__ int len(int o, int d) const { return FIX ? kLatLen[o][d] : C.len[o][d]; }
+  __device__ __forceinline__ int dx0(int o, int d) const { return FIX ? kLatDx0[o][d] : C.dx0[o][d]; }
   __device__ __forceinline__ int field(const double* f) const { return (NF > 1 && f == src[1]) ? 1 : 0; }
   __device__ __forceinline__ double run(int a, int o, int wo) const {
     double acc = 0.0;
     int k = 0;
 #pragma unroll
     for (int d = 0; d < kVcRows; ++d) {
-      const int L = C.len[o][d];
-      const double* tr = &t[a][ly + d][lx + kSH + C.dx0[o][d]];
+      const int L = len(o, d);
+      const double* tr = &t[a][ly + d][lx + kSH + dx0(o, d)];
       for (int q = 0; q < L; ++q) acc = fma(C.w[wo][k + q], tr[q], acc);
       k += L;
     }
@@ -403,8 +429,8 @@ struct LdsRows {
     int k = 0;
 #pragma unroll
     for (int d = 0; d < kVcRows; ++d) {
-      const int L = C.len[o][d];
-      const int c0 = lx + kSH + C.dx0[o][d];
+      const int L = len(o, d);
+      const int c0 = lx + kSH + dx0(o, d);
       for (int q = 0; q < L; ++q) {
         const double w = C.w[o][k + q];
         a = fma(w, t[a0][ly + d][c0 + q], a);
@@ -423,8 +449,8 @@ struct LdsRows {
     int k = 0;
 #pragma unroll
     for (int d = 0; d < kVcRows; ++d) {
-      const int L = C.len[4][d];
-      const int dx0 = C.dx0[4][d];
+      const int L = len(4, d);
+      const int dx0 = this->dx0(4, d);
       const int c0 = lx + kSH + dx0;
       for (int q = 0; q < L; ++q) {
         const double id = exact_id ? (d == 3 && dx0 + q == 0 ? 1.0 : 0.0) : C.w[4][k + q];
@@ -450,6 +476,7 @@ __device__ __forceinline__ void step_rows(const TileView& tv, const TileMeta& m,
   }
 }
 
+template <bool FIX>
 __global__ void __launch_bounds__(kBlock) k_predictor_rhs_tiles(TileView tv, int64_t n, Op m00, Op lap,
                                                                 const int32_t* rowlen, Vips V, VC C, Bnd B,
                                                                 const double* u, const double* v,
@@ -464,7 +491,7 @@ __global__ void __launch_bounds__(kBlock) k_predictor_rhs_tiles(TileView tv, int
       [&](int64_t tk) __attribute__((always_inline)) {
         step_stage<2>(tv, tk, src, t, m);
         step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
-          predictor_interior(LdsRows<2>{C, t, src, ly, lx}, n, i, m00, rowlen, V, u, v, nprev, first, dt, re,
+          predictor_interior(LdsRows<2, FIX>{C, t, src, ly, lx}, n, i, m00, rowlen, V, u, v, nprev, first, dt, re,
                              exact_id, ru, rv);
         });
       },
@@ -473,6 +500,7 @@ __global__ void __launch_bounds__(kBlock) k_predictor_rhs_tiles(TileView tv, int
       });
 }
 
+template <bool FIX>
 __global__ void __launch_bounds__(kBlock) k_divergence_tiles(TileView tv, Vips V, VC C, const int32_t* bpos,
                                                              const double* u, const double* v, double scale,
                                                              double* b) {
@@ -484,12 +512,13 @@ __global__ void __launch_bounds__(kBlock) k_divergence_tiles(TileView tv, Vips V
       [&](int64_t tk) __attribute__((always_inline)) {
         step_stage<2>(tv, tk, src, t, m);
         step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
-          b[i] = divergence_at(LdsRows<2>{C, t, src, ly, lx}, V, i, u, v) * scale;
+          b[i] = divergence_at(LdsRows<2, FIX>{C, t, src, ly, lx}, V, i, u, v) * scale;
         });
       },
       [&](int64_t i) __attribute__((always_inline)) { divergence_node(i, V, C, bpos, u, v, scale, b); });
 }
 
+template <bool FIX>
 __global__ void __launch_bounds__(kBlock) k_project_tiles(TileView tv, Vips V, VC C, Op lap, const int32_t* bpos,
                                                           const double* us, const double* vs, const double* phi,
                                                           double dt, double c, double* u, double* v, double* p) {
@@ -501,7 +530,7 @@ __global__ void __launch_bounds__(kBlock) k_project_tiles(TileView tv, Vips V, V
       [&](int64_t tk) __attribute__((always_inline)) {
         step_stage<1>(tv, tk, src, t, m);
         step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
-          project_at(LdsRows<1>{C, t, src, ly, lx}, V, i, true, us, vs, phi, dt, c, u, v, p);
+          project_at(LdsRows<1, FIX>{C, t, src, ly, lx}, V, i, true, us, vs, phi, dt, c, u, v, p);
         });
       },
       [&](int64_t i) __attribute__((always_inline)) { project_node(i, V, C, lap, bpos, us, vs, phi, dt, c, u, v, p); });
@@ -607,13 +636,17 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   const Bnd B{c->bpos, c->bkind, c->bnx, c->bny, c->bval, 2.0 * c->opt.vip_offset * c->h, c->two_db};
   const VC C = vc_of(c);
   const TileView T = step_tiles(c);
+  const bool fix = vc_is_lattice_shape(C);   // the tiled kernels' unrolled instance applies
   const int64_t tgrid = static_cast<int64_t>(T.tile_blocks) + T.irr_blocks;
   {
     KTimer kt(c, c->ktime[kTimePredRhs], true);
-    if (T.tiles)
-      k_predictor_rhs_tiles<<<tgrid, kBlock, 0, s>>>(T, n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
-                                                      c->have_prev_n ? 0 : 1, dt, re,
-                                                      c->opt.identity == VIP_I_EXACT ? 1 : 0, ru, rv);
+    const int first = c->have_prev_n ? 0 : 1, exact = c->opt.identity == VIP_I_EXACT ? 1 : 0;
+    if (T.tiles && fix)
+      k_predictor_rhs_tiles<true><<<tgrid, kBlock, 0, s>>>(T, n, m00, lap, c->node.rowlen, V, C, B, u, v, p,
+                                                            c->nprev, first, dt, re, exact, ru, rv);
+    else if (T.tiles)
+      k_predictor_rhs_tiles<false><<<tgrid, kBlock, 0, s>>>(T, n, m00, lap, c->node.rowlen, V, C, B, u, v, p,
+                                                             c->nprev, first, dt, re, exact, ru, rv);
     else
       k_predictor_rhs<<<grid_for(n), kBlock, 0, s>>>(n, m00, lap, c->node.rowlen, V, C, B, u, v, p, c->nprev,
                                                       c->have_prev_n ? 0 : 1, dt, re,
@@ -622,7 +655,8 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   VIP_HIP_TRY(c, hipGetLastError());
   int rc_h = helmholtz_solve(c, ru, rv, &us, &vs, st);
   if (rc_h != VIP_OK && rc_h != VIP_E_NOT_CONVERGED) return rc_h;
-  if (T.tiles) k_divergence_tiles<<<tgrid, kBlock, 0, s>>>(T, V, C, c->bpos, us, vs, 1.0 / dt, b);
+  if (T.tiles && fix) k_divergence_tiles<true><<<tgrid, kBlock, 0, s>>>(T, V, C, c->bpos, us, vs, 1.0 / dt, b);
+  else if (T.tiles) k_divergence_tiles<false><<<tgrid, kBlock, 0, s>>>(T, V, C, c->bpos, us, vs, 1.0 / dt, b);
   else k_divergence<<<grid_for(n), kBlock, 0, s>>>(n, V, C, c->bpos, us, vs, 1.0 / dt, b);
   VIP_HIP_TRY(c, hipGetLastError());
   const int ws = c->opt.warmstart;
@@ -647,8 +681,12 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
     c->learn.have_eprev = false;   // the chain of increments is not followed
     c->learn.have_eprev2 = false;
   }
-  if (T.tiles)
-    k_project_tiles<<<tgrid, kBlock, 0, s>>>(T, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u, v, p);
+  if (T.tiles && fix)
+    k_project_tiles<true><<<tgrid, kBlock, 0, s>>>(T, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
+                                                   v, p);
+  else if (T.tiles)
+    k_project_tiles<false><<<tgrid, kBlock, 0, s>>>(T, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
+                                                    v, p);
   else
     k_project<<<grid_for(n), kBlock, 0, s>>>(n, V, C, lap, c->bpos, us, vs, c->phi, dt, dt / (2.0 * re), u,
                                               v, p);
@@ -669,9 +707,12 @@ int convection(Ctx* c, const double* u, const double* v, double* nx, double* ny)
 
 int divergence(Ctx* c, const double* u, const double* v, double* d) {
   const TileView T = step_tiles(c);
-  if (T.tiles)
-    k_divergence_tiles<<<static_cast<int64_t>(T.tile_blocks) + T.irr_blocks, kBlock, 0, c->stream>>>(
-        T, vips_of(c), vc_of(c), c->bpos, u, v, 1.0, d);
+  const VC C = vc_of(c);
+  const int64_t tgrid = static_cast<int64_t>(T.tile_blocks) + T.irr_blocks;
+  if (T.tiles && vc_is_lattice_shape(C))
+    k_divergence_tiles<true><<<tgrid, kBlock, 0, c->stream>>>(T, vips_of(c), C, c->bpos, u, v, 1.0, d);
+  else if (T.tiles)
+    k_divergence_tiles<false><<<tgrid, kBlock, 0, c->stream>>>(T, vips_of(c), C, c->bpos, u, v, 1.0, d);
   else
     k_divergence<<<grid_for(c->n), kBlock, 0, c->stream>>>(c->n, vips_of(c), vc_of(c), c->bpos, u, v, 1.0, d);
   VIP_HIP_TRY(c, hipGetLastError());

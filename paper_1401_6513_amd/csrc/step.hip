@@ -322,28 +322,34 @@ __global__ void k_project(int64_t n, Vips V, VC C, Op lap, const int32_t* bpos, 
 // column, reading its taps from LDS in the slot order of the per-node path, so the two give the
 // same bits.  Boundary nodes, other nodes, and nodes off the lattice are taken one per thread by
 // the first blocks of the same launch (tile_walk).
-constexpr int kSH = 3;
-constexpr int kStW = kTileX + 2 * kSH;
-constexpr int kStH = kTileY + 2 * kSH;
+// Halo of the staged frame: 3 pixels for general runs (every tap within 3 pixels), 2 for the
+// lattice runs (every tap within 2); SH x SH frames of kTileX + 2 SH by kTileY + 2 SH pixels.
+template <int SH>
+struct StFrame {
+  static constexpr int W = kTileX + 2 * SH;
+  static constexpr int H = kTileY + 2 * SH;
+};
 
 // Stage NF fields over listed tile k of the partition (0 where a pixel holds no node).  Starts
 // and ends with a block barrier.
-template <int NF>
+template <int NF, int SH>
 __device__ __forceinline__ void step_stage(const TileView& tv, int64_t k, const double* const (&src)[NF],
-                                           double (&t)[NF][kStH][kStW], TileMeta& m) {
+                                           double (&t)[NF][StFrame<SH>::H][StFrame<SH>::W], TileMeta& m) {
+  constexpr int kStW = StFrame<SH>::W, kStH = StFrame<SH>::H;
   const int tid = static_cast<int>(threadIdx.x);
   __syncthreads();
   if (tid < kTileRecWords) m.w[tid] = tv.rec[k * kTileRecWords + tid];
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
   const int tx = m.tx(), ty = m.ty();
-  // the record's row starts cover rows 1..20 and columns 1..68 of this frame (its 2-pixel halo)
+  // the record's row starts cover the 2-pixel halo frame: rows and columns from SH - 2 on here
+  constexpr int o = SH - 2;
   auto node_at = [&](int r, int cc) __attribute__((always_inline)) -> int32_t {
-    if (r >= 1 && r <= kTileLdsH && cc >= 1 && cc <= kTileLdsW) {
-      const int32_t rs = m.rs(r - 1);
-      if (rs >= 0) return rs + cc - 1;
+    if (r >= o && r < o + kTileLdsH && cc >= o && cc < o + kTileLdsW) {
+      const int32_t rs = m.rs(r - o);
+      if (rs >= 0) return rs + cc - o;
     }
-    const int gx = tx * kTileX + cc - kSH, gy = ty * kTileY + r - kSH;
+    const int gx = tx * kTileX + cc - SH, gy = ty * kTileY + r - SH;
     if (gx >= 0 && gx < tv.W && gy >= 0 && gy < tv.H) return tv.node_of[static_cast<int64_t>(gy) * tv.W + gx];
     return -1;
   };
@@ -403,8 +409,10 @@ bool vc_is_lattice_shape(const VC& C) {
 // named by the pointer it was staged from.  FIX: the runs are the lattice shape above.
 template <int NF, bool FIX = false>
 struct LdsRows {
+  static constexpr int kSH = FIX ? 2 : 3;   // staged halo; stencil row d (dy = d - 3) at ly + kSH - 3 + d
+  static constexpr int kRow = kSH - 3;
   const VC& C;
-  const double (&t)[NF][kStH][kStW];
+  const double (&t)[NF][StFrame<kSH>::H][StFrame<kSH>::W];
   const double* const (&src)[NF];
   int ly, lx;
   __device__ __forceinline__ int len(int o, int d) const { return FIX ? kLatLen[o][d] : C.len[o][d]; }
@@ -416,7 +424,7 @@ struct LdsRows {
 #pragma unroll
     for (int d = 0; d < kVcRows; ++d) {
       const int L = len(o, d);
-      const double* tr = &t[a][ly + d][lx + kSH + dx0(o, d)];
+      const double* tr = &t[a][ly + kRow + d][lx + kSH + dx0(o, d)];
       for (int q = 0; q < L; ++q) acc = fma(C.w[wo][k + q], tr[q], acc);
       k += L;
     }
@@ -433,8 +441,8 @@ struct LdsRows {
       const int c0 = lx + kSH + dx0(o, d);
       for (int q = 0; q < L; ++q) {
         const double w = C.w[o][k + q];
-        a = fma(w, t[a0][ly + d][c0 + q], a);
-        b = fma(w, t[a1][ly + d][c0 + q], b);
+        a = fma(w, t[a0][ly + kRow + d][c0 + q], a);
+        b = fma(w, t[a1][ly + kRow + d][c0 + q], b);
       }
       k += L;
     }
@@ -455,8 +463,8 @@ struct LdsRows {
       for (int q = 0; q < L; ++q) {
         const double id = exact_id ? (d == 3 && dx0 + q == 0 ? 1.0 : 0.0) : C.w[4][k + q];
         const double r = fma(c, C.w[kVcOps][k + q], id);
-        a = fma(r, t[a0][ly + d][c0 + q], a);
-        b = fma(r, t[a1][ly + d][c0 + q], b);
+        a = fma(r, t[a0][ly + kRow + d][c0 + q], a);
+        b = fma(r, t[a1][ly + kRow + d][c0 + q], b);
       }
       k += L;
     }
@@ -483,13 +491,14 @@ __global__ void __launch_bounds__(kBlock) k_predictor_rhs_tiles(TileView tv, int
                                                                 const double* p, double* nprev, int first,
                                                                 double dt, double re, int exact_id, double* ru,
                                                                 double* rv) {
-  __shared__ double t[2][kStH][kStW];
+  constexpr int SH = LdsRows<2, FIX>::kSH;
+  __shared__ double t[2][StFrame<SH>::H][StFrame<SH>::W];
   __shared__ TileMeta m;
   const double* const src[2] = {u, v};
   tile_walk(
       tv,
       [&](int64_t tk) __attribute__((always_inline)) {
-        step_stage<2>(tv, tk, src, t, m);
+        step_stage<2, SH>(tv, tk, src, t, m);
         step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
           predictor_interior(LdsRows<2, FIX>{C, t, src, ly, lx}, n, i, m00, rowlen, V, u, v, nprev, first, dt, re,
                              exact_id, ru, rv);
@@ -504,13 +513,14 @@ template <bool FIX>
 __global__ void __launch_bounds__(kBlock) k_divergence_tiles(TileView tv, Vips V, VC C, const int32_t* bpos,
                                                              const double* u, const double* v, double scale,
                                                              double* b) {
-  __shared__ double t[2][kStH][kStW];
+  constexpr int SH = LdsRows<2, FIX>::kSH;
+  __shared__ double t[2][StFrame<SH>::H][StFrame<SH>::W];
   __shared__ TileMeta m;
   const double* const src[2] = {u, v};
   tile_walk(
       tv,
       [&](int64_t tk) __attribute__((always_inline)) {
-        step_stage<2>(tv, tk, src, t, m);
+        step_stage<2, SH>(tv, tk, src, t, m);
         step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
           b[i] = divergence_at(LdsRows<2, FIX>{C, t, src, ly, lx}, V, i, u, v) * scale;
         });
@@ -522,13 +532,14 @@ template <bool FIX>
 __global__ void __launch_bounds__(kBlock) k_project_tiles(TileView tv, Vips V, VC C, Op lap, const int32_t* bpos,
                                                           const double* us, const double* vs, const double* phi,
                                                           double dt, double c, double* u, double* v, double* p) {
-  __shared__ double t[1][kStH][kStW];
+  constexpr int SH = LdsRows<1, FIX>::kSH;
+  __shared__ double t[1][StFrame<SH>::H][StFrame<SH>::W];
   __shared__ TileMeta m;
   const double* const src[1] = {phi};
   tile_walk(
       tv,
       [&](int64_t tk) __attribute__((always_inline)) {
-        step_stage<1>(tv, tk, src, t, m);
+        step_stage<1, SH>(tv, tk, src, t, m);
         step_rows(tv, m, [&](int64_t i, int ly, int lx) __attribute__((always_inline)) {
           project_at(LdsRows<1, FIX>{C, t, src, ly, lx}, V, i, true, us, vs, phi, dt, c, u, v, p);
         });

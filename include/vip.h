@@ -213,6 +213,9 @@ int vip_set_options(void* ctx, const vip_options* opt);
  *  two, u*(n-1) after one, else the right-hand side); the start does not change
  *  what it converges to.
  *  stats    host, may be NULL.
+ * Returns with the step's statistics final and its last kernels (the projection) enqueued on
+ * the context's stream: work the caller orders after it on that stream sees the new u, v, p;
+ * elsewhere (the host, other streams) synchronize that stream first.
  * Errors: VIP_E_NOT_BUILT, VIP_E_INVALID, VIP_E_NOT_CONVERGED (state is still
  * advanced), VIP_E_NONFINITE, VIP_E_HIP.
  */
@@ -234,6 +237,7 @@ int vip_reset_history(void* ctx);
  *       (the last iterate after VIP_E_NOT_CONVERGED; unspecified after other errors).
  *  tol  relative FP64 residual target.
  *  stats host, may be NULL (poisson_* fields and border_lambda are filled).
+ * As vip_step, returns with phi's last writes possibly still enqueued on the context's stream.
  */
 int vip_poisson_solve(void* ctx, const double* rhs, double* phi, double tol, int use_x0,
                       vip_step_stats* stats);

@@ -1986,13 +1986,13 @@ int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x
   }
   double lam = lambda_proj;
   if (border) {
+    // the border unknown is a statistic: read it back (the only wait after the last check)
     double h = 0.0;
     VIP_HIP_TRY(c, hipMemcpyAsync(&h, x + n, sizeof(double), hipMemcpyDeviceToHost, s));
     VIP_HIP_TRY(c, hipStreamSynchronize(s));
     lam = h;
-  } else {
-    VIP_HIP_TRY(c, hipStreamSynchronize(s));
   }
+  VIP_HIP_TRY(c, hipGetLastError());
   if (st) {
     st->poisson_iters = total_it;
     st->poisson_outer = outer;

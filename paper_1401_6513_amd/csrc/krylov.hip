@@ -2145,49 +2145,86 @@ __global__ void k_apply(int64_t nrows, const int64_t* ptr, const int32_t* cols, 
   y[i] = acc;
 }
 
-// y = P x for the FP64 pressure matrix (canonical rows included), one thread per row.
-__global__ void k_sys_apply(Mat<double> A, const double* x, double* y) {
+// The input of a pressure product: x, or (DIFF) the difference x - x2 formed where it is read,
+// with the bits of the separate difference pass (k_sub).
+template <bool DIFF>
+struct SysInput {
+  const double* x;
+  const double* x2;
+  __device__ __forceinline__ double operator[](int64_t j) const {
+    if constexpr (DIFF) return x[j] - x2[j];
+    else return x[j];
+  }
+};
+
+// Per row i of a pressure product y_i = (P x')_i: stores y, the residual b - y, the input x' (DIFF:
+// the difference) and a copy of x, whichever are set.
+__device__ __forceinline__ void sys_emit(const SysApply& P, int64_t i, double yi, double xi) {
+  if (P.y) P.y[i] = yi;
+  if (P.r) P.r[i] = P.b[i] - yi;
+  if (P.xd) P.xd[i] = xi;
+  if (P.cp) P.cp[i] = P.x[i];
+}
+
+// y = P x' for the FP64 pressure matrix (canonical rows included), one thread per row.
+template <bool DIFF>
+__global__ void k_sys_apply(Mat<double> A, SysApply P) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= A.n) return;
-  y[i] = row_dot(A, 0, i, x);
+  const SysInput<DIFF> x{P.x, P.x2};
+  sys_emit(P, i, row_dot(A, 0, i, x), x[i]);
 }
 
 // The same over the tile partition: canonical rows from LDS tiles, the others row by row (the
 // same bits as k_sys_apply).
-template <bool GEN>
-__global__ void __launch_bounds__(kBlock) k_sys_apply_tiles(Mat<double> A, const double* x, double* y) {
+template <bool GEN, bool DIFF>
+__global__ void __launch_bounds__(kBlock) k_sys_apply_tiles(Mat<double> A, SysApply P) {
   __shared__ double lds[1][kTileLdsH][kTileLdsW];
   __shared__ TileMeta meta;
-  const double* const xs[1] = {x};
+  const SysInput<DIFF> x{P.x, P.x2};
   tile_walk(
       A.tv,
       [&](int64_t tk) __attribute__((always_inline)) {
-        tile_stage<double, 1>(A.tv, tk, xs, lds, meta, !GEN);
+        tile_stage_fn<double, 1>(
+            A.tv, tk, [&](int, int32_t node) __attribute__((always_inline)) { return x[node]; }, lds, meta, !GEN);
         const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
 #pragma unroll 1
         for (int k = 0; k < kTileRowsPerWave; ++k) {
           const int64_t row = tile_row_id(A.tv, meta, k);
           if (row < 0) continue;
-          if constexpr (GEN) y[row] = row_dot_rows(A, 0, row, x);
-          else y[row] = disk_lds(A, 0, lds[0], wave + k * (kBlock / 64), lane);
+          const int ly = wave + k * (kBlock / 64);
+          if constexpr (GEN) sys_emit(P, row, row_dot_rows(A, 0, row, x), x[row]);
+          else sys_emit(P, row, disk_lds(A, 0, lds[0], ly, lane), lds[0][ly + 2][lane + 2]);
         }
       },
-      [&](int64_t i) __attribute__((always_inline)) { y[i] = row_dot_rows(A, 0, i, x); });
+      [&](int64_t i) __attribute__((always_inline)) { sys_emit(P, i, row_dot_rows(A, 0, i, x), x[i]); });
 }
 
-int pressure_apply(Ctx* c, const double* x, double* y) {
+int pressure_apply(Ctx* c, const SysApply& P) {
   Mat<double> A{c->n, 0, c->sys.ptr, c->sys.cols, {c->sys.val[0], nullptr}, {nullptr, nullptr}};
   attach_canon(c, A, 0, -1);
   VIP_TRY(check_mat(c, A, 1));
+  const bool diff = P.x2 != nullptr;
   if (A.tv.tiles) {
-    if (A.tile_general) k_sys_apply_tiles<true><<<spmv_grid(A), kBlock, 0, c->stream>>>(A, x, y);
-    else k_sys_apply_tiles<false><<<spmv_grid(A), kBlock, 0, c->stream>>>(A, x, y);
+    const int64_t g = spmv_grid(A);
+    if (A.tile_general && diff) k_sys_apply_tiles<true, true><<<g, kBlock, 0, c->stream>>>(A, P);
+    else if (A.tile_general) k_sys_apply_tiles<true, false><<<g, kBlock, 0, c->stream>>>(A, P);
+    else if (diff) k_sys_apply_tiles<false, true><<<g, kBlock, 0, c->stream>>>(A, P);
+    else k_sys_apply_tiles<false, false><<<g, kBlock, 0, c->stream>>>(A, P);
     VIP_HIP_TRY(c, hipGetLastError());
     return VIP_OK;
   }
-  k_sys_apply<<<grid_for(c->n), kBlock, 0, c->stream>>>(A, x, y);
+  if (diff) k_sys_apply<true><<<grid_for(c->n), kBlock, 0, c->stream>>>(A, P);
+  else k_sys_apply<false><<<grid_for(c->n), kBlock, 0, c->stream>>>(A, P);
   VIP_HIP_TRY(c, hipGetLastError());
   return VIP_OK;
+}
+
+int pressure_apply(Ctx* c, const double* x, double* y) {
+  SysApply P{};
+  P.x = x;
+  P.y = y;
+  return pressure_apply(c, P);
 }
 
 int ell_apply(Ctx* c, const Ell& e, int vs, const double* x, double* y) {

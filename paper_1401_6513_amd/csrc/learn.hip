@@ -738,26 +738,11 @@ __global__ void k_direction(int64_t n, const int32_t* pix, const float* y, const
   d[i] = p >= 0 && sr > 0.0 ? sr / h2 * static_cast<double>(y[p]) : 0.0;
 }
 
-// phi = phi_prev + alpha e + beta d (d may be null)
-__global__ void k_combine(int64_t n, const double* phi_prev, const double* e, const double* d, double alpha,
-                          double beta, double* phi) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  phi[i] = phi_prev[i] + alpha * e[i] + (d ? beta * d[i] : 0.0);
-}
-
 // e = phi - phi_prev
 __global__ void k_diff(int64_t n, const double* phi, const double* phi_prev, double* e) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
   e[i] = phi[i] - phi_prev[i];
-}
-
-// r = b - a
-__global__ void k_sub(int64_t n, const double* b, const double* a, double* r) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  r[i] = b[i] - a[i];
 }
 
 __global__ void k_f2d(int64_t n, const float* a, double* b) {
@@ -771,12 +756,6 @@ __global__ void k_add2(int64_t n, double* x, const double* d, const double* cv, 
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
   x[i] += alpha * d[i] + (cv ? beta * cv[i] : 0.0);
-}
-
-__global__ void k_copy_d(int64_t n, const double* a, double* b) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  b[i] = a[i];
 }
 
 // block partials of the squared sums of a h^2 and c h^2 over lattice nodes and their count
@@ -1256,10 +1235,13 @@ int ensure_vectors(Ctx* c) {
 // q1 = L eprev and rx = r - q1
 int extrapolation_residual(Ctx* c) {
   Learn& L = c->learn;
-  VIP_TRY(pressure_apply(c, L.eprev, L.q1));
-  k_sub<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, L.r, L.q1, L.rx);
-  VIP_HIP_TRY(c, hipGetLastError());
-  return VIP_OK;
+  // q1 = L e and rx = r - q1 in one pass
+  SysApply P;
+  P.x = L.eprev;
+  P.y = L.q1;
+  P.b = L.r;
+  P.r = L.rx;
+  return pressure_apply(c, P);
 }
 
 }  // namespace
@@ -1394,11 +1376,13 @@ int learn_prepare(Ctx* c, const double* b, const double* phi, bool with_map) {
   Learn& L = c->learn;
   if (with_map) VIP_TRY(learn_map(c));
   VIP_TRY(ensure_vectors(c));
-  k_copy_d<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, phi, L.phi_prev);
-  VIP_TRY(pressure_apply(c, L.phi_prev, L.q1));
-  k_sub<<<blocks_for(c->n), kBlock, 0, c->stream>>>(c->n, b, L.q1, L.r);
-  VIP_HIP_TRY(c, hipGetLastError());
-  return VIP_OK;
+  // phi_prev = phi and r = b - L phi in one pass
+  SysApply P;
+  P.x = phi;
+  P.cp = L.phi_prev;
+  P.b = b;
+  P.r = L.r;
+  return pressure_apply(c, P);
 }
 
 int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_stats* stats) {
@@ -1434,8 +1418,13 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
   // second difference of the increments, e - e_old (the quadratic extrapolation adds it)
   const bool second = L.have_eprev2;
   if (second) {
-    k_sub<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.eprev, L.eprev2, L.dir2);
-    VIP_TRY(pressure_apply(c, L.dir2, L.q3));
+    // dir2 = e - e_old and q3 = L dir2 in one pass
+    SysApply P;
+    P.x = L.eprev;
+    P.x2 = L.eprev2;
+    P.xd = L.dir2;
+    P.y = L.q3;
+    VIP_TRY(pressure_apply(c, P));
   }
   k_dots10_part<<<kRedBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, second ? L.q3 : nullptr, L.r,
                                             L.scal + kScalHead);

@@ -506,6 +506,20 @@ int ensure_partials(Ctx* c, int64_t blocks, int per);
 int ell_apply(Ctx* c, const Ell& e, int vs, const double* x, double* y);
 // y = P x with the FP64 pressure matrix through the canonical-row path (no border).
 int pressure_apply(Ctx* c, const double* x, double* y);
+// A pressure product with its neighbouring element-wise passes folded in: y = P x' with x' = x,
+// or x - x2 when x2 is set (then also stored to xd when that is set); r = b - y when r is set;
+// x copied to cp when that is set.  Unset outputs are not written.  Bit for bit the separate
+// passes.
+struct SysApply {
+  const double* x = nullptr;
+  const double* x2 = nullptr;
+  double* xd = nullptr;
+  double* cp = nullptr;
+  double* y = nullptr;
+  const double* b = nullptr;
+  double* r = nullptr;
+};
+int pressure_apply(Ctx* c, const SysApply& P);
 
 // Solvers (krylov.hip)
 int poisson_solve(Ctx* c, const double* rhs, double* phi, double tol, bool use_x0,

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "vip_internal.h"
@@ -57,8 +58,12 @@ __device__ __forceinline__ bool inside(const Img& g, int i, int j) {
 
 // ---- forward ------------------------------------------------------------------------------------
 
+// two FP32 values to BF16 (round to nearest even) in one v_cvt_pk_bf16_f32, a in the low half
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 __device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
-  return static_cast<uint32_t>(f2bf(a)) | (static_cast<uint32_t>(f2bf(b)) << 16);
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
 // Layer 1 (3 -> 32) as one MFMA K-step: k = 3 t + ci over the 9 taps and 3 channels (27 of the
@@ -252,170 +257,235 @@ __global__ __launch_bounds__(256) void k_conv_out(Img g, const bf16_t* x, const 
 
 // ---- fused inference ---------------------------------------------------------------------------------
 
-// All four layers on one 16 x 16 tile of output pixels per block, activations in LDS: the
-// input region with a halo of 4, layer 1 on 22 x 22 pixels (VALU), layers 2 and 3 on 20 x 20
-// and 18 x 18 (MFMA, groups of 16 pixels in any arrangement), layer 4 on the tile (VALU).
-// Pixels outside the image hold 0 after every layer and taps outside the image are skipped, as
-// in the layer-by-layer kernels, whose arithmetic (tap and channel order, MFMA operands,
-// BF16 rounding of each layer's output) it repeats, so the output has the same bits.
-constexpr int kFT = 16;             // output tile side
-constexpr int kR0 = kFT + 8;        // input region side
-constexpr int kR1 = kFT + 6;        // layer-1 region side
-constexpr int kR2 = kFT + 4;        // layer-2 region side
-constexpr int kR3 = kFT + 2;        // layer-3 region side
-constexpr int kPx = 40;             // LDS stride of one pixel's 32 channels (80 bytes: the
-                                    // 16-byte reads of 16 consecutive pixels hit 64 distinct banks)
+// All four layers in one launch.  A block owns a strip of kSW output columns and th <= kMaxTH
+// output rows and walks down it one row per step: at step k layer 1 computes its row k from
+// the input staged in LDS, and each later layer takes one row of the layer below from a
+// two-row ring in LDS, adds that row's three taps (one per horizontal shift) into each of the
+// three output rows it feeds, and writes the row that is then complete into its own ring.  A
+// row of activations is read from LDS once per consuming layer (three shifted loads), not
+// once per tap, and only the strip's top and bottom margins are computed twice.  For every
+// output pixel and channel the nine taps are still added in tap order starting from zero,
+// with the layer-by-layer kernels' MFMA operands and the BF16 rounding of each layer's
+// output, so the result has the same bits.  Pixels outside the image hold 0 after every layer.
+//
+// Columns: the output covers kSW = 58 columns from the strip origin ox, layer 3 the 60 from
+// ox - 1, layer 2 the 62 from ox - 2, layer 1 the 64 from ox - 3 and the staged input the 66
+// from ox - 4; every layer is four groups of 16 columns (one MFMA pixel block each), and a
+// lane past its layer's width stores 0 (its bias is -inf, so the ReLU gives 0).
+// Rows, for a strip of th output rows from oy: layer 1 has th + 6 rows from oy - 3 (row k at
+// step k), layer 2 th + 4 from oy - 2, layer 3 th + 2 from oy - 1, the output th from oy.  A
+// layer loads a row of the layer below into registers in the step after it was written and
+// uses it in the next one: layer 2 uses layer-1 row i at step i + 2 (and completes its own
+// row i - 2), layer 3 layer-2 row i at step i + 6, layer 4 layer-3 row i at step i + 10; the
+// last output row is done at step th + 11.  Input row r (image row oy - 4 + r) is loaded from HBM at step r - 8 and written to
+// LDS at step r - 7, well before layer 1 reads it at step r - 2.  One barrier per step.
+// Waves: 0-3 layer 2 and 4-7 layer 3 (column group wave % 4), 8-11 layers 1 and 4 of group
+// wave - 8; wave w runs on SIMD w % 4, so every SIMD holds one of each (18 + 18 + 11 MFMA a
+// step).  The step loop is unrolled six times so that the three accumulator rows rotate and
+// the ring slots alternate by renaming instead of copies.
+constexpr int kSW = 58;             // output columns per strip
+constexpr int kRingPx = 68;         // ring row: 64 region columns + 2 read by the shifted loads, padded
+constexpr int kInW = kSW + 8;       // staged input columns
+constexpr int kInRow = kInW * kCin; // values per staged input row
+constexpr int kMaxTH = 128;         // output rows per strip at most
+constexpr int kPx = 40;             // LDS stride of one pixel's 32 channels (80 bytes: the 16-byte
+                                    // reads of 16 consecutive pixels hit 64 distinct banks)
+constexpr int kRingLen = kRingPx * kPx;
+constexpr int kCnnBlock = 768;      // 12 wavefronts, 3 per SIMD
+constexpr int kInPre = 7;           // input rows staged before the first step
 
-constexpr int kCnnBlock = 512;      // 8 wavefronts per tile: the LDS allows 2 blocks per CU, and at
-                                    // 127 VGPRs 4 waves per SIMD (1.53 -> 1.44 ms at 2561 x 3841;
-                                    // the branch-free layer-1 operands then 1.38 ms)
-constexpr int kCnnWaves = kCnnBlock / 64;
+template <int U>
+using Step = std::integral_constant<int, U>;
 
-__global__ __launch_bounds__(kCnnBlock, 4) void k_cnn_fused(Img g, const bf16_t* x, const bf16_t* w1, const float* b1,
-                                                   const bf16_t* w2t, const float* b2, const bf16_t* w3t,
-                                                   const float* b3, const bf16_t* w4, const float* b4, float* y) {
-  __shared__ bf16_t s_in[kR0 * kR0 * kCin];
-  __shared__ __attribute__((aligned(16))) bf16_t s_a[kR1 * kR1 * kPx];   // layer 1, later layer 3
-  __shared__ __attribute__((aligned(16))) bf16_t s_b[kR2 * kR2 * kPx];   // layer 2
+__global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf16_t* x, const bf16_t* w1,
+                                                       const float* b1, const bf16_t* w2t, const float* b2,
+                                                       const bf16_t* w3t, const float* b3, const bf16_t* w4,
+                                                       const float* b4, float* y) {
+  __shared__ bf16_t s_in[(kMaxTH + 8) * kInRow + 8];
+  __shared__ __attribute__((aligned(16))) bf16_t s_ring[3][2][kRingLen];   // layers 1, 2, 3
   const int tid = static_cast<int>(threadIdx.x);
   const int b = static_cast<int>(blockIdx.z);
-  const int oi = static_cast<int>(blockIdx.y) * kFT, oj = static_cast<int>(blockIdx.x) * kFT;   // tile origin
-  // input region (origin oi - 4, oj - 4), zero outside the image
-  for (int q = tid; q < kR0 * kR0; q += blockDim.x) {
-    const int ii = oi - 4 + q / kR0, jj = oj - 4 + q % kR0;
-    bf16_t v0 = 0, v1 = 0, v2 = 0;
-    if (inside(g, ii, jj)) {
-      const bf16_t* xp = x + ((static_cast<int64_t>(b) * g.H + ii) * g.W + jj) * kCin;
-      v0 = xp[0];
-      v1 = xp[1];
-      v2 = xp[2];
-    }
-    s_in[q * kCin] = v0;
-    s_in[q * kCin + 1] = v1;
-    s_in[q * kCin + 2] = v2;
+  const int ox = static_cast<int>(blockIdx.x) * kSW, oy = static_cast<int>(blockIdx.y) * th;
+  const int nin = th + 8;                             // staged input rows
+  // input value tid of a staged row: column ox - 4 + tid / 3, channel tid % 3
+  const bool stager = tid < kInRow;
+  const int sq = tid / kCin, sci = tid - (tid / kCin) * kCin;
+  const bool scol = stager && ox - 4 + sq >= 0 && ox - 4 + sq < g.W;
+  auto in_load = [&](int r) -> bf16_t {
+    const int ii = oy - 4 + r;
+    return scol && r < nin && ii >= 0 && ii < g.H
+               ? x[((static_cast<int64_t>(b) * g.H + ii) * g.W + ox - 4 + sq) * kCin + sci]
+               : bf16_t(0);
+  };
+  {
+    bf16_t v[kInPre];
+#pragma unroll
+    for (int r = 0; r < kInPre; ++r) v[r] = in_load(r);
+    if (stager)
+#pragma unroll
+      for (int r = 0; r < kInPre; ++r) s_in[r * kInRow + tid] = v[r];
+    // ring columns 64..67 feed only discarded lanes; keep them finite
+    for (int e = tid; e < 3 * 2 * 4 * kPx; e += kCnnBlock)
+      (&s_ring[0][0][0])[(e / (4 * kPx)) * kRingLen + 64 * kPx + e % (4 * kPx)] = 0;
   }
-  __syncthreads();
+  bf16_t pend = in_load(kInPre);                      // row kInPre, written at step 0
   const int l = tid & 63, wave = tid >> 6;
   const int kq = (l >> 4) * 8;
   const int n = l & 15;
   const int cq = (l >> 4) * 4;
-  // layer 1 on region 1 (side kR1, origin oi - 3, oj - 3), 16 pixels per MFMA group.  The staged
-  // input is 0 outside the image, so a lane's 8 operand values are plain LDS reads at offsets
-  // fixed per lane (k = kq + j: tap k / 3, channel k % 3; the 5 slots k >= 27 hold 0), taken once
-  // here instead of a bounds test per value.
+  const int role = wave >> 2;        // 0: layer 2, 1: layer 3, 2: layers 1 and 4
+  const int c = (wave & 3) * 16 + n; // this lane's column in its layer's region
+  const int hal = 2 - role;          // region origin ox - hal, oy - hal (layers 2, 3, 4)
+  // role 0 / 1: wa[t][m] = the layer's weights of tap t, output channels 16 m ..; role 2:
+  // wa[t][0] = layer 4 (A row 0 only), wa[0][1], wa[1][1] = layer 1's two channel tiles.
+  // bv: the bias of this lane's 8 channels (layer 2 or 3; layer 1 for role 2), -inf in a
+  // column outside the layer's region or the image.
+  bf16x8 wa[9][2];
+  float bv[2][4];
   {
-    int off1[8];
-    bool use1[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = kq + j;
-      const int kk = k < 9 * kCin ? k : 9 * kCin - 1;
-      const int t = kk / kCin, ci = kk % kCin;
-      off1[j] = ((1 + t / 3 - 1) * kR0 + (1 + t % 3 - 1)) * kCin + ci;
-      use1[j] = k < 9 * kCin;
-    }
-    const bf16x8 wa0 = l1_weights(w1, 0, n, kq), wa1 = l1_weights(w1, 1, n, kq);
-    float bv[2][4];
+    const int jc = role < 2 ? ox - hal + c : ox - 3 + c;
+    const bool colok = (role < 2 ? c < 62 - 2 * role : true) && jc >= 0 && jc < g.W;
+    const float* bias = role == 0 ? b2 : role == 1 ? b3 : b1;
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) bv[m][r] = b1[m * 16 + cq + r];
-    constexpr int np = kR1 * kR1, groups = (np + 15) / 16;
-    for (int grp = wave; grp < groups; grp += kCnnWaves) {
-      const int q = grp * 16 + n;
-      const int qc = q < np ? q : np - 1;
-      const int r = qc / kR1, cc = qc % kR1;
-      const int i = oi - 3 + r, j = oj - 3 + cc;
-      const bf16_t* px = s_in + (r * kR0 + cc) * kCin;
-      uint32_t wv[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int jj = 0; jj < 8; ++jj) {
-        const uint32_t v = static_cast<uint32_t>(px[off1[jj]]);
-        wv[jj / 2] |= (use1[jj] ? v : 0u) << (16 * (jj % 2));
-      }
-      const bf16x8 xb = __builtin_bit_cast(bf16x8, make_uint4(wv[0], wv[1], wv[2], wv[3]));
-      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-      const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, xb, z, 0, 0, 0);
-      const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, xb, z, 0, 0, 0);
-      if (q < np) {
-        uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
-        if (inside(g, i, j)) {
-          v0 = make_uint2(pack_bf2(fmaxf(d0[0] + bv[0][0], 0.0f), fmaxf(d0[1] + bv[0][1], 0.0f)),
-                          pack_bf2(fmaxf(d0[2] + bv[0][2], 0.0f), fmaxf(d0[3] + bv[0][3], 0.0f)));
-          v1 = make_uint2(pack_bf2(fmaxf(d1[0] + bv[1][0], 0.0f), fmaxf(d1[1] + bv[1][1], 0.0f)),
-                          pack_bf2(fmaxf(d1[2] + bv[1][2], 0.0f), fmaxf(d1[3] + bv[1][3], 0.0f)));
-        }
-        *reinterpret_cast<uint2*>(s_a + q * kPx + cq) = v0;
-        *reinterpret_cast<uint2*>(s_a + q * kPx + 16 + cq) = v1;
-      }
-    }
+      for (int r = 0; r < 4; ++r) bv[m][r] = colok ? bias[m * 16 + cq + r] : -INFINITY;
   }
-  __syncthreads();
-  // layers 2 and 3: 16 pixels of the output region per MFMA group, region rs (side) from the
-  // region of side rs + 2 in src, into dst; origin of the output region oi - h, oj - h
-  auto mid = [&](const bf16_t* wt, const float* bias, const bf16_t* src, bf16_t* dst, int rs, int hal)
-      __attribute__((always_inline)) {
-    bf16x8 wa[9][2];
+  if (role < 2) {
+    const bf16_t* wt = role == 0 ? w2t : w3t;
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
       for (int m = 0; m < 2; ++m)
         wa[t][m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wt + (t * kC + m * 16 + n) * kC + kq));
-    float bv[2][4];
+  } else {
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) bv[m][r] = bias[m * 16 + cq + r];
-    const int np = rs * rs, groups = (np + 15) / 16;
-    for (int grp = wave; grp < groups; grp += kCnnWaves) {
-      const int q = grp * 16 + n;
-      const int qc = q < np ? q : np - 1;     // the last group's spare lanes repeat a pixel
-      const int r = qc / rs, cc = qc % rs;
-      f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int sr = r + 1 + (t / 3 - 1), sc = cc + 1 + (t % 3 - 1);
-        const bf16x8 xb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + (sr * (rs + 2) + sc) * kPx + kq));
-        d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][0], xb, d0, 0, 0, 0);
-        d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][1], xb, d1, 0, 0, 0);
-      }
-      if (q < np) {
-        const int i = oi - hal + r, j = oj - hal + cc;
-        uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
-        if (inside(g, i, j)) {
-          v0 = make_uint2(pack_bf2(fmaxf(d0[0] + bv[0][0], 0.0f), fmaxf(d0[1] + bv[0][1], 0.0f)),
-                          pack_bf2(fmaxf(d0[2] + bv[0][2], 0.0f), fmaxf(d0[3] + bv[0][3], 0.0f)));
-          v1 = make_uint2(pack_bf2(fmaxf(d1[0] + bv[1][0], 0.0f), fmaxf(d1[1] + bv[1][1], 0.0f)),
-                          pack_bf2(fmaxf(d1[2] + bv[1][2], 0.0f), fmaxf(d1[3] + bv[1][3], 0.0f)));
-        }
-        *reinterpret_cast<uint2*>(dst + q * kPx + cq) = v0;
-        *reinterpret_cast<uint2*>(dst + q * kPx + 16 + cq) = v1;
-      }
+    for (int t = 0; t < 9; ++t) {
+      wa[t][0] = l4_weights(w4, t, n, kq);
+      wa[t][1] = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
     }
+    wa[0][1] = l1_weights(w1, 0, n, kq);
+    wa[1][1] = l1_weights(w1, 1, n, kq);
+  }
+  const float bias4 = b4[0];
+  const bool ystore = l < 16 && c < kSW && ox + c < g.W;
+  // layer 1: operand slot k = kq + j holds tap k / 3, channel k % 3, i.e. value k % 9 of input
+  // row k / 9 from the pixel's top-left input value: offset k + (kInRow - 9) (k / 9).  With
+  // G = kq / 8 and k = 8 G + j, k / 9 = G - 1 + [j >= G], so a lane reads from one of two bases
+  // at the fixed offset j.  Slots k >= 27 are masked to 0 (their reads stay in s_in's padding).
+  const int G = l >> 4;
+  const int gb0 = c * kCin + 8 * G + (kInRow - 9) * (G - 1);
+  const uint32_t gmask1 = kq == 24 ? 0x0000ffffu : 0xffffffffu;   // k = 27 in the high half
+  const uint32_t gmask23 = kq == 24 ? 0u : 0xffffffffu;           // k = 28..31
+  auto gather = [&](int row) -> bf16x8 {
+    const int r0 = gb0 + row * kInRow, r1 = r0 + kInRow - 9;
+    uint32_t h[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = s_in[(j >= G && 8 * G + j < 9 * kCin ? r1 : r0) + j];
+    return __builtin_bit_cast(bf16x8, make_uint4(h[0] | (h[1] << 16), (h[2] | (h[3] << 16)) & gmask1,
+                                                 (h[4] | (h[5] << 16)) & gmask23, (h[6] | (h[7] << 16)) & gmask23));
   };
-  mid(w2t, b2, s_a, s_b, kR2, 2);
-  __syncthreads();
-  mid(w3t, b3, s_b, s_a, kR3, 1);
-  __syncthreads();
-  // layer 4 on the tile (16 x 16), 16 pixels per MFMA group
-  {
-    bf16x8 wa[9];
+  const int lag = 2 + 4 * role;                       // step at which row 0 of the layer below is used
+  const int nsrc = th + 6 - 2 * role;                 // rows of the layer below
+  const bf16_t* srcp = &s_ring[role][0][0] + c * kPx + kq;            // role r reads layer r + 1
+  bf16_t* dstp = &s_ring[role < 2 ? role + 1 : 0][0][0] + c * kPx + cq;   // role 2: layer 1's ring
+  const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zb = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
+  f32x4 aX[2] = {z, z}, aY[2] = {z, z}, aZ[2] = {z, z};
+  bf16x8 bP[3] = {zb, zb, zb}, bQ[3] = {zb, zb, zb};
+  auto relu_pack = [&](const f32x4& d, int m) -> uint2 {
+    return make_uint2(pack_bf2(fmaxf(d[0] + bv[m][0], 0.0f), fmaxf(d[1] + bv[m][1], 0.0f)),
+                      pack_bf2(fmaxf(d[2] + bv[m][2], 0.0f), fmaxf(d[3] + bv[m][3], 0.0f)));
+  };
+  // One step.  F: accumulator of the row that starts now (row i of the layer), M: row i - 1,
+  // L: row i - 2 (completed now); BC: this step's operands, BN: the next step's.  The slot parity of every ring access equals that of k
+  // (all lags are even), which the unrolling makes a constant.
+  auto step = [&](auto u, int k, f32x4 (&F)[2], f32x4 (&M)[2], f32x4 (&L)[2], bf16x8 (&BC)[3], bf16x8 (&BN)[3])
+      __attribute__((always_inline)) {
+    constexpr int par = decltype(u)::value & 1;
+    const bf16_t nxt = in_load(k + kInPre + 1);
+    const int ip = k - lag + 1;
+    if (ip >= 0 && ip < nsrc) {
 #pragma unroll
-    for (int t = 0; t < 9; ++t) wa[t] = l4_weights(w4, t, n, kq);
-    const float bias = b4[0];
-    for (int grp = wave; grp < kFT * kFT / 16; grp += kCnnWaves) {
-      const int q = grp * 16 + n;
-      const int r = q / kFT, cc = q % kFT;
-      f32x4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int sr = r + 1 + (t / 3 - 1), sc = cc + 1 + (t % 3 - 1);
-        const bf16x8 xb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s_a + (sr * kR3 + sc) * kPx + kq));
-        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t], xb, d, 0, 0, 0);
-      }
-      const int i = oi + r, j = oj + cc;
-      if (l < 16 && inside(g, i, j)) y[(static_cast<int64_t>(b) * g.H + i) * g.W + j] = d[0] + bias;
+      for (int d = 0; d < 3; ++d)
+        BN[d] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(srcp + (1 - par) * kRingLen + d * kPx));
     }
+    const int i = k - lag;
+    const bool live = i >= 0 && i < nsrc;
+    if (role < 2) {
+      if (live) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int m = 0; m < 2; ++m) L[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[6 + d][m], BC[d], L[m], 0, 0, 0);
+        const int j = i - 2;           // the row completed now
+        if (j >= 0) {
+          const int ii = oy - hal + j;
+          uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
+          if (ii >= 0 && ii < g.H) {
+            v0 = relu_pack(L[0], 0);
+            v1 = relu_pack(L[1], 1);
+          }
+          bf16_t* wp = dstp + par * kRingLen;
+          *reinterpret_cast<uint2*>(wp) = v0;
+          *reinterpret_cast<uint2*>(wp + 16) = v1;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            M[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 + d][m], BC[d], M[m], 0, 0, 0);
+            F[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][m], BC[d], d == 0 ? z : F[m], 0, 0, 0);
+          }
+      }
+    } else {
+      const bool l1 = k < th + 6;
+      const bf16x8 xc = l1 ? gather(k) : zb;
+      if (live) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) L[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[6 + d][0], BC[d], L[0], 0, 0, 0);
+      }
+      f32x4 d0 = z, d1 = z;
+      if (l1) {
+        d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], xc, z, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], xc, z, 0, 0, 0);
+      }
+      if (l1) {
+        const int ii = oy - 3 + k;
+        uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
+        if (ii >= 0 && ii < g.H) {
+          v0 = relu_pack(d0, 0);
+          v1 = relu_pack(d1, 1);
+        }
+        bf16_t* wp = dstp + par * kRingLen;
+        *reinterpret_cast<uint2*>(wp) = v0;
+        *reinterpret_cast<uint2*>(wp + 16) = v1;
+      }
+      if (live) {
+        const int o = i - 2;
+        if (o >= 0 && oy + o < g.H && ystore)
+          y[(static_cast<int64_t>(b) * g.H + oy + o) * g.W + ox + c] = L[0][0] + bias4;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          M[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 + d][0], BC[d], M[0], 0, 0, 0);
+          F[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][0], BC[d], d == 0 ? z : F[0], 0, 0, 0);
+        }
+      }
+    }
+    if (stager && k + kInPre < nin) s_in[(k + kInPre) * kInRow + tid] = pend;
+    pend = nxt;
+    __syncthreads();
+  };
+  __syncthreads();
+  const int nsteps = th + 12;
+  // accumulators (F, M, L) rotate (X, Y, Z) -> (Z, X, Y) -> (Y, Z, X); operands alternate P, Q
+  for (int k0 = 0; k0 < nsteps; k0 += 6) {
+    step(Step<0>{}, k0, aX, aY, aZ, bP, bQ);
+    if (k0 + 1 < nsteps) step(Step<1>{}, k0 + 1, aZ, aX, aY, bQ, bP);
+    if (k0 + 2 < nsteps) step(Step<2>{}, k0 + 2, aY, aZ, aX, bP, bQ);
+    if (k0 + 3 < nsteps) step(Step<3>{}, k0 + 3, aX, aY, aZ, bQ, bP);
+    if (k0 + 4 < nsteps) step(Step<4>{}, k0 + 4, aZ, aX, aY, bP, bQ);
+    if (k0 + 5 < nsteps) step(Step<5>{}, k0 + 5, aY, aZ, aX, bQ, bP);
   }
 }
 
@@ -939,6 +1009,7 @@ struct Net {
   bf16_t* ix = nullptr;
   float* iy = nullptr;
   int64_t icap = 0;
+  int ncu = 0;                // compute units of the device (strip height of the fused inference)
 };
 
 void learn_clear(Ctx* c) {
@@ -1099,6 +1170,25 @@ int forward(Ctx* c, const Img& g, bool timed = false) {
   return VIP_OK;
 }
 
+// Output rows per strip of the fused inference.  A block takes th + 12 steps (the first and last
+// are the layers' pipeline filling and draining) and runs alone on a CU, so the launch takes
+// about ceil(blocks / CUs) x (th + 12) steps; the smallest such estimate wins.
+int cnn_strip_rows(const Img& g, int ncu) {
+  const int64_t strips = static_cast<int64_t>((g.W + kSW - 1) / kSW) * g.B;
+  int best = 1;
+  int64_t best_cost = INT64_MAX;
+  for (int cand = 8; cand <= kMaxTH; cand += 8) {
+    const int th = std::min(cand, g.H);
+    const int64_t blocks = strips * ((g.H + th - 1) / th);
+    const int64_t cost = (blocks + ncu - 1) / ncu * (th + 12);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = th;
+    }
+  }
+  return best;
+}
+
 // inference over g in one launch (k_cnn_fused), input in N->ix, prediction in N->iy; timed: HIP
 // events around the launch into c->conv_timing
 int forward_fused(Ctx* c, const Img& g, bool timed) {
@@ -1117,9 +1207,15 @@ int forward_fused(Ctx* c, const Img& g, bool timed) {
     c->conv_timing.pool.pop_back();
     VIP_HIP_TRY(c, hipEventRecord(ev.first, st));
   }
-  const dim3 grid((g.W + kFT - 1) / kFT, (g.H + kFT - 1) / kFT, g.B);
-  k_cnn_fused<<<grid, kCnnBlock, 0, st>>>(g, N->ix, N->w1, N->theta + kB1, N->w2f, N->theta + kB2, N->w3f,
-                                       N->theta + kB3, N->w4, N->theta + kB4, N->iy);
+  if (N->ncu <= 0) {
+    int ncu = 0;
+    VIP_HIP_TRY(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    N->ncu = std::max(ncu, 1);
+  }
+  const int th = cnn_strip_rows(g, N->ncu);
+  const dim3 grid((g.W + kSW - 1) / kSW, (g.H + th - 1) / th, g.B);
+  k_cnn_fused<<<grid, kCnnBlock, 0, st>>>(g, th, N->ix, N->w1, N->theta + kB1, N->w2f, N->theta + kB2,
+                                       N->w3f, N->theta + kB3, N->w4, N->theta + kB4, N->iy);
   VIP_HIP_TRY(c, hipGetLastError());
   if (timed) {
     VIP_HIP_TRY(c, hipEventRecord(ev.second, st));

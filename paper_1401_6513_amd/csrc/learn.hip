@@ -311,11 +311,12 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
   const bool stager = tid < kInRow;
   const int sq = tid / kCin, sci = tid - (tid / kCin) * kCin;
   const bool scol = stager && ox - 4 + sq >= 0 && ox - 4 + sq < g.W;
+  const int soff = (ox - 4) * kCin + tid;             // offset of this value in its image row
   auto in_load = [&](int r) -> bf16_t {
     const int ii = oy - 4 + r;
-    return scol && r < nin && ii >= 0 && ii < g.H
-               ? x[((static_cast<int64_t>(b) * g.H + ii) * g.W + ox - 4 + sq) * kCin + sci]
-               : bf16_t(0);
+    if (r >= nin || ii < 0 || ii >= g.H) return bf16_t(0);
+    const bf16_t* row = x + (static_cast<int64_t>(b) * g.H + ii) * g.W * kCin;   // uniform
+    return scol ? row[soff] : bf16_t(0);
   };
   {
     bf16_t v[kInPre];
@@ -329,7 +330,8 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
       (&s_ring[0][0][0])[(e / (4 * kPx)) * kRingLen + 64 * kPx + e % (4 * kPx)] = 0;
   }
   bf16_t pend = in_load(kInPre);                      // row kInPre, written at step 0
-  const int l = tid & 63, wave = tid >> 6;
+  const int l = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: role branches are scalar
   const int kq = (l >> 4) * 8;
   const int n = l & 15;
   const int cq = (l >> 4) * 4;
@@ -374,14 +376,16 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
   // G = kq / 8 and k = 8 G + j, k / 9 = G - 1 + [j >= G], so a lane reads from one of two bases
   // at the fixed offset j.  Slots k >= 27 are masked to 0 (their reads stay in s_in's padding).
   const int G = l >> 4;
-  const int gb0 = c * kCin + 8 * G + (kInRow - 9) * (G - 1);
+  const int gb0 = 2 * (c * kCin + 8 * G + (kInRow - 9) * (G - 1));   // bytes
   const uint32_t gmask1 = kq == 24 ? 0x0000ffffu : 0xffffffffu;   // k = 27 in the high half
   const uint32_t gmask23 = kq == 24 ? 0u : 0xffffffffu;           // k = 28..31
   auto gather = [&](int row) -> bf16x8 {
-    const int r0 = gb0 + row * kInRow, r1 = r0 + kInRow - 9;
+    const int r0 = gb0 + row * (2 * kInRow), r1 = r0 + 2 * (kInRow - 9);
+    const char* sb = reinterpret_cast<const char*>(s_in);
     uint32_t h[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) h[j] = s_in[(j >= G && 8 * G + j < 9 * kCin ? r1 : r0) + j];
+    for (int j = 0; j < 8; ++j)
+      h[j] = *reinterpret_cast<const bf16_t*>(sb + (j >= G && 8 * G + j < 9 * kCin ? r1 : r0) + 2 * j);
     return __builtin_bit_cast(bf16x8, make_uint4(h[0] | (h[1] << 16), (h[2] | (h[3] << 16)) & gmask1,
                                                  (h[4] | (h[5] << 16)) & gmask23, (h[6] | (h[7] << 16)) & gmask23));
   };
@@ -397,95 +401,105 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
     return make_uint2(pack_bf2(fmaxf(d[0] + bv[m][0], 0.0f), fmaxf(d[1] + bv[m][1], 0.0f)),
                       pack_bf2(fmaxf(d[2] + bv[m][2], 0.0f), fmaxf(d[3] + bv[m][3], 0.0f)));
   };
-  // One step.  F: accumulator of the row that starts now (row i of the layer), M: row i - 1,
-  // L: row i - 2 (completed now); BC: this step's operands, BN: the next step's.  The slot parity of every ring access equals that of k
-  // (all lags are even), which the unrolling makes a constant.
-  auto step = [&](auto u, int k, f32x4 (&F)[2], f32x4 (&M)[2], f32x4 (&L)[2], bf16x8 (&BC)[3], bf16x8 (&BN)[3])
-      __attribute__((always_inline)) {
+  // One step of each role.  F: accumulator of the row that starts now (row i of the layer),
+  // M: row i - 1, L: row i - 2 (completed now); BC: this step's operands, BN: the next step's.
+  // The slot parity of every ring access equals that of k (all lags are even), which the
+  // unrolling makes a constant.  The roles run separate loops with the same barriers, so
+  // that neither role's registers shape the other's.
+  auto fetch = [&](auto u, int k, bf16x8 (&BN)[3]) __attribute__((always_inline)) {
     constexpr int par = decltype(u)::value & 1;
-    const bf16_t nxt = in_load(k + kInPre + 1);
     const int ip = k - lag + 1;
     if (ip >= 0 && ip < nsrc) {
 #pragma unroll
       for (int d = 0; d < 3; ++d)
         BN[d] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(srcp + (1 - par) * kRingLen + d * kPx));
     }
+  };
+  // a completed row into this layer's ring slot; a row outside the image (only near the
+  // image's top and bottom edges) is then overwritten with zeros
+  auto store_row = [&](auto u, const f32x4& d0, const f32x4& d1, bool rowok) __attribute__((always_inline)) {
+    constexpr int par = decltype(u)::value & 1;
+    bf16_t* wp = dstp + par * kRingLen;
+    *reinterpret_cast<uint2*>(wp) = relu_pack(d0, 0);
+    *reinterpret_cast<uint2*>(wp + 16) = relu_pack(d1, 1);
+    if (!rowok) {
+      __builtin_amdgcn_sched_barrier(0);
+      *reinterpret_cast<uint2*>(wp) = make_uint2(0u, 0u);
+      *reinterpret_cast<uint2*>(wp + 16) = make_uint2(0u, 0u);
+    }
+  };
+  auto step_mid = [&](auto u, int k, f32x4 (&F)[2], f32x4 (&M)[2], f32x4 (&L)[2], bf16x8 (&BC)[3],
+                      bf16x8 (&BN)[3]) __attribute__((always_inline)) {
+    const bf16_t nxt = in_load(k + kInPre + 1);
+    fetch(u, k, BN);
     const int i = k - lag;
-    const bool live = i >= 0 && i < nsrc;
-    if (role < 2) {
-      if (live) {
+    if (i >= 0 && i < nsrc) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+      for (int d = 0; d < 3; ++d)
 #pragma unroll
-          for (int m = 0; m < 2; ++m) L[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[6 + d][m], BC[d], L[m], 0, 0, 0);
-        const int j = i - 2;           // the row completed now
-        if (j >= 0) {
-          const int ii = oy - hal + j;
-          uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
-          if (ii >= 0 && ii < g.H) {
-            v0 = relu_pack(L[0], 0);
-            v1 = relu_pack(L[1], 1);
-          }
-          bf16_t* wp = dstp + par * kRingLen;
-          *reinterpret_cast<uint2*>(wp) = v0;
-          *reinterpret_cast<uint2*>(wp + 16) = v1;
+        for (int m = 0; m < 2; ++m) L[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[6 + d][m], BC[d], L[m], 0, 0, 0);
+      const int j = i - 2;             // the row completed now
+      if (j >= 0) store_row(u, L[0], L[1], oy - hal + j >= 0 && oy - hal + j < g.H);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          M[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 + d][m], BC[d], M[m], 0, 0, 0);
+          F[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][m], BC[d], d == 0 ? z : F[m], 0, 0, 0);
         }
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            M[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 + d][m], BC[d], M[m], 0, 0, 0);
-            F[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][m], BC[d], d == 0 ? z : F[m], 0, 0, 0);
-          }
-      }
-    } else {
-      const bool l1 = k < th + 6;
-      const bf16x8 xc = l1 ? gather(k) : zb;
-      if (live) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) L[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[6 + d][0], BC[d], L[0], 0, 0, 0);
-      }
-      f32x4 d0 = z, d1 = z;
-      if (l1) {
-        d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], xc, z, 0, 0, 0);
-        d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], xc, z, 0, 0, 0);
-      }
-      if (l1) {
-        const int ii = oy - 3 + k;
-        uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
-        if (ii >= 0 && ii < g.H) {
-          v0 = relu_pack(d0, 0);
-          v1 = relu_pack(d1, 1);
-        }
-        bf16_t* wp = dstp + par * kRingLen;
-        *reinterpret_cast<uint2*>(wp) = v0;
-        *reinterpret_cast<uint2*>(wp + 16) = v1;
-      }
-      if (live) {
-        const int o = i - 2;
-        if (o >= 0 && oy + o < g.H && ystore)
-          y[(static_cast<int64_t>(b) * g.H + oy + o) * g.W + ox + c] = L[0][0] + bias4;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          M[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 + d][0], BC[d], M[0], 0, 0, 0);
-          F[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][0], BC[d], d == 0 ? z : F[0], 0, 0, 0);
-        }
-      }
     }
     if (stager && k + kInPre < nin) s_in[(k + kInPre) * kInRow + tid] = pend;
     pend = nxt;
     __syncthreads();
   };
+  auto step_edge = [&](auto u, int k, f32x4 (&F)[2], f32x4 (&M)[2], f32x4 (&L)[2], bf16x8 (&BC)[3],
+                       bf16x8 (&BN)[3]) __attribute__((always_inline)) {
+    fetch(u, k, BN);
+    const int i = k - lag;
+    const bool live = i >= 0 && i < nsrc;
+    const bool l1 = k < th + 6;
+    const bf16x8 xc = gather(l1 ? k : th + 5);          // layer 1, row k (past the last row: unused)
+    if (live) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) L[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[6 + d][0], BC[d], L[0], 0, 0, 0);
+    }
+    const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], xc, z, 0, 0, 0);
+    const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], xc, z, 0, 0, 0);
+    if (l1) store_row(u, d0, d1, oy - 3 + k >= 0 && oy - 3 + k < g.H);
+    if (live) {
+      // layer 4: output row i - 2 is complete
+      const int o = i - 2;
+      if (o >= 0 && oy + o < g.H && ystore)
+        y[(static_cast<int64_t>(b) * g.H + oy + o) * g.W + ox + c] = L[0][0] + bias4;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        M[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 + d][0], BC[d], M[0], 0, 0, 0);
+        F[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][0], BC[d], d == 0 ? z : F[0], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  };
   __syncthreads();
   const int nsteps = th + 12;
   // accumulators (F, M, L) rotate (X, Y, Z) -> (Z, X, Y) -> (Y, Z, X); operands alternate P, Q
-  for (int k0 = 0; k0 < nsteps; k0 += 6) {
-    step(Step<0>{}, k0, aX, aY, aZ, bP, bQ);
-    if (k0 + 1 < nsteps) step(Step<1>{}, k0 + 1, aZ, aX, aY, bQ, bP);
-    if (k0 + 2 < nsteps) step(Step<2>{}, k0 + 2, aY, aZ, aX, bP, bQ);
-    if (k0 + 3 < nsteps) step(Step<3>{}, k0 + 3, aX, aY, aZ, bQ, bP);
-    if (k0 + 4 < nsteps) step(Step<4>{}, k0 + 4, aZ, aX, aY, bP, bQ);
-    if (k0 + 5 < nsteps) step(Step<5>{}, k0 + 5, aY, aZ, aX, bQ, bP);
+  if (role < 2) {
+    for (int k0 = 0; k0 < nsteps; k0 += 6) {
+      step_mid(Step<0>{}, k0, aX, aY, aZ, bP, bQ);
+      if (k0 + 1 < nsteps) step_mid(Step<1>{}, k0 + 1, aZ, aX, aY, bQ, bP);
+      if (k0 + 2 < nsteps) step_mid(Step<2>{}, k0 + 2, aY, aZ, aX, bP, bQ);
+      if (k0 + 3 < nsteps) step_mid(Step<3>{}, k0 + 3, aX, aY, aZ, bQ, bP);
+      if (k0 + 4 < nsteps) step_mid(Step<4>{}, k0 + 4, aZ, aX, aY, bP, bQ);
+      if (k0 + 5 < nsteps) step_mid(Step<5>{}, k0 + 5, aY, aZ, aX, bQ, bP);
+    }
+  } else {
+    for (int k0 = 0; k0 < nsteps; k0 += 6) {
+      step_edge(Step<0>{}, k0, aX, aY, aZ, bP, bQ);
+      if (k0 + 1 < nsteps) step_edge(Step<1>{}, k0 + 1, aZ, aX, aY, bQ, bP);
+      if (k0 + 2 < nsteps) step_edge(Step<2>{}, k0 + 2, aY, aZ, aX, bP, bQ);
+      if (k0 + 3 < nsteps) step_edge(Step<3>{}, k0 + 3, aX, aY, aZ, bQ, bP);
+      if (k0 + 4 < nsteps) step_edge(Step<4>{}, k0 + 4, aZ, aX, aY, bP, bQ);
+      if (k0 + 5 < nsteps) step_edge(Step<5>{}, k0 + 5, aY, aZ, aX, bQ, bP);
+    }
   }
 }
 

@@ -32,6 +32,8 @@ steps (all of them under `rooflines`).  The CPU baseline runs the FP64 oracle
 
 Prints one JSON line.  `--summarize-trace DIR [SKIP]` and `--summarize-counter DIR
 COUNTER` instead print markdown summaries of rocprofv3 CSV output of this script.
+`--network-only` times the learned start vector's fused network launch alone on a
+synthetic image of the cylinder lattice (for profiler runs of that kernel).
 """
 import argparse
 import json
@@ -435,6 +437,48 @@ def summarize_counter(d, counter):
     print("\n".join(out))
 
 
+def network_bench(args):
+    """The fused 4-layer network launch alone, on a synthetic input image of the cylinder
+    lattice at the given h (2561 x 3841 pixels at h = D/128): scaled residual and right-hand
+    side N(0, 1) on the lattice, 0 inside the body, plus the lattice mask."""
+    import torch
+    from paper_1401_6513_amd import vip
+    torch.zeros(1, device="cuda")
+    h = args.h
+    W, H = int(round(30.0 / h)) + 1, int(round(20.0 / h)) + 1
+    xs = -10.0 + h * np.arange(W)
+    ys = -10.0 + h * np.arange(H)
+    mask = (xs[None, :] ** 2 + ys[:, None] ** 2 >= 0.25).astype(np.float64)
+    rng = np.random.default_rng(5)
+    x = np.empty((1, H, W, 3))
+    x[0, :, :, 0] = rng.standard_normal((H, W)) * mask
+    x[0, :, :, 1] = rng.standard_normal((H, W)) * mask
+    x[0, :, :, 2] = mask
+    ctx = vip.Context(0)
+    try:
+        ctx.vip_learn_init(11)
+        ctx.vip_kernel_timing(True, True, 1)
+        for _ in range(args.warmup):
+            ctx.vip_learn_infer(x)
+        ctx.vip_kernel_timing(True, True, 1)
+        for _ in range(args.steps):
+            ctx.vip_learn_infer(x)
+        avg_ms, count = ctx.vip_kernel_timing(True, False, 1)
+    finally:
+        ctx.close()
+    per_px = 2 * 9 * (3 * 32 + 32 * 32 + 32 * 32 + 32 * 1)
+    flops = float(per_px) * W * H
+    tf = flops / (avg_ms * 1e-3) / 1e12
+    print(json.dumps({"metric": "network inference pixels/s", "value": W * H / (avg_ms * 1e-3),
+                      "unit": "pixels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": avg_ms, "higher_is_better": True, "dtype": "bf16+f32",
+                      "data": "synthetic", "config": {"workload": "fused network inference",
+                                                      "image": [H, W]},
+                      "roofline": {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s",
+                                   "frac": tf / 2500.0, "traffic": None, "kernel": "k_cnn_fused",
+                                   "flops_per_launch": flops, "launches": count}}))
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-counter"):
         # python bench.py --summarize-trace DIR [SKIP] | --summarize-counter DIR COUNTER
@@ -487,6 +531,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before the timed region, copy a 1 GiB buffer once (reference dispatch "
                          "for the HBM byte counters of a profiler run)")
+    ap.add_argument("--network-only", action="store_true",
+                    help="time the fused network inference launch alone (synthetic image)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -495,6 +541,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.network_only:
+        network_bench(args)
+        return
     import torch
     from paper_1401_6513_amd import vip
     h = args.h
@@ -678,7 +727,7 @@ def main():
         roof_mfma = {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": tf / 2500.0, "traffic": None,
                      "kernel": "k_cnn_fused (the learned start vector's 4-layer BF16 network in one launch, "
-                               "16x16 LDS tiles, v_mfma_f32_16x16x32_bf16)",
+                               "58-column strips walked row by row, v_mfma_f32_16x16x32_bf16)",
                      "flops_per_launch": flops, "flops_per_pixel": per_px, "avg_ms": avg_ms,
                      "launches": count, "image": [H, W]}
 

@@ -446,8 +446,8 @@ int vip_column_bytes(void* ctx, int64_t* sys_entries, int64_t* sys_entries_int16
  * HIP events on the context stream while timing is enabled; *count receives the number of
  * timed launches.  which = 0: the pressure-solve SpMV (the first SpMV of each Krylov
  * iteration; launches after the solve stopped on the device are not counted); which = 1:
- * the learned start vector's inference (the fused 4-layer launch, or each 32 -> 32 layer
- * when VIP_CNN_LAYERED=1 was set at vip_create); which = 2: the predictor's two-system SpMV
+ * the learned start vector's inference (the fused 4-layer launch, also that of
+ * vip_learn_infer, or each 32 -> 32 layer when VIP_CNN_LAYERED=1 was set at vip_create); which = 2: the predictor's two-system SpMV
  * (k_bicg_v); 3: the predictor's t = A s launch with s formed inside (one per system: k_bicg_ts,
  * or k_bicg_t); 4: the predictor's two-system update pass (on lattice tiles k_bicg_e, which
  * applies the last iteration's x and r update and forms the new p; otherwise k_bicg_x;

@@ -66,16 +66,32 @@ __device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
-// Layer 1 (3 -> 32) as one MFMA K-step: k = 3 t + ci over the 9 taps and 3 channels (27 of the
-// 32 K slots, the rest 0).  A = weights (16 output channels x 32 k for this lane's row),
-// B = the pixel's 27 tap values (lane: 8 consecutive k of pixel l % 16).  in(t, ci) returns the
-// BF16 bits of tap t, channel ci (0 outside the image).
+// Layer 1 (3 -> 32) as one MFMA K-step over the 9 taps and 3 channels (27 of the 32 K slots,
+// the rest 0).  Slot k = 8 G + j: for G = 0, 1, 2 tap row dy = G, tap column dx = j / 3,
+// channel j % 3 (j < 8); G = 3 holds tap column 2, channel 2 of the tap rows j = 0, 1, 2.  So
+// each 8-slot group is one contiguous run of input values (three pixels' channels of one row,
+// or the three left over), which the fused kernel reads with one load.  A = weights (16 output
+// channels x 32 k for this lane's row), B = the pixel's 27 tap values (lane: the 8 slots of
+// group l / 16 of pixel l % 16).  in(t, ci) returns the BF16 bits of tap t = 3 dy + dx,
+// channel ci (0 outside the image).
+__device__ __forceinline__ bool l1_slot(int k, int& t, int& ci) {
+  const int G = k >> 3, j = k & 7;
+  if (G < 3) {
+    t = 3 * G + j / 3;
+    ci = j % 3;
+    return true;
+  }
+  t = 3 * j + 2;
+  ci = 2;
+  return j < 3;
+}
+
 __device__ __forceinline__ bf16x8 l1_weights(const bf16_t* w1, int m, int n, int kq) {
   uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int k = kq + j;
-    const uint32_t v = k < 9 * kCin ? w1[k * kC + m * 16 + n] : 0u;
+    int t = 0, ci = 0;
+    const uint32_t v = l1_slot(kq + j, t, ci) ? w1[(t * kCin + ci) * kC + m * 16 + n] : 0u;
     w[j / 2] |= v << (16 * (j % 2));
   }
   return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
@@ -86,8 +102,8 @@ __device__ __forceinline__ bf16x8 l1_operand(int kq, In&& in) {
   uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int k = kq + j;
-    const uint32_t v = k < 9 * kCin ? static_cast<uint32_t>(in(k / kCin, k % kCin)) : 0u;
+    int t = 0, ci = 0;
+    const uint32_t v = l1_slot(kq + j, t, ci) ? static_cast<uint32_t>(in(t, ci)) : 0u;
     w[j / 2] |= v << (16 * (j % 2));
   }
   return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
@@ -277,8 +293,12 @@ __global__ __launch_bounds__(256) void k_conv_out(Img g, const bf16_t* x, const 
 // layer loads a row of the layer below into registers in the step after it was written and
 // uses it in the next one: layer 2 uses layer-1 row i at step i + 2 (and completes its own
 // row i - 2), layer 3 layer-2 row i at step i + 6, layer 4 layer-3 row i at step i + 10; the
-// last output row is done at step th + 11.  Input row r (image row oy - 4 + r) is loaded from HBM at step r - 8 and written to
-// LDS at step r - 7, well before layer 1 reads it at step r - 2.  One barrier per step.
+// last output row is done at step th + 11.  Layer 1's row k is multiplied at the end of step
+// k - 1 and written at the start of step k, which keeps its LDS reads, MFMA wait and epilogue
+// off the end of the step.  Input row r (image row oy - 4 + r) is loaded from HBM at step
+// r - 8 and written to LDS at step r - 7 (channel planes of a row apart, so that the 4 lane
+// groups of one layer-1 load read distinct banks), well before layer 1 reads it at step r - 3.
+// One barrier per step.
 // Waves: 0-3 layer 2 and 4-7 layer 3 (column group wave % 4), 8-11 layers 1 and 4 of group
 // wave - 8; wave w runs on SIMD w % 4, so every SIMD holds one of each (18 + 18 + 11 MFMA a
 // step).  The step loop is unrolled six times so that the three accumulator rows rotate and
@@ -286,7 +306,9 @@ __global__ __launch_bounds__(256) void k_conv_out(Img g, const bf16_t* x, const 
 constexpr int kSW = 58;             // output columns per strip
 constexpr int kRingPx = 68;         // ring row: 64 region columns + 2 read by the shifted loads, padded
 constexpr int kInW = kSW + 8;       // staged input columns
-constexpr int kInRow = kInW * kCin; // values per staged input row
+constexpr int kInPlane = 80;        // LDS stride of one channel's columns in a staged row (the 4
+                                    // planes one layer-1 load touches fall 8 banks apart or more)
+constexpr int kInRow = kCin * kInPlane;   // one staged input row: 3 channel planes
 constexpr int kMaxTH = 128;         // output rows per strip at most
 constexpr int kPx = 40;             // LDS stride of one pixel's 32 channels (80 bytes: the 16-byte
                                     // reads of 16 consecutive pixels hit 64 distinct banks)
@@ -301,16 +323,18 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
                                                        const float* b1, const bf16_t* w2t, const float* b2,
                                                        const bf16_t* w3t, const float* b3, const bf16_t* w4,
                                                        const float* b4, float* y) {
-  __shared__ bf16_t s_in[(kMaxTH + 8) * kInRow + 8];
+  __shared__ bf16_t s_in[(kMaxTH + 8) * kInRow];
   __shared__ __attribute__((aligned(16))) bf16_t s_ring[3][2][kRingLen];   // layers 1, 2, 3
   const int tid = static_cast<int>(threadIdx.x);
   const int b = static_cast<int>(blockIdx.z);
   const int ox = static_cast<int>(blockIdx.x) * kSW, oy = static_cast<int>(blockIdx.y) * th;
   const int nin = th + 8;                             // staged input rows
-  // input value tid of a staged row: column ox - 4 + tid / 3, channel tid % 3
-  const bool stager = tid < kInRow;
+  // input value tid of a staged row: column ox - 4 + tid / 3, channel tid % 3, kept at
+  // sdst = channel plane + column in LDS
+  const bool stager = tid < kInW * kCin;
   const int sq = tid / kCin, sci = tid - (tid / kCin) * kCin;
   const bool scol = stager && ox - 4 + sq >= 0 && ox - 4 + sq < g.W;
+  const int sdst = sci * kInPlane + sq;
   const int soff = (ox - 4) * kCin + tid;             // offset of this value in its image row
   auto in_load = [&](int r) -> bf16_t {
     const int ii = oy - 4 + r;
@@ -324,7 +348,7 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
     for (int r = 0; r < kInPre; ++r) v[r] = in_load(r);
     if (stager)
 #pragma unroll
-      for (int r = 0; r < kInPre; ++r) s_in[r * kInRow + tid] = v[r];
+      for (int r = 0; r < kInPre; ++r) s_in[r * kInRow + sdst] = v[r];
     // ring columns 64..67 feed only discarded lanes; keep them finite
     for (int e = tid; e < 3 * 2 * 4 * kPx; e += kCnnBlock)
       (&s_ring[0][0][0])[(e / (4 * kPx)) * kRingLen + 64 * kPx + e % (4 * kPx)] = 0;
@@ -371,21 +395,20 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
   }
   const float bias4 = b4[0];
   const bool ystore = l < 16 && c < kSW && ox + c < g.W;
-  // layer 1: operand slot k = kq + j holds tap k / 3, channel k % 3, i.e. value k % 9 of input
-  // row k / 9 from the pixel's top-left input value: offset k + (kInRow - 9) (k / 9).  With
-  // G = kq / 8 and k = 8 G + j, k / 9 = G - 1 + [j >= G], so a lane reads from one of two bases
-  // at the fixed offset j.  Slots k >= 27 are masked to 0 (their reads stay in s_in's padding).
-  const int G = l >> 4;
-  const int gb0 = 2 * (c * kCin + 8 * G + (kInRow - 9) * (G - 1));   // bytes
-  const uint32_t gmask1 = kq == 24 ? 0x0000ffffu : 0xffffffffu;   // k = 27 in the high half
-  const uint32_t gmask23 = kq == 24 ? 0u : 0xffffffffu;           // k = 28..31
+  // layer 1: slot j of this lane's group is tap row dy, tap column dx, channel ci (l1_slot), at
+  // goff[j] + row * kInRow in the staged input; slots past the 27 read any value and are masked
+  int goff[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    int t = 0, ci = 0;
+    goff[j] = l1_slot(kq + j, t, ci) ? (t / 3) * kInRow + ci * kInPlane + c + t % 3 : c;
+  }
+  const uint32_t gmask1 = kq == 24 ? 0x0000ffffu : 0xffffffffu;   // slot 27 in the high half
+  const uint32_t gmask23 = kq == 24 ? 0u : 0xffffffffu;           // slots 28..31
   auto gather = [&](int row) -> bf16x8 {
-    const int r0 = gb0 + row * (2 * kInRow), r1 = r0 + 2 * (kInRow - 9);
-    const char* sb = reinterpret_cast<const char*>(s_in);
     uint32_t h[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      h[j] = *reinterpret_cast<const bf16_t*>(sb + (j >= G && 8 * G + j < 9 * kCin ? r1 : r0) + 2 * j);
+    for (int j = 0; j < 8; ++j) h[j] = s_in[goff[j] + row * kInRow];
     return __builtin_bit_cast(bf16x8, make_uint4(h[0] | (h[1] << 16), (h[2] | (h[3] << 16)) & gmask1,
                                                  (h[4] | (h[5] << 16)) & gmask23, (h[6] | (h[7] << 16)) & gmask23));
   };
@@ -448,25 +471,22 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
           F[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][m], BC[d], d == 0 ? z : F[m], 0, 0, 0);
         }
     }
-    if (stager && k + kInPre < nin) s_in[(k + kInPre) * kInRow + tid] = pend;
+    if (stager && k + kInPre < nin) s_in[(k + kInPre) * kInRow + sdst] = pend;
     pend = nxt;
     __syncthreads();
   };
+  // layer 1's row k + 1 is multiplied at the end of step k (D0, D1) and stored at the start of
+  // step k + 1, so that neither the MFMA queue nor the epilogue sits on the step's critical path
   auto step_edge = [&](auto u, int k, f32x4 (&F)[2], f32x4 (&M)[2], f32x4 (&L)[2], bf16x8 (&BC)[3],
-                       bf16x8 (&BN)[3]) __attribute__((always_inline)) {
+                       bf16x8 (&BN)[3], f32x4& D0, f32x4& D1, f32x4& E0, f32x4& E1) __attribute__((always_inline)) {
+    if (k < th + 6) store_row(u, D0, D1, oy - 3 + k >= 0 && oy - 3 + k < g.H);
     fetch(u, k, BN);
     const int i = k - lag;
     const bool live = i >= 0 && i < nsrc;
-    const bool l1 = k < th + 6;
-    const bf16x8 xc = gather(l1 ? k : th + 5);          // layer 1, row k (past the last row: unused)
+    const bf16x8 xn = gather(k + 1 < th + 6 ? k + 1 : th + 5);
     if (live) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) L[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[6 + d][0], BC[d], L[0], 0, 0, 0);
-    }
-    const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], xc, z, 0, 0, 0);
-    const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], xc, z, 0, 0, 0);
-    if (l1) store_row(u, d0, d1, oy - 3 + k >= 0 && oy - 3 + k < g.H);
-    if (live) {
       // layer 4: output row i - 2 is complete
       const int o = i - 2;
       if (o >= 0 && oy + o < g.H && ystore)
@@ -477,6 +497,8 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
         F[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][0], BC[d], d == 0 ? z : F[0], 0, 0, 0);
       }
     }
+    E0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], xn, z, 0, 0, 0);
+    E1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], xn, z, 0, 0, 0);
     __syncthreads();
   };
   __syncthreads();
@@ -492,13 +514,17 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
       if (k0 + 5 < nsteps) step_mid(Step<5>{}, k0 + 5, aY, aZ, aX, bQ, bP);
     }
   } else {
+    const bf16x8 x0 = gather(0);
+    f32x4 dP0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], x0, z, 0, 0, 0);
+    f32x4 dP1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], x0, z, 0, 0, 0);
+    f32x4 dQ0 = z, dQ1 = z;
     for (int k0 = 0; k0 < nsteps; k0 += 6) {
-      step_edge(Step<0>{}, k0, aX, aY, aZ, bP, bQ);
-      if (k0 + 1 < nsteps) step_edge(Step<1>{}, k0 + 1, aZ, aX, aY, bQ, bP);
-      if (k0 + 2 < nsteps) step_edge(Step<2>{}, k0 + 2, aY, aZ, aX, bP, bQ);
-      if (k0 + 3 < nsteps) step_edge(Step<3>{}, k0 + 3, aX, aY, aZ, bQ, bP);
-      if (k0 + 4 < nsteps) step_edge(Step<4>{}, k0 + 4, aZ, aX, aY, bP, bQ);
-      if (k0 + 5 < nsteps) step_edge(Step<5>{}, k0 + 5, aY, aZ, aX, bQ, bP);
+      step_edge(Step<0>{}, k0, aX, aY, aZ, bP, bQ, dP0, dP1, dQ0, dQ1);
+      if (k0 + 1 < nsteps) step_edge(Step<1>{}, k0 + 1, aZ, aX, aY, bQ, bP, dQ0, dQ1, dP0, dP1);
+      if (k0 + 2 < nsteps) step_edge(Step<2>{}, k0 + 2, aY, aZ, aX, bP, bQ, dP0, dP1, dQ0, dQ1);
+      if (k0 + 3 < nsteps) step_edge(Step<3>{}, k0 + 3, aX, aY, aZ, bQ, bP, dQ0, dQ1, dP0, dP1);
+      if (k0 + 4 < nsteps) step_edge(Step<4>{}, k0 + 4, aZ, aX, aY, bP, bQ, dP0, dP1, dQ0, dQ1);
+      if (k0 + 5 < nsteps) step_edge(Step<5>{}, k0 + 5, aY, aZ, aX, bQ, bP, dQ0, dQ1, dP0, dP1);
     }
   }
 }
@@ -1466,10 +1492,11 @@ int learn_infer(Ctx* c, const double* x, int B, int H, int W, double* y) {
   for (int64_t k = 0; k < np * kCin; ++k) hx[k] = host_bf16(x[k]);
   VIP_HIP_TRY(c, hipMemcpyAsync(N->ix, hx.data(), sizeof(uint16_t) * np * kCin, hipMemcpyHostToDevice, st));
   const Img g{B, H, W};
-  VIP_TRY(forward_fused(c, g, false));
+  VIP_TRY(forward_fused(c, g, true));
   std::vector<float> hy(np);
   VIP_HIP_TRY(c, hipMemcpyAsync(hy.data(), N->iy, sizeof(float) * np, hipMemcpyDeviceToHost, st));
   VIP_HIP_TRY(c, hipStreamSynchronize(st));
+  harvest_conv_timing(c);
   for (int64_t k = 0; k < np; ++k) y[k] = hy[k];
   return VIP_OK;
 }

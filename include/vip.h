@@ -296,13 +296,15 @@ int vip_learn_eval(void* ctx, const double* x, const double* target, const doubl
 
 /*
  * Run the network on host images with the single fused launch that vip_step uses for the
- * learned start vector (all four layers on one 16 x 16 output tile per block, activations in
- * LDS), rather than the layer-by-layer training pass of vip_learn_eval.  Same arithmetic as
- * vip_learn_eval's forward pass (the same bits), without loss or gradient.
+ * learned start vector (all four layers in one pass down strips of 58 output columns, the
+ * activations in LDS rings of two rows per layer), rather than the layer-by-layer training
+ * pass of vip_learn_eval.  Same arithmetic as vip_learn_eval's forward pass (the same bits),
+ * without loss or gradient.  The launch is timed as which = 1 of vip_kernel_timing.
  *  x  host [batch][height][width][3] input channels (rounded to BF16).
  *  y  host [batch][height][width] output.
  * Errors: VIP_E_NOT_BUILT (no parameters), VIP_E_INVALID (sizes <= 0, batch > 65535, more
- * than 2^28 pixels, NULL x or y).
+ * than 2^28 pixels, more than 65535 strips of rows (height above about 8.4 million), NULL x
+ * or y).
  */
 int vip_learn_infer(void* ctx, const double* x, int batch, int height, int width, double* y);
 

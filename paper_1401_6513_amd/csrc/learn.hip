@@ -1253,6 +1253,8 @@ int forward_fused(Ctx* c, const Img& g, bool timed) {
     N->ncu = std::max(ncu, 1);
   }
   const int th = cnn_strip_rows(g, N->ncu);
+  if ((g.H + th - 1) / th > 65535)
+    return set_error(c, VIP_E_INVALID, "image too tall for the fused inference (more than 65535 strips of rows)");
   const dim3 grid((g.W + kSW - 1) / kSW, (g.H + th - 1) / th, g.B);
   k_cnn_fused<<<grid, kCnnBlock, 0, st>>>(g, th, N->ix, N->w1, N->theta + kB1, N->w2f, N->theta + kB2,
                                        N->w3f, N->theta + kB3, N->w4, N->theta + kB4, N->iy);

@@ -995,11 +995,89 @@ __global__ void k_dots10_finish(int nb, const double* part, double* scal) {
 }
 
 // phi = phi_prev + a1 d1 + a2 d2 + a3 d3 (a null direction is skipped)
+// The start-vector fit: minimise ||r - sum_k a_k q_k||_2 over the directions in use (e; the
+// network's c; e - e_old) from the Gram sums s[2..11] (q1.q1, q1.q2, q1.q3, q2.q2, q2.q3,
+// q3.q3, q1.r, q2.r, q3.r, r.r): normal equations by Gaussian elimination with partial
+// pivoting; a direction whose pivot vanishes against its Gram diagonal is dropped and the
+// system solved again without it.  The fit is accepted if it lowers the residual; out[0..2] =
+// the coefficients (all 0 if not accepted), out[3] = the residual ratio.  One thread, on the
+// device, so that the step does not wait for the host here; no contraction into FMAs, so the
+// arithmetic is the plain sequence written.
+__global__ void k_fit3(const double* s, int learned, int second, double* out) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double G[3][3] = {{s[2], s[3], s[4]}, {s[3], s[5], s[6]}, {s[4], s[6], s[7]}};
+  const double g[3] = {s[8], s[9], s[10]};
+  const double rr = s[11];
+  bool use[3] = {s[2] > 0.0, learned && s[5] > 0.0, second && s[7] > 0.0};
+  double coef[3] = {0.0, 0.0, 0.0};
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    int idx[3] = {0, 0, 0}, m = 0;
+    for (int k = 0; k < 3; ++k)
+      if (use[k]) idx[m++] = k;
+    coef[0] = coef[1] = coef[2] = 0.0;
+    if (m == 0) break;
+    double A[3][4];
+    for (int a = 0; a < m; ++a) {
+      for (int b2 = 0; b2 < m; ++b2) A[a][b2] = G[idx[a]][idx[b2]];
+      A[a][m] = g[idx[a]];
+    }
+    int bad = -1;
+    for (int col = 0; col < m && bad < 0; ++col) {
+      int piv = col;
+      for (int r2 = col + 1; r2 < m; ++r2)
+        if (fabs(A[r2][col]) > fabs(A[piv][col])) piv = r2;
+      for (int k = 0; k <= m; ++k) {
+        const double t = A[col][k];
+        A[col][k] = A[piv][k];
+        A[piv][k] = t;
+      }
+      if (!(fabs(A[col][col]) > 1e-10 * G[idx[col]][idx[col]])) {
+        bad = col;
+        break;
+      }
+      for (int r2 = col + 1; r2 < m; ++r2) {
+        const double f = A[r2][col] / A[col][col];
+        for (int k = col; k <= m; ++k) A[r2][k] -= f * A[col][k];
+      }
+    }
+    if (bad >= 0) {   // drop the last direction in use (e stays) and solve again
+      for (int k = 2; k >= 1; --k)
+        if (use[k]) {
+          use[k] = false;
+          break;
+        }
+      if (m == 1) use[0] = false;
+      continue;
+    }
+    double sol[3] = {0.0, 0.0, 0.0};
+    for (int a = m - 1; a >= 0; --a) {
+      double v = A[a][m];
+      for (int k = a + 1; k < m; ++k) v -= A[a][k] * sol[k];
+      sol[a] = v / A[a][a];
+    }
+    for (int a = 0; a < m; ++a) coef[idx[a]] = sol[a];
+    break;
+  }
+  const double alpha = coef[0], beta = coef[1], gamma = coef[2];
+  const double ratio2 = rr > 0.0 ? (rr - alpha * g[0] - beta * g[1] - gamma * g[2]) / rr : 1.0;
+  const double ratio = sqrt(fmax(ratio2, 0.0));
+  const bool accept = isfinite(alpha) && isfinite(beta) && isfinite(gamma) && isfinite(ratio) && ratio < 1.0 &&
+                      (alpha != 0.0 || beta != 0.0 || gamma != 0.0);
+  out[0] = accept ? alpha : 0.0;
+  out[1] = accept ? beta : 0.0;
+  out[2] = accept ? gamma : 0.0;
+  out[3] = ratio;
+}
+
+// phi = phi_prev + a1 d1 + a2 d2 + a3 d3 with the coefficients of k_fit3 (a term whose
+// coefficient is 0 is left out; all 0: the fit was not accepted and phi stays)
 __global__ void k_combine3(int64_t n, const double* phi_prev, const double* d1, const double* d2, const double* d3,
-                           double a1, double a2, double a3, double* phi) {
+                           const double* a, double* phi) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  phi[i] = phi_prev[i] + a1 * d1[i] + (d2 ? a2 * d2[i] : 0.0) + (d3 ? a3 * d3[i] : 0.0);
+  const double a1 = a[0], a2 = a[1], a3 = a[2];
+  if (i >= n || (a1 == 0.0 && a2 == 0.0 && a3 == 0.0)) return;
+  phi[i] = phi_prev[i] + a1 * d1[i] + (d2 && a2 != 0.0 ? a2 * d2[i] : 0.0) + (d3 && a3 != 0.0 ? a3 * d3[i] : 0.0);
 }
 
 // scal[2 + k] = sum over blocks of dot k (fixed block order)
@@ -1062,6 +1140,7 @@ void learn_clear(Ctx* c) {
 
 void learn_free_nodeset(Ctx* c) {
   Learn& L = c->learn;
+  L.fit_pending = false;
   for (double** p : {&L.r, &L.phi_prev, &L.eprev, &L.q1, &L.rx, &L.dir, &L.q2, &L.scal, &L.pc_r, &L.pc_d, &L.pc_c,
                      &L.pc_q1, &L.pc_q2, &L.pc_scal, &L.eprev2, &L.dir2, &L.q3})
     dfree(*p);
@@ -1071,6 +1150,11 @@ void learn_free_nodeset(Ctx* c) {
 
 void learn_free(Ctx* c) {
   Learn& L = c->learn;
+  if (L.fit_host) (void)hipHostFree(L.fit_host);
+  if (L.fit_event) (void)hipEventDestroy(L.fit_event);
+  L.fit_host = nullptr;
+  L.fit_event = nullptr;
+  L.fit_pending = false;
   if (L.net) {
     Net* N = static_cast<Net*>(L.net);
     for (float** p : {&N->theta, &N->grad, &N->m, &N->v, &N->y, &N->t, &N->mask, &N->gy, &N->part}) dfree(*p);
@@ -1349,6 +1433,7 @@ uint16_t host_bf16(double x) {
 }
 
 constexpr int kScalHead = 16;
+constexpr int kScalFit = 12;   // scal[12..15]: the start-vector fit's coefficients and residual ratio
 
 // rms of a h^2 and c h^2 over lattice nodes into scal[0], scal[1]
 int lattice_rms(Ctx* c, const double* a, const double* cv) {
@@ -1526,6 +1611,7 @@ int learn_prepare(Ctx* c, const double* b, const double* phi, bool with_map) {
 
 int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_stats* stats) {
   Learn& L = c->learn;
+  L.fit_pending = false;
   if (!L.have_eprev) return VIP_OK;   // no previous change yet: start from phi_prev
   hipStream_t st = c->stream;
   const double h2 = c->h * c->h;
@@ -1568,78 +1654,36 @@ int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_st
   k_dots10_part<<<kRedBlocks, 256, 0, st>>>(c->n, L.q1, learned ? L.q2 : nullptr, second ? L.q3 : nullptr, L.r,
                                             L.scal + kScalHead);
   k_dots10_finish<<<1, 256, 0, st>>>(kRedBlocks, L.scal + kScalHead, L.scal);
+  k_fit3<<<1, 64, 0, st>>>(L.scal, learned ? 1 : 0, second ? 1 : 0, L.scal + kScalFit);
+  k_combine3<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.phi_prev, L.eprev, learned ? L.dir : nullptr,
+                                                  second ? L.dir2 : nullptr, L.scal + kScalFit, phi);
   VIP_HIP_TRY(c, hipGetLastError());
-  double s[12];
-  VIP_HIP_TRY(c, hipMemcpyAsync(s, L.scal, sizeof(s), hipMemcpyDeviceToHost, st));
-  VIP_HIP_TRY(c, hipStreamSynchronize(st));
+  // the fit's outcome reaches the host with the pressure solve's first convergence check
+  if (!L.fit_host) VIP_HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&L.fit_host), 4 * sizeof(double),
+                                                hipHostMallocDefault));
+  if (!L.fit_event) VIP_HIP_TRY(c, hipEventCreateWithFlags(&L.fit_event, hipEventDisableTiming));
+  VIP_HIP_TRY(c, hipMemcpyAsync(L.fit_host, L.scal + kScalFit, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  VIP_HIP_TRY(c, hipEventRecord(L.fit_event, st));
+  L.fit_pending = true;
+  L.fit_mode = mode;
+  (void)stats;
+  return VIP_OK;
+}
+
+int learn_warm_stats(Ctx* c, vip_step_stats* stats) {
+  Learn& L = c->learn;
+  if (!L.fit_pending) return VIP_OK;
+  L.fit_pending = false;
+  VIP_HIP_TRY(c, hipEventSynchronize(L.fit_event));   // complete already after the solve's checks
   harvest_conv_timing(c);
-  // minimise ||r - sum_k a_k q_k||_2 over the directions in use (e; the network's c; e - e_old):
-  // normal equations by Gaussian elimination with partial pivoting; a direction whose pivot
-  // vanishes against the Gram diagonal is dropped and the system solved again without it
-  const double G[3][3] = {{s[2], s[3], s[4]}, {s[3], s[5], s[6]}, {s[4], s[6], s[7]}};
-  const double g[3] = {s[8], s[9], s[10]};
-  const double rr = s[11];
-  bool use[3] = {s[2] > 0.0, learned && s[5] > 0.0, second && s[7] > 0.0};
-  double coef[3] = {0.0, 0.0, 0.0};
-  for (int attempt = 0; attempt < 3; ++attempt) {
-    int idx[3], m = 0;
-    for (int k = 0; k < 3; ++k)
-      if (use[k]) idx[m++] = k;
-    coef[0] = coef[1] = coef[2] = 0.0;
-    if (m == 0) break;
-    double A[3][4];
-    for (int a = 0; a < m; ++a) {
-      for (int b2 = 0; b2 < m; ++b2) A[a][b2] = G[idx[a]][idx[b2]];
-      A[a][m] = g[idx[a]];
-    }
-    int bad = -1;
-    for (int col = 0; col < m && bad < 0; ++col) {
-      int piv = col;
-      for (int r2 = col + 1; r2 < m; ++r2)
-        if (std::fabs(A[r2][col]) > std::fabs(A[piv][col])) piv = r2;
-      for (int k = 0; k <= m; ++k) std::swap(A[col][k], A[piv][k]);
-      if (!(std::fabs(A[col][col]) > 1e-10 * G[idx[col]][idx[col]])) {
-        bad = col;
-        break;
-      }
-      for (int r2 = col + 1; r2 < m; ++r2) {
-        const double f = A[r2][col] / A[col][col];
-        for (int k = col; k <= m; ++k) A[r2][k] -= f * A[col][k];
-      }
-    }
-    if (bad >= 0) {   // drop the last direction in use (e stays) and solve again
-      for (int k = 2; k >= 1; --k)
-        if (use[k]) {
-          use[k] = false;
-          break;
-        }
-      if (m == 1) use[0] = false;
-      continue;
-    }
-    double sol[3] = {0.0, 0.0, 0.0};
-    for (int a = m - 1; a >= 0; --a) {
-      double v = A[a][m];
-      for (int k = a + 1; k < m; ++k) v -= A[a][k] * sol[k];
-      sol[a] = v / A[a][a];
-    }
-    for (int a = 0; a < m; ++a) coef[idx[a]] = sol[a];
-    break;
-  }
-  const double alpha = coef[0], beta = coef[1], gamma = coef[2];
-  const double ratio2 = rr > 0.0 ? (rr - alpha * g[0] - beta * g[1] - gamma * g[2]) / rr : 1.0;
-  const double ratio = std::sqrt(std::max(ratio2, 0.0));
-  const bool accept = std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(gamma) && std::isfinite(ratio) &&
-                      ratio < 1.0 && (alpha != 0.0 || beta != 0.0 || gamma != 0.0);
-  if (accept)
-    k_combine3<<<blocks_for(c->n), kBlock, 0, st>>>(c->n, L.phi_prev, L.eprev, beta != 0.0 ? L.dir : nullptr,
-                                                    gamma != 0.0 ? L.dir2 : nullptr, alpha, beta, gamma, phi);
-  VIP_HIP_TRY(c, hipGetLastError());
   if (stats) {
-    stats->warm_start = accept ? mode : VIP_WS_PREV;
-    stats->warm_ratio = ratio;
-    stats->warm_alpha = accept ? alpha : 0.0;
-    stats->warm_beta = accept ? beta : 0.0;
-    stats->warm_gamma = accept ? gamma : 0.0;
+    const double* f = L.fit_host;
+    const bool accept = f[0] != 0.0 || f[1] != 0.0 || f[2] != 0.0;
+    stats->warm_start = accept ? L.fit_mode : VIP_WS_PREV;
+    stats->warm_ratio = f[3];
+    stats->warm_alpha = f[0];
+    stats->warm_beta = f[1];
+    stats->warm_gamma = f[2];
   }
   return VIP_OK;
 }

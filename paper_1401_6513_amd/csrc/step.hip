@@ -686,6 +686,7 @@ int step(Ctx* c, double* u, double* v, double* p, double dt, double re, vip_step
   if (predict) VIP_TRY(learn_warm_start(c, ws, b, c->phi, st));
   int rc_p = poisson_solve(c, b, c->phi, c->opt.poisson_tol, warm, st);
   if (rc_p != VIP_OK && rc_p != VIP_E_NOT_CONVERGED) return rc_p;
+  if (predict) VIP_TRY(learn_warm_stats(c, st));
   if (track) {
     VIP_TRY(learn_finish(c, b, c->phi, capture));
   } else {

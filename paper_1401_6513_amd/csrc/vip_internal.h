@@ -310,6 +310,12 @@ struct Learn {
   double* pc_q1 = nullptr;
   double* pc_q2 = nullptr;
   double* pc_scal = nullptr;
+  // the last start-vector fit (computed on the device): pinned host copy of its coefficients
+  // and residual ratio, the event after that copy, whether the stats still have to take it
+  double* fit_host = nullptr;
+  hipEvent_t fit_event = nullptr;
+  bool fit_pending = false;
+  int fit_mode = 0;
 };
 
 struct Ctx {
@@ -578,9 +584,12 @@ bool learn_ready(const Ctx* c);
 // before the pressure solve: keep phi_prev = phi and r = b - L phi_prev (with_map: build the
 // lattice map too, which fails on node sets that are not lattice based)
 int learn_prepare(Ctx* c, const double* b, const double* phi, bool with_map);
-// phi = phi_prev + alpha e (+ beta c with the network's correction c in mode VIP_WS_LEARNED),
-// e the previous change of phi, alpha and beta minimising the FP64 residual; fills the stats
+// phi = phi_prev + alpha e (+ beta c with the network's correction c in mode VIP_WS_LEARNED,
+// + gamma e2 with e2 the second difference), e the previous change of phi, the coefficients
+// minimising the FP64 residual (fitted on the device, without waiting for the host)
 int learn_warm_start(Ctx* c, int mode, const double* b, double* phi, vip_step_stats* st);
+// after the pressure solve: the fit's outcome into the stats (and the network's launch timing)
+int learn_warm_stats(Ctx* c, vip_step_stats* st);
 // after the pressure solve: store one snapshot (if capture is on) and the change of phi
 int learn_finish(Ctx* c, const double* b, const double* phi, bool capture);
 int learn_init(Ctx* c, uint64_t seed);

@@ -303,7 +303,7 @@ int vip_learn_eval(void* ctx, const double* x, const double* target, const doubl
  *  x  host [batch][height][width][3] input channels (rounded to BF16).
  *  y  host [batch][height][width] output.
  * Errors: VIP_E_NOT_BUILT (no parameters), VIP_E_INVALID (sizes <= 0, batch > 65535, more
- * than 2^28 pixels, more than 65535 strips of rows (height above about 8.4 million), NULL x
+ * than 2^28 pixels, more than 65535 strips of rows (height above about 10.4 million), NULL x
  * or y).
  */
 int vip_learn_infer(void* ctx, const double* x, int batch, int height, int width, double* y);

@@ -309,7 +309,7 @@ constexpr int kInW = kSW + 8;       // staged input columns
 constexpr int kInPlane = 80;        // LDS stride of one channel's columns in a staged row (the 4
                                     // planes one layer-1 load touches fall 8 banks apart or more)
 constexpr int kInRow = kCin * kInPlane;   // one staged input row: 3 channel planes
-constexpr int kMaxTH = 128;         // output rows per strip at most
+constexpr int kMaxTH = 160;         // output rows per strip at most
 constexpr int kPx = 40;             // LDS stride of one pixel's 32 channels (80 bytes: the 16-byte
                                     // reads of 16 consecutive pixels hit 64 distinct banks)
 constexpr int kRingLen = kRingPx * kPx;
@@ -1301,7 +1301,7 @@ int cnn_strip_rows(const Img& g, int ncu) {
   const int64_t strips = static_cast<int64_t>((g.W + kSW - 1) / kSW) * g.B;
   int best = 1;
   int64_t best_cost = INT64_MAX;
-  for (int cand = 8; cand <= kMaxTH; cand += 8) {
+  for (int cand = 1; cand <= kMaxTH; ++cand) {
     const int th = std::min(cand, g.H);
     const int64_t blocks = strips * ((g.H + th - 1) / th);
     const int64_t cost = (blocks + ncu - 1) / ncu * (th + 12);

@@ -196,8 +196,10 @@ def _image(rng, B, H, W):
     return x
 
 
-@pytest.mark.parametrize("B,H,W", [(1, 16, 16), (2, 19, 37), (1, 45, 70), (3, 5, 50), (1, 1, 33)])
+@pytest.mark.parametrize("B,H,W", [(1, 16, 16), (2, 19, 37), (1, 45, 70), (3, 5, 50), (1, 1, 33), (1, 301, 130)])
 def test_fused_inference_matches_oracle(B, H, W):
+    """The small images run as strips of one row each; 301 x 130 as three 58-column strips of
+    4 rows (the last one row), so that rows pass through the layers' rings."""
     vip = _vip()
     ctx = vip.Context(0)
     try:

@@ -66,6 +66,19 @@ __device__ __forceinline__ uint32_t pack_bf2(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
+// ReLU of a layer's four sums (the bias already in them, as the MFMA's initial accumulator),
+// rounded to BF16 first: a BF16 value is negative exactly when its 16-bit pattern is a
+// negative integer, so one packed integer max with 0 (v_pk_max_i16) per two values clears the
+// negatives (and -0).  For finite sums this is bit for bit the BF16 rounding of the FP32 ReLU.
+typedef short __attribute__((ext_vector_type(2))) s16x2;
+__device__ __forceinline__ uint32_t relu_bf2(uint32_t w) {
+  const s16x2 zero = {0, 0};
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, w), zero));
+}
+__device__ __forceinline__ uint2 relu_pack4(const f32x4& d) {
+  return make_uint2(relu_bf2(pack_bf2(d[0], d[1])), relu_bf2(pack_bf2(d[2], d[3])));
+}
+
 // Layer 1 (3 -> 32) as one MFMA K-step over the 9 taps and 3 channels (27 of the 32 K slots,
 // the rest 0).  Slot k = 8 G + j: for G = 0, 1, 2 tap row dy = G, tap column dx = j / 3,
 // channel j % 3 (j < 8); G = 3 holds tap column 2, channel 2 of the tap rows j = 0, 1, 2.  So
@@ -131,11 +144,8 @@ __global__ __launch_bounds__(256) void k_conv_in(Img g, const bf16_t* x, const b
   const int n = l & 15;
   const int cq = (l >> 4) * 4;
   const bf16x8 wa0 = l1_weights(w1, 0, n, kq), wa1 = l1_weights(w1, 1, n, kq);
-  float bv[2][4];
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bv[m][r] = b1[m * 16 + cq + r];
+  const f32x4 bv0 = {b1[cq], b1[cq + 1], b1[cq + 2], b1[cq + 3]};
+  const f32x4 bv1 = {b1[16 + cq], b1[16 + cq + 1], b1[16 + cq + 2], b1[16 + cq + 3]};
   const int strips_w = (g.W + 15) / 16;
   for (int64_t s = s0; s < s0 + kStripsPerWave && s < nstrips; ++s) {
     const int j0 = static_cast<int>(s % strips_w) * 16;
@@ -146,17 +156,12 @@ __global__ __launch_bounds__(256) void k_conv_in(Img g, const bf16_t* x, const b
       const int ii = i + t / 3 - 1, jj = j + t % 3 - 1;
       return inside(g, ii, jj) ? x[((static_cast<int64_t>(b) * g.H + ii) * g.W + jj) * kCin + ci] : bf16_t(0);
     });
-    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-    const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, xb, z, 0, 0, 0);
-    const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, xb, z, 0, 0, 0);
+    const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, xb, bv0, 0, 0, 0);
+    const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, xb, bv1, 0, 0, 0);
     if (j < g.W) {
       bf16_t* op = out + ((static_cast<int64_t>(b) * g.H + i) * g.W + j) * kC + cq;
-      *reinterpret_cast<uint2*>(op) =
-          make_uint2(pack_bf2(fmaxf(d0[0] + bv[0][0], 0.0f), fmaxf(d0[1] + bv[0][1], 0.0f)),
-                     pack_bf2(fmaxf(d0[2] + bv[0][2], 0.0f), fmaxf(d0[3] + bv[0][3], 0.0f)));
-      *reinterpret_cast<uint2*>(op + 16) =
-          make_uint2(pack_bf2(fmaxf(d1[0] + bv[1][0], 0.0f), fmaxf(d1[1] + bv[1][1], 0.0f)),
-                     pack_bf2(fmaxf(d1[2] + bv[1][2], 0.0f), fmaxf(d1[3] + bv[1][3], 0.0f)));
+      *reinterpret_cast<uint2*>(op) = relu_pack4(d0);
+      *reinterpret_cast<uint2*>(op + 16) = relu_pack4(d1);
     }
   }
 }
@@ -205,17 +210,14 @@ __global__ __launch_bounds__(256) void k_conv_mid(Img g, const bf16_t* x, const 
 #pragma unroll
     for (int m = 0; m < 2; ++m)
       wa[t][m] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wt + (t * kC + m * 16 + n) * kC + kq));
-  float bv[2][4];
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bv[m][r] = bias[m * 16 + cq + r];
+  const f32x4 bv0 = {bias[cq], bias[cq + 1], bias[cq + 2], bias[cq + 3]};
+  const f32x4 bv1 = {bias[16 + cq], bias[16 + cq + 1], bias[16 + cq + 2], bias[16 + cq + 3]};
   const int strips_w = (g.W + 15) / 16;
   for (int64_t s = s0; s < s0 + kStripsPerWave && s < nstrips; ++s) {
     const int j0 = static_cast<int>(s % strips_w) * 16;
     const int i = static_cast<int>((s / strips_w) % g.H);
     const int b = static_cast<int>(s / (static_cast<int64_t>(strips_w) * g.H));
-    f32x4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+    f32x4 d0 = bv0, d1 = bv1;   // the bias is the accumulators' start
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int ii = i + (t / 3 - 1), jj = j0 + n + (t % 3 - 1);
@@ -229,12 +231,8 @@ __global__ __launch_bounds__(256) void k_conv_mid(Img g, const bf16_t* x, const 
     const int j = j0 + n;
     if (j < g.W) {
       bf16_t* op = out + ((static_cast<int64_t>(b) * g.H + i) * g.W + j) * kC + cq;
-      const uint2 v0 = make_uint2(pack_bf2(fmaxf(d0[0] + bv[0][0], 0.0f), fmaxf(d0[1] + bv[0][1], 0.0f)),
-                                  pack_bf2(fmaxf(d0[2] + bv[0][2], 0.0f), fmaxf(d0[3] + bv[0][3], 0.0f)));
-      const uint2 v1 = make_uint2(pack_bf2(fmaxf(d1[0] + bv[1][0], 0.0f), fmaxf(d1[1] + bv[1][1], 0.0f)),
-                                  pack_bf2(fmaxf(d1[2] + bv[1][2], 0.0f), fmaxf(d1[3] + bv[1][3], 0.0f)));
-      *reinterpret_cast<uint2*>(op) = v0;
-      *reinterpret_cast<uint2*>(op + 16) = v1;
+      *reinterpret_cast<uint2*>(op) = relu_pack4(d0);
+      *reinterpret_cast<uint2*>(op + 16) = relu_pack4(d1);
     }
   }
 }
@@ -251,13 +249,13 @@ __global__ __launch_bounds__(256) void k_conv_out(Img g, const bf16_t* x, const 
   bf16x8 wa[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) wa[t] = l4_weights(w4, t, n, kq);
-  const float bias = b4[0];
+  const f32x4 bias = {b4[0], 0.f, 0.f, 0.f};   // output row 0 starts from the bias
   const int strips_w = (g.W + 15) / 16;
   for (int64_t s = s0; s < s0 + kStripsPerWave && s < nstrips; ++s) {
     const int j0 = static_cast<int>(s % strips_w) * 16;
     const int i = static_cast<int>((s / strips_w) % g.H);
     const int b = static_cast<int>(s / (static_cast<int64_t>(strips_w) * g.H));
-    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+    f32x4 d = bias;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int ii = i + (t / 3 - 1), jj = j0 + n + (t % 3 - 1);
@@ -267,7 +265,7 @@ __global__ __launch_bounds__(256) void k_conv_out(Img g, const bf16_t* x, const 
       d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t], __builtin_bit_cast(bf16x8, raw), d, 0, 0, 0);
     }
     const int j = j0 + n;
-    if (l < 16 && j < g.W) y[(static_cast<int64_t>(b) * g.H + i) * g.W + j] = d[0] + bias;
+    if (l < 16 && j < g.W) y[(static_cast<int64_t>(b) * g.H + i) * g.W + j] = d[0];
   }
 }
 
@@ -364,10 +362,11 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
   const int hal = 2 - role;          // region origin ox - hal, oy - hal (layers 2, 3, 4)
   // role 0 / 1: wa[t][m] = the layer's weights of tap t, output channels 16 m ..; role 2:
   // wa[t][0] = layer 4 (A row 0 only), wa[0][1], wa[1][1] = layer 1's two channel tiles.
-  // bv: the bias of this lane's 8 channels (layer 2 or 3; layer 1 for role 2), -inf in a
-  // column outside the layer's region or the image.
+  // bv: the bias of this lane's 8 channels (layer 2 or 3; layer 1 for role 2), the start of a
+  // row's accumulators; -inf in a column outside the layer's region or the image, so that the
+  // ReLU stores 0 there.  bv4: layer 4's start (row 0: its bias).
   bf16x8 wa[9][2];
-  float bv[2][4];
+  f32x4 bv[2];
   {
     const int jc = role < 2 ? ox - hal + c : ox - 3 + c;
     const bool colok = (role < 2 ? c < 62 - 2 * role : true) && jc >= 0 && jc < g.W;
@@ -393,7 +392,7 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
     wa[0][1] = l1_weights(w1, 0, n, kq);
     wa[1][1] = l1_weights(w1, 1, n, kq);
   }
-  const float bias4 = b4[0];
+  const f32x4 bv4 = {b4[0], 0.f, 0.f, 0.f};
   const bool ystore = l < 16 && c < kSW && ox + c < g.W;
   // layer 1: slot j of this lane's group is tap row dy, tap column dx, channel ci (l1_slot), at
   // goff[j] + row * kInRow in the staged input; slots past the 27 read any value and are masked
@@ -420,10 +419,6 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
   const bf16x8 zb = __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
   f32x4 aX[2] = {z, z}, aY[2] = {z, z}, aZ[2] = {z, z};
   bf16x8 bP[3] = {zb, zb, zb}, bQ[3] = {zb, zb, zb};
-  auto relu_pack = [&](const f32x4& d, int m) -> uint2 {
-    return make_uint2(pack_bf2(fmaxf(d[0] + bv[m][0], 0.0f), fmaxf(d[1] + bv[m][1], 0.0f)),
-                      pack_bf2(fmaxf(d[2] + bv[m][2], 0.0f), fmaxf(d[3] + bv[m][3], 0.0f)));
-  };
   // One step of each role.  F: accumulator of the row that starts now (row i of the layer),
   // M: row i - 1, L: row i - 2 (completed now); BC: this step's operands, BN: the next step's.
   // The slot parity of every ring access equals that of k (all lags are even), which the
@@ -443,8 +438,8 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
   auto store_row = [&](auto u, const f32x4& d0, const f32x4& d1, bool rowok) __attribute__((always_inline)) {
     constexpr int par = decltype(u)::value & 1;
     bf16_t* wp = dstp + par * kRingLen;
-    *reinterpret_cast<uint2*>(wp) = relu_pack(d0, 0);
-    *reinterpret_cast<uint2*>(wp + 16) = relu_pack(d1, 1);
+    *reinterpret_cast<uint2*>(wp) = relu_pack4(d0);
+    *reinterpret_cast<uint2*>(wp + 16) = relu_pack4(d1);
     if (!rowok) {
       __builtin_amdgcn_sched_barrier(0);
       *reinterpret_cast<uint2*>(wp) = make_uint2(0u, 0u);
@@ -468,7 +463,7 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
           M[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 + d][m], BC[d], M[m], 0, 0, 0);
-          F[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][m], BC[d], d == 0 ? z : F[m], 0, 0, 0);
+          F[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][m], BC[d], d == 0 ? bv[m] : F[m], 0, 0, 0);
         }
     }
     if (stager && k + kInPre < nin) s_in[(k + kInPre) * kInRow + sdst] = pend;
@@ -490,15 +485,15 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
       // layer 4: output row i - 2 is complete
       const int o = i - 2;
       if (o >= 0 && oy + o < g.H && ystore)
-        y[(static_cast<int64_t>(b) * g.H + oy + o) * g.W + ox + c] = L[0][0] + bias4;
+        y[(static_cast<int64_t>(b) * g.H + oy + o) * g.W + ox + c] = L[0][0];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         M[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[3 + d][0], BC[d], M[0], 0, 0, 0);
-        F[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][0], BC[d], d == 0 ? z : F[0], 0, 0, 0);
+        F[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[d][0], BC[d], d == 0 ? bv4 : F[0], 0, 0, 0);
       }
     }
-    E0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], xn, z, 0, 0, 0);
-    E1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], xn, z, 0, 0, 0);
+    E0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], xn, bv[0], 0, 0, 0);
+    E1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], xn, bv[1], 0, 0, 0);
     __syncthreads();
   };
   __syncthreads();
@@ -515,8 +510,8 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
     }
   } else {
     const bf16x8 x0 = gather(0);
-    f32x4 dP0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], x0, z, 0, 0, 0);
-    f32x4 dP1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], x0, z, 0, 0, 0);
+    f32x4 dP0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0][1], x0, bv[0], 0, 0, 0);
+    f32x4 dP1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[1][1], x0, bv[1], 0, 0, 0);
     f32x4 dQ0 = z, dQ1 = z;
     for (int k0 = 0; k0 < nsteps; k0 += 6) {
       step_edge(Step<0>{}, k0, aX, aY, aZ, bP, bQ, dP0, dP1, dQ0, dQ1);

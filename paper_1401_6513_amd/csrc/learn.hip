@@ -278,9 +278,10 @@ __global__ __launch_bounds__(256) void k_conv_out(Img g, const bf16_t* x, const 
 // three output rows it feeds, and writes the row that is then complete into its own ring.  A
 // row of activations is read from LDS once per consuming layer (three shifted loads), not
 // once per tap, and only the strip's top and bottom margins are computed twice.  For every
-// output pixel and channel the nine taps are still added in tap order starting from zero,
-// with the layer-by-layer kernels' MFMA operands and the BF16 rounding of each layer's
-// output, so the result has the same bits.  Pixels outside the image hold 0 after every layer.
+// output pixel and channel the nine taps are still added in tap order starting from the
+// layer's bias, with the layer-by-layer kernels' MFMA operands and the BF16 rounding of each
+// layer's output, so the result has the same bits.  Pixels outside the image hold 0 after
+// every layer.
 //
 // Columns: the output covers kSW = 58 columns from the strip origin ox, layer 3 the 60 from
 // ox - 1, layer 2 the 62 from ox - 2, layer 1 the 64 from ox - 3 and the staged input the 66

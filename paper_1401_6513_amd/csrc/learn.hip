@@ -351,6 +351,9 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
     // ring columns 64..67 feed only discarded lanes; keep them finite
     for (int e = tid; e < 3 * 2 * 4 * kPx; e += kCnnBlock)
       (&s_ring[0][0][0])[(e / (4 * kPx)) * kRingLen + 64 * kPx + e % (4 * kPx)] = 0;
+    // column kInW of every staged row's first plane is never staged: 0, read by layer 1's
+    // empty K slots
+    for (int r = tid; r < nin; r += kCnnBlock) s_in[r * kInRow + kInW] = 0;
   }
   bf16_t pend = in_load(kInPre);                      // row kInPre, written at step 0
   const int l = tid & 63;
@@ -396,21 +399,20 @@ __global__ __launch_bounds__(kCnnBlock) void k_cnn_fused(Img g, int th, const bf
   const f32x4 bv4 = {b4[0], 0.f, 0.f, 0.f};
   const bool ystore = l < 16 && c < kSW && ox + c < g.W;
   // layer 1: slot j of this lane's group is tap row dy, tap column dx, channel ci (l1_slot), at
-  // goff[j] + row * kInRow in the staged input; slots past the 27 read any value and are masked
+  // goff[j] + row * kInRow in the staged input; the empty slots (k >= 27) read the row's zero
+  // at column kInW, so the 8 values are the operand as loaded
   int goff[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     int t = 0, ci = 0;
-    goff[j] = l1_slot(kq + j, t, ci) ? (t / 3) * kInRow + ci * kInPlane + c + t % 3 : c;
+    goff[j] = l1_slot(kq + j, t, ci) ? (t / 3) * kInRow + ci * kInPlane + c + t % 3 : kInW;
   }
-  const uint32_t gmask1 = kq == 24 ? 0x0000ffffu : 0xffffffffu;   // slot 27 in the high half
-  const uint32_t gmask23 = kq == 24 ? 0u : 0xffffffffu;           // slots 28..31
+  typedef unsigned short __attribute__((ext_vector_type(8))) u16x8;
   auto gather = [&](int row) -> bf16x8 {
-    uint32_t h[8];
+    u16x8 h;
 #pragma unroll
     for (int j = 0; j < 8; ++j) h[j] = s_in[goff[j] + row * kInRow];
-    return __builtin_bit_cast(bf16x8, make_uint4(h[0] | (h[1] << 16), (h[2] | (h[3] << 16)) & gmask1,
-                                                 (h[4] | (h[5] << 16)) & gmask23, (h[6] | (h[7] << 16)) & gmask23));
+    return __builtin_bit_cast(bf16x8, h);
   };
   const int lag = 2 + 4 * role;                       // step at which row 0 of the layer below is used
   const int nsrc = th + 6 - 2 * role;                 // rows of the layer below

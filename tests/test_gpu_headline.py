@@ -196,10 +196,12 @@ def _image(rng, B, H, W):
     return x
 
 
-@pytest.mark.parametrize("B,H,W", [(1, 16, 16), (2, 19, 37), (1, 45, 70), (3, 5, 50), (1, 1, 33), (1, 301, 130)])
+@pytest.mark.parametrize("B,H,W", [(1, 16, 16), (2, 19, 37), (1, 45, 70), (3, 5, 50), (1, 1, 33), (1, 301, 130),
+                                   (2, 150, 250)])
 def test_fused_inference_matches_oracle(B, H, W):
     """The small images run as strips of one row each; 301 x 130 as three 58-column strips of
-    4 rows (the last one row), so that rows pass through the layers' rings."""
+    4 rows (the last one row), so that rows pass through the layers' rings; 2 x 150 x 250 as
+    five strips (the last 18 columns wide) of 6 rows per image of the batch."""
     vip = _vip()
     ctx = vip.Context(0)
     try:
